@@ -1,0 +1,194 @@
+"""Oracle for red-black Gauss-Seidel (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It wraps the plain C oracle (rbgs_oracle.c) for numpy
+arrays in the natural layout: an (n+2) x ld row-major array whose ring (row 0,
+row n+1, column 0, column n+1) holds the Dirichlet data g.  Nothing here is
+shared with, or imported by, the GPU library.
+
+Paper anchors: the point update is Eq. (1) of Section 2; the colouring (red
+when i+j is even) is stated in Section 2; one sweep is the red half-sweep
+then the black half-sweep, as in Algorithms 1 and 2.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OK = 0
+EINVAL = -1
+ENOCONV = -3
+
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_f64 = ctypes.c_double
+_vp = ctypes.c_void_p
+
+
+def _load(path=None):
+    """Load liboracle.so (building it if absent).  path: load another build
+    of the same source instead (the tests use this for planted mistakes)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    if path is None and not os.path.exists(_LIB_PATH):
+        from . import build as _build
+        _build.build()
+    lib = ctypes.CDLL(path or _LIB_PATH)
+    sig = {
+        "rbgs_ref_half_sweep_f64": [_i32, _i64, _f64, _vp, _vp, _i32],
+        "rbgs_ref_sweep_f64": [_i32, _i64, _f64, _vp, _vp, _i32],
+        "rbgs_ref_half_sweep_f32": [_i32, _i64, _f64, _vp, _vp, _i32],
+        "rbgs_ref_sweep_f32": [_i32, _i64, _f64, _vp, _vp, _i32],
+        "rbgs_ref_residual_f64": [_i32, _i64, _f64, _vp, _vp, _vp, _vp, _vp],
+        "rbgs_ref_residual_f32": [_i32, _i64, _f64, _vp, _vp, _vp, _vp, _vp],
+        "rbgs_ref_solve_f64": [_i32, _i64, _f64, _vp, _vp, _i32, _f64, _i32, _vp, _vp],
+        "rbgs_ref_ir_solve": [_i32, _i64, _f64, _vp, _vp, _i32, _i32, _i32, _f64, _vp, _vp],
+        "rbgs_ref_colour": [_i64, _i64],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = _i32
+    lib.rbgs_ref_round_bf16.argtypes = [ctypes.c_float]
+    lib.rbgs_ref_round_bf16.restype = ctypes.c_float
+    if path is None:
+        _lib = lib
+    return lib
+
+
+class use_library:
+    """Context manager: route every call of this module to another build of
+    the oracle source (used to check that the pins catch planted mistakes)."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        _lib = _load(self.path)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def _grid(a):
+    if a.ndim != 2 or a.shape[0] < 3 or a.shape[1] < a.shape[0]:
+        raise ValueError("expected an (n+2) x ld array with ld >= n+2")
+    if not a.flags.c_contiguous:
+        raise ValueError("array must be C-contiguous")
+    return a.shape[0] - 2, a.shape[1]
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _check(rc, name):
+    if rc not in (OK, ENOCONV):
+        raise RuntimeError(f"{name} returned {rc}")
+    return rc
+
+
+def half_sweep(u, f, h, colour):
+    """One half-sweep in place; colour 0 = red (i+j even), 1 = black."""
+    n, ld = _grid(u)
+    if u.dtype == np.float64:
+        assert f.dtype == np.float64 and f.shape == u.shape
+        _check(_load().rbgs_ref_half_sweep_f64(n, ld, h, _ptr(u), _ptr(f), colour), "half_sweep_f64")
+    elif u.dtype == np.float32:
+        assert f.dtype == np.float32 and f.shape == u.shape
+        _check(_load().rbgs_ref_half_sweep_f32(n, ld, h, _ptr(u), _ptr(f), colour), "half_sweep_f32")
+    else:
+        raise TypeError(u.dtype)
+    return u
+
+
+def sweep(u, f, h, nsweeps):
+    """nsweeps full red-then-black sweeps in place (FP64, or FP32 emulation)."""
+    n, ld = _grid(u)
+    if u.dtype == np.float64:
+        assert f.dtype == np.float64 and f.shape == u.shape
+        _check(_load().rbgs_ref_sweep_f64(n, ld, h, _ptr(u), _ptr(f), nsweeps), "sweep_f64")
+    elif u.dtype == np.float32:
+        assert f.dtype == np.float32 and f.shape == u.shape
+        _check(_load().rbgs_ref_sweep_f32(n, ld, h, _ptr(u), _ptr(f), nsweeps), "sweep_f32")
+    else:
+        raise TypeError(u.dtype)
+    return u
+
+
+def residual(u, f, h, want_field=False):
+    """(||r||_2, ||r||_2/||b||_2[, r]) in FP64 with compensated sums."""
+    n, ld = _grid(u)
+    a = _f64()
+    r = _f64()
+    field = np.zeros(u.shape, np.float64) if want_field else None
+    fp = _ptr(field) if want_field else None
+    if u.dtype == np.float64:
+        fn = _load().rbgs_ref_residual_f64
+    elif u.dtype == np.float32:
+        fn = _load().rbgs_ref_residual_f32
+    else:
+        raise TypeError(u.dtype)
+    assert f.dtype == u.dtype and f.shape == u.shape
+    _check(fn(n, ld, h, _ptr(u), _ptr(f), ctypes.byref(a), ctypes.byref(r), fp), "residual")
+    if want_field:
+        return a.value, r.value, field
+    return a.value, r.value
+
+
+def solve(u, f, h, max_sweeps, rel_tol, check_every):
+    """Sweeps until rel <= rel_tol (checked every check_every sweeps).
+
+    Returns (status, sweeps_done, rel)."""
+    n, ld = _grid(u)
+    assert u.dtype == np.float64 and f.dtype == np.float64
+    done = _i32()
+    rel = _f64()
+    rc = _check(_load().rbgs_ref_solve_f64(n, ld, h, _ptr(u), _ptr(f), max_sweeps, rel_tol,
+                                           check_every, ctypes.byref(done), ctypes.byref(rel)),
+                "solve_f64")
+    return rc, done.value, rel.value
+
+
+def ir_solve(u, f, h, inner_sweeps, max_outer, rel_tol, rhs_bf16=False):
+    """FP64 iterative refinement around FP32 inner sweeps.
+
+    Returns (status, outer_steps, rel)."""
+    n, ld = _grid(u)
+    assert u.dtype == np.float64 and f.dtype == np.float64
+    outer = _i32()
+    rel = _f64()
+    rc = _check(_load().rbgs_ref_ir_solve(n, ld, h, _ptr(u), _ptr(f), 1 if rhs_bf16 else 0,
+                                          inner_sweeps, max_outer, rel_tol,
+                                          ctypes.byref(outer), ctypes.byref(rel)),
+                "ir_solve")
+    return rc, outer.value, rel.value
+
+
+def round_bf16(x):
+    """binary32 -> bfloat16 (round to nearest even) -> binary32, elementwise."""
+    fn = _load().rbgs_ref_round_bf16
+    flat = np.asarray(x, np.float32).ravel()
+    out = np.array([fn(float(v)) for v in flat], np.float32)
+    return out.reshape(np.shape(x))
+
+
+def colour(i, j):
+    return _load().rbgs_ref_colour(i, j)
+
+
+def sweep_batched(us, fs, hs, nsweeps):
+    """Independent sweeps of many grids: a plain loop over sweep()."""
+    for u, f, h in zip(us, fs, hs):
+        sweep(u, f, h, nsweeps)
+    return us

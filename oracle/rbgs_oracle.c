@@ -1,0 +1,318 @@
+/*
+ * Oracle for red-black Gauss-Seidel on the 5-point 2D Poisson stencil.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * CPU definition that the GPU library is checked against.  Only the tests,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * GPU library neither links nor calls it, and it shares no code with the GPU
+ * library.
+ *
+ * What it computes (paper: Section 2, Eq. (1) and Algorithm 1):
+ *   - the Poisson problem  laplace(u) = f  on the unit square with Dirichlet
+ *     data g on the boundary, discretised on a uniform grid of N x N interior
+ *     points with spacing h = 1/(N+1);
+ *   - the Gauss-Seidel point update of Eq. (1),
+ *         u_ij <- 1/4 (u_{i+1,j} + u_{i-1,j} + u_{i,j+1} + u_{i,j-1} - h^2 f_ij),
+ *     where neighbours on the boundary ring take the Dirichlet value g;
+ *   - red-black ordering: red points have i+j even, black points i+j odd
+ *     (Section 2); one sweep (one "iteration" of Algorithms 1 and 2) is all
+ *     red points, then all black points.
+ *
+ * Storage: natural row-major layout with the boundary ring included.  The
+ * grid has n+2 rows of ld >= n+2 elements; element (i, j), 0 <= i, j <= n+1,
+ * is a[i*ld + j]; i is the row (x, the outer loop of Algorithm 1) and j the
+ * column (y, the inner loop).  Row 0, row n+1, column 0 and column n+1 hold g
+ * in u and are read, never written; the ring entries of f are never read.
+ *
+ * Floating point (the paper states no term order; this is the reading used
+ * throughout): the four neighbours are summed left to right in the order of
+ * Eq. (1), h^2 is the product h*h rounded once in the working precision, the
+ * product h^2*f is subtracted, the result is scaled by 1/4, and nothing is
+ * contracted into FMA (build with -ffp-contract=off).  Points of one colour
+ * never read each other (Section 2), so the loop order inside a colour and
+ * the OpenMP split of its rows cannot change a single bit.
+ *
+ * Precision: FP64 (the paper's workload; its arithmetic intensity of about
+ * 0.29 FLOP/B in Section 3 corresponds to 8-byte words).  The _f32 functions
+ * are the same algorithm with every value held and every operation rounded
+ * in IEEE binary32; they exist to check the FP32 forms of the GPU sweep.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define RBGS_REF_OK 0
+#define RBGS_REF_EINVAL (-1)
+#define RBGS_REF_ENOCONV (-3)
+#define RBGS_REF_ENOMEM (-7)
+
+#define AT(a, i, j) ((a)[(size_t)(i) * (size_t)ld + (size_t)(j)])
+
+static int bad_grid(int32_t n, int64_t ld, double h)
+{
+    return n < 1 || ld < (int64_t)n + 2 || !(h > 0.0) || !isfinite(h);
+}
+
+/* Colour of point (i, j): 0 = red (i+j even), 1 = black (i+j odd). */
+static int colour_of(int64_t i, int64_t j) { return (int)((i + j) & 1); }
+
+/* ------------------------------------------------------------------------- */
+/* FP64 half-sweep: Eq. (1) on every interior point of one colour.            */
+/* Row x starts at column 2 or 1 by the parity rule of Algorithm 1 and steps  */
+/* by two, so it visits exactly the points of the requested colour.           */
+/* ------------------------------------------------------------------------- */
+int rbgs_ref_half_sweep_f64(int32_t n, int64_t ld, double h, double *u,
+                            const double *f, int32_t colour)
+{
+    if (bad_grid(n, ld, h) || !u || !f || (colour != 0 && colour != 1))
+        return RBGS_REF_EINVAL;
+    const double h2 = h * h;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 1; i <= n; ++i) {
+        /* red: even rows start at column 2, odd rows at 1; black the reverse */
+        int64_t j_start = (i % 2 == 0) ? (colour == 0 ? 2 : 1) : (colour == 0 ? 1 : 2);
+        for (int64_t j = j_start; j <= n; j += 2) {
+            double s = AT(u, i + 1, j) + AT(u, i - 1, j);
+            s = s + AT(u, i, j + 1);
+            s = s + AT(u, i, j - 1);
+            double t = h2 * AT(f, i, j);
+            s = s - t;
+            AT(u, i, j) = 0.25 * s;
+        }
+    }
+    return RBGS_REF_OK;
+}
+
+/* nsweeps full sweeps: red half-sweep, then black half-sweep (Algorithm 2's
+ * loop runs exactly num_iterations times; the bound one lower in Algorithm 1
+ * is read as a typo). */
+int rbgs_ref_sweep_f64(int32_t n, int64_t ld, double h, double *u,
+                       const double *f, int32_t nsweeps)
+{
+    if (bad_grid(n, ld, h) || !u || !f || nsweeps < 0) return RBGS_REF_EINVAL;
+    for (int32_t it = 0; it < nsweeps; ++it) {
+        rbgs_ref_half_sweep_f64(n, ld, h, u, f, 0);
+        rbgs_ref_half_sweep_f64(n, ld, h, u, f, 1);
+    }
+    return RBGS_REF_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* FP32 emulation of the same sweep.  h^2 is h*h formed in double and rounded  */
+/* once to binary32; every other value and operation is binary32.            */
+/* ------------------------------------------------------------------------- */
+int rbgs_ref_half_sweep_f32(int32_t n, int64_t ld, double h, float *u,
+                            const float *f, int32_t colour)
+{
+    if (bad_grid(n, ld, h) || !u || !f || (colour != 0 && colour != 1))
+        return RBGS_REF_EINVAL;
+    const float h2 = (float)(h * h);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 1; i <= n; ++i) {
+        int64_t j_start = (i % 2 == 0) ? (colour == 0 ? 2 : 1) : (colour == 0 ? 1 : 2);
+        for (int64_t j = j_start; j <= n; j += 2) {
+            float s = AT(u, i + 1, j) + AT(u, i - 1, j);
+            s = s + AT(u, i, j + 1);
+            s = s + AT(u, i, j - 1);
+            float t = h2 * AT(f, i, j);
+            s = s - t;
+            AT(u, i, j) = 0.25f * s;
+        }
+    }
+    return RBGS_REF_OK;
+}
+
+int rbgs_ref_sweep_f32(int32_t n, int64_t ld, double h, float *u,
+                       const float *f, int32_t nsweeps)
+{
+    if (bad_grid(n, ld, h) || !u || !f || nsweeps < 0) return RBGS_REF_EINVAL;
+    for (int32_t it = 0; it < nsweeps; ++it) {
+        rbgs_ref_half_sweep_f32(n, ld, h, u, f, 0);
+        rbgs_ref_half_sweep_f32(n, ld, h, u, f, 1);
+    }
+    return RBGS_REF_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Residual.  The paper runs a fixed iteration count and defines no residual; */
+/* the reading used here is the residual of the discrete system A_h u = f     */
+/* whose Jacobi-form solution step is Eq. (1):                                */
+/*   (A_h u)_ij = (u_{i+1,j} + u_{i-1,j} + u_{i,j+1} + u_{i,j-1} - 4 u_ij)/h^2 */
+/*   r_ij = f_ij - (A_h u)_ij,            over the interior points,           */
+/* and the scale b = r evaluated with the interior of u set to zero (b = f    */
+/* when g = 0).  rel = ||r||_2 / ||b||_2, or ||r||_2 when ||b||_2 = 0.        */
+/* Per point: s = ((u[i+1][j] + u[i-1][j]) + u[i][j+1]) + u[i][j-1];          */
+/* r = f - (s - 4u) * (1/(h*h)), all in FP64.  Sums of squares use Neumaier's */
+/* compensated summation in row-major order.                                  */
+/* ------------------------------------------------------------------------- */
+static void neumaier_add(double *sum, double *comp, double x)
+{
+    double t = *sum + x;
+    if (fabs(*sum) >= fabs(x))
+        *comp += (*sum - t) + x;
+    else
+        *comp += (x - t) + *sum;
+    *sum = t;
+}
+
+static int on_ring(int32_t n, int64_t i, int64_t j)
+{
+    return i == 0 || j == 0 || i == (int64_t)n + 1 || j == (int64_t)n + 1;
+}
+
+/* The value of neighbour (i, j) as seen by b: the ring keeps g, the interior
+ * counts as zero. */
+#define RING_ONLY(a, i, j) (on_ring(n, (i), (j)) ? (double)AT(a, i, j) : 0.0)
+
+#define RESIDUAL_BODY(T)                                                        \
+    const double inv_h2 = 1.0 / (h * h);                                        \
+    double rs = 0.0, rc = 0.0, bs = 0.0, bc = 0.0;                              \
+    for (int64_t i = 1; i <= n; ++i) {                                          \
+        for (int64_t j = 1; j <= n; ++j) {                                      \
+            double s = (double)AT(u, i + 1, j) + (double)AT(u, i - 1, j);       \
+            s = s + (double)AT(u, i, j + 1);                                    \
+            s = s + (double)AT(u, i, j - 1);                                    \
+            double lap = (s - 4.0 * (double)AT(u, i, j)) * inv_h2;              \
+            double r = (double)AT(f, i, j) - lap;                               \
+            double sb = RING_ONLY(u, i + 1, j) + RING_ONLY(u, i - 1, j);        \
+            sb = sb + RING_ONLY(u, i, j + 1);                                   \
+            sb = sb + RING_ONLY(u, i, j - 1);                                   \
+            double b = (double)AT(f, i, j) - sb * inv_h2;                       \
+            if (r_out) AT(r_out, i, j) = r;                                     \
+            neumaier_add(&rs, &rc, r * r);                                      \
+            neumaier_add(&bs, &bc, b * b);                                      \
+        }                                                                       \
+    }                                                                           \
+    double rn = sqrt(rs + rc), bn = sqrt(bs + bc);                              \
+    if (abs_norm) *abs_norm = rn;                                               \
+    if (rel_norm) *rel_norm = (bn > 0.0) ? rn / bn : rn;                        \
+    return RBGS_REF_OK;
+
+/* r_out (optional, may be NULL): natural-layout array receiving r_ij at the
+ * interior points; its ring is left untouched. */
+int rbgs_ref_residual_f64(int32_t n, int64_t ld, double h, const double *u,
+                          const double *f, double *abs_norm, double *rel_norm,
+                          double *r_out)
+{
+    if (bad_grid(n, ld, h) || !u || !f) return RBGS_REF_EINVAL;
+    RESIDUAL_BODY(double)
+}
+
+/* Same residual of a binary32 iterate: every value is widened to FP64 first
+ * and the arithmetic is the FP64 arithmetic above. */
+int rbgs_ref_residual_f32(int32_t n, int64_t ld, double h, const float *u,
+                          const float *f, double *abs_norm, double *rel_norm,
+                          double *r_out)
+{
+    if (bad_grid(n, ld, h) || !u || !f) return RBGS_REF_EINVAL;
+    RESIDUAL_BODY(float)
+}
+
+/* ------------------------------------------------------------------------- */
+/* Solve to a relative residual: the residual is checked before the first    */
+/* sweep and after every check_every sweeps (the last group may be shorter   */
+/* so that exactly max_sweeps can be reached).  rel_tol <= 0 means "run       */
+/* exactly max_sweeps sweeps", with one residual at the end.                 */
+/* Returns 0 when rel <= rel_tol was reached (or rel_tol <= 0), else          */
+/* RBGS_REF_ENOCONV with u holding the last iterate.                          */
+/* ------------------------------------------------------------------------- */
+int rbgs_ref_solve_f64(int32_t n, int64_t ld, double h, double *u,
+                       const double *f, int32_t max_sweeps, double rel_tol,
+                       int32_t check_every, int32_t *sweeps_done,
+                       double *rel_out)
+{
+    if (bad_grid(n, ld, h) || !u || !f || max_sweeps < 0 || check_every < 1)
+        return RBGS_REF_EINVAL;
+    int32_t done = 0;
+    double rel = 0.0;
+    if (rel_tol <= 0.0) {
+        rbgs_ref_sweep_f64(n, ld, h, u, f, max_sweeps);
+        done = max_sweeps;
+        rbgs_ref_residual_f64(n, ld, h, u, f, NULL, &rel, NULL);
+        if (sweeps_done) *sweeps_done = done;
+        if (rel_out) *rel_out = rel;
+        return RBGS_REF_OK;
+    }
+    rbgs_ref_residual_f64(n, ld, h, u, f, NULL, &rel, NULL);
+    while (!(rel <= rel_tol) && done < max_sweeps) {
+        int32_t k = max_sweeps - done < check_every ? max_sweeps - done : check_every;
+        rbgs_ref_sweep_f64(n, ld, h, u, f, k);
+        done += k;
+        rbgs_ref_residual_f64(n, ld, h, u, f, NULL, &rel, NULL);
+    }
+    if (sweeps_done) *sweeps_done = done;
+    if (rel_out) *rel_out = rel;
+    return rel <= rel_tol ? RBGS_REF_OK : RBGS_REF_ENOCONV;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Round a binary32 value to bfloat16 (8 significand bits, round to nearest, */
+/* ties to even) and widen it back to binary32.  NaN stays NaN.               */
+/* ------------------------------------------------------------------------- */
+float rbgs_ref_round_bf16(float x)
+{
+    uint32_t bits;
+    memcpy(&bits, &x, sizeof bits);
+    if ((bits & 0x7f800000u) == 0x7f800000u && (bits & 0x007fffffu) != 0u) {
+        bits |= 0x00400000u; /* quiet NaN */
+    } else {
+        uint32_t lsb = (bits >> 16) & 1u;
+        bits += 0x7fffu + lsb;
+    }
+    bits &= 0xffff0000u;
+    float y;
+    memcpy(&y, &bits, sizeof y);
+    return y;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Mixed-precision iterative refinement (not in the paper; the outer loop is  */
+/* classical iterative refinement around the FP32 sweep above):               */
+/*   repeat: r = f - A_h u in FP64 (the residual above), stop when            */
+/*           rel <= rel_tol; round r to binary32 (rhs_bf16 != 0: then further */
+/*           to bfloat16); e = 0 with a zero ring; inner_sweeps FP32 sweeps   */
+/*           of A_h e = r; u <- u + e in FP64 at the interior points.          */
+/* The residual is checked before each outer step; the ring of u is g and is  */
+/* never written.  Returns 0 when converged, RBGS_REF_ENOCONV otherwise.      */
+/* ------------------------------------------------------------------------- */
+int rbgs_ref_ir_solve(int32_t n, int64_t ld, double h, double *u,
+                      const double *f, int32_t rhs_bf16, int32_t inner_sweeps,
+                      int32_t max_outer, double rel_tol, int32_t *outer_done,
+                      double *rel_out)
+{
+    if (bad_grid(n, ld, h) || !u || !f || inner_sweeps < 1 || max_outer < 0)
+        return RBGS_REF_EINVAL;
+    size_t cells = (size_t)(n + 2) * (size_t)ld;
+    double *r = (double *)calloc(cells, sizeof(double));
+    float *r32 = (float *)calloc(cells, sizeof(float));
+    float *e = (float *)calloc(cells, sizeof(float));
+    if (!r || !r32 || !e) {
+        free(r); free(r32); free(e);
+        return RBGS_REF_ENOMEM;
+    }
+    int32_t outer = 0;
+    double rel = 0.0;
+    rbgs_ref_residual_f64(n, ld, h, u, f, NULL, &rel, r);
+    while (!(rel <= rel_tol) && outer < max_outer) {
+        for (int64_t i = 1; i <= n; ++i)
+            for (int64_t j = 1; j <= n; ++j) {
+                float v = (float)AT(r, i, j);
+                AT(r32, i, j) = rhs_bf16 ? rbgs_ref_round_bf16(v) : v;
+            }
+        memset(e, 0, cells * sizeof(float));
+        rbgs_ref_sweep_f32(n, ld, h, e, r32, inner_sweeps);
+        for (int64_t i = 1; i <= n; ++i)
+            for (int64_t j = 1; j <= n; ++j)
+                AT(u, i, j) = AT(u, i, j) + (double)AT(e, i, j);
+        ++outer;
+        rbgs_ref_residual_f64(n, ld, h, u, f, NULL, &rel, r);
+    }
+    free(r); free(r32); free(e);
+    if (outer_done) *outer_done = outer;
+    if (rel_out) *rel_out = rel;
+    return rel <= rel_tol ? RBGS_REF_OK : RBGS_REF_ENOCONV;
+}
+
+/* Colour query used by the tests to check the colouring convention. */
+int32_t rbgs_ref_colour(int64_t i, int64_t j) { return colour_of(i, j); }

@@ -1,0 +1,72 @@
+"""The pins have teeth: plant plausible mistakes in a copy of the oracle
+source, build it on the CPU, and check that the pins reject every mutant."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import build as obuild
+from tests import closed_form as cf
+from tests import test_oracle_pins as pins
+
+MUTANTS = {
+    "dropped_left_neighbour": ("s = s + AT(u, i, j - 1);\n            double t = h2", "double t = h2"),
+    "wrong_sign_of_f": ("s = s - t;\n            AT(u, i, j) = 0.25 * s;", "s = s + t;\n            AT(u, i, j) = 0.25 * s;"),
+    "wrong_index_up": ("double s = AT(u, i + 1, j) + AT(u, i - 1, j);\n            s = s + AT(u, i, j + 1);\n            s = s + AT(u, i, j - 1);\n            double t = h2 * AT(f, i, j);\n            s = s - t;\n            AT(u, i, j) = 0.25 * s;",
+                       "double s = AT(u, i + 1, j) + AT(u, i + 1, j);\n            s = s + AT(u, i, j + 1);\n            s = s + AT(u, i, j - 1);\n            double t = h2 * AT(f, i, j);\n            s = s - t;\n            AT(u, i, j) = 0.25 * s;"),
+    "colours_swapped": ("(i % 2 == 0) ? (colour == 0 ? 2 : 1) : (colour == 0 ? 1 : 2);\n        for (int64_t j = j_start; j <= n; j += 2) {\n            double",
+                        "(i % 2 == 0) ? (colour == 0 ? 1 : 2) : (colour == 0 ? 2 : 1);\n        for (int64_t j = j_start; j <= n; j += 2) {\n            double"),
+    "black_before_red": ("rbgs_ref_half_sweep_f64(n, ld, h, u, f, 0);\n        rbgs_ref_half_sweep_f64(n, ld, h, u, f, 1);",
+                         "rbgs_ref_half_sweep_f64(n, ld, h, u, f, 1);\n        rbgs_ref_half_sweep_f64(n, ld, h, u, f, 0);"),
+    "residual_missing_centre": ("double lap = (s - 4.0 * (double)AT(u, i, j)) * inv_h2;",
+                                "double lap = (s - 2.0 * (double)AT(u, i, j)) * inv_h2;"),
+    "h_not_squared": ("const double h2 = h * h;\n#pragma omp parallel for schedule(static)\n    for (int64_t i = 1; i <= n; ++i) {\n        /* red",
+                      "const double h2 = h;\n#pragma omp parallel for schedule(static)\n    for (int64_t i = 1; i <= n; ++i) {\n        /* red"),
+}
+
+
+def _build_mutant(tmp_path, name):
+    src = open(obuild.SRC).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) >= 1, name
+    mutated = src.replace(old, new, 1)
+    path = os.path.join(str(tmp_path), f"rbgs_{name}.c")
+    lib = os.path.join(str(tmp_path), f"lib_{name}.so")
+    with open(path, "w") as fh:
+        fh.write(mutated)
+    subprocess.run(["gcc", *obuild.CFLAGS, path, "-o", lib, "-lm"], check=True)
+    return lib
+
+
+def _pins_that_run():
+    """A small set of pins; a mutant must fail at least one."""
+    yield lambda: pins.test_half_sweep_visits_exactly_algorithm1_points(oracle)
+    yield lambda: pins.test_n1_single_point(oracle)
+    yield lambda: pins.test_single_mode_iterate(oracle, 15, 40)
+    yield lambda: pins.test_multi_mode_iterate(oracle)
+    yield lambda: pins.test_converges_to_dense_solve(oracle, 9)
+    yield lambda: pins.test_residual_special_cases(oracle)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_mutant(tmp_path, name):
+    lib = _build_mutant(tmp_path, name)
+    caught = 0
+    with oracle.use_library(lib):
+        for pin in _pins_that_run():
+            try:
+                pin()
+            except AssertionError:
+                caught += 1
+    assert caught >= 1, f"mutant {name} passed every pin"
+
+
+def test_unmutated_source_passes(tmp_path):
+    src_copy = os.path.join(str(tmp_path), "lib_clean.so")
+    subprocess.run(["gcc", *obuild.CFLAGS, obuild.SRC, "-o", src_copy, "-lm"], check=True)
+    with oracle.use_library(src_copy):
+        for pin in _pins_that_run():
+            pin()
