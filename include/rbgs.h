@@ -1,0 +1,196 @@
+/*
+ * rbgs.h - red-black Gauss-Seidel for the 5-point 2D Poisson stencil on
+ * AMD Instinct MI355X (gfx950).  C ABI of librbgs.so.
+ *
+ * The method (paper, Section 2): laplace(u) = f on the unit square with
+ * Dirichlet data u = g on the boundary, N x N interior points, spacing
+ * h = 1/(N+1), point update Eq. (1)
+ *     u_ij <- 1/4 (u_{i+1,j} + u_{i-1,j} + u_{i,j+1} + u_{i,j-1} - h^2 f_ij),
+ * red points (i+j even) first, then black points (i+j odd); one red and one
+ * black half-sweep form one full sweep (one iteration of Algorithms 1 and 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid arrays (u, f) are DEVICE pointers owned by the caller, in the natural
+ * row-major layout with the boundary ring included: n+2 rows of ld >= n+2
+ * elements, element (i, j) at a[i*ld + j], 0 <= i, j <= n+1; i is the row
+ * (the outer loop of Algorithm 1), j the column.  In u the ring (row 0, row
+ * n+1, column 0, column n+1) holds g and is read, never written; the ring of
+ * f is never read.  u is in/out.
+ *
+ * Arithmetic: the four neighbours are summed in the order written in Eq. (1)
+ * (i+1, i-1, j+1, j-1), then h^2*f is subtracted and the sum scaled by 1/4;
+ * h^2 = h*h is formed in FP64 and rounded once to the working precision; no
+ * FMA contraction.  With these rules the FP64 sweep reproduces, bit for bit,
+ * any correct sequential red-black Gauss-Seidel that uses the same order.
+ *
+ * Scratch: the library never allocates device memory.  Entry points that
+ * need scratch take a caller-owned device workspace of at least the size
+ * returned by the matching *_workspace_size call, 256-byte aligned.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  All
+ * device work is enqueued on it.  Entry points that return host values
+ * (residual norms, solve statistics) synchronise that stream; rbgs_sweep
+ * and rbgs_sweep_batched do not.
+ *
+ * Errors: every entry point returns RBGS_OK (0) or a negative rbgs_status.
+ * Argument checks run before any device work, so RBGS_EINVAL and
+ * RBGS_EWORKSPACE leave every buffer untouched.  rbgs_last_error() gives a
+ * human-readable message for the calling thread's last failure.
+ * Calls on different streams with disjoint buffers are independent.
+ */
+#ifndef RBGS_H
+#define RBGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RBGS_OK = 0,
+    RBGS_EINVAL = -1,       /* bad argument (size, pointer, h, count, ...) */
+    RBGS_EHIP = -2,         /* a HIP runtime call or kernel launch failed  */
+    RBGS_ENOCONV = -3,      /* tolerance not reached within the sweep cap  */
+    RBGS_ETIMEOUT = -4,     /* a bounded wait in the persistent kernel expired */
+    RBGS_ENONFINITE = -5,   /* the residual became NaN or infinite         */
+    RBGS_EUNSUPPORTED = -6, /* valid but not implemented (e.g. omega != 1) */
+    RBGS_EWORKSPACE = -8    /* workspace missing, too small or misaligned  */
+} rbgs_status;
+
+typedef enum {
+    RBGS_F64 = 0, /* IEEE binary64 storage and arithmetic */
+    RBGS_F32 = 1  /* IEEE binary32 storage and arithmetic */
+} rbgs_dtype;
+
+typedef enum {
+    RBGS_KERNEL_AUTO = 0,    /* library choice                                  */
+    RBGS_KERNEL_PLAIN = 1,   /* one kernel launch per half-sweep (Algorithm 1's
+                                barrier after every colour)                     */
+    RBGS_KERNEL_BLOCKED = 2  /* persistent, temporally blocked kernel: several
+                                half-sweeps per pass over HBM, tiles ordered by
+                                per-tile progress flags instead of grid-wide
+                                barriers (the dependency idea of Algorithm 2)   */
+} rbgs_kernel;
+
+typedef enum {
+    RBGS_PREC_F64 = 0,        /* plain sweeps in the storage precision          */
+    RBGS_PREC_F32_IR = 1,     /* FP64 residual + correction, FP32 inner sweeps  */
+    RBGS_PREC_BF16RHS_IR = 2  /* as above with the inner rhs rounded to bfloat16 */
+} rbgs_precision;
+
+/* One grid: N = n interior points per side, row pitch ld (elements), h. */
+typedef struct {
+    int32_t n;   /* interior points per side, 1 <= n <= 65533         */
+    int64_t ld;  /* row pitch in elements, ld >= n + 2                */
+    double h;    /* grid spacing, finite and > 0 (1/(n+1) on [0,1]^2) */
+} rbgs_grid;
+
+/* Optional per-call timing, filled when rbgs_sweep_opts.timing != NULL
+ * (in rbgs_sweep, or in rbgs_solve through rbgs_solve_opts.sweep).  The
+ * library then brackets its kernel groups with HIP events on `stream` and
+ * synchronises the stream before returning; in a solve, sweep_ms sums the
+ * sweep groups between residual checks. */
+typedef struct {
+    float pack_ms;          /* natural -> split packing of u and f            */
+    float sweep_ms;         /* all sweep kernels (half-sweeps or blocked passes) */
+    float unpack_ms;        /* split -> natural unpacking of u                */
+    int32_t sweep_launches; /* kernel launches inside sweep_ms                */
+} rbgs_timing;
+
+/* Kernel selection for sweeps.  Zero-initialise for the library defaults. */
+typedef struct {
+    int32_t kernel;     /* rbgs_kernel                                         */
+    int32_t fuse;       /* BLOCKED: full sweeps per pass, 0 = default          */
+    int32_t tile_rows;  /* BLOCKED: interior rows per tile, 0 = default        */
+    int32_t tile_cols;  /* BLOCKED: interior columns per tile, 0 = default     */
+    int32_t rows_per_block; /* PLAIN: rows each workgroup marches, 0 = default */
+    int32_t debug_delay;    /* BLOCKED: >0 injects pseudo-random per-tile delays
+                               (schedule stress); results must not change      */
+    int32_t debug_spin_limit; /* BLOCKED: >0 bounds each flag wait to this many
+                               polls (watchdog tests); 0 = default bound       */
+    rbgs_timing *timing;    /* HOST pointer or NULL (see rbgs_timing)          */
+} rbgs_sweep_opts;
+
+/* Solve options.  Zero-initialise, then set what is needed. */
+typedef struct {
+    int32_t max_sweeps;    /* cap on full sweeps (all inner sweeps in IR modes) */
+    double rel_tol;        /* stop at ||r||_2/||b||_2 <= rel_tol; <= 0: run
+                              exactly max_sweeps sweeps                       */
+    int32_t check_every;   /* full sweeps between residual checks, >= 1        */
+    int32_t precision;     /* rbgs_precision; IR modes need RBGS_F64 storage   */
+    int32_t inner_sweeps;  /* IR: FP32 sweeps per outer step (0 = check_every) */
+    double omega;          /* relaxation; only 1.0 (plain Gauss-Seidel)        */
+    rbgs_sweep_opts sweep; /* kernel choice for the (inner) sweeps             */
+} rbgs_solve_opts;
+
+typedef struct {
+    int32_t sweeps;        /* full sweeps performed (inner sweeps in IR)       */
+    int32_t outer_iters;   /* IR outer steps performed (0 for plain solves)    */
+    double rel_residual;   /* final ||r||_2/||b||_2 (||r||_2 if ||b||_2 = 0)   */
+    double abs_residual;   /* final ||r||_2                                    */
+    int32_t status;        /* same value as the return code                    */
+} rbgs_solve_info;
+
+/* Size in bytes of the workspace that rbgs_sweep, rbgs_residual and
+ * rbgs_solve need for grid g and storage type dt; `opts` (may be NULL)
+ * selects the solve mode (IR modes need more).  Returns 0 for invalid
+ * arguments. */
+size_t rbgs_workspace_size(const rbgs_grid *g, rbgs_dtype dt,
+                           const rbgs_solve_opts *opts);
+
+/* nsweeps full red-black sweeps of u in place (Eq. (1); red half-sweep then
+ * black half-sweep, Algorithms 1 and 2).  u, f: device arrays as above, of
+ * type dt.  nsweeps >= 0 (0 is a no-op).  opts may be NULL (defaults).
+ * Every kernel choice gives the same bits.  Asynchronous on `stream`. */
+int rbgs_sweep(const rbgs_grid *g, rbgs_dtype dt, void *u, const void *f,
+               int32_t nsweeps, const rbgs_sweep_opts *opts, void *workspace,
+               size_t workspace_bytes, void *stream);
+
+/* Residual of the discrete system whose Gauss-Seidel step is Eq. (1):
+ *   r_ij = f_ij - (u_{i+1,j} + u_{i-1,j} + u_{i,j+1} + u_{i,j-1} - 4 u_ij)/h^2
+ * over the interior, and b = r evaluated with the interior of u set to zero
+ * (b = f for g = 0).  Writes ||r||_2 to *abs_norm and ||r||_2/||b||_2 (or
+ * ||r||_2 when ||b||_2 = 0) to *rel_norm, both HOST pointers (either may be
+ * NULL).  All arithmetic in FP64 (FP32 data is widened); the sums of squares
+ * are reduced in a fixed order, so repeated calls give identical bits.
+ * Synchronises `stream`. */
+int rbgs_residual(const rbgs_grid *g, rbgs_dtype dt, const void *u,
+                  const void *f, double *abs_norm, double *rel_norm,
+                  void *workspace, size_t workspace_bytes, void *stream);
+
+/* Sweeps until rel <= opts->rel_tol or opts->max_sweeps sweeps.  The
+ * residual is evaluated before the first sweep and after every check_every
+ * sweeps (the last group is shortened to end exactly at max_sweeps).
+ * RBGS_PREC_F64: plain sweeps in dt.  IR modes (dt must be RBGS_F64): each
+ * outer step computes r = f - A_h u in FP64, stops if rel <= rel_tol, rounds
+ * r to FP32 (or bfloat16), runs inner_sweeps FP32 sweeps of A_h e = r from
+ * e = 0 with a zero ring, and adds e to u in FP64.  info (HOST, may be NULL)
+ * receives the statistics.  Returns RBGS_OK, RBGS_ENOCONV (u holds the last
+ * iterate), RBGS_ENONFINITE, or an error.  Synchronises `stream`. */
+int rbgs_solve(const rbgs_grid *g, rbgs_dtype dt, void *u, const void *f,
+               const rbgs_solve_opts *opts, rbgs_solve_info *info,
+               void *workspace, size_t workspace_bytes, void *stream);
+
+/* Device-memory bandwidth probe: the copy (kind 0: b = a) and triad
+ * (kind 1: a = b + s*c) kernels of the STREAM benchmark, which the paper
+ * uses for the attainable memory bandwidth in its roofline (Section 3,
+ * Eq. (2)).  a, b, c: DEVICE arrays of n_elems FP64 values, 16-byte
+ * aligned, n_elems even and > 0 (c unused for copy).  Asynchronous on
+ * `stream`; time it with events around the call. */
+int rbgs_stream_probe(int32_t kind, double *a, double *b, double *c,
+                      int64_t n_elems, double s, void *stream);
+
+/* Human-readable name of a status code (static string). */
+const char *rbgs_strerror(int status);
+
+/* Message describing the calling thread's last failure (static per thread). */
+const char *rbgs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBGS_H */

@@ -1,0 +1,13 @@
+"""MI355X-native red-black Gauss-Seidel for the 5-point 2D Poisson stencil.
+
+The solver lives in librbgs.so (HIP kernels for gfx950 behind the C ABI of
+include/rbgs.h); this package is its Python binding.  Importing the package
+fails loudly when the library has not been built.
+"""
+from .rbgs import (  # noqa: F401
+    EXPORTED, RbgsError, make_grid, rbgs_last_error, rbgs_residual, rbgs_solve,
+    rbgs_stream_probe, rbgs_strerror, rbgs_sweep, rbgs_workspace_size,
+)
+
+__all__ = ["rbgs_sweep", "rbgs_residual", "rbgs_solve", "rbgs_workspace_size",
+           "rbgs_stream_probe", "rbgs_strerror", "rbgs_last_error", "make_grid", "RbgsError", "EXPORTED"]

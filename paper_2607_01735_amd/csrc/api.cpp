@@ -1,0 +1,491 @@
+// Host side of librbgs.so: argument validation, workspace carving, kernel
+// dispatch and the solve drivers.  The public contract is include/rbgs.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "rbgs.h"
+#include "rbgs_internal.h"
+#include "rbgs_blocked.h"
+
+using namespace rbgs;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int fail(int status, const std::string& msg) {
+    g_last_error = msg;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(RBGS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+constexpr int kMaxN = 65533;  // n + 2 rows must fit a grid dimension
+
+bool valid_grid(const rbgs_grid* g, std::string* why) {
+    if (!g) { *why = "grid is NULL"; return false; }
+    if (g->n < 1 || g->n > kMaxN) { *why = "n must be in [1, 65533]"; return false; }
+    if (g->ld < int64_t(g->n) + 2) { *why = "ld must be >= n + 2"; return false; }
+    if (!(g->h > 0.0) || !std::isfinite(g->h)) { *why = "h must be finite and > 0"; return false; }
+    return true;
+}
+
+size_t elem_size(rbgs_dtype dt) { return dt == RBGS_F64 ? 8 : 4; }
+bool valid_dtype(int dt) { return dt == RBGS_F64 || dt == RBGS_F32; }
+
+// The device allocation that contains [p, p + bytes) must exist.
+int check_device_range(const void* p, size_t bytes, const char* name) {
+    if (!p) return fail(RBGS_EINVAL, std::string(name) + " is NULL");
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof attr);
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RBGS_EINVAL, std::string(name) + " is not a device pointer");
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return fail(RBGS_EINVAL, std::string(name) + " is not device memory");
+    void* base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(reinterpret_cast<hipDeviceptr_t*>(&base), &size,
+                              const_cast<void*>(p));
+    if (e == hipSuccess && base) {
+        size_t off = size_t(static_cast<const char*>(p) - static_cast<const char*>(base));
+        if (off + bytes > size)
+            return fail(RBGS_EINVAL, std::string(name) + " allocation is smaller than the grid");
+    } else {
+        (void)hipGetLastError();
+    }
+    return RBGS_OK;
+}
+
+size_t grid_bytes(const rbgs_grid* g, rbgs_dtype dt) {
+    return (size_t(g->n + 1) * size_t(g->ld) + size_t(g->n) + 2) * elem_size(dt);
+}
+
+// Workspace carving.  All pieces 256-byte aligned.
+struct Workspace {
+    int64_t pitch = 0;      // split pitch of the storage type
+    int64_t pitch32 = 0;    // split pitch of FP32 refinement arrays
+    void* u_red = nullptr;
+    void* u_black = nullptr;
+    void* f_red = nullptr;
+    void* f_black = nullptr;
+    double* partials = nullptr;
+    double* sums = nullptr;  // 2 doubles: sum r^2, sum b^2
+    float* e_red = nullptr;  // refinement: correction and its right-hand side
+    float* e_black = nullptr;
+    float* r_red = nullptr;
+    float* r_black = nullptr;
+    void* blocked = nullptr;  // persistent-kernel state (flags, ticket, error word)
+    size_t blocked_bytes = 0;
+    size_t total = 0;
+};
+
+bool is_ir(const rbgs_solve_opts* o) {
+    return o && (o->precision == RBGS_PREC_F32_IR || o->precision == RBGS_PREC_BF16RHS_IR);
+}
+
+Workspace plan_workspace(const rbgs_grid* g, rbgs_dtype dt, bool ir, char* base) {
+    Workspace w;
+    const int n = g->n;
+    const size_t es = elem_size(dt);
+    w.pitch = split_pitch(n, es);
+    const size_t colour = align256(size_t(n + 2) * size_t(w.pitch) * es);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return static_cast<void*>(p);
+    };
+    w.u_red = take(colour);
+    w.u_black = take(colour);
+    w.f_red = take(colour);
+    w.f_black = take(colour);
+    int slots = residual_partial_slots(n, w.pitch, es);
+    int nslots = residual_natural_partial_slots(n);
+    if (nslots > slots) slots = nslots;
+    w.partials = static_cast<double*>(take(size_t(slots) * 2 * sizeof(double)));
+    w.sums = static_cast<double*>(take(256));
+    w.blocked_bytes = blocked_state_bytes(n, dt == RBGS_F64 ? 8 : 4);
+    w.blocked = take(w.blocked_bytes);
+    if (ir) {
+        w.pitch32 = split_pitch(n, 4);
+        const size_t c32 = align256(size_t(n + 2) * size_t(w.pitch32) * 4);
+        w.e_red = static_cast<float*>(take(c32));
+        w.e_black = static_cast<float*>(take(c32));
+        w.r_red = static_cast<float*>(take(c32));
+        w.r_black = static_cast<float*>(take(c32));
+    }
+    w.total = off;
+    return w;
+}
+
+int check_workspace(void* ws, size_t ws_bytes, size_t need) {
+    if (!ws) return fail(RBGS_EWORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return fail(RBGS_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(RBGS_EWORKSPACE, "workspace too small: need " + std::to_string(need) +
+                                         " bytes, got " + std::to_string(ws_bytes));
+    return check_device_range(ws, need, "workspace");
+}
+
+int validate_sweep_opts(const rbgs_sweep_opts* o) {
+    if (!o) return RBGS_OK;
+    if (o->kernel < RBGS_KERNEL_AUTO || o->kernel > RBGS_KERNEL_BLOCKED)
+        return fail(RBGS_EINVAL, "unknown kernel");
+    if (o->fuse < 0 || o->tile_rows < 0 || o->tile_cols < 0 || o->rows_per_block < 0 ||
+        o->debug_delay < 0 || o->debug_spin_limit < 0)
+        return fail(RBGS_EINVAL, "sweep options must be >= 0");
+    if (o->rows_per_block > 4096) return fail(RBGS_EINVAL, "rows_per_block must be <= 4096");
+    return validate_blocked_opts(o->fuse, o->tile_rows, o->tile_cols, &g_last_error);
+}
+
+// Half-sweeps on the split arrays already in the workspace.
+template <typename T>
+int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rbgs_sweep_opts* o,
+               hipStream_t s, int* launches) {
+    const int n = g->n;
+    const T h2 = T(g->h * g->h);
+    T* ur = static_cast<T*>(w.u_red);
+    T* ub = static_cast<T*>(w.u_black);
+    const T* fr = static_cast<const T*>(w.f_red);
+    const T* fb = static_cast<const T*>(w.f_black);
+    int kernel = o ? o->kernel : RBGS_KERNEL_AUTO;
+    if (kernel == RBGS_KERNEL_AUTO) kernel = auto_kernel(n, sizeof(T));
+    *launches = 0;
+    if (kernel == RBGS_KERNEL_BLOCKED) {
+        BlockedParams bp = blocked_params(n, sizeof(T), o);
+        int err = 0;
+        hipError_t e = run_blocked<T>(ur, ub, fr, fb, n, w.pitch, h2, nsweeps, bp, w.blocked,
+                                      w.blocked_bytes, s, launches, &err);
+        if (e != hipSuccess) return hip_fail(e, "blocked sweep");
+        return RBGS_OK;
+    }
+    const int rows = o ? o->rows_per_block : 0;
+    for (int32_t it = 0; it < nsweeps; ++it) {
+        HIP_TRY(launch_half_sweep<T>(ur, ub, fr, n, w.pitch, h2, 0, rows, s), "red half-sweep");
+        HIP_TRY(launch_half_sweep<T>(ub, ur, fb, n, w.pitch, h2, 1, rows, s), "black half-sweep");
+        *launches += 2;
+    }
+    return RBGS_OK;
+}
+
+int run_sweeps_dt(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w, int32_t nsweeps,
+                  const rbgs_sweep_opts* o, hipStream_t s, int* launches) {
+    return dt == RBGS_F64 ? run_sweeps<double>(g, w, nsweeps, o, s, launches)
+                          : run_sweeps<float>(g, w, nsweeps, o, s, launches);
+}
+
+// Reads the two device sums, synchronising the stream.
+int fetch_norms(const Workspace& w, hipStream_t s, double* abs_norm, double* rel_norm) {
+    double host[2] = {0.0, 0.0};
+    HIP_TRY(hipMemcpyAsync(host, w.sums, sizeof host, hipMemcpyDeviceToHost, s), "norm copy");
+    HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+    double rn = std::sqrt(host[0]);
+    double bn = std::sqrt(host[1]);
+    if (abs_norm) *abs_norm = rn;
+    if (rel_norm) *rel_norm = bn > 0.0 ? rn / bn : rn;
+    return RBGS_OK;
+}
+
+template <typename T>
+int split_residual(const rbgs_grid* g, const Workspace& w, hipStream_t s, float* r_red,
+                   float* r_black, int rhs_bf16) {
+    HIP_TRY(launch_residual_split<T>(static_cast<const T*>(w.u_red),
+                                     static_cast<const T*>(w.u_black),
+                                     static_cast<const T*>(w.f_red),
+                                     static_cast<const T*>(w.f_black), g->n, w.pitch,
+                                     1.0 / (g->h * g->h), w.partials, w.sums, r_red, r_black,
+                                     w.pitch32, rhs_bf16, s),
+            "residual");
+    return RBGS_OK;
+}
+
+int split_residual_dt(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w, hipStream_t s) {
+    return dt == RBGS_F64 ? split_residual<double>(g, w, s, nullptr, nullptr, 0)
+                          : split_residual<float>(g, w, s, nullptr, nullptr, 0);
+}
+
+struct EventTimer {
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool on = false;
+    hipError_t init(bool enable) {
+        on = enable;
+        if (!on) return hipSuccess;
+        for (auto& e : ev) {
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
+    hipError_t mark(int k, hipStream_t s) { return on ? hipEventRecord(ev[k], s) : hipSuccess; }
+    ~EventTimer() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// Accumulates the time of sweep groups inside a solve (events on the stream;
+// every group is followed by a synchronising residual fetch).
+struct GroupTimer {
+    EventTimer t;
+    rbgs_timing acc{0.f, 0.f, 0.f, 0};
+    hipError_t begin(hipStream_t s) { return t.mark(1, s); }
+    hipError_t end(hipStream_t s) { return t.mark(2, s); }
+    hipError_t collect(int launches) {
+        if (!t.on) return hipSuccess;
+        hipError_t e = hipEventSynchronize(t.ev[2]);
+        if (e != hipSuccess) return e;
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, t.ev[1], t.ev[2]);
+        acc.sweep_ms += ms;
+        acc.sweep_launches += launches;
+        return e;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* rbgs_strerror(int status) {
+    switch (status) {
+        case RBGS_OK: return "RBGS_OK";
+        case RBGS_EINVAL: return "RBGS_EINVAL: invalid argument";
+        case RBGS_EHIP: return "RBGS_EHIP: HIP runtime error";
+        case RBGS_ENOCONV: return "RBGS_ENOCONV: tolerance not reached";
+        case RBGS_ETIMEOUT: return "RBGS_ETIMEOUT: dependency wait timed out";
+        case RBGS_ENONFINITE: return "RBGS_ENONFINITE: non-finite residual";
+        case RBGS_EUNSUPPORTED: return "RBGS_EUNSUPPORTED: unsupported option";
+        case RBGS_EWORKSPACE: return "RBGS_EWORKSPACE: bad workspace";
+        default: return "unknown rbgs status";
+    }
+}
+
+const char* rbgs_last_error(void) { return g_last_error.c_str(); }
+
+size_t rbgs_workspace_size(const rbgs_grid* g, rbgs_dtype dt, const rbgs_solve_opts* opts) {
+    std::string why;
+    if (!valid_grid(g, &why) || !valid_dtype(dt)) return 0;
+    return plan_workspace(g, dt, is_ir(opts) && dt == RBGS_F64, nullptr).total;
+}
+
+int rbgs_sweep(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f, int32_t nsweeps,
+               const rbgs_sweep_opts* opts, void* workspace, size_t workspace_bytes,
+               void* stream) {
+    std::string why;
+    if (!valid_grid(g, &why)) return fail(RBGS_EINVAL, why);
+    if (!valid_dtype(dt)) return fail(RBGS_EINVAL, "unknown dtype");
+    if (nsweeps < 0) return fail(RBGS_EINVAL, "nsweeps must be >= 0");
+    int rc = validate_sweep_opts(opts);
+    if (rc) return fail(rc, g_last_error);
+    Workspace plan = plan_workspace(g, dt, false, nullptr);
+    if ((rc = check_workspace(workspace, workspace_bytes, plan.total))) return rc;
+    if ((rc = check_device_range(u, grid_bytes(g, dt), "u"))) return rc;
+    if ((rc = check_device_range(f, grid_bytes(g, dt), "f"))) return rc;
+    if (nsweeps == 0) {
+        if (opts && opts->timing) *opts->timing = rbgs_timing{0.f, 0.f, 0.f, 0};
+        return RBGS_OK;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace w = plan_workspace(g, dt, false, static_cast<char*>(workspace));
+    const int es = int(elem_size(dt));
+    EventTimer tm;
+    HIP_TRY(tm.init(opts && opts->timing), "event create");
+    HIP_TRY(tm.mark(0, s), "event record");
+    HIP_TRY(launch_pack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, es, s), "pack u");
+    HIP_TRY(launch_pack(f, g->ld, w.f_red, w.f_black, g->n, w.pitch, es, s), "pack f");
+    HIP_TRY(tm.mark(1, s), "event record");
+    int launches = 0;
+    if ((rc = run_sweeps_dt(dt, g, w, nsweeps, opts, s, &launches))) return rc;
+    HIP_TRY(tm.mark(2, s), "event record");
+    HIP_TRY(launch_unpack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, es, s), "unpack u");
+    HIP_TRY(tm.mark(3, s), "event record");
+    if (tm.on) {
+        HIP_TRY(hipEventSynchronize(tm.ev[3]), "event synchronise");
+        rbgs_timing t{0.f, 0.f, 0.f, launches};
+        HIP_TRY(hipEventElapsedTime(&t.pack_ms, tm.ev[0], tm.ev[1]), "event time");
+        HIP_TRY(hipEventElapsedTime(&t.sweep_ms, tm.ev[1], tm.ev[2]), "event time");
+        HIP_TRY(hipEventElapsedTime(&t.unpack_ms, tm.ev[2], tm.ev[3]), "event time");
+        *opts->timing = t;
+    }
+    return blocked_check_error(w.blocked, s, &g_last_error);
+}
+
+int rbgs_residual(const rbgs_grid* g, rbgs_dtype dt, const void* u, const void* f,
+                  double* abs_norm, double* rel_norm, void* workspace, size_t workspace_bytes,
+                  void* stream) {
+    std::string why;
+    if (!valid_grid(g, &why)) return fail(RBGS_EINVAL, why);
+    if (!valid_dtype(dt)) return fail(RBGS_EINVAL, "unknown dtype");
+    Workspace plan = plan_workspace(g, dt, false, nullptr);
+    int rc;
+    if ((rc = check_workspace(workspace, workspace_bytes, plan.total))) return rc;
+    if ((rc = check_device_range(u, grid_bytes(g, dt), "u"))) return rc;
+    if ((rc = check_device_range(f, grid_bytes(g, dt), "f"))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace w = plan_workspace(g, dt, false, static_cast<char*>(workspace));
+    const double inv_h2 = 1.0 / (g->h * g->h);
+    if (dt == RBGS_F64)
+        HIP_TRY(launch_residual_natural<double>(static_cast<const double*>(u),
+                                                static_cast<const double*>(f), g->n, g->ld,
+                                                inv_h2, w.partials, w.sums, s),
+                "residual");
+    else
+        HIP_TRY(launch_residual_natural<float>(static_cast<const float*>(u),
+                                               static_cast<const float*>(f), g->n, g->ld, inv_h2,
+                                               w.partials, w.sums, s),
+                "residual");
+    return fetch_norms(w, s, abs_norm, rel_norm);
+}
+
+int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
+               const rbgs_solve_opts* o, rbgs_solve_info* info, void* workspace,
+               size_t workspace_bytes, void* stream) {
+    std::string why;
+    if (!valid_grid(g, &why)) return fail(RBGS_EINVAL, why);
+    if (!valid_dtype(dt)) return fail(RBGS_EINVAL, "unknown dtype");
+    if (!o) return fail(RBGS_EINVAL, "solve options are NULL");
+    if (o->max_sweeps < 0) return fail(RBGS_EINVAL, "max_sweeps must be >= 0");
+    if (o->check_every < 1) return fail(RBGS_EINVAL, "check_every must be >= 1");
+    if (std::isnan(o->rel_tol)) return fail(RBGS_EINVAL, "rel_tol is NaN");
+    if (o->precision < RBGS_PREC_F64 || o->precision > RBGS_PREC_BF16RHS_IR)
+        return fail(RBGS_EINVAL, "unknown precision");
+    if (o->inner_sweeps < 0) return fail(RBGS_EINVAL, "inner_sweeps must be >= 0");
+    if (o->omega != 1.0)
+        return fail(RBGS_EUNSUPPORTED, "only omega = 1 (Gauss-Seidel) is implemented");
+    const bool ir = is_ir(o);
+    if (ir && dt != RBGS_F64)
+        return fail(RBGS_EINVAL, "refinement modes need FP64 storage of u and f");
+    int rc = validate_sweep_opts(&o->sweep);
+    if (rc) return rc;
+    Workspace plan = plan_workspace(g, dt, ir, nullptr);
+    if ((rc = check_workspace(workspace, workspace_bytes, plan.total))) return rc;
+    if ((rc = check_device_range(u, grid_bytes(g, dt), "u"))) return rc;
+    if ((rc = check_device_range(f, grid_bytes(g, dt), "f"))) return rc;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace w = plan_workspace(g, dt, ir, static_cast<char*>(workspace));
+    const int es = int(elem_size(dt));
+    GroupTimer gt;
+    HIP_TRY(gt.t.init(o->sweep.timing != nullptr), "event create");
+    HIP_TRY(gt.t.mark(0, s), "event record");
+    HIP_TRY(launch_pack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, es, s), "pack u");
+    HIP_TRY(launch_pack(f, g->ld, w.f_red, w.f_black, g->n, w.pitch, es, s), "pack f");
+    HIP_TRY(gt.t.mark(3, s), "event record");
+    if (gt.t.on) {
+        HIP_TRY(hipEventSynchronize(gt.t.ev[3]), "event synchronise");
+        HIP_TRY(hipEventElapsedTime(&gt.acc.pack_ms, gt.t.ev[0], gt.t.ev[3]), "event time");
+    }
+
+    rbgs_solve_info out{0, 0, 0.0, 0.0, RBGS_OK};
+    int launches = 0;
+    rbgs_sweep_opts sw = o->sweep;
+    sw.timing = nullptr;
+    if (!ir) {
+        double rel = 0.0, ab = 0.0;
+        int32_t done = 0;
+        if (o->rel_tol <= 0.0) {
+            HIP_TRY(gt.begin(s), "event record");
+            if ((rc = run_sweeps_dt(dt, g, w, o->max_sweeps, &sw, s, &launches))) return rc;
+            HIP_TRY(gt.end(s), "event record");
+            HIP_TRY(gt.collect(launches), "event time");
+            done = o->max_sweeps;
+            if ((rc = split_residual_dt(dt, g, w, s))) return rc;
+            if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+        } else {
+            if ((rc = split_residual_dt(dt, g, w, s))) return rc;
+            if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+            while (!(rel <= o->rel_tol) && done < o->max_sweeps && std::isfinite(rel)) {
+                int32_t k = o->max_sweeps - done < o->check_every ? o->max_sweeps - done
+                                                                  : o->check_every;
+                HIP_TRY(gt.begin(s), "event record");
+                if ((rc = run_sweeps_dt(dt, g, w, k, &sw, s, &launches))) return rc;
+                HIP_TRY(gt.end(s), "event record");
+                HIP_TRY(gt.collect(launches), "event time");
+                done += k;
+                if ((rc = split_residual_dt(dt, g, w, s))) return rc;
+                if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+                if ((rc = blocked_check_error(w.blocked, s, &g_last_error))) return rc;
+            }
+        }
+        out.sweeps = done;
+        out.rel_residual = rel;
+        out.abs_residual = ab;
+        if (!std::isfinite(rel))
+            out.status = RBGS_ENONFINITE;
+        else
+            out.status = (o->rel_tol <= 0.0 || rel <= o->rel_tol) ? RBGS_OK : RBGS_ENOCONV;
+    } else {
+        // Iterative refinement: FP64 residual and correction, FP32 inner sweeps.
+        const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : o->check_every;
+        const int bf16 = o->precision == RBGS_PREC_BF16RHS_IR;
+        Workspace inner_w = w;  // FP32 view: e is the iterate, r the right-hand side
+        inner_w.pitch = w.pitch32;
+        inner_w.u_red = w.e_red;
+        inner_w.u_black = w.e_black;
+        inner_w.f_red = w.r_red;
+        inner_w.f_black = w.r_black;
+        const size_t c32 = align256(size_t(g->n + 2) * size_t(w.pitch32) * 4);
+        rbgs_grid gi = *g;
+        double rel = 0.0, ab = 0.0;
+        int32_t done = 0, outer = 0;
+        if ((rc = split_residual<double>(g, w, s, w.r_red, w.r_black, bf16))) return rc;
+        if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+        while (!(rel <= o->rel_tol) && done < o->max_sweeps && std::isfinite(rel)) {
+            int32_t k = o->max_sweeps - done < inner ? o->max_sweeps - done : inner;
+            HIP_TRY(launch_zero(w.e_red, c32, s), "zero correction");
+            HIP_TRY(launch_zero(w.e_black, c32, s), "zero correction");
+            HIP_TRY(gt.begin(s), "event record");
+            if ((rc = run_sweeps<float>(&gi, inner_w, k, &sw, s, &launches))) return rc;
+            HIP_TRY(gt.end(s), "event record");
+            HIP_TRY(gt.collect(launches), "event time");
+            HIP_TRY(launch_add_correction(static_cast<double*>(w.u_red),
+                                          static_cast<double*>(w.u_black), w.pitch, w.e_red,
+                                          w.e_black, w.pitch32, g->n, s),
+                    "correction");
+            done += k;
+            ++outer;
+            if ((rc = split_residual<double>(g, w, s, w.r_red, w.r_black, bf16))) return rc;
+            if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+            if ((rc = blocked_check_error(w.blocked, s, &g_last_error))) return rc;
+        }
+        out.sweeps = done;
+        out.outer_iters = outer;
+        out.rel_residual = rel;
+        out.abs_residual = ab;
+        if (!std::isfinite(rel))
+            out.status = RBGS_ENONFINITE;
+        else
+            out.status = rel <= o->rel_tol ? RBGS_OK : RBGS_ENOCONV;
+    }
+    HIP_TRY(gt.t.mark(0, s), "event record");
+    HIP_TRY(launch_unpack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, es, s), "unpack u");
+    HIP_TRY(gt.t.mark(3, s), "event record");
+    HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+    if (gt.t.on) {
+        HIP_TRY(hipEventElapsedTime(&gt.acc.unpack_ms, gt.t.ev[0], gt.t.ev[3]), "event time");
+        *o->sweep.timing = gt.acc;
+    }
+    if ((rc = blocked_check_error(w.blocked, s, &g_last_error))) out.status = rc;
+    if (info) *info = out;
+    if (out.status == RBGS_ENONFINITE) g_last_error = "residual is not finite";
+    if (out.status == RBGS_ENOCONV) g_last_error = "tolerance not reached";
+    return out.status;
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Layout kernels: natural <-> split colour layout, FP64 -> FP32 packing,
+// the FP64 correction u <- u + e of iterative refinement, and a zero fill.
+// All are single streaming passes; one thread handles one (row, q) pair,
+// i.e. the two natural elements (i, 2q) and (i, 2q+1).
+#include "rbgs_internal.h"
+
+namespace rbgs {
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename W>
+__global__ __launch_bounds__(kThreads) void k_pack(const W* __restrict__ nat, int64_t ld,
+                                                   W* __restrict__ red, W* __restrict__ black,
+                                                   int n, int64_t pitch) {
+    int64_t q = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    int64_t i = blockIdx.y;
+    if (q >= pitch) return;
+    // (i, 2q) has colour i & 1; (i, 2q + 1) has the other colour.
+    W* even_dst = (i & 1) ? black : red;
+    W* odd_dst = (i & 1) ? red : black;
+    int64_t j0 = 2 * q, j1 = 2 * q + 1;
+    const W* row = nat + i * ld;
+    even_dst[i * pitch + q] = (j0 <= n + 1) ? row[j0] : W(0);
+    odd_dst[i * pitch + q] = (j1 <= n + 1) ? row[j1] : W(0);
+}
+
+template <typename W>
+__global__ __launch_bounds__(kThreads) void k_unpack(W* __restrict__ nat, int64_t ld,
+                                                     const W* __restrict__ red,
+                                                     const W* __restrict__ black, int n,
+                                                     int64_t pitch) {
+    int64_t q = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    int64_t i = int64_t(blockIdx.y) + 1;  // interior rows only: the ring is never written
+    if (q >= pitch) return;
+    const W* even_src = (i & 1) ? black : red;
+    const W* odd_src = (i & 1) ? red : black;
+    int64_t j0 = 2 * q, j1 = 2 * q + 1;
+    W* row = nat + i * ld;
+    if (j0 >= 1 && j0 <= n) row[j0] = even_src[i * pitch + q];
+    if (j1 >= 1 && j1 <= n) row[j1] = odd_src[i * pitch + q];
+}
+
+__global__ __launch_bounds__(kThreads) void k_pack_f64_to_f32(const double* __restrict__ nat,
+                                                              int64_t ld, float* __restrict__ red,
+                                                              float* __restrict__ black, int n,
+                                                              int64_t pitch) {
+    int64_t q = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    int64_t i = blockIdx.y;
+    if (q >= pitch) return;
+    float* even_dst = (i & 1) ? black : red;
+    float* odd_dst = (i & 1) ? red : black;
+    int64_t j0 = 2 * q, j1 = 2 * q + 1;
+    const double* row = nat + i * ld;
+    even_dst[i * pitch + q] = (j0 <= n + 1) ? float(row[j0]) : 0.0f;
+    odd_dst[i * pitch + q] = (j1 <= n + 1) ? float(row[j1]) : 0.0f;
+}
+
+// u <- u + e at the interior points of row i = blockIdx.y + 1, both colours.
+__global__ __launch_bounds__(kThreads) void k_add_correction(double* __restrict__ u_red,
+                                                             double* __restrict__ u_black,
+                                                             int64_t pitch,
+                                                             const float* __restrict__ e_red,
+                                                             const float* __restrict__ e_black,
+                                                             int64_t e_pitch, int n) {
+    int64_t q = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    int64_t i = int64_t(blockIdx.y) + 1;
+#pragma unroll
+    for (int colour = 0; colour < 2; ++colour) {
+        int p = int((i + colour) & 1);
+        int64_t q_lo = 1 - p, q_hi = (int64_t(n) - p) >> 1;
+        if (q < q_lo || q > q_hi) continue;
+        double* u = colour ? u_black : u_red;
+        const float* e = colour ? e_black : e_red;
+        u[i * pitch + q] = u[i * pitch + q] + double(e[i * e_pitch + q]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero(uint32_t* __restrict__ p, size_t words) {
+    size_t k = size_t(blockIdx.x) * kThreads + threadIdx.x;
+    size_t stride = size_t(gridDim.x) * kThreads;
+    for (; k < words; k += stride) p[k] = 0u;
+}
+
+}  // namespace
+
+hipError_t launch_pack(const void* nat, int64_t ld, void* red, void* black, int n, int64_t pitch,
+                       int elem_bytes, hipStream_t s) {
+    dim3 grid(unsigned((pitch + kThreads - 1) / kThreads), unsigned(n + 2));
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_pack<uint64_t>, grid, dim3(kThreads), 0, s,
+                           static_cast<const uint64_t*>(nat), ld, static_cast<uint64_t*>(red),
+                           static_cast<uint64_t*>(black), n, pitch);
+    else
+        hipLaunchKernelGGL(k_pack<uint32_t>, grid, dim3(kThreads), 0, s,
+                           static_cast<const uint32_t*>(nat), ld, static_cast<uint32_t*>(red),
+                           static_cast<uint32_t*>(black), n, pitch);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(void* nat, int64_t ld, const void* red, const void* black, int n,
+                         int64_t pitch, int elem_bytes, hipStream_t s) {
+    dim3 grid(unsigned((pitch + kThreads - 1) / kThreads), unsigned(n));
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_unpack<uint64_t>, grid, dim3(kThreads), 0, s,
+                           static_cast<uint64_t*>(nat), ld, static_cast<const uint64_t*>(red),
+                           static_cast<const uint64_t*>(black), n, pitch);
+    else
+        hipLaunchKernelGGL(k_unpack<uint32_t>, grid, dim3(kThreads), 0, s,
+                           static_cast<uint32_t*>(nat), ld, static_cast<const uint32_t*>(red),
+                           static_cast<const uint32_t*>(black), n, pitch);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_f64_to_f32(const double* nat, int64_t ld, float* red, float* black, int n,
+                                  int64_t pitch, hipStream_t s) {
+    dim3 grid(unsigned((pitch + kThreads - 1) / kThreads), unsigned(n + 2));
+    hipLaunchKernelGGL(k_pack_f64_to_f32, grid, dim3(kThreads), 0, s, nat, ld, red, black, n,
+                       pitch);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_correction(double* u_red, double* u_black, int64_t pitch,
+                                 const float* e_red, const float* e_black, int64_t e_pitch, int n,
+                                 hipStream_t s) {
+    dim3 grid(unsigned((pitch + kThreads - 1) / kThreads), unsigned(n));
+    hipLaunchKernelGGL(k_add_correction, grid, dim3(kThreads), 0, s, u_red, u_black, pitch, e_red,
+                       e_black, e_pitch, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    size_t words = bytes / 4;
+    if (words == 0) return hipSuccess;
+    size_t blocks = (words + kThreads - 1) / kThreads;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_zero, dim3(unsigned(blocks)), dim3(kThreads), 0, s,
+                       static_cast<uint32_t*>(p), words);
+    return hipGetLastError();
+}
+
+}  // namespace rbgs

@@ -1,0 +1,92 @@
+// Internal declarations shared by the host API and the kernel files of
+// librbgs.so.  Nothing here is part of the public ABI (include/rbgs.h).
+//
+// Split colour layout (the paper stores red and black values separately,
+// Section 2.1): colour C of point (i, j) is (i + j) & 1 (0 = red, 1 = black)
+// and the point is stored at C[i][j >> 1] of that colour's array, which has
+// n+2 rows (ring rows included) of `pitch` elements.  In row i the points of
+// colour C sit at j = p + 2q with p = p_C(i) = (i + C) & 1, so j >> 1 == q.
+// Neighbours of C[i][q] (all of the other colour O):
+//     (i+1, j) -> O[i+1][q]     (i-1, j) -> O[i-1][q]
+//     (i, j+1) -> O[i][q + p]   (i, j-1) -> O[i][q - 1 + p]
+// Interior points of colour C in row i: q in [1 - p, (n - p) >> 1].
+// A half-sweep therefore streams the other colour once (three rows reused
+// from registers), its own right-hand side once and writes its own colour
+// once: 3 words per point update instead of the 6 of the natural layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace rbgs {
+
+constexpr int kWaveSize = 64;
+constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, round-robin dispatch
+
+// Elements per colour row: ceil((n+2)/2) rounded up to 256 bytes.
+inline int64_t split_pitch(int n, size_t elem_bytes) {
+    int64_t half = (int64_t(n) + 3) / 2;
+    int64_t align = int64_t(256 / elem_bytes);
+    return (half + align - 1) / align * align;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workgroup id remapping so that each XCD (die with its own L2) receives a
+// contiguous range of logical block ids.  Hardware dispatches workgroup b to
+// XCD b % 8; we give XCD x the logical range starting at
+// x * (nb / 8) + min(x, nb % 8), in the order the XCD receives its blocks.
+__device__ __forceinline__ int xcd_logical_block(int b, int nb) {
+    int x = b % kNumXcd;
+    int k = b / kNumXcd;
+    int base = nb / kNumXcd;
+    int rem = nb % kNumXcd;
+    return x * base + (x < rem ? x : rem) + k;
+}
+
+// ----- kernel launchers (defined in the .hip files) -----------------------
+
+// natural <-> split permutation (pure data movement; elem_bytes is 4 or 8).
+hipError_t launch_pack(const void* nat, int64_t ld, void* red, void* black, int n,
+                       int64_t pitch, int elem_bytes, hipStream_t s);
+hipError_t launch_unpack(void* nat, int64_t ld, const void* red, const void* black, int n,
+                         int64_t pitch, int elem_bytes, hipStream_t s);
+// Convert a natural FP64 array to split FP32 (round to nearest even).
+hipError_t launch_pack_f64_to_f32(const double* nat, int64_t ld, float* red, float* black,
+                                  int n, int64_t pitch, hipStream_t s);
+
+// One half-sweep of colour `colour` (0 red, 1 black) in the split layout.
+template <typename T>
+hipError_t launch_half_sweep(T* self, const T* other, const T* f_self, int n, int64_t pitch,
+                             T h2, int colour, int rows_per_block, hipStream_t s);
+
+// Number of partial-sum slots the residual kernels need for grid size n.
+int residual_partial_slots(int n, int64_t pitch, size_t elem_bytes);
+
+// Residual norms of a split-layout iterate.  partials: residual_partial_slots
+// * 2 doubles; out: 2 doubles (sum r^2, sum b^2) in device memory.
+// r_out_red/black (optional): store r rounded to FP32 (or bfloat16 when
+// rhs_bf16) in a split FP32 array of pitch r_pitch, for refinement.
+template <typename T>
+hipError_t launch_residual_split(const T* u_red, const T* u_black, const T* f_red,
+                                 const T* f_black, int n, int64_t pitch, double inv_h2,
+                                 double* partials, double* out, float* r_out_red,
+                                 float* r_out_black, int64_t r_pitch, int rhs_bf16,
+                                 hipStream_t s);
+
+// Residual norms of a natural-layout iterate (no packing).
+template <typename T>
+hipError_t launch_residual_natural(const T* u, const T* f, int n, int64_t ld, double inv_h2,
+                                   double* partials, double* out, hipStream_t s);
+int residual_natural_partial_slots(int n);
+
+// u <- u + e at the interior points (split layouts; u FP64, e FP32).
+hipError_t launch_add_correction(double* u_red, double* u_black, int64_t pitch,
+                                 const float* e_red, const float* e_black, int64_t e_pitch,
+                                 int n, hipStream_t s);
+
+// Zero a device range with a kernel (usable inside graph capture).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace rbgs

@@ -1,0 +1,153 @@
+// Plain half-sweep kernel: one launch updates every interior point of one
+// colour (Eq. (1)), so consecutive launches play the role of the barriers
+// after each colour in Algorithm 1.
+//
+// Data: split colour layout (rbgs_internal.h).  A workgroup owns a column
+// band of BT*V q-columns and a strip of R interior rows; each thread owns V
+// consecutive q-columns (one 16-byte vector) and marches down the strip,
+// keeping rows i-1, i, i+1 of the other colour in registers, so the other
+// colour is read from HBM about once ((R+2)/R times), the own right-hand side
+// once, and the own colour written once: 3 words per point update.  The
+// horizontal neighbour that lies outside the thread's vector (q-1 or q+V)
+// is re-read from the same, just-loaded cache lines.
+//
+// Term order (no FMA contraction, -ffp-contract=off):
+//   s = O[i+1][q] + O[i-1][q]; s += right; s += left; s -= h2*f; u = 0.25*s
+// which is u_{i+1,j} + u_{i-1,j} + u_{i,j+1} + u_{i,j-1} - h^2 f_ij of Eq. (1).
+#include "rbgs_internal.h"
+
+namespace rbgs {
+namespace {
+
+template <typename T, int V>
+struct alignas(sizeof(T) * V) Pack {
+    T v[V];
+};
+
+template <typename T, int V>
+__device__ __forceinline__ Pack<T, V> load_pack(const T* p) {
+    return *reinterpret_cast<const Pack<T, V>*>(p);
+}
+
+// Update row i whose parity p = (i + colour) & 1 is a compile-time value.
+// up/mid/dn: other colour, rows i-1, i, i+1 at q0..q0+V-1.
+template <typename T, int V, int P>
+__device__ __forceinline__ void update_row(T* __restrict__ self_row, const T* __restrict__ mid_row,
+                                           const Pack<T, V>& up, const Pack<T, V>& mid,
+                                           const Pack<T, V>& dn, const Pack<T, V>& fc, T h2,
+                                           int64_t q0, int n) {
+    // P = 1: right neighbour of q is q+1, left is q; P = 0: right q, left q-1.
+    T extra = P ? mid_row[q0 + V] : mid_row[q0 - 1];
+    Pack<T, V> out;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        T right = P ? (e + 1 < V ? mid.v[e + 1] : extra) : mid.v[e];
+        T left = P ? mid.v[e] : (e > 0 ? mid.v[e - 1] : extra);
+        T s = dn.v[e] + up.v[e];
+        s = s + right;
+        s = s + left;
+        T t = h2 * fc.v[e];
+        s = s - t;
+        out.v[e] = T(0.25) * s;
+    }
+    const int64_t q_lo = 1 - P, q_hi = (int64_t(n) - P) >> 1;
+    if (q0 >= q_lo && q0 + V - 1 <= q_hi) {
+        *reinterpret_cast<Pack<T, V>*>(self_row + q0) = out;
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            if (q0 + e >= q_lo && q0 + e <= q_hi) self_row[q0 + e] = out.v[e];
+    }
+}
+
+// Rows i0..i1 of one strip, first row parity P0; two rows per step so both
+// parities are compile-time constants.
+template <typename T, int V, int P0>
+__device__ __forceinline__ void march(T* __restrict__ self, const T* __restrict__ other,
+                                      const T* __restrict__ f_self, int n, int64_t pitch, T h2,
+                                      int64_t q0, int i0, int i1) {
+    const T* o = other + q0;
+    Pack<T, V> up = load_pack<T, V>(o + int64_t(i0 - 1) * pitch);
+    Pack<T, V> mid = load_pack<T, V>(o + int64_t(i0) * pitch);
+    int i = i0;
+    for (; i + 1 <= i1; i += 2) {
+        Pack<T, V> dn0 = load_pack<T, V>(o + int64_t(i + 1) * pitch);
+        Pack<T, V> dn1 = load_pack<T, V>(o + int64_t(i + 2) * pitch);
+        Pack<T, V> f0 = load_pack<T, V>(f_self + int64_t(i) * pitch + q0);
+        Pack<T, V> f1 = load_pack<T, V>(f_self + int64_t(i + 1) * pitch + q0);
+        update_row<T, V, P0>(self + int64_t(i) * pitch, other + int64_t(i) * pitch, up, mid, dn0,
+                             f0, h2, q0, n);
+        update_row<T, V, 1 - P0>(self + int64_t(i + 1) * pitch, other + int64_t(i + 1) * pitch,
+                                 mid, dn0, dn1, f1, h2, q0, n);
+        up = dn0;
+        mid = dn1;
+    }
+    if (i <= i1) {
+        Pack<T, V> dn0 = load_pack<T, V>(o + int64_t(i + 1) * pitch);
+        Pack<T, V> f0 = load_pack<T, V>(f_self + int64_t(i) * pitch + q0);
+        update_row<T, V, P0>(self + int64_t(i) * pitch, other + int64_t(i) * pitch, up, mid, dn0,
+                             f0, h2, q0, n);
+    }
+}
+
+template <typename T, int V>
+__global__ __launch_bounds__(256) void k_half_sweep(T* __restrict__ self,
+                                                    const T* __restrict__ other,
+                                                    const T* __restrict__ f_self, int n,
+                                                    int64_t pitch, T h2, int colour,
+                                                    int rows_per_block, int col_blocks,
+                                                    int nblocks) {
+    const int L = xcd_logical_block(blockIdx.x, nblocks);
+    const int strip = L / col_blocks;
+    const int cb = L - strip * col_blocks;
+    const int64_t q0 = (int64_t(cb) * blockDim.x + threadIdx.x) * V;
+    if (q0 > (n >> 1)) return;  // beyond the last interior q of either parity
+    const int i0 = 1 + strip * rows_per_block;
+    const int i1 = min(n, i0 + rows_per_block - 1);
+    if (((i0 + colour) & 1) == 0)
+        march<T, V, 0>(self, other, f_self, n, pitch, h2, q0, i0, i1);
+    else
+        march<T, V, 1>(self, other, f_self, n, pitch, h2, q0, i0, i1);
+}
+
+struct PlainConfig {
+    int threads, col_blocks, rows, strips, blocks;
+};
+
+template <int V>
+PlainConfig plain_config(int n, int rows_per_block) {
+    PlainConfig c;
+    int64_t qcols = int64_t(n >> 1) + 1;  // q = 0 .. n>>1
+    int64_t vecs = (qcols + V - 1) / V;
+    c.threads = vecs >= 256 ? 256 : (vecs > 128 ? 256 : (vecs > 64 ? 128 : 64));
+    c.col_blocks = int((vecs + c.threads - 1) / c.threads);
+    int r = rows_per_block;
+    if (r <= 0) {
+        // aim for >= 2048 workgroups (8 per CU) with strips of 2..32 rows
+        r = 32;
+        while (r > 2 && int64_t(c.col_blocks) * ((n + r - 1) / r) < 2048) r >>= 1;
+    }
+    c.rows = r;
+    c.strips = (n + r - 1) / r;
+    c.blocks = c.col_blocks * c.strips;
+    return c;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_half_sweep(T* self, const T* other, const T* f_self, int n, int64_t pitch, T h2,
+                             int colour, int rows_per_block, hipStream_t s) {
+    constexpr int V = 16 / sizeof(T);
+    PlainConfig c = plain_config<V>(n, rows_per_block);
+    hipLaunchKernelGGL((k_half_sweep<T, V>), dim3(c.blocks), dim3(c.threads), 0, s, self, other,
+                       f_self, n, pitch, h2, colour, c.rows, c.col_blocks, c.blocks);
+    return hipGetLastError();
+}
+
+template hipError_t launch_half_sweep<double>(double*, const double*, const double*, int, int64_t,
+                                              double, int, int, hipStream_t);
+template hipError_t launch_half_sweep<float>(float*, const float*, const float*, int, int64_t,
+                                             float, int, int, hipStream_t);
+
+}  // namespace rbgs

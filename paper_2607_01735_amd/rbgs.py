@@ -1,0 +1,232 @@
+"""Thin ctypes binding of librbgs.so (include/rbgs.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  Tensors are torch CUDA (HIP) tensors in the natural layout, a
+2-D view of shape (n+2, m) with m >= n+2, unit column stride and row stride
+ld >= n+2; the ring holds the Dirichlet data.  Streams default to torch's
+current stream; workspaces are allocated through torch unless given.
+
+If the shared library is missing this module raises ImportError: there is
+no CPU or PyTorch fallback.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbgs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -c 'import __graft_entry__ as g; g.build()'`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, EINVAL, EHIP, ENOCONV, ETIMEOUT, ENONFINITE, EUNSUPPORTED, EWORKSPACE = 0, -1, -2, -3, -4, -5, -6, -8
+F64, F32 = 0, 1
+KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BLOCKED = 0, 1, 2
+PREC_F64, PREC_F32_IR, PREC_BF16RHS_IR = 0, 1, 2
+
+_KERNELS = {"auto": KERNEL_AUTO, "plain": KERNEL_PLAIN, "blocked": KERNEL_BLOCKED}
+_PRECISIONS = {"f64": PREC_F64, "f32_ir": PREC_F32_IR, "bf16rhs_ir": PREC_BF16RHS_IR}
+
+
+class rbgs_grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("ld", ctypes.c_int64), ("h", ctypes.c_double)]
+
+
+class rbgs_timing(ctypes.Structure):
+    _fields_ = [("pack_ms", ctypes.c_float), ("sweep_ms", ctypes.c_float),
+                ("unpack_ms", ctypes.c_float), ("sweep_launches", ctypes.c_int32)]
+
+
+class rbgs_sweep_opts(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("fuse", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
+                ("rows_per_block", ctypes.c_int32), ("debug_delay", ctypes.c_int32),
+                ("debug_spin_limit", ctypes.c_int32), ("timing", ctypes.POINTER(rbgs_timing))]
+
+
+class rbgs_solve_opts(ctypes.Structure):
+    _fields_ = [("max_sweeps", ctypes.c_int32), ("rel_tol", ctypes.c_double),
+                ("check_every", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("inner_sweeps", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("sweep", rbgs_sweep_opts)]
+
+
+class rbgs_solve_info(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("abs_residual", ctypes.c_double),
+                ("status", ctypes.c_int32)]
+
+
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+_lib.rbgs_workspace_size.argtypes = [_P(rbgs_grid), ctypes.c_int, _P(rbgs_solve_opts)]
+_lib.rbgs_workspace_size.restype = ctypes.c_size_t
+_lib.rbgs_sweep.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, ctypes.c_int32,
+                            _P(rbgs_sweep_opts), _vp, ctypes.c_size_t, _vp]
+_lib.rbgs_sweep.restype = ctypes.c_int
+_lib.rbgs_residual.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, _P(ctypes.c_double),
+                               _P(ctypes.c_double), _vp, ctypes.c_size_t, _vp]
+_lib.rbgs_residual.restype = ctypes.c_int
+_lib.rbgs_solve.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, _P(rbgs_solve_opts),
+                            _P(rbgs_solve_info), _vp, ctypes.c_size_t, _vp]
+_lib.rbgs_solve.restype = ctypes.c_int
+_lib.rbgs_stream_probe.argtypes = [ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int64,
+                                   ctypes.c_double, _vp]
+_lib.rbgs_stream_probe.restype = ctypes.c_int
+_lib.rbgs_strerror.argtypes = [ctypes.c_int]
+_lib.rbgs_strerror.restype = ctypes.c_char_p
+_lib.rbgs_last_error.argtypes = []
+_lib.rbgs_last_error.restype = ctypes.c_char_p
+
+EXPORTED = ("rbgs_workspace_size", "rbgs_sweep", "rbgs_residual", "rbgs_solve",
+            "rbgs_stream_probe", "rbgs_strerror", "rbgs_last_error")
+
+
+class RbgsError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{rbgs_strerror(status)}: {message}")
+        self.status = status
+
+
+def rbgs_strerror(status):
+    return _lib.rbgs_strerror(int(status)).decode()
+
+
+def rbgs_last_error():
+    return _lib.rbgs_last_error().decode()
+
+
+def _check(rc, allow=(OK,)):
+    if rc not in allow:
+        raise RbgsError(rc, rbgs_last_error())
+    return rc
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def make_grid(u, h=None):
+    """rbgs_grid for a natural-layout tensor of shape (n+2, m >= n+2)."""
+    if u.dim() != 2 or u.shape[0] < 3 or u.shape[1] < u.shape[0] or u.stride(1) != 1:
+        raise ValueError("expected a 2-D (n+2, m>=n+2) tensor with unit column stride")
+    n = u.shape[0] - 2
+    h = 1.0 / (n + 1) if h is None else float(h)
+    return rbgs_grid(n, u.stride(0), h)
+
+
+def _stream_ptr(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device if device.type == "cuda" else None)
+    return _vp(stream.cuda_stream)
+
+
+def _same_layout(u, f):
+    if f.shape != u.shape or f.stride() != u.stride() or f.dtype != u.dtype or f.device != u.device:
+        raise ValueError("u and f must share shape, strides, dtype and device")
+
+
+def rbgs_workspace_size(grid, dtype_code, precision=PREC_F64):
+    opts = rbgs_solve_opts()
+    opts.precision = precision
+    return int(_lib.rbgs_workspace_size(ctypes.byref(grid), dtype_code, ctypes.byref(opts)))
+
+
+def _workspace(grid, code, device, precision=PREC_F64, workspace=None):
+    import torch
+    need = rbgs_workspace_size(grid, code, precision)
+    if need == 0:
+        raise RbgsError(EINVAL, "invalid grid")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=device)
+    return workspace
+
+
+def _sweep_opts(kernel="auto", fuse=0, tile_rows=0, tile_cols=0, rows_per_block=0,
+                debug_delay=0, debug_spin_limit=0, timing=None):
+    o = rbgs_sweep_opts()
+    o.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    o.fuse, o.tile_rows, o.tile_cols = fuse, tile_rows, tile_cols
+    o.rows_per_block, o.debug_delay, o.debug_spin_limit = rows_per_block, debug_delay, debug_spin_limit
+    if timing is not None:
+        o.timing = ctypes.pointer(timing)
+    return o
+
+
+def rbgs_sweep(u, f, nsweeps, h=None, kernel="auto", workspace=None, stream=None, timing=False,
+               **tuning):
+    """nsweeps red-black sweeps of u in place on the GPU (asynchronous unless
+    timing=True, which returns a dict of per-phase milliseconds)."""
+    _same_layout(u, f)
+    grid = make_grid(u, h)
+    code = _dtype_code(u)
+    ws = _workspace(grid, code, u.device, workspace=workspace)
+    t = rbgs_timing() if timing else None
+    opts = _sweep_opts(kernel=kernel, timing=t, **tuning)
+    _check(_lib.rbgs_sweep(ctypes.byref(grid), code, _vp(u.data_ptr()), _vp(f.data_ptr()),
+                           int(nsweeps), ctypes.byref(opts), _vp(ws.data_ptr()), ws.numel(),
+                           _stream_ptr(stream, u.device)))
+    if timing:
+        return {"pack_ms": t.pack_ms, "sweep_ms": t.sweep_ms, "unpack_ms": t.unpack_ms,
+                "sweep_launches": t.sweep_launches}
+    return None
+
+
+def rbgs_residual(u, f, h=None, workspace=None, stream=None):
+    """(||r||_2, ||r||_2/||b||_2) computed on the GPU in FP64."""
+    _same_layout(u, f)
+    grid = make_grid(u, h)
+    code = _dtype_code(u)
+    ws = _workspace(grid, code, u.device, workspace=workspace)
+    a = ctypes.c_double()
+    r = ctypes.c_double()
+    _check(_lib.rbgs_residual(ctypes.byref(grid), code, _vp(u.data_ptr()), _vp(f.data_ptr()),
+                              ctypes.byref(a), ctypes.byref(r), _vp(ws.data_ptr()), ws.numel(),
+                              _stream_ptr(stream, u.device)))
+    return a.value, r.value
+
+
+def rbgs_solve(u, f, max_sweeps, rel_tol, check_every=100, h=None, precision="f64",
+               inner_sweeps=0, omega=1.0, kernel="auto", workspace=None, stream=None,
+               raise_on_noconv=False, timing=False, **tuning):
+    """Solve to rel_tol on the GPU; returns a dict with sweeps, outer_iters,
+    rel_residual, abs_residual and status."""
+    _same_layout(u, f)
+    grid = make_grid(u, h)
+    code = _dtype_code(u)
+    prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    ws = _workspace(grid, code, u.device, precision=prec, workspace=workspace)
+    opts = rbgs_solve_opts()
+    opts.max_sweeps, opts.rel_tol, opts.check_every = int(max_sweeps), float(rel_tol), int(check_every)
+    opts.precision, opts.inner_sweeps, opts.omega = prec, int(inner_sweeps), float(omega)
+    t = rbgs_timing() if timing else None
+    opts.sweep = _sweep_opts(kernel=kernel, timing=t, **tuning)
+    info = rbgs_solve_info()
+    rc = _lib.rbgs_solve(ctypes.byref(grid), code, _vp(u.data_ptr()), _vp(f.data_ptr()),
+                         ctypes.byref(opts), ctypes.byref(info), _vp(ws.data_ptr()), ws.numel(),
+                         _stream_ptr(stream, u.device))
+    _check(rc, allow=(OK,) if raise_on_noconv else (OK, ENOCONV, ENONFINITE))
+    out = {"sweeps": info.sweeps, "outer_iters": info.outer_iters,
+           "rel_residual": info.rel_residual, "abs_residual": info.abs_residual,
+           "status": info.status}
+    if timing:
+        out["timing"] = {"pack_ms": t.pack_ms, "sweep_ms": t.sweep_ms, "unpack_ms": t.unpack_ms,
+                         "sweep_launches": t.sweep_launches}
+    return out
+
+
+def rbgs_stream_probe(kind, a, b, c=None, s=3.0, stream=None):
+    """STREAM copy (kind 0: b = a) or triad (kind 1: a = b + s*c) on FP64
+    device tensors of equal, even length."""
+    n = a.numel()
+    cp = _vp(c.data_ptr()) if c is not None else None
+    _check(_lib.rbgs_stream_probe(int(kind), _vp(a.data_ptr()), _vp(b.data_ptr()), cp, n,
+                                  float(s), _stream_ptr(stream, a.device)))

@@ -1,0 +1,163 @@
+"""C-ABI host checks that need no GPU: the library loads, exports every
+function include/rbgs.h declares, and rejects bad arguments before any
+device call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER_DIR = os.path.join(ROOT, "include")
+
+
+def declared_functions():
+    names = set()
+    for fname in os.listdir(HEADER_DIR):
+        if not fname.endswith(".h"):
+            continue
+        text = open(os.path.join(HEADER_DIR, fname)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(rbgs_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2607_01735_amd import rbgs
+    return rbgs
+
+
+def test_library_exports_every_declared_symbol(lib):
+    declared = declared_functions()
+    assert {"rbgs_sweep", "rbgs_residual", "rbgs_solve", "rbgs_workspace_size"} <= declared
+    raw = ctypes.CDLL(lib.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(raw, name), f"{name} declared in include/ but not exported"
+
+
+def test_binding_names_match_abi(lib):
+    import paper_2607_01735_amd as pkg
+    for name in ("rbgs_sweep", "rbgs_residual", "rbgs_solve", "rbgs_workspace_size",
+                 "rbgs_strerror", "rbgs_last_error"):
+        assert callable(getattr(pkg, name))
+
+
+def test_strerror(lib):
+    assert lib.rbgs_strerror(0) == "RBGS_OK"
+    for code in (-1, -2, -3, -4, -5, -6, -8):
+        assert lib.rbgs_strerror(code).startswith("RBGS_E")
+    assert "unknown" in lib.rbgs_strerror(12345)
+
+
+def _grid(lib, n=31, ld=None, h=None):
+    return lib.rbgs_grid(n, n + 2 if ld is None else ld, 1.0 / (n + 1) if h is None else h)
+
+
+def test_workspace_size(lib):
+    g = _grid(lib, 255)
+    s64 = lib.rbgs_workspace_size(g, lib.F64)
+    s32 = lib.rbgs_workspace_size(g, lib.F32)
+    # four split colour arrays (u red/black, f red/black) at least
+    assert s64 >= 4 * 257 * 129 * 8 and s32 >= 4 * 257 * 129 * 4
+    assert s64 % 256 == 0
+    assert lib.rbgs_workspace_size(g, lib.F64, lib.PREC_F32_IR) > s64
+    assert lib.rbgs_workspace_size(_grid(lib, 0), lib.F64) == 0
+    assert lib.rbgs_workspace_size(_grid(lib, 31, ld=32), lib.F64) == 0
+    assert lib.rbgs_workspace_size(_grid(lib, 31, h=-1.0), lib.F64) == 0
+    assert lib.rbgs_workspace_size(_grid(lib, 31, h=float("inf")), lib.F64) == 0
+    assert lib.rbgs_workspace_size(_grid(lib, 31), 7) == 0
+
+
+def _sweep(lib, grid, dtype=0, nsweeps=1, opts=None, ws=None, ws_bytes=0):
+    o = ctypes.byref(opts) if opts is not None else None
+    return lib._lib.rbgs_sweep(ctypes.byref(grid), dtype, None, None, nsweeps, o, ws, ws_bytes,
+                               None)
+
+
+@pytest.mark.parametrize("bad", ["n0", "nbig", "ld", "h0", "hnan", "dtype", "nsweeps", "kernel",
+                                 "negopt", "ws_null", "ws_align", "ws_small"])
+def test_sweep_validation_before_device_work(lib, bad):
+    g = _grid(lib, 31)
+    dtype, nsweeps, opts = lib.F64, 1, lib.rbgs_sweep_opts()
+    ws, ws_bytes = ctypes.c_void_p(1 << 20), 1 << 30
+    expect = lib.EINVAL
+    if bad == "n0":
+        g = _grid(lib, 0)
+    elif bad == "nbig":
+        g = lib.rbgs_grid(70000, 70002, 1e-5)
+    elif bad == "ld":
+        g = _grid(lib, 31, ld=32)
+    elif bad == "h0":
+        g = _grid(lib, 31, h=0.0)
+    elif bad == "hnan":
+        g = _grid(lib, 31, h=float("nan"))
+    elif bad == "dtype":
+        dtype = 5
+    elif bad == "nsweeps":
+        nsweeps = -1
+    elif bad == "kernel":
+        opts.kernel = 9
+    elif bad == "negopt":
+        opts.fuse = -2
+    elif bad == "ws_null":
+        ws, expect = None, lib.EWORKSPACE
+    elif bad == "ws_align":
+        ws, expect = ctypes.c_void_p((1 << 20) + 8), lib.EWORKSPACE
+    elif bad == "ws_small":
+        ws_bytes, expect = 100, lib.EWORKSPACE
+    rc = _sweep(lib, g, dtype, nsweeps, opts, ws, ws_bytes)
+    assert rc == expect, lib.rbgs_last_error()
+    assert lib.rbgs_last_error()
+
+
+@pytest.mark.parametrize("bad", ["omega", "check", "maxs", "prec", "ir_f32", "nan_tol", "inner"])
+def test_solve_validation_before_device_work(lib, bad):
+    g = _grid(lib, 31)
+    o = lib.rbgs_solve_opts()
+    o.max_sweeps, o.rel_tol, o.check_every, o.omega = 10, 1e-8, 5, 1.0
+    dtype = lib.F64
+    expect = lib.EINVAL
+    if bad == "omega":
+        o.omega, expect = 1.5, lib.EUNSUPPORTED
+    elif bad == "check":
+        o.check_every = 0
+    elif bad == "maxs":
+        o.max_sweeps = -1
+    elif bad == "prec":
+        o.precision = 7
+    elif bad == "ir_f32":
+        o.precision, dtype = lib.PREC_F32_IR, lib.F32
+    elif bad == "nan_tol":
+        o.rel_tol = float("nan")
+    elif bad == "inner":
+        o.inner_sweeps = -3
+    info = lib.rbgs_solve_info()
+    rc = lib._lib.rbgs_solve(ctypes.byref(g), dtype, None, None, ctypes.byref(o),
+                             ctypes.byref(info), None, 0, None)
+    assert rc == expect, lib.rbgs_last_error()
+
+
+def test_residual_validation(lib):
+    g = _grid(lib, 0)
+    a = ctypes.c_double()
+    rc = lib._lib.rbgs_residual(ctypes.byref(g), lib.F64, None, None, ctypes.byref(a), None,
+                                None, 0, None)
+    assert rc == lib.EINVAL
+    g = _grid(lib, 15)
+    rc = lib._lib.rbgs_residual(ctypes.byref(g), lib.F64, None, None, ctypes.byref(a), None,
+                                None, 0, None)
+    assert rc == lib.EWORKSPACE
+
+
+def test_python_binding_rejects_mismatched_tensors(lib):
+    torch = pytest.importorskip("torch")
+    u = torch.zeros(10, 10, dtype=torch.float64)
+    f = torch.zeros(10, 10, dtype=torch.float32)
+    with pytest.raises(ValueError):
+        lib.rbgs_sweep(u, f, 1)
+    with pytest.raises(ValueError):
+        lib.make_grid(torch.zeros(10, 5, dtype=torch.float64))
+    with pytest.raises(TypeError):
+        lib._dtype_code(torch.zeros(3, 3, dtype=torch.int32))
