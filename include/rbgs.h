@@ -111,6 +111,10 @@ typedef struct {
                                (schedule stress); results must not change      */
     int32_t debug_spin_limit; /* BLOCKED: >0 bounds each flag wait to this many
                                polls (watchdog tests); 0 = default bound       */
+    int32_t debug_stall_tile; /* BLOCKED: t+1 > 0 makes tile t never publish its
+                               progress, so its neighbours' bounded waits expire
+                               and the call returns RBGS_ETIMEOUT (watchdog
+                               test; every wave still exits)                   */
     rbgs_timing *timing;    /* HOST pointer or NULL (see rbgs_timing)          */
 } rbgs_sweep_opts;
 

@@ -81,6 +81,8 @@ struct Workspace {
     int64_t pitch32 = 0;    // split pitch of FP32 refinement arrays
     void* u_red = nullptr;
     void* u_black = nullptr;
+    void* u2_red = nullptr;   // second buffer of the persistent kernel's ping-pong
+    void* u2_black = nullptr;
     void* f_red = nullptr;
     void* f_black = nullptr;
     double* partials = nullptr;
@@ -89,6 +91,8 @@ struct Workspace {
     float* e_black = nullptr;
     float* r_red = nullptr;
     float* r_black = nullptr;
+    float* e2_red = nullptr;  // second buffer for blocked inner sweeps
+    float* e2_black = nullptr;
     void* blocked = nullptr;  // persistent-kernel state (flags, ticket, error word)
     size_t blocked_bytes = 0;
     size_t total = 0;
@@ -112,6 +116,8 @@ Workspace plan_workspace(const rbgs_grid* g, rbgs_dtype dt, bool ir, char* base)
     };
     w.u_red = take(colour);
     w.u_black = take(colour);
+    w.u2_red = take(colour);
+    w.u2_black = take(colour);
     w.f_red = take(colour);
     w.f_black = take(colour);
     int slots = residual_partial_slots(n, w.pitch, es);
@@ -128,6 +134,8 @@ Workspace plan_workspace(const rbgs_grid* g, rbgs_dtype dt, bool ir, char* base)
         w.e_black = static_cast<float*>(take(c32));
         w.r_red = static_cast<float*>(take(c32));
         w.r_black = static_cast<float*>(take(c32));
+        w.e2_red = static_cast<float*>(take(c32));
+        w.e2_black = static_cast<float*>(take(c32));
     }
     w.total = off;
     return w;
@@ -148,16 +156,18 @@ int validate_sweep_opts(const rbgs_sweep_opts* o) {
     if (o->kernel < RBGS_KERNEL_AUTO || o->kernel > RBGS_KERNEL_BLOCKED)
         return fail(RBGS_EINVAL, "unknown kernel");
     if (o->fuse < 0 || o->tile_rows < 0 || o->tile_cols < 0 || o->rows_per_block < 0 ||
-        o->debug_delay < 0 || o->debug_spin_limit < 0)
+        o->debug_delay < 0 || o->debug_spin_limit < 0 || o->debug_stall_tile < 0)
         return fail(RBGS_EINVAL, "sweep options must be >= 0");
     if (o->rows_per_block > 4096) return fail(RBGS_EINVAL, "rows_per_block must be <= 4096");
+    if (o->debug_delay > 1000) return fail(RBGS_EINVAL, "debug_delay must be <= 1000");
     return validate_blocked_opts(o->fuse, o->tile_rows, o->tile_cols, &g_last_error);
 }
 
-// Half-sweeps on the split arrays already in the workspace.
+// Half-sweeps on the split arrays already in the workspace.  *used_blocked
+// is set when the persistent kernel ran (its error word must be checked).
 template <typename T>
 int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rbgs_sweep_opts* o,
-               hipStream_t s, int* launches) {
+               hipStream_t s, int* launches, bool* used_blocked) {
     const int n = g->n;
     const T h2 = T(g->h * g->h);
     T* ur = static_cast<T*>(w.u_red);
@@ -169,10 +179,12 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
     *launches = 0;
     if (kernel == RBGS_KERNEL_BLOCKED) {
         BlockedParams bp = blocked_params(n, sizeof(T), o);
-        int err = 0;
-        hipError_t e = run_blocked<T>(ur, ub, fr, fb, n, w.pitch, h2, nsweeps, bp, w.blocked,
-                                      w.blocked_bytes, s, launches, &err);
-        if (e != hipSuccess) return hip_fail(e, "blocked sweep");
+        T* const bred[2] = {ur, static_cast<T*>(w.u2_red)};
+        T* const bblack[2] = {ub, static_cast<T*>(w.u2_black)};
+        HIP_TRY(run_blocked<T>(bred, bblack, fr, fb, n, w.pitch, h2, nsweeps, bp, w.blocked,
+                               w.blocked_bytes, s, launches),
+                "blocked sweep");
+        *used_blocked = true;
         return RBGS_OK;
     }
     const int rows = o ? o->rows_per_block : 0;
@@ -185,9 +197,9 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
 }
 
 int run_sweeps_dt(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w, int32_t nsweeps,
-                  const rbgs_sweep_opts* o, hipStream_t s, int* launches) {
-    return dt == RBGS_F64 ? run_sweeps<double>(g, w, nsweeps, o, s, launches)
-                          : run_sweeps<float>(g, w, nsweeps, o, s, launches);
+                  const rbgs_sweep_opts* o, hipStream_t s, int* launches, bool* used_blocked) {
+    return dt == RBGS_F64 ? run_sweeps<double>(g, w, nsweeps, o, s, launches, used_blocked)
+                          : run_sweeps<float>(g, w, nsweeps, o, s, launches, used_blocked);
 }
 
 // Reads the two device sums, synchronising the stream.
@@ -311,7 +323,8 @@ int rbgs_sweep(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f, int32_
     HIP_TRY(launch_pack(f, g->ld, w.f_red, w.f_black, g->n, w.pitch, es, s), "pack f");
     HIP_TRY(tm.mark(1, s), "event record");
     int launches = 0;
-    if ((rc = run_sweeps_dt(dt, g, w, nsweeps, opts, s, &launches))) return rc;
+    bool used_blocked = false;
+    if ((rc = run_sweeps_dt(dt, g, w, nsweeps, opts, s, &launches, &used_blocked))) return rc;
     HIP_TRY(tm.mark(2, s), "event record");
     HIP_TRY(launch_unpack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, es, s), "unpack u");
     HIP_TRY(tm.mark(3, s), "event record");
@@ -323,7 +336,7 @@ int rbgs_sweep(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f, int32_
         HIP_TRY(hipEventElapsedTime(&t.unpack_ms, tm.ev[2], tm.ev[3]), "event time");
         *opts->timing = t;
     }
-    return blocked_check_error(w.blocked, s, &g_last_error);
+    return used_blocked ? blocked_check_error(w.blocked, s, &g_last_error) : RBGS_OK;
 }
 
 int rbgs_residual(const rbgs_grid* g, rbgs_dtype dt, const void* u, const void* f,
@@ -394,6 +407,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
 
     rbgs_solve_info out{0, 0, 0.0, 0.0, RBGS_OK};
     int launches = 0;
+    bool used_blocked = false;
     rbgs_sweep_opts sw = o->sweep;
     sw.timing = nullptr;
     if (!ir) {
@@ -401,7 +415,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         int32_t done = 0;
         if (o->rel_tol <= 0.0) {
             HIP_TRY(gt.begin(s), "event record");
-            if ((rc = run_sweeps_dt(dt, g, w, o->max_sweeps, &sw, s, &launches))) return rc;
+            if ((rc = run_sweeps_dt(dt, g, w, o->max_sweeps, &sw, s, &launches, &used_blocked))) return rc;
             HIP_TRY(gt.end(s), "event record");
             HIP_TRY(gt.collect(launches), "event time");
             done = o->max_sweeps;
@@ -414,13 +428,14 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
                 int32_t k = o->max_sweeps - done < o->check_every ? o->max_sweeps - done
                                                                   : o->check_every;
                 HIP_TRY(gt.begin(s), "event record");
-                if ((rc = run_sweeps_dt(dt, g, w, k, &sw, s, &launches))) return rc;
+                if ((rc = run_sweeps_dt(dt, g, w, k, &sw, s, &launches, &used_blocked))) return rc;
                 HIP_TRY(gt.end(s), "event record");
                 HIP_TRY(gt.collect(launches), "event time");
                 done += k;
                 if ((rc = split_residual_dt(dt, g, w, s))) return rc;
                 if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
-                if ((rc = blocked_check_error(w.blocked, s, &g_last_error))) return rc;
+                if (used_blocked && (rc = blocked_check_error(w.blocked, s, &g_last_error)))
+                    return rc;
             }
         }
         out.sweeps = done;
@@ -440,6 +455,8 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         inner_w.u_black = w.e_black;
         inner_w.f_red = w.r_red;
         inner_w.f_black = w.r_black;
+        inner_w.u2_red = w.e2_red;
+        inner_w.u2_black = w.e2_black;
         const size_t c32 = align256(size_t(g->n + 2) * size_t(w.pitch32) * 4);
         rbgs_grid gi = *g;
         double rel = 0.0, ab = 0.0;
@@ -451,7 +468,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
             HIP_TRY(launch_zero(w.e_red, c32, s), "zero correction");
             HIP_TRY(launch_zero(w.e_black, c32, s), "zero correction");
             HIP_TRY(gt.begin(s), "event record");
-            if ((rc = run_sweeps<float>(&gi, inner_w, k, &sw, s, &launches))) return rc;
+            if ((rc = run_sweeps<float>(&gi, inner_w, k, &sw, s, &launches, &used_blocked))) return rc;
             HIP_TRY(gt.end(s), "event record");
             HIP_TRY(gt.collect(launches), "event time");
             HIP_TRY(launch_add_correction(static_cast<double*>(w.u_red),
@@ -462,7 +479,8 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
             ++outer;
             if ((rc = split_residual<double>(g, w, s, w.r_red, w.r_black, bf16))) return rc;
             if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
-            if ((rc = blocked_check_error(w.blocked, s, &g_last_error))) return rc;
+            if (used_blocked && (rc = blocked_check_error(w.blocked, s, &g_last_error)))
+                return rc;
         }
         out.sweeps = done;
         out.outer_iters = outer;
@@ -481,7 +499,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         HIP_TRY(hipEventElapsedTime(&gt.acc.unpack_ms, gt.t.ev[0], gt.t.ev[3]), "event time");
         *o->sweep.timing = gt.acc;
     }
-    if ((rc = blocked_check_error(w.blocked, s, &g_last_error))) out.status = rc;
+    if (used_blocked && (rc = blocked_check_error(w.blocked, s, &g_last_error))) out.status = rc;
     if (info) *info = out;
     if (out.status == RBGS_ENONFINITE) g_last_error = "residual is not finite";
     if (out.status == RBGS_ENOCONV) g_last_error = "tolerance not reached";

@@ -1,0 +1,159 @@
+"""GPU parity of the persistent, temporally blocked sweep.
+
+Every schedule that respects the tile dependencies computes the values of
+the sequential red-black sweep (Section 2.3: the task runtime serialises
+only conflicting accesses), so the blocked kernel must equal the oracle bit
+for bit for every fusion depth, tile height, grid size, ragged tail and
+injected delay pattern.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.sampling import sample_after_sweeps
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2607_01735_amd as rb  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def start(n, seed, ld=None, dtype=np.float64):
+    u = W.random_ring(n, seed=seed, ld=ld)
+    u[1:n + 1, 1:n + 1] = W.uniform_rhs(n, seed=seed + 1)[1:n + 1, 1:n + 1]
+    f = W.uniform_rhs(n, seed=seed + 2, ld=ld)
+    return u.astype(dtype), f.astype(dtype)
+
+
+CASES = [  # n, sweeps, fuse, tile_rows
+    (1, 5, 4, 0), (2, 8, 2, 8), (5, 7, 3, 8), (31, 12, 4, 8), (64, 9, 1, 8), (100, 16, 4, 16),
+    (255, 24, 4, 0), (255, 25, 3, 32), (300, 8, 2, 8), (513, 20, 4, 64), (1000, 12, 4, 24),
+    (1023, 40, 4, 0), (1025, 6, 1, 0), (2049, 16, 4, 128),
+]
+
+
+@pytest.mark.parametrize("n,sweeps,fuse,rows", CASES)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_blocked_sweep_bitwise(oracle, n, sweeps, fuse, rows, dtype):
+    say(f"blocked n={n} sweeps={sweeps} fuse={fuse} rows={rows} {dtype.__name__}")
+    h = W.spacing(n)
+    ld = n + 2 + (n % 5)
+    u0, f = start(n, n, ld=ld, dtype=dtype)
+    ut, ft = dev(u0), dev(f)
+    rb.rbgs_sweep(ut, ft, sweeps, h=h, kernel="blocked", fuse=fuse, tile_rows=rows)
+    got = host(ut)
+    ref = u0.copy()
+    oracle.sweep(ref, f, h, sweeps)
+    assert np.array_equal(got.view(np.uint8), ref.view(np.uint8)), \
+        f"max |diff| {np.max(np.abs(got.astype(np.float64) - ref))}"
+
+
+@pytest.mark.parametrize("delay", [3, 25])
+def test_blocked_delay_injection(oracle, delay):
+    """Pseudo-random stalls per work item reorder the execution; the bits
+    must not change (the GPU form of the paper's hardware asynchronicity)."""
+    n, sweeps = 700, 24
+    say(f"blocked delay={delay} n={n}")
+    h = W.spacing(n)
+    u0, f = start(n, 5)
+    ut, ft = dev(u0), dev(f)
+    rb.rbgs_sweep(ut, ft, sweeps, h=h, kernel="blocked", fuse=4, tile_rows=16,
+                  debug_delay=delay)
+    ref = u0.copy()
+    oracle.sweep(ref, f, h, sweeps)
+    assert np.array_equal(host(ut), ref)
+
+
+def test_blocked_equals_plain_large():
+    n, sweeps = 4095, 16
+    say(f"blocked vs plain n={n}")
+    h = W.spacing(n)
+    u0, f = start(n, 9)
+    a, b, ft = dev(u0), dev(u0), dev(f)
+    rb.rbgs_sweep(a, ft, sweeps, h=h, kernel="blocked")
+    rb.rbgs_sweep(b, ft, sweeps, h=h, kernel="plain")
+    assert torch.equal(a, b)
+
+
+def test_watchdog_returns_timeout():
+    """Tile 0 never publishes its progress; its neighbours' bounded waits
+    expire, every wave leaves the kernel and the call reports a timeout."""
+    n = 255
+    say("blocked watchdog (stalled tile, bounded waits)")
+    u0, f = start(n, 3)
+    ut, ft = dev(u0), dev(f)
+    with pytest.raises(rb.RbgsError) as e:
+        rb.rbgs_sweep(ut, ft, 8, kernel="blocked", fuse=1, tile_rows=8, debug_stall_tile=1,
+                      debug_spin_limit=2000)
+    assert e.value.status == rb.rbgs.ETIMEOUT
+    # the library stays usable afterwards
+    ut, ft = dev(u0), dev(f)
+    rb.rbgs_sweep(ut, ft, 8, kernel="blocked", fuse=1, tile_rows=8)
+    torch.cuda.synchronize()
+
+
+def test_blocked_solve_matches_oracle(oracle):
+    n, tol, check, cap = 1023, 2e-2, 40, 400
+    say(f"blocked solve n={n} tol={tol}")
+    h = W.spacing(n)
+    f = W.uniform_rhs(n, seed=4)
+    ref = W.zeros(n)
+    rc, done, rel = oracle.solve(ref, f, h, cap, tol, check)
+    ut = dev(W.zeros(n))
+    info = rb.rbgs_solve(ut, dev(f), cap, tol, check_every=check, h=h, kernel="blocked")
+    assert info["status"] == rc and info["sweeps"] == done
+    assert info["rel_residual"] == pytest.approx(rel, rel=1e-12)
+    assert np.array_equal(host(ut), ref)
+
+
+def test_blocked_ir_matches_oracle(oracle):
+    n, inner = 255, 64
+    say(f"blocked IR n={n}")
+    h = W.spacing(n)
+    f = W.fourier_rhs(n, seed=3, count=16, kmax=16)
+    ref = W.zeros(n)
+    rc, outer, rel = oracle.ir_solve(ref, f, h, inner, 20, 1e-9)
+    ut = dev(W.zeros(n))
+    info = rb.rbgs_solve(ut, dev(f), inner * 20, 1e-9, check_every=inner, h=h,
+                         precision="f32_ir", inner_sweeps=inner, kernel="blocked", tile_rows=16)
+    assert info["outer_iters"] == outer and rc == info["status"]
+    assert np.array_equal(host(ut), ref)
+
+
+def test_blocked_large_grid_sampled(oracle):
+    """8191 x 8191 FP64, 200 sweeps with the default blocked configuration
+    (the benchmark's launch): sampled points equal the oracle bit for bit."""
+    n, m = 8191, 200
+    say(f"blocked large grid n={n} sweeps={m}")
+    h = W.spacing(n)
+    f = W.uniform_rhs(n, seed=0)
+    ut = torch.zeros((n + 2, n + 2), dtype=torch.float64, device=DEV)
+    rb.rbgs_sweep(ut, dev(f), m, h=h, kernel="blocked")
+    got = host(ut)
+    pts = [(1, 1), (1, n), (n, 1), (n, n), (256, 117), (257, 116), (4096, 4097), (3000, 233),
+           (8000, 8000), (511, 4000), (7777, 1)]
+    ref = sample_after_sweeps(oracle, W.zeros(n), f, h, m, pts)
+    for p, r in zip(pts, ref):
+        assert got[p] == r, f"point {p}: {got[p]!r} vs {r!r}"
+    assert np.all(np.isfinite(got))
