@@ -5,13 +5,17 @@ Workload: 8191 x 8191 interior points (h = 1/8192), FP64, zero Dirichlet
 ring, f i.i.d. uniform[-1, 1) from seed 0, u0 = 0, 200 full sweeps.  One
 step is one rbgs_solve call with a fixed sweep count: pack u and f into the
 split colour layout, 200 red+black sweeps, the FP64 residual norm, unpack.
-Inputs are resident in HBM before the timed region.
+Inputs are resident in HBM before the timed region.  The timed kernel is
+the library's default (the persistent temporally blocked sweep at this
+size); the plain one-launch-per-half-sweep kernel is timed beside it.
 
 Output: one JSON line with GLUP/s (lattice point updates per second,
 N^2 * sweeps / time), the dominant kernel's roofline (algorithmic bytes per
-launch over its measured average duration, against 8 TB/s HBM), the STREAM
-probe bandwidth, and the CPU oracle timed on a bounded sample as baseline.
-Progress goes to stderr.
+launch over its measured average duration, against 8 TB/s HBM), the plain
+kernel's figures, time to a relative residual of 1e-8 on the 255 x 255 sine
+problem for the plain FP64, blocked FP64 and FP32-refinement solves, the
+STREAM probe bandwidth, and the CPU oracle timed on a bounded sample as
+baseline.  Progress goes to stderr.
 """
 import argparse
 import hashlib
@@ -33,13 +37,19 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    """Hash of the sources of the kernels the roofline figure refers to."""
+def kernel_source_hash(names):
+    """Hash of the sources of the kernel a roofline figure refers to."""
     h = hashlib.sha256()
-    for name in ("sweep_plain.hip", "sweep_blocked.hip", "rbgs_internal.h"):
+    for name in names:
         with open(os.path.join(ROOT, "paper_2607_01735_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {
+    "half_sweep_f64": ("sweep_plain.hip", "rbgs_internal.h"),
+    "blocked_f64": ("sweep_blocked.hip", "blocked_pipeline.h", "rbgs_blocked.h", "rbgs_internal.h"),
+}
 
 
 def read_traffic(kernel_name, n):
@@ -54,7 +64,7 @@ def read_traffic(kernel_name, n):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256") != kernel_source_hash():
+    if vals.get("kernel_source_sha256") != kernel_source_hash(KERNEL_SOURCES[kernel_name]):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -85,6 +95,37 @@ def stream_probe(torch, rb, gib=2.0):
         out[f"{name}_gbs"] = round(words * n * 8 / (ms * 1e-3) / 1e9, 1)
     del a, b, c
     torch.cuda.empty_cache()
+    return out
+
+
+def time_to_tolerance(torch, rb, W, n=255, tol=1e-8):
+    """Wall time and sweeps to rel <= tol from u = 0 on the n x n problem with
+    f = 2 pi^2 sin(pi x) sin(pi y) (124 616 sweeps at n = 255 by the closed
+    form), for the plain FP64 judge and the faster forms."""
+    h = W.spacing(n)
+    f = torch.from_numpy(W.sine_rhs(n)).to("cuda")
+    out = {"problem": f"{n}x{n} FP64 sine, u0=0, rel<={tol:g}, residual every 1000 sweeps"}
+    forms = [("plain_f64", dict(kernel="plain")),
+             ("blocked_f64", dict(kernel="blocked", tile_rows=16)),
+             ("f32_ir_blocked", dict(kernel="blocked", tile_rows=16, precision="f32_ir",
+                                     inner_sweeps=4000))]
+    for name, kw in forms:
+        u = torch.zeros((n + 2, n + 2), dtype=torch.float64, device="cuda")
+        rb.rbgs_solve(u, f, 8, 0.0, check_every=8, h=h, **{k: v for k, v in kw.items()
+                                                              if k != "inner_sweeps"})
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = rb.rbgs_solve(u, f, 400000, tol, check_every=1000, h=h, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"seconds": round(dt, 4), "sweeps": info["sweeps"],
+                     "rel_residual": info["rel_residual"], "status": info["status"]}
+        log(f"time-to-tol {name}: {dt:.3f} s, {info['sweeps']} sweeps, "
+            f"rel={info['rel_residual']:.3e}")
+    base = out["plain_f64"]["seconds"]
+    for name, _ in forms[1:]:
+        out[name]["speedup_vs_plain_f64"] = round(base / out[name]["seconds"], 3)
     return out
 
 
@@ -124,6 +165,8 @@ def main():
     ap.add_argument("--kernel", default="auto", choices=["auto", "plain", "blocked"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-time-to-tol", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -149,41 +192,64 @@ def main():
     ws = torch.empty(rb.rbgs_workspace_size(grid, rb.rbgs.F64), dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
 
-    def step():
-        return rb.rbgs_solve(u, f, sweeps, 0.0, check_every=sweeps, h=h, kernel=args.kernel,
-                             workspace=ws, timing=True)
+    def run_steps(kernel, warmup, steps):
+        def step():
+            return rb.rbgs_solve(u, f, sweeps, 0.0, check_every=sweeps, h=h, kernel=kernel,
+                                 workspace=ws, timing=True)
+        for k in range(warmup):
+            info = step()
+            log(f"[{kernel}] warmup {k + 1}/{warmup}: rel={info['rel_residual']:.6e} "
+                f"sweep_ms={info['timing']['sweep_ms']:.2f}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sweep_ms, launches = 0.0, 0
+        for _ in range(steps):
+            info = step()
+            sweep_ms += info["timing"]["sweep_ms"]
+            launches += info["timing"]["sweep_launches"]
+        torch.cuda.synchronize()
+        ms_step = (time.perf_counter() - t0) * 1e3 / steps
+        glups = n * n * sweeps / (ms_step * 1e-3) / 1e9
+        log(f"[{kernel}] {steps} steps: {ms_step:.3f} ms/step, {glups:.1f} GLUP/s")
+        return ms_step, glups, sweep_ms / max(launches, 1), launches / steps
 
-    for k in range(args.warmup):
-        info = step()
-        log(f"warmup {k + 1}/{args.warmup}: rel={info['rel_residual']:.6e} "
-            f"sweep_ms={info['timing']['sweep_ms']:.2f}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sweep_ms = 0.0
-    launches = 0
-    for k in range(args.steps):
-        info = step()
-        sweep_ms += info["timing"]["sweep_ms"]
-        launches += info["timing"]["sweep_launches"]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
-    glups = n * n * sweeps / (ms_per_step * 1e-3) / 1e9
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {glups:.1f} GLUP/s, "
-        f"rel={info['rel_residual']:.6e}")
-
-    kernel_used = args.kernel if args.kernel != "auto" else "plain"
-    # Dominant kernel: the half-sweep.  One launch updates one colour:
-    # ceil(n^2/2) red or floor(n^2/2) black points, 24 B each (FP64).
-    avg_launch_ms = sweep_ms / max(launches, 1)
-    per_launch_bytes = BYTES_PER_LUP["f64"] * n * n / 2.0
+    ms_per_step, glups, avg_launch_ms, launches_per_step = run_steps(args.kernel, args.warmup,
+                                                                     args.steps)
+    # the plain kernel launches twice per sweep; the persistent one once per step
+    kernel_used = "plain" if launches_per_step >= 2 * sweeps else "blocked"
+    if kernel_used == "blocked":
+        # One persistent launch runs all 50 passes of 4 fused sweeps; per pass
+        # the algorithmic traffic is one read of u and f and one write of u,
+        # 3 words per point (the launch time includes the ring copy into the
+        # second buffer).
+        fuse = 4
+        per_launch_bytes = BYTES_PER_LUP["f64"] * n * n * (sweeps // fuse)
+        bytes_per_lup = BYTES_PER_LUP["f64"] / fuse
+        kname, traffic_key = "k_blocked<double,2,8> (persistent, fuse 4)", "blocked_f64"
+    else:
+        # One launch updates one colour: half the points, 3 words each.
+        per_launch_bytes = BYTES_PER_LUP["f64"] * n * n / 2.0
+        bytes_per_lup = BYTES_PER_LUP["f64"]
+        kname, traffic_key = "k_half_sweep<double,2>", "half_sweep_f64"
     achieved = per_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
-    traffic = read_traffic("half_sweep_f64", n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "k_half_sweep<double,2>",
+                "traffic": read_traffic(traffic_key, n), "kernel": kname,
                 "avg_launch_us": round(avg_launch_ms * 1e3, 2),
                 "bytes_per_launch": per_launch_bytes}
+    plain = None
+    if kernel_used != "plain" and not args.no_plain:
+        p_ms, p_glups, p_launch_ms, _ = run_steps("plain", 1, max(2, args.steps // 3))
+        p_bytes = BYTES_PER_LUP["f64"] * n * n / 2.0
+        p_ach = p_bytes / (p_launch_ms * 1e-3) / 1e9
+        plain = {"value": round(p_glups, 2), "unit": "GLUP/s", "ms_per_step": round(p_ms, 3),
+                 "kernel": "k_half_sweep<double,2>", "avg_launch_us": round(p_launch_ms * 1e3, 2),
+                 "achieved_GBs": round(p_ach, 1), "frac_of_8TBs": round(p_ach / HBM_PEAK_GBS, 4),
+                 "traffic": read_traffic("half_sweep_f64", n),
+                 "speedup_of_timed_kernel": round(glups / p_glups, 3)}
+    del u, f, ws
+    torch.cuda.empty_cache()
+    ttt = None if args.no_time_to_tol else time_to_tolerance(torch, rb, W)
     probe = None if args.no_probe else stream_probe(torch, rb)
     if probe:
         log(f"STREAM probe: {probe}")
@@ -200,8 +266,11 @@ def main():
         "config": {"workload": f"{n}x{n} interior FP64, h=1/{n + 1}, zero Dirichlet, "
                                f"f~U[-1,1) seed 0, u0=0, {sweeps} sweeps per step",
                    "n": n, "sweeps": sweeps, "kernel": kernel_used},
-        "hbm_gbs_algorithmic": round(glups * BYTES_PER_LUP["f64"], 1),
+        "hbm_gbs_algorithmic": round(glups * bytes_per_lup, 1),
+        "bytes_per_lup_algorithmic": bytes_per_lup,
         "roofline": roofline,
+        "plain_kernel": plain,
+        "time_to_1e-8": ttt,
         "stream_probe": probe,
         "cpu_baseline": base,
     }

@@ -178,6 +178,65 @@ int rbgs_solve(const rbgs_grid *g, rbgs_dtype dt, void *u, const void *f,
                const rbgs_solve_opts *opts, rbgs_solve_info *info,
                void *workspace, size_t workspace_bytes, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Batches of independent grids (one persistent launch for all of them).
+ * Grid g has its own size grids[g], device arrays u[g] and f[g] (natural
+ * layout, type dt; the HOST arrays u and f hold the device pointers).  Work
+ * items are (pass, grid, tile) of the persistent blocked kernel, handed out
+ * pass by pass with the largest grids first; each grid's tiles follow the
+ * same dependency rule as a single grid, so every grid's result is bitwise
+ * what rbgs_sweep gives it alone.  count in [1, 65535].
+ * opts: kernel must be AUTO or BLOCKED; fuse/tile_rows 0 take the values
+ * rbgs_autotune_batched stored for this batch shape (else the defaults).
+ * --------------------------------------------------------------------- */
+
+/* Workspace bytes for a batch (0 for invalid arguments). */
+size_t rbgs_batch_workspace_size(int32_t count, const rbgs_grid *grids,
+                                 rbgs_dtype dt);
+
+/* nsweeps sweeps of every grid of the batch, in place.  Uploads its tables
+ * and reads the kernel's error word, so it synchronises `stream`.  Returns
+ * RBGS_ETIMEOUT if a bounded dependency wait expired. */
+int rbgs_sweep_batched(int32_t count, const rbgs_grid *grids, rbgs_dtype dt,
+                       void *const *u, const void *const *f, int32_t nsweeps,
+                       const rbgs_sweep_opts *opts, void *workspace,
+                       size_t workspace_bytes, void *stream);
+
+/* A batched sweep captured once into a HIP graph (pack, persistent
+ * kernel(s), unpack; flags and tickets are cleared by kernels inside the
+ * graph, so every replay starts clean).  The plan keeps the pointers given
+ * here: u, f and the workspace must stay allocated while it is used.  Each
+ * rbgs_batch_plan_launch advances every grid by nsweeps sweeps,
+ * asynchronously on `stream`; rbgs_batch_plan_check synchronises `stream`
+ * and returns RBGS_ETIMEOUT if a wait expired in any replay since the last
+ * check (RBGS_OK otherwise). */
+typedef struct rbgs_batch_plan rbgs_batch_plan;
+int rbgs_batch_plan_create(rbgs_batch_plan **plan, int32_t count,
+                           const rbgs_grid *grids, rbgs_dtype dt,
+                           void *const *u, const void *const *f,
+                           int32_t nsweeps, const rbgs_sweep_opts *opts,
+                           void *workspace, size_t workspace_bytes);
+int rbgs_batch_plan_launch(rbgs_batch_plan *plan, void *stream);
+int rbgs_batch_plan_check(rbgs_batch_plan *plan, void *stream);
+int rbgs_batch_plan_destroy(rbgs_batch_plan *plan);
+
+/* Autotuner: times the persistent kernel on this batch for fusion depths
+ * {2, 3, 4} and tile heights {64, 128, 256} (two passes each after a
+ * warm-up pass; the workspace copies are swept, u and f are only read),
+ * stores the fastest choice for the batch shape (dtype, CU count and the
+ * multiset of grid sizes) in a process-wide table, appends it to the file
+ * named by the environment variable RBGS_TUNE_CACHE if set (and reads that
+ * file on first use), and returns it in *best (HOST, may be NULL) with its
+ * time per sweep in *best_ms_per_sweep (HOST, may be NULL).  Synchronises. */
+int rbgs_autotune_batched(int32_t count, const rbgs_grid *grids,
+                          rbgs_dtype dt, void *const *u, const void *const *f,
+                          void *workspace, size_t workspace_bytes,
+                          void *stream, rbgs_sweep_opts *best,
+                          float *best_ms_per_sweep);
+
+/* Message for the calling thread's last failure in a batched call. */
+const char *rbgs_batch_last_error(void);
+
 /* Device-memory bandwidth probe: the copy (kind 0: b = a) and triad
  * (kind 1: a = b + s*c) kernels of the STREAM benchmark, which the paper
  * uses for the attainable memory bandwidth in its roofline (Section 3,

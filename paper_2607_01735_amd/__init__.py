@@ -5,9 +5,12 @@ include/rbgs.h); this package is its Python binding.  Importing the package
 fails loudly when the library has not been built.
 """
 from .rbgs import (  # noqa: F401
-    EXPORTED, RbgsError, make_grid, rbgs_last_error, rbgs_residual, rbgs_solve,
-    rbgs_stream_probe, rbgs_strerror, rbgs_sweep, rbgs_workspace_size,
+    EXPORTED, BatchPlan, RbgsError, make_grid, rbgs_autotune_batched, rbgs_batch_last_error,
+    rbgs_batch_workspace_size, rbgs_last_error, rbgs_residual, rbgs_solve, rbgs_stream_probe,
+    rbgs_strerror, rbgs_sweep, rbgs_sweep_batched, rbgs_workspace_size,
 )
 
-__all__ = ["rbgs_sweep", "rbgs_residual", "rbgs_solve", "rbgs_workspace_size",
+__all__ = ["rbgs_sweep_batched", "BatchPlan", "rbgs_autotune_batched",
+           "rbgs_batch_workspace_size", "rbgs_batch_last_error",
+           "rbgs_sweep", "rbgs_residual", "rbgs_solve", "rbgs_workspace_size",
            "rbgs_stream_probe", "rbgs_strerror", "rbgs_last_error", "make_grid", "RbgsError", "EXPORTED"]

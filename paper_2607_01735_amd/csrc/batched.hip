@@ -1,0 +1,671 @@
+// Batched persistent sweep: many independent grids of uneven sizes in one
+// launch of the tile pipeline (blocked_pipeline.h), plus the batched
+// pack/unpack kernels, the graph-captured plan and the autotuner.
+//
+// Work items are (pass, grid, tile).  Tickets run pass-major, and inside a
+// pass the grids are ordered largest first (longest-processing-time first),
+// so the biggest grids' tiles, which bound the makespan, start earliest.
+// Pass-major order is a topological order of every grid's dependency graph,
+// so the deadlock-freedom argument of the single-grid kernel carries over.
+// Each grid keeps its own progress flags (offset flag_base); its tiles wait
+// only on their own 3 x 3 neighbourhood.
+//
+// A grid of a few tens of points fits in one tile: it is then a chain of
+// passes that other grids' tiles interleave with; no separate code path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "blocked_pipeline.h"
+#include "rbgs.h"
+#include "rbgs_blocked.h"
+#include "rbgs_internal.h"
+
+namespace rbgs {
+namespace {
+
+using namespace blocked;
+
+// Per-grid pack/unpack description (natural <-> split, both buffers).
+struct PackDesc {
+    const void* nat_u;
+    const void* nat_f;
+    void* nat_out;       // unpack destination (the caller's u)
+    void* red[2];
+    void* black[2];
+    void* f_red;
+    void* f_black;
+    int64_t ld;
+    int64_t pitch;
+    int64_t row_start;   // first global row index of this grid
+    int n;
+};
+
+__device__ __forceinline__ int find_grid(const PackDesc* d, int count, int64_t row) {
+    int lo = 0, hi = count - 1;  // last grid whose row_start <= row
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d[mid].row_start <= row)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// One workgroup per grid row (all grids' rows numbered consecutively).
+// Packs u into both ping-pong buffers (so both hold the Dirichlet ring) and f.
+template <typename W>
+__global__ __launch_bounds__(256) void k_batch_pack(const PackDesc* __restrict__ descs, int count) {
+    const int64_t row = blockIdx.x;
+    const int gi = __builtin_amdgcn_readfirstlane(find_grid(descs, count, row));
+    const PackDesc d = descs[gi];
+    const int64_t i = row - d.row_start;
+    const W* u = static_cast<const W*>(d.nat_u) + i * d.ld;
+    const W* f = static_cast<const W*>(d.nat_f) + i * d.ld;
+    const int c0 = int(i & 1);  // colour of (i, 2q); (i, 2q+1) has the other
+    for (int64_t q = threadIdx.x; q < d.pitch; q += 256) {
+        const int64_t j0 = 2 * q, j1 = 2 * q + 1;
+        const W u0 = j0 <= d.n + 1 ? u[j0] : W(0), u1 = j1 <= d.n + 1 ? u[j1] : W(0);
+        const W f0 = j0 <= d.n + 1 ? f[j0] : W(0), f1 = j1 <= d.n + 1 ? f[j1] : W(0);
+        const int64_t o = i * d.pitch + q;
+        W* r0 = static_cast<W*>(d.red[0]);
+        W* b0 = static_cast<W*>(d.black[0]);
+        W* r1 = static_cast<W*>(d.red[1]);
+        W* b1 = static_cast<W*>(d.black[1]);
+        (c0 ? b0 : r0)[o] = u0;
+        (c0 ? r0 : b0)[o] = u1;
+        (c0 ? b1 : r1)[o] = u0;
+        (c0 ? r1 : b1)[o] = u1;
+        (c0 ? static_cast<W*>(d.f_black) : static_cast<W*>(d.f_red))[o] = f0;
+        (c0 ? static_cast<W*>(d.f_red) : static_cast<W*>(d.f_black))[o] = f1;
+    }
+}
+
+// Interior points of every grid back to the caller's arrays, from buffer b.
+template <typename W>
+__global__ __launch_bounds__(256) void k_batch_unpack(const PackDesc* __restrict__ descs, int count,
+                                                      int b) {
+    const int64_t row = blockIdx.x;
+    const int gi = __builtin_amdgcn_readfirstlane(find_grid(descs, count, row));
+    const PackDesc d = descs[gi];
+    const int64_t i = row - d.row_start;
+    if (i < 1 || i > d.n) return;
+    W* u = static_cast<W*>(d.nat_out) + i * d.ld;
+    const W* red = static_cast<const W*>(d.red[b]);
+    const W* black = static_cast<const W*>(d.black[b]);
+    const W* even_src = (i & 1) ? black : red;
+    const W* odd_src = (i & 1) ? red : black;
+    for (int64_t q = threadIdx.x; q < d.pitch; q += 256) {
+        const int64_t j0 = 2 * q, j1 = 2 * q + 1;
+        if (j0 >= 1 && j0 <= d.n) u[j0] = even_src[i * d.pitch + q];
+        if (j1 >= 1 && j1 <= d.n) u[j1] = odd_src[i * d.pitch + q];
+    }
+}
+
+template <typename T, int V, int L>
+__global__ __launch_bounds__(kLanes) void k_blocked_batched(const GridDesc<T>* __restrict__ descs,
+                                                            const int* __restrict__ tile_grid,
+                                                            int total_tiles, Queue qu) {
+    const int total = qu.passes * total_tiles;
+    for (;;) {
+        const int tk = next_ticket(qu);
+        if (tk >= total) break;
+        const int pass = tk / total_tiles;
+        const int idx = tk - pass * total_tiles;
+        const int gi = __builtin_amdgcn_readfirstlane(tile_grid[idx]);
+        const GridDesc<T> g = descs[gi];
+        if (!run_item<T, V, L>(g, qu, pass, idx - g.flag_base)) break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+size_t elem_bytes_of(rbgs_dtype dt) { return dt == RBGS_F64 ? 8 : 4; }
+
+// Workspace layout of a batch: queue header, flags, tables, then the split
+// arrays of every grid (u twice, f once; two colours each).
+struct BatchLayout {
+    size_t header = 0, flags = 0, gdesc = 0, pdesc = 0, tile_map = 0, arrays = 0, total = 0;
+    std::vector<size_t> grid_off;  // offset of each grid's six colour arrays
+    std::vector<int64_t> pitch;
+    int max_tiles_total = 0;
+};
+
+BatchLayout batch_layout(int count, const rbgs_grid* grids, rbgs_dtype dt) {
+    BatchLayout b;
+    const size_t es = elem_bytes_of(dt);
+    int64_t tiles = 0;
+    for (int g = 0; g < count; ++g) tiles += max_tiles(grids[g].n);
+    b.max_tiles_total = int(std::min<int64_t>(tiles, INT32_MAX / 2));
+    size_t off = 0;
+    b.header = off;
+    off += 256;
+    b.flags = off;
+    off += align256(size_t(tiles) * 4);
+    b.gdesc = off;
+    off += align256(size_t(count) * std::max(sizeof(GridDesc<double>), sizeof(GridDesc<float>)));
+    b.pdesc = off;
+    off += align256(size_t(count) * sizeof(PackDesc));
+    b.tile_map = off;
+    off += align256(size_t(tiles) * 4);
+    b.arrays = off;
+    b.grid_off.resize(count);
+    b.pitch.resize(count);
+    for (int g = 0; g < count; ++g) {
+        b.pitch[g] = split_pitch(grids[g].n, es);
+        b.grid_off[g] = off;
+        off += 6 * align256(size_t(grids[g].n + 2) * size_t(b.pitch[g]) * es);
+    }
+    b.total = off;
+    return b;
+}
+
+struct BatchSetup {
+    int passes = 0, rem = 0, total_tiles = 0, fuse = 0;
+    int64_t total_rows = 0;
+    std::vector<char> gdesc;    // GridDesc<T> table, LPT order of tiles
+    std::vector<PackDesc> pdesc;
+    std::vector<int> tile_map;
+};
+
+template <typename T>
+BatchSetup build_setup(int count, const rbgs_grid* grids, void* const* u, const void* const* f,
+                       const BatchLayout& lay, char* ws, int fuse, int rows_opt, int nsweeps) {
+    BatchSetup s;
+    s.fuse = fuse;
+    s.passes = nsweeps / fuse;
+    s.rem = nsweeps - s.passes * fuse;
+    const size_t es = sizeof(T);
+    // largest grids first
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return grids[a].n > grids[b].n; });
+    std::vector<GridDesc<T>> gd(count);
+    s.pdesc.resize(count);
+    int flag = 0;
+    int64_t row = 0;
+    for (int g = 0; g < count; ++g) {
+        const int n = grids[g].n;
+        const int64_t P = lay.pitch[g];
+        const size_t colour = align256(size_t(n + 2) * size_t(P) * es);
+        char* base = ws + lay.grid_off[g];
+        int rows = rows_opt > 0 ? rows_opt : default_rows(n, 2 * fuse);
+        if (rows < 2 * fuse) rows = 2 * fuse;
+        if (rows < kMinRows) rows = kMinRows;
+        const Geometry geo = geometry(n, int(es), fuse, rows);
+        GridDesc<T>& d = gd[g];
+        d.red[0] = reinterpret_cast<T*>(base + 0 * colour);
+        d.black[0] = reinterpret_cast<T*>(base + 1 * colour);
+        d.red[1] = reinterpret_cast<T*>(base + 2 * colour);
+        d.black[1] = reinterpret_cast<T*>(base + 3 * colour);
+        d.f_red = reinterpret_cast<const T*>(base + 4 * colour);
+        d.f_black = reinterpret_cast<const T*>(base + 5 * colour);
+        d.n = n;
+        d.pitch = P;
+        d.h2 = T(grids[g].h * grids[g].h);
+        d.rows = geo.rows;
+        d.halo_q = geo.halo_q;
+        d.q_core = geo.q_core;
+        d.strips = geo.strips;
+        d.bands = geo.bands;
+        d.ntiles = geo.ntiles;
+        PackDesc& p = s.pdesc[g];
+        p.nat_u = u[g];
+        p.nat_f = f[g];
+        p.nat_out = u[g];
+        p.red[0] = d.red[0];
+        p.black[0] = d.black[0];
+        p.red[1] = d.red[1];
+        p.black[1] = d.black[1];
+        p.f_red = base + 4 * colour;
+        p.f_black = base + 5 * colour;
+        p.ld = grids[g].ld;
+        p.pitch = P;
+        p.row_start = row;
+        p.n = n;
+        row += n + 2;
+    }
+    s.total_rows = row;
+    for (int k = 0; k < count; ++k) {
+        const int g = order[k];
+        gd[g].flag_base = flag;
+        for (int t = 0; t < gd[g].ntiles; ++t) s.tile_map.push_back(g);
+        flag += gd[g].ntiles;
+    }
+    s.total_tiles = flag;
+    s.gdesc.resize(sizeof(GridDesc<T>) * count);
+    std::memcpy(s.gdesc.data(), gd.data(), s.gdesc.size());
+    return s;
+}
+
+template <typename T, int V, int L>
+hipError_t launch_batched_k(const GridDesc<T>* d, const int* map, int total_tiles, const Queue& qu,
+                            hipStream_t s) {
+    int per_cu = 0, cus = 0;
+    hipError_t e = persistent_occupancy(reinterpret_cast<const void*>(&k_blocked_batched<T, V, L>),
+                                        &per_cu, &cus);
+    if (e != hipSuccess) return e;
+    int64_t total = int64_t(qu.passes) * total_tiles;
+    int64_t grid = int64_t(cus) * per_cu;
+    if (grid > total) grid = total;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((k_blocked_batched<T, V, L>), dim3(unsigned(grid)), dim3(kLanes), 0, s, d,
+                       map, total_tiles, qu);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batched_by_fuse(int fuse, const GridDesc<T>* d, const int* map, int tiles,
+                                  const Queue& qu, hipStream_t s) {
+    constexpr int V = 16 / int(sizeof(T));
+    switch (fuse) {
+        case 1: return launch_batched_k<T, V, 2>(d, map, tiles, qu, s);
+        case 2: return launch_batched_k<T, V, 4>(d, map, tiles, qu, s);
+        case 3: return launch_batched_k<T, V, 6>(d, map, tiles, qu, s);
+        default: return launch_batched_k<T, V, 8>(d, map, tiles, qu, s);
+    }
+}
+
+// Enqueue the device work of one batched sweep: pack, persistent passes,
+// remaining sweeps as short persistent launches of fuse 1, unpack.
+template <typename T>
+hipError_t enqueue_batch(const BatchSetup& su, const BatchLayout& lay, char* ws, int count,
+                         const rbgs_sweep_opts* o, bool do_pack, bool do_unpack, hipStream_t s) {
+    hipError_t e;
+    const PackDesc* pd = reinterpret_cast<const PackDesc*>(ws + lay.pdesc);
+    const GridDesc<T>* gd = reinterpret_cast<const GridDesc<T>*>(ws + lay.gdesc);
+    const int* map = reinterpret_cast<const int*>(ws + lay.tile_map);
+    if (do_pack) {
+        hipLaunchKernelGGL((k_batch_pack<typename std::conditional<sizeof(T) == 8, uint64_t, uint32_t>::type>),
+                           dim3(unsigned(su.total_rows)), dim3(256), 0, s, pd, count);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    Queue qu;
+    qu.ticket = reinterpret_cast<int*>(ws + lay.header);
+    qu.error = reinterpret_cast<int*>(ws + lay.header + 64);
+    qu.progress = reinterpret_cast<int*>(ws + lay.flags);
+    qu.spin_limit = (o && o->debug_spin_limit > 0) ? o->debug_spin_limit : (1 << 22);
+    qu.delay = o ? o->debug_delay : 0;
+    qu.stall_tile = o ? o->debug_stall_tile : 0;
+    // the error word is cleared once; tickets and flags before every launch
+    if ((e = launch_zero(ws + lay.header, 256, s)) != hipSuccess) return e;
+    int parity = 0;
+    // full passes of `fuse` sweeps, then (if nsweeps is not a multiple) one
+    // pass of the remaining sweeps; its smaller depth fits the same tiles,
+    // whose halo was sized for `fuse`
+    const int launches[2][2] = {{su.fuse, su.passes}, {su.rem, su.rem > 0 ? 1 : 0}};
+    for (const auto& lp : launches) {
+        if (lp[1] == 0) continue;
+        if ((e = launch_zero(ws + lay.header, 64, s)) != hipSuccess) return e;
+        if ((e = launch_zero(ws + lay.flags, size_t(su.total_tiles) * 4, s)) != hipSuccess) return e;
+        qu.passes = lp[1];
+        qu.buf_offset = parity;
+        if ((e = launch_batched_by_fuse<T>(lp[0], gd, map, su.total_tiles, qu, s)) != hipSuccess)
+            return e;
+        parity = (parity + lp[1]) & 1;
+    }
+    if (do_unpack) {
+        hipLaunchKernelGGL((k_batch_unpack<typename std::conditional<sizeof(T) == 8, uint64_t, uint32_t>::type>),
+                           dim3(unsigned(su.total_rows)), dim3(256), 0, s, pd, count, parity);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+thread_local std::string g_batch_error = "no error";
+
+int bfail(int status, const std::string& msg) {
+    g_batch_error = msg;
+    return status;
+}
+
+int validate_batch(int32_t count, const rbgs_grid* grids, int dt, void* const* u,
+                   const void* const* f, int32_t nsweeps, const rbgs_sweep_opts* o) {
+    if (count < 1 || count > 65535) return bfail(RBGS_EINVAL, "count must be in [1, 65535]");
+    if (!grids || !u || !f) return bfail(RBGS_EINVAL, "grids, u and f must not be NULL");
+    if (dt != RBGS_F64 && dt != RBGS_F32) return bfail(RBGS_EINVAL, "unknown dtype");
+    if (nsweeps < 0) return bfail(RBGS_EINVAL, "nsweeps must be >= 0");
+    for (int g = 0; g < count; ++g) {
+        const rbgs_grid& gr = grids[g];
+        if (gr.n < 1 || gr.n > 65533 || gr.ld < int64_t(gr.n) + 2 || !(gr.h > 0.0) ||
+            !std::isfinite(gr.h))
+            return bfail(RBGS_EINVAL, "grid " + std::to_string(g) + " is invalid");
+        if (!u[g] || !f[g]) return bfail(RBGS_EINVAL, "grid " + std::to_string(g) + ": NULL array");
+    }
+    if (o) {
+        if (o->kernel != RBGS_KERNEL_AUTO && o->kernel != RBGS_KERNEL_BLOCKED)
+            return bfail(RBGS_EINVAL, "batched sweeps use the persistent kernel");
+        if (o->fuse < 0 || o->fuse > kMaxFuse) return bfail(RBGS_EINVAL, "fuse must be in [0, 4]");
+        if (o->tile_rows != 0 && o->tile_rows < kMinRows)
+            return bfail(RBGS_EINVAL, "tile_rows must be >= 8 (0 = default)");
+        if (o->tile_cols != 0) return bfail(RBGS_EINVAL, "tile_cols must be 0");
+        if (o->debug_delay < 0 || o->debug_delay > 1000 || o->debug_spin_limit < 0 ||
+            o->debug_stall_tile < 0)
+            return bfail(RBGS_EINVAL, "bad debug option");
+    }
+    return RBGS_OK;
+}
+
+int check_ws(void* ws, size_t bytes, size_t need) {
+    if (!ws) return bfail(RBGS_EWORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return bfail(RBGS_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (bytes < need)
+        return bfail(RBGS_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    return RBGS_OK;
+}
+
+// --- autotuner cache --------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune;  // key -> (fuse, rows)
+
+std::string tune_key(int count, const rbgs_grid* grids, int dt) {
+    std::map<int, int> hist;
+    for (int g = 0; g < count; ++g) hist[grids[g].n]++;
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    std::string k = std::string(dt == RBGS_F64 ? "f64" : "f32") + "/cu" + std::to_string(cus);
+    for (auto& kv : hist) k += "/" + std::to_string(kv.first) + "x" + std::to_string(kv.second);
+    return k;
+}
+
+void load_tune_file() {
+    static bool loaded = false;
+    if (loaded) return;
+    loaded = true;
+    const char* path = std::getenv("RBGS_TUNE_CACHE");
+    if (!path) return;
+    FILE* fp = std::fopen(path, "r");
+    if (!fp) return;
+    char key[4096];
+    int fuse = 0, rows = 0;
+    float ms = 0.f;
+    while (std::fscanf(fp, "%4095s %d %d %f", key, &fuse, &rows, &ms) == 4)
+        if (fuse >= 1 && fuse <= kMaxFuse && rows >= kMinRows) g_tune[key] = {fuse, rows};
+    std::fclose(fp);
+}
+
+void store_tune(const std::string& key, int fuse, int rows, float ms) {
+    g_tune[key] = {fuse, rows};
+    const char* path = std::getenv("RBGS_TUNE_CACHE");
+    if (!path) return;
+    FILE* fp = std::fopen(path, "a");
+    if (!fp) return;
+    std::fprintf(fp, "%s %d %d %.6f\n", key.c_str(), fuse, rows, double(ms));
+    std::fclose(fp);
+}
+
+// (fuse, rows) for a batch: explicit options first, then the tuned choice,
+// then the defaults (fuse 4, per-grid default tile height).
+void choose_params(int count, const rbgs_grid* grids, int dt, const rbgs_sweep_opts* o,
+                   int* fuse, int* rows) {
+    *fuse = (o && o->fuse > 0) ? o->fuse : 0;
+    *rows = (o && o->tile_rows > 0) ? o->tile_rows : 0;
+    if (*fuse == 0 || *rows == 0) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_tune_file();
+        auto it = g_tune.find(tune_key(count, grids, dt));
+        if (it != g_tune.end()) {
+            if (*fuse == 0) *fuse = it->second.first;
+            if (*rows == 0) *rows = it->second.second;
+        }
+    }
+    if (*fuse == 0) *fuse = kMaxFuse;
+}
+
+template <typename T>
+int upload_setup(const BatchSetup& su, const BatchLayout& lay, char* ws, int count,
+                 hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(ws + lay.gdesc, su.gdesc.data(), su.gdesc.size(),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + lay.pdesc, su.pdesc.data(), sizeof(PackDesc) * count,
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + lay.tile_map, su.tile_map.data(), sizeof(int) * su.tile_map.size(),
+                           hipMemcpyHostToDevice, s);
+    // the host tables are freed when the caller returns: wait for the copies
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bfail(RBGS_EHIP, std::string("table upload: ") + hipGetErrorString(e));
+    return RBGS_OK;
+}
+
+int read_error_word(const BatchLayout& lay, char* ws, hipStream_t s) {
+    int err = 0;
+    hipError_t e = hipMemcpyAsync(&err, ws + lay.header + 64, sizeof err, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bfail(RBGS_EHIP, std::string("error word: ") + hipGetErrorString(e));
+    if (err) return bfail(RBGS_ETIMEOUT, "a tile dependency wait in the batched kernel timed out");
+    return RBGS_OK;
+}
+
+template <typename T>
+int sweep_batched_t(int32_t count, const rbgs_grid* grids, void* const* u, const void* const* f,
+                    int32_t nsweeps, const rbgs_sweep_opts* o, char* ws, hipStream_t s) {
+    const rbgs_dtype dt = sizeof(T) == 8 ? RBGS_F64 : RBGS_F32;
+    const BatchLayout lay = batch_layout(count, grids, dt);
+    int fuse = 0, rows = 0;
+    choose_params(count, grids, dt, o, &fuse, &rows);
+    const BatchSetup su = build_setup<T>(count, grids, u, f, lay, ws, fuse, rows, nsweeps);
+    int rc = upload_setup<T>(su, lay, ws, count, s);
+    if (rc) return rc;
+    EventPair ev;
+    if (o && o->timing) {
+        if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess)
+            return bfail(RBGS_EHIP, "event create");
+        (void)hipEventRecord(ev.a, s);
+    }
+    hipError_t e = enqueue_batch<T>(su, lay, ws, count, o, true, true, s);
+    if (e != hipSuccess) return bfail(RBGS_EHIP, std::string("batched sweep: ") + hipGetErrorString(e));
+    if (o && o->timing) {
+        (void)hipEventRecord(ev.b, s);
+        (void)hipEventSynchronize(ev.b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev.a, ev.b);
+        *o->timing = rbgs_timing{0.f, ms, 0.f, (su.passes > 0) + (su.rem > 0)};
+    }
+    return read_error_word(lay, ws, s);
+}
+
+}  // namespace
+}  // namespace rbgs
+
+using namespace rbgs;
+
+struct rbgs_batch_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BatchLayout lay;
+    char* ws = nullptr;
+    int passes = 0, fuse = 0;
+};
+
+extern "C" {
+
+size_t rbgs_batch_workspace_size(int32_t count, const rbgs_grid* grids, rbgs_dtype dt) {
+    if (count < 1 || count > 65535 || !grids || (dt != RBGS_F64 && dt != RBGS_F32)) return 0;
+    for (int g = 0; g < count; ++g)
+        if (grids[g].n < 1 || grids[g].n > 65533 || grids[g].ld < int64_t(grids[g].n) + 2) return 0;
+    return batch_layout(count, grids, dt).total;
+}
+
+const char* rbgs_batch_last_error(void) { return g_batch_error.c_str(); }
+
+int rbgs_sweep_batched(int32_t count, const rbgs_grid* grids, rbgs_dtype dt, void* const* u,
+                       const void* const* f, int32_t nsweeps, const rbgs_sweep_opts* opts,
+                       void* workspace, size_t workspace_bytes, void* stream) {
+    int rc = validate_batch(count, grids, dt, u, f, nsweeps, opts);
+    if (rc) return rc;
+    if ((rc = check_ws(workspace, workspace_bytes, batch_layout(count, grids, dt).total))) return rc;
+    if (nsweeps == 0) return RBGS_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(workspace);
+    return dt == RBGS_F64 ? sweep_batched_t<double>(count, grids, u, f, nsweeps, opts, ws, s)
+                          : sweep_batched_t<float>(count, grids, u, f, nsweeps, opts, ws, s);
+}
+
+int rbgs_batch_plan_create(rbgs_batch_plan** plan, int32_t count, const rbgs_grid* grids,
+                           rbgs_dtype dt, void* const* u, const void* const* f, int32_t nsweeps,
+                           const rbgs_sweep_opts* opts, void* workspace, size_t workspace_bytes) {
+    if (!plan) return bfail(RBGS_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    int rc = validate_batch(count, grids, dt, u, f, nsweeps, opts);
+    if (rc) return rc;
+    if (nsweeps < 1) return bfail(RBGS_EINVAL, "a plan needs nsweeps >= 1");
+    BatchLayout lay = batch_layout(count, grids, dt);
+    if ((rc = check_ws(workspace, workspace_bytes, lay.total))) return rc;
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        return bfail(RBGS_EHIP, "stream create");
+    int fuse = 0, rows = 0;
+    choose_params(count, grids, dt, opts, &fuse, &rows);
+    BatchSetup su;
+    if (dt == RBGS_F64) {
+        su = build_setup<double>(count, grids, u, f, lay, ws, fuse, rows, nsweeps);
+        rc = upload_setup<double>(su, lay, ws, count, cs);
+    } else {
+        su = build_setup<float>(count, grids, u, f, lay, ws, fuse, rows, nsweeps);
+        rc = upload_setup<float>(su, lay, ws, count, cs);
+    }
+    if (rc) {
+        (void)hipStreamDestroy(cs);
+        return rc;
+    }
+    rbgs_batch_plan* p = new rbgs_batch_plan;
+    p->lay = lay;
+    p->ws = ws;
+    p->passes = su.passes;
+    p->fuse = fuse;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e2 = dt == RBGS_F64 ? enqueue_batch<double>(su, lay, ws, count, opts, true, true, cs)
+                                       : enqueue_batch<float>(su, lay, ws, count, opts, true, true, cs);
+        e = hipStreamEndCapture(cs, &p->graph);
+        if (e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        delete p;
+        return bfail(RBGS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    *plan = p;
+    return RBGS_OK;
+}
+
+int rbgs_batch_plan_launch(rbgs_batch_plan* plan, void* stream) {
+    if (!plan || !plan->exec) return bfail(RBGS_EINVAL, "plan is NULL");
+    hipError_t e = hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return bfail(RBGS_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+    return RBGS_OK;
+}
+
+int rbgs_batch_plan_check(rbgs_batch_plan* plan, void* stream) {
+    if (!plan) return bfail(RBGS_EINVAL, "plan is NULL");
+    return read_error_word(plan->lay, plan->ws, static_cast<hipStream_t>(stream));
+}
+
+int rbgs_batch_plan_destroy(rbgs_batch_plan* plan) {
+    if (!plan) return RBGS_OK;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
+    return RBGS_OK;
+}
+
+int rbgs_autotune_batched(int32_t count, const rbgs_grid* grids, rbgs_dtype dt, void* const* u,
+                          const void* const* f, void* workspace, size_t workspace_bytes,
+                          void* stream, rbgs_sweep_opts* best, float* best_ms_per_sweep) {
+    int rc = validate_batch(count, grids, dt, u, f, 0, nullptr);
+    if (rc) return rc;
+    BatchLayout lay = batch_layout(count, grids, dt);
+    if ((rc = check_ws(workspace, workspace_bytes, lay.total))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(workspace);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return bfail(RBGS_EHIP, "event create");
+    const int fuses[] = {2, 3, 4};
+    const int rowsv[] = {64, 128, 256};
+    float best_ms = 1e30f;
+    int bf = kMaxFuse, br = 0;
+    bool packed = false;
+    for (int fu : fuses) {
+        for (int ro : rowsv) {
+            // two passes per candidate, timed after one untimed warm-up pass
+            BatchSetup su = dt == RBGS_F64
+                                ? build_setup<double>(count, grids, u, f, lay, ws, fu, ro, 2 * fu)
+                                : build_setup<float>(count, grids, u, f, lay, ws, fu, ro, 2 * fu);
+            rc = dt == RBGS_F64 ? upload_setup<double>(su, lay, ws, count, s)
+                                : upload_setup<float>(su, lay, ws, count, s);
+            if (rc) break;
+            BatchSetup warm = su;
+            warm.passes = 1;
+            hipError_t e = dt == RBGS_F64
+                               ? enqueue_batch<double>(warm, lay, ws, count, nullptr, !packed, false, s)
+                               : enqueue_batch<float>(warm, lay, ws, count, nullptr, !packed, false, s);
+            packed = true;
+            if (e == hipSuccess) e = hipEventRecord(a, s);
+            if (e == hipSuccess)
+                e = dt == RBGS_F64 ? enqueue_batch<double>(su, lay, ws, count, nullptr, false, false, s)
+                                   : enqueue_batch<float>(su, lay, ws, count, nullptr, false, false, s);
+            if (e == hipSuccess) e = hipEventRecord(b, s);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e != hipSuccess) {
+                rc = bfail(RBGS_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+                break;
+            }
+            if ((rc = read_error_word(lay, ws, s))) break;
+            const float per_sweep = ms / float(2 * fu);
+            if (per_sweep < best_ms) {
+                best_ms = per_sweep;
+                bf = fu;
+                br = ro;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_tune_file();
+        store_tune(tune_key(count, grids, dt), bf, br, best_ms);
+    }
+    if (best) {
+        std::memset(best, 0, sizeof *best);
+        best->kernel = RBGS_KERNEL_BLOCKED;
+        best->fuse = bf;
+        best->tile_rows = br;
+    }
+    if (best_ms_per_sweep) *best_ms_per_sweep = best_ms;
+    return RBGS_OK;
+}
+
+}  // extern "C"

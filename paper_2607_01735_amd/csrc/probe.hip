@@ -7,11 +7,12 @@
 namespace rbgs {
 namespace {
 
+// One 16-byte vector per thread and no loop: measured fastest on MI355X
+// (grid-stride loops and deeper unrolling both streamed more slowly).
 __global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ a,
                                               double2* __restrict__ b, int64_t n2) {
     int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    const int64_t stride = int64_t(gridDim.x) * 256;
-    for (; k < n2; k += stride) b[k] = a[k];
+    if (k < n2) b[k] = a[k];
 }
 
 __global__ __launch_bounds__(256) void k_triad(double2* __restrict__ a,
@@ -19,8 +20,7 @@ __global__ __launch_bounds__(256) void k_triad(double2* __restrict__ a,
                                                const double2* __restrict__ c, double s,
                                                int64_t n2) {
     int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    const int64_t stride = int64_t(gridDim.x) * 256;
-    for (; k < n2; k += stride) {
+    if (k < n2) {
         double2 x = b[k], y = c[k];
         double2 r;
         r.x = x.x + s * y.x;
@@ -42,8 +42,8 @@ extern "C" int rbgs_stream_probe(int32_t kind, double* a, double* b, double* c, 
          reinterpret_cast<uintptr_t>(c)) % 16 != 0)
         return RBGS_EINVAL;
     const int64_t n2 = n_elems / 2;
-    int64_t blocks = (n2 + 255) / 256;
-    if (blocks > 256 * 64) blocks = 256 * 64;  // 64 workgroups per CU, grid-stride beyond
+    const int64_t blocks = (n2 + 255) / 256;
+    if (blocks > 0x7fffffff) return RBGS_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (kind == 0)
         hipLaunchKernelGGL(k_copy, dim3(unsigned(blocks)), dim3(256), 0, st,

@@ -10,6 +10,48 @@
 
 namespace rbgs {
 
+constexpr int kBlockedLanes = 64;  // one wave per tile
+constexpr int kMinRows = 8;
+constexpr int kMaxFuse = 4;
+
+// Tile geometry of one grid: a tile is kBlockedLanes lanes x V q-columns
+// wide (V = 16 bytes / element size) with halo_q columns of halo on each
+// side, and `rows` interior rows tall.
+struct Geometry {
+    int V, L, halo_q, q_core, rows, strips, bands, ntiles;
+};
+
+inline Geometry geometry(int n, int elem_bytes, int fuse, int rows) {
+    Geometry g;
+    g.V = 16 / elem_bytes;
+    g.L = 2 * fuse;
+    const int need = g.L / 2 + 1;  // validity lost per side over L half-sweeps, in q
+    g.halo_q = (need + g.V - 1) / g.V * g.V;
+    g.q_core = kBlockedLanes * g.V - 2 * g.halo_q;
+    g.rows = rows;
+    g.strips = (n + rows - 1) / rows;
+    g.bands = int(((int64_t(n) >> 1) + 1 + g.q_core - 1) / g.q_core);
+    g.ntiles = g.strips * g.bands;
+    return g;
+}
+
+// Upper bound on the tile count of any allowed geometry (rows >= kMinRows,
+// q_core >= 64) for grid size n.
+inline int max_tiles(int n) {
+    int64_t strips = (int64_t(n) + kMinRows - 1) / kMinRows;
+    int64_t bands = ((int64_t(n) >> 1) + 1 + 63) / 64 + 1;
+    return int(strips * bands);
+}
+
+inline int default_rows(int n, int L) {
+    int r = 256;
+    while (r > 2 * L && r > kMinRows && r * 4 > n) r >>= 1;
+    return r < L ? L : r;
+}
+
+// Resident one-wave workgroups per CU for a persistent kernel, and CU count.
+hipError_t persistent_occupancy(const void* kernel, int* per_cu, int* cus);
+
 struct BlockedParams {
     int fuse = 0;       // full sweeps per pass
     int tile_rows = 0;  // interior rows per tile

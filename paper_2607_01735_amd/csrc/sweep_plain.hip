@@ -29,6 +29,29 @@ __device__ __forceinline__ Pack<T, V> load_pack(const T* p) {
     return *reinterpret_cast<const Pack<T, V>*>(p);
 }
 
+// The right-hand side is read exactly once per launch and the updated
+// colour is not read again within it: both go through non-temporal
+// accesses so they do not displace the other colour's rows, which the
+// workgroups of neighbouring strips re-read from L2.
+template <typename T, int V>
+__device__ __forceinline__ Pack<T, V> load_pack_nt(const T* p) {
+    typedef T VT __attribute__((ext_vector_type(V)));
+    VT x = __builtin_nontemporal_load(reinterpret_cast<const VT*>(p));
+    Pack<T, V> r;
+#pragma unroll
+    for (int e = 0; e < V; ++e) r.v[e] = x[e];
+    return r;
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void store_pack_nt(T* p, const Pack<T, V>& v) {
+    typedef T VT __attribute__((ext_vector_type(V)));
+    VT x;
+#pragma unroll
+    for (int e = 0; e < V; ++e) x[e] = v.v[e];
+    __builtin_nontemporal_store(x, reinterpret_cast<VT*>(p));
+}
+
 // Update row i whose parity p = (i + colour) & 1 is a compile-time value.
 // up/mid/dn: other colour, rows i-1, i, i+1 at q0..q0+V-1.
 template <typename T, int V, int P>
@@ -52,7 +75,7 @@ __device__ __forceinline__ void update_row(T* __restrict__ self_row, const T* __
     }
     const int64_t q_lo = 1 - P, q_hi = (int64_t(n) - P) >> 1;
     if (q0 >= q_lo && q0 + V - 1 <= q_hi) {
-        *reinterpret_cast<Pack<T, V>*>(self_row + q0) = out;
+        store_pack_nt<T, V>(self_row + q0, out);
     } else {
 #pragma unroll
         for (int e = 0; e < V; ++e)
@@ -73,8 +96,8 @@ __device__ __forceinline__ void march(T* __restrict__ self, const T* __restrict_
     for (; i + 1 <= i1; i += 2) {
         Pack<T, V> dn0 = load_pack<T, V>(o + int64_t(i + 1) * pitch);
         Pack<T, V> dn1 = load_pack<T, V>(o + int64_t(i + 2) * pitch);
-        Pack<T, V> f0 = load_pack<T, V>(f_self + int64_t(i) * pitch + q0);
-        Pack<T, V> f1 = load_pack<T, V>(f_self + int64_t(i + 1) * pitch + q0);
+        Pack<T, V> f0 = load_pack_nt<T, V>(f_self + int64_t(i) * pitch + q0);
+        Pack<T, V> f1 = load_pack_nt<T, V>(f_self + int64_t(i + 1) * pitch + q0);
         update_row<T, V, P0>(self + int64_t(i) * pitch, other + int64_t(i) * pitch, up, mid, dn0,
                              f0, h2, q0, n);
         update_row<T, V, 1 - P0>(self + int64_t(i + 1) * pitch, other + int64_t(i + 1) * pitch,
@@ -84,7 +107,7 @@ __device__ __forceinline__ void march(T* __restrict__ self, const T* __restrict_
     }
     if (i <= i1) {
         Pack<T, V> dn0 = load_pack<T, V>(o + int64_t(i + 1) * pitch);
-        Pack<T, V> f0 = load_pack<T, V>(f_self + int64_t(i) * pitch + q0);
+        Pack<T, V> f0 = load_pack_nt<T, V>(f_self + int64_t(i) * pitch + q0);
         update_row<T, V, P0>(self + int64_t(i) * pitch, other + int64_t(i) * pitch, up, mid, dn0,
                              f0, h2, q0, n);
     }
@@ -121,12 +144,11 @@ PlainConfig plain_config(int n, int rows_per_block) {
     int64_t vecs = (qcols + V - 1) / V;
     c.threads = vecs >= 256 ? 256 : (vecs > 128 ? 256 : (vecs > 64 ? 128 : 64));
     c.col_blocks = int((vecs + c.threads - 1) / c.threads);
-    int r = rows_per_block;
-    if (r <= 0) {
-        // aim for >= 2048 workgroups (8 per CU) with strips of 2..32 rows
-        r = 32;
-        while (r > 2 && int64_t(c.col_blocks) * ((n + r - 1) / r) < 2048) r >>= 1;
-    }
+    // Short strips (4 rows by default, measured best on MI355X at 8191^2)
+    // give many workgroups in flight; the extra reads of the two halo rows
+    // per strip are served by L2 because consecutive strips run on the same
+    // XCD (xcd_logical_block).
+    int r = rows_per_block > 0 ? rows_per_block : 4;
     c.rows = r;
     c.strips = (n + r - 1) / r;
     c.blocks = c.col_blocks * c.strips;

@@ -81,8 +81,33 @@ _lib.rbgs_strerror.restype = ctypes.c_char_p
 _lib.rbgs_last_error.argtypes = []
 _lib.rbgs_last_error.restype = ctypes.c_char_p
 
+_lib.rbgs_batch_workspace_size.argtypes = [ctypes.c_int32, _P(rbgs_grid), ctypes.c_int]
+_lib.rbgs_batch_workspace_size.restype = ctypes.c_size_t
+_lib.rbgs_sweep_batched.argtypes = [ctypes.c_int32, _P(rbgs_grid), ctypes.c_int, _P(_vp), _P(_vp),
+                                    ctypes.c_int32, _P(rbgs_sweep_opts), _vp, ctypes.c_size_t, _vp]
+_lib.rbgs_sweep_batched.restype = ctypes.c_int
+_lib.rbgs_batch_plan_create.argtypes = [_P(_vp), ctypes.c_int32, _P(rbgs_grid), ctypes.c_int,
+                                        _P(_vp), _P(_vp), ctypes.c_int32, _P(rbgs_sweep_opts), _vp,
+                                        ctypes.c_size_t]
+_lib.rbgs_batch_plan_create.restype = ctypes.c_int
+_lib.rbgs_batch_plan_launch.argtypes = [_vp, _vp]
+_lib.rbgs_batch_plan_launch.restype = ctypes.c_int
+_lib.rbgs_batch_plan_check.argtypes = [_vp, _vp]
+_lib.rbgs_batch_plan_check.restype = ctypes.c_int
+_lib.rbgs_batch_plan_destroy.argtypes = [_vp]
+_lib.rbgs_batch_plan_destroy.restype = ctypes.c_int
+_lib.rbgs_autotune_batched.argtypes = [ctypes.c_int32, _P(rbgs_grid), ctypes.c_int, _P(_vp),
+                                       _P(_vp), _vp, ctypes.c_size_t, _vp, _P(rbgs_sweep_opts),
+                                       _P(ctypes.c_float)]
+_lib.rbgs_autotune_batched.restype = ctypes.c_int
+_lib.rbgs_batch_last_error.argtypes = []
+_lib.rbgs_batch_last_error.restype = ctypes.c_char_p
+
 EXPORTED = ("rbgs_workspace_size", "rbgs_sweep", "rbgs_residual", "rbgs_solve",
-            "rbgs_stream_probe", "rbgs_strerror", "rbgs_last_error")
+            "rbgs_stream_probe", "rbgs_strerror", "rbgs_last_error", "rbgs_batch_workspace_size",
+            "rbgs_sweep_batched", "rbgs_batch_plan_create", "rbgs_batch_plan_launch",
+            "rbgs_batch_plan_check", "rbgs_batch_plan_destroy", "rbgs_autotune_batched",
+            "rbgs_batch_last_error")
 
 
 class RbgsError(RuntimeError):
@@ -102,6 +127,16 @@ def rbgs_last_error():
 def _check(rc, allow=(OK,)):
     if rc not in allow:
         raise RbgsError(rc, rbgs_last_error())
+    return rc
+
+
+def rbgs_batch_last_error():
+    return _lib.rbgs_batch_last_error().decode()
+
+
+def _bcheck(rc):
+    if rc != OK:
+        raise RbgsError(rc, rbgs_batch_last_error())
     return rc
 
 
@@ -232,3 +267,109 @@ def rbgs_stream_probe(kind, a, b, c=None, s=3.0, stream=None):
     cp = _vp(c.data_ptr()) if c is not None else None
     _check(_lib.rbgs_stream_probe(int(kind), _vp(a.data_ptr()), _vp(b.data_ptr()), cp, n,
                                   float(s), _stream_ptr(stream, a.device)))
+
+
+# ---------------------------------------------------------------------------
+# Batches of grids
+# ---------------------------------------------------------------------------
+class _Batch:
+    """Host arrays of one batch: grid descriptors and device pointers."""
+
+    def __init__(self, us, fs, hs=None):
+        if len(us) != len(fs) or not us:
+            raise ValueError("need equal, non-empty lists of u and f tensors")
+        self.count = len(us)
+        self.code = _dtype_code(us[0])
+        self.grids = (rbgs_grid * self.count)()
+        self.u = (_vp * self.count)()
+        self.f = (_vp * self.count)()
+        for g, (u, f) in enumerate(zip(us, fs)):
+            _same_layout(u, f)
+            if _dtype_code(u) != self.code or u.device != us[0].device:
+                raise ValueError("all grids of a batch share dtype and device")
+            self.grids[g] = make_grid(u, None if hs is None else hs[g])
+            self.u[g] = u.data_ptr()
+            self.f[g] = f.data_ptr()
+        self.device = us[0].device
+        self.tensors = (list(us), list(fs))  # keep the arrays alive
+
+    def workspace(self, workspace=None):
+        import torch
+        need = int(_lib.rbgs_batch_workspace_size(self.count, self.grids, self.code))
+        if need == 0:
+            raise RbgsError(EINVAL, "invalid batch")
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return workspace
+
+
+def rbgs_batch_workspace_size(us, fs, hs=None):
+    b = _Batch(us, fs, hs)
+    return int(_lib.rbgs_batch_workspace_size(b.count, b.grids, b.code))
+
+
+def rbgs_sweep_batched(us, fs, nsweeps, hs=None, workspace=None, stream=None, timing=False,
+                       **tuning):
+    """nsweeps sweeps of every grid in one persistent launch (synchronises)."""
+    b = _Batch(us, fs, hs)
+    ws = b.workspace(workspace)
+    t = rbgs_timing() if timing else None
+    opts = _sweep_opts(kernel=tuning.pop("kernel", "auto"), timing=t, **tuning)
+    _bcheck(_lib.rbgs_sweep_batched(b.count, b.grids, b.code, b.u, b.f, int(nsweeps),
+                                    ctypes.byref(opts), _vp(ws.data_ptr()), ws.numel(),
+                                    _stream_ptr(stream, b.device)))
+    if timing:
+        return {"sweep_ms": t.sweep_ms, "sweep_launches": t.sweep_launches}
+    return None
+
+
+class BatchPlan:
+    """A batched sweep captured into a HIP graph; launch() replays it."""
+
+    def __init__(self, us, fs, nsweeps, hs=None, workspace=None, **tuning):
+        self._batch = _Batch(us, fs, hs)
+        self.workspace = self._batch.workspace(workspace)
+        opts = _sweep_opts(kernel=tuning.pop("kernel", "auto"), **tuning)
+        handle = _vp()
+        b = self._batch
+        _bcheck(_lib.rbgs_batch_plan_create(ctypes.byref(handle), b.count, b.grids, b.code, b.u,
+                                            b.f, int(nsweeps), ctypes.byref(opts),
+                                            _vp(self.workspace.data_ptr()), self.workspace.numel()))
+        self._handle = handle
+        self.nsweeps = int(nsweeps)
+
+    def launch(self, stream=None):
+        _bcheck(_lib.rbgs_batch_plan_launch(self._handle, _stream_ptr(stream, self._batch.device)))
+
+    def check(self, stream=None):
+        _bcheck(_lib.rbgs_batch_plan_check(self._handle, _stream_ptr(stream, self._batch.device)))
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            _lib.rbgs_batch_plan_destroy(self._handle)
+            self._handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rbgs_autotune_batched(us, fs, hs=None, workspace=None, stream=None):
+    """Tune (fuse, tile_rows) for this batch shape; returns the choice."""
+    b = _Batch(us, fs, hs)
+    ws = b.workspace(workspace)
+    best = rbgs_sweep_opts()
+    ms = ctypes.c_float()
+    _bcheck(_lib.rbgs_autotune_batched(b.count, b.grids, b.code, b.u, b.f, _vp(ws.data_ptr()),
+                                       ws.numel(), _stream_ptr(stream, b.device),
+                                       ctypes.byref(best), ctypes.byref(ms)))
+    return {"fuse": best.fuse, "tile_rows": best.tile_rows, "ms_per_sweep": ms.value}
