@@ -1,0 +1,108 @@
+"""Pins of the reference U-Net (CPU): library correlation for the conv,
+adjoint identities for restriction/prolongation, and finite differences for
+the hand-written backward pass."""
+import numpy as np
+import pytest
+
+from oracle import unet_ref as U
+
+scipy_signal = pytest.importorskip("scipy.signal")
+
+
+def test_conv_matches_library_correlation():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((3, 9, 7))
+    w = rng.standard_normal((4, 3, 3, 3))
+    b = rng.standard_normal(4)
+    y = U.conv3x3(x, w, b)
+    for co in range(4):
+        ref = sum(scipy_signal.correlate2d(x[ci], w[co, ci], mode="same", boundary="fill")
+                  for ci in range(3)) + b[co]
+        assert np.allclose(y[co], ref, rtol=1e-13, atol=1e-13)
+
+
+def test_restrict_and_prolong_identities():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((2, 15, 15))
+    y = rng.standard_normal((2, 7, 7))
+    # adjoint: <R x, y> = <x, R^T y>
+    assert np.isclose(np.sum(U.restrict(x) * y), np.sum(x * U.restrict_transpose(y, 15)), rtol=1e-13)
+    # weights sum to one: a constant restricts to itself
+    assert np.allclose(U.restrict(np.full((1, 15, 15), 2.5)), 2.5)
+    # prolongation injects coarse values at coinciding points and averages between
+    p = U.prolong(y, 15)
+    assert np.allclose(p[:, 1::2, 1::2], y)
+    assert np.allclose(p[:, 1::2, 2:-1:2], 0.5 * (y[:, :, :-1] + y[:, :, 1:]))
+    assert np.allclose(p[:, 2:-1:2, 2:-1:2],
+                       0.25 * (y[:, :-1, :-1] + y[:, 1:, :-1] + y[:, :-1, 1:] + y[:, 1:, 1:]))
+
+
+def test_conv_backward_by_finite_differences():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((2, 5, 6))
+    w = rng.standard_normal((3, 2, 3, 3))
+    b = rng.standard_normal(3)
+    dy = rng.standard_normal((3, 5, 6))
+    dx, dw, db = U.conv3x3_backward(x, w, dy)
+    loss = lambda x_, w_, b_: float(np.sum(U.conv3x3(x_, w_, b_) * dy))
+    eps = 1e-6
+    for _ in range(10):
+        idx = tuple(rng.integers(0, s) for s in x.shape)
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += eps
+        xm[idx] -= eps
+        assert np.isclose((loss(xp, w, b) - loss(xm, w, b)) / (2 * eps), dx[idx], rtol=1e-6, atol=1e-8)
+        idx = tuple(rng.integers(0, s) for s in w.shape)
+        wp, wm = w.copy(), w.copy()
+        wp[idx] += eps
+        wm[idx] -= eps
+        assert np.isclose((loss(x, wp, b) - loss(x, wm, b)) / (2 * eps), dw[idx], rtol=1e-6, atol=1e-8)
+    bp = b.copy()
+    bp[1] += eps
+    bm = b.copy()
+    bm[1] -= eps
+    assert np.isclose((loss(x, w, bp) - loss(x, w, bm)) / (2 * eps), db[1], rtol=1e-6)
+
+
+def test_network_gradient_by_finite_differences():
+    channels = (2, 3, 4, 5)
+    n = 15
+    p = U.init_params(channels, seed=3)
+    rng = np.random.default_rng(4)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = rng.standard_normal(p[k].shape) * 0.1
+    x0 = rng.standard_normal((n, n))
+    target = rng.standard_normal((n, n))
+
+    def loss_of(params):
+        y, _ = U.forward(params, x0, channels)
+        return U.mse_loss(y, target)[0]
+
+    y, cache = U.forward(p, x0, channels)
+    _, dy = U.mse_loss(y, target)
+    g = U.backward(p, cache, dy, channels)
+    assert set(g) == set(p)
+    eps = 1e-6
+    checked = 0
+    for k in sorted(p):
+        flat = p[k].reshape(-1)
+        for j in rng.choice(flat.size, size=min(3, flat.size), replace=False):
+            pp = {kk: vv.copy() for kk, vv in p.items()}
+            pm = {kk: vv.copy() for kk, vv in p.items()}
+            pp[k].reshape(-1)[j] += eps
+            pm[k].reshape(-1)[j] -= eps
+            fd = (loss_of(pp) - loss_of(pm)) / (2 * eps)
+            an = g[k].reshape(-1)[j]
+            assert np.isclose(fd, an, rtol=1e-4, atol=1e-8), (k, j, fd, an)
+            checked += 1
+    assert checked > 40
+
+
+def test_adam_step_moves_against_gradient():
+    p = {"a": np.array([1.0, -2.0])}
+    g = {"a": np.array([0.5, -0.25])}
+    state = {}
+    U.adam_step(p, g, state, lr=0.1)
+    # first bias-corrected Adam step is lr * sign(g)
+    assert np.allclose(p["a"], [0.9, -1.9], atol=1e-7)
