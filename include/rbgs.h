@@ -237,6 +237,56 @@ int rbgs_autotune_batched(int32_t count, const rbgs_grid *grids,
 /* Message for the calling thread's last failure in a batched call. */
 const char *rbgs_batch_last_error(void);
 
+/* ---------------------------------------------------------------------
+ * Learned initial guess (not in the paper): a small U-Net f -> u0 trained
+ * on (f, u*) pairs that this library's solver produced, run and trained by
+ * the library's own BF16/FP32 kernels.  Grids are N x N with N = 2^k - 1 in
+ * [63, 8191] (four levels of halving); input f/rms(f), output u0 =
+ * net(f/rms(f)) * rms(f).  Batched arrays are `batch` natural-layout grids
+ * of (n+2) x ld doubles stored back to back.  Parameters: one FP32 vector of
+ * rbgs_unet_param_count() values, per conv layer its weight (cout, cin,
+ * 3, 3) then bias (cout), in the order enc0.0, enc0.1, ..., enc3.1,
+ * dec2.0, dec2.1, dec1.0, dec1.1, dec0.0, dec0.1, then the 1x1 head's 16
+ * weights and 1 bias.  All state (master weights, Adam moments, BF16
+ * copies, activations) lives in the caller's workspace.
+ * --------------------------------------------------------------------- */
+typedef struct rbgs_unet rbgs_unet;
+size_t rbgs_unet_param_count(void);
+size_t rbgs_unet_workspace_size(int32_t n, int32_t batch);
+int rbgs_unet_create(rbgs_unet **net, int32_t n, int32_t batch,
+                     void *workspace, size_t workspace_bytes);
+int rbgs_unet_destroy(rbgs_unet *net);
+/* HOST vector in; resets the Adam state.  Synchronises. */
+int rbgs_unet_set_params(rbgs_unet *net, const float *params, size_t count,
+                         void *stream);
+/* HOST vectors out.  Synchronise. */
+int rbgs_unet_get_params(rbgs_unet *net, float *params, size_t count,
+                         void *stream);
+int rbgs_unet_get_grads(rbgs_unet *net, float *grads, size_t count,
+                        void *stream);
+/* u0 (device) interior <- network guess for f (device); u0's ring is left
+ * untouched.  batch <= the batch given at creation.  Asynchronous. */
+int rbgs_unet_forward(rbgs_unet *net, int32_t batch, const double *f,
+                      int64_t ld, double *u0, void *stream);
+/* One training step on a batch: forward, mean squared error against
+ * u_target/rms(f) on the interior, backward into the gradient vector, and
+ * (update != 0) one Adam step with learning rate lr (beta 0.9/0.999,
+ * eps 1e-8).  *loss (HOST, may be NULL) receives the loss before the
+ * update; passing it synchronises. */
+int rbgs_unet_train_step(rbgs_unet *net, int32_t batch, const double *f,
+                         const double *u_target, int64_t ld, float lr,
+                         int32_t update, float *loss, void *stream);
+/* Solve with the learned guess: the network's guess replaces the caller's
+ * start u only if its relative residual is lower (the plain start is both
+ * fallback and judge), then rbgs_solve runs.  *used_guess and *rel_start
+ * (HOST, may be NULL) report the choice.  Needs ld = n + 2. */
+int rbgs_solve_learned(rbgs_unet *net, const rbgs_grid *g, double *u,
+                       const double *f, const rbgs_solve_opts *opts,
+                       rbgs_solve_info *info, int32_t *used_guess,
+                       double *rel_start, void *workspace,
+                       size_t workspace_bytes, void *stream);
+const char *rbgs_unet_last_error(void);
+
 /* Device-memory bandwidth probe: the copy (kind 0: b = a) and triad
  * (kind 1: a = b + s*c) kernels of the STREAM benchmark, which the paper
  * uses for the attainable memory bandwidth in its roofline (Section 3,

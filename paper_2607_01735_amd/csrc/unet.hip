@@ -1,0 +1,931 @@
+// Learned initial guess: a small U-Net, trained and run by hand-written
+// kernels (BF16 activations and weights, FP32 accumulation on MFMA, FP32
+// master weights and Adam).
+//
+// Network: input x0 = f / rms(f) on the N x N interior (N = 2^k - 1);
+// four levels on grids N_l = (N_{l-1}-1)/2 with 16/32/64/128 channels; each
+// encoder level is conv3x3+ReLU twice, levels are linked by full-weighting
+// restriction R; each decoder level concatenates the bilinear prolongation
+// P = 4 R^T of the level below with the encoder's output of its own level
+// and applies conv3x3+ReLU twice; a 1x1 head gives y, and u0 = y * rms(f).
+// The restriction/prolongation pair is the multigrid transfer pair, fixed
+// (no weights).  Loss: mean squared error against u*/rms(f).
+//
+// Tensors are NHWC (batch, row, column, channel) in bfloat16; a tensor view
+// has a pixel stride (channels per pixel of its buffer), so an encoder
+// output is written straight into the channel slice of the decoder's
+// concatenation buffer.  Convolutions are implicit GEMMs on the 16x16x16
+// BF16 MFMA: pixels x output channels, K = 9 taps x input channels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rbgs.h"
+#include "rbgs_internal.h"
+
+namespace rbgs {
+namespace nn {
+
+typedef uint16_t bf16;
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(bf16 v) { return __uint_as_float(uint32_t(v) << 16); }
+
+__device__ __forceinline__ bf16 f2bf(float x) {
+    // round to nearest, ties to even (NaN kept quiet)
+    uint32_t b = __float_as_uint(x);
+    if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu) != 0u) return bf16((b | 0x00400000u) >> 16);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return bf16(b >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution, stride 1, zero padding 1, as an implicit GEMM.
+// One wave computes 16 consecutive pixels of one row for all output
+// channels.  MFMA 16x16x16 lane layout (checked on the device):
+//   A[m][k]: lane l holds m = l%16, k = 4(l/16)+j;  B[k][n]: n = l%16,
+//   k = 4(l/16)+j;  D[m][n]: lane l holds m = 4(l/16)+i, n = l%16.
+// X may be masked: an input element counts as 0 where mask <= 0 (this is
+// how the backward pass applies the ReLU derivative of the layer output).
+// ---------------------------------------------------------------------------
+struct ConvArgs {
+    const bf16* x;
+    int64_t xs;        // pixel stride of x (channels of its buffer)
+    const bf16* mask;  // optional, same geometry as x, stride ms
+    int64_t ms;
+    const bf16* w;     // [cout][9][cin]
+    const float* bias; // optional
+    bf16* y;
+    int64_t ys;
+    int batch, h, wd, cin, cout, relu;
+};
+
+constexpr int kMaxCoutTiles = 12;  // up to 192 output channels
+
+__global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int segs = (a.wd + 15) / 16;
+    const int64_t total = int64_t(a.batch) * a.h * segs;
+    if (wave >= total) return;
+    const int seg = int(wave % segs);
+    const int row = int((wave / segs) % a.h);
+    const int b = int(wave / (int64_t(segs) * a.h));
+    const int x0 = seg * 16;
+    const int ntiles = a.cout / 16;
+    f32x4 acc[kMaxCoutTiles];
+#pragma unroll
+    for (int t = 0; t < kMaxCoutTiles; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int m = lane & 15, kq = (lane >> 4) * 4;
+    for (int tap = 0; tap < 9; ++tap) {
+        const int yy = row + tap / 3 - 1, xx = x0 + m + tap % 3 - 1;
+        const bool inside = yy >= 0 && yy < a.h && xx >= 0 && xx < a.wd;
+        const int64_t pix = (int64_t(b) * a.h + yy) * a.wd + xx;
+        for (int c0 = 0; c0 < a.cin; c0 += 16) {
+            bf16x4 av = {0, 0, 0, 0};
+            if (inside) {
+                const bf16* px = a.x + pix * a.xs + c0 + kq;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) av[j] = short(px[j]);
+                if (a.mask) {
+                    const bf16* pm = a.mask + pix * a.ms + c0 + kq;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (!(bf2f(pm[j]) > 0.f)) av[j] = 0;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kMaxCoutTiles; ++t) {
+                if (t < ntiles) {
+                    const bf16* pw = a.w + (int64_t(t * 16 + m) * 9 + tap) * a.cin + c0 + kq;
+                    bf16x4 bv;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) bv[j] = short(pw[j]);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
+                }
+            }
+        }
+    }
+    const int n = lane & 15, mq = (lane >> 4) * 4;
+#pragma unroll
+    for (int t = 0; t < kMaxCoutTiles; ++t) {
+        if (t < ntiles) {
+            const int co = t * 16 + n;
+            const float bias = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int xx = x0 + mq + i;
+                float v = acc[t][i] + bias;
+                if (a.relu) v = v > 0.f ? v : 0.f;
+                if (xx < a.wd) a.y[((int64_t(b) * a.h + row) * a.wd + xx) * a.ys + co] = f2bf(v);
+            }
+        }
+    }
+}
+
+// Weight gradient dW[co][ci][tap] += sum_p dZ[p][co] * X[p + off(tap)][ci],
+// dZ = dY masked by (Y > 0).  MFMA with M = 16 output channels, N = 16
+// input channels, K = 16 pixels of a row; one wave per (row block, tap,
+// ci tile, co tile), partial sums added atomically in FP32.
+struct WGradArgs {
+    const bf16* x;
+    int64_t xs;
+    const bf16* dy;
+    int64_t dys;
+    const bf16* y;  // layer output (mask), stride ys
+    int64_t ys;
+    float* dw;      // [cout][cin_w][9]
+    int batch, h, wd, cin, cout, rows_per_wave;
+    int cin_w;      // input channels of the weight tensor (cin is padded to 16)
+};
+
+__global__ __launch_bounds__(256) void k_conv3x3_wgrad(WGradArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int cit = a.cin / 16, cot = a.cout / 16;
+    const int rblocks = (a.h + a.rows_per_wave - 1) / a.rows_per_wave;
+    const int64_t total = int64_t(a.batch) * rblocks * 9 * cit * cot;
+    if (wave >= total) return;
+    int64_t r = wave;
+    const int co_t = int(r % cot); r /= cot;
+    const int ci_t = int(r % cit); r /= cit;
+    const int tap = int(r % 9); r /= 9;
+    const int rb = int(r % rblocks); r /= rblocks;
+    const int b = int(r);
+    const int dyo = tap / 3 - 1, dxo = tap % 3 - 1;
+    const int l16 = lane & 15, kq = (lane >> 4) * 4;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int r0 = rb * a.rows_per_wave, r1 = min(a.h, r0 + a.rows_per_wave);
+    for (int row = r0; row < r1; ++row) {
+        const int yy = row + dyo;
+        for (int x0 = 0; x0 < a.wd; x0 += 16) {
+            bf16x4 av, bv;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int xx = x0 + kq + j;
+                float g = 0.f;
+                float xv = 0.f;
+                if (xx < a.wd) {
+                    const int64_t p = (int64_t(b) * a.h + row) * a.wd + xx;
+                    const int co = co_t * 16 + l16;
+                    if (bf2f(a.y[p * a.ys + co]) > 0.f) g = bf2f(a.dy[p * a.dys + co]);
+                    const int xs2 = xx + dxo;
+                    if (yy >= 0 && yy < a.h && xs2 >= 0 && xs2 < a.wd) {
+                        const int64_t q = (int64_t(b) * a.h + yy) * a.wd + xs2;
+                        xv = bf2f(a.x[q * a.xs + ci_t * 16 + l16]);
+                    }
+                }
+                av[j] = short(f2bf(g));
+                bv[j] = short(f2bf(xv));
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+        }
+    }
+    const int n = lane & 15, mq = (lane >> 4) * 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int co = co_t * 16 + mq + i, ci = ci_t * 16 + n;
+        if (ci < a.cin_w) atomicAdd(a.dw + (int64_t(co) * a.cin_w + ci) * 9 + tap, acc[i]);
+    }
+}
+
+// Bias gradient db[c] += sum_p dY[p][c] (Y[p][c] > 0); one block per row.
+__global__ __launch_bounds__(256) void k_bias_grad(const bf16* dy, int64_t dys, const bf16* y,
+                                                   int64_t ys, float* db, int rows, int wd,
+                                                   int c) {
+    const int64_t row = blockIdx.x;
+    for (int ch = threadIdx.x; ch < c; ch += 256) {
+        float s = 0.f;
+        for (int x = 0; x < wd; ++x) {
+            const int64_t p = row * wd + x;
+            if (bf2f(y[p * ys + ch]) > 0.f) s += bf2f(dy[p * dys + ch]);
+        }
+        atomicAdd(db + ch, s);
+    }
+    (void)rows;
+}
+
+// Full-weighting restriction (fine 2n+1 -> coarse n) or bilinear
+// prolongation (coarse n -> fine 2n+1, P = 4 R^T), per channel, scaled by
+// `scale`; accumulate != 0 adds into the output instead of overwriting.
+__global__ __launch_bounds__(256) void k_restrict(const bf16* in, int64_t is, bf16* out, int64_t os,
+                                                  int batch, int nc, int c, float scale,
+                                                  int accumulate) {
+    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t total = int64_t(batch) * nc * nc * c;
+    if (idx >= total) return;
+    const int ch = int(idx % c);
+    int64_t r = idx / c;
+    const int J = int(r % nc); r /= nc;
+    const int I = int(r % nc);
+    const int b = int(r / nc);
+    const int nf = 2 * nc + 1;
+    const float w1[3] = {1.f, 2.f, 1.f};
+    float s = 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb)
+            s += w1[a] * w1[bb] * bf2f(in[((int64_t(b) * nf + 2 * I + a) * nf + 2 * J + bb) * is + ch]);
+    s *= scale / 16.f;
+    bf16* o = out + ((int64_t(b) * nc + I) * nc + J) * os + ch;
+    if (accumulate) s += bf2f(*o);
+    *o = f2bf(s);
+}
+
+__global__ __launch_bounds__(256) void k_prolong(const bf16* in, int64_t is, bf16* out, int64_t os,
+                                                 int batch, int nc, int c, float scale,
+                                                 int accumulate) {
+    const int nf = 2 * nc + 1;
+    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t total = int64_t(batch) * nf * nf * c;
+    if (idx >= total) return;
+    const int ch = int(idx % c);
+    int64_t r = idx / c;
+    const int j = int(r % nf); r /= nf;
+    const int i = int(r % nf);
+    const int b = int(r / nf);
+    // coarse (I, J) sits on fine (2I+1, 2J+1); 1D weight 1 there, 1/2 at +-1
+    float s = 0.f;
+    for (int I = (i - 2) / 2; I <= i / 2; ++I) {
+        if (I < 0 || I >= nc) continue;
+        const int di = i - (2 * I + 1);
+        if (di < -1 || di > 1) continue;
+        const float wi = di == 0 ? 1.f : 0.5f;
+        for (int J = (j - 2) / 2; J <= j / 2; ++J) {
+            if (J < 0 || J >= nc) continue;
+            const int dj = j - (2 * J + 1);
+            if (dj < -1 || dj > 1) continue;
+            const float wj = dj == 0 ? 1.f : 0.5f;
+            s += wi * wj * bf2f(in[((int64_t(b) * nc + I) * nc + J) * is + ch]);
+        }
+    }
+    s *= scale;
+    bf16* o = out + ((int64_t(b) * nf + i) * nf + j) * os + ch;
+    if (accumulate) s += bf2f(*o);
+    *o = f2bf(s);
+}
+
+// Per-sample rms of f over the interior (FP64 sums, one block per sample).
+__global__ __launch_bounds__(256) void k_rms(const double* f, int n, int64_t ld, int64_t gstride,
+                                             float* rms) {
+    const int b = blockIdx.x;
+    const double* fb = f + int64_t(b) * gstride;
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < int64_t(n) * n; k += 256) {
+        const int64_t i = k / n + 1, j = k % n + 1;
+        const double v = fb[i * ld + j];
+        s += v * v;
+    }
+    __shared__ double sh[256];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double r = sqrt(sh[0] / (double(n) * n));
+        rms[b] = r > 0.0 ? float(r) : 1.f;
+    }
+}
+
+// Network input: channel 0 = f / rms, channels 1..15 = 0 (the first conv's
+// K is padded to one 16-wide MFMA chunk per tap).
+__global__ __launch_bounds__(256) void k_input(const double* f, int n, int64_t ld, int64_t gstride,
+                                               const float* rms, bf16* x, int batch) {
+    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t total = int64_t(batch) * n * n;
+    if (idx >= total) return;
+    const int b = int(idx / (int64_t(n) * n));
+    const int64_t k = idx % (int64_t(n) * n);
+    const int64_t i = k / n + 1, j = k % n + 1;
+    const float v = float(f[int64_t(b) * gstride + i * ld + j] / double(rms[b]));
+    bf16* px = x + idx * 16;
+    px[0] = f2bf(v);
+#pragma unroll
+    for (int c = 1; c < 16; ++c) px[c] = 0;
+}
+
+// Head: y[p] = sum_c w[c] d[p][c] + b (FP32 out).
+__global__ __launch_bounds__(256) void k_head(const bf16* d, int64_t ds, const float* w,
+                                              const float* bias, float* y, int64_t npix, int c) {
+    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (p >= npix) return;
+    float s = bias[0];
+    for (int ch = 0; ch < c; ++ch) s += w[ch] * bf2f(d[p * ds + ch]);
+    y[p] = s;
+}
+
+// u0 = y * rms on the interior of the natural-layout output.
+__global__ __launch_bounds__(256) void k_output(const float* y, const float* rms, double* u, int n,
+                                                int64_t ld, int64_t gstride, int batch) {
+    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= int64_t(batch) * n * n) return;
+    const int b = int(idx / (int64_t(n) * n));
+    const int64_t k = idx % (int64_t(n) * n);
+    const int64_t i = k / n + 1, j = k % n + 1;
+    u[int64_t(b) * gstride + i * ld + j] = double(y[idx]) * double(rms[b]);
+}
+
+// MSE against u*/rms: dy = 2 (y - t) / count, loss accumulated in FP32.
+__global__ __launch_bounds__(256) void k_mse(const float* y, const double* u, const float* rms,
+                                             int n, int64_t ld, int64_t gstride, int batch,
+                                             float* dy, float* loss) {
+    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t count = int64_t(batch) * n * n;
+    float d = 0.f;
+    if (idx < count) {
+        const int b = int(idx / (int64_t(n) * n));
+        const int64_t k = idx % (int64_t(n) * n);
+        const int64_t i = k / n + 1, j = k % n + 1;
+        const float t = float(u[int64_t(b) * gstride + i * ld + j] / double(rms[b]));
+        d = y[idx] - t;
+        dy[idx] = 2.f * d / float(count);
+    }
+    __shared__ float sh[256];
+    sh[threadIdx.x] = d * d;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(loss, sh[0] / float(count));
+}
+
+// Head backward: dd[p][c] = w[c] dy[p] (BF16); dw[c] += sum dy d; db += sum dy.
+__global__ __launch_bounds__(256) void k_head_grad(const bf16* d, int64_t ds, const float* w,
+                                                   const float* dy, bf16* dd, int64_t dds,
+                                                   float* dw, float* db, int64_t npix, int c) {
+    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    __shared__ float sw[17][256];
+    const bool ok = p < npix;
+    const float g = ok ? dy[p] : 0.f;
+    for (int ch = 0; ch < c; ++ch) {
+        if (ok) dd[p * dds + ch] = f2bf(w[ch] * g);
+        sw[ch][threadIdx.x] = ok ? g * bf2f(d[p * ds + ch]) : 0.f;
+    }
+    sw[16][threadIdx.x] = g;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int ch = 0; ch <= 16; ++ch) sw[ch][threadIdx.x] += sw[ch][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int ch = 0; ch < c; ++ch) atomicAdd(dw + ch, sw[ch][0]);
+        atomicAdd(db, sw[16][0]);
+    }
+}
+
+// Master FP32 weights [co][ci][9] -> forward BF16 [co][9][cin_p] (zero-padded
+// input channels) and backward-data BF16 [ci][9][co] with the taps flipped.
+__global__ __launch_bounds__(256) void k_prep_weights(const float* w, int cout, int cin, int cin_p,
+                                                      bf16* wf, bf16* wb) {
+    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t total = int64_t(cout) * cin_p * 9;
+    if (idx >= total) return;
+    const int ci = int(idx % cin_p);
+    const int tap = int((idx / cin_p) % 9);
+    const int co = int(idx / (int64_t(cin_p) * 9));
+    const float v = ci < cin ? w[(int64_t(co) * cin + ci) * 9 + tap] : 0.f;
+    wf[(int64_t(co) * 9 + tap) * cin_p + ci] = f2bf(v);
+    if (wb && ci < cin) wb[(int64_t(ci) * 9 + (8 - tap)) * cout + co] = f2bf(v);
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* p, const float* g, float* m, float* v,
+                                              int64_t count, float lr, float b1, float b2,
+                                              float eps, float c1, float c2) {
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (k >= count) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.f - b1) * gk;
+    const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+__global__ __launch_bounds__(256) void k_fill(uint32_t* p, int64_t words) {
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (k < words) p[k] = 0u;
+}
+
+}  // namespace nn
+}  // namespace rbgs
+
+// ===========================================================================
+// Host side: the network object and the C ABI.
+// ===========================================================================
+namespace rbgs {
+namespace nn {
+namespace {
+
+constexpr int kLevels = 4;
+constexpr int kC[kLevels] = {16, 32, 64, 128};
+
+struct Layer {
+    const char* name;
+    int cin, cin_p, cout, level;
+    size_t w_off, b_off;  // float offsets in the master parameter vector
+    bf16* wf = nullptr;   // [cout][9][cin_p]
+    bf16* wb = nullptr;   // [cin][9][cout] (flipped taps) for the input gradient
+};
+
+// Parameter order and shapes: each conv's weight (cout, cin, 3, 3) then its
+// bias (cout), in the order enc0.0 ... enc3.1, dec2.0 ... dec0.1, head.
+std::vector<Layer> make_layers(size_t* count) {
+    std::vector<Layer> L;
+    auto add = [&](const char* name, int cin, int cout, int level) {
+        Layer l;
+        l.name = name;
+        l.cin = cin;
+        l.cin_p = cin < 16 ? 16 : cin;
+        l.cout = cout;
+        l.level = level;
+        L.push_back(l);
+    };
+    add("enc0.0", 1, 16, 0);
+    add("enc0.1", 16, 16, 0);
+    add("enc1.0", 16, 32, 1);
+    add("enc1.1", 32, 32, 1);
+    add("enc2.0", 32, 64, 2);
+    add("enc2.1", 64, 64, 2);
+    add("enc3.0", 64, 128, 3);
+    add("enc3.1", 128, 128, 3);
+    add("dec2.0", 192, 64, 2);
+    add("dec2.1", 64, 64, 2);
+    add("dec1.0", 96, 32, 1);
+    add("dec1.1", 32, 32, 1);
+    add("dec0.0", 48, 16, 0);
+    add("dec0.1", 16, 16, 0);
+    size_t off = 0;
+    for (auto& l : L) {
+        l.w_off = off;
+        off += size_t(l.cout) * l.cin * 9;
+        l.b_off = off;
+        off += l.cout;
+    }
+    *count = off + 16 + 1;  // head weight (1, 16, 1, 1) and bias
+    return L;
+}
+
+}  // namespace
+
+struct Net {
+    int n[kLevels];
+    int batch;
+    std::vector<Layer> layers;
+    size_t nparam;
+    float *param, *grad, *m, *v, *rms, *loss, *y, *dy;
+    double* guess;  // natural-layout scratch grid for the learned solve
+    int adam_t = 0;
+    // activations (level-indexed) and their gradients
+    bf16 *in[kLevels], *aenc[kLevels], *cat[kLevels - 1], *e3, *adec[kLevels - 1], *d[kLevels - 1];
+    bf16 *gd[kLevels - 1], *ge3, *gadec[kLevels - 1], *gcat[kLevels - 1], *gaenc[kLevels],
+        *gin[kLevels];
+    size_t total = 0;
+};
+
+namespace {
+
+int cat_channels(int l) { return kC[l + 1] + kC[l]; }
+int in_channels(int l) { return l == 0 ? 16 : kC[l - 1]; }
+
+// Carves every buffer; with base == nullptr only computes the size.
+size_t carve(Net& net, char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    const int64_t B = net.batch;
+    net.param = reinterpret_cast<float*>(take(net.nparam * 4));
+    net.grad = reinterpret_cast<float*>(take(net.nparam * 4));
+    net.m = reinterpret_cast<float*>(take(net.nparam * 4));
+    net.v = reinterpret_cast<float*>(take(net.nparam * 4));
+    for (auto& l : net.layers) {
+        l.wf = reinterpret_cast<bf16*>(take(size_t(l.cout) * 9 * l.cin_p * 2));
+        l.wb = reinterpret_cast<bf16*>(take(size_t(l.cin) * 9 * l.cout * 2));
+    }
+    net.rms = reinterpret_cast<float*>(take(B * 4));
+    net.loss = reinterpret_cast<float*>(take(4));
+    const int64_t px0 = int64_t(net.n[0]) * net.n[0];
+    net.y = reinterpret_cast<float*>(take(B * px0 * 4));
+    net.dy = reinterpret_cast<float*>(take(B * px0 * 4));
+    net.guess = reinterpret_cast<double*>(take(size_t(net.n[0] + 2) * (net.n[0] + 2) * 8));
+    for (int l = 0; l < kLevels; ++l) {
+        const int64_t px = B * net.n[l] * net.n[l];
+        auto act = [&](int ch) { return reinterpret_cast<bf16*>(take(size_t(px) * ch * 2)); };
+        net.in[l] = act(in_channels(l));
+        net.aenc[l] = act(kC[l]);
+        net.gaenc[l] = act(kC[l]);
+        net.gin[l] = act(in_channels(l));
+        if (l < kLevels - 1) {
+            net.cat[l] = act(cat_channels(l));
+            net.gcat[l] = act(cat_channels(l));
+            net.adec[l] = act(kC[l]);
+            net.gadec[l] = act(kC[l]);
+            net.d[l] = act(kC[l]);
+            net.gd[l] = act(kC[l]);
+        } else {
+            net.e3 = act(kC[l]);
+            net.ge3 = act(kC[l]);
+        }
+    }
+    return off;
+}
+
+unsigned blocks_for(int64_t items, int per_block = 256) {
+    return unsigned((items + per_block - 1) / per_block);
+}
+
+hipError_t conv(const Net& net, const Layer& L, const bf16* x, int64_t xs, const bf16* mask,
+                int64_t ms, bool forward, bf16* y, int64_t ys, int batch, hipStream_t s) {
+    ConvArgs a;
+    a.x = x;
+    a.xs = xs;
+    a.mask = mask;
+    a.ms = ms;
+    a.batch = batch;
+    a.h = a.wd = net.n[L.level];
+    if (forward) {
+        a.w = L.wf;
+        a.bias = net.param + L.b_off;
+        a.cin = L.cin_p;
+        a.cout = L.cout;
+        a.relu = 1;
+    } else {  // input gradient: K runs over the layer's outputs
+        a.w = L.wb;
+        a.bias = nullptr;
+        a.cin = L.cout;
+        a.cout = L.cin;
+        a.relu = 0;
+    }
+    a.y = y;
+    a.ys = ys;
+    const int64_t waves = int64_t(batch) * a.h * ((a.wd + 15) / 16);
+    hipLaunchKernelGGL(k_conv3x3, dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t wgrad(const Net& net, const Layer& L, const bf16* x, int64_t xs, const bf16* dy,
+                 int64_t dys, const bf16* y, int64_t ys, int batch, hipStream_t s) {
+    WGradArgs a;
+    a.x = x;
+    a.xs = xs;
+    a.dy = dy;
+    a.dys = dys;
+    a.y = y;
+    a.ys = ys;
+    a.batch = batch;
+    a.h = a.wd = net.n[L.level];
+    a.cin = L.cin_p;
+    a.cout = L.cout;
+    a.rows_per_wave = a.h >= 128 ? 4 : (a.h >= 64 ? 8 : 16);
+    a.cin_w = L.cin;  // the first layer's padded input channels feed no weight
+    a.dw = net.grad + L.w_off;
+    const int rb = (a.h + a.rows_per_wave - 1) / a.rows_per_wave;
+    const int64_t waves = int64_t(batch) * rb * 9 * (a.cin / 16) * (a.cout / 16);
+    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bias_grad, dim3(unsigned(int64_t(batch) * a.h)), dim3(256), 0, s, dy, dys,
+                       y, ys, net.grad + L.b_off, batch * a.h, a.wd, L.cout);
+    return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace nn
+}  // namespace rbgs
+
+namespace rbgs {
+namespace nn {
+namespace {
+
+#define NN_TRY(expr)                         \
+    do {                                     \
+        hipError_t _e = (expr);              \
+        if (_e != hipSuccess) return _e;     \
+    } while (0)
+
+hipError_t restrict_op(const bf16* in, int64_t is, bf16* out, int64_t os, int batch, int nc, int c,
+                       float scale, int acc, hipStream_t s) {
+    hipLaunchKernelGGL(k_restrict, dim3(blocks_for(int64_t(batch) * nc * nc * c)), dim3(256), 0, s,
+                       in, is, out, os, batch, nc, c, scale, acc);
+    return hipGetLastError();
+}
+
+hipError_t prolong_op(const bf16* in, int64_t is, bf16* out, int64_t os, int batch, int nc, int c,
+                      float scale, int acc, hipStream_t s) {
+    const int nf = 2 * nc + 1;
+    hipLaunchKernelGGL(k_prolong, dim3(blocks_for(int64_t(batch) * nf * nf * c)), dim3(256), 0, s,
+                       in, is, out, os, batch, nc, c, scale, acc);
+    return hipGetLastError();
+}
+
+hipError_t prep_weights(Net& net, hipStream_t s) {
+    for (auto& l : net.layers) {
+        hipLaunchKernelGGL(k_prep_weights, dim3(blocks_for(int64_t(l.cout) * l.cin_p * 9)), dim3(256),
+                           0, s, net.param + l.w_off, l.cout, l.cin, l.cin_p, l.wf, l.wb);
+        NN_TRY(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
+const Layer& layer(const Net& net, const char* name) {
+    for (const auto& l : net.layers)
+        if (std::strcmp(l.name, name) == 0) return l;
+    return net.layers[0];
+}
+
+// Forward pass of `batch` samples; f: batch grids back to back (natural
+// layout, gstride elements apart).  Leaves y (FP32, normalised) and rms.
+hipError_t forward(Net& net, int batch, const double* f, int64_t ld, int64_t gstride,
+                   hipStream_t s) {
+    const int n0 = net.n[0];
+    hipLaunchKernelGGL(k_rms, dim3(batch), dim3(256), 0, s, f, n0, ld, gstride, net.rms);
+    NN_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_input, dim3(blocks_for(int64_t(batch) * n0 * n0)), dim3(256), 0, s, f, n0,
+                       ld, gstride, net.rms, net.in[0], batch);
+    NN_TRY(hipGetLastError());
+    // encoder
+    for (int l = 0; l < kLevels; ++l) {
+        char n0name[8] = "enc0.0", n1name[8] = "enc0.1";
+        n0name[3] = n1name[3] = char('0' + l);
+        const Layer& c0 = layer(net, n0name);
+        const Layer& c1 = layer(net, n1name);
+        NN_TRY(conv(net, c0, net.in[l], in_channels(l), nullptr, 0, true, net.aenc[l], kC[l], batch, s));
+        bf16* e = l < kLevels - 1 ? net.cat[l] + kC[l + 1] : net.e3;
+        const int64_t es = l < kLevels - 1 ? cat_channels(l) : kC[l];
+        NN_TRY(conv(net, c1, net.aenc[l], kC[l], nullptr, 0, true, e, es, batch, s));
+        if (l + 1 < kLevels)
+            NN_TRY(restrict_op(e, es, net.in[l + 1], in_channels(l + 1), batch, net.n[l + 1], kC[l],
+                               1.f, 0, s));
+    }
+    // decoder
+    for (int l = kLevels - 2; l >= 0; --l) {
+        const bf16* below = l == kLevels - 2 ? net.e3 : net.d[l + 1];
+        NN_TRY(prolong_op(below, kC[l + 1], net.cat[l], cat_channels(l), batch, net.n[l + 1],
+                          kC[l + 1], 1.f, 0, s));
+        char n0name[8] = "dec0.0", n1name[8] = "dec0.1";
+        n0name[3] = n1name[3] = char('0' + l);
+        NN_TRY(conv(net, layer(net, n0name), net.cat[l], cat_channels(l), nullptr, 0, true,
+                    net.adec[l], kC[l], batch, s));
+        NN_TRY(conv(net, layer(net, n1name), net.adec[l], kC[l], nullptr, 0, true, net.d[l], kC[l],
+                    batch, s));
+    }
+    const size_t hw = net.nparam - 17;
+    hipLaunchKernelGGL(k_head, dim3(blocks_for(int64_t(batch) * n0 * n0)), dim3(256), 0, s, net.d[0],
+                       kC[0], net.param + hw, net.param + hw + 16, net.y, int64_t(batch) * n0 * n0,
+                       kC[0]);
+    return hipGetLastError();
+}
+
+// Backward pass from dy (FP32, normalised output gradient) into net.grad.
+hipError_t backward(Net& net, int batch, hipStream_t s) {
+    const int n0 = net.n[0];
+    const size_t hw = net.nparam - 17;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(int64_t(net.nparam))), dim3(256), 0, s,
+                       reinterpret_cast<uint32_t*>(net.grad), int64_t(net.nparam));
+    NN_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_head_grad, dim3(blocks_for(int64_t(batch) * n0 * n0)), dim3(256), 0, s,
+                       net.d[0], kC[0], net.param + hw, net.dy, net.gd[0], kC[0], net.grad + hw,
+                       net.grad + hw + 16, int64_t(batch) * n0 * n0, kC[0]);
+    NN_TRY(hipGetLastError());
+    // decoder, from level 0 (computed last) up
+    for (int l = 0; l < kLevels - 1; ++l) {
+        char n0name[8] = "dec0.0", n1name[8] = "dec0.1";
+        n0name[3] = n1name[3] = char('0' + l);
+        const Layer& c0 = layer(net, n0name);
+        const Layer& c1 = layer(net, n1name);
+        const int C = kC[l], CC = cat_channels(l);
+        NN_TRY(wgrad(net, c1, net.adec[l], C, net.gd[l], C, net.d[l], C, batch, s));
+        NN_TRY(conv(net, c1, net.gd[l], C, net.d[l], C, false, net.gadec[l], C, batch, s));
+        NN_TRY(wgrad(net, c0, net.cat[l], CC, net.gadec[l], C, net.adec[l], C, batch, s));
+        NN_TRY(conv(net, c0, net.gadec[l], C, net.adec[l], C, false, net.gcat[l], CC, batch, s));
+        // up = P(d_{l+1}) with P = 4 R^T: the gradient reaching d_{l+1} is 4 R(dup)
+        bf16* gbelow = l == kLevels - 2 ? net.ge3 : net.gd[l + 1];
+        NN_TRY(restrict_op(net.gcat[l], CC, gbelow, kC[l + 1], batch, net.n[l + 1], kC[l + 1], 4.f, 0, s));
+    }
+    // encoder, from the bottom level up
+    for (int l = kLevels - 1; l >= 0; --l) {
+        char n0name[8] = "enc0.0", n1name[8] = "enc0.1";
+        n0name[3] = n1name[3] = char('0' + l);
+        const Layer& c0 = layer(net, n0name);
+        const Layer& c1 = layer(net, n1name);
+        const int C = kC[l];
+        const bf16* e = l < kLevels - 1 ? net.cat[l] + kC[l + 1] : net.e3;
+        bf16* ge = l < kLevels - 1 ? net.gcat[l] + kC[l + 1] : net.ge3;
+        const int64_t es = l < kLevels - 1 ? cat_channels(l) : C;
+        NN_TRY(wgrad(net, c1, net.aenc[l], C, ge, es, e, es, batch, s));
+        NN_TRY(conv(net, c1, ge, es, e, es, false, net.gaenc[l], C, batch, s));
+        NN_TRY(wgrad(net, c0, net.in[l], in_channels(l), net.gaenc[l], C, net.aenc[l], C, batch, s));
+        if (l > 0) {
+            NN_TRY(conv(net, c0, net.gaenc[l], C, net.aenc[l], C, false, net.gin[l], in_channels(l),
+                        batch, s));
+            // in_l = R(e_{l-1}): add R^T(g_in) = P(g_in)/4 to e_{l-1}'s gradient
+            // (which already holds its skip-connection part)
+            bf16* gprev = net.gcat[l - 1] + kC[l];
+            NN_TRY(prolong_op(net.gin[l], in_channels(l), gprev, cat_channels(l - 1), batch, net.n[l],
+                              in_channels(l), 0.25f, 1, s));
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t adam(Net& net, float lr, hipStream_t s) {
+    net.adam_t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, float(net.adam_t)), c2 = 1.f - std::pow(b2, float(net.adam_t));
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(int64_t(net.nparam))), dim3(256), 0, s, net.param,
+                       net.grad, net.m, net.v, int64_t(net.nparam), lr, b1, b2, 1e-8f, c1, c2);
+    NN_TRY(hipGetLastError());
+    return prep_weights(net, s);
+}
+
+thread_local std::string g_nn_error = "no error";
+
+int nnfail(int status, const std::string& msg) {
+    g_nn_error = msg;
+    return status;
+}
+
+int nn_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return RBGS_OK;
+    return nnfail(RBGS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool valid_size(int n) {
+    // four levels of 2^k - 1 grids down to at least 7 points
+    if (n < 63 || n > 8191) return false;
+    return ((n + 1) & n) == 0;
+}
+
+}  // namespace
+}  // namespace nn
+}  // namespace rbgs
+
+using namespace rbgs;
+
+struct rbgs_unet {
+    nn::Net net;
+};
+
+extern "C" {
+
+size_t rbgs_unet_param_count(void) {
+    size_t c = 0;
+    (void)nn::make_layers(&c);
+    return c;
+}
+
+size_t rbgs_unet_workspace_size(int32_t n, int32_t batch) {
+    if (!nn::valid_size(n) || batch < 1 || batch > 4096) return 0;
+    nn::Net net;
+    net.layers = nn::make_layers(&net.nparam);
+    net.batch = batch;
+    net.n[0] = n;
+    for (int l = 1; l < nn::kLevels; ++l) net.n[l] = (net.n[l - 1] - 1) / 2;
+    return nn::carve(net, nullptr);
+}
+
+const char* rbgs_unet_last_error(void) { return nn::g_nn_error.c_str(); }
+
+int rbgs_unet_create(rbgs_unet** out, int32_t n, int32_t batch, void* workspace,
+                     size_t workspace_bytes) {
+    if (!out) return nn::nnfail(RBGS_EINVAL, "net is NULL");
+    *out = nullptr;
+    if (!nn::valid_size(n)) return nn::nnfail(RBGS_EINVAL, "n must be 2^k - 1 in [63, 8191]");
+    if (batch < 1 || batch > 4096) return nn::nnfail(RBGS_EINVAL, "batch must be in [1, 4096]");
+    const size_t need = rbgs_unet_workspace_size(n, batch);
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 || workspace_bytes < need)
+        return nn::nnfail(RBGS_EWORKSPACE, "workspace missing, misaligned or smaller than " +
+                                               std::to_string(need) + " bytes");
+    rbgs_unet* u = new rbgs_unet;
+    u->net.layers = nn::make_layers(&u->net.nparam);
+    u->net.batch = batch;
+    u->net.n[0] = n;
+    for (int l = 1; l < nn::kLevels; ++l) u->net.n[l] = (u->net.n[l - 1] - 1) / 2;
+    u->net.total = nn::carve(u->net, static_cast<char*>(workspace));
+    *out = u;
+    return RBGS_OK;
+}
+
+int rbgs_unet_destroy(rbgs_unet* u) {
+    delete u;
+    return RBGS_OK;
+}
+
+int rbgs_unet_set_params(rbgs_unet* u, const float* host, size_t count, void* stream) {
+    if (!u || !host || count != u->net.nparam) return nn::nnfail(RBGS_EINVAL, "bad parameter vector");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    nn::Net& net = u->net;
+    int rc = nn::nn_hip(hipMemcpyAsync(net.param, host, count * 4, hipMemcpyHostToDevice, s), "upload");
+    if (rc) return rc;
+    // a fresh parameter vector restarts Adam
+    for (float* p : {net.m, net.v}) {
+        hipLaunchKernelGGL(nn::k_fill, dim3(nn::blocks_for(int64_t(count))), dim3(256), 0, s,
+                           reinterpret_cast<uint32_t*>(p), int64_t(count));
+        if ((rc = nn::nn_hip(hipGetLastError(), "fill"))) return rc;
+    }
+    net.adam_t = 0;
+    if ((rc = nn::nn_hip(nn::prep_weights(net, s), "weights"))) return rc;
+    return nn::nn_hip(hipStreamSynchronize(s), "synchronise");
+}
+
+static int copy_out(float* host, const float* dev, size_t count, hipStream_t s) {
+    int rc = nn::nn_hip(hipMemcpyAsync(host, dev, count * 4, hipMemcpyDeviceToHost, s), "download");
+    if (rc) return rc;
+    return nn::nn_hip(hipStreamSynchronize(s), "synchronise");
+}
+
+int rbgs_unet_get_params(rbgs_unet* u, float* host, size_t count, void* stream) {
+    if (!u || !host || count != u->net.nparam) return nn::nnfail(RBGS_EINVAL, "bad parameter vector");
+    return copy_out(host, u->net.param, count, static_cast<hipStream_t>(stream));
+}
+
+int rbgs_unet_get_grads(rbgs_unet* u, float* host, size_t count, void* stream) {
+    if (!u || !host || count != u->net.nparam) return nn::nnfail(RBGS_EINVAL, "bad gradient vector");
+    return copy_out(host, u->net.grad, count, static_cast<hipStream_t>(stream));
+}
+
+int rbgs_unet_forward(rbgs_unet* u, int32_t batch, const double* f, int64_t ld, double* u0,
+                      void* stream) {
+    if (!u || !f || !u0) return nn::nnfail(RBGS_EINVAL, "NULL argument");
+    nn::Net& net = u->net;
+    if (batch < 1 || batch > net.batch) return nn::nnfail(RBGS_EINVAL, "batch out of range");
+    if (ld < int64_t(net.n[0]) + 2) return nn::nnfail(RBGS_EINVAL, "ld must be >= n + 2");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t gs = int64_t(net.n[0] + 2) * ld;
+    int rc = nn::nn_hip(nn::forward(net, batch, f, ld, gs, s), "forward");
+    if (rc) return rc;
+    const int n0 = net.n[0];
+    hipLaunchKernelGGL(nn::k_output, dim3(nn::blocks_for(int64_t(batch) * n0 * n0)), dim3(256), 0, s,
+                       net.y, net.rms, u0, n0, ld, gs, batch);
+    return nn::nn_hip(hipGetLastError(), "output");
+}
+
+int rbgs_unet_train_step(rbgs_unet* u, int32_t batch, const double* f, const double* target,
+                         int64_t ld, float lr, int32_t update, float* loss, void* stream) {
+    if (!u || !f || !target) return nn::nnfail(RBGS_EINVAL, "NULL argument");
+    nn::Net& net = u->net;
+    if (batch < 1 || batch > net.batch) return nn::nnfail(RBGS_EINVAL, "batch out of range");
+    if (ld < int64_t(net.n[0]) + 2) return nn::nnfail(RBGS_EINVAL, "ld must be >= n + 2");
+    if (!(lr >= 0.f)) return nn::nnfail(RBGS_EINVAL, "lr must be >= 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t gs = int64_t(net.n[0] + 2) * ld;
+    const int n0 = net.n[0];
+    int rc = nn::nn_hip(nn::forward(net, batch, f, ld, gs, s), "forward");
+    if (rc) return rc;
+    hipLaunchKernelGGL(nn::k_fill, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t*>(net.loss),
+                       int64_t(1));
+    hipLaunchKernelGGL(nn::k_mse, dim3(nn::blocks_for(int64_t(batch) * n0 * n0)), dim3(256), 0, s,
+                       net.y, target, net.rms, n0, ld, gs, batch, net.dy, net.loss);
+    if ((rc = nn::nn_hip(hipGetLastError(), "loss"))) return rc;
+    if ((rc = nn::nn_hip(nn::backward(net, batch, s), "backward"))) return rc;
+    if (update && (rc = nn::nn_hip(nn::adam(net, lr, s), "adam"))) return rc;
+    if (loss) {
+        if ((rc = copy_out(loss, net.loss, 1, s))) return rc;
+    }
+    return RBGS_OK;
+}
+
+int rbgs_solve_learned(rbgs_unet* u, const rbgs_grid* g, double* uu, const double* f,
+                       const rbgs_solve_opts* o, rbgs_solve_info* info, int32_t* used_guess,
+                       double* rel_start, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!u || !g || !uu || !f || !o) return nn::nnfail(RBGS_EINVAL, "NULL argument");
+    nn::Net& net = u->net;
+    if (g->n != net.n[0]) return nn::nnfail(RBGS_EINVAL, "grid size differs from the network's");
+    if (g->ld != int64_t(g->n) + 2)
+        return nn::nnfail(RBGS_EINVAL, "the learned solve needs a dense grid (ld = n + 2)");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int n = g->n;
+    const size_t bytes = size_t(n + 2) * size_t(n + 2) * 8;
+    // the caller's start (normally zero inside the Dirichlet ring) and the
+    // network's guess on the same ring; keep whichever has the lower
+    // relative residual (the plain start is both fallback and judge)
+    double rel0 = 0.0, reln = 0.0;
+    int rc = rbgs_residual(g, RBGS_F64, uu, f, nullptr, &rel0, workspace, workspace_bytes, stream);
+    if (rc) return nn::nnfail(rc, rbgs_last_error());
+    rc = nn::nn_hip(hipMemcpyAsync(net.guess, uu, bytes, hipMemcpyDeviceToDevice, s), "copy");
+    if (rc) return rc;
+    if ((rc = rbgs_unet_forward(u, 1, f, g->ld, net.guess, stream))) return rc;
+    rc = rbgs_residual(g, RBGS_F64, net.guess, f, nullptr, &reln, workspace, workspace_bytes, stream);
+    if (rc) return nn::nnfail(rc, rbgs_last_error());
+    const bool use = reln < rel0;
+    if (use) {
+        rc = nn::nn_hip(hipMemcpyAsync(uu, net.guess, bytes, hipMemcpyDeviceToDevice, s), "copy");
+        if (rc) return rc;
+    }
+    if (used_guess) *used_guess = use ? 1 : 0;
+    if (rel_start) *rel_start = use ? reln : rel0;
+    return rbgs_solve(g, RBGS_F64, uu, f, o, info, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"

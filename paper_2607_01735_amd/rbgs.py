@@ -107,7 +107,10 @@ EXPORTED = ("rbgs_workspace_size", "rbgs_sweep", "rbgs_residual", "rbgs_solve",
             "rbgs_stream_probe", "rbgs_strerror", "rbgs_last_error", "rbgs_batch_workspace_size",
             "rbgs_sweep_batched", "rbgs_batch_plan_create", "rbgs_batch_plan_launch",
             "rbgs_batch_plan_check", "rbgs_batch_plan_destroy", "rbgs_autotune_batched",
-            "rbgs_batch_last_error")
+            "rbgs_batch_last_error", "rbgs_unet_param_count", "rbgs_unet_workspace_size",
+            "rbgs_unet_create", "rbgs_unet_destroy", "rbgs_unet_set_params",
+            "rbgs_unet_get_params", "rbgs_unet_get_grads", "rbgs_unet_forward",
+            "rbgs_unet_train_step", "rbgs_solve_learned", "rbgs_unet_last_error")
 
 
 class RbgsError(RuntimeError):
@@ -373,3 +376,141 @@ def rbgs_autotune_batched(us, fs, hs=None, workspace=None, stream=None):
                                        ws.numel(), _stream_ptr(stream, b.device),
                                        ctypes.byref(best), ctypes.byref(ms)))
     return {"fuse": best.fuse, "tile_rows": best.tile_rows, "ms_per_sweep": ms.value}
+
+
+# ---------------------------------------------------------------------------
+# Learned initial guess (U-Net run and trained by the library's kernels)
+# ---------------------------------------------------------------------------
+_lib.rbgs_unet_param_count.argtypes = []
+_lib.rbgs_unet_param_count.restype = ctypes.c_size_t
+_lib.rbgs_unet_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
+_lib.rbgs_unet_workspace_size.restype = ctypes.c_size_t
+_lib.rbgs_unet_create.argtypes = [_P(_vp), ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t]
+_lib.rbgs_unet_create.restype = ctypes.c_int
+_lib.rbgs_unet_destroy.argtypes = [_vp]
+_lib.rbgs_unet_destroy.restype = ctypes.c_int
+for _name in ("rbgs_unet_set_params", "rbgs_unet_get_params", "rbgs_unet_get_grads"):
+    getattr(_lib, _name).argtypes = [_vp, _vp, ctypes.c_size_t, _vp]
+    getattr(_lib, _name).restype = ctypes.c_int
+_lib.rbgs_unet_forward.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp]
+_lib.rbgs_unet_forward.restype = ctypes.c_int
+_lib.rbgs_unet_train_step.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int64, ctypes.c_float,
+                                      ctypes.c_int32, _P(ctypes.c_float), _vp]
+_lib.rbgs_unet_train_step.restype = ctypes.c_int
+_lib.rbgs_solve_learned.argtypes = [_vp, _P(rbgs_grid), _vp, _vp, _P(rbgs_solve_opts),
+                                    _P(rbgs_solve_info), _P(ctypes.c_int32), _P(ctypes.c_double),
+                                    _vp, ctypes.c_size_t, _vp]
+_lib.rbgs_solve_learned.restype = ctypes.c_int
+_lib.rbgs_unet_last_error.argtypes = []
+_lib.rbgs_unet_last_error.restype = ctypes.c_char_p
+
+
+def rbgs_unet_param_count():
+    return int(_lib.rbgs_unet_param_count())
+
+
+def _ncheck(rc, allow=(OK,)):
+    if rc not in allow:
+        raise RbgsError(rc, _lib.rbgs_unet_last_error().decode())
+    return rc
+
+
+class UNet:
+    """The learned-guess network for N x N grids (N = 2^k - 1 >= 63) and up
+    to `batch` samples per call; all state in one device workspace."""
+
+    def __init__(self, n, batch, device="cuda", workspace=None):
+        import torch
+        self.n, self.batch = int(n), int(batch)
+        need = int(_lib.rbgs_unet_workspace_size(self.n, self.batch))
+        if need == 0:
+            raise RbgsError(EINVAL, "n must be 2^k - 1 in [63, 8191] and batch in [1, 4096]")
+        self.device = torch.device(device)
+        self.workspace = workspace if workspace is not None else torch.empty(
+            need, dtype=torch.uint8, device=self.device)
+        h = _vp()
+        _ncheck(_lib.rbgs_unet_create(ctypes.byref(h), self.n, self.batch,
+                                      _vp(self.workspace.data_ptr()), self.workspace.numel()))
+        self._h = h
+        self.count = rbgs_unet_param_count()
+
+    def _stream(self, stream):
+        return _stream_ptr(stream, self.device)
+
+    def set_params(self, params, stream=None):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.count:
+            raise ValueError(f"expected {self.count} parameters")
+        _ncheck(_lib.rbgs_unet_set_params(self._h, _vp(p.ctypes.data), p.size, self._stream(stream)))
+
+    def _get(self, fn, stream):
+        import numpy as np
+        out = np.empty(self.count, np.float32)
+        _ncheck(fn(self._h, _vp(out.ctypes.data), out.size, self._stream(stream)))
+        return out
+
+    def get_params(self, stream=None):
+        return self._get(_lib.rbgs_unet_get_params, stream)
+
+    def get_grads(self, stream=None):
+        return self._get(_lib.rbgs_unet_get_grads, stream)
+
+    def _check_batch(self, f):
+        if f.dim() != 3 or f.shape[1] != self.n + 2 or f.stride(2) != 1 or f.dtype.itemsize != 8:
+            raise ValueError("expected a float64 (batch, n+2, ld) tensor with unit column stride")
+        if f.stride(0) != (self.n + 2) * f.stride(1):
+            raise ValueError("grids of a batch must be stored back to back")
+        return f.shape[0], f.stride(1)
+
+    def forward(self, f, u0, stream=None):
+        """u0[b] interior <- the network's guess for f[b]."""
+        b, ld = self._check_batch(f)
+        if u0.shape != f.shape or u0.stride() != f.stride():
+            raise ValueError("u0 must have f's shape and strides")
+        _ncheck(_lib.rbgs_unet_forward(self._h, b, _vp(f.data_ptr()), ld, _vp(u0.data_ptr()),
+                                       self._stream(stream)))
+
+    def train_step(self, f, u_target, lr, update=True, stream=None):
+        b, ld = self._check_batch(f)
+        if u_target.shape != f.shape or u_target.stride() != f.stride():
+            raise ValueError("u_target must have f's shape and strides")
+        loss = ctypes.c_float()
+        _ncheck(_lib.rbgs_unet_train_step(self._h, b, _vp(f.data_ptr()), _vp(u_target.data_ptr()),
+                                          ld, float(lr), 1 if update else 0, ctypes.byref(loss),
+                                          self._stream(stream)))
+        return loss.value
+
+    def solve_learned(self, u, f, max_sweeps, rel_tol, check_every=1000, kernel="auto",
+                      workspace=None, stream=None, **tuning):
+        """Solve from the better of the caller's start and the network's
+        guess (lower relative residual); returns rbgs_solve's statistics
+        plus used_guess and rel_start."""
+        _same_layout(u, f)
+        grid = make_grid(u)
+        ws = _workspace(grid, F64, u.device, workspace=workspace)
+        opts = rbgs_solve_opts()
+        opts.max_sweeps, opts.rel_tol, opts.check_every = int(max_sweeps), float(rel_tol), int(check_every)
+        opts.omega = 1.0
+        opts.sweep = _sweep_opts(kernel=kernel, **tuning)
+        info = rbgs_solve_info()
+        used = ctypes.c_int32()
+        rel0 = ctypes.c_double()
+        rc = _lib.rbgs_solve_learned(self._h, ctypes.byref(grid), _vp(u.data_ptr()),
+                                     _vp(f.data_ptr()), ctypes.byref(opts), ctypes.byref(info),
+                                     ctypes.byref(used), ctypes.byref(rel0), _vp(ws.data_ptr()),
+                                     ws.numel(), self._stream(stream))
+        _ncheck(rc, allow=(OK, ENOCONV))
+        return {"sweeps": info.sweeps, "rel_residual": info.rel_residual, "status": info.status,
+                "used_guess": bool(used.value), "rel_start": rel0.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.rbgs_unet_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

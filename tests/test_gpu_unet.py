@@ -1,0 +1,188 @@
+"""GPU U-Net kernels against the FP64 reference network (oracle/unet_ref.py).
+
+The GPU path keeps weights and activations in bfloat16 and accumulates in
+FP32, so it is compared with the reference run on bfloat16-rounded weights
+and inputs, within tolerances set by bfloat16 rounding through ~15 layers:
+forward relative L2 error <= 3e-2, gradients per parameter tensor with
+cosine >= 0.99 and relative norm error <= 0.1.  The learned solve's choice
+rule is checked exactly: the final iterate is the oracle's solve from the
+chosen start, bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import unet_ref as U
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2607_01735_amd as rb  # noqa: E402
+
+DEV = torch.device("cuda:0")
+N = 63
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def flatten(p):
+    parts = []
+    for name in U.param_names():
+        parts += [p[name + ".w"].ravel(), p[name + ".b"].ravel()]
+    return np.concatenate(parts)
+
+
+def unflatten(vec, like):
+    out, off = {}, 0
+    for name in U.param_names():
+        for suffix in (".w", ".b"):
+            k = name + suffix
+            size = like[k].size
+            out[k] = vec[off:off + size].reshape(like[k].shape).astype(np.float64)
+            off += size
+    assert off == vec.size
+    return out
+
+
+def bf16_round(a):
+    return torch.from_numpy(np.asarray(a, np.float64)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def make_params(seed=1):
+    p = U.init_params(seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = rng.standard_normal(p[k].shape) * 0.05
+    # the library stores FP32 masters: start from FP32-representable values
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+
+
+def batch_fields(seeds, n=N):
+    fs = [W.grf_rhs(n, seed=s)[0] for s in seeds]
+    return np.stack(fs)
+
+
+def ref_forward(p, f_nat):
+    """Reference output u0 (interior) with bfloat16-rounded weights/input."""
+    pr = {k: bf16_round(v) for k, v in p.items()}
+    n = f_nat.shape[0] - 2
+    x0, rms = U.normalise(f_nat[1:n + 1, 1:n + 1])
+    y, cache = U.forward(pr, bf16_round(x0))
+    return y * rms, y, cache, pr, rms
+
+
+def test_forward_matches_reference():
+    say("unet forward n=63 batch=2")
+    p = make_params()
+    net = rb.UNet(N, 2)
+    net.set_params(flatten(p).astype(np.float32))
+    assert np.array_equal(net.get_params(), flatten(p).astype(np.float32))
+    f = batch_fields([0, 1])
+    ft = torch.from_numpy(f).to(DEV)
+    u0 = torch.zeros_like(ft)
+    net.forward(ft, u0)
+    got = u0.cpu().numpy()
+    for b in range(2):
+        ref, *_ = ref_forward(p, f[b])
+        g = got[b, 1:N + 1, 1:N + 1]
+        err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+        assert err < 3e-2, f"sample {b}: relative error {err}"
+        assert not np.any(got[b, 0]) and not np.any(got[b, :, 0])  # ring untouched
+
+
+def test_gradients_match_reference():
+    say("unet gradients n=63 batch=2")
+    p = make_params(seed=2)
+    net = rb.UNet(N, 2)
+    net.set_params(flatten(p).astype(np.float32))
+    f = batch_fields([5, 6])
+    target = np.zeros_like(f)
+    rng = np.random.default_rng(7)
+    target[:, 1:N + 1, 1:N + 1] = rng.standard_normal((2, N, N)) * 0.01
+    loss = net.train_step(torch.from_numpy(f).to(DEV), torch.from_numpy(target).to(DEV), 0.0,
+                          update=False)
+    g_gpu = unflatten(net.get_grads().astype(np.float64), p)
+    # reference: mean over the batch of per-sample mean squared errors
+    g_ref = {k: np.zeros_like(v) for k, v in p.items()}
+    loss_ref = 0.0
+    for b in range(2):
+        _, y, cache, pr, rms = ref_forward(p, f[b])
+        t = target[b, 1:N + 1, 1:N + 1] / rms
+        lb, dy = U.mse_loss(y, t)
+        loss_ref += lb / 2
+        gb = U.backward(pr, cache, dy / 2)
+        for k in g_ref:
+            g_ref[k] += gb[k]
+    assert loss == pytest.approx(loss_ref, rel=3e-2)
+    for k in g_ref:
+        a, r = g_gpu[k].ravel(), g_ref[k].ravel()
+        if np.linalg.norm(r) < 1e-6 * max(1.0, np.abs(loss_ref)):
+            continue
+        cos = a @ r / (np.linalg.norm(a) * np.linalg.norm(r))
+        rel = np.linalg.norm(a - r) / np.linalg.norm(r)
+        assert cos > 0.99 and rel < 0.1, f"{k}: cos={cos:.4f} rel={rel:.4f}"
+
+
+def test_adam_step_and_training_decreases_loss():
+    say("unet adam + short training")
+    p = make_params(seed=3)
+    vec = flatten(p).astype(np.float32)
+    net = rb.UNet(N, 2)
+    net.set_params(vec)
+    f = torch.from_numpy(batch_fields([11, 12])).to(DEV)
+    fn = f.cpu().numpy()
+    u = np.zeros_like(fn)
+    for b in range(2):
+        u[b, 1:N + 1, 1:N + 1] = -W.grf_rhs(N, seed=11 + b)[0][1:N + 1, 1:N + 1] * 0.02
+    ut = torch.from_numpy(u).to(DEV)
+    net.train_step(f, ut, 0.0, update=False)
+    g = net.get_grads()
+    lr = 1e-3
+    net.set_params(vec)
+    first = net.train_step(f, ut, lr, update=True)
+    new = net.get_params()
+    # first bias-corrected Adam step moves each weight by lr * g/(|g| + eps')
+    step = vec - new
+    big = np.abs(g) > 1e-4
+    assert np.allclose(step[big], lr * np.sign(g[big]), rtol=1e-3, atol=1e-7)
+    assert np.all(np.abs(step) <= lr * 1.001)
+    losses = [first]
+    for _ in range(40):
+        losses.append(net.train_step(f, ut, lr, update=True))
+    assert losses[-1] < 0.5 * losses[0], losses[::10]
+
+
+def test_learned_solve_choice_rule(oracle):
+    """Both branches of the rule: a zero start beats an untrained network's
+    guess, and the guess beats a deliberately bad start; either way the
+    result is the oracle's solve from the chosen start, bit for bit."""
+    say("learned solve choice rule")
+    p = make_params(seed=4)
+    net = rb.UNet(N, 1)
+    net.set_params(flatten(p).astype(np.float32))
+    h = W.spacing(N)
+    f = W.grf_rhs(N, seed=21)[0]
+    ft = torch.from_numpy(f).to(DEV)
+    guess = torch.zeros((1, N + 2, N + 2), dtype=torch.float64, device=DEV)
+    net.forward(ft[None].contiguous(), guess)
+    guess_np = guess[0].cpu().numpy()
+    _, rel_guess = oracle.residual(guess_np, f, h)
+    for start in (W.zeros(N), W.uniform_rhs(N, seed=3) * 1e3):
+        _, rel_start = oracle.residual(start, f, h)
+        ut = torch.from_numpy(start.copy()).to(DEV)
+        info = net.solve_learned(ut, ft, 300, 1e-12, check_every=100, kernel="plain")
+        use = rel_guess < rel_start
+        assert info["used_guess"] == use
+        ref = (guess_np if use else start).copy()
+        oracle.sweep(ref, f, h, 300)
+        assert np.array_equal(ut.cpu().numpy(), ref)
+        assert info["sweeps"] == 300
