@@ -276,15 +276,19 @@ int rbgs_unet_forward(rbgs_unet *net, int32_t batch, const double *f,
 int rbgs_unet_train_step(rbgs_unet *net, int32_t batch, const double *f,
                          const double *u_target, int64_t ld, float lr,
                          int32_t update, float *loss, void *stream);
-/* Solve with the learned guess: the network's guess replaces the caller's
- * start u only if its relative residual is lower (the plain start is both
- * fallback and judge), then rbgs_solve runs.  *used_guess and *rel_start
+/* Solve with the learned guess.  The network's guess and the caller's start
+ * u (same Dirichlet ring) are both given compare_after sweeps (0: none);
+ * the guess replaces the start only if its relative residual is then lower
+ * (the plain start is both fallback and judge), and rbgs_solve continues
+ * for the remaining max_sweeps - compare_after sweeps; info->sweeps counts
+ * the comparison sweeps of the kept path.  *used_guess and *rel_start
  * (HOST, may be NULL) report the choice.  Needs ld = n + 2. */
 int rbgs_solve_learned(rbgs_unet *net, const rbgs_grid *g, double *u,
                        const double *f, const rbgs_solve_opts *opts,
-                       rbgs_solve_info *info, int32_t *used_guess,
-                       double *rel_start, void *workspace,
-                       size_t workspace_bytes, void *stream);
+                       int32_t compare_after, rbgs_solve_info *info,
+                       int32_t *used_guess, double *rel_start,
+                       void *workspace, size_t workspace_bytes,
+                       void *stream);
 const char *rbgs_unet_last_error(void);
 
 /* Device-memory bandwidth probe: the copy (kind 0: b = a) and triad

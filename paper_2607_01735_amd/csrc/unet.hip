@@ -897,25 +897,37 @@ int rbgs_unet_train_step(rbgs_unet* u, int32_t batch, const double* f, const dou
 }
 
 int rbgs_solve_learned(rbgs_unet* u, const rbgs_grid* g, double* uu, const double* f,
-                       const rbgs_solve_opts* o, rbgs_solve_info* info, int32_t* used_guess,
-                       double* rel_start, void* workspace, size_t workspace_bytes, void* stream) {
+                       const rbgs_solve_opts* o, int32_t compare_after, rbgs_solve_info* info,
+                       int32_t* used_guess, double* rel_start, void* workspace,
+                       size_t workspace_bytes, void* stream) {
     if (!u || !g || !uu || !f || !o) return nn::nnfail(RBGS_EINVAL, "NULL argument");
     nn::Net& net = u->net;
     if (g->n != net.n[0]) return nn::nnfail(RBGS_EINVAL, "grid size differs from the network's");
     if (g->ld != int64_t(g->n) + 2)
         return nn::nnfail(RBGS_EINVAL, "the learned solve needs a dense grid (ld = n + 2)");
+    if (compare_after < 0 || compare_after > o->max_sweeps)
+        return nn::nnfail(RBGS_EINVAL, "compare_after must be in [0, max_sweeps]");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int n = g->n;
     const size_t bytes = size_t(n + 2) * size_t(n + 2) * 8;
-    // the caller's start (normally zero inside the Dirichlet ring) and the
-    // network's guess on the same ring; keep whichever has the lower
-    // relative residual (the plain start is both fallback and judge)
-    double rel0 = 0.0, reln = 0.0;
-    int rc = rbgs_residual(g, RBGS_F64, uu, f, nullptr, &rel0, workspace, workspace_bytes, stream);
-    if (rc) return nn::nnfail(rc, rbgs_last_error());
-    rc = nn::nn_hip(hipMemcpyAsync(net.guess, uu, bytes, hipMemcpyDeviceToDevice, s), "copy");
+    // The caller's start (normally zero inside the Dirichlet ring) and the
+    // network's guess on the same ring; after compare_after sweeps of both
+    // (0: as they are), keep whichever has the lower relative residual.  The
+    // plain start is both fallback and judge.
+    int rc = nn::nn_hip(hipMemcpyAsync(net.guess, uu, bytes, hipMemcpyDeviceToDevice, s), "copy");
     if (rc) return rc;
     if ((rc = rbgs_unet_forward(u, 1, f, g->ld, net.guess, stream))) return rc;
+    if (compare_after > 0) {
+        rbgs_sweep_opts so = o->sweep;
+        so.timing = nullptr;
+        if ((rc = rbgs_sweep(g, RBGS_F64, uu, f, compare_after, &so, workspace, workspace_bytes, stream)) ||
+            (rc = rbgs_sweep(g, RBGS_F64, net.guess, f, compare_after, &so, workspace,
+                             workspace_bytes, stream)))
+            return nn::nnfail(rc, rbgs_last_error());
+    }
+    double rel0 = 0.0, reln = 0.0;
+    rc = rbgs_residual(g, RBGS_F64, uu, f, nullptr, &rel0, workspace, workspace_bytes, stream);
+    if (rc) return nn::nnfail(rc, rbgs_last_error());
     rc = rbgs_residual(g, RBGS_F64, net.guess, f, nullptr, &reln, workspace, workspace_bytes, stream);
     if (rc) return nn::nnfail(rc, rbgs_last_error());
     const bool use = reln < rel0;
@@ -925,7 +937,13 @@ int rbgs_solve_learned(rbgs_unet* u, const rbgs_grid* g, double* uu, const doubl
     }
     if (used_guess) *used_guess = use ? 1 : 0;
     if (rel_start) *rel_start = use ? reln : rel0;
-    return rbgs_solve(g, RBGS_F64, uu, f, o, info, workspace, workspace_bytes, stream);
+    rbgs_solve_opts rest = *o;
+    rest.max_sweeps = o->max_sweeps - compare_after;
+    rbgs_solve_info inner{0, 0, 0.0, 0.0, RBGS_OK};
+    rc = rbgs_solve(g, RBGS_F64, uu, f, &rest, &inner, workspace, workspace_bytes, stream);
+    inner.sweeps += compare_after;
+    if (info) *info = inner;
+    return rc;
 }
 
 }  // extern "C"

@@ -1,0 +1,219 @@
+"""Learned initial guess: data generation, training and held-out evaluation.
+
+Every numerical step runs in librbgs.so: the (f, u*) training pairs come
+from the library's batched persistent Gauss-Seidel (FP32, a fixed number of
+sweeps from u = 0), the network is trained by the library's U-Net kernels,
+and the evaluation compares the library's FP64 solve to a relative residual
+from u = 0 (the judge) with the same solve started from the network's guess
+(rbgs_solve_learned).  This module only orchestrates and moves tensors.
+
+Inputs are Gaussian random fields (workloads.grf_rhs): squared-exponential
+covariance through a sine series, length scale uniform on [0.02, 0.3],
+normalised to unit RMS; training seeds 0, 1, ..., test seeds 10^6 + i.
+
+Usage (from the repository root, on a GPU):
+  python -m paper_2607_01735_amd.learned --train 2048 --epochs 8 --out unet.npy
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+TEST_SEED0 = 10 ** 6
+
+# (name, input channels, output channels) of the library's conv layers, in
+# its parameter order; the 1x1 head (16 -> 1) follows them.
+LAYERS = (("enc0.0", 1, 16), ("enc0.1", 16, 16), ("enc1.0", 16, 32), ("enc1.1", 32, 32),
+          ("enc2.0", 32, 64), ("enc2.1", 64, 64), ("enc3.0", 64, 128), ("enc3.1", 128, 128),
+          ("dec2.0", 192, 64), ("dec2.1", 64, 64), ("dec1.0", 96, 32), ("dec1.1", 32, 32),
+          ("dec0.0", 48, 16), ("dec0.1", 16, 16))
+
+
+def initial_params(seed=0):
+    """He-normal weights (std sqrt(2 / fan_in)), zero biases, FP32 vector in
+    the library's parameter order."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for _, cin, cout in LAYERS:
+        parts.append(rng.standard_normal(cout * cin * 9) * math.sqrt(2.0 / (cin * 9)))
+        parts.append(np.zeros(cout))
+    parts.append(rng.standard_normal(16) * math.sqrt(1.0 / 16))
+    parts.append(np.zeros(1))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def log(msg):
+    print(f"[learned] {msg}", file=sys.stderr, flush=True)
+
+
+def fields(n, seeds):
+    """Stack of GRF right-hand sides, natural layout (B, n+2, n+2), FP64."""
+    import workloads as W
+    return np.stack([W.grf_rhs(n, seed=int(s))[0] for s in seeds])
+
+
+def solve_targets(rb, torch, f, sweeps, chunk=256):
+    """u* for every f (device FP64 (B, n+2, n+2)): `sweeps` FP32 sweeps from
+    u = 0 in batched persistent launches of `chunk` grids, widened to FP64."""
+    out = torch.empty_like(f)
+    for s in range(0, f.shape[0], chunk):
+        fc = f[s:s + chunk].to(torch.float32).contiguous()
+        uc = torch.zeros_like(fc)
+        plan = rb.BatchPlan([uc[i] for i in range(fc.shape[0])],
+                            [fc[i] for i in range(fc.shape[0])], sweeps)
+        plan.launch()
+        plan.check()
+        plan.close()
+        out[s:s + chunk] = uc.to(torch.float64)
+        log(f"targets {s + fc.shape[0]}/{f.shape[0]}")
+    return out
+
+
+def target_residuals(rb, f, u, count=8):
+    rels = []
+    for i in range(min(count, f.shape[0])):
+        rels.append(rb.rbgs_residual(u[i], f[i])[1])
+    return rels
+
+
+def train(net, torch, f, u, epochs, batch, lr0, seed=0, lr_min_frac=0.05):
+    """Adam with cosine-decayed learning rate over shuffled minibatches."""
+    rng = np.random.default_rng(seed)
+    count = f.shape[0]
+    steps_per_epoch = count // batch
+    total = epochs * steps_per_epoch
+    step = 0
+    history = []
+    for ep in range(epochs):
+        order = rng.permutation(count)
+        losses = []
+        for k in range(steps_per_epoch):
+            idx = torch.as_tensor(order[k * batch:(k + 1) * batch], device=f.device)
+            lr = lr0 * (lr_min_frac + (1 - lr_min_frac) * 0.5 * (1 + math.cos(math.pi * step / total)))
+            losses.append(net.train_step(f[idx].contiguous(), u[idx].contiguous(), lr))
+            step += 1
+        history.append(float(np.mean(losses)))
+        log(f"epoch {ep + 1}/{epochs}: loss {history[-1]:.4e} lr {lr:.2e}")
+    return history
+
+
+def evaluate(rb, torch, net, n, seeds, tol, compare_after, kernel="auto", max_sweeps=2_000_000,
+             check_every=2000):
+    """Time and sweeps to rel <= tol: FP64 solve from u = 0 versus the same
+    solve from the network's guess (kept only if it wins the comparison)."""
+    rows = []
+    f_all = torch.from_numpy(fields(n, seeds)).to("cuda")
+    for i, s in enumerate(seeds):
+        f = f_all[i]
+        u = torch.zeros_like(f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        base = rb.rbgs_solve(u, f, max_sweeps, tol, check_every=check_every, kernel=kernel)
+        torch.cuda.synchronize()
+        t_base = time.perf_counter() - t0
+        u = torch.zeros_like(f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        got = net.solve_learned(u, f, max_sweeps, tol, check_every=check_every, kernel=kernel,
+                                compare_after=compare_after)
+        torch.cuda.synchronize()
+        t_nn = time.perf_counter() - t0
+        rows.append({"seed": int(s), "zero_start": {"sweeps": base["sweeps"], "seconds": round(t_base, 4),
+                                                    "rel": base["rel_residual"]},
+                     "learned": {"sweeps": got["sweeps"], "seconds": round(t_nn, 4),
+                                 "rel": got["rel_residual"], "used_guess": got["used_guess"],
+                                 "rel_start": got["rel_start"]}})
+        log(f"test seed {s}: {rows[-1]}")
+    return rows
+
+
+def guess_quality(rb, torch, net, n, seeds, gen_sweeps):
+    """Relative error of the network's guess against the solver's u* on
+    held-out fields (the same target definition as training)."""
+    f = torch.from_numpy(fields(n, seeds)).to("cuda")
+    us = solve_targets(rb, torch, f, gen_sweeps, chunk=len(seeds))
+    g = torch.zeros_like(f)
+    net.forward(f, g)
+    err = [(torch.linalg.norm(g[i] - us[i]) / torch.linalg.norm(us[i])).item()
+           for i in range(len(seeds))]
+    return err
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--n", type=int, default=511)
+    ap.add_argument("--train", type=int, default=2048)
+    ap.add_argument("--gen-sweeps", type=int, default=180000,
+                    help="FP32 sweeps from u = 0 that define u* (error of the slowest mode "
+                         "falls by cos^2(pi h) per sweep)")
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--init-seed", type=int, default=0)
+    ap.add_argument("--test", type=int, default=4)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--compare-after", type=int, default=0)
+    ap.add_argument("--params", default=None, help="start from these parameters (.npy)")
+    ap.add_argument("--out", default=None, help="write the trained parameters here (.npy)")
+    ap.add_argument("--summary", default=None, help="write a JSON summary here")
+    ap.add_argument("--skip-eval", action="store_true")
+    args = ap.parse_args()
+
+    import torch
+
+    import paper_2607_01735_amd as rb
+
+    n = args.n
+    net = rb.UNet(n, args.batch)
+    if args.params:
+        net.set_params(np.load(args.params))
+    else:
+        vec = initial_params(args.init_seed)
+        if vec.size != rb.rbgs_unet_param_count():
+            raise RuntimeError("layer table out of step with the library")
+        net.set_params(vec)
+    summary = {"n": n, "train": args.train, "gen_sweeps": args.gen_sweeps, "epochs": args.epochs,
+               "batch": args.batch, "lr": args.lr}
+    if args.train > 0:
+        t0 = time.perf_counter()
+        f = torch.from_numpy(fields(n, range(args.train))).to("cuda")
+        summary["field_seconds"] = round(time.perf_counter() - t0, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = solve_targets(rb, torch, f, args.gen_sweeps)
+        torch.cuda.synchronize()
+        summary["target_seconds"] = round(time.perf_counter() - t0, 2)
+        summary["target_rel_residual"] = target_residuals(rb, f, u)
+        log(f"targets: {summary['target_seconds']} s, residuals {summary['target_rel_residual'][:4]}")
+        t0 = time.perf_counter()
+        summary["loss_history"] = train(net, torch, f, u, args.epochs, args.batch, args.lr)
+        torch.cuda.synchronize()
+        summary["train_seconds"] = round(time.perf_counter() - t0, 2)
+        del f, u
+        torch.cuda.empty_cache()
+        if args.out:
+            np.save(args.out, net.get_params())
+    test_seeds = [TEST_SEED0 + i for i in range(args.test)]
+    summary["guess_rel_error"] = guess_quality(rb, torch, net, n, test_seeds, args.gen_sweeps)
+    log(f"held-out guess error vs u*: {summary['guess_rel_error']}")
+    if not args.skip_eval:
+        for ca in sorted({0, args.compare_after}):
+            summary[f"eval_compare_after_{ca}"] = evaluate(rb, torch, net, n, test_seeds[:2],
+                                                           args.tol, ca)
+    out = json.dumps(summary)
+    if args.summary:
+        with open(args.summary, "w") as fh:
+            fh.write(out + "\n")
+    print(out, flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -12,6 +12,10 @@ no CPU or PyTorch fallback.
 import ctypes
 import os
 
+# torch first: its bundled HIP runtime and librbgs.so's must be one and the
+# same library in the process (same SONAME; the first one loaded is shared).
+import torch  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librbgs.so")
 
@@ -398,8 +402,8 @@ _lib.rbgs_unet_train_step.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_in
                                       ctypes.c_int32, _P(ctypes.c_float), _vp]
 _lib.rbgs_unet_train_step.restype = ctypes.c_int
 _lib.rbgs_solve_learned.argtypes = [_vp, _P(rbgs_grid), _vp, _vp, _P(rbgs_solve_opts),
-                                    _P(rbgs_solve_info), _P(ctypes.c_int32), _P(ctypes.c_double),
-                                    _vp, ctypes.c_size_t, _vp]
+                                    ctypes.c_int32, _P(rbgs_solve_info), _P(ctypes.c_int32),
+                                    _P(ctypes.c_double), _vp, ctypes.c_size_t, _vp]
 _lib.rbgs_solve_learned.restype = ctypes.c_int
 _lib.rbgs_unet_last_error.argtypes = []
 _lib.rbgs_unet_last_error.restype = ctypes.c_char_p
@@ -482,10 +486,10 @@ class UNet:
         return loss.value
 
     def solve_learned(self, u, f, max_sweeps, rel_tol, check_every=1000, kernel="auto",
-                      workspace=None, stream=None, **tuning):
+                      compare_after=0, workspace=None, stream=None, **tuning):
         """Solve from the better of the caller's start and the network's
-        guess (lower relative residual); returns rbgs_solve's statistics
-        plus used_guess and rel_start."""
+        guess (lower relative residual, after compare_after sweeps of both);
+        returns rbgs_solve's statistics plus used_guess and rel_start."""
         _same_layout(u, f)
         grid = make_grid(u)
         ws = _workspace(grid, F64, u.device, workspace=workspace)
@@ -497,7 +501,8 @@ class UNet:
         used = ctypes.c_int32()
         rel0 = ctypes.c_double()
         rc = _lib.rbgs_solve_learned(self._h, ctypes.byref(grid), _vp(u.data_ptr()),
-                                     _vp(f.data_ptr()), ctypes.byref(opts), ctypes.byref(info),
+                                     _vp(f.data_ptr()), ctypes.byref(opts), int(compare_after),
+                                     ctypes.byref(info),
                                      ctypes.byref(used), ctypes.byref(rel0), _vp(ws.data_ptr()),
                                      ws.numel(), self._stream(stream))
         _ncheck(rc, allow=(OK, ENOCONV))

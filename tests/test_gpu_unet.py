@@ -186,3 +186,17 @@ def test_learned_solve_choice_rule(oracle):
         oracle.sweep(ref, f, h, 300)
         assert np.array_equal(ut.cpu().numpy(), ref)
         assert info["sweeps"] == 300
+    # comparing after 10 sweeps of both starts
+    k = 10
+    for start in (W.zeros(N), W.uniform_rhs(N, seed=3) * 1e3):
+        a, b = start.copy(), guess_np.copy()
+        oracle.sweep(a, f, h, k)
+        oracle.sweep(b, f, h, k)
+        use = oracle.residual(b, f, h)[1] < oracle.residual(a, f, h)[1]
+        ut = torch.from_numpy(start.copy()).to(DEV)
+        info = net.solve_learned(ut, ft, 300, 1e-12, check_every=100, kernel="plain",
+                                 compare_after=k)
+        assert info["used_guess"] == use and info["sweeps"] == 300
+        ref = (guess_np if use else start).copy()
+        oracle.sweep(ref, f, h, 300)
+        assert np.array_equal(ut.cpu().numpy(), ref)
