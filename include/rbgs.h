@@ -291,6 +291,33 @@ int rbgs_solve_learned(rbgs_unet *net, const rbgs_grid *g, double *u,
                        void *stream);
 const char *rbgs_unet_last_error(void);
 
+/* ---------------------------------------------------------------------
+ * Grid transfers for nested iteration (not in the paper): the learned
+ * guess's training targets are converged by solving a coarse grid first,
+ * interpolating, and sweeping the next finer grid.  Levels are vertex-
+ * centred: fine n_f = 2 n_c + 1, and coarse point (I, J) sits on fine point
+ * (2I, 2J) in natural indexing (rings at index 0 and n+1 on both levels).
+ * `batch` >= 1 grids per level, stored at a constant element stride of at
+ * least (n+2) * ld of that level; input and output must not overlap.  Only
+ * n and ld of each rbgs_grid are used (h must still be valid).
+ * Asynchronous on `stream`.
+ * --------------------------------------------------------------------- */
+
+/* Coarse interior <- full weighting, (1,2,1) x (1,2,1) / 16, of the fine
+ * interior.  The fine ring is not read and the coarse ring not written. */
+int rbgs_restrict(int32_t batch, rbgs_dtype dt, const rbgs_grid *fine,
+                  const void *x_fine, int64_t fine_stride,
+                  const rbgs_grid *coarse, void *x_coarse,
+                  int64_t coarse_stride, void *stream);
+
+/* Fine interior <- bilinear interpolation of the coarse grid (its ring
+ * included: fine points next to the ring interpolate towards it).  The fine
+ * ring is not written. */
+int rbgs_prolong(int32_t batch, rbgs_dtype dt, const rbgs_grid *coarse,
+                 const void *x_coarse, int64_t coarse_stride,
+                 const rbgs_grid *fine, void *x_fine, int64_t fine_stride,
+                 void *stream);
+
 /* Device-memory bandwidth probe: the copy (kind 0: b = a) and triad
  * (kind 1: a = b + s*c) kernels of the STREAM benchmark, which the paper
  * uses for the attainable memory bandwidth in its roofline (Section 3,

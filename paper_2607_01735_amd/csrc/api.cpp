@@ -270,6 +270,33 @@ struct GroupTimer {
     }
 };
 
+// Shared argument checks of the grid transfers: coarse/fine sizes related by
+// n_f = 2 n_c + 1, strides covering a grid, and device ranges that hold all
+// `batch` grids of each level.
+int check_transfer(int32_t batch, rbgs_dtype dt, const rbgs_grid* coarse, const void* xc,
+                   int64_t cstride, const rbgs_grid* fine, const void* xf, int64_t fstride) {
+    std::string why;
+    if (batch < 1) return fail(RBGS_EINVAL, "batch must be >= 1");
+    if (!valid_dtype(dt)) return fail(RBGS_EINVAL, "unknown dtype");
+    if (!valid_grid(coarse, &why)) return fail(RBGS_EINVAL, "coarse: " + why);
+    if (!valid_grid(fine, &why)) return fail(RBGS_EINVAL, "fine: " + why);
+    if (int64_t(fine->n) != 2 * int64_t(coarse->n) + 1)
+        return fail(RBGS_EINVAL, "fine n must be 2 * coarse n + 1");
+    const int64_t cext = int64_t(coarse->n + 2) * coarse->ld;
+    const int64_t fext = int64_t(fine->n + 2) * fine->ld;
+    if (cstride < cext || fstride < fext)
+        return fail(RBGS_EINVAL, "grid stride must be >= (n + 2) * ld");
+    const size_t es = elem_size(dt);
+    int rc;
+    if ((rc = check_device_range(xc, (size_t(batch - 1) * size_t(cstride) + size_t(cext)) * es,
+                                 "coarse array")))
+        return rc;
+    if ((rc = check_device_range(xf, (size_t(batch - 1) * size_t(fstride) + size_t(fext)) * es,
+                                 "fine array")))
+        return rc;
+    return RBGS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -504,6 +531,44 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
     if (out.status == RBGS_ENONFINITE) g_last_error = "residual is not finite";
     if (out.status == RBGS_ENOCONV) g_last_error = "tolerance not reached";
     return out.status;
+}
+
+int rbgs_restrict(int32_t batch, rbgs_dtype dt, const rbgs_grid* fine, const void* x_fine,
+                  int64_t fine_stride, const rbgs_grid* coarse, void* x_coarse,
+                  int64_t coarse_stride, void* stream) {
+    int rc = check_transfer(batch, dt, coarse, x_coarse, coarse_stride, fine, x_fine, fine_stride);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dt == RBGS_F64)
+        HIP_TRY(launch_restrict<double>(static_cast<const double*>(x_fine), fine->ld, fine_stride,
+                                        static_cast<double*>(x_coarse), coarse->ld,
+                                        coarse_stride, coarse->n, batch, s),
+                "restrict");
+    else
+        HIP_TRY(launch_restrict<float>(static_cast<const float*>(x_fine), fine->ld, fine_stride,
+                                       static_cast<float*>(x_coarse), coarse->ld, coarse_stride,
+                                       coarse->n, batch, s),
+                "restrict");
+    return RBGS_OK;
+}
+
+int rbgs_prolong(int32_t batch, rbgs_dtype dt, const rbgs_grid* coarse, const void* x_coarse,
+                 int64_t coarse_stride, const rbgs_grid* fine, void* x_fine, int64_t fine_stride,
+                 void* stream) {
+    int rc = check_transfer(batch, dt, coarse, x_coarse, coarse_stride, fine, x_fine, fine_stride);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dt == RBGS_F64)
+        HIP_TRY(launch_prolong<double>(static_cast<const double*>(x_coarse), coarse->ld,
+                                       coarse_stride, static_cast<double*>(x_fine), fine->ld,
+                                       fine_stride, fine->n, batch, s),
+                "prolong");
+    else
+        HIP_TRY(launch_prolong<float>(static_cast<const float*>(x_coarse), coarse->ld,
+                                      coarse_stride, static_cast<float*>(x_fine), fine->ld,
+                                      fine_stride, fine->n, batch, s),
+                "prolong");
+    return RBGS_OK;
 }
 
 }  // extern "C"

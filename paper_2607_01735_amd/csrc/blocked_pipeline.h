@@ -107,6 +107,20 @@ __device__ __forceinline__ float lane_shift(float v) {
     return __int_as_float(dpp_shift<CTRL>(__float_as_int(v)));
 }
 
+// c ? a : b as a bitwise blend, so the compiler cannot turn it into a
+// branch around the computation of a (it did, with exec-mask juggling and
+// scalar-register spills, when this was a plain conditional).
+__device__ __forceinline__ double blend(bool c, double a, double b) {
+    const uint64_t m = uint64_t(0) - uint64_t(c);
+    return __longlong_as_double(
+        (long long)((uint64_t(__double_as_longlong(a)) & m) | (uint64_t(__double_as_longlong(b)) & ~m)));
+}
+
+__device__ __forceinline__ float blend(bool c, float a, float b) {
+    const uint32_t m = uint32_t(0) - uint32_t(c);
+    return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
+}
+
 template <typename T, int V, int L>
 struct Pipe {
     Vec<T, V> win[L][3];   // level l: other-colour rows (ring buffer of 3), version l-1
@@ -229,7 +243,7 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, const GridDesc<T>& 
                 T nv = T(0.25) * s;
                 if constexpr (EDGE) {
                     const int64_t q = q0 + e;
-                    out.v[e] = (row_in && q >= q_lo && q <= q_hi) ? nv : prev.v[e];
+                    out.v[e] = blend(row_in && q >= q_lo && q <= q_hi, nv, prev.v[e]);
                 } else {
                     out.v[e] = nv;  // every loaded point of an interior tile is interior
                 }

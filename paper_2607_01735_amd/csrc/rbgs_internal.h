@@ -86,6 +86,18 @@ hipError_t launch_add_correction(double* u_red, double* u_black, int64_t pitch,
                                  const float* e_red, const float* e_black, int64_t e_pitch,
                                  int n, hipStream_t s);
 
+// Vertex-centred grid transfers over `batch` grids at constant strides
+// (natural layout): full-weighting restriction onto the nc x nc coarse
+// interior, bilinear prolongation onto the nf x nf fine interior.
+template <typename T>
+hipError_t launch_restrict(const T* fine, int64_t fine_ld, int64_t fine_stride, T* coarse,
+                           int64_t coarse_ld, int64_t coarse_stride, int nc, int batch,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_prolong(const T* coarse, int64_t coarse_ld, int64_t coarse_stride, T* fine,
+                          int64_t fine_ld, int64_t fine_stride, int nf, int batch,
+                          hipStream_t s);
+
 // Zero a device range with a kernel (usable inside graph capture).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 

@@ -114,7 +114,8 @@ EXPORTED = ("rbgs_workspace_size", "rbgs_sweep", "rbgs_residual", "rbgs_solve",
             "rbgs_batch_last_error", "rbgs_unet_param_count", "rbgs_unet_workspace_size",
             "rbgs_unet_create", "rbgs_unet_destroy", "rbgs_unet_set_params",
             "rbgs_unet_get_params", "rbgs_unet_get_grads", "rbgs_unet_forward",
-            "rbgs_unet_train_step", "rbgs_solve_learned", "rbgs_unet_last_error")
+            "rbgs_unet_train_step", "rbgs_solve_learned", "rbgs_unet_last_error",
+            "rbgs_restrict", "rbgs_prolong")
 
 
 class RbgsError(RuntimeError):
@@ -274,6 +275,45 @@ def rbgs_stream_probe(kind, a, b, c=None, s=3.0, stream=None):
     cp = _vp(c.data_ptr()) if c is not None else None
     _check(_lib.rbgs_stream_probe(int(kind), _vp(a.data_ptr()), _vp(b.data_ptr()), cp, n,
                                   float(s), _stream_ptr(stream, a.device)))
+
+
+_lib.rbgs_restrict.argtypes = [ctypes.c_int32, ctypes.c_int, _P(rbgs_grid), _vp, ctypes.c_int64,
+                               _P(rbgs_grid), _vp, ctypes.c_int64, _vp]
+_lib.rbgs_restrict.restype = ctypes.c_int
+_lib.rbgs_prolong.argtypes = [ctypes.c_int32, ctypes.c_int, _P(rbgs_grid), _vp, ctypes.c_int64,
+                              _P(rbgs_grid), _vp, ctypes.c_int64, _vp]
+_lib.rbgs_prolong.restype = ctypes.c_int
+
+
+def _level(x):
+    """(batch, grid, stride) of a (B, n+2, m) or (n+2, m) natural-layout tensor."""
+    if x.dim() == 2:
+        return 1, make_grid(x), x.shape[0] * x.stride(0)
+    if x.dim() != 3:
+        raise ValueError("expected a (n+2, m) or (B, n+2, m) tensor")
+    return x.shape[0], make_grid(x[0]), x.stride(0)
+
+
+def _transfer(src, dst, stream):
+    bs, gs, ss = _level(src)
+    bd, gd, sd = _level(dst)
+    if bs != bd or src.dtype != dst.dtype or src.device != dst.device:
+        raise ValueError("src and dst must share batch size, dtype and device")
+    return bs, gs, ss, gd, sd, _stream_ptr(stream, src.device)
+
+
+def rbgs_restrict(fine, coarse, stream=None):
+    """coarse interior <- full weighting of fine's interior (n_f = 2 n_c + 1)."""
+    b, gf, sf, gc, sc, st = _transfer(fine, coarse, stream)
+    _check(_lib.rbgs_restrict(b, _dtype_code(fine), ctypes.byref(gf), _vp(fine.data_ptr()), sf,
+                              ctypes.byref(gc), _vp(coarse.data_ptr()), sc, st))
+
+
+def rbgs_prolong(coarse, fine, stream=None):
+    """fine interior <- bilinear interpolation of coarse (ring included)."""
+    b, gc, sc, gf, sf, st = _transfer(coarse, fine, stream)
+    _check(_lib.rbgs_prolong(b, _dtype_code(coarse), ctypes.byref(gc), _vp(coarse.data_ptr()), sc,
+                             ctypes.byref(gf), _vp(fine.data_ptr()), sf, st))
 
 
 # ---------------------------------------------------------------------------

@@ -161,3 +161,25 @@ def test_python_binding_rejects_mismatched_tensors(lib):
         lib.make_grid(torch.zeros(10, 5, dtype=torch.float64))
     with pytest.raises(TypeError):
         lib._dtype_code(torch.zeros(3, 3, dtype=torch.int32))
+
+
+@pytest.mark.parametrize("case", ["batch", "dtype", "sizes", "stride", "null"])
+def test_transfer_validation(lib, case):
+    fine, coarse = _grid(lib, 15), _grid(lib, 7)
+    batch, dt, fs, cs = 2, lib.F64, 17 * 17, 9 * 9
+    if case == "batch":
+        batch = 0
+    elif case == "dtype":
+        dt = 7
+    elif case == "sizes":
+        coarse = _grid(lib, 6)
+    elif case == "stride":
+        cs = 9 * 9 - 1
+    for fn in (lib._lib.rbgs_restrict, lib._lib.rbgs_prolong):
+        if fn is lib._lib.rbgs_restrict:
+            rc = fn(batch, dt, ctypes.byref(fine), None, fs, ctypes.byref(coarse), None, cs, None)
+        else:
+            rc = fn(batch, dt, ctypes.byref(coarse), None, cs, ctypes.byref(fine), None, fs, None)
+        assert rc == lib.EINVAL, (case, rc)
+        if case == "null":
+            assert "NULL" in lib.rbgs_last_error()
