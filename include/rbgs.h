@@ -240,9 +240,10 @@ const char *rbgs_batch_last_error(void);
 /* ---------------------------------------------------------------------
  * Learned initial guess (not in the paper): a small U-Net f -> u0 trained
  * on (f, u*) pairs that this library's solver produced, run and trained by
- * the library's own BF16/FP32 kernels.  Grids are N x N with N = 2^k - 1 in
- * [63, 8191] (four levels of halving); input f/rms(f), output u0 =
- * net(f/rms(f)) * rms(f).  Batched arrays are `batch` natural-layout grids
+ * the library's own BF16/FP32 kernels.  Four levels N_l = (N_{l-1}+1)/F - 1
+ * with coarsening factor F = 2 (N = 2^k - 1 in [63, 8191]) or F = 4 (N + 1
+ * a multiple of 64, N in [127, 8191]; the coarsest level's convolutions then
+ * see the whole grid); input f/rms(f), output u0 = net(f/rms(f)) * rms(f).  Batched arrays are `batch` natural-layout grids
  * of (n+2) x ld doubles stored back to back.  Parameters: one FP32 vector of
  * rbgs_unet_param_count() values, per conv layer its weight (cout, cin,
  * 3, 3) then bias (cout), in the order enc0.0, enc0.1, ..., enc3.1,
@@ -252,9 +253,9 @@ const char *rbgs_batch_last_error(void);
  * --------------------------------------------------------------------- */
 typedef struct rbgs_unet rbgs_unet;
 size_t rbgs_unet_param_count(void);
-size_t rbgs_unet_workspace_size(int32_t n, int32_t batch);
+size_t rbgs_unet_workspace_size(int32_t n, int32_t batch, int32_t factor);
 int rbgs_unet_create(rbgs_unet **net, int32_t n, int32_t batch,
-                     void *workspace, size_t workspace_bytes);
+                     int32_t factor, void *workspace, size_t workspace_bytes);
 int rbgs_unet_destroy(rbgs_unet *net);
 /* HOST vector in; resets the Adam state.  Synchronises. */
 int rbgs_unet_set_params(rbgs_unet *net, const float *params, size_t count,

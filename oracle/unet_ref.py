@@ -9,11 +9,13 @@ the library.
 Network (the build's reading of the learned-guess configuration; the paper
 has no learned part):
   input   x0 = f / rms(f) on the N x N interior, 1 channel
-  level l = 0..3 on grids of N_l = (N_{l-1} - 1)/2 points (2^k - 1 sizes)
+  level l = 0..3 on grids of N_l = (N_{l-1} + 1)/F - 1 points, coarsening
+          factor F = 2 (default) or 4
   encoder e_l = relu(conv(relu(conv(in_l))))   channels C = (16, 32, 64, 128)
-          in_0 = x0, in_{l+1} = R(e_l)          R: full-weighting restriction
+          in_0 = x0, in_{l+1} = R(e_l)          R: averaging restriction,
+          1-D weights (F - |d|)/F^2 for |d| < F (full weighting for F = 2)
   decoder d_3 = e_3; d_l = relu(conv(relu(conv([P(d_{l+1}), e_l]))))
-          P: bilinear prolongation (= 4 R^T), [., .] channel concatenation
+          P: bilinear prolongation (= F^2 R^T), [., .] channel concatenation
   head    y = conv1x1(d_0) (no activation);  u0 = y * rms(f)
   convs are 3x3, stride 1, zero padding 1, with bias.
 Loss: mean squared error against u*/rms(f) over the interior.
@@ -56,36 +58,44 @@ def conv3x3_backward(x, w, dy):
     return dxp[:, 1:-1, 1:-1], dw, db
 
 
-WEIGHTS_1D = np.array([1.0, 2.0, 1.0])
+def _weights_1d(factor):
+    """Offsets d = 1-F .. F-1 and their restriction weights (F - |d|)/F^2."""
+    d = np.arange(1 - factor, factor)
+    return d, (factor - np.abs(d)) / float(factor * factor)
 
 
-def restrict(x):
-    """Full weighting from (C, 2n+1, 2n+1) to (C, n, n): coarse point (I, J)
-    sits on fine point (2I+1, 2J+1); weights (1,2,1)x(1,2,1)/16."""
+def restrict(x, factor=2):
+    """Restriction from (C, F n + F - 1, same) to (C, n, n): coarse point
+    (I, J) sits on fine point (F I + F - 1, F J + F - 1) (0-based interior
+    indices); separable weights (F - |d|)/F^2 per axis ((1,2,1)/4 for F = 2)."""
     c, nf, _ = x.shape
-    nc = (nf - 1) // 2
+    if (nf + 1) % factor:
+        raise ValueError("fine size must be F n + F - 1")
+    nc = (nf + 1) // factor - 1
+    d, w = _weights_1d(factor)
     out = np.zeros((c, nc, nc))
-    for a in range(3):
-        for bb in range(3):
-            wgt = WEIGHTS_1D[a] * WEIGHTS_1D[bb] / 16.0
-            out += wgt * x[:, a:a + 2 * nc:2, bb:bb + 2 * nc:2]
+    for a, wa in zip(d, w):
+        for bb, wb in zip(d, w):
+            r0, c0 = factor - 1 + a, factor - 1 + bb
+            out += wa * wb * x[:, r0:r0 + factor * nc:factor, c0:c0 + factor * nc:factor]
     return out
 
 
-def restrict_transpose(y, nf):
+def restrict_transpose(y, nf, factor=2):
     """The adjoint of restrict: (C, n, n) -> (C, nf, nf)."""
     c, nc, _ = y.shape
+    d, w = _weights_1d(factor)
     out = np.zeros((c, nf, nf))
-    for a in range(3):
-        for bb in range(3):
-            wgt = WEIGHTS_1D[a] * WEIGHTS_1D[bb] / 16.0
-            out[:, a:a + 2 * nc:2, bb:bb + 2 * nc:2] += wgt * y
+    for a, wa in zip(d, w):
+        for bb, wb in zip(d, w):
+            r0, c0 = factor - 1 + a, factor - 1 + bb
+            out[:, r0:r0 + factor * nc:factor, c0:c0 + factor * nc:factor] += wa * wb * y
     return out
 
 
-def prolong(y, nf):
-    """Bilinear prolongation P = 4 R^T from (C, n, n) to (C, 2n+1, 2n+1)."""
-    return 4.0 * restrict_transpose(y, nf)
+def prolong(y, nf, factor=2):
+    """Bilinear prolongation P = F^2 R^T from (C, n, n) to (C, nf, nf)."""
+    return float(factor * factor) * restrict_transpose(y, nf, factor)
 
 
 def init_params(channels=CHANNELS, seed=0):
@@ -121,7 +131,7 @@ def param_names(channels=CHANNELS):
     return names
 
 
-def forward(p, x0, channels=CHANNELS):
+def forward(p, x0, channels=CHANNELS, factor=2):
     """Normalised network output y (N x N) for normalised input x0 (N x N);
     returns (y, cache) where cache holds what the backward pass needs."""
     L = len(channels)
@@ -136,10 +146,10 @@ def forward(p, x0, channels=CHANNELS):
         cache[f"enc{l}"] = (inp, z0, a0, z1)
         enc.append(a1)
         if l + 1 < L:
-            inp = restrict(a1)
+            inp = restrict(a1, factor)
     d = enc[-1]
     for l in range(L - 2, -1, -1):
-        up = prolong(d, enc[l].shape[1])
+        up = prolong(d, enc[l].shape[1], factor)
         cat = np.concatenate([up, enc[l]], axis=0)
         z0 = conv3x3(cat, p[f"dec{l}.0.w"], p[f"dec{l}.0.b"])
         a0 = np.maximum(z0, 0.0)
@@ -151,7 +161,7 @@ def forward(p, x0, channels=CHANNELS):
     return y, cache
 
 
-def backward(p, cache, dy, channels=CHANNELS):
+def backward(p, cache, dy, channels=CHANNELS, factor=2):
     """Gradients of a loss with dL/dy = dy with respect to every parameter."""
     L = len(channels)
     g = {}
@@ -169,8 +179,8 @@ def backward(p, cache, dy, channels=CHANNELS):
         dcat, g[f"dec{l}.0.w"], g[f"dec{l}.0.b"] = conv3x3_backward(cat, p[f"dec{l}.0.w"], dz0)
         dup, denc_l = dcat[:cup], dcat[cup:]
         denc[l] = denc[l] + denc_l
-        # up = P(d_{l+1}) with P = 4 R^T, so dL/dd_{l+1} = 4 R(dup)
-        grad_d = 4.0 * restrict(dup)
+        # up = P(d_{l+1}) with P = F^2 R^T, so dL/dd_{l+1} = F^2 R(dup)
+        grad_d = float(factor * factor) * restrict(dup, factor)
     denc[L - 1] = grad_d
     # encoder, from the bottom level up
     carry = None
@@ -183,7 +193,7 @@ def backward(p, cache, dy, channels=CHANNELS):
         dinp, g[f"enc{l}.0.w"], g[f"enc{l}.0.b"] = conv3x3_backward(inp, p[f"enc{l}.0.w"], dz0)
         if l > 0:
             # inp = R(e_{l-1})
-            carry = restrict_transpose(dinp, cache[f"enc{l - 1}"][1].shape[1])
+            carry = restrict_transpose(dinp, cache[f"enc{l - 1}"][1].shape[1], factor)
     return g
 
 

@@ -2,12 +2,14 @@
 // kernels (BF16 activations and weights, FP32 accumulation on MFMA, FP32
 // master weights and Adam).
 //
-// Network: input x0 = f / rms(f) on the N x N interior (N = 2^k - 1);
-// four levels on grids N_l = (N_{l-1}-1)/2 with 16/32/64/128 channels; each
-// encoder level is conv3x3+ReLU twice, levels are linked by full-weighting
-// restriction R; each decoder level concatenates the bilinear prolongation
-// P = 4 R^T of the level below with the encoder's output of its own level
-// and applies conv3x3+ReLU twice; a 1x1 head gives y, and u0 = y * rms(f).
+// Network: input x0 = f / rms(f) on the N x N interior; four levels on
+// grids N_l = (N_{l-1} + 1)/F - 1 (coarsening factor F = 2 or 4) with
+// 16/32/64/128 channels; each encoder level is conv3x3+ReLU twice, levels
+// are linked by the averaging restriction R; each decoder level
+// concatenates the bilinear prolongation P = F^2 R^T of the level below with
+// the encoder's output of its own level and applies conv3x3+ReLU twice; a
+// 1x1 head gives y, and u0 = y * rms(f).  With F = 4 the coarsest level's
+// 3x3 convolutions span the whole grid (N = 511: levels 511, 127, 31, 7).
 // The restriction/prolongation pair is the multigrid transfer pair, fixed
 // (no weights).  Loss: mean squared error against u*/rms(f).
 //
@@ -209,11 +211,16 @@ __global__ __launch_bounds__(256) void k_bias_grad(const bf16* dy, int64_t dys, 
     (void)rows;
 }
 
-// Full-weighting restriction (fine 2n+1 -> coarse n) or bilinear
-// prolongation (coarse n -> fine 2n+1, P = 4 R^T), per channel, scaled by
-// `scale`; accumulate != 0 adds into the output instead of overwriting.
+// Grid transfers between levels coarsened by a factor F (2 or 4): fine
+// n_f = F n_c + F - 1, and coarse interior point (I, J) (0-based) sits on
+// fine interior point (F I + F - 1, F J + F - 1).  Restriction averages the
+// fine points within F - 1 of that point with the separable weights
+// (F - |d|) / F^2 per axis (full weighting for F = 2: (1, 2, 1) / 4);
+// prolongation is bilinear interpolation, P = F^2 R^T (1-D weights
+// (F - |d|) / F).  Per channel, scaled by `scale`; accumulate != 0 adds into
+// the output instead of overwriting.
 __global__ __launch_bounds__(256) void k_restrict(const bf16* in, int64_t is, bf16* out, int64_t os,
-                                                  int batch, int nc, int c, float scale,
+                                                  int batch, int nc, int c, int F, float scale,
                                                   int accumulate) {
     const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
     const int64_t total = int64_t(batch) * nc * nc * c;
@@ -223,24 +230,27 @@ __global__ __launch_bounds__(256) void k_restrict(const bf16* in, int64_t is, bf
     const int J = int(r % nc); r /= nc;
     const int I = int(r % nc);
     const int b = int(r / nc);
-    const int nf = 2 * nc + 1;
-    const float w1[3] = {1.f, 2.f, 1.f};
+    const int nf = F * nc + F - 1;
+    const int ci = F * I + F - 1, cj = F * J + F - 1;
     float s = 0.f;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int bb = 0; bb < 3; ++bb)
-            s += w1[a] * w1[bb] * bf2f(in[((int64_t(b) * nf + 2 * I + a) * nf + 2 * J + bb) * is + ch]);
-    s *= scale / 16.f;
+    for (int di = 1 - F; di < F; ++di) {
+        const float wi = float(F - (di < 0 ? -di : di));
+        const bf16* row = in + ((int64_t(b) * nf + ci + di) * nf + cj) * is + ch;
+        float t = 0.f;
+        for (int dj = 1 - F; dj < F; ++dj)
+            t += float(F - (dj < 0 ? -dj : dj)) * bf2f(row[dj * is]);
+        s += wi * t;
+    }
+    s *= scale / float(F * F * F * F);
     bf16* o = out + ((int64_t(b) * nc + I) * nc + J) * os + ch;
     if (accumulate) s += bf2f(*o);
     *o = f2bf(s);
 }
 
 __global__ __launch_bounds__(256) void k_prolong(const bf16* in, int64_t is, bf16* out, int64_t os,
-                                                 int batch, int nc, int c, float scale,
+                                                 int batch, int nc, int c, int F, float scale,
                                                  int accumulate) {
-    const int nf = 2 * nc + 1;
+    const int nf = F * nc + F - 1;
     const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
     const int64_t total = int64_t(batch) * nf * nf * c;
     if (idx >= total) return;
@@ -249,18 +259,18 @@ __global__ __launch_bounds__(256) void k_prolong(const bf16* in, int64_t is, bf1
     const int j = int(r % nf); r /= nf;
     const int i = int(r % nf);
     const int b = int(r / nf);
-    // coarse (I, J) sits on fine (2I+1, 2J+1); 1D weight 1 there, 1/2 at +-1
+    // the coarse points within F - 1 of fine i are I = (i + 1) / F - 1 and
+    // the next one; weight (F - |d|) / F with d = i - (F I + F - 1)
+    const float invF = 1.f / float(F);
     float s = 0.f;
-    for (int I = (i - 2) / 2; I <= i / 2; ++I) {
-        if (I < 0 || I >= nc) continue;
-        const int di = i - (2 * I + 1);
-        if (di < -1 || di > 1) continue;
-        const float wi = di == 0 ? 1.f : 0.5f;
-        for (int J = (j - 2) / 2; J <= j / 2; ++J) {
-            if (J < 0 || J >= nc) continue;
-            const int dj = j - (2 * J + 1);
-            if (dj < -1 || dj > 1) continue;
-            const float wj = dj == 0 ? 1.f : 0.5f;
+    for (int I = (i + 1) / F - 1; I <= (i + 1) / F; ++I) {
+        const int di = i - (F * I + F - 1);
+        if (I < 0 || I >= nc || di <= -F || di >= F) continue;
+        const float wi = float(F - (di < 0 ? -di : di)) * invF;
+        for (int J = (j + 1) / F - 1; J <= (j + 1) / F; ++J) {
+            const int dj = j - (F * J + F - 1);
+            if (J < 0 || J >= nc || dj <= -F || dj >= F) continue;
+            const float wj = float(F - (dj < 0 ? -dj : dj)) * invF;
             s += wi * wj * bf2f(in[((int64_t(b) * nc + I) * nc + J) * is + ch]);
         }
     }
@@ -478,6 +488,7 @@ std::vector<Layer> make_layers(size_t* count) {
 
 struct Net {
     int n[kLevels];
+    int factor = 2;  // coarsening factor between levels (2 or 4)
     int batch;
     std::vector<Layer> layers;
     size_t nparam;
@@ -614,18 +625,18 @@ namespace {
         if (_e != hipSuccess) return _e;     \
     } while (0)
 
-hipError_t restrict_op(const bf16* in, int64_t is, bf16* out, int64_t os, int batch, int nc, int c,
-                       float scale, int acc, hipStream_t s) {
+hipError_t restrict_op(const Net& net, const bf16* in, int64_t is, bf16* out, int64_t os, int batch,
+                       int nc, int c, float scale, int acc, hipStream_t s) {
     hipLaunchKernelGGL(k_restrict, dim3(blocks_for(int64_t(batch) * nc * nc * c)), dim3(256), 0, s,
-                       in, is, out, os, batch, nc, c, scale, acc);
+                       in, is, out, os, batch, nc, c, net.factor, scale, acc);
     return hipGetLastError();
 }
 
-hipError_t prolong_op(const bf16* in, int64_t is, bf16* out, int64_t os, int batch, int nc, int c,
-                      float scale, int acc, hipStream_t s) {
-    const int nf = 2 * nc + 1;
+hipError_t prolong_op(const Net& net, const bf16* in, int64_t is, bf16* out, int64_t os, int batch,
+                      int nc, int c, float scale, int acc, hipStream_t s) {
+    const int nf = net.factor * nc + net.factor - 1;
     hipLaunchKernelGGL(k_prolong, dim3(blocks_for(int64_t(batch) * nf * nf * c)), dim3(256), 0, s,
-                       in, is, out, os, batch, nc, c, scale, acc);
+                       in, is, out, os, batch, nc, c, net.factor, scale, acc);
     return hipGetLastError();
 }
 
@@ -665,13 +676,13 @@ hipError_t forward(Net& net, int batch, const double* f, int64_t ld, int64_t gst
         const int64_t es = l < kLevels - 1 ? cat_channels(l) : kC[l];
         NN_TRY(conv(net, c1, net.aenc[l], kC[l], nullptr, 0, true, e, es, batch, s));
         if (l + 1 < kLevels)
-            NN_TRY(restrict_op(e, es, net.in[l + 1], in_channels(l + 1), batch, net.n[l + 1], kC[l],
-                               1.f, 0, s));
+            NN_TRY(restrict_op(net, e, es, net.in[l + 1], in_channels(l + 1), batch, net.n[l + 1],
+                               kC[l], 1.f, 0, s));
     }
     // decoder
     for (int l = kLevels - 2; l >= 0; --l) {
         const bf16* below = l == kLevels - 2 ? net.e3 : net.d[l + 1];
-        NN_TRY(prolong_op(below, kC[l + 1], net.cat[l], cat_channels(l), batch, net.n[l + 1],
+        NN_TRY(prolong_op(net, below, kC[l + 1], net.cat[l], cat_channels(l), batch, net.n[l + 1],
                           kC[l + 1], 1.f, 0, s));
         char n0name[8] = "dec0.0", n1name[8] = "dec0.1";
         n0name[3] = n1name[3] = char('0' + l);
@@ -709,9 +720,10 @@ hipError_t backward(Net& net, int batch, hipStream_t s) {
         NN_TRY(conv(net, c1, net.gd[l], C, net.d[l], C, false, net.gadec[l], C, batch, s));
         NN_TRY(wgrad(net, c0, net.cat[l], CC, net.gadec[l], C, net.adec[l], C, batch, s));
         NN_TRY(conv(net, c0, net.gadec[l], C, net.adec[l], C, false, net.gcat[l], CC, batch, s));
-        // up = P(d_{l+1}) with P = 4 R^T: the gradient reaching d_{l+1} is 4 R(dup)
+        // up = P(d_{l+1}) with P = F^2 R^T: the gradient reaching d_{l+1} is F^2 R(dup)
         bf16* gbelow = l == kLevels - 2 ? net.ge3 : net.gd[l + 1];
-        NN_TRY(restrict_op(net.gcat[l], CC, gbelow, kC[l + 1], batch, net.n[l + 1], kC[l + 1], 4.f, 0, s));
+        NN_TRY(restrict_op(net, net.gcat[l], CC, gbelow, kC[l + 1], batch, net.n[l + 1], kC[l + 1],
+                           float(net.factor * net.factor), 0, s));
     }
     // encoder, from the bottom level up
     for (int l = kLevels - 1; l >= 0; --l) {
@@ -729,11 +741,11 @@ hipError_t backward(Net& net, int batch, hipStream_t s) {
         if (l > 0) {
             NN_TRY(conv(net, c0, net.gaenc[l], C, net.aenc[l], C, false, net.gin[l], in_channels(l),
                         batch, s));
-            // in_l = R(e_{l-1}): add R^T(g_in) = P(g_in)/4 to e_{l-1}'s gradient
+            // in_l = R(e_{l-1}): add R^T(g_in) = P(g_in)/F^2 to e_{l-1}'s gradient
             // (which already holds its skip-connection part)
             bf16* gprev = net.gcat[l - 1] + kC[l];
-            NN_TRY(prolong_op(net.gin[l], in_channels(l), gprev, cat_channels(l - 1), batch, net.n[l],
-                              in_channels(l), 0.25f, 1, s));
+            NN_TRY(prolong_op(net, net.gin[l], in_channels(l), gprev, cat_channels(l - 1), batch,
+                              net.n[l], in_channels(l), 1.f / float(net.factor * net.factor), 1, s));
         }
     }
     return hipSuccess;
@@ -761,10 +773,20 @@ int nn_hip(hipError_t e, const char* what) {
     return nnfail(RBGS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-bool valid_size(int n) {
-    // four levels of 2^k - 1 grids down to at least 7 points
-    if (n < 63 || n > 8191) return false;
-    return ((n + 1) & n) == 0;
+// Four levels n_l = (n_{l-1} + 1) / F - 1 with at least one point on the
+// coarsest: F = 2 takes n = 2^k - 1 in [63, 8191] (coarsest >= 7 points),
+// F = 4 takes n + 1 divisible by 64 in [127, 8191].
+bool valid_size(int n, int factor) {
+    if (n > 8191) return false;
+    if (factor == 2) return n >= 63 && ((n + 1) & n) == 0;
+    if (factor == 4) return n >= 127 && (n + 1) % 64 == 0;
+    return false;
+}
+
+void set_levels(Net& net, int n, int factor) {
+    net.factor = factor;
+    net.n[0] = n;
+    for (int l = 1; l < kLevels; ++l) net.n[l] = (net.n[l - 1] + 1) / factor - 1;
 }
 
 }  // namespace
@@ -785,33 +807,35 @@ size_t rbgs_unet_param_count(void) {
     return c;
 }
 
-size_t rbgs_unet_workspace_size(int32_t n, int32_t batch) {
-    if (!nn::valid_size(n) || batch < 1 || batch > 4096) return 0;
+size_t rbgs_unet_workspace_size(int32_t n, int32_t batch, int32_t factor) {
+    if (!nn::valid_size(n, factor) || batch < 1 || batch > 4096) return 0;
     nn::Net net;
     net.layers = nn::make_layers(&net.nparam);
     net.batch = batch;
-    net.n[0] = n;
-    for (int l = 1; l < nn::kLevels; ++l) net.n[l] = (net.n[l - 1] - 1) / 2;
+    nn::set_levels(net, n, factor);
     return nn::carve(net, nullptr);
 }
 
 const char* rbgs_unet_last_error(void) { return nn::g_nn_error.c_str(); }
 
-int rbgs_unet_create(rbgs_unet** out, int32_t n, int32_t batch, void* workspace,
+int rbgs_unet_create(rbgs_unet** out, int32_t n, int32_t batch, int32_t factor, void* workspace,
                      size_t workspace_bytes) {
     if (!out) return nn::nnfail(RBGS_EINVAL, "net is NULL");
     *out = nullptr;
-    if (!nn::valid_size(n)) return nn::nnfail(RBGS_EINVAL, "n must be 2^k - 1 in [63, 8191]");
+    if (factor != 2 && factor != 4) return nn::nnfail(RBGS_EINVAL, "factor must be 2 or 4");
+    if (!nn::valid_size(n, factor))
+        return nn::nnfail(RBGS_EINVAL, factor == 2 ? "n must be 2^k - 1 in [63, 8191] for factor 2"
+                                                   : "n + 1 must be a multiple of 64 in "
+                                                     "[128, 8192] for factor 4");
     if (batch < 1 || batch > 4096) return nn::nnfail(RBGS_EINVAL, "batch must be in [1, 4096]");
-    const size_t need = rbgs_unet_workspace_size(n, batch);
+    const size_t need = rbgs_unet_workspace_size(n, batch, factor);
     if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 || workspace_bytes < need)
         return nn::nnfail(RBGS_EWORKSPACE, "workspace missing, misaligned or smaller than " +
                                                std::to_string(need) + " bytes");
     rbgs_unet* u = new rbgs_unet;
     u->net.layers = nn::make_layers(&u->net.nparam);
     u->net.batch = batch;
-    u->net.n[0] = n;
-    for (int l = 1; l < nn::kLevels; ++l) u->net.n[l] = (u->net.n[l - 1] - 1) / 2;
+    nn::set_levels(u->net, n, factor);
     u->net.total = nn::carve(u->net, static_cast<char*>(workspace));
     *out = u;
     return RBGS_OK;

@@ -152,39 +152,59 @@ def train(net, torch, f, u, epochs, batch, lr0, seed=0, lr_min_frac=0.05):
             lr = lr0 * (lr_min_frac + (1 - lr_min_frac) * 0.5 * (1 + math.cos(math.pi * step / total)))
             losses.append(net.train_step(f[idx].contiguous(), u[idx].contiguous(), lr))
             step += 1
+            if step % 1000 == 0:
+                log(f"step {step}/{total}: loss {np.mean(losses[-1000:]):.4e}")
         history.append(float(np.mean(losses)))
         log(f"epoch {ep + 1}/{epochs}: loss {history[-1]:.4e} lr {lr:.2e}")
     return history
 
 
-def evaluate(rb, torch, net, n, seeds, tol, compare_after, kernel="auto", max_sweeps=2_000_000,
-             check_every=2000):
-    """Time and sweeps to rel <= tol: FP64 solve from u = 0 versus the same
-    solve from the network's guess (kept only if it wins the comparison)."""
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def evaluate(rb, torch, net, n, seeds, tol, compare_after=(0,), kernel="auto",
+             max_sweeps=2_000_000, check_every=2000):
+    """Sweeps and wall time (network inference included) to rel <= tol: the
+    FP64 solve from u = 0 (the judge) against the same solve through
+    rbgs_solve_learned for each comparison depth in `compare_after`."""
     rows = []
-    f_all = torch.from_numpy(fields(n, seeds)).to("cuda")
+    f_all = fields_on_device(torch, n, seeds)
     for i, s in enumerate(seeds):
         f = f_all[i]
         u = torch.zeros_like(f)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        base = rb.rbgs_solve(u, f, max_sweeps, tol, check_every=check_every, kernel=kernel)
-        torch.cuda.synchronize()
-        t_base = time.perf_counter() - t0
-        u = torch.zeros_like(f)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        got = net.solve_learned(u, f, max_sweeps, tol, check_every=check_every, kernel=kernel,
-                                compare_after=compare_after)
-        torch.cuda.synchronize()
-        t_nn = time.perf_counter() - t0
-        rows.append({"seed": int(s), "zero_start": {"sweeps": base["sweeps"], "seconds": round(t_base, 4),
-                                                    "rel": base["rel_residual"]},
-                     "learned": {"sweeps": got["sweeps"], "seconds": round(t_nn, 4),
-                                 "rel": got["rel_residual"], "used_guess": got["used_guess"],
-                                 "rel_start": got["rel_start"]}})
-        log(f"test seed {s}: {rows[-1]}")
+        base, t_base = _timed(torch, lambda: rb.rbgs_solve(u, f, max_sweeps, tol,
+                                                           check_every=check_every, kernel=kernel))
+        row = {"seed": int(s), "zero_start": {"sweeps": base["sweeps"], "seconds": round(t_base, 4),
+                                              "rel": base["rel_residual"]}}
+        for ca in compare_after:
+            u = torch.zeros_like(f)
+            got, t_nn = _timed(torch, lambda: net.solve_learned(
+                u, f, max_sweeps, tol, check_every=check_every, kernel=kernel, compare_after=ca))
+            row[f"learned_k{ca}"] = {"sweeps": got["sweeps"], "seconds": round(t_nn, 4),
+                                     "rel": got["rel_residual"], "used_guess": got["used_guess"],
+                                     "rel_start": got["rel_start"]}
+        rows.append(row)
+        log(f"test seed {s}: {row}")
     return rows
+
+
+def summarise(rows, compare_after):
+    """Totals over the test seeds: sweep and time ratios learned / zero start."""
+    out = {}
+    zs = sum(r["zero_start"]["sweeps"] for r in rows)
+    zt = sum(r["zero_start"]["seconds"] for r in rows)
+    for ca in compare_after:
+        key = f"learned_k{ca}"
+        out[key] = {"sweep_ratio": round(sum(r[key]["sweeps"] for r in rows) / zs, 4),
+                    "time_ratio": round(sum(r[key]["seconds"] for r in rows) / zt, 4),
+                    "guess_used": sum(bool(r[key]["used_guess"]) for r in rows),
+                    "of": len(rows)}
+    return out
 
 
 def guess_quality(rb, torch, net, n, seeds, level_sweeps):
@@ -207,11 +227,14 @@ def main():
                     help="FP32 sweeps per nested-iteration level, coarsest first")
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--factor", type=int, default=4, help="coarsening factor between levels")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--init-seed", type=int, default=0)
-    ap.add_argument("--test", type=int, default=4)
+    ap.add_argument("--test", type=int, default=4, help="held-out fields for the guess error")
+    ap.add_argument("--eval", type=int, default=2, help="held-out fields solved to --tol")
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--compare-after", type=int, default=0)
+    ap.add_argument("--compare-after", type=int, default=500,
+                    help="sweeps given to both starts before the residual comparison")
     ap.add_argument("--params", default=None, help="start from these parameters (.npy)")
     ap.add_argument("--out", default=None, help="write the trained parameters here (.npy)")
     ap.add_argument("--summary", default=None, help="write a JSON summary here")
@@ -223,7 +246,7 @@ def main():
     import paper_2607_01735_amd as rb
 
     n = args.n
-    net = rb.UNet(n, args.batch)
+    net = rb.UNet(n, args.batch, factor=args.factor)
     if args.params:
         net.set_params(np.load(args.params))
     else:
@@ -233,7 +256,7 @@ def main():
         net.set_params(vec)
     level_sweeps = tuple(int(x) for x in args.level_sweeps.split(","))
     summary = {"n": n, "train": args.train, "level_sweeps": level_sweeps, "epochs": args.epochs,
-               "batch": args.batch, "lr": args.lr}
+               "batch": args.batch, "lr": args.lr, "factor": args.factor}
     if args.train > 0:
         t0 = time.perf_counter()
         f = fields_on_device(torch, n, range(args.train))
@@ -257,9 +280,11 @@ def main():
     summary["guess_rel_error"] = guess_quality(rb, torch, net, n, test_seeds, level_sweeps)
     log(f"held-out guess error vs u*: {summary['guess_rel_error']}")
     if not args.skip_eval:
-        for ca in sorted({0, args.compare_after}):
-            summary[f"eval_compare_after_{ca}"] = evaluate(rb, torch, net, n, test_seeds[:2],
-                                                           args.tol, ca)
+        depths = sorted({0, args.compare_after})
+        rows = evaluate(rb, torch, net, n, test_seeds[:args.eval], args.tol, depths)
+        summary["eval"] = rows
+        summary["eval_summary"] = summarise(rows, depths)
+        log(f"evaluation: {summary['eval_summary']}")
     out = json.dumps(summary)
     if args.summary:
         with open(args.summary, "w") as fh:

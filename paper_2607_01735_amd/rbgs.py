@@ -427,9 +427,10 @@ def rbgs_autotune_batched(us, fs, hs=None, workspace=None, stream=None):
 # ---------------------------------------------------------------------------
 _lib.rbgs_unet_param_count.argtypes = []
 _lib.rbgs_unet_param_count.restype = ctypes.c_size_t
-_lib.rbgs_unet_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
+_lib.rbgs_unet_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
 _lib.rbgs_unet_workspace_size.restype = ctypes.c_size_t
-_lib.rbgs_unet_create.argtypes = [_P(_vp), ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t]
+_lib.rbgs_unet_create.argtypes = [_P(_vp), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp,
+                                  ctypes.c_size_t]
 _lib.rbgs_unet_create.restype = ctypes.c_int
 _lib.rbgs_unet_destroy.argtypes = [_vp]
 _lib.rbgs_unet_destroy.restype = ctypes.c_int
@@ -460,20 +461,22 @@ def _ncheck(rc, allow=(OK,)):
 
 
 class UNet:
-    """The learned-guess network for N x N grids (N = 2^k - 1 >= 63) and up
-    to `batch` samples per call; all state in one device workspace."""
+    """The learned-guess network for N x N grids and up to `batch` samples
+    per call, levels coarsened by `factor` (2: N = 2^k - 1 >= 63; 4: N + 1 a
+    multiple of 64, N >= 127); all state in one device workspace."""
 
-    def __init__(self, n, batch, device="cuda", workspace=None):
+    def __init__(self, n, batch, factor=4, device="cuda", workspace=None):
         import torch
-        self.n, self.batch = int(n), int(batch)
-        need = int(_lib.rbgs_unet_workspace_size(self.n, self.batch))
+        self.n, self.batch, self.factor = int(n), int(batch), int(factor)
+        need = int(_lib.rbgs_unet_workspace_size(self.n, self.batch, self.factor))
         if need == 0:
-            raise RbgsError(EINVAL, "n must be 2^k - 1 in [63, 8191] and batch in [1, 4096]")
+            raise RbgsError(EINVAL, "unsupported n / batch / factor (factor 2: n = 2^k - 1 >= 63; "
+                                    "factor 4: n + 1 a multiple of 64, n >= 127; batch 1..4096)")
         self.device = torch.device(device)
         self.workspace = workspace if workspace is not None else torch.empty(
             need, dtype=torch.uint8, device=self.device)
         h = _vp()
-        _ncheck(_lib.rbgs_unet_create(ctypes.byref(h), self.n, self.batch,
+        _ncheck(_lib.rbgs_unet_create(ctypes.byref(h), self.n, self.batch, self.factor,
                                       _vp(self.workspace.data_ptr()), self.workspace.numel()))
         self._h = h
         self.count = rbgs_unet_param_count()

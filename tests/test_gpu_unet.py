@@ -25,7 +25,9 @@ if not torch.cuda.is_available():
 import paper_2607_01735_amd as rb  # noqa: E402
 
 DEV = torch.device("cuda:0")
-N = 63
+N = 127     # the factor-4 network (levels 127, 31, 7, 1)
+FACTOR = 4
+CONFIGS = [(2, 63), (4, 127)]  # (coarsening factor, N)
 
 
 def say(msg):
@@ -71,43 +73,45 @@ def batch_fields(seeds, n=N):
     return np.stack(fs)
 
 
-def ref_forward(p, f_nat):
+def ref_forward(p, f_nat, factor=FACTOR):
     """Reference output u0 (interior) with bfloat16-rounded weights/input."""
     pr = {k: bf16_round(v) for k, v in p.items()}
     n = f_nat.shape[0] - 2
     x0, rms = U.normalise(f_nat[1:n + 1, 1:n + 1])
-    y, cache = U.forward(pr, bf16_round(x0))
+    y, cache = U.forward(pr, bf16_round(x0), factor=factor)
     return y * rms, y, cache, pr, rms
 
 
-def test_forward_matches_reference():
-    say("unet forward n=63 batch=2")
+@pytest.mark.parametrize("factor,n", CONFIGS)
+def test_forward_matches_reference(factor, n):
+    say(f"unet forward n={n} factor={factor} batch=2")
     p = make_params()
-    net = rb.UNet(N, 2)
+    net = rb.UNet(n, 2, factor=factor)
     net.set_params(flatten(p).astype(np.float32))
     assert np.array_equal(net.get_params(), flatten(p).astype(np.float32))
-    f = batch_fields([0, 1])
+    f = batch_fields([0, 1], n)
     ft = torch.from_numpy(f).to(DEV)
     u0 = torch.zeros_like(ft)
     net.forward(ft, u0)
     got = u0.cpu().numpy()
     for b in range(2):
-        ref, *_ = ref_forward(p, f[b])
-        g = got[b, 1:N + 1, 1:N + 1]
+        ref, *_ = ref_forward(p, f[b], factor)
+        g = got[b, 1:n + 1, 1:n + 1]
         err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
         assert err < 3e-2, f"sample {b}: relative error {err}"
         assert not np.any(got[b, 0]) and not np.any(got[b, :, 0])  # ring untouched
 
 
-def test_gradients_match_reference():
-    say("unet gradients n=63 batch=2")
+@pytest.mark.parametrize("factor,n", CONFIGS)
+def test_gradients_match_reference(factor, n):
+    say(f"unet gradients n={n} factor={factor} batch=2")
     p = make_params(seed=2)
-    net = rb.UNet(N, 2)
+    net = rb.UNet(n, 2, factor=factor)
     net.set_params(flatten(p).astype(np.float32))
-    f = batch_fields([5, 6])
+    f = batch_fields([5, 6], n)
     target = np.zeros_like(f)
     rng = np.random.default_rng(7)
-    target[:, 1:N + 1, 1:N + 1] = rng.standard_normal((2, N, N)) * 0.01
+    target[:, 1:n + 1, 1:n + 1] = rng.standard_normal((2, n, n)) * 0.01
     loss = net.train_step(torch.from_numpy(f).to(DEV), torch.from_numpy(target).to(DEV), 0.0,
                           update=False)
     g_gpu = unflatten(net.get_grads().astype(np.float64), p)
@@ -115,11 +119,11 @@ def test_gradients_match_reference():
     g_ref = {k: np.zeros_like(v) for k, v in p.items()}
     loss_ref = 0.0
     for b in range(2):
-        _, y, cache, pr, rms = ref_forward(p, f[b])
-        t = target[b, 1:N + 1, 1:N + 1] / rms
+        _, y, cache, pr, rms = ref_forward(p, f[b], factor)
+        t = target[b, 1:n + 1, 1:n + 1] / rms
         lb, dy = U.mse_loss(y, t)
         loss_ref += lb / 2
-        gb = U.backward(pr, cache, dy / 2)
+        gb = U.backward(pr, cache, dy / 2, factor=factor)
         for k in g_ref:
             g_ref[k] += gb[k]
     assert loss == pytest.approx(loss_ref, rel=3e-2)

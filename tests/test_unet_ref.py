@@ -37,6 +37,33 @@ def test_restrict_and_prolong_identities():
                        0.25 * (y[:, :-1, :-1] + y[:, 1:, :-1] + y[:, :-1, 1:] + y[:, 1:, 1:]))
 
 
+def test_factor_four_transfers():
+    """F = 4: 1-D weights (1,2,3,4,3,2,1)/16, P = 16 R^T; both exact on
+    linear functions (R at every coarse point, P between coarse points)."""
+    rng = np.random.default_rng(5)
+    nc, nf = 7, 31
+    x = rng.standard_normal((2, nf, nf))
+    y = rng.standard_normal((2, nc, nc))
+    assert np.isclose(np.sum(U.restrict(x, 4) * y), np.sum(x * U.restrict_transpose(y, nf, 4)),
+                      rtol=1e-13)
+    assert np.allclose(U.restrict(np.full((1, nf, nf), -1.25), 4), -1.25)
+    i = np.arange(nf, dtype=np.float64)
+    lin = (0.3 + 0.7 * i[:, None] - 1.1 * i[None, :])[None]
+    centres = 4 * np.arange(nc) + 3
+    assert np.allclose(U.restrict(lin, 4)[0], lin[0][np.ix_(centres, centres)], rtol=0, atol=1e-12)
+    coarse = lin[0][np.ix_(centres, centres)][None]
+    p = U.prolong(coarse, nf, 4)
+    inner = slice(3, 4 * (nc - 1) + 4)
+    assert np.allclose(p[0, inner, inner], lin[0, inner, inner], rtol=0, atol=1e-12)
+    # one coarse point: a pyramid of height 1 and base 7 x 7
+    e = np.zeros((1, nc, nc))
+    e[0, 2, 3] = 1.0
+    p = U.prolong(e, nf, 4)
+    tri = np.array([1, 2, 3, 4, 3, 2, 1]) / 4.0
+    assert np.allclose(p[0, 8:15, 12:19], np.outer(tri, tri))
+    assert np.isclose(p.sum(), 16.0)
+
+
 def test_conv_backward_by_finite_differences():
     rng = np.random.default_rng(2)
     x = rng.standard_normal((2, 5, 6))
@@ -64,9 +91,9 @@ def test_conv_backward_by_finite_differences():
     assert np.isclose((loss(x, w, bp) - loss(x, w, bm)) / (2 * eps), db[1], rtol=1e-6)
 
 
-def test_network_gradient_by_finite_differences():
+@pytest.mark.parametrize("factor,n", [(2, 15), (4, 127)])
+def test_network_gradient_by_finite_differences(factor, n):
     channels = (2, 3, 4, 5)
-    n = 15
     p = U.init_params(channels, seed=3)
     rng = np.random.default_rng(4)
     for k in p:
@@ -76,12 +103,12 @@ def test_network_gradient_by_finite_differences():
     target = rng.standard_normal((n, n))
 
     def loss_of(params):
-        y, _ = U.forward(params, x0, channels)
+        y, _ = U.forward(params, x0, channels, factor)
         return U.mse_loss(y, target)[0]
 
-    y, cache = U.forward(p, x0, channels)
+    y, cache = U.forward(p, x0, channels, factor)
     _, dy = U.mse_loss(y, target)
-    g = U.backward(p, cache, dy, channels)
+    g = U.backward(p, cache, dy, channels, factor)
     assert set(g) == set(p)
     eps = 1e-6
     checked = 0
