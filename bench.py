@@ -98,27 +98,36 @@ def stream_probe(torch, rb, gib=2.0):
     return out
 
 
+def _timed_solve(torch, rb, u, f, **kw):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = rb.rbgs_solve(u, f, **kw)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, info
+
+
 def time_to_tolerance(torch, rb, W, n=255, tol=1e-8):
     """Wall time and sweeps to rel <= tol from u = 0 on the n x n problem with
     f = 2 pi^2 sin(pi x) sin(pi y) (124 616 sweeps at n = 255 by the closed
-    form), for the plain FP64 judge and the faster forms."""
+    form), for the plain FP64 judge and the faster forms: the resident band
+    kernel and the blocked kernel in FP64, and FP64 refinement around FP32
+    (or bfloat16-rhs) inner sweeps on the resident kernel."""
     h = W.spacing(n)
     f = torch.from_numpy(W.sine_rhs(n)).to("cuda")
-    out = {"problem": f"{n}x{n} FP64 sine, u0=0, rel<={tol:g}, residual every 1000 sweeps"}
-    forms = [("plain_f64", dict(kernel="plain")),
-             ("blocked_f64", dict(kernel="blocked", tile_rows=16)),
-             ("f32_ir_blocked", dict(kernel="blocked", tile_rows=16, precision="f32_ir",
-                                     inner_sweeps=4000))]
+    out = {"problem": f"{n}x{n} FP64 sine, u0=0, rel<={tol:g}"}
+    forms = [("plain_f64", dict(kernel="plain", check_every=1000)),
+             ("resident_f64", dict(kernel="resident", check_every=1000)),
+             ("blocked_f64", dict(kernel="blocked", tile_rows=8, check_every=1000)),
+             ("f32_ir_resident", dict(kernel="resident", precision="f32_ir", inner_sweeps=4000,
+                                      check_every=4000)),
+             ("bf16rhs_ir_resident", dict(kernel="resident", precision="bf16rhs_ir",
+                                          inner_sweeps=1000, check_every=1000))]
     for name, kw in forms:
         u = torch.zeros((n + 2, n + 2), dtype=torch.float64, device="cuda")
-        rb.rbgs_solve(u, f, 8, 0.0, check_every=8, h=h, **{k: v for k, v in kw.items()
-                                                              if k != "inner_sweeps"})
+        warm = {k: v for k, v in kw.items() if k not in ("inner_sweeps", "check_every")}
+        rb.rbgs_solve(u, f, 8, 0.0, check_every=8, h=h, **warm)
         u.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        info = rb.rbgs_solve(u, f, 400000, tol, check_every=1000, h=h, **kw)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        dt, info = _timed_solve(torch, rb, u, f, max_sweeps=4_000_000, rel_tol=tol, h=h, **kw)
         out[name] = {"seconds": round(dt, 4), "sweeps": info["sweeps"],
                      "rel_residual": info["rel_residual"], "status": info["status"]}
         log(f"time-to-tol {name}: {dt:.3f} s, {info['sweeps']} sweeps, "
@@ -126,6 +135,97 @@ def time_to_tolerance(torch, rb, W, n=255, tol=1e-8):
     base = out["plain_f64"]["seconds"]
     for name, _ in forms[1:]:
         out[name]["speedup_vs_plain_f64"] = round(base / out[name]["seconds"], 3)
+    return out
+
+
+def learned_guess(torch, rb, tol=1e-8, seeds=2):
+    """The learned-guess workload: 511 x 511 GRF right-hand sides (held-out
+    seeds 10^6 + 20 + i), FP64 solve to rel <= tol from u = 0 (the judge)
+    against the same solve started from the shipped network's guess, kept
+    only if it wins the residual comparison after 500 sweeps of both starts
+    (inference and comparison sweeps included in the time); the literal
+    comparison of starting residuals is reported beside it."""
+    from paper_2607_01735_amd import learned
+    n = 511
+    net = learned.pretrained_net(rb)
+    ids = [learned.TEST_SEED0 + 20 + i for i in range(seeds)]
+    fs = learned.fields_on_device(torch, n, ids)
+    rows = []
+    for i, seed in enumerate(ids):
+        f = fs[i]
+        u = torch.zeros_like(f)
+        rb.rbgs_solve(u, f, 16, 0.0, check_every=16)  # warm-up
+        u.zero_()
+        dt0, base = _timed_solve(torch, rb, u, f, max_sweeps=2_000_000, rel_tol=tol,
+                                 check_every=2000)
+        row = {"seed": seed, "zero_start": {"seconds": round(dt0, 4), "sweeps": base["sweeps"]}}
+        for k in (500, 0):
+            u = torch.zeros_like(f)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            got = net.solve_learned(u, f, 2_000_000, tol, check_every=2000, compare_after=k)
+            torch.cuda.synchronize()
+            row[f"learned_k{k}"] = {"seconds": round(time.perf_counter() - t0, 4),
+                                    "sweeps": got["sweeps"], "used_guess": got["used_guess"],
+                                    "rel_residual": got["rel_residual"]}
+        log(f"learned seed {seed}: {row}")
+        rows.append(row)
+    z = sum(r["zero_start"]["seconds"] for r in rows)
+    out = {"workload": f"{n}x{n} GRF (length scale U[0.02,0.3]), held-out seeds {ids}, FP64, "
+                       f"rel<={tol:g}, network weights/unet_grf511_f4.npy", "per_seed": rows}
+    for k in (500, 0):
+        out[f"time_ratio_k{k}"] = round(sum(r[f"learned_k{k}"]["seconds"] for r in rows) / z, 4)
+        out[f"sweep_ratio_k{k}"] = round(sum(r[f"learned_k{k}"]["sweeps"] for r in rows) /
+                                         sum(r["zero_start"]["sweeps"] for r in rows), 4)
+    del fs
+    torch.cuda.empty_cache()
+    return out
+
+
+def batched_to_tolerance(torch, rb, W, count=16, tol=1e-8, chunk=4000):
+    """Many small grids to rel <= tol: `count` grids with sizes uniform on
+    {63, 127, 255} (seed 1), f i.i.d. N(0,1) (seed 1000+g), FP64, u0 = 0.
+    Batched: one graph-captured persistent launch of `chunk` sweeps for all
+    grids, then every grid's residual, until all are below tol.  Judge: each
+    grid solved alone with the plain FP64 kernel (residual every 1000
+    sweeps)."""
+    import numpy as np
+    rng = np.random.default_rng(1)
+    sizes = [int(x) for x in rng.choice([63, 127, 255], size=count)]
+    fs = [torch.from_numpy(W.normal_rhs(n, seed=1000 + g)).to("cuda") for g, n in enumerate(sizes)]
+    us = [torch.zeros_like(f) for f in fs]
+    plan = rb.BatchPlan(us, fs, chunk)
+    plan.launch()
+    plan.check()
+    for u in us:
+        u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while True:
+        plan.launch()
+        plan.check()
+        done += chunk
+        rels = [rb.rbgs_residual(u, f)[1] for u, f in zip(us, fs)]
+        if max(rels) <= tol or done >= 400_000:
+            break
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan.close()
+    out = {"workload": f"{count} grids, N in {{63,127,255}} seed 1, f~N(0,1), FP64, u0=0, "
+                       f"rel<={tol:g} for every grid", "sizes": sizes,
+           "batched": {"seconds": round(dt, 4), "sweeps": done, "max_rel": max(rels)}}
+    t_plain = 0.0
+    sweeps_plain = 0
+    for f in fs:
+        u = torch.zeros_like(f)
+        dt1, info = _timed_solve(torch, rb, u, f, max_sweeps=400_000, rel_tol=tol,
+                                 check_every=1000, kernel="plain")
+        t_plain += dt1
+        sweeps_plain = max(sweeps_plain, info["sweeps"])
+    out["plain_f64_one_by_one"] = {"seconds": round(t_plain, 4), "max_sweeps": sweeps_plain}
+    out["speedup_vs_plain_f64"] = round(t_plain / dt, 2)
+    log(f"batched to tolerance: {out}")
     return out
 
 
@@ -250,7 +350,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the refinement (16383^2) and batched (512 grids) workloads")
+                    help="skip the refinement (16383^2), batched and learned-guess workloads")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -336,6 +436,8 @@ def main():
     ttt = None if args.no_time_to_tol else time_to_tolerance(torch, rb, W)
     refine = None if args.no_extras else refinement_throughput(torch, rb, W)
     batched = None if args.no_extras else batched_throughput(torch, rb, W)
+    batched_tol = None if args.no_extras else batched_to_tolerance(torch, rb, W)
+    learned_511 = None if args.no_extras else learned_guess(torch, rb)
     probe = None if args.no_probe else stream_probe(torch, rb)
     if probe:
         log(f"STREAM probe: {probe}")
@@ -359,6 +461,8 @@ def main():
         "time_to_1e-8": ttt,
         "refinement_16383": refine,
         "batched_512": batched,
+        "batched_to_1e-8": batched_tol,
+        "learned_guess_511": learned_511,
         "stream_probe": probe,
         "cpu_baseline": base,
     }

@@ -66,13 +66,22 @@ typedef enum {
 } rbgs_dtype;
 
 typedef enum {
-    RBGS_KERNEL_AUTO = 0,    /* library choice                                  */
+    RBGS_KERNEL_AUTO = 0,    /* library choice, from measured time per sweep:
+                                PLAIN below 8 sweeps; else RESIDENT up to
+                                n = 384 (FP64) / 768 (FP32), PLAIN for FP32
+                                n < 1536, BLOCKED otherwise                    */
     RBGS_KERNEL_PLAIN = 1,   /* one kernel launch per half-sweep (Algorithm 1's
                                 barrier after every colour)                     */
-    RBGS_KERNEL_BLOCKED = 2  /* persistent, temporally blocked kernel: several
+    RBGS_KERNEL_BLOCKED = 2, /* persistent, temporally blocked kernel: several
                                 half-sweeps per pass over HBM, tiles ordered by
                                 per-tile progress flags instead of grid-wide
                                 barriers (the dependency idea of Algorithm 2)   */
+    RBGS_KERNEL_RESIDENT = 3 /* small grids (n <= 512 in FP64, n <= 1024 in
+                                FP32): Algorithm 2's stripes as co-resident
+                                workgroups that keep their rows in registers
+                                for all sweeps of the call and trade boundary
+                                rows with their two neighbours every 4 sweeps;
+                                RBGS_EUNSUPPORTED for larger n              */
 } rbgs_kernel;
 
 typedef enum {

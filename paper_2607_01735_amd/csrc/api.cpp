@@ -10,6 +10,7 @@
 #include "rbgs.h"
 #include "rbgs_internal.h"
 #include "rbgs_blocked.h"
+#include "rbgs_resident.h"
 
 using namespace rbgs;
 
@@ -95,6 +96,8 @@ struct Workspace {
     float* e2_black = nullptr;
     void* blocked = nullptr;  // persistent-kernel state (flags, ticket, error word)
     size_t blocked_bytes = 0;
+    void* resident = nullptr;  // resident-kernel state (error word, band flags, exchange rows)
+    size_t resident_bytes = 0;
     size_t total = 0;
 };
 
@@ -127,6 +130,8 @@ Workspace plan_workspace(const rbgs_grid* g, rbgs_dtype dt, bool ir, char* base)
     w.sums = static_cast<double*>(take(256));
     w.blocked_bytes = blocked_state_bytes(n, dt == RBGS_F64 ? 8 : 4);
     w.blocked = take(w.blocked_bytes);
+    w.resident_bytes = resident::state_bytes(n, es);
+    if (w.resident_bytes) w.resident = take(w.resident_bytes);
     if (ir) {
         w.pitch32 = split_pitch(n, 4);
         const size_t c32 = align256(size_t(n + 2) * size_t(w.pitch32) * 4);
@@ -153,7 +158,7 @@ int check_workspace(void* ws, size_t ws_bytes, size_t need) {
 
 int validate_sweep_opts(const rbgs_sweep_opts* o) {
     if (!o) return RBGS_OK;
-    if (o->kernel < RBGS_KERNEL_AUTO || o->kernel > RBGS_KERNEL_BLOCKED)
+    if (o->kernel < RBGS_KERNEL_AUTO || o->kernel > RBGS_KERNEL_RESIDENT)
         return fail(RBGS_EINVAL, "unknown kernel");
     if (o->fuse < 0 || o->tile_rows < 0 || o->tile_cols < 0 || o->rows_per_block < 0 ||
         o->debug_delay < 0 || o->debug_spin_limit < 0 || o->debug_stall_tile < 0)
@@ -163,11 +168,12 @@ int validate_sweep_opts(const rbgs_sweep_opts* o) {
     return validate_blocked_opts(o->fuse, o->tile_rows, o->tile_cols, &g_last_error);
 }
 
-// Half-sweeps on the split arrays already in the workspace.  *used_blocked
-// is set when the persistent kernel ran (its error word must be checked).
+// Half-sweeps on the split arrays already in the workspace.  *err_state is
+// set to the state of the persistent kernel that ran (blocked or resident),
+// whose error word must be checked.
 template <typename T>
 int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rbgs_sweep_opts* o,
-               hipStream_t s, int* launches, bool* used_blocked) {
+               hipStream_t s, int* launches, void** err_state) {
     const int n = g->n;
     const T h2 = T(g->h * g->h);
     T* ur = static_cast<T*>(w.u_red);
@@ -175,7 +181,7 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
     const T* fr = static_cast<const T*>(w.f_red);
     const T* fb = static_cast<const T*>(w.f_black);
     int kernel = o ? o->kernel : RBGS_KERNEL_AUTO;
-    if (kernel == RBGS_KERNEL_AUTO) kernel = auto_kernel(n, sizeof(T));
+    if (kernel == RBGS_KERNEL_AUTO) kernel = auto_kernel(n, sizeof(T), nsweeps);
     *launches = 0;
     if (kernel == RBGS_KERNEL_BLOCKED) {
         BlockedParams bp = blocked_params(n, sizeof(T), o);
@@ -184,7 +190,23 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
         HIP_TRY(run_blocked<T>(bred, bblack, fr, fb, n, w.pitch, h2, nsweeps, bp, w.blocked,
                                w.blocked_bytes, s, launches),
                 "blocked sweep");
-        *used_blocked = true;
+        *err_state = w.blocked;
+        return RBGS_OK;
+    }
+    if (kernel == RBGS_KERNEL_RESIDENT) {
+        if (n > resident::max_n<T>() || !w.resident)
+            return fail(RBGS_EUNSUPPORTED, "the resident kernel takes n <= " +
+                                               std::to_string(resident::max_n<T>()) +
+                                               " for this precision");
+        if (resident::bands_for(n) > resident::max_resident_bands<T>(n))
+            return fail(RBGS_EUNSUPPORTED, "the resident kernel's bands do not fit on the device");
+        const int spin = (o && o->debug_spin_limit > 0) ? o->debug_spin_limit : (1 << 22);
+        HIP_TRY(resident::run<T>(ur, ub, fr, fb, n, w.pitch, h2, nsweeps, spin,
+                                 o ? o->debug_delay : 0, o ? o->debug_stall_tile : 0, w.resident,
+                                 s),
+                "resident sweep");
+        *launches = nsweeps > 0 ? 1 : 0;
+        *err_state = w.resident;
         return RBGS_OK;
     }
     const int rows = o ? o->rows_per_block : 0;
@@ -197,9 +219,9 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
 }
 
 int run_sweeps_dt(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w, int32_t nsweeps,
-                  const rbgs_sweep_opts* o, hipStream_t s, int* launches, bool* used_blocked) {
-    return dt == RBGS_F64 ? run_sweeps<double>(g, w, nsweeps, o, s, launches, used_blocked)
-                          : run_sweeps<float>(g, w, nsweeps, o, s, launches, used_blocked);
+                  const rbgs_sweep_opts* o, hipStream_t s, int* launches, void** err_state) {
+    return dt == RBGS_F64 ? run_sweeps<double>(g, w, nsweeps, o, s, launches, err_state)
+                          : run_sweeps<float>(g, w, nsweeps, o, s, launches, err_state);
 }
 
 // Reads the two device sums, synchronising the stream.
@@ -350,8 +372,8 @@ int rbgs_sweep(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f, int32_
     HIP_TRY(launch_pack(f, g->ld, w.f_red, w.f_black, g->n, w.pitch, es, s), "pack f");
     HIP_TRY(tm.mark(1, s), "event record");
     int launches = 0;
-    bool used_blocked = false;
-    if ((rc = run_sweeps_dt(dt, g, w, nsweeps, opts, s, &launches, &used_blocked))) return rc;
+    void* err_state = nullptr;
+    if ((rc = run_sweeps_dt(dt, g, w, nsweeps, opts, s, &launches, &err_state))) return rc;
     HIP_TRY(tm.mark(2, s), "event record");
     HIP_TRY(launch_unpack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, es, s), "unpack u");
     HIP_TRY(tm.mark(3, s), "event record");
@@ -363,7 +385,7 @@ int rbgs_sweep(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f, int32_
         HIP_TRY(hipEventElapsedTime(&t.unpack_ms, tm.ev[2], tm.ev[3]), "event time");
         *opts->timing = t;
     }
-    return used_blocked ? blocked_check_error(w.blocked, s, &g_last_error) : RBGS_OK;
+    return err_state ? blocked_check_error(err_state, s, &g_last_error) : RBGS_OK;
 }
 
 int rbgs_residual(const rbgs_grid* g, rbgs_dtype dt, const void* u, const void* f,
@@ -434,7 +456,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
 
     rbgs_solve_info out{0, 0, 0.0, 0.0, RBGS_OK};
     int launches = 0;
-    bool used_blocked = false;
+    void* err_state = nullptr;
     rbgs_sweep_opts sw = o->sweep;
     sw.timing = nullptr;
     if (!ir) {
@@ -442,7 +464,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         int32_t done = 0;
         if (o->rel_tol <= 0.0) {
             HIP_TRY(gt.begin(s), "event record");
-            if ((rc = run_sweeps_dt(dt, g, w, o->max_sweeps, &sw, s, &launches, &used_blocked))) return rc;
+            if ((rc = run_sweeps_dt(dt, g, w, o->max_sweeps, &sw, s, &launches, &err_state))) return rc;
             HIP_TRY(gt.end(s), "event record");
             HIP_TRY(gt.collect(launches), "event time");
             done = o->max_sweeps;
@@ -455,13 +477,13 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
                 int32_t k = o->max_sweeps - done < o->check_every ? o->max_sweeps - done
                                                                   : o->check_every;
                 HIP_TRY(gt.begin(s), "event record");
-                if ((rc = run_sweeps_dt(dt, g, w, k, &sw, s, &launches, &used_blocked))) return rc;
+                if ((rc = run_sweeps_dt(dt, g, w, k, &sw, s, &launches, &err_state))) return rc;
                 HIP_TRY(gt.end(s), "event record");
                 HIP_TRY(gt.collect(launches), "event time");
                 done += k;
                 if ((rc = split_residual_dt(dt, g, w, s))) return rc;
                 if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
-                if (used_blocked && (rc = blocked_check_error(w.blocked, s, &g_last_error)))
+                if (err_state && (rc = blocked_check_error(err_state, s, &g_last_error)))
                     return rc;
             }
         }
@@ -495,7 +517,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
             HIP_TRY(launch_zero(w.e_red, c32, s), "zero correction");
             HIP_TRY(launch_zero(w.e_black, c32, s), "zero correction");
             HIP_TRY(gt.begin(s), "event record");
-            if ((rc = run_sweeps<float>(&gi, inner_w, k, &sw, s, &launches, &used_blocked))) return rc;
+            if ((rc = run_sweeps<float>(&gi, inner_w, k, &sw, s, &launches, &err_state))) return rc;
             HIP_TRY(gt.end(s), "event record");
             HIP_TRY(gt.collect(launches), "event time");
             HIP_TRY(launch_add_correction(static_cast<double*>(w.u_red),
@@ -506,7 +528,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
             ++outer;
             if ((rc = split_residual<double>(g, w, s, w.r_red, w.r_black, bf16))) return rc;
             if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
-            if (used_blocked && (rc = blocked_check_error(w.blocked, s, &g_last_error)))
+            if (err_state && (rc = blocked_check_error(err_state, s, &g_last_error)))
                 return rc;
         }
         out.sweeps = done;
@@ -526,7 +548,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         HIP_TRY(hipEventElapsedTime(&gt.acc.unpack_ms, gt.t.ev[0], gt.t.ev[3]), "event time");
         *o->sweep.timing = gt.acc;
     }
-    if (used_blocked && (rc = blocked_check_error(w.blocked, s, &g_last_error))) out.status = rc;
+    if (err_state && (rc = blocked_check_error(err_state, s, &g_last_error))) out.status = rc;
     if (info) *info = out;
     if (out.status == RBGS_ENONFINITE) g_last_error = "residual is not finite";
     if (out.status == RBGS_ENOCONV) g_last_error = "tolerance not reached";

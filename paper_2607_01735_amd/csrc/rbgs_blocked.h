@@ -49,6 +49,18 @@ inline int default_rows(int n, int L) {
     return r < L ? L : r;
 }
 
+// Tile height for one grid on its own: small grids need many tiles to keep
+// waves busy (about 64 row tiles up to n = 2047, measured best on MI355X
+// at 255..2047), large ones need tall tiles for fewer halo rows (256 at
+// 8191).  The tile also has to hold the L halo rows.
+inline int single_grid_rows(int n, int L) {
+    const int64_t m = int64_t(n) + 1;
+    int64_t want = m <= 2048 ? m / 64 : m / 32;
+    int r = kMinRows;
+    while (r * 2 <= want && r < 256) r <<= 1;
+    return r < L ? L : r;
+}
+
 // Resident one-wave workgroups per CU for a persistent kernel, and CU count.
 hipError_t persistent_occupancy(const void* kernel, int* per_cu, int* cus);
 
@@ -66,7 +78,7 @@ size_t blocked_state_bytes(int n, int elem_bytes);
 // Checks fuse / tile options; writes a message to *why on failure.
 int validate_blocked_opts(int fuse, int tile_rows, int tile_cols, std::string* why);
 // Kernel the library picks for RBGS_KERNEL_AUTO.
-int auto_kernel(int n, size_t elem_bytes);
+int auto_kernel(int n, size_t elem_bytes, int nsweeps);
 BlockedParams blocked_params(int n, size_t elem_bytes, const rbgs_sweep_opts* o);
 // nsweeps sweeps of the split iterate in buffer 0 (buf_red[0], buf_black[0])
 // with the persistent kernel; buffer 1 is scratch of the same size.  The

@@ -116,12 +116,23 @@ int validate_blocked_opts(int fuse, int tile_rows, int tile_cols, std::string* w
     return RBGS_OK;
 }
 
-int auto_kernel(int n, size_t) { return n >= 1024 ? RBGS_KERNEL_BLOCKED : RBGS_KERNEL_PLAIN; }
+// Kernel choice measured on MI355X (time per sweep over thousands of
+// sweeps): the resident band kernel up to n = 384 (FP64) or 768 (FP32),
+// where it holds the grid in registers; above that the persistent blocked
+// kernel, except FP32 below 1536, where it has too few tiles and the plain
+// kernel is as fast.  A handful of sweeps does not pay for a persistent
+// launch.
+int auto_kernel(int n, size_t elem_bytes, int nsweeps) {
+    if (nsweeps < 8) return RBGS_KERNEL_PLAIN;
+    if (elem_bytes == 8) return n <= 384 ? RBGS_KERNEL_RESIDENT : RBGS_KERNEL_BLOCKED;
+    if (n <= 768) return RBGS_KERNEL_RESIDENT;
+    return n < 1536 ? RBGS_KERNEL_PLAIN : RBGS_KERNEL_BLOCKED;
+}
 
 BlockedParams blocked_params(int n, size_t, const rbgs_sweep_opts* o) {
     BlockedParams bp;
     bp.fuse = (o && o->fuse > 0) ? o->fuse : kMaxFuse;
-    bp.tile_rows = (o && o->tile_rows > 0) ? o->tile_rows : default_rows(n, 2 * bp.fuse);
+    bp.tile_rows = (o && o->tile_rows > 0) ? o->tile_rows : single_grid_rows(n, 2 * bp.fuse);
     if (bp.tile_rows < 2 * bp.fuse) bp.tile_rows = 2 * bp.fuse;  // halo rows must fit one strip
     bp.delay = o ? o->debug_delay : 0;
     bp.spin_limit = (o && o->debug_spin_limit > 0) ? o->debug_spin_limit : kDefaultSpinLimit;
@@ -229,7 +240,7 @@ int blocked_check_error(void* state, hipStream_t s, std::string* why) {
         return RBGS_EHIP;
     }
     if (err != 0) {
-        *why = "a tile dependency wait in the persistent kernel timed out";
+        *why = "a dependency wait in a persistent kernel timed out";
         return RBGS_ETIMEOUT;
     }
     return RBGS_OK;

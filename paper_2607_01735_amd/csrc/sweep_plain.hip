@@ -9,7 +9,7 @@
 // colour is read from HBM about once ((R+2)/R times), the own right-hand side
 // once, and the own colour written once: 3 words per point update.  The
 // horizontal neighbour that lies outside the thread's vector (q-1 or q+V)
-// is re-read from the same, just-loaded cache lines.
+// comes from the neighbouring lane through DPP.
 //
 // Term order (no FMA contraction, -ffp-contract=off):
 //   s = O[i+1][q] + O[i-1][q]; s += right; s += left; s -= h2*f; u = 0.25*s
@@ -18,6 +18,25 @@
 
 namespace rbgs {
 namespace {
+
+// Whole-wave DPP shifts: lane i receives lane i+1's value (wave_shl:1) or
+// lane i-1's (wave_shr:1); a lane with no source keeps its own value.
+template <int CTRL>
+__device__ __forceinline__ int dpp_int(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_val(double v) {
+    return __hiloint2double(dpp_int<CTRL>(__double2hiint(v)), dpp_int<CTRL>(__double2loint(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_val(float v) {
+    return __int_as_float(dpp_int<CTRL>(__float_as_int(v)));
+}
+template <typename T>
+__device__ __forceinline__ T lane_from_next(T v) { return dpp_val<0x130>(v); }
+template <typename T>
+__device__ __forceinline__ T lane_from_prev(T v) { return dpp_val<0x138>(v); }
 
 template <typename T, int V>
 struct alignas(sizeof(T) * V) Pack {
@@ -60,7 +79,19 @@ __device__ __forceinline__ void update_row(T* __restrict__ self_row, const T* __
                                            const Pack<T, V>& dn, const Pack<T, V>& fc, T h2,
                                            int64_t q0, int n) {
     // P = 1: right neighbour of q is q+1, left is q; P = 0: right q, left q-1.
-    T extra = P ? mid_row[q0 + V] : mid_row[q0 - 1];
+    // The value outside the thread's vector is the neighbouring lane's first
+    // (or last) element, taken through a DPP whole-wave shift; only the lanes
+    // at a wave edge, or next to the last active lane, read it from memory.
+    // This halves the load instructions the texture units see per row.
+    const int lane = threadIdx.x & 63;
+    T extra;
+    if constexpr (P) {
+        extra = lane_from_next(mid.v[0]);
+        if (lane == 63 || q0 + V > (n >> 1)) extra = mid_row[q0 + V];
+    } else {
+        extra = lane_from_prev(mid.v[V - 1]);
+        if (lane == 0) extra = mid_row[q0 - 1];
+    }
     Pack<T, V> out;
 #pragma unroll
     for (int e = 0; e < V; ++e) {

@@ -30,6 +30,18 @@ if ROOT not in sys.path:
 
 TEST_SEED0 = 10 ** 6
 
+# Parameters trained by this module for 511 x 511 GRF problems (coarsening
+# factor 4); weights/unet_grf511_f4.json records how.
+PRETRAINED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                          "unet_grf511_f4.npy")
+
+
+def pretrained_net(rb, batch=1, path=PRETRAINED):
+    """The library's U-Net for 511 x 511 grids with the shipped parameters."""
+    net = rb.UNet(511, batch, factor=4)
+    net.set_params(np.load(path))
+    return net
+
 # (name, input channels, output channels) of the library's conv layers, in
 # its parameter order; the 1x1 head (16 -> 1) follows them.
 LAYERS = (("enc0.0", 1, 16), ("enc0.1", 16, 16), ("enc1.0", 16, 32), ("enc1.1", 32, 32),

@@ -27,10 +27,11 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, EHIP, ENOCONV, ETIMEOUT, ENONFINITE, EUNSUPPORTED, EWORKSPACE = 0, -1, -2, -3, -4, -5, -6, -8
 F64, F32 = 0, 1
-KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BLOCKED = 0, 1, 2
+KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BLOCKED, KERNEL_RESIDENT = 0, 1, 2, 3
 PREC_F64, PREC_F32_IR, PREC_BF16RHS_IR = 0, 1, 2
 
-_KERNELS = {"auto": KERNEL_AUTO, "plain": KERNEL_PLAIN, "blocked": KERNEL_BLOCKED}
+_KERNELS = {"auto": KERNEL_AUTO, "plain": KERNEL_PLAIN, "blocked": KERNEL_BLOCKED,
+            "resident": KERNEL_RESIDENT}
 _PRECISIONS = {"f64": PREC_F64, "f32_ir": PREC_F32_IR, "bf16rhs_ir": PREC_BF16RHS_IR}
 
 
