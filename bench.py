@@ -12,9 +12,12 @@ size); the plain one-launch-per-half-sweep kernel is timed beside it.
 Output: one JSON line with GLUP/s (lattice point updates per second,
 N^2 * sweeps / time), the dominant kernel's roofline (algorithmic bytes per
 launch over its measured average duration, against 8 TB/s HBM), the plain
-kernel's figures, time to a relative residual of 1e-8 on the 255 x 255 sine
-problem for the plain FP64, blocked FP64 and FP32-refinement solves, the
-STREAM probe bandwidth, and the CPU oracle timed on a bounded sample as
+kernel's figures, and the comparisons of time to a relative residual of
+1e-8 against the plain FP64 sweep: the 255 x 255 sine problem for the
+resident, blocked and mixed-precision solves, 16 small grids solved as one
+batch, and 511 x 511 GRF problems with the learned initial guess; beside
+them the 16383^2 refinement throughput, the 512-grid batch throughput, the
+STREAM probe bandwidth and the CPU oracle timed on a bounded sample as
 baseline.  Progress goes to stderr.
 """
 import argparse
