@@ -120,7 +120,7 @@ def time_to_tolerance(torch, rb, W, n=255, tol=1e-8):
     out = {"problem": f"{n}x{n} FP64 sine, u0=0, rel<={tol:g}"}
     forms = [("plain_f64", dict(kernel="plain", check_every=1000)),
              ("resident_f64", dict(kernel="resident", check_every=1000)),
-             ("blocked_f64", dict(kernel="blocked", tile_rows=8, check_every=1000)),
+             ("blocked_f64", dict(kernel="blocked", fuse=4, tile_rows=8, check_every=1000)),
              ("f32_ir_resident", dict(kernel="resident", precision="f32_ir", inner_sweeps=4000,
                                       check_every=4000)),
              ("bf16rhs_ir_resident", dict(kernel="resident", precision="bf16rhs_ir",
@@ -389,32 +389,36 @@ def main():
                 f"sweep_ms={info['timing']['sweep_ms']:.2f}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sweep_ms, launches = 0.0, 0
+        acc = {"sweep_ms": 0.0, "sweep_launches": 0, "persistent_ms": 0.0,
+               "persistent_launches": 0, "passes": 0, "fuse": 0}
         for _ in range(steps):
-            info = step()
-            sweep_ms += info["timing"]["sweep_ms"]
-            launches += info["timing"]["sweep_launches"]
+            t = step()["timing"]
+            for key in acc:
+                acc[key] = t[key] if key == "fuse" else acc[key] + t[key]
         torch.cuda.synchronize()
         ms_step = (time.perf_counter() - t0) * 1e3 / steps
         glups = n * n * sweeps / (ms_step * 1e-3) / 1e9
-        log(f"[{kernel}] {steps} steps: {ms_step:.3f} ms/step, {glups:.1f} GLUP/s")
-        return ms_step, glups, sweep_ms / max(launches, 1), launches / steps
+        log(f"[{kernel}] {steps} steps: {ms_step:.3f} ms/step, {glups:.1f} GLUP/s; timing {acc}")
+        return ms_step, glups, acc
 
-    ms_per_step, glups, avg_launch_ms, launches_per_step = run_steps(args.kernel, args.warmup,
-                                                                     args.steps)
-    # the plain kernel launches twice per sweep; the persistent one once per step
-    kernel_used = "plain" if launches_per_step >= 2 * sweeps else "blocked"
-    if kernel_used == "blocked":
-        # One persistent launch runs all 50 passes of 4 fused sweeps; per pass
-        # the algorithmic traffic is one read of u and f and one write of u,
-        # 3 words per point (the launch time includes the ring copy into the
-        # second buffer).
-        fuse = 4
-        per_launch_bytes = BYTES_PER_LUP["f64"] * n * n * (sweeps // fuse)
+    ms_per_step, glups, acc = run_steps(args.kernel, args.warmup, args.steps)
+    if acc["persistent_launches"] > 0:
+        # The persistent blocked kernel: each launch runs `passes` passes of
+        # `fuse` fused sweeps; per pass the algorithmic traffic is one read of
+        # u and f and one write of u, 3 words per point.  Its duration comes
+        # from HIP events around the persistent launches alone (remainder
+        # sweeps and the ring copy into the second buffer are outside).
+        kernel_used, fuse = "blocked", acc["fuse"]
+        launches = acc["persistent_launches"]
+        avg_launch_ms = acc["persistent_ms"] / launches
+        per_launch_bytes = BYTES_PER_LUP["f64"] * n * n * acc["passes"] / launches
         bytes_per_lup = BYTES_PER_LUP["f64"] / fuse
-        kname, traffic_key = "k_blocked<double,2,8> (persistent, fuse 4)", "blocked_f64"
+        kname = f"k_blocked<double,2,{2 * fuse}> (persistent, fuse {fuse})"
+        traffic_key = "blocked_f64"
     else:
         # One launch updates one colour: half the points, 3 words each.
+        kernel_used, fuse = "plain", 0
+        avg_launch_ms = acc["sweep_ms"] / max(acc["sweep_launches"], 1)
         per_launch_bytes = BYTES_PER_LUP["f64"] * n * n / 2.0
         bytes_per_lup = BYTES_PER_LUP["f64"]
         kname, traffic_key = "k_half_sweep<double,2>", "half_sweep_f64"
@@ -426,7 +430,8 @@ def main():
                 "bytes_per_launch": per_launch_bytes}
     plain = None
     if kernel_used != "plain" and not args.no_plain:
-        p_ms, p_glups, p_launch_ms, _ = run_steps("plain", 1, max(2, args.steps // 3))
+        p_ms, p_glups, p_acc = run_steps("plain", 1, max(2, args.steps // 3))
+        p_launch_ms = p_acc["sweep_ms"] / max(p_acc["sweep_launches"], 1)
         p_bytes = BYTES_PER_LUP["f64"] * n * n / 2.0
         p_ach = p_bytes / (p_launch_ms * 1e-3) / 1e9
         plain = {"value": round(p_glups, 2), "unit": "GLUP/s", "ms_per_step": round(p_ms, 3),
@@ -456,7 +461,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{n}x{n} interior FP64, h=1/{n + 1}, zero Dirichlet, "
                                f"f~U[-1,1) seed 0, u0=0, {sweeps} sweeps per step",
-                   "n": n, "sweeps": sweeps, "kernel": kernel_used},
+                   "n": n, "sweeps": sweeps, "kernel": kernel_used, "fuse": fuse},
         "hbm_gbs_algorithmic": round(glups * bytes_per_lup, 1),
         "bytes_per_lup_algorithmic": bytes_per_lup,
         "roofline": roofline,

@@ -168,12 +168,89 @@ int validate_sweep_opts(const rbgs_sweep_opts* o) {
     return validate_blocked_opts(o->fuse, o->tile_rows, o->tile_cols, &g_last_error);
 }
 
+struct EventTimer {
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool on = false;
+    hipError_t init(bool enable) {
+        on = enable;
+        if (!on) return hipSuccess;
+        for (auto& e : ev) {
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
+    hipError_t mark(int k, hipStream_t s) { return on ? hipEventRecord(ev[k], s) : hipSuccess; }
+    ~EventTimer() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// Times the persistent launches alone (the blocked kernel's passes or the
+// resident kernel), accumulated over the sweep groups of a call.
+struct PersistentTimer {
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool on = false, armed = false;
+    float ms = 0.f;
+    int launches = 0, passes = 0, fuse = 0;
+    hipError_t init(bool enable) {
+        on = enable;
+        if (!on) return hipSuccess;
+        for (auto& e : ev) {
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
+    // after a group whose events were recorded: add their interval
+    hipError_t collect() {
+        if (!on || !armed) return hipSuccess;
+        armed = false;
+        hipError_t e = hipEventSynchronize(ev[1]);
+        if (e != hipSuccess) return e;
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, ev[0], ev[1]);
+        ms += t;
+        return e;
+    }
+    void fill(rbgs_timing* t) const {
+        t->persistent_ms = ms;
+        t->persistent_launches = launches;
+        t->passes = passes;
+        t->fuse = fuse;
+    }
+    ~PersistentTimer() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// Accumulates the time of sweep groups inside a solve (events on the stream;
+// every group is followed by a synchronising residual fetch).
+struct GroupTimer {
+    EventTimer t;
+    rbgs_timing acc{0.f, 0.f, 0.f, 0};
+    hipError_t begin(hipStream_t s) { return t.mark(1, s); }
+    hipError_t end(hipStream_t s) { return t.mark(2, s); }
+    hipError_t collect(int launches) {
+        if (!t.on) return hipSuccess;
+        hipError_t e = hipEventSynchronize(t.ev[2]);
+        if (e != hipSuccess) return e;
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, t.ev[1], t.ev[2]);
+        acc.sweep_ms += ms;
+        acc.sweep_launches += launches;
+        return e;
+    }
+};
+
 // Half-sweeps on the split arrays already in the workspace.  *err_state is
 // set to the state of the persistent kernel that ran (blocked or resident),
 // whose error word must be checked.
 template <typename T>
 int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rbgs_sweep_opts* o,
-               hipStream_t s, int* launches, void** err_state) {
+               hipStream_t s, int* launches, void** err_state, PersistentTimer* pt) {
     const int n = g->n;
     const T h2 = T(g->h * g->h);
     T* ur = static_cast<T*>(w.u_red);
@@ -187,9 +264,18 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
         BlockedParams bp = blocked_params(n, sizeof(T), o);
         T* const bred[2] = {ur, static_cast<T*>(w.u2_red)};
         T* const bblack[2] = {ub, static_cast<T*>(w.u2_black)};
+        const bool timed = pt && pt->on;
+        int plaunches = 0, passes = 0;
         HIP_TRY(run_blocked<T>(bred, bblack, fr, fb, n, w.pitch, h2, nsweeps, bp, w.blocked,
-                               w.blocked_bytes, s, launches),
+                               w.blocked_bytes, s, launches, timed ? pt->ev[0] : nullptr,
+                               timed ? pt->ev[1] : nullptr, &plaunches, &passes),
                 "blocked sweep");
+        if (timed && plaunches > 0) {
+            pt->armed = true;
+            pt->launches += plaunches;
+            pt->passes += passes;
+            pt->fuse = bp.fuse;
+        }
         *err_state = w.blocked;
         return RBGS_OK;
     }
@@ -201,10 +287,17 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
         if (resident::bands_for(n) > resident::max_resident_bands<T>(n))
             return fail(RBGS_EUNSUPPORTED, "the resident kernel's bands do not fit on the device");
         const int spin = (o && o->debug_spin_limit > 0) ? o->debug_spin_limit : (1 << 22);
+        const bool timed = pt && pt->on && nsweeps > 0;
+        if (timed) HIP_TRY(hipEventRecord(pt->ev[0], s), "event record");
         HIP_TRY(resident::run<T>(ur, ub, fr, fb, n, w.pitch, h2, nsweeps, spin,
                                  o ? o->debug_delay : 0, o ? o->debug_stall_tile : 0, w.resident,
                                  s),
                 "resident sweep");
+        if (timed) {
+            HIP_TRY(hipEventRecord(pt->ev[1], s), "event record");
+            pt->armed = true;
+            pt->launches += 1;
+        }
         *launches = nsweeps > 0 ? 1 : 0;
         *err_state = w.resident;
         return RBGS_OK;
@@ -219,9 +312,10 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
 }
 
 int run_sweeps_dt(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w, int32_t nsweeps,
-                  const rbgs_sweep_opts* o, hipStream_t s, int* launches, void** err_state) {
-    return dt == RBGS_F64 ? run_sweeps<double>(g, w, nsweeps, o, s, launches, err_state)
-                          : run_sweeps<float>(g, w, nsweeps, o, s, launches, err_state);
+                  const rbgs_sweep_opts* o, hipStream_t s, int* launches, void** err_state,
+                  PersistentTimer* pt) {
+    return dt == RBGS_F64 ? run_sweeps<double>(g, w, nsweeps, o, s, launches, err_state, pt)
+                          : run_sweeps<float>(g, w, nsweeps, o, s, launches, err_state, pt);
 }
 
 // Reads the two device sums, synchronising the stream.
@@ -254,43 +348,6 @@ int split_residual_dt(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w, hip
                           : split_residual<float>(g, w, s, nullptr, nullptr, 0);
 }
 
-struct EventTimer {
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    bool on = false;
-    hipError_t init(bool enable) {
-        on = enable;
-        if (!on) return hipSuccess;
-        for (auto& e : ev) {
-            hipError_t r = hipEventCreate(&e);
-            if (r != hipSuccess) return r;
-        }
-        return hipSuccess;
-    }
-    hipError_t mark(int k, hipStream_t s) { return on ? hipEventRecord(ev[k], s) : hipSuccess; }
-    ~EventTimer() {
-        for (auto& e : ev)
-            if (e) (void)hipEventDestroy(e);
-    }
-};
-
-// Accumulates the time of sweep groups inside a solve (events on the stream;
-// every group is followed by a synchronising residual fetch).
-struct GroupTimer {
-    EventTimer t;
-    rbgs_timing acc{0.f, 0.f, 0.f, 0};
-    hipError_t begin(hipStream_t s) { return t.mark(1, s); }
-    hipError_t end(hipStream_t s) { return t.mark(2, s); }
-    hipError_t collect(int launches) {
-        if (!t.on) return hipSuccess;
-        hipError_t e = hipEventSynchronize(t.ev[2]);
-        if (e != hipSuccess) return e;
-        float ms = 0.f;
-        e = hipEventElapsedTime(&ms, t.ev[1], t.ev[2]);
-        acc.sweep_ms += ms;
-        acc.sweep_launches += launches;
-        return e;
-    }
-};
 
 // Shared argument checks of the grid transfers: coarse/fine sizes related by
 // n_f = 2 n_c + 1, strides covering a grid, and device ranges that hold all
@@ -367,13 +424,15 @@ int rbgs_sweep(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f, int32_
     const int es = int(elem_size(dt));
     EventTimer tm;
     HIP_TRY(tm.init(opts && opts->timing), "event create");
+    PersistentTimer pt;
+    HIP_TRY(pt.init(opts && opts->timing), "event create");
     HIP_TRY(tm.mark(0, s), "event record");
     HIP_TRY(launch_pack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, es, s), "pack u");
     HIP_TRY(launch_pack(f, g->ld, w.f_red, w.f_black, g->n, w.pitch, es, s), "pack f");
     HIP_TRY(tm.mark(1, s), "event record");
     int launches = 0;
     void* err_state = nullptr;
-    if ((rc = run_sweeps_dt(dt, g, w, nsweeps, opts, s, &launches, &err_state))) return rc;
+    if ((rc = run_sweeps_dt(dt, g, w, nsweeps, opts, s, &launches, &err_state, &pt))) return rc;
     HIP_TRY(tm.mark(2, s), "event record");
     HIP_TRY(launch_unpack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, es, s), "unpack u");
     HIP_TRY(tm.mark(3, s), "event record");
@@ -383,6 +442,8 @@ int rbgs_sweep(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f, int32_
         HIP_TRY(hipEventElapsedTime(&t.pack_ms, tm.ev[0], tm.ev[1]), "event time");
         HIP_TRY(hipEventElapsedTime(&t.sweep_ms, tm.ev[1], tm.ev[2]), "event time");
         HIP_TRY(hipEventElapsedTime(&t.unpack_ms, tm.ev[2], tm.ev[3]), "event time");
+        HIP_TRY(pt.collect(), "event time");
+        pt.fill(&t);
         *opts->timing = t;
     }
     return err_state ? blocked_check_error(err_state, s, &g_last_error) : RBGS_OK;
@@ -445,6 +506,8 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
     const int es = int(elem_size(dt));
     GroupTimer gt;
     HIP_TRY(gt.t.init(o->sweep.timing != nullptr), "event create");
+    PersistentTimer pt;
+    HIP_TRY(pt.init(o->sweep.timing != nullptr), "event create");
     HIP_TRY(gt.t.mark(0, s), "event record");
     HIP_TRY(launch_pack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, es, s), "pack u");
     HIP_TRY(launch_pack(f, g->ld, w.f_red, w.f_black, g->n, w.pitch, es, s), "pack f");
@@ -464,9 +527,10 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         int32_t done = 0;
         if (o->rel_tol <= 0.0) {
             HIP_TRY(gt.begin(s), "event record");
-            if ((rc = run_sweeps_dt(dt, g, w, o->max_sweeps, &sw, s, &launches, &err_state))) return rc;
+            if ((rc = run_sweeps_dt(dt, g, w, o->max_sweeps, &sw, s, &launches, &err_state, &pt))) return rc;
             HIP_TRY(gt.end(s), "event record");
             HIP_TRY(gt.collect(launches), "event time");
+            HIP_TRY(pt.collect(), "event time");
             done = o->max_sweeps;
             if ((rc = split_residual_dt(dt, g, w, s))) return rc;
             if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
@@ -477,9 +541,10 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
                 int32_t k = o->max_sweeps - done < o->check_every ? o->max_sweeps - done
                                                                   : o->check_every;
                 HIP_TRY(gt.begin(s), "event record");
-                if ((rc = run_sweeps_dt(dt, g, w, k, &sw, s, &launches, &err_state))) return rc;
+                if ((rc = run_sweeps_dt(dt, g, w, k, &sw, s, &launches, &err_state, &pt))) return rc;
                 HIP_TRY(gt.end(s), "event record");
                 HIP_TRY(gt.collect(launches), "event time");
+                HIP_TRY(pt.collect(), "event time");
                 done += k;
                 if ((rc = split_residual_dt(dt, g, w, s))) return rc;
                 if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
@@ -517,9 +582,10 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
             HIP_TRY(launch_zero(w.e_red, c32, s), "zero correction");
             HIP_TRY(launch_zero(w.e_black, c32, s), "zero correction");
             HIP_TRY(gt.begin(s), "event record");
-            if ((rc = run_sweeps<float>(&gi, inner_w, k, &sw, s, &launches, &err_state))) return rc;
+            if ((rc = run_sweeps<float>(&gi, inner_w, k, &sw, s, &launches, &err_state, &pt))) return rc;
             HIP_TRY(gt.end(s), "event record");
             HIP_TRY(gt.collect(launches), "event time");
+            HIP_TRY(pt.collect(), "event time");
             HIP_TRY(launch_add_correction(static_cast<double*>(w.u_red),
                                           static_cast<double*>(w.u_black), w.pitch, w.e_red,
                                           w.e_black, w.pitch32, g->n, s),
@@ -546,6 +612,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
     HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
     if (gt.t.on) {
         HIP_TRY(hipEventElapsedTime(&gt.acc.unpack_ms, gt.t.ev[0], gt.t.ev[3]), "event time");
+        pt.fill(&gt.acc);
         *o->sweep.timing = gt.acc;
     }
     if (err_state && (rc = blocked_check_error(err_state, s, &g_last_error))) out.status = rc;

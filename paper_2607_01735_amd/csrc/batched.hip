@@ -282,7 +282,10 @@ hipError_t launch_batched_by_fuse(int fuse, const GridDesc<T>* d, const int* map
         case 1: return launch_batched_k<T, V, 2>(d, map, tiles, qu, s);
         case 2: return launch_batched_k<T, V, 4>(d, map, tiles, qu, s);
         case 3: return launch_batched_k<T, V, 6>(d, map, tiles, qu, s);
-        default: return launch_batched_k<T, V, 8>(d, map, tiles, qu, s);
+        case 4: return launch_batched_k<T, V, 8>(d, map, tiles, qu, s);
+        case 5: return launch_batched_k<T, V, 10>(d, map, tiles, qu, s);
+        case 6: return launch_batched_k<T, V, 12>(d, map, tiles, qu, s);
+        default: return launch_batched_k<T, V, 14>(d, map, tiles, qu, s);
     }
 }
 
@@ -355,7 +358,7 @@ int validate_batch(int32_t count, const rbgs_grid* grids, int dt, void* const* u
     if (o) {
         if (o->kernel != RBGS_KERNEL_AUTO && o->kernel != RBGS_KERNEL_BLOCKED)
             return bfail(RBGS_EINVAL, "batched sweeps use the persistent kernel");
-        if (o->fuse < 0 || o->fuse > kMaxFuse) return bfail(RBGS_EINVAL, "fuse must be in [0, 4]");
+        if (o->fuse < 0 || o->fuse > kMaxFuse) return bfail(RBGS_EINVAL, "fuse must be in [0, 7]");
         if (o->tile_rows != 0 && o->tile_rows < kMinRows)
             return bfail(RBGS_EINVAL, "tile_rows must be >= 8 (0 = default)");
         if (o->tile_cols != 0) return bfail(RBGS_EINVAL, "tile_cols must be 0");
@@ -417,7 +420,7 @@ void store_tune(const std::string& key, int fuse, int rows, float ms) {
 }
 
 // (fuse, rows) for a batch: explicit options first, then the tuned choice,
-// then the defaults (fuse 4, per-grid default tile height).
+// then the defaults (default_fuse, per-grid default tile height).
 void choose_params(int count, const rbgs_grid* grids, int dt, const rbgs_sweep_opts* o,
                    int* fuse, int* rows) {
     *fuse = (o && o->fuse > 0) ? o->fuse : 0;
@@ -431,7 +434,11 @@ void choose_params(int count, const rbgs_grid* grids, int dt, const rbgs_sweep_o
             if (*rows == 0) *rows = it->second.second;
         }
     }
-    if (*fuse == 0) *fuse = kMaxFuse;
+    if (*fuse == 0) {
+        int nmax = 1;
+        for (int g = 0; g < count; ++g) nmax = grids[g].n > nmax ? grids[g].n : nmax;
+        *fuse = default_fuse(dt == RBGS_F64 ? 8 : 4, nmax);
+    }
 }
 
 template <typename T>
@@ -608,7 +615,7 @@ int rbgs_autotune_batched(int32_t count, const rbgs_grid* grids, rbgs_dtype dt, 
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
         return bfail(RBGS_EHIP, "event create");
-    const int fuses[] = {2, 3, 4};
+    const int fuses[] = {4, 5, 6, 7};
     const int rowsv[] = {64, 128, 256};
     float best_ms = 1e30f;
     int bf = kMaxFuse, br = 0;

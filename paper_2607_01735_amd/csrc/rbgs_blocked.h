@@ -12,7 +12,18 @@ namespace rbgs {
 
 constexpr int kBlockedLanes = 64;  // one wave per tile
 constexpr int kMinRows = 8;
-constexpr int kMaxFuse = 4;
+constexpr int kMaxFuse = 7;
+
+// Full sweeps per pass when the caller leaves fuse = 0, from time per sweep
+// measured on MI355X: deep fusion pays on large grids (FP64 fuse 6: 669
+// GLUP/s at 8191^2 against 578 for fuse 4; FP32 fuse 7: 1188 against 959),
+// shallow fusion on small ones, whose short tiles would be mostly halo.
+inline int default_fuse(int elem_bytes, int n) {
+    if (n < 768) return 4;
+    if (n < 1536) return 5;
+    if (elem_bytes == 8 || n < 4096) return 6;
+    return 7;
+}
 
 // Tile geometry of one grid: a tile is kBlockedLanes lanes x V q-columns
 // wide (V = 16 bytes / element size) with halo_q columns of halo on each
@@ -52,10 +63,12 @@ inline int default_rows(int n, int L) {
 // Tile height for one grid on its own: small grids need many tiles to keep
 // waves busy (about 64 row tiles up to n = 2047, measured best on MI355X
 // at 255..2047), large ones need tall tiles for fewer halo rows (256 at
-// 8191).  The tile also has to hold the L halo rows.
-inline int single_grid_rows(int n, int L) {
+// 8191 in FP64).  FP32 tiles are twice as wide, so half as tall.  The tile
+// also has to hold the L halo rows.
+inline int single_grid_rows(int n, int L, int elem_bytes) {
     const int64_t m = int64_t(n) + 1;
     int64_t want = m <= 2048 ? m / 64 : m / 32;
+    if (elem_bytes == 4) want /= 2;
     int r = kMinRows;
     while (r * 2 <= want && r < 256) r <<= 1;
     return r < L ? L : r;
@@ -83,12 +96,15 @@ BlockedParams blocked_params(int n, size_t elem_bytes, const rbgs_sweep_opts* o)
 // nsweeps sweeps of the split iterate in buffer 0 (buf_red[0], buf_black[0])
 // with the persistent kernel; buffer 1 is scratch of the same size.  The
 // result is left in buffer 0.  Sweeps that do not fill a whole pass of
-// `fuse` sweeps run with the plain kernel.
+// `fuse` sweeps run with the plain kernel.  When ev_begin/ev_end are given
+// they are recorded right before the first and after the last persistent
+// launch; *persistent_launches and *passes receive what those launches did.
 template <typename T>
 hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_red,
                        const T* f_black, int n, int64_t pitch, T h2, int nsweeps,
                        const BlockedParams& bp, void* state, size_t state_bytes, hipStream_t s,
-                       int* launches);
+                       int* launches, hipEvent_t ev_begin, hipEvent_t ev_end,
+                       int* persistent_launches, int* passes_done);
 // Reads the persistent kernel's error word (synchronising the stream when
 // the kernel ran); returns RBGS_OK or RBGS_ETIMEOUT.
 int blocked_check_error(void* state, hipStream_t s, std::string* why);

@@ -7,7 +7,7 @@
 // does several half-sweeps per trip through HBM:
 //
 // * Work item = (pass p, tile t).  A pass fuses k full sweeps (L = 2k
-//   half-sweeps).  Tiles are (row strip) x (q-column band) of the split
+//   half-sweeps, k = 1..7).  Tiles are (row strip) x (q-column band) of the split
 //   colour layout; one wave of 64 lanes owns one tile, each lane V
 //   consecutive q-columns (a 16-byte vector) of the band.
 // * Inside a tile the L half-sweeps are pipelined down the strip in
@@ -80,7 +80,10 @@ hipError_t launch_by_fuse(int fuse, const GridDesc<T>& g, const Queue& qu, hipSt
         case 1: return launch_k<T, V, 2>(g, qu, s);
         case 2: return launch_k<T, V, 4>(g, qu, s);
         case 3: return launch_k<T, V, 6>(g, qu, s);
-        default: return launch_k<T, V, 8>(g, qu, s);
+        case 4: return launch_k<T, V, 8>(g, qu, s);
+        case 5: return launch_k<T, V, 10>(g, qu, s);
+        case 6: return launch_k<T, V, 12>(g, qu, s);
+        default: return launch_k<T, V, 14>(g, qu, s);
     }
 }
 
@@ -102,7 +105,7 @@ size_t blocked_state_bytes(int n, int) { return 256 + align256(size_t(max_tiles(
 
 int validate_blocked_opts(int fuse, int tile_rows, int tile_cols, std::string* why) {
     if (fuse > kMaxFuse) {
-        *why = "fuse must be in [1, 4] (0 = default)";
+        *why = "fuse must be in [1, 7] (0 = default)";
         return RBGS_EINVAL;
     }
     if (tile_rows != 0 && tile_rows < kMinRows) {
@@ -129,10 +132,11 @@ int auto_kernel(int n, size_t elem_bytes, int nsweeps) {
     return n < 1536 ? RBGS_KERNEL_PLAIN : RBGS_KERNEL_BLOCKED;
 }
 
-BlockedParams blocked_params(int n, size_t, const rbgs_sweep_opts* o) {
+BlockedParams blocked_params(int n, size_t elem_bytes, const rbgs_sweep_opts* o) {
     BlockedParams bp;
-    bp.fuse = (o && o->fuse > 0) ? o->fuse : kMaxFuse;
-    bp.tile_rows = (o && o->tile_rows > 0) ? o->tile_rows : single_grid_rows(n, 2 * bp.fuse);
+    bp.fuse = (o && o->fuse > 0) ? o->fuse : default_fuse(int(elem_bytes), n);
+    bp.tile_rows = (o && o->tile_rows > 0) ? o->tile_rows
+                                           : single_grid_rows(n, 2 * bp.fuse, int(elem_bytes));
     if (bp.tile_rows < 2 * bp.fuse) bp.tile_rows = 2 * bp.fuse;  // halo rows must fit one strip
     bp.delay = o ? o->debug_delay : 0;
     bp.spin_limit = (o && o->debug_spin_limit > 0) ? o->debug_spin_limit : kDefaultSpinLimit;
@@ -144,8 +148,11 @@ template <typename T>
 hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_red,
                        const T* f_black, int n, int64_t pitch, T h2, int nsweeps,
                        const BlockedParams& bp, void* state, size_t state_bytes, hipStream_t s,
-                       int* launches) {
+                       int* launches, hipEvent_t ev_begin, hipEvent_t ev_end,
+                       int* persistent_launches, int* passes_done) {
     constexpr int V = 16 / int(sizeof(T));
+    *persistent_launches = 0;
+    *passes_done = 0;
     const int k = bp.fuse;
     const int passes = nsweeps / k;
     const int rem = nsweeps - passes * k;
@@ -197,11 +204,21 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
             qu.delay = bp.delay;
             qu.stall_tile = bp.stall_tile;
             qu.buf_offset = 0;
+            if (ev_begin && done == 0) {
+                e = hipEventRecord(ev_begin, s);
+                if (e != hipSuccess) return e;
+            }
             e = launch_by_fuse<T, V>(k, g, qu, s);
             if (e != hipSuccess) return e;
             *launches += 1;
+            *persistent_launches += 1;
             done += chunk;
         }
+        if (ev_end) {
+            e = hipEventRecord(ev_end, s);
+            if (e != hipSuccess) return e;
+        }
+        *passes_done = passes;
         if (passes & 1) {
             e = hipMemcpyAsync(buf_red[0], buf_red[1], colour_bytes, hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) return e;
@@ -225,10 +242,12 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
 
 template hipError_t run_blocked<double>(double* const[2], double* const[2], const double*,
                                         const double*, int, int64_t, double, int,
-                                        const BlockedParams&, void*, size_t, hipStream_t, int*);
+                                        const BlockedParams&, void*, size_t, hipStream_t, int*,
+                                        hipEvent_t, hipEvent_t, int*, int*);
 template hipError_t run_blocked<float>(float* const[2], float* const[2], const float*,
                                        const float*, int, int64_t, float, int,
-                                       const BlockedParams&, void*, size_t, hipStream_t, int*);
+                                       const BlockedParams&, void*, size_t, hipStream_t, int*,
+                                       hipEvent_t, hipEvent_t, int*, int*);
 
 int blocked_check_error(void* state, hipStream_t s, std::string* why) {
     int err = 0;

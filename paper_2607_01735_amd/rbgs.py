@@ -41,7 +41,13 @@ class rbgs_grid(ctypes.Structure):
 
 class rbgs_timing(ctypes.Structure):
     _fields_ = [("pack_ms", ctypes.c_float), ("sweep_ms", ctypes.c_float),
-                ("unpack_ms", ctypes.c_float), ("sweep_launches", ctypes.c_int32)]
+                ("unpack_ms", ctypes.c_float), ("sweep_launches", ctypes.c_int32),
+                ("persistent_ms", ctypes.c_float), ("persistent_launches", ctypes.c_int32),
+                ("passes", ctypes.c_int32), ("fuse", ctypes.c_int32)]
+
+
+def _timing_dict(t):
+    return {name: getattr(t, name) for name, _ in rbgs_timing._fields_}
 
 
 class rbgs_sweep_opts(ctypes.Structure):
@@ -221,8 +227,7 @@ def rbgs_sweep(u, f, nsweeps, h=None, kernel="auto", workspace=None, stream=None
                            int(nsweeps), ctypes.byref(opts), _vp(ws.data_ptr()), ws.numel(),
                            _stream_ptr(stream, u.device)))
     if timing:
-        return {"pack_ms": t.pack_ms, "sweep_ms": t.sweep_ms, "unpack_ms": t.unpack_ms,
-                "sweep_launches": t.sweep_launches}
+        return _timing_dict(t)
     return None
 
 
@@ -264,8 +269,7 @@ def rbgs_solve(u, f, max_sweeps, rel_tol, check_every=100, h=None, precision="f6
            "rel_residual": info.rel_residual, "abs_residual": info.abs_residual,
            "status": info.status}
     if timing:
-        out["timing"] = {"pack_ms": t.pack_ms, "sweep_ms": t.sweep_ms, "unpack_ms": t.unpack_ms,
-                         "sweep_launches": t.sweep_launches}
+        out["timing"] = _timing_dict(t)
     return out
 
 

@@ -46,10 +46,12 @@ def start(n, seed, ld=None, dtype=np.float64):
     return u.astype(dtype), f.astype(dtype)
 
 
-CASES = [  # n, sweeps, fuse, tile_rows
+CASES = [  # n, sweeps, fuse, tile_rows (0 = default)
     (1, 5, 4, 0), (2, 8, 2, 8), (5, 7, 3, 8), (31, 12, 4, 8), (64, 9, 1, 8), (100, 16, 4, 16),
     (255, 24, 4, 0), (255, 25, 3, 32), (300, 8, 2, 8), (513, 20, 4, 64), (1000, 12, 4, 24),
     (1023, 40, 4, 0), (1025, 6, 1, 0), (2049, 16, 4, 128),
+    (7, 11, 5, 8), (200, 30, 5, 16), (255, 26, 6, 0), (511, 43, 6, 14), (1023, 40, 7, 0),
+    (1500, 21, 7, 32), (2047, 36, 6, 0), (3000, 14, 7, 0),
 ]
 
 
