@@ -412,7 +412,8 @@ def main():
         launches = acc["persistent_launches"]
         avg_launch_ms = acc["persistent_ms"] / launches
         per_launch_bytes = BYTES_PER_LUP["f64"] * n * n * acc["passes"] / launches
-        bytes_per_lup = BYTES_PER_LUP["f64"] / fuse
+        tail = 1 if sweeps % fuse >= 2 else 0  # one shallower pass per step
+        bytes_per_lup = BYTES_PER_LUP["f64"] * (sweeps // fuse + tail) / sweeps
         kname = f"k_blocked<double,2,{2 * fuse}> (persistent, fuse {fuse})"
         traffic_key = "blocked_f64"
     else:

@@ -285,7 +285,10 @@ hipError_t launch_batched_by_fuse(int fuse, const GridDesc<T>* d, const int* map
         case 4: return launch_batched_k<T, V, 8>(d, map, tiles, qu, s);
         case 5: return launch_batched_k<T, V, 10>(d, map, tiles, qu, s);
         case 6: return launch_batched_k<T, V, 12>(d, map, tiles, qu, s);
-        default: return launch_batched_k<T, V, 14>(d, map, tiles, qu, s);
+        case 7: return launch_batched_k<T, V, 14>(d, map, tiles, qu, s);
+        case 8: return launch_batched_k<T, V, 16>(d, map, tiles, qu, s);
+        case 9: return launch_batched_k<T, V, 18>(d, map, tiles, qu, s);
+        default: return launch_batched_k<T, V, 20>(d, map, tiles, qu, s);
     }
 }
 
@@ -358,7 +361,7 @@ int validate_batch(int32_t count, const rbgs_grid* grids, int dt, void* const* u
     if (o) {
         if (o->kernel != RBGS_KERNEL_AUTO && o->kernel != RBGS_KERNEL_BLOCKED)
             return bfail(RBGS_EINVAL, "batched sweeps use the persistent kernel");
-        if (o->fuse < 0 || o->fuse > kMaxFuse) return bfail(RBGS_EINVAL, "fuse must be in [0, 7]");
+        if (o->fuse < 0 || o->fuse > kMaxFuse) return bfail(RBGS_EINVAL, "fuse must be in [0, 10]");
         if (o->tile_rows != 0 && o->tile_rows < kMinRows)
             return bfail(RBGS_EINVAL, "tile_rows must be >= 8 (0 = default)");
         if (o->tile_cols != 0) return bfail(RBGS_EINVAL, "tile_cols must be 0");

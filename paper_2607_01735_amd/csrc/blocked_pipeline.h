@@ -126,7 +126,23 @@ struct Pipe {
     Vec<T, V> win[L][3];   // level l: other-colour rows (ring buffer of 3), version l-1
     Vec<T, V> red_in[2];   // red input rows x-1, x (ring values pass through level 0)
     StepIn<T, V> in[3];    // inputs of steps x, x+1, x+2 (slot x mod 3)
-    Vec<T, V> fl[2][L];    // right-hand sides of levels >= 2 for steps x, x+1 (slot x mod 2)
+};
+
+// Right-hand-side rows of a wave, kept in LDS for the deeper levels.  Level
+// l of step x needs f of colour l & 1 at row x-1-l, a row that levels 0
+// (red) or 1 (black) loaded l or l-1 steps earlier; each wave keeps the rows
+// it loaded in a ring of L + 2 rows per colour, one 16-byte slot per lane,
+// instead of fetching them again from memory for every level (those
+// re-reads missed L2 and doubled the HBM read traffic at 6 fused sweeps).
+// The ring holds at least L + 2 rows per colour (rows x-1 .. x-L are live
+// at step x): 16 up to L = 14, where a power of two makes the slot a mask;
+// L + 2 beyond, so that the ring stays within 40 KB and four waves fit a CU.
+template <int L>
+constexpr int fring_rows() { return L <= 14 ? 16 : L + 2; }
+
+template <typename T, int V, int L>
+struct FRing {
+    Vec<T, V> row[2][fring_rows<L>()][kLanes];
 };
 
 // Loads never branch: row and column indices are clamped into the grid.
@@ -155,16 +171,6 @@ __device__ __forceinline__ StepIn<T, V> load_in(const GridDesc<T>& a, const T* _
     return in;
 }
 
-template <typename T, int V, int L>
-__device__ __forceinline__ void load_fl(const GridDesc<T>& a, Vec<T, V> (&dst)[L], int x,
-                                        int64_t qv) {
-    static_for<2, L>([&](auto lc) {
-        constexpr int l = decltype(lc)::value;
-        const int y = clamp_row(x - 1 - l, 1, a.n);
-        dst[l] = vload<T, V>(((l & 1) ? a.f_black : a.f_red) + int64_t(y) * a.pitch + qv);
-    });
-}
-
 // Store the core part of one row: q in [qc0, qc1) and interior for parity p.
 template <typename T, int V>
 __device__ __forceinline__ void store_core(T* row, const Vec<T, V>& v, int64_t q0, int64_t qc0,
@@ -184,7 +190,7 @@ __device__ __forceinline__ void store_core(T* row, const Vec<T, V>& v, int64_t q
 // One pipeline step at input row x; S = x mod 6 fixes, at compile time, the
 // ring-buffer slots (period 3) and the row parities (period 2).
 template <typename T, int V, int L, int S, bool EDGE>
-__device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, const GridDesc<T>& a,
+__device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, FRing<T, V, L>& fr, const GridDesc<T>& a,
                                           const T* __restrict__ xr, const T* __restrict__ xb,
                                           T* __restrict__ yr, T* __restrict__ yb, int x, int xs,
                                           int xe, int r0, int r1, int64_t q0, int64_t qv,
@@ -192,20 +198,33 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, const GridDesc<T>& 
     const int n = a.n;
     const int64_t P = a.pitch;
     const StepIn<T, V> cur = st.in[S % 3];
-    // prefetch: step x+2's rows into the slot step x-1 used, step x+1's
-    // right-hand sides into the other half of the double buffer
+    // prefetch: step x+2's rows into the slot step x-1 used
     st.in[(S + 2) % 3] = load_in<T, V, EDGE>(a, xr, xb, x + 2, qv);
-    load_fl<T, V, L>(a, st.fl[(S + 1) % 2], x + 1, qv);
+    // this step's right-hand-side rows join the ring (red row x-1, black
+    // row x-2); the deeper levels read older rows from it.  Row r sits in
+    // slot r mod R; base = x mod R (x >= 0), and every slot below is base
+    // minus a compile-time offset, wrapped once.
+    constexpr int R = fring_rows<L>();
+    const int lane = threadIdx.x;
+    const int base = (R & (R - 1)) == 0 ? (x & (R - 1)) : x % R;
+    auto slot = [&](int back) {
+        if constexpr ((R & (R - 1)) == 0)
+            return (base - back) & (R - 1);
+        else
+            return base - back < 0 ? base - back + R : base - back;
+    };
+    fr.row[0][slot(1)][lane] = cur.f0;
+    fr.row[1][slot(2)][lane] = cur.f1;
     const Vec<T, V> bin = cur.b;
     const Vec<T, V> rin = cur.r;
-    auto rhs = [&](auto lc) -> const Vec<T, V>& {
+    auto rhs = [&](auto lc) -> Vec<T, V> {
         constexpr int l = decltype(lc)::value;
         if constexpr (l == 0)
             return cur.f0;
         else if constexpr (l == 1)
             return cur.f1;
         else
-            return st.fl[S % 2][l];
+            return fr.row[l & 1][slot(1 + l)][lane];
     };
     Vec<T, V> carry = bin;  // row entering level l's window
     static_for<0, L>([&](auto lc) {
@@ -230,6 +249,7 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, const GridDesc<T>& 
         Vec<T, V> out;
         // prev: this colour's previous version of row y, kept where nothing
         // is updated (the Dirichlet ring and rows outside the interior)
+        const Vec<T, V> fl = rhs(lc);
         auto update = [&](const Vec<T, V>& prev) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
@@ -238,7 +258,7 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, const GridDesc<T>& 
                 T s = dn.v[e] + up.v[e];
                 s = s + right;
                 s = s + left;
-                T t = a.h2 * rhs(lc).v[e];
+                T t = a.h2 * fl.v[e];
                 s = s - t;
                 T nv = T(0.25) * s;
                 if constexpr (EDGE) {
@@ -271,8 +291,8 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, const GridDesc<T>& 
 }
 
 template <typename T, int V, int L, bool EDGE>
-__device__ __forceinline__ void run_tile(const GridDesc<T>& a, int pass, int r0, int r1,
-                                         int64_t qc0, int64_t qc1) {
+__device__ __forceinline__ void run_tile(FRing<T, V, L>& fr, const GridDesc<T>& a, int pass, int r0,
+                                         int r1, int64_t qc0, int64_t qc1) {
     const int lane = threadIdx.x;
     const int64_t q0 = qc0 - a.halo_q + int64_t(lane) * V;
     // column actually loaded: q0 clamped into the row (lanes past the grid
@@ -295,14 +315,13 @@ __device__ __forceinline__ void run_tile(const GridDesc<T>& a, int pass, int r0,
     const int x0 = xs - xs % 6;
     st.in[0] = load_in<T, V, EDGE>(a, xr, xb, x0, qv);
     st.in[1] = load_in<T, V, EDGE>(a, xr, xb, x0 + 1, qv);
-    load_fl<T, V, L>(a, st.fl[0], x0, qv);
     for (int x = x0; x <= x_last; x += 6) {
-        pipe_step<T, V, L, 0, EDGE>(st, a, xr, xb, yr, yb, x + 0, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
-        pipe_step<T, V, L, 1, EDGE>(st, a, xr, xb, yr, yb, x + 1, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
-        pipe_step<T, V, L, 2, EDGE>(st, a, xr, xb, yr, yb, x + 2, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
-        pipe_step<T, V, L, 3, EDGE>(st, a, xr, xb, yr, yb, x + 3, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
-        pipe_step<T, V, L, 4, EDGE>(st, a, xr, xb, yr, yb, x + 4, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
-        pipe_step<T, V, L, 5, EDGE>(st, a, xr, xb, yr, yb, x + 5, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
+        pipe_step<T, V, L, 0, EDGE>(st, fr, a, xr, xb, yr, yb, x + 0, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
+        pipe_step<T, V, L, 1, EDGE>(st, fr, a, xr, xb, yr, yb, x + 1, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
+        pipe_step<T, V, L, 2, EDGE>(st, fr, a, xr, xb, yr, yb, x + 2, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
+        pipe_step<T, V, L, 3, EDGE>(st, fr, a, xr, xb, yr, yb, x + 3, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
+        pipe_step<T, V, L, 4, EDGE>(st, fr, a, xr, xb, yr, yb, x + 4, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
+        pipe_step<T, V, L, 5, EDGE>(st, fr, a, xr, xb, yr, yb, x + 5, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
     }
 }
 
@@ -322,10 +341,11 @@ __device__ __forceinline__ void process_tile(const GridDesc<T>& a, int pass, int
     const bool interior = r0 - L >= 1 && r1 + L <= a.n && qa >= 1 &&
                           qa + int64_t(kLanes) * V - 1 <= (int64_t(a.n) - 1) >> 1 &&
                           qc1 - qc0 == a.q_core;
+    __shared__ FRing<T, V, L> fr;
     if (interior)
-        run_tile<T, V, L, false>(a, pass, r0, r1, qc0, qc1);
+        run_tile<T, V, L, false>(fr, a, pass, r0, r1, qc0, qc1);
     else
-        run_tile<T, V, L, true>(a, pass, r0, r1, qc0, qc1);
+        run_tile<T, V, L, true>(fr, a, pass, r0, r1, qc0, qc1);
 }
 
 // Waits until the 3 x 3 neighbourhood of `tile` has finished pass-1.

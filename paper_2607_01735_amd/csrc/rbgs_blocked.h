@@ -12,16 +12,18 @@ namespace rbgs {
 
 constexpr int kBlockedLanes = 64;  // one wave per tile
 constexpr int kMinRows = 8;
-constexpr int kMaxFuse = 7;
+constexpr int kMaxFuse = 10;
 
 // Full sweeps per pass when the caller leaves fuse = 0, from time per sweep
-// measured on MI355X: deep fusion pays on large grids (FP64 fuse 6: 669
-// GLUP/s at 8191^2 against 578 for fuse 4; FP32 fuse 7: 1188 against 959),
-// shallow fusion on small ones, whose short tiles would be mostly halo.
+// measured on MI355X: deep fusion pays on large grids (8191^2: FP64 fuse 7
+// with 256-row tiles 1157 GLUP/s, fuse 6 1036, fuse 9 1111; FP32 fuse 7 with
+// 128-row tiles 1520), shallow fusion on small ones, whose short tiles
+// would be mostly halo.
 inline int default_fuse(int elem_bytes, int n) {
+    (void)elem_bytes;
     if (n < 768) return 4;
     if (n < 1536) return 5;
-    if (elem_bytes == 8 || n < 4096) return 6;
+    if (n < 4096) return 6;
     return 7;
 }
 
@@ -96,9 +98,11 @@ BlockedParams blocked_params(int n, size_t elem_bytes, const rbgs_sweep_opts* o)
 // nsweeps sweeps of the split iterate in buffer 0 (buf_red[0], buf_black[0])
 // with the persistent kernel; buffer 1 is scratch of the same size.  The
 // result is left in buffer 0.  Sweeps that do not fill a whole pass of
-// `fuse` sweeps run with the plain kernel.  When ev_begin/ev_end are given
-// they are recorded right before the first and after the last persistent
-// launch; *persistent_launches and *passes receive what those launches did.
+// `fuse` sweeps run as one shallower pass (a single one with the plain
+// kernel).  When ev_begin/ev_end are given
+// they are recorded right before the first and after the last full-depth
+// persistent launch (around the shallower pass when there is no full one);
+// *persistent_launches and *passes_done receive what those launches did.
 template <typename T>
 hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_red,
                        const T* f_black, int n, int64_t pitch, T h2, int nsweeps,

@@ -7,7 +7,7 @@
 // does several half-sweeps per trip through HBM:
 //
 // * Work item = (pass p, tile t).  A pass fuses k full sweeps (L = 2k
-//   half-sweeps, k = 1..7).  Tiles are (row strip) x (q-column band) of the split
+//   half-sweeps, k = 1..10).  Tiles are (row strip) x (q-column band) of the split
 //   colour layout; one wave of 64 lanes owns one tile, each lane V
 //   consecutive q-columns (a 16-byte vector) of the band.
 // * Inside a tile the L half-sweeps are pipelined down the strip in
@@ -83,7 +83,10 @@ hipError_t launch_by_fuse(int fuse, const GridDesc<T>& g, const Queue& qu, hipSt
         case 4: return launch_k<T, V, 8>(g, qu, s);
         case 5: return launch_k<T, V, 10>(g, qu, s);
         case 6: return launch_k<T, V, 12>(g, qu, s);
-        default: return launch_k<T, V, 14>(g, qu, s);
+        case 7: return launch_k<T, V, 14>(g, qu, s);
+        case 8: return launch_k<T, V, 16>(g, qu, s);
+        case 9: return launch_k<T, V, 18>(g, qu, s);
+        default: return launch_k<T, V, 20>(g, qu, s);
     }
 }
 
@@ -105,7 +108,7 @@ size_t blocked_state_bytes(int n, int) { return 256 + align256(size_t(max_tiles(
 
 int validate_blocked_opts(int fuse, int tile_rows, int tile_cols, std::string* why) {
     if (fuse > kMaxFuse) {
-        *why = "fuse must be in [1, 7] (0 = default)";
+        *why = "fuse must be in [1, 10] (0 = default)";
         return RBGS_EINVAL;
     }
     if (tile_rows != 0 && tile_rows < kMinRows) {
@@ -153,35 +156,58 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
     constexpr int V = 16 / int(sizeof(T));
     *persistent_launches = 0;
     *passes_done = 0;
+    *launches = 0;
     const int k = bp.fuse;
     const int passes = nsweeps / k;
     const int rem = nsweeps - passes * k;
     const size_t colour_bytes = size_t(n + 2) * size_t(pitch) * sizeof(T);
-    *launches = 0;
-    hipError_t e;
-    if (passes > 0) {
-        const Geometry geo = geometry(n, int(sizeof(T)), k, bp.tile_rows);
+    char* base = static_cast<char*>(state);
+    // the error word starts at zero once per call; tickets and flags before
+    // every launch (an error seen by an earlier launch must survive)
+    hipError_t e = launch_zero(base, 256, s);
+    if (e != hipSuccess) return e;
+    // A remainder of two or more sweeps runs as one shallower pass of the
+    // same kernel; a single leftover sweep runs with the plain kernel.
+    const int tail_fuse = rem >= 2 ? rem : 0;
+    if (passes == 0 && tail_fuse == 0) {
+        for (int it = 0; it < nsweeps; ++it) {
+            e = launch_half_sweep<T>(buf_red[0], buf_black[0], f_red, n, pitch, h2, 0, 0, s);
+            if (e != hipSuccess) return e;
+            e = launch_half_sweep<T>(buf_black[0], buf_red[0], f_black, n, pitch, h2, 1, 0, s);
+            if (e != hipSuccess) return e;
+            *launches += 2;
+        }
+        return hipSuccess;
+    }
+    // the second buffer needs the Dirichlet ring: start from a full copy
+    e = hipMemcpyAsync(buf_red[1], buf_red[0], colour_bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(buf_black[1], buf_black[0], colour_bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    int cur = 0;  // buffer holding the current iterate
+    bool started = false;
+    // `count` passes of `fuse` sweeps starting from buffer cur; `timed`
+    // launches are bracketed by the events and counted
+    auto run_passes = [&](int fuse, int count, bool timed) -> hipError_t {
+        const int rows = bp.tile_rows < 2 * fuse ? 2 * fuse : bp.tile_rows;
+        const Geometry geo = geometry(n, int(sizeof(T)), fuse, rows);
         if (geo.ntiles > max_tiles(n)) return hipErrorInvalidValue;
-        // the second buffer needs the Dirichlet ring: start from a full copy
-        e = hipMemcpyAsync(buf_red[1], buf_red[0], colour_bytes, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return e;
-        e = hipMemcpyAsync(buf_black[1], buf_black[0], colour_bytes, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return e;
         // tickets are ints: split very long runs into launches of at most
         // 2^30 work items, each starting from freshly zeroed flags
         const int max_passes = int((int64_t(1) << 30) / geo.ntiles) > 0
                                    ? int((int64_t(1) << 30) / geo.ntiles) : 1;
         int done = 0;
-        while (done < passes) {
-            const int chunk = passes - done < max_passes ? passes - done : max_passes;
-            e = launch_zero(state, 256 + size_t(geo.ntiles) * 4, s);
-            if (e != hipSuccess) return e;
-            const int in = done & 1;  // buffer holding the input of this chunk
+        while (done < count) {
+            const int chunk = count - done < max_passes ? count - done : max_passes;
+            hipError_t r = launch_zero(base, 64, s);  // ticket
+            if (r != hipSuccess) return r;
+            r = launch_zero(base + 256, size_t(geo.ntiles) * 4, s);  // progress flags
+            if (r != hipSuccess) return r;
             GridDesc<T> g;
-            g.red[0] = buf_red[in];
-            g.red[1] = buf_red[in ^ 1];
-            g.black[0] = buf_black[in];
-            g.black[1] = buf_black[in ^ 1];
+            g.red[0] = buf_red[cur];
+            g.red[1] = buf_red[cur ^ 1];
+            g.black[0] = buf_black[cur];
+            g.black[1] = buf_black[cur ^ 1];
             g.f_red = f_red;
             g.f_black = f_black;
             g.n = n;
@@ -196,7 +222,6 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
             g.flag_base = 0;
             Queue qu;
             qu.passes = chunk;
-            char* base = static_cast<char*>(state);
             qu.ticket = reinterpret_cast<int*>(base);
             qu.error = reinterpret_cast<int*>(base + 64);
             qu.progress = reinterpret_cast<int*>(base + 256);
@@ -204,33 +229,42 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
             qu.delay = bp.delay;
             qu.stall_tile = bp.stall_tile;
             qu.buf_offset = 0;
-            if (ev_begin && done == 0) {
-                e = hipEventRecord(ev_begin, s);
-                if (e != hipSuccess) return e;
+            if (timed && ev_begin && !started) {
+                r = hipEventRecord(ev_begin, s);
+                if (r != hipSuccess) return r;
+                started = true;
             }
-            e = launch_by_fuse<T, V>(k, g, qu, s);
-            if (e != hipSuccess) return e;
+            r = launch_by_fuse<T, V>(fuse, g, qu, s);
+            if (r != hipSuccess) return r;
             *launches += 1;
-            *persistent_launches += 1;
+            if (timed) {
+                *persistent_launches += 1;
+                *passes_done += chunk;
+            }
             done += chunk;
+            cur ^= chunk & 1;
         }
-        if (ev_end) {
-            e = hipEventRecord(ev_end, s);
-            if (e != hipSuccess) return e;
-        }
-        *passes_done = passes;
-        if (passes & 1) {
-            e = hipMemcpyAsync(buf_red[0], buf_red[1], colour_bytes, hipMemcpyDeviceToDevice, s);
-            if (e != hipSuccess) return e;
-            e = hipMemcpyAsync(buf_black[0], buf_black[1], colour_bytes, hipMemcpyDeviceToDevice, s);
-            if (e != hipSuccess) return e;
-        }
-    } else {
-        // no persistent launch: make sure a stale error word cannot be reported
-        e = launch_zero(state, 256, s);
+        return hipSuccess;
+    };
+    // the events time the full-depth passes (the tail pass when there are
+    // none), so that their duration is that of one kernel
+    if (passes > 0 && (e = run_passes(k, passes, true)) != hipSuccess) return e;
+    if (ev_end && started) {
+        e = hipEventRecord(ev_end, s);
         if (e != hipSuccess) return e;
     }
-    for (int it = 0; it < rem; ++it) {
+    if (tail_fuse > 0 && (e = run_passes(tail_fuse, 1, passes == 0)) != hipSuccess) return e;
+    if (ev_end && passes == 0 && started) {
+        e = hipEventRecord(ev_end, s);
+        if (e != hipSuccess) return e;
+    }
+    if (cur != 0) {
+        e = hipMemcpyAsync(buf_red[0], buf_red[1], colour_bytes, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(buf_black[0], buf_black[1], colour_bytes, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    if (rem == 1) {
         e = launch_half_sweep<T>(buf_red[0], buf_black[0], f_red, n, pitch, h2, 0, 0, s);
         if (e != hipSuccess) return e;
         e = launch_half_sweep<T>(buf_black[0], buf_red[0], f_black, n, pitch, h2, 1, 0, s);

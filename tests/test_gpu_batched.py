@@ -44,7 +44,7 @@ SIZES = [1, 2, 7, 31, 63, 64, 100, 127, 255, 300, 511, 63, 127, 1, 255, 65]
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("nsweeps,fuse", [(12, 4), (13, 4), (10, 3), (7, 2), (5, 1), (17, 5),
-                                          (20, 6), (23, 7)])
+                                          (20, 6), (23, 7), (16, 8), (30, 10)])
 def test_batched_bitwise(oracle, dtype, nsweeps, fuse):
     say(f"batched {dtype.__name__} sweeps={nsweeps} fuse={fuse} grids={len(SIZES)}")
     us, fs = make_batch(SIZES, dtype)

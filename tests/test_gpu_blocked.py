@@ -52,6 +52,8 @@ CASES = [  # n, sweeps, fuse, tile_rows (0 = default)
     (1023, 40, 4, 0), (1025, 6, 1, 0), (2049, 16, 4, 128),
     (7, 11, 5, 8), (200, 30, 5, 16), (255, 26, 6, 0), (511, 43, 6, 14), (1023, 40, 7, 0),
     (1500, 21, 7, 32), (2047, 36, 6, 0), (3000, 14, 7, 0),
+    (9, 17, 8, 16), (333, 40, 8, 0), (1023, 27, 9, 24), (1200, 50, 10, 20), (4095, 30, 10, 0),
+    (100, 3, 7, 16), (700, 9, 5, 0), (2048, 11, 9, 0),  # remainders run as a shallower pass
 ]
 
 
