@@ -141,6 +141,39 @@ def time_to_tolerance(torch, rb, W, n=255, tol=1e-8):
     return out
 
 
+def time_to_tolerance_fourier(torch, rb, W, n=1023, tol=1e-8):
+    """The mixed-precision recipe at a size where the solve finishes: the
+    64-mode Fourier right-hand side (seed 0) on n x n from u = 0 to rel <=
+    tol (108 000 sweeps at n = 1023 by the closed form), for the plain FP64
+    judge, the library's FP64 choice (blocked) and FP64 refinement around
+    FP32 / bfloat16-rhs inner sweeps."""
+    h = W.spacing(n)
+    f = torch.from_numpy(W.fourier_rhs(n, seed=0)).to("cuda")
+    out = {"problem": f"{n}x{n} FP64, 64 Fourier modes seed 0, u0=0, rel<={tol:g}"}
+    forms = [("plain_f64", dict(kernel="plain", check_every=1000)),
+             ("auto_f64", dict(kernel="auto", check_every=1000)),
+             ("f32_ir", dict(kernel="auto", precision="f32_ir", inner_sweeps=4000,
+                             check_every=4000)),
+             ("f32_ir_blocked", dict(kernel="blocked", precision="f32_ir", inner_sweeps=4000,
+                                     check_every=4000)),
+             ("bf16rhs_ir", dict(kernel="auto", precision="bf16rhs_ir", inner_sweeps=1000,
+                                 check_every=1000))]
+    for name, kw in forms:
+        u = torch.zeros((n + 2, n + 2), dtype=torch.float64, device="cuda")
+        warm = {k: v for k, v in kw.items() if k not in ("inner_sweeps", "check_every")}
+        rb.rbgs_solve(u, f, 16, 0.0, check_every=16, h=h, **warm)
+        u.zero_()
+        dt, info = _timed_solve(torch, rb, u, f, max_sweeps=1_000_000, rel_tol=tol, h=h, **kw)
+        out[name] = {"seconds": round(dt, 4), "sweeps": info["sweeps"],
+                     "rel_residual": info["rel_residual"], "status": info["status"]}
+        log(f"time-to-tol {n} {name}: {dt:.3f} s, {info['sweeps']} sweeps, "
+            f"rel={info['rel_residual']:.3e}")
+    base = out["plain_f64"]["seconds"]
+    for name, _ in forms[1:]:
+        out[name]["speedup_vs_plain_f64"] = round(base / out[name]["seconds"], 3)
+    return out
+
+
 def learned_guess(torch, rb, tol=1e-8, seeds=2):
     """The learned-guess workload: 511 x 511 GRF right-hand sides (held-out
     seeds 10^6 + 20 + i), FP64 solve to rel <= tol from u = 0 (the judge)
@@ -443,6 +476,7 @@ def main():
     del u, f, ws
     torch.cuda.empty_cache()
     ttt = None if args.no_time_to_tol else time_to_tolerance(torch, rb, W)
+    ttt_1023 = None if args.no_time_to_tol else time_to_tolerance_fourier(torch, rb, W)
     refine = None if args.no_extras else refinement_throughput(torch, rb, W)
     batched = None if args.no_extras else batched_throughput(torch, rb, W)
     batched_tol = None if args.no_extras else batched_to_tolerance(torch, rb, W)
@@ -468,6 +502,7 @@ def main():
         "roofline": roofline,
         "plain_kernel": plain,
         "time_to_1e-8": ttt,
+        "time_to_1e-8_fourier_1023": ttt_1023,
         "refinement_16383": refine,
         "batched_512": batched,
         "batched_to_1e-8": batched_tol,
