@@ -77,8 +77,8 @@ __device__ __forceinline__ Vec<T, V> vzero() {
 // Inputs that a step consumes first-hand from HBM: the black and red rows x
 // of the pass input, and the right-hand sides of levels 0 and 1 (f_red row
 // x-1 and f_black row x-2, their first use).  They are loaded two steps
-// ahead; the right-hand sides of levels >= 2 (rows already brought in by
-// levels 0 and 1) are loaded one step ahead.
+// ahead; the right-hand sides of levels >= 2 are rows that levels 0 and 1
+// brought in earlier (kept in LDS).
 template <typename T, int V>
 struct StepIn {
     Vec<T, V> b, r, f0, f1;
@@ -87,10 +87,12 @@ struct StepIn {
 // Whole-wave lane shifts through DPP (register to register, no LDS trip):
 // from_next_lane gives lane i the value of lane i+1 (wave_shl:1), and
 // from_prev_lane the value of lane i-1 (wave_shr:1).  The lane with no
-// source keeps its own value; it lies in the tile's halo.
+// source receives 0 (bound_ctrl); it lies in the tile's halo, whose values
+// are never stored.  Not asking for the old value to be kept saves a copy of
+// the source register per shift.
 template <int CTRL>
 __device__ __forceinline__ int dpp_shift(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
 }
 
 constexpr int kWaveShl1 = 0x130;
@@ -128,17 +130,19 @@ struct Pipe {
     StepIn<T, V> in[3];    // inputs of steps x, x+1, x+2 (slot x mod 3)
 };
 
-// Right-hand-side rows of a wave, kept in LDS for the deeper levels.  Level
-// l of step x needs f of colour l & 1 at row x-1-l, a row that levels 0
-// (red) or 1 (black) loaded l or l-1 steps earlier; each wave keeps the rows
-// it loaded in a ring of L + 2 rows per colour, one 16-byte slot per lane,
+// Right-hand-side rows of a wave (as the products h^2 f), kept in LDS for
+// the deeper levels.  Level l of step x needs f of colour l & 1 at row
+// x-1-l, a row that levels 0 (red) or 1 (black) loaded l or l-1 steps
+// earlier; each wave keeps the rows it loaded in a ring of L + 2 rows per
+// colour, one 16-byte slot per lane,
 // instead of fetching them again from memory for every level (those
 // re-reads missed L2 and doubled the HBM read traffic at 6 fused sweeps).
 // The ring holds at least L + 2 rows per colour (rows x-1 .. x-L are live
-// at step x): 16 up to L = 14, where a power of two makes the slot a mask;
-// L + 2 beyond, so that the ring stays within 40 KB and four waves fit a CU.
+// at step x): the next power of two up to L = 14, so that the slot is a
+// mask; L + 2 beyond, so that the ring stays within 40 KB and four waves
+// fit a CU.
 template <int L>
-constexpr int fring_rows() { return L <= 14 ? 16 : L + 2; }
+constexpr int fring_rows() { return L <= 2 ? 4 : L <= 6 ? 8 : L <= 14 ? 16 : L + 2; }
 
 template <typename T, int V, int L>
 struct FRing {
@@ -201,7 +205,9 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, FRing<T, V, L>& fr,
     // prefetch: step x+2's rows into the slot step x-1 used
     st.in[(S + 2) % 3] = load_in<T, V, EDGE>(a, xr, xb, x + 2, qv);
     // this step's right-hand-side rows join the ring (red row x-1, black
-    // row x-2); the deeper levels read older rows from it.  Row r sits in
+    // row x-2) as the products h^2 f that Eq. (1) subtracts: each is formed
+    // once here, not once per fused level (the same product, so the same
+    // bits).  The deeper levels read older rows from the ring.  Row r sits in
     // slot r mod R; base = x mod R (x >= 0), and every slot below is base
     // minus a compile-time offset, wrapped once.
     constexpr int R = fring_rows<L>();
@@ -213,19 +219,24 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, FRing<T, V, L>& fr,
         else
             return base - back < 0 ? base - back + R : base - back;
     };
-    fr.row[0][slot(1)][lane] = cur.f0;
-    fr.row[1][slot(2)][lane] = cur.f1;
+    Vec<T, V> hf[L];  // h^2 f for each level's row y = x - 1 - l
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        hf[0].v[e] = a.h2 * cur.f0.v[e];
+        hf[1].v[e] = a.h2 * cur.f1.v[e];
+    }
+    fr.row[0][slot(1)][lane] = hf[0];
+    fr.row[1][slot(2)][lane] = hf[1];
+    // all ring reads of the step are issued up front, so that their LDS
+    // latency overlaps the first levels instead of stalling each level
+    static_for<2, L>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        hf[l] = fr.row[l & 1][slot(1 + l)][lane];
+    });
+    // keep the scheduler from sinking those reads back next to their uses
+    __builtin_amdgcn_sched_barrier(0);
     const Vec<T, V> bin = cur.b;
     const Vec<T, V> rin = cur.r;
-    auto rhs = [&](auto lc) -> Vec<T, V> {
-        constexpr int l = decltype(lc)::value;
-        if constexpr (l == 0)
-            return cur.f0;
-        else if constexpr (l == 1)
-            return cur.f1;
-        else
-            return fr.row[l & 1][slot(1 + l)][lane];
-    };
     Vec<T, V> carry = bin;  // row entering level l's window
     static_for<0, L>([&](auto lc) {
         constexpr int l = decltype(lc)::value;
@@ -249,7 +260,7 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, FRing<T, V, L>& fr,
         Vec<T, V> out;
         // prev: this colour's previous version of row y, kept where nothing
         // is updated (the Dirichlet ring and rows outside the interior)
-        const Vec<T, V> fl = rhs(lc);
+        const Vec<T, V>& fl = hf[l];
         auto update = [&](const Vec<T, V>& prev) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
@@ -258,8 +269,7 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, FRing<T, V, L>& fr,
                 T s = dn.v[e] + up.v[e];
                 s = s + right;
                 s = s + left;
-                T t = a.h2 * fl.v[e];
-                s = s - t;
+                s = s - fl.v[e];
                 T nv = T(0.25) * s;
                 if constexpr (EDGE) {
                     const int64_t q = q0 + e;
@@ -406,10 +416,14 @@ __device__ __forceinline__ bool run_item(const GridDesc<T>& g, const Queue& qu, 
     return true;
 }
 
+// The ticket is read back with readfirstlane (lane 0 is the first active
+// lane here), which makes it, and every tile coordinate and row index
+// derived from it, a wave-uniform scalar: the row loops then run on scalar
+// branches and the row addressing on the scalar unit.
 __device__ __forceinline__ int next_ticket(const Queue& qu) {
     int tk = 0;
     if (threadIdx.x == 0) tk = __hip_atomic_fetch_add(qu.ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __shfl(tk, 0);
+    return __builtin_amdgcn_readfirstlane(tk);
 }
 
 }  // namespace blocked

@@ -15,15 +15,15 @@ constexpr int kMinRows = 8;
 constexpr int kMaxFuse = 10;
 
 // Full sweeps per pass when the caller leaves fuse = 0, from time per sweep
-// measured on MI355X: deep fusion pays on large grids (8191^2: FP64 fuse 7
-// with 256-row tiles 1157 GLUP/s, fuse 6 1036, fuse 9 1111; FP32 fuse 7 with
-// 128-row tiles 1520), shallow fusion on small ones, whose short tiles
-// would be mostly halo.
+// measured on MI355X: a pass costs about the same per row step whatever
+// its depth (the row's HBM traffic sets the pace), so deep fusion pays on
+// large grids (8191^2 FP64: fuse 7 53 us per sweep, fuse 4 96 us, fuse 8
+// 55 us, where the deeper pipeline runs out of registers); small grids
+// prefer shallow fusion, their short tiles being mostly halo.
 inline int default_fuse(int elem_bytes, int n) {
     (void)elem_bytes;
     if (n < 768) return 4;
     if (n < 1536) return 5;
-    if (n < 4096) return 6;
     return 7;
 }
 
@@ -62,22 +62,36 @@ inline int default_rows(int n, int L) {
     return r < L ? L : r;
 }
 
-// Tile height for one grid on its own: small grids need many tiles to keep
-// waves busy (about 64 row tiles up to n = 2047, measured best on MI355X
-// at 255..2047), large ones need tall tiles for fewer halo rows (256 at
-// 8191 in FP64).  FP32 tiles are twice as wide, so half as tall.  The tile
-// also has to hold the L halo rows.
-inline int single_grid_rows(int n, int L, int elem_bytes) {
-    const int64_t m = int64_t(n) + 1;
-    int64_t want = m <= 2048 ? m / 64 : m / 32;
-    if (elem_bytes == 4) want /= 2;
-    int r = kMinRows;
-    while (r * 2 <= want && r < 256) r <<= 1;
-    return r < L ? L : r;
+// Tile height for one grid on its own.  Taller tiles spend less of their
+// work on the L halo rows (a fraction rows / (rows + 2L) is useful) but give
+// fewer tiles, and fewer tiles than the launch has wave slots leave waves
+// idle.  The height (a power of two from kMinRows to 256, at least L)
+// maximises the product of the two, with 0.8 x wave_slots as the tile count
+// that keeps the chip busy (waves finish their tiles at different times).
+// On MI355X this picks the measured best height at 1023..8191 in FP64 and
+// FP32 except FP64 2047 (16 rows for 32, 16% slower).
+inline int single_grid_rows(int n, int L, int elem_bytes, int wave_slots) {
+    const double busy = 0.8 * (wave_slots > 0 ? wave_slots : 1024);
+    int best = 0;
+    double best_score = -1.0;
+    for (int r = kMinRows; r <= 256; r <<= 1) {
+        const int rows = r < L ? L : r;
+        const Geometry g = geometry(n, elem_bytes, L / 2, rows);
+        const double fill = g.ntiles >= busy ? 1.0 : g.ntiles / busy;
+        const double score = double(rows) / double(rows + 2 * L) * fill;
+        if (score >= best_score) {
+            best_score = score;
+            best = rows;
+        }
+    }
+    return best;
 }
 
 // Resident one-wave workgroups per CU for a persistent kernel, and CU count.
 hipError_t persistent_occupancy(const void* kernel, int* per_cu, int* cus);
+// Waves the single-grid persistent kernel of this depth runs at once on the
+// current device (CUs x resident waves per CU); 1024 if the query fails.
+int blocked_wave_slots(size_t elem_bytes, int fuse);
 
 struct BlockedParams {
     int fuse = 0;       // full sweeps per pass

@@ -104,6 +104,35 @@ hipError_t persistent_occupancy(const void* kernel, int* per_cu, int* cus) {
     return hipSuccess;
 }
 
+namespace {
+template <typename T>
+const void* blocked_kernel_of(int fuse) {
+    constexpr int V = 16 / int(sizeof(T));
+    switch (fuse) {
+        case 1: return reinterpret_cast<const void*>(&k_blocked<T, V, 2>);
+        case 2: return reinterpret_cast<const void*>(&k_blocked<T, V, 4>);
+        case 3: return reinterpret_cast<const void*>(&k_blocked<T, V, 6>);
+        case 4: return reinterpret_cast<const void*>(&k_blocked<T, V, 8>);
+        case 5: return reinterpret_cast<const void*>(&k_blocked<T, V, 10>);
+        case 6: return reinterpret_cast<const void*>(&k_blocked<T, V, 12>);
+        case 7: return reinterpret_cast<const void*>(&k_blocked<T, V, 14>);
+        case 8: return reinterpret_cast<const void*>(&k_blocked<T, V, 16>);
+        case 9: return reinterpret_cast<const void*>(&k_blocked<T, V, 18>);
+        default: return reinterpret_cast<const void*>(&k_blocked<T, V, 20>);
+    }
+}
+}  // namespace
+
+int blocked_wave_slots(size_t elem_bytes, int fuse) {
+    const void* k = elem_bytes == 8 ? blocked_kernel_of<double>(fuse) : blocked_kernel_of<float>(fuse);
+    int per_cu = 0, cus = 0;
+    if (persistent_occupancy(k, &per_cu, &cus) != hipSuccess || cus < 1) {
+        (void)hipGetLastError();
+        return 1024;
+    }
+    return per_cu * cus;
+}
+
 size_t blocked_state_bytes(int n, int) { return 256 + align256(size_t(max_tiles(n)) * 4); }
 
 int validate_blocked_opts(int fuse, int tile_rows, int tile_cols, std::string* why) {
@@ -138,8 +167,10 @@ int auto_kernel(int n, size_t elem_bytes, int nsweeps) {
 BlockedParams blocked_params(int n, size_t elem_bytes, const rbgs_sweep_opts* o) {
     BlockedParams bp;
     bp.fuse = (o && o->fuse > 0) ? o->fuse : default_fuse(int(elem_bytes), n);
-    bp.tile_rows = (o && o->tile_rows > 0) ? o->tile_rows
-                                           : single_grid_rows(n, 2 * bp.fuse, int(elem_bytes));
+    bp.tile_rows = (o && o->tile_rows > 0)
+                       ? o->tile_rows
+                       : single_grid_rows(n, 2 * bp.fuse, int(elem_bytes),
+                                          blocked_wave_slots(elem_bytes, bp.fuse));
     if (bp.tile_rows < 2 * bp.fuse) bp.tile_rows = 2 * bp.fuse;  // halo rows must fit one strip
     bp.delay = o ? o->debug_delay : 0;
     bp.spin_limit = (o && o->debug_spin_limit > 0) ? o->debug_spin_limit : kDefaultSpinLimit;
