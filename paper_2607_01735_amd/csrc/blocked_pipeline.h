@@ -198,7 +198,7 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, FRing<T, V, L>& fr,
                                           const T* __restrict__ xr, const T* __restrict__ xb,
                                           T* __restrict__ yr, T* __restrict__ yb, int x, int xs,
                                           int xe, int r0, int r1, int64_t q0, int64_t qv,
-                                          int64_t qc0, int64_t qc1, bool in_core) {
+                                          int64_t qc0, int64_t qc1, bool in_core, bool store_red) {
     const int n = a.n;
     const int64_t P = a.pitch;
     const StepIn<T, V> cur = st.in[S % 3];
@@ -291,18 +291,21 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, FRing<T, V, L>& fr,
         // black (level L-1) and red (level L-2, still in level L-1's window)
         if constexpr (EDGE) {
             store_core<T, V>(yb + int64_t(y) * P, carry, q0, qc0, qc1, pmod(S - L + 1, 2), n);
-            store_core<T, V>(yr + int64_t(y) * P, st.win[L - 1][pmod(S - L, 3)], q0, qc0, qc1,
-                             pmod(S - L, 2), n);
+            if (store_red)
+                store_core<T, V>(yr + int64_t(y) * P, st.win[L - 1][pmod(S - L, 3)], q0, qc0,
+                                 qc1, pmod(S - L, 2), n);
         } else if (in_core) {
             *reinterpret_cast<Vec<T, V>*>(yb + int64_t(y) * P + q0) = carry;
-            *reinterpret_cast<Vec<T, V>*>(yr + int64_t(y) * P + q0) = st.win[L - 1][pmod(S - L, 3)];
+            if (store_red)
+                *reinterpret_cast<Vec<T, V>*>(yr + int64_t(y) * P + q0) =
+                    st.win[L - 1][pmod(S - L, 3)];
         }
     }
 }
 
 template <typename T, int V, int L, bool EDGE>
 __device__ __forceinline__ void run_tile(FRing<T, V, L>& fr, const GridDesc<T>& a, int pass, int r0,
-                                         int r1, int64_t qc0, int64_t qc1) {
+                                         int r1, int64_t qc0, int64_t qc1, bool store_red) {
     const int lane = threadIdx.x;
     const int64_t q0 = qc0 - a.halo_q + int64_t(lane) * V;
     // column actually loaded: q0 clamped into the row (lanes past the grid
@@ -326,20 +329,31 @@ __device__ __forceinline__ void run_tile(FRing<T, V, L>& fr, const GridDesc<T>& 
     st.in[0] = load_in<T, V, EDGE>(a, xr, xb, x0, qv);
     st.in[1] = load_in<T, V, EDGE>(a, xr, xb, x0 + 1, qv);
     for (int x = x0; x <= x_last; x += 6) {
-        pipe_step<T, V, L, 0, EDGE>(st, fr, a, xr, xb, yr, yb, x + 0, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
-        pipe_step<T, V, L, 1, EDGE>(st, fr, a, xr, xb, yr, yb, x + 1, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
-        pipe_step<T, V, L, 2, EDGE>(st, fr, a, xr, xb, yr, yb, x + 2, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
-        pipe_step<T, V, L, 3, EDGE>(st, fr, a, xr, xb, yr, yb, x + 3, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
-        pipe_step<T, V, L, 4, EDGE>(st, fr, a, xr, xb, yr, yb, x + 4, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
-        pipe_step<T, V, L, 5, EDGE>(st, fr, a, xr, xb, yr, yb, x + 5, xs, xe, r0, r1, q0, qv, qc0, qc1, in_core);
+        pipe_step<T, V, L, 0, EDGE>(st, fr, a, xr, xb, yr, yb, x + 0, xs, xe, r0, r1, q0, qv, qc0, qc1,
+                                    in_core, store_red);
+        pipe_step<T, V, L, 1, EDGE>(st, fr, a, xr, xb, yr, yb, x + 1, xs, xe, r0, r1, q0, qv, qc0, qc1,
+                                    in_core, store_red);
+        pipe_step<T, V, L, 2, EDGE>(st, fr, a, xr, xb, yr, yb, x + 2, xs, xe, r0, r1, q0, qv, qc0, qc1,
+                                    in_core, store_red);
+        pipe_step<T, V, L, 3, EDGE>(st, fr, a, xr, xb, yr, yb, x + 3, xs, xe, r0, r1, q0, qv, qc0, qc1,
+                                    in_core, store_red);
+        pipe_step<T, V, L, 4, EDGE>(st, fr, a, xr, xb, yr, yb, x + 4, xs, xe, r0, r1, q0, qv, qc0, qc1,
+                                    in_core, store_red);
+        pipe_step<T, V, L, 5, EDGE>(st, fr, a, xr, xb, yr, yb, x + 5, xs, xe, r0, r1, q0, qv, qc0, qc1,
+                                    in_core, store_red);
     }
 }
 
 // A tile is interior when every point it loads (core plus halo, both
 // colours) is an interior grid point: then no ring value needs to pass
 // through, no red input row is needed and every core vector is stored whole.
+// store_red: a pass reads only the black colour of its input (level 0
+// recomputes every interior red point from black), so the red colour is
+// written only by the launch's last pass, whose output leaves the kernel;
+// the Dirichlet ring, the only red input that is read, is never written.
 template <typename T, int V, int L>
-__device__ __forceinline__ void process_tile(const GridDesc<T>& a, int pass, int tile) {
+__device__ __forceinline__ void process_tile(const GridDesc<T>& a, int pass, int tile,
+                                             bool store_red) {
     const int strip = tile / a.bands;
     const int band = tile - strip * a.bands;
     const int r0 = 1 + strip * a.rows;
@@ -353,9 +367,9 @@ __device__ __forceinline__ void process_tile(const GridDesc<T>& a, int pass, int
                           qc1 - qc0 == a.q_core;
     __shared__ FRing<T, V, L> fr;
     if (interior)
-        run_tile<T, V, L, false>(fr, a, pass, r0, r1, qc0, qc1);
+        run_tile<T, V, L, false>(fr, a, pass, r0, r1, qc0, qc1, store_red);
     else
-        run_tile<T, V, L, true>(fr, a, pass, r0, r1, qc0, qc1);
+        run_tile<T, V, L, true>(fr, a, pass, r0, r1, qc0, qc1, store_red);
 }
 
 // Waits until the 3 x 3 neighbourhood of `tile` has finished pass-1.
@@ -408,7 +422,7 @@ __device__ __forceinline__ bool run_item(const GridDesc<T>& g, const Queue& qu, 
                          uint32_t(qu.delay + 1);
         for (uint32_t i = 0; i < loops; ++i) __builtin_amdgcn_s_sleep(127);
     }
-    process_tile<T, V, L>(g, pass + qu.buf_offset, tile);
+    process_tile<T, V, L>(g, pass + qu.buf_offset, tile, pass == qu.passes - 1);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (threadIdx.x == 0 && g.flag_base + tile + 1 != qu.stall_tile)
         __hip_atomic_store(qu.progress + g.flag_base + tile, pass + 1, __ATOMIC_RELAXED,

@@ -13,8 +13,9 @@
 // * Inside a tile the L half-sweeps are pipelined down the strip in
 //   registers: at input row x, level l (colour l & 1, red first) updates row
 //   x-1-l from the three other-colour rows that level l-1 produced last.
-//   Rows are visited once per pass, so HBM sees one read of u and f and one
-//   write of u per k sweeps.  Horizontal neighbours outside a lane's vector
+//   Rows are visited once per pass, so HBM sees one read of u (its black
+//   colour: level 0 recomputes red from it) and of f, and one write of
+//   black, per k sweeps; red is written by the last pass of a launch only.  Horizontal neighbours outside a lane's vector
 //   come from the adjacent lane (cross-lane shuffle).
 // * Overlapped tiling: a tile loads a halo of L rows above and below and
 //   halo_q columns left and right; values there are recomputed redundantly,
