@@ -76,13 +76,20 @@ __device__ __forceinline__ Vec<T, V> vzero() {
 
 // Inputs that a step consumes first-hand from HBM: the black and red rows x
 // of the pass input, and the right-hand sides of levels 0 and 1 (f_red row
-// x-1 and f_black row x-2, their first use).  They are loaded two steps
-// ahead; the right-hand sides of levels >= 2 are rows that levels 0 and 1
-// brought in earlier (kept in LDS).
+// x-1 and f_black row x-2, their first use).  The right-hand sides of levels
+// >= 2 are rows that levels 0 and 1 brought in earlier (kept in LDS).
 template <typename T, int V>
 struct StepIn {
     Vec<T, V> b, r, f0, f1;
 };
+
+// Steps ahead that a tile loads its inputs.  The deep pipelines run one
+// wave per SIMD, so the loads in flight alone must cover HBM latency: three
+// steps ahead was 5% faster than two for FP64 at 8191^2 and 2% at 4095^2
+// (four was no better than two); FP32 and the deepest pipelines (L > 14),
+// short of registers, keep two.
+template <typename T, int L>
+constexpr int prefetch_steps() { return sizeof(T) == 8 && L <= 14 ? 3 : 2; }
 
 // Whole-wave lane shifts through DPP (register to register, no LDS trip):
 // from_next_lane gives lane i the value of lane i+1 (wave_shl:1), and
@@ -127,7 +134,7 @@ template <typename T, int V, int L>
 struct Pipe {
     Vec<T, V> win[L][3];   // level l: other-colour rows (ring buffer of 3), version l-1
     Vec<T, V> red_in[2];   // red input rows x-1, x (ring values pass through level 0)
-    StepIn<T, V> in[3];    // inputs of steps x, x+1, x+2 (slot x mod 3)
+    StepIn<T, V> in[6];    // inputs of steps x .. x+D (slot x mod 6), D = prefetch_steps
 };
 
 // Right-hand-side rows of a wave (as the products h^2 f), kept in LDS for
@@ -201,9 +208,10 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, FRing<T, V, L>& fr,
                                           int64_t qc0, int64_t qc1, bool in_core, bool store_red) {
     const int n = a.n;
     const int64_t P = a.pitch;
-    const StepIn<T, V> cur = st.in[S % 3];
-    // prefetch: step x+2's rows into the slot step x-1 used
-    st.in[(S + 2) % 3] = load_in<T, V, EDGE>(a, xr, xb, x + 2, qv);
+    constexpr int D = prefetch_steps<T, L>();
+    const StepIn<T, V> cur = st.in[S];
+    // prefetch: step x+D's rows into a slot no pending step holds
+    st.in[(S + D) % 6] = load_in<T, V, EDGE>(a, xr, xb, x + D, qv);
     // this step's right-hand-side rows join the ring (red row x-1, black
     // row x-2) as the products h^2 f that Eq. (1) subtracts: each is formed
     // once here, not once per fused level (the same product, so the same
@@ -326,8 +334,9 @@ __device__ __forceinline__ void run_tile(FRing<T, V, L>& fr, const GridDesc<T>& 
         for (int r = 0; r < 3; ++r) st.win[l][r] = vzero<T, V>();
     st.red_in[0] = st.red_in[1] = vzero<T, V>();
     const int x0 = xs - xs % 6;
-    st.in[0] = load_in<T, V, EDGE>(a, xr, xb, x0, qv);
-    st.in[1] = load_in<T, V, EDGE>(a, xr, xb, x0 + 1, qv);
+#pragma unroll
+    for (int d = 0; d < prefetch_steps<T, L>(); ++d)
+        st.in[d] = load_in<T, V, EDGE>(a, xr, xb, x0 + d, qv);
     for (int x = x0; x <= x_last; x += 6) {
         pipe_step<T, V, L, 0, EDGE>(st, fr, a, xr, xb, yr, yb, x + 0, xs, xe, r0, r1, q0, qv, qc0, qc1,
                                     in_core, store_red);
