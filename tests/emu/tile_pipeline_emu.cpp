@@ -1,0 +1,180 @@
+// Runs the persistent tile pipeline of the blocked sweep (the device code in
+// paper_2607_01735_amd/csrc/blocked_pipeline.h, unchanged) on the CPU: one
+// emulated wave of 64 fibers takes every (pass, tile) ticket in order,
+// exactly as one wave of the persistent kernel would.  Every array the
+// pipeline touches is its own heap block of exactly the size the library
+// allocates, so an AddressSanitizer build reports any access outside them.
+// Test infrastructure only: tests/test_tile_pipeline_emu.py builds it and
+// compares the result with the oracle bit for bit.
+//
+// Build: g++ -std=c++17 -DEMU_T=double -DEMU_FUSE=7 -I tests/emu
+//            -I paper_2607_01735_amd/csrc -I include ...
+// Run:   emu n rows passes h in.bin out.bin
+//   in.bin  = u then f, natural (n+2) x (n+2) arrays of EMU_T, row major
+//   out.bin = u after passes x fuse full sweeps, same layout
+#include <hip/hip_runtime.h>
+
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <vector>
+
+#include "blocked_pipeline.h"
+#include "rbgs_blocked.h"
+
+namespace emu {
+int current = 0;
+jmp_buf lane_jmp[kLanes];
+bool lane_done[kLanes];
+uint64_t lane_slot[kLanes];
+}  // namespace emu
+
+// Fibers: each lane's stack is entered once through makecontext/swapcontext
+// (lane_start parks it with _setjmp and returns to the host); from then on
+// lanes switch with _setjmp/_longjmp.
+static ucontext_t g_host_ctx, g_start_ctx[emu::kLanes];
+static jmp_buf g_host_jmp;
+
+using namespace rbgs;
+using namespace rbgs::blocked;
+typedef EMU_T T;
+constexpr int kFuse = EMU_FUSE;
+constexpr int kL = 2 * kFuse;
+constexpr int kV = 16 / int(sizeof(T));
+
+static GridDesc<T> g_grid;
+static Queue g_queue;
+
+// The body of the persistent kernel for one wave, run by every lane fiber;
+// a finished lane hands over to the next live one, the last to the host.
+static void lane_start(int lane) {
+    if (_setjmp(emu::lane_jmp[lane]) == 0) swapcontext(&g_start_ctx[lane], &g_host_ctx);
+    const int total = g_queue.passes * g_grid.ntiles;
+    for (;;) {
+        const int tk = next_ticket(g_queue);
+        if (tk >= total) break;
+        const int pass = tk / g_grid.ntiles;
+        if (!run_item<T, kV, kL>(g_grid, g_queue, pass, tk - pass * g_grid.ntiles)) break;
+    }
+    emu::lane_done[lane] = true;
+    for (int k = 1; k < emu::kLanes; ++k) {
+        const int nx = (lane + k) % emu::kLanes;
+        if (!emu::lane_done[nx]) {
+            emu::current = nx;
+            _longjmp(emu::lane_jmp[nx], 1);
+        }
+    }
+    _longjmp(g_host_jmp, 1);
+}
+
+static T* block_of(size_t count) {
+    T* p = static_cast<T*>(malloc(count * sizeof(T)));
+    if (!p) abort();
+    for (size_t k = 0; k < count; ++k) p[k] = T(-12345);
+    return p;
+}
+
+int main(int argc, char** argv) {
+    if (argc != 7) {
+        fprintf(stderr, "usage: %s n rows passes h in.bin out.bin\n", argv[0]);
+        return 2;
+    }
+    const int n = atoi(argv[1]), rows = atoi(argv[2]), passes = atoi(argv[3]);
+    const double h = atof(argv[4]);
+    const Geometry geo = geometry(n, int(sizeof(T)), kFuse, rows < kL ? kL : rows);
+    if (geo.ntiles > max_tiles(n)) {
+        fprintf(stderr, "tile count %d above the state bound %d\n", geo.ntiles, max_tiles(n));
+        return 3;
+    }
+    const size_t W = size_t(n) + 2;
+    std::vector<T> u(W * W), f(W * W);
+    FILE* fin = fopen(argv[5], "rb");
+    if (!fin || fread(u.data(), sizeof(T), u.size(), fin) != u.size() ||
+        fread(f.data(), sizeof(T), f.size(), fin) != f.size()) {
+        fprintf(stderr, "cannot read %s\n", argv[5]);
+        return 2;
+    }
+    fclose(fin);
+    // split colour layout: point (i, j) of colour (i + j) & 1 at C[i][j >> 1]
+    const int64_t P = split_pitch(n, sizeof(T));
+    const size_t cells = W * size_t(P);
+    T* red[2] = {block_of(cells), block_of(cells)};
+    T* black[2] = {block_of(cells), block_of(cells)};
+    T* f_red = block_of(cells);
+    T* f_black = block_of(cells);
+    for (size_t i = 0; i < W; ++i)
+        for (size_t j = 0; j < W; ++j) {
+            const size_t at = i * size_t(P) + (j >> 1);
+            const bool is_red = ((i + j) & 1) == 0;
+            for (int b = 0; b < 2; ++b) (is_red ? red[b] : black[b])[at] = u[i * W + j];
+            (is_red ? f_red : f_black)[at] = f[i * W + j];
+        }
+    GridDesc<T>& g = g_grid;
+    g.red[0] = red[0];
+    g.red[1] = red[1];
+    g.black[0] = black[0];
+    g.black[1] = black[1];
+    g.f_red = f_red;
+    g.f_black = f_black;
+    g.n = n;
+    g.pitch = P;
+    g.h2 = T(h * h);
+    g.rows = geo.rows;
+    g.halo_q = geo.halo_q;
+    g.q_core = geo.q_core;
+    g.strips = geo.strips;
+    g.bands = geo.bands;
+    g.ntiles = geo.ntiles;
+    g.flag_base = 0;
+    Queue& qu = g_queue;
+    qu.passes = passes;
+    qu.progress = static_cast<int*>(calloc(size_t(geo.ntiles), sizeof(int)));
+    qu.ticket = static_cast<int*>(calloc(1, sizeof(int)));
+    qu.error = static_cast<int*>(calloc(1, sizeof(int)));
+    qu.spin_limit = 1 << 20;
+    qu.delay = 0;
+    qu.stall_tile = 0;
+    qu.buf_offset = 0;
+    const size_t stack_bytes = size_t(1) << 20;
+    std::vector<char*> stacks(emu::kLanes);
+    for (int l = 0; l < emu::kLanes; ++l) {
+        stacks[l] = static_cast<char*>(malloc(stack_bytes));
+        if (!stacks[l] || getcontext(&g_start_ctx[l]) != 0) abort();
+        g_start_ctx[l].uc_stack.ss_sp = stacks[l];
+        g_start_ctx[l].uc_stack.ss_size = stack_bytes;
+        g_start_ctx[l].uc_link = nullptr;
+        makecontext(&g_start_ctx[l], reinterpret_cast<void (*)()>(lane_start), 1, l);
+        emu::lane_done[l] = false;
+        if (swapcontext(&g_host_ctx, &g_start_ctx[l]) != 0) abort();  // parks lane l
+    }
+    if (_setjmp(g_host_jmp) == 0) {
+        emu::current = 0;
+        _longjmp(emu::lane_jmp[0], 1);
+    }
+    for (int l = 0; l < emu::kLanes; ++l) free(stacks[l]);
+    if (*qu.error != 0) {
+        fprintf(stderr, "the pipeline raised its error word\n");
+        return 4;
+    }
+    const int out = passes & 1;
+    for (size_t i = 0; i < W; ++i)
+        for (size_t j = 0; j < W; ++j) {
+            const size_t at = i * size_t(P) + (j >> 1);
+            u[i * W + j] = (((i + j) & 1) == 0 ? red[out] : black[out])[at];
+        }
+    FILE* fout = fopen(argv[6], "wb");
+    if (!fout || fwrite(u.data(), sizeof(T), u.size(), fout) != u.size()) return 2;
+    fclose(fout);
+    printf("n=%d rows=%d passes=%d fuse=%d tiles=%d halo_q=%d q_core=%d\n", n, geo.rows, passes,
+           kFuse, geo.ntiles, geo.halo_q, geo.q_core);
+    for (int b = 0; b < 2; ++b) {
+        free(red[b]);
+        free(black[b]);
+    }
+    free(f_red);
+    free(f_black);
+    free(qu.progress);
+    free(qu.ticket);
+    free(qu.error);
+    return 0;
+}
