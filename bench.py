@@ -439,14 +439,14 @@ def main():
         # The persistent blocked kernel: each launch runs `passes` passes of
         # `fuse` fused sweeps; per pass the algorithmic traffic is one read of
         # u and f and one write of u, 3 words per point.  Its duration comes
-        # from HIP events around the persistent launches alone (remainder
-        # sweeps and the ring copy into the second buffer are outside).
+        # from HIP events around the launch of the deeper passes alone (the
+        # passes one sweep shallower and the ring copies are outside).
         kernel_used, fuse = "blocked", acc["fuse"]
         launches = acc["persistent_launches"]
         avg_launch_ms = acc["persistent_ms"] / launches
         per_launch_bytes = BYTES_PER_LUP["f64"] * n * n * acc["passes"] / launches
-        tail = 1 if sweeps % fuse >= 2 else 0  # one shallower pass per step
-        bytes_per_lup = BYTES_PER_LUP["f64"] * (sweeps // fuse + tail) / sweeps
+        # a step runs ceil(sweeps / fuse) passes (depths differ by at most one)
+        bytes_per_lup = BYTES_PER_LUP["f64"] * (-(-sweeps // fuse)) / sweeps
         kname = f"k_blocked<double,2,{2 * fuse}> (persistent, fuse {fuse})"
         traffic_key = "blocked_f64"
     else:

@@ -107,18 +107,20 @@ typedef struct {
     float sweep_ms;         /* all sweep kernels (half-sweeps or blocked passes) */
     float unpack_ms;        /* split -> natural unpacking of u                */
     int32_t sweep_launches; /* kernel launches inside sweep_ms                */
-    float persistent_ms;    /* BLOCKED: the launches of full fuse-deep passes
-                               alone (no ring copies, no shallower remainder
-                               pass); RESIDENT: its launches                  */
+    float persistent_ms;    /* BLOCKED: the launch(es) of the deeper passes
+                               alone (no ring copies, no passes one sweep
+                               shallower); RESIDENT: its launches             */
     int32_t persistent_launches; /* launches inside persistent_ms             */
     int32_t passes;         /* BLOCKED: passes those launches ran             */
-    int32_t fuse;           /* BLOCKED: full sweeps per pass (0 otherwise)    */
+    int32_t fuse;           /* BLOCKED: sweeps per pass in those launches     */
 } rbgs_timing;
 
 /* Kernel selection for sweeps.  Zero-initialise for the library defaults. */
 typedef struct {
     int32_t kernel;     /* rbgs_kernel                                         */
-    int32_t fuse;       /* BLOCKED: full sweeps per pass (1..10), 0 = default   */
+    int32_t fuse;       /* BLOCKED: most sweeps per pass (1..10), 0 = default;
+                           nsweeps runs as ceil(nsweeps / fuse) passes whose
+                           depths differ by at most one                      */
     int32_t tile_rows;  /* BLOCKED: interior rows per tile, 0 = default        */
     int32_t tile_cols;  /* BLOCKED: interior columns per tile, 0 = default     */
     int32_t rows_per_block; /* PLAIN: rows each workgroup marches, 0 = default */

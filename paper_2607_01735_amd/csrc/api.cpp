@@ -265,16 +265,16 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
         T* const bred[2] = {ur, static_cast<T*>(w.u2_red)};
         T* const bblack[2] = {ub, static_cast<T*>(w.u2_black)};
         const bool timed = pt && pt->on;
-        int plaunches = 0, passes = 0;
+        int plaunches = 0, passes = 0, depth = 0;
         HIP_TRY(run_blocked<T>(bred, bblack, fr, fb, n, w.pitch, h2, nsweeps, bp, w.blocked,
                                w.blocked_bytes, s, launches, timed ? pt->ev[0] : nullptr,
-                               timed ? pt->ev[1] : nullptr, &plaunches, &passes),
+                               timed ? pt->ev[1] : nullptr, &plaunches, &passes, &depth),
                 "blocked sweep");
         if (timed && plaunches > 0) {
             pt->armed = true;
             pt->launches += plaunches;
             pt->passes += passes;
-            pt->fuse = bp.fuse;
+            pt->fuse = depth;
         }
         *err_state = w.blocked;
         return RBGS_OK;

@@ -1,5 +1,6 @@
 // Layout kernels: natural <-> split colour layout, FP64 -> FP32 packing,
-// the FP64 correction u <- u + e of iterative refinement, and a zero fill.
+// the FP64 correction u <- u + e of iterative refinement, a copy of the
+// Dirichlet ring between split grids, and a zero fill.
 // All are single streaming passes; one thread handles one (row, q) pair,
 // i.e. the two natural elements (i, 2q) and (i, 2q+1).
 #include "rbgs_internal.h"
@@ -23,6 +24,29 @@ __global__ __launch_bounds__(kThreads) void k_pack(const W* __restrict__ nat, in
     const W* row = nat + i * ld;
     even_dst[i * pitch + q] = (j0 <= n + 1) ? row[j0] : W(0);
     odd_dst[i * pitch + q] = (j1 <= n + 1) ? row[j1] : W(0);
+}
+
+// The Dirichlet ring of a split grid, both colours: rows 0 and n+1 whole,
+// and in every other row the q-columns 0 and (n+1)/2, which hold j = 0 and
+// j = n+1 in one of the two colours (the other colour's interior point at
+// those q comes along, harmlessly).  One workgroup per row.
+template <typename W>
+__global__ __launch_bounds__(64) void k_copy_ring(W* __restrict__ dst_red, W* __restrict__ dst_black,
+                                                  const W* __restrict__ src_red,
+                                                  const W* __restrict__ src_black, int n,
+                                                  int64_t pitch) {
+    const int64_t i = blockIdx.x;
+    const int64_t at = i * pitch;
+    if (i == 0 || i == int64_t(n) + 1) {
+        for (int64_t q = threadIdx.x; q < pitch; q += 64) {
+            dst_red[at + q] = src_red[at + q];
+            dst_black[at + q] = src_black[at + q];
+        }
+    } else if (threadIdx.x < 2) {
+        const int64_t q = threadIdx.x == 0 ? 0 : (int64_t(n) + 1) >> 1;
+        dst_red[at + q] = src_red[at + q];
+        dst_black[at + q] = src_black[at + q];
+    }
 }
 
 template <typename W>
@@ -126,6 +150,23 @@ hipError_t launch_add_correction(double* u_red, double* u_black, int64_t pitch,
     dim3 grid(unsigned((pitch + kThreads - 1) / kThreads), unsigned(n));
     hipLaunchKernelGGL(k_add_correction, grid, dim3(kThreads), 0, s, u_red, u_black, pitch, e_red,
                        e_black, e_pitch, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_ring(void* dst_red, void* dst_black, const void* src_red,
+                            const void* src_black, int n, int64_t pitch, int elem_bytes,
+                            hipStream_t s) {
+    const dim3 grid(unsigned(n + 2));
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_copy_ring<uint64_t>, grid, dim3(64), 0, s,
+                           static_cast<uint64_t*>(dst_red), static_cast<uint64_t*>(dst_black),
+                           static_cast<const uint64_t*>(src_red),
+                           static_cast<const uint64_t*>(src_black), n, pitch);
+    else
+        hipLaunchKernelGGL(k_copy_ring<uint32_t>, grid, dim3(64), 0, s,
+                           static_cast<uint32_t*>(dst_red), static_cast<uint32_t*>(dst_black),
+                           static_cast<const uint32_t*>(src_red),
+                           static_cast<const uint32_t*>(src_black), n, pitch);
     return hipGetLastError();
 }
 

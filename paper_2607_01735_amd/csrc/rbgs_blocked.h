@@ -112,18 +112,18 @@ int auto_kernel(int n, size_t elem_bytes, int nsweeps);
 BlockedParams blocked_params(int n, size_t elem_bytes, const rbgs_sweep_opts* o);
 // nsweeps sweeps of the split iterate in buffer 0 (buf_red[0], buf_black[0])
 // with the persistent kernel; buffer 1 is scratch of the same size.  The
-// result is left in buffer 0.  Sweeps that do not fill a whole pass of
-// `fuse` sweeps run as one shallower pass (a single one with the plain
-// kernel).  When ev_begin/ev_end are given
-// they are recorded right before the first and after the last full-depth
-// persistent launch (around the shallower pass when there is no full one);
-// *persistent_launches and *passes_done receive what those launches did.
+// result is left in buffer 0.  The sweeps run as ceil(nsweeps / fuse)
+// passes whose depths differ by at most one (one launch of the deeper
+// passes, then one of the shallower ones); a single sweep runs with the
+// plain kernel.  When ev_begin/ev_end are given they are recorded around the
+// launch(es) of the deeper passes; *persistent_launches, *passes_done and
+// *timed_fuse receive what those launches did.
 template <typename T>
 hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_red,
                        const T* f_black, int n, int64_t pitch, T h2, int nsweeps,
                        const BlockedParams& bp, void* state, size_t state_bytes, hipStream_t s,
                        int* launches, hipEvent_t ev_begin, hipEvent_t ev_end,
-                       int* persistent_launches, int* passes_done);
+                       int* persistent_launches, int* passes_done, int* timed_fuse);
 // Reads the persistent kernel's error word (synchronising the stream when
 // the kernel ran); returns RBGS_OK or RBGS_ETIMEOUT.
 int blocked_check_error(void* state, hipStream_t s, std::string* why);

@@ -99,6 +99,12 @@ hipError_t launch_prolong(const T* coarse, int64_t coarse_ld, int64_t coarse_str
                           hipStream_t s);
 
 // Zero a device range with a kernel (usable inside graph capture).
+// Copies the Dirichlet ring (and nothing that a pass would not overwrite
+// before reading) of split grid src into dst; n + 2 rows of `pitch` elements.
+hipError_t launch_copy_ring(void* dst_red, void* dst_black, const void* src_red,
+                            const void* src_black, int n, int64_t pitch, int elem_bytes,
+                            hipStream_t s);
+
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
 }  // namespace rbgs

@@ -184,24 +184,20 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
                        const T* f_black, int n, int64_t pitch, T h2, int nsweeps,
                        const BlockedParams& bp, void* state, size_t state_bytes, hipStream_t s,
                        int* launches, hipEvent_t ev_begin, hipEvent_t ev_end,
-                       int* persistent_launches, int* passes_done) {
+                       int* persistent_launches, int* passes_done, int* timed_fuse) {
     constexpr int V = 16 / int(sizeof(T));
     *persistent_launches = 0;
     *passes_done = 0;
+    *timed_fuse = 0;
     *launches = 0;
     const int k = bp.fuse;
-    const int passes = nsweeps / k;
-    const int rem = nsweeps - passes * k;
     const size_t colour_bytes = size_t(n + 2) * size_t(pitch) * sizeof(T);
     char* base = static_cast<char*>(state);
     // the error word starts at zero once per call; tickets and flags before
     // every launch (an error seen by an earlier launch must survive)
     hipError_t e = launch_zero(base, 256, s);
     if (e != hipSuccess) return e;
-    // A remainder of two or more sweeps runs as one shallower pass of the
-    // same kernel; a single leftover sweep runs with the plain kernel.
-    const int tail_fuse = rem >= 2 ? rem : 0;
-    if (passes == 0 && tail_fuse == 0) {
+    if (nsweeps < 2) {  // a single sweep does not pay for a persistent launch
         for (int it = 0; it < nsweeps; ++it) {
             e = launch_half_sweep<T>(buf_red[0], buf_black[0], f_red, n, pitch, h2, 0, 0, s);
             if (e != hipSuccess) return e;
@@ -211,10 +207,20 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
         }
         return hipSuccess;
     }
-    // the second buffer needs the Dirichlet ring: start from a full copy
-    e = hipMemcpyAsync(buf_red[1], buf_red[0], colour_bytes, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(buf_black[1], buf_black[0], colour_bytes, hipMemcpyDeviceToDevice, s);
+    // ceil(nsweeps / k) passes whose depths differ by at most one: n_hi of
+    // depth d_hi, then n_lo of depth d_hi - 1 (200 sweeps at k = 7: 26 x 7 +
+    // 3 x 6), rather than full passes and one much shallower remainder pass,
+    // whose fixed cost per pass buys few sweeps
+    const int total_passes = (nsweeps + k - 1) / k;
+    const int d_hi = (nsweeps + total_passes - 1) / total_passes;
+    const int n_hi = nsweeps - total_passes * (d_hi - 1);
+    const int n_lo = total_passes - n_hi;
+    // The second buffer needs the Dirichlet ring, and only that: a pass
+    // writes every interior black point of its output before the next pass
+    // reads it, and reads no interior red point (red is written by the last
+    // pass of a launch only).
+    e = launch_copy_ring(buf_red[1], buf_black[1], buf_red[0], buf_black[0], n, pitch,
+                         int(sizeof(T)), s);
     if (e != hipSuccess) return e;
     int cur = 0;  // buffer holding the current iterate
     bool started = false;
@@ -278,30 +284,20 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
         }
         return hipSuccess;
     };
-    // the events time the full-depth passes (the tail pass when there are
-    // none), so that their duration is that of one kernel
-    if (passes > 0 && (e = run_passes(k, passes, true)) != hipSuccess) return e;
+    // the events time the n_hi passes of depth d_hi, so that their duration
+    // is that of one kernel
+    if ((e = run_passes(d_hi, n_hi, true)) != hipSuccess) return e;
     if (ev_end && started) {
         e = hipEventRecord(ev_end, s);
         if (e != hipSuccess) return e;
     }
-    if (tail_fuse > 0 && (e = run_passes(tail_fuse, 1, passes == 0)) != hipSuccess) return e;
-    if (ev_end && passes == 0 && started) {
-        e = hipEventRecord(ev_end, s);
-        if (e != hipSuccess) return e;
-    }
+    *timed_fuse = d_hi;
+    if (n_lo > 0 && (e = run_passes(d_hi - 1, n_lo, false)) != hipSuccess) return e;
     if (cur != 0) {
         e = hipMemcpyAsync(buf_red[0], buf_red[1], colour_bytes, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
         e = hipMemcpyAsync(buf_black[0], buf_black[1], colour_bytes, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
-    }
-    if (rem == 1) {
-        e = launch_half_sweep<T>(buf_red[0], buf_black[0], f_red, n, pitch, h2, 0, 0, s);
-        if (e != hipSuccess) return e;
-        e = launch_half_sweep<T>(buf_black[0], buf_red[0], f_black, n, pitch, h2, 1, 0, s);
-        if (e != hipSuccess) return e;
-        *launches += 2;
     }
     return hipSuccess;
 }
@@ -309,11 +305,11 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
 template hipError_t run_blocked<double>(double* const[2], double* const[2], const double*,
                                         const double*, int, int64_t, double, int,
                                         const BlockedParams&, void*, size_t, hipStream_t, int*,
-                                        hipEvent_t, hipEvent_t, int*, int*);
+                                        hipEvent_t, hipEvent_t, int*, int*, int*);
 template hipError_t run_blocked<float>(float* const[2], float* const[2], const float*,
                                        const float*, int, int64_t, float, int,
                                        const BlockedParams&, void*, size_t, hipStream_t, int*,
-                                       hipEvent_t, hipEvent_t, int*, int*);
+                                       hipEvent_t, hipEvent_t, int*, int*, int*);
 
 int blocked_check_error(void* state, hipStream_t s, std::string* why) {
     int err = 0;

@@ -53,7 +53,8 @@ CASES = [  # n, sweeps, fuse, tile_rows (0 = default)
     (7, 11, 5, 8), (200, 30, 5, 16), (255, 26, 6, 0), (511, 43, 6, 14), (1023, 40, 7, 0),
     (1500, 21, 7, 32), (2047, 36, 6, 0), (3000, 14, 7, 0),
     (9, 17, 8, 16), (333, 40, 8, 0), (1023, 27, 9, 24), (1200, 50, 10, 20), (4095, 30, 10, 0),
-    (100, 3, 7, 16), (700, 9, 5, 0), (2048, 11, 9, 0),  # remainders run as a shallower pass
+    (100, 3, 7, 16), (700, 9, 5, 0), (2048, 11, 9, 0),  # passes of two depths
+    (300, 13, 4, 8), (255, 200, 7, 0),                 # 4 + 3 x 3; 26 x 7 + 3 x 6
 ]
 
 
@@ -161,3 +162,16 @@ def test_blocked_large_grid_sampled(oracle):
     for p, r in zip(pts, ref):
         assert got[p] == r, f"point {p}: {got[p]!r} vs {r!r}"
     assert np.all(np.isfinite(got))
+
+
+@pytest.mark.parametrize("nsweeps,fuse,deep,passes", [(200, 7, 7, 26), (14, 7, 7, 2), (13, 7, 7, 1),
+                                                      (8, 7, 4, 2), (3, 7, 3, 1)])
+def test_blocked_pass_split(nsweeps, fuse, deep, passes):
+    """nsweeps run as ceil(nsweeps / fuse) passes whose depths differ by at
+    most one; the timing reports the launch of the deeper ones."""
+    say(f"blocked pass split nsweeps={nsweeps} fuse={fuse}")
+    n = 127
+    u0, f = start(n, 5)
+    ut, ft = dev(u0), dev(f)
+    t = rb.rbgs_sweep(ut, ft, nsweeps, h=W.spacing(n), kernel="blocked", fuse=fuse, timing=True)
+    assert t["fuse"] == deep and t["passes"] == passes, t
