@@ -133,6 +133,12 @@ typedef struct {
                                and the call returns RBGS_ETIMEOUT (watchdog
                                test; every wave still exits)                   */
     rbgs_timing *timing;    /* HOST pointer or NULL (see rbgs_timing)          */
+    int32_t lds_max_n;      /* BATCHED: grids with n <= lds_max_n whose iterate
+                               and h^2 f fit in one workgroup's LDS are swept
+                               there, one workgroup per grid, for all sweeps
+                               of the call; the others go through the
+                               persistent tiles.  0 = tuned or default (127
+                               FP32, 63 FP64), -1 = never.  Ignored elsewhere. */
 } rbgs_sweep_opts;
 
 /* Solve options.  Zero-initialise, then set what is needed. */
@@ -202,7 +208,9 @@ int rbgs_solve(const rbgs_grid *g, rbgs_dtype dt, void *u, const void *f,
  * items are (pass, grid, tile) of the persistent blocked kernel, handed out
  * pass by pass with the largest grids first; each grid's tiles follow the
  * same dependency rule as a single grid, so every grid's result is bitwise
- * what rbgs_sweep gives it alone.  count in [1, 65535].
+ * what rbgs_sweep gives it alone.  Small grids (opts->lds_max_n) are instead
+ * swept entirely in one workgroup's LDS, with the same operations in the
+ * same order, hence the same bits.  count in [1, 65535].
  * opts: kernel must be AUTO or BLOCKED; fuse/tile_rows 0 take the values
  * rbgs_autotune_batched stored for this batch shape (else the defaults).
  * --------------------------------------------------------------------- */
@@ -238,9 +246,11 @@ int rbgs_batch_plan_check(rbgs_batch_plan *plan, void *stream);
 int rbgs_batch_plan_destroy(rbgs_batch_plan *plan);
 
 /* Autotuner: times the persistent kernel on this batch for fusion depths
- * {2, 3, 4} and tile heights {64, 128, 256} (two passes each after a
+ * {4, 5, 6, 7} and tile heights {64, 128, 256} (two passes each after a
  * warm-up pass; the workspace copies are swept, u and f are only read),
- * stores the fastest choice for the batch shape (dtype, CU count and the
+ * then, for the best of those, the LDS-resident threshold (lds_max_n: the
+ * default, or never), and stores the fastest choice for the batch shape
+ * (dtype, CU count and the
  * multiset of grid sizes) in a process-wide table, appends it to the file
  * named by the environment variable RBGS_TUNE_CACHE if set (and reads that
  * file on first use), and returns it in *best (HOST, may be NULL) with its

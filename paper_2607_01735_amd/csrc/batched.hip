@@ -10,8 +10,11 @@
 // Each grid keeps its own progress flags (offset flag_base); its tiles wait
 // only on their own 3 x 3 neighbourhood.
 //
-// A grid of a few tens of points fits in one tile: it is then a chain of
-// passes that other grids' tiles interleave with; no separate code path.
+// Small grids (n <= lds_max_n, default 127 in FP32 and 63 in FP64, when
+// both colours of u and of h^2 f fit in one workgroup's LDS) leave the tile
+// queue: k_batch_lds sweeps each in one workgroup, all sweeps of the call
+// in LDS, before the persistent launch.  A 63^2 grid would otherwise be one
+// 64-lane tile with a halo as wide as the grid, for every pass.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -139,12 +142,100 @@ struct EventPair {
     }
 };
 
+constexpr int kLdsThreads = 512;
+
+// LDS bytes that k_batch_lds needs for an n x n grid: both colours of u and
+// of h^2 f, (n + 2) rows of (n + 3) / 2 elements each.
+inline size_t lds_grid_bytes(int n, size_t es) {
+    return 4 * size_t(n + 2) * size_t((n + 3) / 2) * es;
+}
+
+// Largest dynamic LDS one workgroup may use on the current device.
+inline size_t lds_limit_bytes() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess ||
+        v <= 0) {
+        (void)hipGetLastError();
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            return 0;
+    }
+    return size_t(v);
+}
+
+// One colour's half-sweep of an LDS-resident grid.  Split layout with row
+// pitch pl: colour c holds (i, j = 2q + ((i + c) & 1)) at [i][q]; the
+// other colour's neighbours of that point sit at [i +- 1][q] and at
+// [i][(j +- 1) / 2].  Same operations, same order as every other kernel.
+template <typename T, int C>
+__device__ __forceinline__ void lds_half_sweep(T* __restrict__ self, const T* __restrict__ other,
+                                               const T* __restrict__ hf, int n, int pl) {
+    const int items = n * pl;
+    for (int k = threadIdx.x; k < items; k += kLdsThreads) {
+        const int i = 1 + k / pl;
+        const int q = k - (i - 1) * pl;
+        const int j = 2 * q + ((i + C) & 1);
+        if (j < 1 || j > n) continue;
+        T s = other[(i + 1) * pl + q] + other[(i - 1) * pl + q];
+        s = s + other[i * pl + ((j + 1) >> 1)];
+        s = s + other[i * pl + ((j - 1) >> 1)];
+        s = s - hf[i * pl + q];
+        self[i * pl + q] = T(0.25) * s;
+    }
+}
+
+// One workgroup per small grid: loads buffer 0 (both colours) and h^2 f into
+// LDS, runs nsweeps red-then-black sweeps there with a barrier after each
+// colour (the barriers of Algorithm 1 inside one workgroup), and writes the
+// iterate to buffer `out`, the one the unpack reads.
+template <typename T>
+__global__ __launch_bounds__(kLdsThreads) void k_batch_lds(const GridDesc<T>* __restrict__ descs,
+                                                           const int* __restrict__ ids,
+                                                           int nsweeps, int out) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int gi = __builtin_amdgcn_readfirstlane(ids[blockIdx.x]);
+    const GridDesc<T>& g = descs[gi];
+    const int n = g.n;
+    const int64_t P = g.pitch;
+    const int pl = (n + 3) / 2;
+    const int cells = (n + 2) * pl;
+    T* ur = reinterpret_cast<T*>(lds_raw);
+    T* ub = ur + cells;
+    T* hr = ub + cells;
+    T* hb = hr + cells;
+    const T h2 = g.h2;
+    for (int k = threadIdx.x; k < cells; k += kLdsThreads) {
+        const int i = k / pl;
+        const int64_t at = int64_t(i) * P + (k - i * pl);
+        ur[k] = g.red[0][at];
+        ub[k] = g.black[0][at];
+        hr[k] = h2 * g.f_red[at];
+        hb[k] = h2 * g.f_black[at];
+    }
+    __syncthreads();
+    for (int sw = 0; sw < nsweeps; ++sw) {
+        lds_half_sweep<T, 0>(ur, ub, hr, n, pl);
+        __syncthreads();
+        lds_half_sweep<T, 1>(ub, ur, hb, n, pl);
+        __syncthreads();
+    }
+    T* yr = g.red[out];
+    T* yb = g.black[out];
+    for (int k = threadIdx.x; k < cells; k += kLdsThreads) {
+        const int i = k / pl;
+        const int64_t at = int64_t(i) * P + (k - i * pl);
+        yr[at] = ur[k];
+        yb[at] = ub[k];
+    }
+}
+
 size_t elem_bytes_of(rbgs_dtype dt) { return dt == RBGS_F64 ? 8 : 4; }
 
 // Workspace layout of a batch: queue header, flags, tables, then the split
 // arrays of every grid (u twice, f once; two colours each).
 struct BatchLayout {
-    size_t header = 0, flags = 0, gdesc = 0, pdesc = 0, tile_map = 0, arrays = 0, total = 0;
+    size_t header = 0, flags = 0, gdesc = 0, pdesc = 0, tile_map = 0, small = 0, arrays = 0,
+           total = 0;
     std::vector<size_t> grid_off;  // offset of each grid's six colour arrays
     std::vector<int64_t> pitch;
     int max_tiles_total = 0;
@@ -167,6 +258,8 @@ BatchLayout batch_layout(int count, const rbgs_grid* grids, rbgs_dtype dt) {
     off += align256(size_t(count) * sizeof(PackDesc));
     b.tile_map = off;
     off += align256(size_t(tiles) * 4);
+    b.small = off;
+    off += align256(size_t(count) * 4);
     b.arrays = off;
     b.grid_off.resize(count);
     b.pitch.resize(count);
@@ -185,12 +278,20 @@ struct BatchSetup {
     std::vector<char> gdesc;    // GridDesc<T> table, LPT order of tiles
     std::vector<PackDesc> pdesc;
     std::vector<int> tile_map;
+    std::vector<int> small_ids;  // grids swept LDS-resident by k_batch_lds
+    size_t small_lds_bytes = 0;  // dynamic LDS for the largest of them
 };
+
+// Built-in LDS-resident threshold: the largest grid of the batch sizes in
+// the benchmark mix that fits (127 in FP32: 133 KB; 63 in FP64: 68 KB).
+inline int default_lds_max_n(size_t es) { return es == 4 ? 127 : 63; }
 
 template <typename T>
 BatchSetup build_setup(int count, const rbgs_grid* grids, void* const* u, const void* const* f,
-                       const BatchLayout& lay, char* ws, int fuse, int rows_opt, int nsweeps) {
+                       const BatchLayout& lay, char* ws, int fuse, int rows_opt, int nsweeps,
+                       int lds_max_n) {
     BatchSetup s;
+    const size_t lds_limit = lds_max_n > 0 ? lds_limit_bytes() : 0;
     s.fuse = fuse;
     s.passes = nsweeps / fuse;
     s.rem = nsweeps - s.passes * fuse;
@@ -248,6 +349,13 @@ BatchSetup build_setup(int count, const rbgs_grid* grids, void* const* u, const 
     s.total_rows = row;
     for (int k = 0; k < count; ++k) {
         const int g = order[k];
+        const size_t lds = lds_grid_bytes(grids[g].n, es);
+        if (grids[g].n <= lds_max_n && lds <= lds_limit) {
+            s.small_ids.push_back(g);
+            s.small_lds_bytes = std::max(s.small_lds_bytes, lds);
+            gd[g].flag_base = 0;
+            continue;
+        }
         gd[g].flag_base = flag;
         for (int t = 0; t < gd[g].ntiles; ++t) s.tile_map.push_back(g);
         flag += gd[g].ntiles;
@@ -320,8 +428,21 @@ hipError_t enqueue_batch(const BatchSetup& su, const BatchLayout& lay, char* ws,
     // pass of the remaining sweeps; its smaller depth fits the same tiles,
     // whose halo was sized for `fuse`
     const int launches[2][2] = {{su.fuse, su.passes}, {su.rem, su.rem > 0 ? 1 : 0}};
+    const int final_parity = (su.passes + (su.rem > 0 ? 1 : 0)) & 1;
+    if (!su.small_ids.empty()) {
+        // the LDS-resident grids: all their sweeps in one launch, written to
+        // the buffer the unpack reads
+        const int nsweeps = su.passes * su.fuse + su.rem;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_lds<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(su.small_lds_bytes));
+        hipLaunchKernelGGL((k_batch_lds<T>), dim3(unsigned(su.small_ids.size())), dim3(kLdsThreads),
+                           su.small_lds_bytes, s, gd, reinterpret_cast<const int*>(ws + lay.small),
+                           nsweeps, final_parity);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     for (const auto& lp : launches) {
-        if (lp[1] == 0) continue;
+        if (lp[1] == 0 || su.total_tiles == 0) continue;
         if ((e = launch_zero(ws + lay.header, 64, s)) != hipSuccess) return e;
         if ((e = launch_zero(ws + lay.flags, size_t(su.total_tiles) * 4, s)) != hipSuccess) return e;
         qu.passes = lp[1];
@@ -330,6 +451,7 @@ hipError_t enqueue_batch(const BatchSetup& su, const BatchLayout& lay, char* ws,
             return e;
         parity = (parity + lp[1]) & 1;
     }
+    parity = final_parity;
     if (do_unpack) {
         hipLaunchKernelGGL((k_batch_unpack<typename std::conditional<sizeof(T) == 8, uint64_t, uint32_t>::type>),
                            dim3(unsigned(su.total_rows)), dim3(256), 0, s, pd, count, parity);
@@ -365,6 +487,7 @@ int validate_batch(int32_t count, const rbgs_grid* grids, int dt, void* const* u
         if (o->tile_rows != 0 && o->tile_rows < kMinRows)
             return bfail(RBGS_EINVAL, "tile_rows must be >= 8 (0 = default)");
         if (o->tile_cols != 0) return bfail(RBGS_EINVAL, "tile_cols must be 0");
+        if (o->lds_max_n < -1) return bfail(RBGS_EINVAL, "lds_max_n must be >= -1");
         if (o->debug_delay < 0 || o->debug_delay > 1000 || o->debug_spin_limit < 0 ||
             o->debug_stall_tile < 0)
             return bfail(RBGS_EINVAL, "bad debug option");
@@ -381,9 +504,13 @@ int check_ws(void* ws, size_t bytes, size_t need) {
     return RBGS_OK;
 }
 
+
 // --- autotuner cache --------------------------------------------------------
+struct Tuned {
+    int fuse, rows, lds_max_n;
+};
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune;  // key -> (fuse, rows)
+std::map<std::string, Tuned> g_tune;  // batch shape -> tuned parameters
 
 std::string tune_key(int count, const rbgs_grid* grids, int dt) {
     std::map<int, int> hist;
@@ -391,7 +518,7 @@ std::string tune_key(int count, const rbgs_grid* grids, int dt) {
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    std::string k = std::string(dt == RBGS_F64 ? "f64" : "f32") + "/cu" + std::to_string(cus);
+    std::string k = std::string(dt == RBGS_F64 ? "v2/f64" : "v2/f32") + "/cu" + std::to_string(cus);
     for (auto& kv : hist) k += "/" + std::to_string(kv.first) + "x" + std::to_string(kv.second);
     return k;
 }
@@ -404,37 +531,44 @@ void load_tune_file() {
     if (!path) return;
     FILE* fp = std::fopen(path, "r");
     if (!fp) return;
-    char key[4096];
-    int fuse = 0, rows = 0;
-    float ms = 0.f;
-    while (std::fscanf(fp, "%4095s %d %d %f", key, &fuse, &rows, &ms) == 4)
-        if (fuse >= 1 && fuse <= kMaxFuse && rows >= kMinRows) g_tune[key] = {fuse, rows};
+    // one entry per line: key fuse rows lds_max_n ms (other lines are skipped)
+    char line[4352], key[4096];
+    while (std::fgets(line, sizeof line, fp)) {
+        int fuse = 0, rows = 0, lds = 0;
+        float ms = 0.f;
+        if (std::sscanf(line, "%4095s %d %d %d %f", key, &fuse, &rows, &lds, &ms) == 5 &&
+            fuse >= 1 && fuse <= kMaxFuse && rows >= kMinRows && lds >= -1)
+            g_tune[key] = Tuned{fuse, rows, lds};
+    }
     std::fclose(fp);
 }
 
-void store_tune(const std::string& key, int fuse, int rows, float ms) {
-    g_tune[key] = {fuse, rows};
+void store_tune(const std::string& key, const Tuned& t, float ms) {
+    g_tune[key] = t;
     const char* path = std::getenv("RBGS_TUNE_CACHE");
     if (!path) return;
     FILE* fp = std::fopen(path, "a");
     if (!fp) return;
-    std::fprintf(fp, "%s %d %d %.6f\n", key.c_str(), fuse, rows, double(ms));
+    std::fprintf(fp, "%s %d %d %d %.6f\n", key.c_str(), t.fuse, t.rows, t.lds_max_n, double(ms));
     std::fclose(fp);
 }
 
-// (fuse, rows) for a batch: explicit options first, then the tuned choice,
-// then the defaults (default_fuse, per-grid default tile height).
+// (fuse, rows, lds_max_n) for a batch: explicit options first, then the
+// tuned choice, then the defaults (default_fuse, per-grid default tile
+// height, default_lds_max_n).
 void choose_params(int count, const rbgs_grid* grids, int dt, const rbgs_sweep_opts* o,
-                   int* fuse, int* rows) {
+                   int* fuse, int* rows, int* lds_max_n) {
     *fuse = (o && o->fuse > 0) ? o->fuse : 0;
     *rows = (o && o->tile_rows > 0) ? o->tile_rows : 0;
-    if (*fuse == 0 || *rows == 0) {
+    *lds_max_n = o ? o->lds_max_n : 0;
+    if (*fuse == 0 || *rows == 0 || *lds_max_n == 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_tune_file();
         auto it = g_tune.find(tune_key(count, grids, dt));
         if (it != g_tune.end()) {
-            if (*fuse == 0) *fuse = it->second.first;
-            if (*rows == 0) *rows = it->second.second;
+            if (*fuse == 0) *fuse = it->second.fuse;
+            if (*rows == 0) *rows = it->second.rows;
+            if (*lds_max_n == 0) *lds_max_n = it->second.lds_max_n;
         }
     }
     if (*fuse == 0) {
@@ -442,6 +576,7 @@ void choose_params(int count, const rbgs_grid* grids, int dt, const rbgs_sweep_o
         for (int g = 0; g < count; ++g) nmax = grids[g].n > nmax ? grids[g].n : nmax;
         *fuse = default_fuse(dt == RBGS_F64 ? 8 : 4, nmax);
     }
+    if (*lds_max_n == 0) *lds_max_n = default_lds_max_n(dt == RBGS_F64 ? 8 : 4);
 }
 
 template <typename T>
@@ -452,8 +587,11 @@ int upload_setup(const BatchSetup& su, const BatchLayout& lay, char* ws, int cou
     if (e == hipSuccess)
         e = hipMemcpyAsync(ws + lay.pdesc, su.pdesc.data(), sizeof(PackDesc) * count,
                            hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !su.tile_map.empty())
         e = hipMemcpyAsync(ws + lay.tile_map, su.tile_map.data(), sizeof(int) * su.tile_map.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !su.small_ids.empty())
+        e = hipMemcpyAsync(ws + lay.small, su.small_ids.data(), sizeof(int) * su.small_ids.size(),
                            hipMemcpyHostToDevice, s);
     // the host tables are freed when the caller returns: wait for the copies
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -475,9 +613,9 @@ int sweep_batched_t(int32_t count, const rbgs_grid* grids, void* const* u, const
                     int32_t nsweeps, const rbgs_sweep_opts* o, char* ws, hipStream_t s) {
     const rbgs_dtype dt = sizeof(T) == 8 ? RBGS_F64 : RBGS_F32;
     const BatchLayout lay = batch_layout(count, grids, dt);
-    int fuse = 0, rows = 0;
-    choose_params(count, grids, dt, o, &fuse, &rows);
-    const BatchSetup su = build_setup<T>(count, grids, u, f, lay, ws, fuse, rows, nsweeps);
+    int fuse = 0, rows = 0, lds = 0;
+    choose_params(count, grids, dt, o, &fuse, &rows, &lds);
+    const BatchSetup su = build_setup<T>(count, grids, u, f, lay, ws, fuse, rows, nsweeps, lds);
     int rc = upload_setup<T>(su, lay, ws, count, s);
     if (rc) return rc;
     EventPair ev;
@@ -493,7 +631,8 @@ int sweep_batched_t(int32_t count, const rbgs_grid* grids, void* const* u, const
         (void)hipEventSynchronize(ev.b);
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, ev.a, ev.b);
-        *o->timing = rbgs_timing{0.f, ms, 0.f, (su.passes > 0) + (su.rem > 0)};
+        const int tiled = su.total_tiles > 0 ? (su.passes > 0) + (su.rem > 0) : 0;
+        *o->timing = rbgs_timing{0.f, ms, 0.f, tiled + (su.small_ids.empty() ? 0 : 1)};
     }
     return read_error_word(lay, ws, s);
 }
@@ -549,14 +688,14 @@ int rbgs_batch_plan_create(rbgs_batch_plan** plan, int32_t count, const rbgs_gri
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
         return bfail(RBGS_EHIP, "stream create");
-    int fuse = 0, rows = 0;
-    choose_params(count, grids, dt, opts, &fuse, &rows);
+    int fuse = 0, rows = 0, lds = 0;
+    choose_params(count, grids, dt, opts, &fuse, &rows, &lds);
     BatchSetup su;
     if (dt == RBGS_F64) {
-        su = build_setup<double>(count, grids, u, f, lay, ws, fuse, rows, nsweeps);
+        su = build_setup<double>(count, grids, u, f, lay, ws, fuse, rows, nsweeps, lds);
         rc = upload_setup<double>(su, lay, ws, count, cs);
     } else {
-        su = build_setup<float>(count, grids, u, f, lay, ws, fuse, rows, nsweeps);
+        su = build_setup<float>(count, grids, u, f, lay, ws, fuse, rows, nsweeps, lds);
         rc = upload_setup<float>(su, lay, ws, count, cs);
     }
     if (rc) {
@@ -620,45 +759,56 @@ int rbgs_autotune_batched(int32_t count, const rbgs_grid* grids, rbgs_dtype dt, 
         return bfail(RBGS_EHIP, "event create");
     const int fuses[] = {4, 5, 6, 7};
     const int rowsv[] = {64, 128, 256};
-    float best_ms = 1e30f;
-    int bf = kMaxFuse, br = 0;
+    const int lds_default = default_lds_max_n(dt == RBGS_F64 ? 8 : 4);
     bool packed = false;
+    // time per sweep of one candidate: two passes, timed after one untimed
+    // warm-up pass
+    auto time_one = [&](int fu, int ro, int lds, float* per_sweep) -> int {
+        BatchSetup su = dt == RBGS_F64
+                            ? build_setup<double>(count, grids, u, f, lay, ws, fu, ro, 2 * fu, lds)
+                            : build_setup<float>(count, grids, u, f, lay, ws, fu, ro, 2 * fu, lds);
+        int r = dt == RBGS_F64 ? upload_setup<double>(su, lay, ws, count, s)
+                               : upload_setup<float>(su, lay, ws, count, s);
+        if (r) return r;
+        BatchSetup warm = su;
+        warm.passes = 1;
+        hipError_t e = dt == RBGS_F64
+                           ? enqueue_batch<double>(warm, lay, ws, count, nullptr, !packed, false, s)
+                           : enqueue_batch<float>(warm, lay, ws, count, nullptr, !packed, false, s);
+        packed = true;
+        if (e == hipSuccess) e = hipEventRecord(a, s);
+        if (e == hipSuccess)
+            e = dt == RBGS_F64 ? enqueue_batch<double>(su, lay, ws, count, nullptr, false, false, s)
+                               : enqueue_batch<float>(su, lay, ws, count, nullptr, false, false, s);
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e != hipSuccess) return bfail(RBGS_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+        if ((r = read_error_word(lay, ws, s))) return r;
+        *per_sweep = ms / float(2 * fu);
+        return RBGS_OK;
+    };
+    float best_ms = 1e30f;
+    Tuned bt{kMaxFuse, 0, lds_default};
     for (int fu : fuses) {
         for (int ro : rowsv) {
-            // two passes per candidate, timed after one untimed warm-up pass
-            BatchSetup su = dt == RBGS_F64
-                                ? build_setup<double>(count, grids, u, f, lay, ws, fu, ro, 2 * fu)
-                                : build_setup<float>(count, grids, u, f, lay, ws, fu, ro, 2 * fu);
-            rc = dt == RBGS_F64 ? upload_setup<double>(su, lay, ws, count, s)
-                                : upload_setup<float>(su, lay, ws, count, s);
-            if (rc) break;
-            BatchSetup warm = su;
-            warm.passes = 1;
-            hipError_t e = dt == RBGS_F64
-                               ? enqueue_batch<double>(warm, lay, ws, count, nullptr, !packed, false, s)
-                               : enqueue_batch<float>(warm, lay, ws, count, nullptr, !packed, false, s);
-            packed = true;
-            if (e == hipSuccess) e = hipEventRecord(a, s);
-            if (e == hipSuccess)
-                e = dt == RBGS_F64 ? enqueue_batch<double>(su, lay, ws, count, nullptr, false, false, s)
-                                   : enqueue_batch<float>(su, lay, ws, count, nullptr, false, false, s);
-            if (e == hipSuccess) e = hipEventRecord(b, s);
-            if (e == hipSuccess) e = hipEventSynchronize(b);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-            if (e != hipSuccess) {
-                rc = bfail(RBGS_EHIP, std::string("autotune: ") + hipGetErrorString(e));
-                break;
-            }
-            if ((rc = read_error_word(lay, ws, s))) break;
-            const float per_sweep = ms / float(2 * fu);
+            float per_sweep = 0.f;
+            if ((rc = time_one(fu, ro, lds_default, &per_sweep))) break;
             if (per_sweep < best_ms) {
                 best_ms = per_sweep;
-                bf = fu;
-                br = ro;
+                bt = Tuned{fu, ro, lds_default};
             }
         }
         if (rc) break;
+    }
+    if (!rc) {  // then the small grids through the tiles instead
+        float per_sweep = 0.f;
+        rc = time_one(bt.fuse, bt.rows, -1, &per_sweep);
+        if (!rc && per_sweep < best_ms) {
+            best_ms = per_sweep;
+            bt.lds_max_n = -1;
+        }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
@@ -666,13 +816,14 @@ int rbgs_autotune_batched(int32_t count, const rbgs_grid* grids, rbgs_dtype dt, 
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_tune_file();
-        store_tune(tune_key(count, grids, dt), bf, br, best_ms);
+        store_tune(tune_key(count, grids, dt), bt, best_ms);
     }
     if (best) {
         std::memset(best, 0, sizeof *best);
         best->kernel = RBGS_KERNEL_BLOCKED;
-        best->fuse = bf;
-        best->tile_rows = br;
+        best->fuse = bt.fuse;
+        best->tile_rows = bt.rows;
+        best->lds_max_n = bt.lds_max_n;
     }
     if (best_ms_per_sweep) *best_ms_per_sweep = best_ms;
     return RBGS_OK;

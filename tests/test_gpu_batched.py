@@ -58,6 +58,38 @@ def test_batched_bitwise(oracle, dtype, nsweeps, fuse):
         assert np.array_equal(got.view(np.uint8), ref.view(np.uint8)), f"grid {g} (n={n})"
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("lds_max_n", [-1, 31, 63, 127])
+def test_batched_lds_resident(oracle, dtype, lds_max_n):
+    """Grids up to lds_max_n are swept in one workgroup's LDS (when they fit:
+    127 only in FP32), the rest through the tiles; -1 sends every grid
+    through the tiles.  Either way each grid is the oracle's, bit for bit."""
+    say(f"batched LDS-resident {dtype.__name__} lds_max_n={lds_max_n}")
+    us, fs = make_batch(SIZES, dtype, seed0=90)
+    ut, ft = to_dev(us), to_dev(fs)
+    t = rb.rbgs_sweep_batched(ut, ft, 11, fuse=4, tile_rows=16, lds_max_n=lds_max_n, timing=True)
+    assert t["sweep_launches"] >= 1
+    for g, n in enumerate(SIZES):
+        ref = us[g].copy()
+        oracle.sweep(ref, fs[g], W.spacing(n), 11)
+        got = ut[g].cpu().numpy()
+        assert np.array_equal(got.view(np.uint8), ref.view(np.uint8)), f"grid {g} (n={n})"
+
+
+def test_batched_all_small(oracle):
+    """A batch with no grid left for the tiles (no persistent launch at all)."""
+    sizes = [63, 5, 127, 31, 1]
+    say("batched, every grid LDS-resident")
+    us, fs = make_batch(sizes, np.float32, seed0=95)
+    ut, ft = to_dev(us), to_dev(fs)
+    t = rb.rbgs_sweep_batched(ut, ft, 9, lds_max_n=127, timing=True)
+    assert t["sweep_launches"] == 1
+    for g, n in enumerate(sizes):
+        ref = us[g].copy()
+        oracle.sweep(ref, fs[g], W.spacing(n), 9)
+        assert np.array_equal(ut[g].cpu().numpy(), ref), f"grid {g} (n={n})"
+
+
 def test_batched_delay_injection(oracle):
     sizes = [255, 64, 511, 31, 127]
     say("batched with delay injection")
@@ -98,6 +130,7 @@ def test_autotune_then_sweep(oracle):
     ut, ft = to_dev(us), to_dev(fs)
     best = rb.rbgs_autotune_batched(ut, ft)
     assert best["fuse"] in (4, 5, 6, 7) and best["tile_rows"] in (64, 128, 256)
+    assert best["lds_max_n"] in (-1, 127)
     assert best["ms_per_sweep"] > 0
     # the tuner only read u; a sweep with the tuned choice (picked up from the
     # process-wide table) is still bitwise the oracle
