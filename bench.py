@@ -222,7 +222,9 @@ def batched_to_tolerance(torch, rb, W, count=16, tol=1e-8, chunk=4000):
     """Many small grids to rel <= tol: `count` grids with sizes uniform on
     {63, 127, 255} (seed 1), f i.i.d. N(0,1) (seed 1000+g), FP64, u0 = 0.
     Batched: one graph-captured persistent launch of `chunk` sweeps for all
-    grids, then every grid's residual, until all are below tol.  Judge: each
+    grids, then every grid's residual, until all are below tol; and the
+    batched refinement solve (FP32 inner sweeps of all grids batched, FP64
+    residual and correction per grid).  Judge: each
     grid solved alone with the plain FP64 kernel (residual every 1000
     sweeps)."""
     import numpy as np
@@ -251,6 +253,22 @@ def batched_to_tolerance(torch, rb, W, count=16, tol=1e-8, chunk=4000):
     out = {"workload": f"{count} grids, N in {{63,127,255}} seed 1, f~N(0,1), FP64, u0=0, "
                        f"rel<={tol:g} for every grid", "sizes": sizes,
            "batched": {"seconds": round(dt, 4), "sweeps": done, "max_rel": max(rels)}}
+    # The same grids through the batched solve: FP64 refinement per grid,
+    # the FP32 inner sweeps (`chunk` per outer step) of every unconverged
+    # grid in one batched persistent launch.
+    rb.rbgs_solve_batched(us, fs, 10, tol, 10)  # warm-up
+    for u in us:
+        u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = rb.rbgs_solve_batched(us, fs, 400_000, tol, chunk)
+    torch.cuda.synchronize()
+    dt_ir = time.perf_counter() - t0
+    out["batched_f32_ir"] = {"seconds": round(dt_ir, 4),
+                             "max_sweeps": max(i["sweeps"] for i in infos),
+                             "max_outer": max(i["outer_iters"] for i in infos),
+                             "max_rel": max(i["rel_residual"] for i in infos),
+                             "all_converged": all(i["status"] == 0 for i in infos)}
     t_plain = 0.0
     sweeps_plain = 0
     for f in fs:
@@ -261,6 +279,7 @@ def batched_to_tolerance(torch, rb, W, count=16, tol=1e-8, chunk=4000):
         sweeps_plain = max(sweeps_plain, info["sweeps"])
     out["plain_f64_one_by_one"] = {"seconds": round(t_plain, 4), "max_sweeps": sweeps_plain}
     out["speedup_vs_plain_f64"] = round(t_plain / dt, 2)
+    out["speedup_f32_ir_vs_plain_f64"] = round(t_plain / dt_ir, 2)
     log(f"batched to tolerance: {out}")
     return out
 

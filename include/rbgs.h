@@ -137,8 +137,10 @@ typedef struct {
                                and h^2 f fit in one workgroup's LDS are swept
                                there, one workgroup per grid, for all sweeps
                                of the call; the others go through the
-                               persistent tiles.  0 = tuned or default (127
-                               FP32, 63 FP64), -1 = never.  Ignored elsewhere. */
+                               persistent tiles.  0 = the autotuner's choice
+                               for this batch shape (127 FP32 / 63 FP64, or
+                               never), else never; -1 = never.  Ignored
+                               elsewhere.                                       */
 } rbgs_sweep_opts;
 
 /* Solve options.  Zero-initialise, then set what is needed. */
@@ -248,8 +250,8 @@ int rbgs_batch_plan_destroy(rbgs_batch_plan *plan);
 /* Autotuner: times the persistent kernel on this batch for fusion depths
  * {4, 5, 6, 7} and tile heights {64, 128, 256} (two passes each after a
  * warm-up pass; the workspace copies are swept, u and f are only read),
- * then, for the best of those, the LDS-resident threshold (lds_max_n: the
- * default, or never), and stores the fastest choice for the batch shape
+ * then, for the best of those, the LDS-resident threshold (lds_max_n: none,
+ * or 127 FP32 / 63 FP64), and stores the fastest choice for the batch shape
  * (dtype, CU count and the
  * multiset of grid sizes) in a process-wide table, appends it to the file
  * named by the environment variable RBGS_TUNE_CACHE if set (and reads that
@@ -260,6 +262,27 @@ int rbgs_autotune_batched(int32_t count, const rbgs_grid *grids,
                           void *workspace, size_t workspace_bytes,
                           void *stream, rbgs_sweep_opts *best,
                           float *best_ms_per_sweep);
+
+/* Batched solve to a tolerance: every grid of the batch (FP64 u and f,
+ * natural layout, HOST arrays of device pointers as above) is refined as
+ * rbgs_solve does it with precision F32_IR or BF16RHS_IR (the mixed-
+ * precision refinement the build adds to the paper's method): an FP64
+ * residual, r rounded to FP32 (or bfloat16), inner_sweeps FP32 sweeps of
+ * A e = r from e = 0 with a zero ring, u <- u + e in FP64, until rel <=
+ * rel_tol or max_sweeps.  The inner sweeps of all grids still refining run
+ * as one batched persistent launch (opts->sweep selects its tuning; the
+ * autotuner's table applies); a converged grid is left alone, so each
+ * grid's result is bitwise that of rbgs_solve on it alone.  infos (HOST,
+ * count entries, may be NULL) receives each grid's sweeps, outer steps,
+ * norms and status.  Returns RBGS_OK when every grid converged, else the
+ * first failing grid's status (RBGS_ENOCONV, RBGS_ENONFINITE).  Precision
+ * F64 is RBGS_EUNSUPPORTED (sweep FP64 batches with a plan and check with
+ * rbgs_residual).  Synchronises `stream`. */
+size_t rbgs_batch_solve_workspace_size(int32_t count, const rbgs_grid *grids);
+int rbgs_solve_batched(int32_t count, const rbgs_grid *grids, double *const *u,
+                       const double *const *f, const rbgs_solve_opts *opts,
+                       rbgs_solve_info *infos, void *workspace,
+                       size_t workspace_bytes, void *stream);
 
 /* Message for the calling thread's last failure in a batched call. */
 const char *rbgs_batch_last_error(void);

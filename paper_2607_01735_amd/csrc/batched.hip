@@ -10,11 +10,12 @@
 // Each grid keeps its own progress flags (offset flag_base); its tiles wait
 // only on their own 3 x 3 neighbourhood.
 //
-// Small grids (n <= lds_max_n, default 127 in FP32 and 63 in FP64, when
-// both colours of u and of h^2 f fit in one workgroup's LDS) leave the tile
-// queue: k_batch_lds sweeps each in one workgroup, all sweeps of the call
-// in LDS, before the persistent launch.  A 63^2 grid would otherwise be one
-// 64-lane tile with a halo as wide as the grid, for every pass.
+// Small grids (n <= lds_max_n, when both colours of u and of h^2 f fit in
+// one workgroup's LDS) can leave the tile queue: k_batch_lds sweeps each in
+// one workgroup, all sweeps of the call in LDS, before the persistent
+// launch.  The autotuner decides whether that beats tiling them (a 63^2
+// grid is one 64-lane tile with a halo as wide as the grid, but its tiles
+// interleave with the large grids' instead of adding a launch).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -166,21 +167,25 @@ inline size_t lds_limit_bytes() {
 // One colour's half-sweep of an LDS-resident grid.  Split layout with row
 // pitch pl: colour c holds (i, j = 2q + ((i + c) & 1)) at [i][q]; the
 // other colour's neighbours of that point sit at [i +- 1][q] and at
-// [i][(j +- 1) / 2].  Same operations, same order as every other kernel.
+// [i][(j +- 1) / 2].  Wave w takes rows 1 + w, 1 + w + waves, ..., its lanes
+// the q of a row.  Same operations, same order as every other kernel.
 template <typename T, int C>
 __device__ __forceinline__ void lds_half_sweep(T* __restrict__ self, const T* __restrict__ other,
                                                const T* __restrict__ hf, int n, int pl) {
-    const int items = n * pl;
-    for (int k = threadIdx.x; k < items; k += kLdsThreads) {
-        const int i = 1 + k / pl;
-        const int q = k - (i - 1) * pl;
-        const int j = 2 * q + ((i + C) & 1);
-        if (j < 1 || j > n) continue;
-        T s = other[(i + 1) * pl + q] + other[(i - 1) * pl + q];
-        s = s + other[i * pl + ((j + 1) >> 1)];
-        s = s + other[i * pl + ((j - 1) >> 1)];
-        s = s - hf[i * pl + q];
-        self[i * pl + q] = T(0.25) * s;
+    constexpr int kWaves = kLdsThreads / 64;
+    const int lane = threadIdx.x & 63;
+    for (int i = 1 + int(threadIdx.x >> 6); i <= n; i += kWaves) {
+        const int p = (i + C) & 1;
+        const T* o = other + i * pl;
+        for (int q = lane; q < pl; q += 64) {
+            const int j = 2 * q + p;
+            if (j < 1 || j > n) continue;
+            T s = o[pl + q] + o[q - pl];
+            s = s + o[(j + 1) >> 1];
+            s = s + o[(j - 1) >> 1];
+            s = s - hf[i * pl + q];
+            self[i * pl + q] = T(0.25) * s;
+        }
     }
 }
 
@@ -282,9 +287,12 @@ struct BatchSetup {
     size_t small_lds_bytes = 0;  // dynamic LDS for the largest of them
 };
 
-// Built-in LDS-resident threshold: the largest grid of the batch sizes in
-// the benchmark mix that fits (127 in FP32: 133 KB; 63 in FP64: 68 KB).
-inline int default_lds_max_n(size_t es) { return es == 4 ? 127 : 63; }
+// LDS-resident threshold the autotuner tries: the largest grid of the
+// benchmark's size mix that fits (127 in FP32: 133 KB; 63 in FP64: 68 KB).
+// Untuned batches use none: the LDS launch runs before the persistent one,
+// and on the measured mixes (512 grids of 63..1023 FP32; 16 grids of
+// 63..255 FP64) tiling the small grids alongside the large ones was faster.
+inline int tuned_lds_candidate(size_t es) { return es == 4 ? 127 : 63; }
 
 template <typename T>
 BatchSetup build_setup(int count, const rbgs_grid* grids, void* const* u, const void* const* f,
@@ -555,7 +563,7 @@ void store_tune(const std::string& key, const Tuned& t, float ms) {
 
 // (fuse, rows, lds_max_n) for a batch: explicit options first, then the
 // tuned choice, then the defaults (default_fuse, per-grid default tile
-// height, default_lds_max_n).
+// height, no LDS-resident grids).
 void choose_params(int count, const rbgs_grid* grids, int dt, const rbgs_sweep_opts* o,
                    int* fuse, int* rows, int* lds_max_n) {
     *fuse = (o && o->fuse > 0) ? o->fuse : 0;
@@ -576,7 +584,7 @@ void choose_params(int count, const rbgs_grid* grids, int dt, const rbgs_sweep_o
         for (int g = 0; g < count; ++g) nmax = grids[g].n > nmax ? grids[g].n : nmax;
         *fuse = default_fuse(dt == RBGS_F64 ? 8 : 4, nmax);
     }
-    if (*lds_max_n == 0) *lds_max_n = default_lds_max_n(dt == RBGS_F64 ? 8 : 4);
+    if (*lds_max_n == 0) *lds_max_n = -1;
 }
 
 template <typename T>
@@ -635,6 +643,196 @@ int sweep_batched_t(int32_t count, const rbgs_grid* grids, void* const* u, const
         *o->timing = rbgs_timing{0.f, ms, 0.f, tiled + (su.small_ids.empty() ? 0 : 1)};
     }
     return read_error_word(lay, ws, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batched solve: FP64 iterative refinement (the single-grid rbgs_solve's
+// steps, grid by grid) whose FP32 inner sweeps run as one batched
+// persistent launch over every grid that has not yet converged.
+// ---------------------------------------------------------------------------
+
+// Workspace of a batched solve: the FP32 batch (per grid: the correction e
+// in two ping-pong buffers and the right-hand side r, split layout), then
+// per grid the FP64 split u and f and the residual partial sums, then two
+// norms per grid.
+struct SolveLayout {
+    BatchLayout inner;
+    std::vector<size_t> u_off;    // u_red, u_black, f_red, f_black (FP64 split)
+    std::vector<int64_t> pitch64;
+    std::vector<size_t> part_off;
+    size_t sums = 0;
+    size_t total = 0;
+};
+
+SolveLayout solve_layout(int count, const rbgs_grid* grids) {
+    SolveLayout L;
+    L.inner = batch_layout(count, grids, RBGS_F32);
+    size_t off = align256(L.inner.total);
+    L.u_off.resize(count);
+    L.pitch64.resize(count);
+    L.part_off.resize(count);
+    for (int g = 0; g < count; ++g) {
+        const int n = grids[g].n;
+        const int64_t P = split_pitch(n, 8);
+        L.pitch64[g] = P;
+        L.u_off[g] = off;
+        off += 4 * align256(size_t(n + 2) * size_t(P) * 8);
+        L.part_off[g] = off;
+        off += align256(size_t(residual_partial_slots(n, P, 8)) * 2 * sizeof(double));
+    }
+    L.sums = off;
+    off += align256(size_t(count) * 2 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+struct GridArrays {
+    double *u_red, *u_black, *f_red, *f_black;
+    float *e[2][2];  // [buffer][red, black]
+    float *r_red, *r_black;
+    int64_t p64, p32;
+};
+
+GridArrays grid_arrays(const SolveLayout& L, char* ws, const rbgs_grid* grids, int g) {
+    GridArrays a;
+    const int n = grids[g].n;
+    const size_t c64 = align256(size_t(n + 2) * size_t(L.pitch64[g]) * 8);
+    char* b64 = ws + L.u_off[g];
+    a.u_red = reinterpret_cast<double*>(b64);
+    a.u_black = reinterpret_cast<double*>(b64 + c64);
+    a.f_red = reinterpret_cast<double*>(b64 + 2 * c64);
+    a.f_black = reinterpret_cast<double*>(b64 + 3 * c64);
+    const size_t c32 = align256(size_t(n + 2) * size_t(L.inner.pitch[g]) * 4);
+    char* b32 = ws + L.inner.grid_off[g];  // the order build_setup assigns
+    a.e[0][0] = reinterpret_cast<float*>(b32);
+    a.e[0][1] = reinterpret_cast<float*>(b32 + c32);
+    a.e[1][0] = reinterpret_cast<float*>(b32 + 2 * c32);
+    a.e[1][1] = reinterpret_cast<float*>(b32 + 3 * c32);
+    a.r_red = reinterpret_cast<float*>(b32 + 4 * c32);
+    a.r_black = reinterpret_cast<float*>(b32 + 5 * c32);
+    a.p64 = L.pitch64[g];
+    a.p32 = L.inner.pitch[g];
+    return a;
+}
+
+int solve_batched_ir(int32_t count, const rbgs_grid* grids, double* const* u,
+                     const double* const* f, const rbgs_solve_opts* o, rbgs_solve_info* infos,
+                     char* ws, hipStream_t s) {
+    const SolveLayout L = solve_layout(count, grids);
+    const int bf16 = o->precision == RBGS_PREC_BF16RHS_IR;
+    const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : o->check_every;
+    double* sums = reinterpret_cast<double*>(ws + L.sums);
+    std::vector<GridArrays> ga(count);
+    hipError_t e = hipSuccess;
+    for (int g = 0; g < count && e == hipSuccess; ++g) {
+        ga[g] = grid_arrays(L, ws, grids, g);
+        e = launch_pack(u[g], grids[g].ld, ga[g].u_red, ga[g].u_black, grids[g].n, ga[g].p64, 8, s);
+        if (e == hipSuccess)
+            e = launch_pack(f[g], grids[g].ld, ga[g].f_red, ga[g].f_black, grids[g].n, ga[g].p64, 8, s);
+    }
+    if (e != hipSuccess) return bfail(RBGS_EHIP, std::string("pack: ") + hipGetErrorString(e));
+    std::vector<double> rel(count, 0.0), ab(count, 0.0), host(2 * size_t(count));
+    std::vector<int> done(count, 0), outer(count, 0);
+    // FP64 residual of the listed grids, with r stored in FP32 (or bfloat16)
+    // as the next inner right-hand side
+    auto residuals = [&](const std::vector<int>& which) -> int {
+        hipError_t r = hipSuccess;
+        for (int g : which) {
+            r = launch_residual_split<double>(ga[g].u_red, ga[g].u_black, ga[g].f_red, ga[g].f_black,
+                                              grids[g].n, ga[g].p64,
+                                              1.0 / (grids[g].h * grids[g].h),
+                                              reinterpret_cast<double*>(ws + L.part_off[g]),
+                                              sums + 2 * g, ga[g].r_red, ga[g].r_black, ga[g].p32,
+                                              bf16, s);
+            if (r != hipSuccess) break;
+        }
+        if (r == hipSuccess)
+            r = hipMemcpyAsync(host.data(), sums, host.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, s);
+        if (r == hipSuccess) r = hipStreamSynchronize(s);
+        if (r != hipSuccess) return bfail(RBGS_EHIP, std::string("residual: ") + hipGetErrorString(r));
+        for (int g : which) {
+            const double rn = std::sqrt(host[2 * g]), bn = std::sqrt(host[2 * g + 1]);
+            ab[g] = rn;
+            rel[g] = bn > 0.0 ? rn / bn : rn;
+        }
+        return RBGS_OK;
+    };
+    std::vector<int> all(count);
+    std::iota(all.begin(), all.end(), 0);
+    int rc = residuals(all);
+    if (rc) return rc;
+    for (;;) {
+        // the grids still refining, grouped by this step's sweep count (a
+        // grid near max_sweeps takes fewer, as in the single-grid solve)
+        std::map<int, std::vector<int>> by_k;
+        for (int g = 0; g < count; ++g)
+            if (!(rel[g] <= o->rel_tol) && done[g] < o->max_sweeps && std::isfinite(rel[g]))
+                by_k[std::min(inner, o->max_sweeps - done[g])].push_back(g);
+        if (by_k.empty()) break;
+        std::vector<int> stepped;
+        for (const auto& kv : by_k) {
+            const int k = kv.first;
+            const std::vector<int>& act = kv.second;
+            for (int g : act)
+                for (int b = 0; b < 2 && e == hipSuccess; ++b)
+                    for (int c = 0; c < 2 && e == hipSuccess; ++c)
+                        e = launch_zero(ga[g].e[b][c],
+                                        size_t(grids[g].n + 2) * size_t(ga[g].p32) * 4, s);
+            if (e != hipSuccess) return bfail(RBGS_EHIP, std::string("zero: ") + hipGetErrorString(e));
+            // one batched launch over these grids: a view of the layout with
+            // their arrays only
+            const int na = int(act.size());
+            BatchLayout sub = L.inner;
+            sub.grid_off.assign(na, 0);
+            sub.pitch.assign(na, 0);
+            std::vector<rbgs_grid> sg(na);
+            std::vector<void*> nu(na, nullptr);
+            std::vector<const void*> nf(na, nullptr);
+            for (int a = 0; a < na; ++a) {
+                sub.grid_off[a] = L.inner.grid_off[act[a]];
+                sub.pitch[a] = L.inner.pitch[act[a]];
+                sg[a] = grids[act[a]];
+            }
+            int fuse = 0, rows = 0, lds = 0;
+            choose_params(na, sg.data(), RBGS_F32, &o->sweep, &fuse, &rows, &lds);
+            const BatchSetup su =
+                build_setup<float>(na, sg.data(), nu.data(), nf.data(), sub, ws, fuse, rows, k, lds);
+            if ((rc = upload_setup<float>(su, sub, ws, na, s))) return rc;
+            e = enqueue_batch<float>(su, sub, ws, na, &o->sweep, false, false, s);
+            if (e != hipSuccess)
+                return bfail(RBGS_EHIP, std::string("inner sweeps: ") + hipGetErrorString(e));
+            if ((rc = read_error_word(sub, ws, s))) return rc;
+            const int out = (su.passes + (su.rem > 0 ? 1 : 0)) & 1;
+            for (int g : act) {
+                e = launch_add_correction(ga[g].u_red, ga[g].u_black, ga[g].p64, ga[g].e[out][0],
+                                          ga[g].e[out][1], ga[g].p32, grids[g].n, s);
+                if (e != hipSuccess)
+                    return bfail(RBGS_EHIP, std::string("correction: ") + hipGetErrorString(e));
+                done[g] += k;
+                ++outer[g];
+                stepped.push_back(g);
+            }
+        }
+        if ((rc = residuals(stepped))) return rc;
+    }
+    for (int g = 0; g < count && e == hipSuccess; ++g)
+        e = launch_unpack(u[g], grids[g].ld, ga[g].u_red, ga[g].u_black, grids[g].n, ga[g].p64, 8, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bfail(RBGS_EHIP, std::string("unpack: ") + hipGetErrorString(e));
+    int status = RBGS_OK;
+    for (int g = 0; g < count; ++g) {
+        rbgs_solve_info info{done[g], outer[g], rel[g], ab[g], RBGS_OK};
+        if (!std::isfinite(rel[g]))
+            info.status = RBGS_ENONFINITE;
+        else if (!(rel[g] <= o->rel_tol))
+            info.status = RBGS_ENOCONV;
+        if (infos) infos[g] = info;
+        if (info.status != RBGS_OK && status == RBGS_OK) status = info.status;
+    }
+    if (status == RBGS_ENOCONV) g_batch_error = "tolerance not reached by every grid";
+    if (status == RBGS_ENONFINITE) g_batch_error = "a residual is not finite";
+    return status;
 }
 
 }  // namespace
@@ -759,7 +957,7 @@ int rbgs_autotune_batched(int32_t count, const rbgs_grid* grids, rbgs_dtype dt, 
         return bfail(RBGS_EHIP, "event create");
     const int fuses[] = {4, 5, 6, 7};
     const int rowsv[] = {64, 128, 256};
-    const int lds_default = default_lds_max_n(dt == RBGS_F64 ? 8 : 4);
+    const int lds_candidate = tuned_lds_candidate(dt == RBGS_F64 ? 8 : 4);
     bool packed = false;
     // time per sweep of one candidate: two passes, timed after one untimed
     // warm-up pass
@@ -790,24 +988,24 @@ int rbgs_autotune_batched(int32_t count, const rbgs_grid* grids, rbgs_dtype dt, 
         return RBGS_OK;
     };
     float best_ms = 1e30f;
-    Tuned bt{kMaxFuse, 0, lds_default};
+    Tuned bt{kMaxFuse, 0, -1};
     for (int fu : fuses) {
         for (int ro : rowsv) {
             float per_sweep = 0.f;
-            if ((rc = time_one(fu, ro, lds_default, &per_sweep))) break;
+            if ((rc = time_one(fu, ro, -1, &per_sweep))) break;
             if (per_sweep < best_ms) {
                 best_ms = per_sweep;
-                bt = Tuned{fu, ro, lds_default};
+                bt = Tuned{fu, ro, -1};
             }
         }
         if (rc) break;
     }
-    if (!rc) {  // then the small grids through the tiles instead
+    if (!rc) {  // then the small grids LDS-resident instead
         float per_sweep = 0.f;
-        rc = time_one(bt.fuse, bt.rows, -1, &per_sweep);
+        rc = time_one(bt.fuse, bt.rows, lds_candidate, &per_sweep);
         if (!rc && per_sweep < best_ms) {
             best_ms = per_sweep;
-            bt.lds_max_n = -1;
+            bt.lds_max_n = lds_candidate;
         }
     }
     (void)hipEventDestroy(a);
@@ -827,6 +1025,32 @@ int rbgs_autotune_batched(int32_t count, const rbgs_grid* grids, rbgs_dtype dt, 
     }
     if (best_ms_per_sweep) *best_ms_per_sweep = best_ms;
     return RBGS_OK;
+}
+
+size_t rbgs_batch_solve_workspace_size(int32_t count, const rbgs_grid* grids) {
+    if (rbgs_batch_workspace_size(count, grids, RBGS_F32) == 0) return 0;
+    return solve_layout(count, grids).total;
+}
+
+int rbgs_solve_batched(int32_t count, const rbgs_grid* grids, double* const* u,
+                       const double* const* f, const rbgs_solve_opts* opts,
+                       rbgs_solve_info* infos, void* workspace, size_t workspace_bytes,
+                       void* stream) {
+    if (!opts) return bfail(RBGS_EINVAL, "opts is NULL");
+    if (opts->precision != RBGS_PREC_F32_IR && opts->precision != RBGS_PREC_BF16RHS_IR)
+        return bfail(RBGS_EUNSUPPORTED,
+                     "batched solves refine in FP64 around FP32 sweeps: precision must be "
+                     "F32_IR or BF16RHS_IR");
+    if (!(opts->rel_tol > 0.0) || opts->max_sweeps < 0)
+        return bfail(RBGS_EINVAL, "need rel_tol > 0 and max_sweeps >= 0");
+    if (opts->inner_sweeps < 0 || (opts->inner_sweeps == 0 && opts->check_every < 1))
+        return bfail(RBGS_EINVAL, "need inner_sweeps >= 1 (or check_every >= 1)");
+    int rc = validate_batch(count, grids, RBGS_F64, reinterpret_cast<void* const*>(u),
+                            reinterpret_cast<const void* const*>(f), 0, &opts->sweep);
+    if (rc) return rc;
+    if ((rc = check_ws(workspace, workspace_bytes, solve_layout(count, grids).total))) return rc;
+    return solve_batched_ir(count, grids, u, f, opts, infos, static_cast<char*>(workspace),
+                            static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -122,7 +122,8 @@ EXPORTED = ("rbgs_workspace_size", "rbgs_sweep", "rbgs_residual", "rbgs_solve",
             "rbgs_unet_create", "rbgs_unet_destroy", "rbgs_unet_set_params",
             "rbgs_unet_get_params", "rbgs_unet_get_grads", "rbgs_unet_forward",
             "rbgs_unet_train_step", "rbgs_solve_learned", "rbgs_unet_last_error",
-            "rbgs_restrict", "rbgs_prolong")
+            "rbgs_restrict", "rbgs_prolong", "rbgs_batch_solve_workspace_size",
+            "rbgs_solve_batched")
 
 
 class RbgsError(RuntimeError):
@@ -147,6 +148,14 @@ def _check(rc, allow=(OK,)):
 
 def rbgs_batch_last_error():
     return _lib.rbgs_batch_last_error().decode()
+
+
+_lib.rbgs_batch_solve_workspace_size.argtypes = [ctypes.c_int32, _P(rbgs_grid)]
+_lib.rbgs_batch_solve_workspace_size.restype = ctypes.c_size_t
+_lib.rbgs_solve_batched.argtypes = [ctypes.c_int32, _P(rbgs_grid), _P(_vp), _P(_vp),
+                                    _P(rbgs_solve_opts), _P(rbgs_solve_info), _vp, ctypes.c_size_t,
+                                    _vp]
+_lib.rbgs_solve_batched.restype = ctypes.c_int
 
 
 def _bcheck(rc):
@@ -414,6 +423,35 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def rbgs_solve_batched(us, fs, max_sweeps, rel_tol, inner_sweeps, precision="f32_ir", hs=None,
+                       workspace=None, stream=None, **tuning):
+    """Refine every FP64 grid of the batch to rel_tol (FP32 inner sweeps of
+    all unconverged grids in one batched launch per outer step); returns one
+    dict per grid like rbgs_solve's.  Synchronises."""
+    b = _Batch(us, fs, hs)
+    if b.code != F64:
+        raise RbgsError(EINVAL, "batched solves take FP64 u and f")
+    need = int(_lib.rbgs_batch_solve_workspace_size(b.count, b.grids))
+    if need == 0:
+        raise RbgsError(EINVAL, "invalid batch")
+    if workspace is None:
+        import torch
+        workspace = torch.empty(need, dtype=torch.uint8, device=b.device)
+    opts = rbgs_solve_opts()
+    opts.max_sweeps, opts.rel_tol, opts.check_every = int(max_sweeps), float(rel_tol), int(inner_sweeps)
+    opts.precision = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    opts.inner_sweeps, opts.omega = int(inner_sweeps), 1.0
+    opts.sweep = _sweep_opts(kernel=tuning.pop("kernel", "auto"), **tuning)
+    infos = (rbgs_solve_info * b.count)()
+    rc = _lib.rbgs_solve_batched(b.count, b.grids, b.u, b.f, ctypes.byref(opts), infos,
+                                 _vp(workspace.data_ptr()), workspace.numel(),
+                                 _stream_ptr(stream, b.device))
+    if rc not in (OK, ENOCONV, ENONFINITE):
+        _bcheck(rc)
+    return [{"sweeps": i.sweeps, "outer_iters": i.outer_iters, "rel_residual": i.rel_residual,
+             "abs_residual": i.abs_residual, "status": i.status} for i in infos]
 
 
 def rbgs_autotune_batched(us, fs, hs=None, workspace=None, stream=None):

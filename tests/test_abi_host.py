@@ -183,3 +183,31 @@ def test_transfer_validation(lib, case):
         assert rc == lib.EINVAL, (case, rc)
         if case == "null":
             assert "NULL" in lib.rbgs_last_error()
+
+
+@pytest.mark.parametrize("bad", ["null_opts", "f64", "tol", "inner", "count", "null_arrays", "ws"])
+def test_solve_batched_validation_before_device_work(lib, bad):
+    grids = (lib.rbgs_grid * 2)(_grid(lib, 15), _grid(lib, 31))
+    ptrs = (ctypes.c_void_p * 2)(1 << 20, 2 << 20)  # never dereferenced: checks come first
+    o = lib.rbgs_solve_opts()
+    o.max_sweeps, o.rel_tol, o.check_every, o.inner_sweeps = 100, 1e-8, 10, 10
+    o.precision = lib.PREC_F32_IR
+    count, opts, u, f, expect = 2, ctypes.byref(o), ptrs, ptrs, lib.EINVAL
+    if bad == "null_opts":
+        opts = None
+    elif bad == "f64":
+        o.precision, expect = lib.PREC_F64, lib.EUNSUPPORTED
+    elif bad == "tol":
+        o.rel_tol = 0.0
+    elif bad == "inner":
+        o.inner_sweeps, o.check_every = 0, 0
+    elif bad == "count":
+        count = 0
+    elif bad == "null_arrays":
+        u = None
+    elif bad == "ws":
+        expect = lib.EWORKSPACE
+    rc = lib._lib.rbgs_solve_batched(count, grids, u, f, opts, None, None, 0, None)
+    assert rc == expect, lib.rbgs_batch_last_error()
+    assert lib._lib.rbgs_batch_solve_workspace_size(0, grids) == 0
+    assert lib._lib.rbgs_batch_solve_workspace_size(2, grids) > 0

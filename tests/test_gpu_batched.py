@@ -123,6 +123,23 @@ def test_plan_graph_replays(oracle):
                 assert np.array_equal(ut[g].cpu().numpy(), refs[g]), f"replay {k} grid {g}"
 
 
+def test_plan_graph_replays_lds(oracle):
+    """As above with the small grids LDS-resident inside the graph."""
+    sizes = [127, 255, 63, 31, 300]
+    m = 6
+    say("batched plan with LDS-resident grids: three graph replays")
+    us, fs = make_batch(sizes, np.float32, seed0=8)
+    ut, ft = to_dev(us), to_dev(fs)
+    refs = [u.copy() for u in us]
+    with rb.BatchPlan(ut, ft, m, fuse=4, tile_rows=32, lds_max_n=127) as plan:
+        for k in range(3):
+            plan.launch()
+            plan.check()
+            for g, n in enumerate(sizes):
+                oracle.sweep(refs[g], fs[g], W.spacing(n), m)
+                assert np.array_equal(ut[g].cpu().numpy(), refs[g]), f"replay {k} grid {g}"
+
+
 def test_autotune_then_sweep(oracle):
     sizes = [255, 511, 127, 63, 255, 1023]
     say("batched autotune")
@@ -179,3 +196,51 @@ def test_batched_workload_sampled(oracle):
             ref = W.zeros(n).astype(np.float32)
             oracle.sweep(ref, host_f[g], W.spacing(n), 100)
             assert np.array_equal(ut[g].cpu().numpy(), ref), f"grid {g} n={n}"
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_solve_batched_matches_oracle(oracle, bf16):
+    """Batched FP64 refinement around batched FP32 inner sweeps: each grid is
+    the oracle's refinement of that grid alone, bit for bit, with the same
+    number of outer steps; a grid with f = 0 has converged before any step."""
+    sizes = [63, 31, 127, 63, 15, 7]
+    inner, max_outer, tol = 1000, 40, 1e-9
+    say(f"batched IR solve bf16={bf16}")
+    fs = [W.fourier_rhs(n, seed=g + 1, count=8, kmax=8) for g, n in enumerate(sizes)]
+    fs[5] = np.zeros_like(fs[5])
+    ut = to_dev([W.zeros(n) for n in sizes])
+    ft = to_dev(fs)
+    infos = rb.rbgs_solve_batched(ut, ft, inner * max_outer, tol, inner,
+                                  precision="bf16rhs_ir" if bf16 else "f32_ir")
+    for g, n in enumerate(sizes):
+        ref = W.zeros(n)
+        rc, outer, rel = oracle.ir_solve(ref, fs[g], W.spacing(n), inner, max_outer, tol,
+                                         rhs_bf16=bf16)
+        assert rc == 0 and infos[g]["status"] == 0, (g, infos[g], rc)
+        assert infos[g]["outer_iters"] == outer, (g, infos[g], outer)
+        assert infos[g]["sweeps"] == inner * outer
+        assert np.array_equal(ut[g].cpu().numpy(), ref), f"grid {g} (n={n})"
+        assert infos[g]["rel_residual"] == pytest.approx(rel, rel=1e-12, abs=1e-300)
+    assert infos[5]["outer_iters"] == 0
+
+
+def test_solve_batched_sweep_cap():
+    """max_sweeps not a multiple of inner_sweeps: the last step of a grid takes
+    the remaining sweeps (the single-grid solve's rule), and a grid that does
+    not reach the tolerance reports RBGS_ENOCONV with sweeps == max_sweeps."""
+    sizes = [127, 63]
+    say("batched IR solve, sweep cap")
+    fs = [W.fourier_rhs(n, seed=11 + g, count=8, kmax=8) for g, n in enumerate(sizes)]
+    ut = to_dev([W.zeros(n) for n in sizes])
+    ft = to_dev(fs)
+    infos = rb.rbgs_solve_batched(ut, ft, 1000, 1e-14, 300)
+    single = []
+    for g, n in enumerate(sizes):
+        u1 = to_dev([W.zeros(n)])[0]
+        single.append(rb.rbgs_solve(u1, ft[g], 1000, 1e-14, check_every=300, precision="f32_ir",
+                                    inner_sweeps=300, kernel="plain"))
+        assert np.array_equal(ut[g].cpu().numpy(), u1.cpu().numpy()), f"grid {g}"
+    for g in range(len(sizes)):
+        assert infos[g]["sweeps"] == 1000 == single[g]["sweeps"]
+        assert infos[g]["outer_iters"] == 4 == single[g]["outer_iters"]
+        assert infos[g]["status"] == rb.rbgs.ENOCONV
