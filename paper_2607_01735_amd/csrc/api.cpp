@@ -250,7 +250,8 @@ struct GroupTimer {
 // whose error word must be checked.
 template <typename T>
 int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rbgs_sweep_opts* o,
-               hipStream_t s, int* launches, void** err_state, PersistentTimer* pt) {
+               hipStream_t s, int* launches, void** err_state, PersistentTimer* pt,
+               const int* stop = nullptr) {
     const int n = g->n;
     const T h2 = T(g->h * g->h);
     T* ur = static_cast<T*>(w.u_red);
@@ -262,6 +263,8 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
     *launches = 0;
     if (kernel == RBGS_KERNEL_BLOCKED) {
         BlockedParams bp = blocked_params(n, sizeof(T), o);
+        bp.stop = stop;
+        bp.keep_error = stop != nullptr;
         T* const bred[2] = {ur, static_cast<T*>(w.u2_red)};
         T* const bblack[2] = {ub, static_cast<T*>(w.u2_black)};
         const bool timed = pt && pt->on;
@@ -291,7 +294,7 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
         if (timed) HIP_TRY(hipEventRecord(pt->ev[0], s), "event record");
         HIP_TRY(resident::run<T>(ur, ub, fr, fb, n, w.pitch, h2, nsweeps, spin,
                                  o ? o->debug_delay : 0, o ? o->debug_stall_tile : 0, w.resident,
-                                 s),
+                                 s, stop, stop != nullptr),
                 "resident sweep");
         if (timed) {
             HIP_TRY(hipEventRecord(pt->ev[1], s), "event record");
@@ -304,8 +307,10 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
     }
     const int rows = o ? o->rows_per_block : 0;
     for (int32_t it = 0; it < nsweeps; ++it) {
-        HIP_TRY(launch_half_sweep<T>(ur, ub, fr, n, w.pitch, h2, 0, rows, s), "red half-sweep");
-        HIP_TRY(launch_half_sweep<T>(ub, ur, fb, n, w.pitch, h2, 1, rows, s), "black half-sweep");
+        HIP_TRY(launch_half_sweep<T>(ur, ub, fr, n, w.pitch, h2, 0, rows, s, stop),
+                "red half-sweep");
+        HIP_TRY(launch_half_sweep<T>(ub, ur, fb, n, w.pitch, h2, 1, rows, s, stop),
+                "black half-sweep");
         *launches += 2;
     }
     return RBGS_OK;
@@ -313,9 +318,9 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
 
 int run_sweeps_dt(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w, int32_t nsweeps,
                   const rbgs_sweep_opts* o, hipStream_t s, int* launches, void** err_state,
-                  PersistentTimer* pt) {
-    return dt == RBGS_F64 ? run_sweeps<double>(g, w, nsweeps, o, s, launches, err_state, pt)
-                          : run_sweeps<float>(g, w, nsweeps, o, s, launches, err_state, pt);
+                  PersistentTimer* pt, const int* stop = nullptr) {
+    return dt == RBGS_F64 ? run_sweeps<double>(g, w, nsweeps, o, s, launches, err_state, pt, stop)
+                          : run_sweeps<float>(g, w, nsweeps, o, s, launches, err_state, pt, stop);
 }
 
 // Reads the two device sums, synchronising the stream.
@@ -346,6 +351,76 @@ int split_residual(const rbgs_grid* g, const Workspace& w, hipStream_t s, float*
 int split_residual_dt(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w, hipStream_t s) {
     return dt == RBGS_F64 ? split_residual<double>(g, w, s, nullptr, nullptr, 0)
                           : split_residual<float>(g, w, s, nullptr, nullptr, 0);
+}
+
+// The residual-cadence loop of a solve, run as a captured graph: one round
+// is k sweeps, the FP64 residual and a device-side test that raises a
+// converged flag (rel <= rel_tol, rel not finite, or `cap` rounds done); the
+// sweep kernels of later rounds see the flag and do nothing, so the iterate
+// and the sweep count are those of the host loop.  The host launches a few
+// rounds at a time and reads the flag once per batch.  *used = false when
+// the graph could not be built (e.g. a launch that cannot be captured); the
+// caller then runs the host loop.  *rounds_done: rounds whose sweeps ran.
+int solve_rounds_graph(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w,
+                       const rbgs_sweep_opts* sw, int k, int cap, double rel_tol, hipStream_t s,
+                       void** err_state, int* rounds_done, bool* used) {
+    *used = false;
+    *rounds_done = 0;
+    int* state = reinterpret_cast<int*>(reinterpret_cast<char*>(w.sums) + 64);  // {flag, rounds}
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    auto cleanup = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cs) (void)hipStreamDestroy(cs);
+    };
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return RBGS_OK;
+    }
+    int launches = 0;
+    void* es = nullptr;
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        const std::string saved = g_last_error;
+        bool body = run_sweeps_dt(dt, g, w, k, sw, cs, &launches, &es, nullptr, state) == RBGS_OK;
+        body = body && split_residual_dt(dt, g, w, cs) == RBGS_OK;
+        body = body && launch_judge(w.sums, rel_tol, state, cap, cs) == hipSuccess;
+        const bool ended = hipStreamEndCapture(cs, &graph) == hipSuccess;
+        ok = body && ended &&
+             hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (!ok) g_last_error = saved;  // a launch that cannot be captured is not a failure
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        cleanup();
+        return RBGS_OK;
+    }
+    *used = true;
+    *err_state = es;
+    // the error word of a persistent kernel is cleared once here, not per round
+    hipError_t e = launch_zero(state, 16, s);
+    if (e == hipSuccess && es) e = launch_zero(static_cast<char*>(es) + 64, 4, s);
+    const int per_poll = cap < 4 ? cap : 4;
+    int host[2] = {0, 0};
+    while (e == hipSuccess) {
+        for (int r = 0; r < per_poll && e == hipSuccess; ++r) e = hipGraphLaunch(exec, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(host, state, sizeof host, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess || host[0] != 0) break;
+        if (es) {  // a timed-out dependency wait ends the solve at once
+            int err = 0;
+            e = hipMemcpyAsync(&err, static_cast<char*>(es) + 64, sizeof err,
+                               hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e == hipSuccess && err != 0) break;
+        }
+    }
+    cleanup();
+    if (e != hipSuccess) return fail(RBGS_EHIP, std::string("solve graph: ") + hipGetErrorString(e));
+    *rounds_done = host[1];
+    return RBGS_OK;
 }
 
 
@@ -537,6 +612,22 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         } else {
             if ((rc = split_residual_dt(dt, g, w, s))) return rc;
             if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+            const int cap = o->max_sweeps / o->check_every;
+            if (!gt.t.on && !(rel <= o->rel_tol) && std::isfinite(rel) && cap > 0) {
+                // whole rounds as a captured graph; the sweeps beyond the last
+                // whole round (if still needed) in the host loop below
+                int rounds = 0;
+                bool used = false;
+                if ((rc = solve_rounds_graph(dt, g, w, &sw, o->check_every, cap, o->rel_tol, s,
+                                             &err_state, &rounds, &used)))
+                    return rc;
+                if (used) {
+                    done = rounds * o->check_every;
+                    if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+                    if (err_state && (rc = blocked_check_error(err_state, s, &g_last_error)))
+                        return rc;
+                }
+            }
             while (!(rel <= o->rel_tol) && done < o->max_sweeps && std::isfinite(rel)) {
                 int32_t k = o->max_sweeps - done < o->check_every ? o->max_sweeps - done
                                                                   : o->check_every;

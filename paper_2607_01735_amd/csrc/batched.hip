@@ -120,6 +120,7 @@ template <typename T, int V, int L>
 __global__ __launch_bounds__(kLanes) void k_blocked_batched(const GridDesc<T>* __restrict__ descs,
                                                             const int* __restrict__ tile_grid,
                                                             int total_tiles, Queue qu) {
+    if (stopped(qu)) return;
     const int total = qu.passes * total_tiles;
     for (;;) {
         const int tk = next_ticket(qu);
@@ -429,6 +430,7 @@ hipError_t enqueue_batch(const BatchSetup& su, const BatchLayout& lay, char* ws,
     qu.spin_limit = (o && o->debug_spin_limit > 0) ? o->debug_spin_limit : (1 << 22);
     qu.delay = o ? o->debug_delay : 0;
     qu.stall_tile = o ? o->debug_stall_tile : 0;
+    qu.stop = nullptr;
     // the error word is cleared once; tickets and flags before every launch
     if ((e = launch_zero(ws + lay.header, 256, s)) != hipSuccess) return e;
     int parity = 0;

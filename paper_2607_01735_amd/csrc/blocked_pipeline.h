@@ -59,7 +59,15 @@ struct Queue {
     int delay;
     int stall_tile;   // debug: global tile index + 1 that never publishes (0 = off)
     int buf_offset;   // pass p reads buffer (p + buf_offset) & 1
+    const int* stop;  // converged flag of a graph-captured solve (nullptr: none)
 };
+
+// True when a graph-captured solve has converged before this launch (the
+// flag is written by an earlier kernel of the stream, so every wave reads
+// the same value and leaves together).
+__device__ __forceinline__ bool stopped(const Queue& qu) {
+    return qu.stop != nullptr && __hip_atomic_load(qu.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
 
 template <typename T, int V>
 __device__ __forceinline__ Vec<T, V> vload(const T* p) {

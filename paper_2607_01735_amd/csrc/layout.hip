@@ -170,6 +170,27 @@ hipError_t launch_copy_ring(void* dst_red, void* dst_black, const void* src_red,
     return hipGetLastError();
 }
 
+namespace {
+__global__ __launch_bounds__(256) void k_copy_unless(uint4* __restrict__ dst,
+                                                     const uint4* __restrict__ src, size_t n,
+                                                     const int* __restrict__ stop) {
+    if (stop != nullptr && *stop != 0) return;
+    for (size_t k = size_t(blockIdx.x) * 256 + threadIdx.x; k < n; k += size_t(gridDim.x) * 256)
+        dst[k] = src[k];
+}
+}  // namespace
+
+hipError_t launch_copy_unless(void* dst, const void* src, size_t bytes, const int* stop,
+                              hipStream_t s) {
+    const size_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_copy_unless, dim3(unsigned(blocks)), dim3(256), 0, s,
+                       static_cast<uint4*>(dst), static_cast<const uint4*>(src), n, stop);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
     size_t words = bytes / 4;
     if (words == 0) return hipSuccess;

@@ -101,6 +101,8 @@ struct BlockedParams {
     int delay = 0;      // debug: per-tile delay injection
     int spin_limit = 0; // debug: bound on each flag wait
     int stall_tile = 0; // debug: tile + 1 that never publishes its progress
+    const int* stop = nullptr;  // converged flag of a graph-captured solve
+    bool keep_error = false;    // the caller cleared the error word (graph rounds)
 };
 
 // Bytes of device state (flags, ticket counter, error word) for grid size n.

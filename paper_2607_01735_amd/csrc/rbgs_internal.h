@@ -57,9 +57,12 @@ hipError_t launch_pack_f64_to_f32(const double* nat, int64_t ld, float* red, flo
                                   int n, int64_t pitch, hipStream_t s);
 
 // One half-sweep of colour `colour` (0 red, 1 black) in the split layout.
+// stop (device, optional): the kernel does nothing when *stop != 0 (the
+// converged flag of a graph-captured solve).
 template <typename T>
 hipError_t launch_half_sweep(T* self, const T* other, const T* f_self, int n, int64_t pitch,
-                             T h2, int colour, int rows_per_block, hipStream_t s);
+                             T h2, int colour, int rows_per_block, hipStream_t s,
+                             const int* stop = nullptr);
 
 // Number of partial-sum slots the residual kernels need for grid size n.
 int residual_partial_slots(int n, int64_t pitch, size_t elem_bytes);
@@ -74,6 +77,12 @@ hipError_t launch_residual_split(const T* u_red, const T* u_black, const T* f_re
                                  double* partials, double* out, float* r_out_red,
                                  float* r_out_black, int64_t r_pitch, int rhs_bf16,
                                  hipStream_t s);
+
+// Convergence test of a graph-captured solve round (device-side): from the
+// residual kernel's sums, sets state[0] (the converged flag the sweep
+// kernels' `stop` reads) when rel <= rel_tol, rel is not finite or
+// state[1] (rounds done, incremented here) reaches cap.
+hipError_t launch_judge(const double* sums, double rel_tol, int* state, int cap, hipStream_t s);
 
 // Residual norms of a natural-layout iterate (no packing).
 template <typename T>
@@ -106,5 +115,10 @@ hipError_t launch_copy_ring(void* dst_red, void* dst_black, const void* src_red,
                             hipStream_t s);
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// dst <- src for `bytes` (a multiple of 16, 16-byte aligned buffers) unless
+// stop != nullptr and *stop != 0.
+hipError_t launch_copy_unless(void* dst, const void* src, size_t bytes, const int* stop,
+                              hipStream_t s);
 
 }  // namespace rbgs

@@ -31,6 +31,7 @@ struct Args {
     int spin_limit;
     int delay;       // debug: pseudo-random stalls between epochs
     int stall_band;  // debug: band b+1 = stall_band never publishes
+    const int* stop; // converged flag of a graph-captured solve (nullptr: none)
 };
 
 // Bands for an n x n grid: ceil(n / kR), so every band owns between kH + 1
@@ -59,7 +60,8 @@ size_t state_bytes(int n, size_t elem_bytes);
 // launch's error when the bands do not fit on the device at once.
 template <typename T>
 hipError_t run(T* u_red, T* u_black, const T* f_red, const T* f_black, int n, int64_t pitch, T h2,
-               int nsweeps, int spin_limit, int delay, int stall_band, void* state, hipStream_t s);
+               int nsweeps, int spin_limit, int delay, int stall_band, void* state, hipStream_t s,
+               const int* stop = nullptr, bool keep_error = false);
 
 template <typename T>
 hipError_t launch_resident(const Args<T>& a, hipStream_t s);

@@ -203,6 +203,28 @@ hipError_t launch_residual_natural(const T* u, const T* f, int n, int64_t ld, do
     return hipGetLastError();
 }
 
+namespace {
+// The convergence test of a graph-captured solve, after each round's
+// residual: rel = ||r|| / ||b|| (||r|| when b = 0), formed exactly as the
+// host forms it; the flag stops the later rounds' sweeps.  state = {flag,
+// rounds done}; cap = rounds the sweep budget allows.
+__global__ __launch_bounds__(64) void k_judge(const double* __restrict__ sums, double rel_tol,
+                                              int* __restrict__ state, int cap) {
+    if (threadIdx.x != 0 || state[0] != 0) return;
+    const double rn = sqrt(sums[0]);
+    const double bn = sqrt(sums[1]);
+    const double rel = bn > 0.0 ? rn / bn : rn;
+    const int rounds = state[1] + 1;
+    state[1] = rounds;
+    if (rel <= rel_tol || !isfinite(rel) || rounds >= cap) state[0] = 1;
+}
+}  // namespace
+
+hipError_t launch_judge(const double* sums, double rel_tol, int* state, int cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_judge, dim3(1), dim3(64), 0, s, sums, rel_tol, state, cap);
+    return hipGetLastError();
+}
+
 template hipError_t launch_residual_split<double>(const double*, const double*, const double*,
                                                   const double*, int, int64_t, double, double*,
                                                   double*, float*, float*, int64_t, int,

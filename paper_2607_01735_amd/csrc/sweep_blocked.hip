@@ -50,6 +50,7 @@ using namespace blocked;
 
 template <typename T, int V, int L>
 __global__ __launch_bounds__(kLanes) void k_blocked(GridDesc<T> g, Queue qu) {
+    if (stopped(qu)) return;
     const int total = qu.passes * g.ntiles;
     for (;;) {
         const int tk = next_ticket(qu);
@@ -193,15 +194,18 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
     const int k = bp.fuse;
     const size_t colour_bytes = size_t(n + 2) * size_t(pitch) * sizeof(T);
     char* base = static_cast<char*>(state);
-    // the error word starts at zero once per call; tickets and flags before
-    // every launch (an error seen by an earlier launch must survive)
-    hipError_t e = launch_zero(base, 256, s);
+    // the error word starts at zero once per call (once per solve for the
+    // rounds of a captured graph); tickets and flags before every launch (an
+    // error seen by an earlier launch must survive)
+    hipError_t e = bp.keep_error ? hipSuccess : launch_zero(base, 256, s);
     if (e != hipSuccess) return e;
     if (nsweeps < 2) {  // a single sweep does not pay for a persistent launch
         for (int it = 0; it < nsweeps; ++it) {
-            e = launch_half_sweep<T>(buf_red[0], buf_black[0], f_red, n, pitch, h2, 0, 0, s);
+            e = launch_half_sweep<T>(buf_red[0], buf_black[0], f_red, n, pitch, h2, 0, 0, s,
+                                     bp.stop);
             if (e != hipSuccess) return e;
-            e = launch_half_sweep<T>(buf_black[0], buf_red[0], f_black, n, pitch, h2, 1, 0, s);
+            e = launch_half_sweep<T>(buf_black[0], buf_red[0], f_black, n, pitch, h2, 1, 0, s,
+                                     bp.stop);
             if (e != hipSuccess) return e;
             *launches += 2;
         }
@@ -267,6 +271,7 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
             qu.delay = bp.delay;
             qu.stall_tile = bp.stall_tile;
             qu.buf_offset = 0;
+            qu.stop = bp.stop;
             if (timed && ev_begin && !started) {
                 r = hipEventRecord(ev_begin, s);
                 if (r != hipSuccess) return r;
@@ -293,10 +298,10 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
     }
     *timed_fuse = d_hi;
     if (n_lo > 0 && (e = run_passes(d_hi - 1, n_lo, false)) != hipSuccess) return e;
-    if (cur != 0) {
-        e = hipMemcpyAsync(buf_red[0], buf_red[1], colour_bytes, hipMemcpyDeviceToDevice, s);
+    if (cur != 0) {  // a kernel, so that a converged graph-captured solve skips it too
+        e = launch_copy_unless(buf_red[0], buf_red[1], colour_bytes, bp.stop, s);
         if (e != hipSuccess) return e;
-        e = hipMemcpyAsync(buf_black[0], buf_black[1], colour_bytes, hipMemcpyDeviceToDevice, s);
+        e = launch_copy_unless(buf_black[0], buf_black[1], colour_bytes, bp.stop, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

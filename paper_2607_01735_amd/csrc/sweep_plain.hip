@@ -150,7 +150,10 @@ __global__ __launch_bounds__(256) void k_half_sweep(T* __restrict__ self,
                                                     const T* __restrict__ f_self, int n,
                                                     int64_t pitch, T h2, int colour,
                                                     int rows_per_block, int col_blocks,
-                                                    int nblocks) {
+                                                    int nblocks, const int* __restrict__ stop) {
+    // a solve captured in a graph stops sweeping once its residual check
+    // has raised the converged flag (set by an earlier kernel of the stream)
+    if (stop != nullptr && *stop != 0) return;
     const int L = xcd_logical_block(blockIdx.x, nblocks);
     const int strip = L / col_blocks;
     const int cb = L - strip * col_blocks;
@@ -190,17 +193,17 @@ PlainConfig plain_config(int n, int rows_per_block) {
 
 template <typename T>
 hipError_t launch_half_sweep(T* self, const T* other, const T* f_self, int n, int64_t pitch, T h2,
-                             int colour, int rows_per_block, hipStream_t s) {
+                             int colour, int rows_per_block, hipStream_t s, const int* stop) {
     constexpr int V = 16 / sizeof(T);
     PlainConfig c = plain_config<V>(n, rows_per_block);
     hipLaunchKernelGGL((k_half_sweep<T, V>), dim3(c.blocks), dim3(c.threads), 0, s, self, other,
-                       f_self, n, pitch, h2, colour, c.rows, c.col_blocks, c.blocks);
+                       f_self, n, pitch, h2, colour, c.rows, c.col_blocks, c.blocks, stop);
     return hipGetLastError();
 }
 
 template hipError_t launch_half_sweep<double>(double*, const double*, const double*, int, int64_t,
-                                              double, int, int, hipStream_t);
+                                              double, int, int, hipStream_t, const int*);
 template hipError_t launch_half_sweep<float>(float*, const float*, const float*, int, int64_t,
-                                             float, int, int, hipStream_t);
+                                             float, int, int, hipStream_t, const int*);
 
 }  // namespace rbgs

@@ -280,6 +280,9 @@ __device__ __forceinline__ void run_band(const Args<T>& a, const Band<T>& bd, T 
 // most (the register budget: u and f of the window live in registers).
 template <typename T, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_resident(Args<T> a) {
+    // a converged graph-captured solve: every workgroup leaves before any
+    // exchange (the flag was written by an earlier kernel of the stream)
+    if (a.stop != nullptr && *a.stop != 0) return;
     __shared__ Lds<T> lds;
     Band<T> bd;
     bd.n = a.n;
@@ -370,13 +373,17 @@ size_t state_bytes(int n, size_t elem_bytes) {
 
 template <typename T>
 hipError_t run(T* u_red, T* u_black, const T* f_red, const T* f_black, int n, int64_t pitch, T h2,
-               int nsweeps, int spin_limit, int delay, int stall_band, void* state, hipStream_t s) {
+               int nsweeps, int spin_limit, int delay, int stall_band, void* state, hipStream_t s,
+               const int* stop, bool keep_error) {
     if (nsweeps <= 0) return hipSuccess;
     char* base = static_cast<char*>(state);
     const int bands = bands_for(n);
     const size_t flag_bytes = align256(size_t(bands) * 4);
-    // error word (at kErrorOffset) and flags start at zero in every launch
-    hipError_t e = launch_zero(base, kHeader + flag_bytes, s);
+    // error word (at kErrorOffset) and flags start at zero in every launch;
+    // the rounds of a captured solve keep the error word, which the caller
+    // cleared once
+    hipError_t e = keep_error ? launch_zero(base + kHeader, flag_bytes, s)
+                              : launch_zero(base, kHeader + flag_bytes, s);
     if (e != hipSuccess) return e;
     Args<T> a;
     a.u_red = u_red;
@@ -395,15 +402,16 @@ hipError_t run(T* u_red, T* u_black, const T* f_red, const T* f_black, int n, in
     a.spin_limit = spin_limit;
     a.delay = delay;
     a.stall_band = stall_band;
+    a.stop = stop;
     return launch_resident<T>(a, s);
 }
 
 template hipError_t launch_resident<double>(const Args<double>&, hipStream_t);
 template hipError_t launch_resident<float>(const Args<float>&, hipStream_t);
 template hipError_t run<double>(double*, double*, const double*, const double*, int, int64_t,
-                                double, int, int, int, int, void*, hipStream_t);
+                                double, int, int, int, int, void*, hipStream_t, const int*, bool);
 template hipError_t run<float>(float*, float*, const float*, const float*, int, int64_t, float,
-                               int, int, int, int, void*, hipStream_t);
+                               int, int, int, int, void*, hipStream_t, const int*, bool);
 template int max_resident_bands<double>(int);
 template int max_resident_bands<float>(int);
 template int max_n<double>();

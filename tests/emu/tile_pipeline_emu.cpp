@@ -146,6 +146,7 @@ int main(int argc, char** argv) {
     qu.delay = 0;
     qu.stall_tile = 0;
     qu.buf_offset = 0;
+    qu.stop = nullptr;
     const size_t stack_bytes = size_t(1) << 20;
     std::vector<char*> stacks(emu::kLanes);
     for (int l = 0; l < emu::kLanes; ++l) {
