@@ -49,6 +49,9 @@ def _load(path=None):
         "rbgs_ref_solve_f64": [_i32, _i64, _f64, _vp, _vp, _i32, _f64, _i32, _vp, _vp],
         "rbgs_ref_ir_solve": [_i32, _i64, _f64, _vp, _vp, _i32, _i32, _i32, _f64, _vp, _vp],
         "rbgs_ref_colour": [_i64, _i64],
+        "rbgs_ref_sor_half_sweep_f64": [_i32, _i64, _f64, _f64, _vp, _vp, _i32],
+        "rbgs_ref_sor_sweep_f64": [_i32, _i64, _f64, _f64, _vp, _vp, _i32],
+        "rbgs_ref_sor_solve_f64": [_i32, _i64, _f64, _f64, _vp, _vp, _i32, _f64, _i32, _vp, _vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -173,6 +176,35 @@ def ir_solve(u, f, h, inner_sweeps, max_outer, rel_tol, rhs_bf16=False):
                                           ctypes.byref(outer), ctypes.byref(rel)),
                 "ir_solve")
     return rc, outer.value, rel.value
+
+
+def omega_opt(n):
+    """Optimal SOR factor of the model problem, 2 / (1 + sin(pi h)), h = 1/(n+1)."""
+    import math
+    return 2.0 / (1.0 + math.sin(math.pi / (n + 1)))
+
+
+def sor_sweep(u, f, h, omega, nsweeps):
+    """nsweeps red-black SOR sweeps in place (FP64)."""
+    n, ld = _grid(u)
+    assert u.dtype == np.float64 and f.dtype == np.float64 and f.shape == u.shape
+    _check(_load().rbgs_ref_sor_sweep_f64(n, ld, h, omega, _ptr(u), _ptr(f), nsweeps),
+           "sor_sweep_f64")
+    return u
+
+
+def sor_solve(u, f, h, omega, max_sweeps, rel_tol, check_every):
+    """SOR sweeps until rel <= rel_tol (checked every check_every sweeps).
+
+    Returns (status, sweeps_done, rel)."""
+    n, ld = _grid(u)
+    assert u.dtype == np.float64 and f.dtype == np.float64
+    done = _i32()
+    rel = _f64()
+    rc = _check(_load().rbgs_ref_sor_solve_f64(n, ld, h, omega, _ptr(u), _ptr(f), max_sweeps,
+                                               rel_tol, check_every, ctypes.byref(done),
+                                               ctypes.byref(rel)), "sor_solve_f64")
+    return rc, done.value, rel.value
 
 
 def round_bf16(x):

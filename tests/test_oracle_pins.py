@@ -492,3 +492,93 @@ def test_ir_reaches_fp64_solution(oracle, bf16):
     assert rel_err(u, cf.dst_solve(f)) < 1e-10
     _, rel_check = oracle.residual(u, f, h)
     assert rel_check == rel
+
+
+# --------------------------------------------------------------------------
+# Red-black SOR (the first extension: over-relaxed Gauss-Seidel)
+# --------------------------------------------------------------------------
+def sor_sweep_numpy(u, f, h, omega, nsweeps):
+    """The same SOR, written independently of the oracle: each colour is
+    updated as a whole array (points of one colour never read each other)."""
+    n = u.shape[0] - 2
+    h2 = h * h
+    ii, jj = np.meshgrid(np.arange(1, n + 1), np.arange(1, n + 1), indexing="ij")
+    for _ in range(nsweeps):
+        for c in (0, 1):
+            m = ((ii + jj) & 1) == c
+            i, j = ii[m], jj[m]
+            s = u[i + 1, j] + u[i - 1, j]
+            s = s + u[i, j + 1]
+            s = s + u[i, j - 1]
+            s = s - h2 * f[i, j]
+            g = 0.25 * s
+            old = u[i, j]
+            u[i, j] = old + omega * (g - old)
+    return u
+
+
+@pytest.mark.parametrize("n,omega", [(15, 0.7), (16, 1.3), (23, 1.9)])
+def test_sor_matches_independent_numpy(oracle, n, omega):
+    h = W.spacing(n)
+    f = W.uniform_rhs(n, seed=n)
+    u = W.random_ring(n, seed=n + 1)
+    u[1:n + 1, 1:n + 1] = W.uniform_rhs(n, seed=n + 2)[1:n + 1, 1:n + 1]
+    ref = sor_sweep_numpy(u.copy(), f, h, omega, 7)
+    got = oracle.sor_sweep(u.copy(), f, h, omega, 7)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("omega", [0.6, 1.5, 1.95])
+def test_sor_fixed_point_is_the_discrete_solution(oracle, omega):
+    """A sweep leaves the exact discrete solution in place (to rounding)."""
+    n = 13
+    h = W.spacing(n)
+    f = W.uniform_rhs(n, seed=3)
+    ring = W.random_ring(n, seed=4)
+    u = cf.dense_solve(f, ring)
+    before = u.copy()
+    oracle.sor_sweep(u, f, h, omega, 3)
+    assert rel_err(u, before) < 1e-13
+
+
+def test_sor_omega_one_is_gauss_seidel(oracle):
+    n = 31
+    h = W.spacing(n)
+    f = W.uniform_rhs(n, seed=5)
+    a, b = W.zeros(n), W.zeros(n)
+    oracle.sor_sweep(a, f, h, 1.0, 50)
+    oracle.sweep(b, f, h, 50)
+    assert rel_err(a, b) < 1e-13
+
+
+@pytest.mark.parametrize("omega", [1.3, 1.6])
+def test_sor_rate_is_youngs(oracle, omega):
+    """Below the optimum, the asymptotic error factor per red-black SOR sweep
+    is Young's ((omega mu + sqrt(omega^2 mu^2 - 4(omega - 1))) / 2)^2 with
+    mu = cos(pi h), the Jacobi factor of the model problem."""
+    n = 31
+    h = W.spacing(n)
+    mu = np.cos(np.pi * h)
+    assert omega < oracle.omega_opt(n)
+    rho = ((omega * mu + np.sqrt(omega ** 2 * mu ** 2 - 4 * (omega - 1))) / 2) ** 2
+    f = W.uniform_rhs(n, seed=6)
+    exact = cf.dst_solve(f)
+    u = W.zeros(n)
+    oracle.sor_sweep(u, f, h, omega, 150)
+    e0 = np.linalg.norm(u - exact)
+    oracle.sor_sweep(u, f, h, omega, 40)
+    e1 = np.linalg.norm(u - exact)
+    assert (e1 / e0) ** (1 / 40) == pytest.approx(rho, rel=2e-3)
+
+
+def test_sor_optimal_omega_cuts_sweeps(oracle):
+    """At omega_opt = 2/(1 + sin(pi h)) the sweeps to 1e-8 fall from O(N^2)
+    to O(N): at N = 63, a few hundred instead of about ten thousand."""
+    n = 63
+    h = W.spacing(n)
+    f = W.sine_rhs(n)
+    rc, done_sor, rel = oracle.sor_solve(W.zeros(n), f, h, oracle.omega_opt(n), 20000, 1e-8, 10)
+    assert rc == 0 and rel <= 1e-8
+    rc, done_gs, _ = oracle.solve(W.zeros(n), f, h, 20000, 1e-8, 10)
+    assert rc == 0
+    assert done_sor < 400 and done_gs > 10 * done_sor
