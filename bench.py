@@ -113,8 +113,9 @@ def time_to_tolerance(torch, rb, W, n=255, tol=1e-8):
     """Wall time and sweeps to rel <= tol from u = 0 on the n x n problem with
     f = 2 pi^2 sin(pi x) sin(pi y) (124 616 sweeps at n = 255 by the closed
     form), for the plain FP64 judge and the faster forms: the resident band
-    kernel and the blocked kernel in FP64, and FP64 refinement around FP32
-    (or bfloat16-rhs) inner sweeps on the resident kernel."""
+    kernel and the blocked kernel in FP64, FP64 refinement around FP32 (or
+    bfloat16-rhs) inner sweeps on the resident kernel, and red-black SOR at
+    the optimal omega (the extension that changes the sweep count)."""
     h = W.spacing(n)
     f = torch.from_numpy(W.sine_rhs(n)).to("cuda")
     out = {"problem": f"{n}x{n} FP64 sine, u0=0, rel<={tol:g}"}
@@ -124,7 +125,8 @@ def time_to_tolerance(torch, rb, W, n=255, tol=1e-8):
              ("f32_ir_resident", dict(kernel="resident", precision="f32_ir", inner_sweeps=4000,
                                       check_every=4000)),
              ("bf16rhs_ir_resident", dict(kernel="resident", precision="bf16rhs_ir",
-                                          inner_sweeps=1000, check_every=1000))]
+                                          inner_sweeps=1000, check_every=1000)),
+             ("sor_f64", dict(kernel="plain", omega=0.0, check_every=10))]
     for name, kw in forms:
         u = torch.zeros((n + 2, n + 2), dtype=torch.float64, device="cuda")
         warm = {k: v for k, v in kw.items() if k not in ("inner_sweeps", "check_every")}
@@ -157,7 +159,8 @@ def time_to_tolerance_fourier(torch, rb, W, n=1023, tol=1e-8):
              ("f32_ir_blocked", dict(kernel="blocked", precision="f32_ir", inner_sweeps=4000,
                                      check_every=4000)),
              ("bf16rhs_ir", dict(kernel="auto", precision="bf16rhs_ir", inner_sweeps=1000,
-                                 check_every=1000))]
+                                 check_every=1000)),
+             ("sor_f64", dict(kernel="plain", omega=0.0, check_every=50))]
     for name, kw in forms:
         u = torch.zeros((n + 2, n + 2), dtype=torch.float64, device="cuda")
         warm = {k: v for k, v in kw.items() if k not in ("inner_sweeps", "check_every")}

@@ -56,7 +56,7 @@ typedef enum {
     RBGS_ENOCONV = -3,      /* tolerance not reached within the sweep cap  */
     RBGS_ETIMEOUT = -4,     /* a bounded wait in the persistent kernel expired */
     RBGS_ENONFINITE = -5,   /* the residual became NaN or infinite         */
-    RBGS_EUNSUPPORTED = -6, /* valid but not implemented (e.g. omega != 1) */
+    RBGS_EUNSUPPORTED = -6, /* valid but not implemented (e.g. SOR in FP32)  */
     RBGS_EWORKSPACE = -8    /* workspace missing, too small or misaligned  */
 } rbgs_status;
 
@@ -151,7 +151,12 @@ typedef struct {
     int32_t check_every;   /* full sweeps between residual checks, >= 1        */
     int32_t precision;     /* rbgs_precision; IR modes need RBGS_F64 storage   */
     int32_t inner_sweeps;  /* IR: FP32 sweeps per outer step (0 = check_every) */
-    double omega;          /* relaxation; only 1.0 (plain Gauss-Seidel)        */
+    double omega;          /* relaxation: 1.0 = Gauss-Seidel (the paper's method);
+                              in (0, 2) = red-black SOR, u <- u + omega (g - u)
+                              with g the Gauss-Seidel value (an extension: FP64,
+                              plain kernel, no refinement; else
+                              RBGS_EUNSUPPORTED); 0.0 = the model problem's
+                              optimum 2 / (1 + sin(pi h)) for this grid's h   */
     rbgs_sweep_opts sweep; /* kernel choice for the (inner) sweeps             */
 } rbgs_solve_opts;
 

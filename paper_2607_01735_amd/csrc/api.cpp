@@ -251,7 +251,7 @@ struct GroupTimer {
 template <typename T>
 int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rbgs_sweep_opts* o,
                hipStream_t s, int* launches, void** err_state, PersistentTimer* pt,
-               const int* stop = nullptr) {
+               const int* stop = nullptr, double omega = 1.0) {
     const int n = g->n;
     const T h2 = T(g->h * g->h);
     T* ur = static_cast<T*>(w.u_red);
@@ -259,6 +259,7 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
     const T* fr = static_cast<const T*>(w.f_red);
     const T* fb = static_cast<const T*>(w.f_black);
     int kernel = o ? o->kernel : RBGS_KERNEL_AUTO;
+    if (omega != 1.0) kernel = RBGS_KERNEL_PLAIN;  // SOR: the plain kernel only (checked by the caller)
     if (kernel == RBGS_KERNEL_AUTO) kernel = auto_kernel(n, sizeof(T), nsweeps);
     *launches = 0;
     if (kernel == RBGS_KERNEL_BLOCKED) {
@@ -307,9 +308,9 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
     }
     const int rows = o ? o->rows_per_block : 0;
     for (int32_t it = 0; it < nsweeps; ++it) {
-        HIP_TRY(launch_half_sweep<T>(ur, ub, fr, n, w.pitch, h2, 0, rows, s, stop),
+        HIP_TRY(launch_half_sweep<T>(ur, ub, fr, n, w.pitch, h2, 0, rows, s, stop, T(omega)),
                 "red half-sweep");
-        HIP_TRY(launch_half_sweep<T>(ub, ur, fb, n, w.pitch, h2, 1, rows, s, stop),
+        HIP_TRY(launch_half_sweep<T>(ub, ur, fb, n, w.pitch, h2, 1, rows, s, stop, T(omega)),
                 "black half-sweep");
         *launches += 2;
     }
@@ -318,9 +319,10 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
 
 int run_sweeps_dt(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w, int32_t nsweeps,
                   const rbgs_sweep_opts* o, hipStream_t s, int* launches, void** err_state,
-                  PersistentTimer* pt, const int* stop = nullptr) {
-    return dt == RBGS_F64 ? run_sweeps<double>(g, w, nsweeps, o, s, launches, err_state, pt, stop)
-                          : run_sweeps<float>(g, w, nsweeps, o, s, launches, err_state, pt, stop);
+                  PersistentTimer* pt, const int* stop = nullptr, double omega = 1.0) {
+    return dt == RBGS_F64
+               ? run_sweeps<double>(g, w, nsweeps, o, s, launches, err_state, pt, stop, omega)
+               : run_sweeps<float>(g, w, nsweeps, o, s, launches, err_state, pt, stop, omega);
 }
 
 // Reads the two device sums, synchronising the stream.
@@ -362,8 +364,8 @@ int split_residual_dt(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w, hip
 // the graph could not be built (e.g. a launch that cannot be captured); the
 // caller then runs the host loop.  *rounds_done: rounds whose sweeps ran.
 int solve_rounds_graph(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w,
-                       const rbgs_sweep_opts* sw, int k, int cap, double rel_tol, hipStream_t s,
-                       void** err_state, int* rounds_done, bool* used) {
+                       const rbgs_sweep_opts* sw, int k, int cap, double rel_tol, double omega,
+                       hipStream_t s, void** err_state, int* rounds_done, bool* used) {
     *used = false;
     *rounds_done = 0;
     int* state = reinterpret_cast<int*>(reinterpret_cast<char*>(w.sums) + 64);  // {flag, rounds}
@@ -384,7 +386,8 @@ int solve_rounds_graph(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w,
     bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
         const std::string saved = g_last_error;
-        bool body = run_sweeps_dt(dt, g, w, k, sw, cs, &launches, &es, nullptr, state) == RBGS_OK;
+        bool body =
+            run_sweeps_dt(dt, g, w, k, sw, cs, &launches, &es, nullptr, state, omega) == RBGS_OK;
         body = body && split_residual_dt(dt, g, w, cs) == RBGS_OK;
         body = body && launch_judge(w.sums, rel_tol, state, cap, cs) == hipSuccess;
         const bool ended = hipStreamEndCapture(cs, &graph) == hipSuccess;
@@ -564,9 +567,18 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
     if (o->precision < RBGS_PREC_F64 || o->precision > RBGS_PREC_BF16RHS_IR)
         return fail(RBGS_EINVAL, "unknown precision");
     if (o->inner_sweeps < 0) return fail(RBGS_EINVAL, "inner_sweeps must be >= 0");
-    if (o->omega != 1.0)
-        return fail(RBGS_EUNSUPPORTED, "only omega = 1 (Gauss-Seidel) is implemented");
     const bool ir = is_ir(o);
+    // omega: 1 = Gauss-Seidel; (0, 2) = red-black SOR; 0 = the model
+    // problem's optimum 2 / (1 + sin(pi h)) for this grid's h
+    const double omega = o->omega == 0.0 ? 2.0 / (1.0 + std::sin(M_PI * g->h)) : o->omega;
+    if (omega != 1.0) {
+        if (!(omega > 0.0 && omega < 2.0))
+            return fail(RBGS_EINVAL, "omega must be in (0, 2), or 0 for the optimum");
+        if (dt != RBGS_F64 || ir)
+            return fail(RBGS_EUNSUPPORTED, "SOR (omega != 1) runs in FP64 without refinement");
+        if (o->sweep.kernel != RBGS_KERNEL_AUTO && o->sweep.kernel != RBGS_KERNEL_PLAIN)
+            return fail(RBGS_EUNSUPPORTED, "SOR (omega != 1) runs on the plain kernel");
+    }
     if (ir && dt != RBGS_F64)
         return fail(RBGS_EINVAL, "refinement modes need FP64 storage of u and f");
     int rc = validate_sweep_opts(&o->sweep);
@@ -602,7 +614,9 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         int32_t done = 0;
         if (o->rel_tol <= 0.0) {
             HIP_TRY(gt.begin(s), "event record");
-            if ((rc = run_sweeps_dt(dt, g, w, o->max_sweeps, &sw, s, &launches, &err_state, &pt))) return rc;
+            if ((rc = run_sweeps_dt(dt, g, w, o->max_sweeps, &sw, s, &launches, &err_state, &pt,
+                                    nullptr, omega)))
+                return rc;
             HIP_TRY(gt.end(s), "event record");
             HIP_TRY(gt.collect(launches), "event time");
             HIP_TRY(pt.collect(), "event time");
@@ -618,8 +632,8 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
                 // whole round (if still needed) in the host loop below
                 int rounds = 0;
                 bool used = false;
-                if ((rc = solve_rounds_graph(dt, g, w, &sw, o->check_every, cap, o->rel_tol, s,
-                                             &err_state, &rounds, &used)))
+                if ((rc = solve_rounds_graph(dt, g, w, &sw, o->check_every, cap, o->rel_tol, omega,
+                                             s, &err_state, &rounds, &used)))
                     return rc;
                 if (used) {
                     done = rounds * o->check_every;
@@ -632,7 +646,9 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
                 int32_t k = o->max_sweeps - done < o->check_every ? o->max_sweeps - done
                                                                   : o->check_every;
                 HIP_TRY(gt.begin(s), "event record");
-                if ((rc = run_sweeps_dt(dt, g, w, k, &sw, s, &launches, &err_state, &pt))) return rc;
+                if ((rc = run_sweeps_dt(dt, g, w, k, &sw, s, &launches, &err_state, &pt, nullptr,
+                                        omega)))
+                    return rc;
                 HIP_TRY(gt.end(s), "event record");
                 HIP_TRY(gt.collect(launches), "event time");
                 HIP_TRY(pt.collect(), "event time");

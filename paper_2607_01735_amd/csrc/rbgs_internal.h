@@ -58,11 +58,12 @@ hipError_t launch_pack_f64_to_f32(const double* nat, int64_t ld, float* red, flo
 
 // One half-sweep of colour `colour` (0 red, 1 black) in the split layout.
 // stop (device, optional): the kernel does nothing when *stop != 0 (the
-// converged flag of a graph-captured solve).
+// converged flag of a graph-captured solve).  omega != 1: red-black SOR,
+// u <- u + omega (g - u) with g the Gauss-Seidel value.
 template <typename T>
 hipError_t launch_half_sweep(T* self, const T* other, const T* f_self, int n, int64_t pitch,
                              T h2, int colour, int rows_per_block, hipStream_t s,
-                             const int* stop = nullptr);
+                             const int* stop = nullptr, T omega = T(1));
 
 // Number of partial-sum slots the residual kernels need for grid size n.
 int residual_partial_slots(int n, int64_t pitch, size_t elem_bytes);

@@ -1,6 +1,7 @@
 // Plain half-sweep kernel: one launch updates every interior point of one
 // colour (Eq. (1)), so consecutive launches play the role of the barriers
-// after each colour in Algorithm 1.
+// after each colour in Algorithm 1.  A variant over-relaxes the update
+// (red-black SOR); it also reads the colour it writes, 4 words per update.
 //
 // Data: split colour layout (rbgs_internal.h).  A workgroup owns a column
 // band of BT*V q-columns and a strip of R interior rows; each thread owns V
@@ -73,11 +74,13 @@ __device__ __forceinline__ void store_pack_nt(T* p, const Pack<T, V>& v) {
 
 // Update row i whose parity p = (i + colour) & 1 is a compile-time value.
 // up/mid/dn: other colour, rows i-1, i, i+1 at q0..q0+V-1.
-template <typename T, int V, int P>
+// SOR: the Gauss-Seidel value g relaxes the old value, u + omega (g - u),
+// each operation rounded once (red-black SOR, the over-relaxed method).
+template <typename T, int V, int P, bool SOR>
 __device__ __forceinline__ void update_row(T* __restrict__ self_row, const T* __restrict__ mid_row,
                                            const Pack<T, V>& up, const Pack<T, V>& mid,
                                            const Pack<T, V>& dn, const Pack<T, V>& fc, T h2,
-                                           int64_t q0, int n) {
+                                           int64_t q0, int n, T omega) {
     // P = 1: right neighbour of q is q+1, left is q; P = 0: right q, left q-1.
     // The value outside the thread's vector is the neighbouring lane's first
     // (or last) element, taken through a DPP whole-wave shift; only the lanes
@@ -93,6 +96,8 @@ __device__ __forceinline__ void update_row(T* __restrict__ self_row, const T* __
         if (lane == 0) extra = mid_row[q0 - 1];
     }
     Pack<T, V> out;
+    Pack<T, V> old;
+    if constexpr (SOR) old = load_pack<T, V>(self_row + q0);
 #pragma unroll
     for (int e = 0; e < V; ++e) {
         T right = P ? (e + 1 < V ? mid.v[e + 1] : extra) : mid.v[e];
@@ -102,7 +107,14 @@ __device__ __forceinline__ void update_row(T* __restrict__ self_row, const T* __
         s = s + left;
         T t = h2 * fc.v[e];
         s = s - t;
-        out.v[e] = T(0.25) * s;
+        const T g = T(0.25) * s;
+        if constexpr (SOR) {
+            const T d = g - old.v[e];
+            const T w = omega * d;
+            out.v[e] = old.v[e] + w;
+        } else {
+            out.v[e] = g;
+        }
     }
     const int64_t q_lo = 1 - P, q_hi = (int64_t(n) - P) >> 1;
     if (q0 >= q_lo && q0 + V - 1 <= q_hi) {
@@ -116,10 +128,10 @@ __device__ __forceinline__ void update_row(T* __restrict__ self_row, const T* __
 
 // Rows i0..i1 of one strip, first row parity P0; two rows per step so both
 // parities are compile-time constants.
-template <typename T, int V, int P0>
+template <typename T, int V, int P0, bool SOR>
 __device__ __forceinline__ void march(T* __restrict__ self, const T* __restrict__ other,
                                       const T* __restrict__ f_self, int n, int64_t pitch, T h2,
-                                      int64_t q0, int i0, int i1) {
+                                      int64_t q0, int i0, int i1, T omega) {
     const T* o = other + q0;
     Pack<T, V> up = load_pack<T, V>(o + int64_t(i0 - 1) * pitch);
     Pack<T, V> mid = load_pack<T, V>(o + int64_t(i0) * pitch);
@@ -129,28 +141,30 @@ __device__ __forceinline__ void march(T* __restrict__ self, const T* __restrict_
         Pack<T, V> dn1 = load_pack<T, V>(o + int64_t(i + 2) * pitch);
         Pack<T, V> f0 = load_pack_nt<T, V>(f_self + int64_t(i) * pitch + q0);
         Pack<T, V> f1 = load_pack_nt<T, V>(f_self + int64_t(i + 1) * pitch + q0);
-        update_row<T, V, P0>(self + int64_t(i) * pitch, other + int64_t(i) * pitch, up, mid, dn0,
-                             f0, h2, q0, n);
-        update_row<T, V, 1 - P0>(self + int64_t(i + 1) * pitch, other + int64_t(i + 1) * pitch,
-                                 mid, dn0, dn1, f1, h2, q0, n);
+        update_row<T, V, P0, SOR>(self + int64_t(i) * pitch, other + int64_t(i) * pitch, up, mid,
+                                  dn0, f0, h2, q0, n, omega);
+        update_row<T, V, 1 - P0, SOR>(self + int64_t(i + 1) * pitch,
+                                      other + int64_t(i + 1) * pitch, mid, dn0, dn1, f1, h2, q0, n,
+                                      omega);
         up = dn0;
         mid = dn1;
     }
     if (i <= i1) {
         Pack<T, V> dn0 = load_pack<T, V>(o + int64_t(i + 1) * pitch);
         Pack<T, V> f0 = load_pack_nt<T, V>(f_self + int64_t(i) * pitch + q0);
-        update_row<T, V, P0>(self + int64_t(i) * pitch, other + int64_t(i) * pitch, up, mid, dn0,
-                             f0, h2, q0, n);
+        update_row<T, V, P0, SOR>(self + int64_t(i) * pitch, other + int64_t(i) * pitch, up, mid,
+                                  dn0, f0, h2, q0, n, omega);
     }
 }
 
-template <typename T, int V>
+template <typename T, int V, bool SOR>
 __global__ __launch_bounds__(256) void k_half_sweep(T* __restrict__ self,
                                                     const T* __restrict__ other,
                                                     const T* __restrict__ f_self, int n,
                                                     int64_t pitch, T h2, int colour,
                                                     int rows_per_block, int col_blocks,
-                                                    int nblocks, const int* __restrict__ stop) {
+                                                    int nblocks, const int* __restrict__ stop,
+                                                    T omega) {
     // a solve captured in a graph stops sweeping once its residual check
     // has raised the converged flag (set by an earlier kernel of the stream)
     if (stop != nullptr && *stop != 0) return;
@@ -162,9 +176,9 @@ __global__ __launch_bounds__(256) void k_half_sweep(T* __restrict__ self,
     const int i0 = 1 + strip * rows_per_block;
     const int i1 = min(n, i0 + rows_per_block - 1);
     if (((i0 + colour) & 1) == 0)
-        march<T, V, 0>(self, other, f_self, n, pitch, h2, q0, i0, i1);
+        march<T, V, 0, SOR>(self, other, f_self, n, pitch, h2, q0, i0, i1, omega);
     else
-        march<T, V, 1>(self, other, f_self, n, pitch, h2, q0, i0, i1);
+        march<T, V, 1, SOR>(self, other, f_self, n, pitch, h2, q0, i0, i1, omega);
 }
 
 struct PlainConfig {
@@ -193,17 +207,24 @@ PlainConfig plain_config(int n, int rows_per_block) {
 
 template <typename T>
 hipError_t launch_half_sweep(T* self, const T* other, const T* f_self, int n, int64_t pitch, T h2,
-                             int colour, int rows_per_block, hipStream_t s, const int* stop) {
+                             int colour, int rows_per_block, hipStream_t s, const int* stop,
+                             T omega) {
     constexpr int V = 16 / sizeof(T);
     PlainConfig c = plain_config<V>(n, rows_per_block);
-    hipLaunchKernelGGL((k_half_sweep<T, V>), dim3(c.blocks), dim3(c.threads), 0, s, self, other,
-                       f_self, n, pitch, h2, colour, c.rows, c.col_blocks, c.blocks, stop);
+    if (omega == T(1))
+        hipLaunchKernelGGL((k_half_sweep<T, V, false>), dim3(c.blocks), dim3(c.threads), 0, s, self,
+                           other, f_self, n, pitch, h2, colour, c.rows, c.col_blocks, c.blocks, stop,
+                           omega);
+    else
+        hipLaunchKernelGGL((k_half_sweep<T, V, true>), dim3(c.blocks), dim3(c.threads), 0, s, self,
+                           other, f_self, n, pitch, h2, colour, c.rows, c.col_blocks, c.blocks, stop,
+                           omega);
     return hipGetLastError();
 }
 
 template hipError_t launch_half_sweep<double>(double*, const double*, const double*, int, int64_t,
-                                              double, int, int, hipStream_t, const int*);
+                                              double, int, int, hipStream_t, const int*, double);
 template hipError_t launch_half_sweep<float>(float*, const float*, const float*, int, int64_t,
-                                             float, int, int, hipStream_t, const int*);
+                                             float, int, int, hipStream_t, const int*, float);
 
 }  // namespace rbgs

@@ -112,15 +112,22 @@ def test_sweep_validation_before_device_work(lib, bad):
     assert lib.rbgs_last_error()
 
 
-@pytest.mark.parametrize("bad", ["omega", "check", "maxs", "prec", "ir_f32", "nan_tol", "inner"])
+@pytest.mark.parametrize("bad", ["omega", "omega_range", "sor_f32", "sor_ir", "check", "maxs",
+                                 "prec", "ir_f32", "nan_tol", "inner"])
 def test_solve_validation_before_device_work(lib, bad):
     g = _grid(lib, 31)
     o = lib.rbgs_solve_opts()
     o.max_sweeps, o.rel_tol, o.check_every, o.omega = 10, 1e-8, 5, 1.0
     dtype = lib.F64
     expect = lib.EINVAL
-    if bad == "omega":
-        o.omega, expect = 1.5, lib.EUNSUPPORTED
+    if bad == "omega":  # SOR runs on the plain kernel only
+        o.omega, o.sweep.kernel, expect = 1.5, lib._KERNELS["blocked"], lib.EUNSUPPORTED
+    elif bad == "omega_range":
+        o.omega = 2.5
+    elif bad == "sor_f32":
+        o.omega, dtype, expect = 1.5, lib.F32, lib.EUNSUPPORTED
+    elif bad == "sor_ir":
+        o.omega, o.precision, expect = 1.5, lib.PREC_F32_IR, lib.EUNSUPPORTED
     elif bad == "check":
         o.check_every = 0
     elif bad == "maxs":

@@ -178,9 +178,9 @@ def test_error_paths_on_device():
     with pytest.raises(rb.RbgsError) as e:
         rb.rbgs_sweep(u, f, 1, workspace=ws)
     assert e.value.status == rb.rbgs.EWORKSPACE
-    # omega != 1 is not implemented
+    # SOR (omega != 1) runs on the plain kernel only
     with pytest.raises(rb.RbgsError) as e:
-        rb.rbgs_solve(u, f, 10, 1e-6, omega=1.5)
+        rb.rbgs_solve(u, f, 10, 1e-6, omega=1.5, kernel="blocked")
     assert e.value.status == rb.rbgs.EUNSUPPORTED
     # a NaN right-hand side gives a non-finite residual
     fn = f.clone()

@@ -1,0 +1,79 @@
+"""Red-black SOR on the GPU (the over-relaxed extension of the method):
+sweeps and solves must equal the oracle's SOR bit for bit, and omega = 0
+selects the model problem's optimum."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2607_01735_amd as rb  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def start(n, seed, ld=None):
+    u = W.random_ring(n, seed=seed, ld=ld)
+    u[1:n + 1, 1:n + 1] = W.uniform_rhs(n, seed=seed + 1)[1:n + 1, 1:n + 1]
+    return u, W.uniform_rhs(n, seed=seed + 2, ld=ld)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 63, 100, 255, 1023])
+@pytest.mark.parametrize("omega", [0.8, 1.5, 1.9])
+def test_sor_sweeps_bitwise(oracle, n, omega):
+    say(f"SOR sweeps n={n} omega={omega}")
+    h = W.spacing(n)
+    ld = n + 2 + (n % 3)
+    u0, f = start(n, n, ld=ld)
+    ut, ft = dev(u0), dev(f)
+    info = rb.rbgs_solve(ut, ft, 5, 0.0, check_every=5, h=h, omega=omega, kernel="plain")
+    assert info["sweeps"] == 5
+    ref = oracle.sor_sweep(u0.copy(), f, h, omega, 5)
+    assert np.array_equal(ut.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("kernel", ["plain", "auto"])
+def test_sor_solve_matches_oracle(oracle, kernel):
+    n = 127
+    say(f"SOR solve n={n} kernel={kernel}")
+    h = W.spacing(n)
+    f = W.fourier_rhs(n, seed=2, count=16, kmax=16)
+    omega = oracle.omega_opt(n)
+    ut = dev(W.zeros(n))
+    info = rb.rbgs_solve(ut, dev(f), 20000, 1e-9, check_every=10, h=h, omega=omega, kernel=kernel)
+    ref = W.zeros(n)
+    rc, done, rel = oracle.sor_solve(ref, f, h, omega, 20000, 1e-9, 10)
+    assert rc == 0 and info["status"] == 0
+    assert info["sweeps"] == done
+    assert np.array_equal(ut.cpu().numpy(), ref)
+    assert info["rel_residual"] == pytest.approx(rel, rel=1e-12)
+
+
+def test_sor_omega_zero_is_the_optimum():
+    n = 255
+    say("SOR omega = 0")
+    h = W.spacing(n)
+    f = dev(W.sine_rhs(n))
+    a, b = dev(W.zeros(n)), dev(W.zeros(n))
+    ia = rb.rbgs_solve(a, f, 20000, 1e-8, check_every=10, h=h, omega=0.0)
+    ib = rb.rbgs_solve(b, f, 20000, 1e-8, check_every=10, h=h,
+                       omega=2.0 / (1.0 + np.sin(np.pi * h)))
+    assert ia["status"] == ib["status"] == 0
+    assert ia["sweeps"] == ib["sweeps"] < 2000
+    assert torch.equal(a, b)
