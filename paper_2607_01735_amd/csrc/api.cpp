@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <functional>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -363,8 +364,11 @@ int split_residual_dt(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w, hip
 // rounds at a time and reads the flag once per batch.  *used = false when
 // the graph could not be built (e.g. a launch that cannot be captured); the
 // caller then runs the host loop.  *rounds_done: rounds whose sweeps ran.
-int solve_rounds_graph(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w,
-                       const rbgs_sweep_opts* sw, int k, int cap, double rel_tol, double omega,
+// body(stream, stop, &err_state) enqueues one round's work up to and
+// including the residual (sums in w.sums); the judge follows it.
+using RoundBody = std::function<int(hipStream_t, const int*, void**)>;
+
+int solve_rounds_graph(const Workspace& w, const RoundBody& body_fn, int cap, double rel_tol,
                        hipStream_t s, void** err_state, int* rounds_done, bool* used) {
     *used = false;
     *rounds_done = 0;
@@ -381,14 +385,11 @@ int solve_rounds_graph(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w,
         (void)hipGetLastError();
         return RBGS_OK;
     }
-    int launches = 0;
     void* es = nullptr;
     bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
         const std::string saved = g_last_error;
-        bool body =
-            run_sweeps_dt(dt, g, w, k, sw, cs, &launches, &es, nullptr, state, omega) == RBGS_OK;
-        body = body && split_residual_dt(dt, g, w, cs) == RBGS_OK;
+        bool body = body_fn(cs, state, &es) == RBGS_OK;
         body = body && launch_judge(w.sums, rel_tol, state, cap, cs) == hipSuccess;
         const bool ended = hipStreamEndCapture(cs, &graph) == hipSuccess;
         ok = body && ended &&
@@ -632,8 +633,14 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
                 // whole round (if still needed) in the host loop below
                 int rounds = 0;
                 bool used = false;
-                if ((rc = solve_rounds_graph(dt, g, w, &sw, o->check_every, cap, o->rel_tol, omega,
-                                             s, &err_state, &rounds, &used)))
+                const int k = o->check_every;
+                RoundBody body = [&](hipStream_t cs, const int* stop, void** es) -> int {
+                    int l = 0;
+                    int r = run_sweeps_dt(dt, g, w, k, &sw, cs, &l, es, nullptr, stop, omega);
+                    return r ? r : split_residual_dt(dt, g, w, cs);
+                };
+                if ((rc = solve_rounds_graph(w, body, cap, o->rel_tol, s, &err_state, &rounds,
+                                             &used)))
                     return rc;
                 if (used) {
                     done = rounds * o->check_every;
@@ -684,6 +691,34 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         int32_t done = 0, outer = 0;
         if ((rc = split_residual<double>(g, w, s, w.r_red, w.r_black, bf16))) return rc;
         if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+        const int cap = o->max_sweeps / inner;
+        if (!gt.t.on && !(rel <= o->rel_tol) && std::isfinite(rel) && cap > 0) {
+            // whole outer steps as a captured graph (zero e, inner sweeps,
+            // correction, residual with r for the next step, the judge)
+            RoundBody body = [&](hipStream_t cs, const int* stop, void** es) -> int {
+                int l = 0;
+                HIP_TRY(launch_zero(w.e_red, c32, cs), "zero correction");
+                HIP_TRY(launch_zero(w.e_black, c32, cs), "zero correction");
+                int r = run_sweeps<float>(&gi, inner_w, inner, &sw, cs, &l, es, nullptr, stop);
+                if (r) return r;
+                HIP_TRY(launch_add_correction(static_cast<double*>(w.u_red),
+                                              static_cast<double*>(w.u_black), w.pitch, w.e_red,
+                                              w.e_black, w.pitch32, g->n, cs, stop),
+                        "correction");
+                return split_residual<double>(g, w, cs, w.r_red, w.r_black, bf16);
+            };
+            int rounds = 0;
+            bool used = false;
+            if ((rc = solve_rounds_graph(w, body, cap, o->rel_tol, s, &err_state, &rounds, &used)))
+                return rc;
+            if (used) {
+                done = rounds * inner;
+                outer = rounds;
+                if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+                if (err_state && (rc = blocked_check_error(err_state, s, &g_last_error)))
+                    return rc;
+            }
+        }
         while (!(rel <= o->rel_tol) && done < o->max_sweeps && std::isfinite(rel)) {
             int32_t k = o->max_sweeps - done < inner ? o->max_sweeps - done : inner;
             HIP_TRY(launch_zero(w.e_red, c32, s), "zero correction");

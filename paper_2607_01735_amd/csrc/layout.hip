@@ -86,7 +86,9 @@ __global__ __launch_bounds__(kThreads) void k_add_correction(double* __restrict_
                                                              int64_t pitch,
                                                              const float* __restrict__ e_red,
                                                              const float* __restrict__ e_black,
-                                                             int64_t e_pitch, int n) {
+                                                             int64_t e_pitch, int n,
+                                                             const int* __restrict__ stop) {
+    if (stop != nullptr && *stop != 0) return;  // a converged graph-captured solve
     int64_t q = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     int64_t i = int64_t(blockIdx.y) + 1;
 #pragma unroll
@@ -146,10 +148,10 @@ hipError_t launch_pack_f64_to_f32(const double* nat, int64_t ld, float* red, flo
 
 hipError_t launch_add_correction(double* u_red, double* u_black, int64_t pitch,
                                  const float* e_red, const float* e_black, int64_t e_pitch, int n,
-                                 hipStream_t s) {
+                                 hipStream_t s, const int* stop) {
     dim3 grid(unsigned((pitch + kThreads - 1) / kThreads), unsigned(n));
     hipLaunchKernelGGL(k_add_correction, grid, dim3(kThreads), 0, s, u_red, u_black, pitch, e_red,
-                       e_black, e_pitch, n);
+                       e_black, e_pitch, n, stop);
     return hipGetLastError();
 }
 

@@ -91,10 +91,11 @@ hipError_t launch_residual_natural(const T* u, const T* f, int n, int64_t ld, do
                                    double* partials, double* out, hipStream_t s);
 int residual_natural_partial_slots(int n);
 
-// u <- u + e at the interior points (split layouts; u FP64, e FP32).
+// u <- u + e at the interior points (split layouts; u FP64, e FP32);
+// nothing when stop != nullptr and *stop != 0.
 hipError_t launch_add_correction(double* u_red, double* u_black, int64_t pitch,
                                  const float* e_red, const float* e_black, int64_t e_pitch,
-                                 int n, hipStream_t s);
+                                 int n, hipStream_t s, const int* stop = nullptr);
 
 // Vertex-centred grid transfers over `batch` grids at constant strides
 // (natural layout): full-weighting restriction onto the nc x nc coarse

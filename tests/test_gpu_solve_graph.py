@@ -88,3 +88,27 @@ def test_graph_rounds_timeout_is_reported():
     # slowly: below 1.4 within 100 sweeps)
     info = rb.rbgs_solve(u, f, 400, 1.4, check_every=20, h=h, kernel="blocked")
     assert info["status"] == 0
+
+
+@pytest.mark.parametrize("kernel,precision", [("plain", "f32_ir"), ("blocked", "f32_ir"),
+                                              ("plain", "bf16rhs_ir"), ("resident", "f32_ir")])
+def test_graph_refinement_equals_host_loop(oracle, kernel, precision):
+    """Refinement steps (zero e, inner FP32 sweeps, correction, residual with
+    r for the next step) captured as graph rounds: same outer steps, sweeps,
+    residual and bits as the host loop and the oracle's refinement."""
+    n, inner, tol = 63, 500, 1e-10
+    say(f"graph refinement {kernel} {precision}")
+    h = W.spacing(n)
+    f = W.fourier_rhs(n, seed=4, count=8, kmax=8)
+    a_u, b_u = dev(W.zeros(n)), dev(W.zeros(n))
+    kw = dict(check_every=inner, h=h, precision=precision, inner_sweeps=inner, kernel=kernel)
+    a = rb.rbgs_solve(a_u, dev(f), 40 * inner + 123, tol, **kw)
+    b = rb.rbgs_solve(b_u, dev(f), 40 * inner + 123, tol, timing=True, **kw)
+    assert a["status"] == b["status"] == 0
+    assert a["outer_iters"] == b["outer_iters"] and a["sweeps"] == b["sweeps"]
+    assert a["rel_residual"] == b["rel_residual"]
+    assert np.array_equal(a_u.cpu().numpy(), b_u.cpu().numpy())
+    ref = W.zeros(n)
+    rc, outer, rel = oracle.ir_solve(ref, f, h, inner, 40, tol, rhs_bf16=precision == "bf16rhs_ir")
+    assert rc == 0 and outer == a["outer_iters"]
+    assert np.array_equal(a_u.cpu().numpy(), ref)
