@@ -52,6 +52,11 @@ def _load(path=None):
         "rbgs_ref_sor_half_sweep_f64": [_i32, _i64, _f64, _f64, _vp, _vp, _i32],
         "rbgs_ref_sor_sweep_f64": [_i32, _i64, _f64, _f64, _vp, _vp, _i32],
         "rbgs_ref_sor_solve_f64": [_i32, _i64, _f64, _f64, _vp, _vp, _i32, _f64, _i32, _vp, _vp],
+        "rbgs_ref_mg_levels": [_i32, _i32, _vp],
+        "rbgs_ref_mg_restrict_f64": [_i32, _vp, _i64, _vp, _i64],
+        "rbgs_ref_mg_prolong_add_f64": [_i32, _vp, _i64, _vp, _i64],
+        "rbgs_ref_mg_solve_f64": [_i32, _i64, _f64, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _f64,
+                                  _vp, _vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -205,6 +210,69 @@ def sor_solve(u, f, h, omega, max_sweeps, rel_tol, check_every):
                                                rel_tol, check_every, ctypes.byref(done),
                                                ctypes.byref(rel)), "sor_solve_f64")
     return rc, done.value, rel.value
+
+
+def mg_levels(n, max_levels=0):
+    """Grid sizes of the multigrid hierarchy: n, then (n - 1) / 2 while odd
+    and >= 3 (at most max_levels levels when max_levels > 0)."""
+    sizes = (ctypes.c_int32 * 32)()
+    cnt = _load().rbgs_ref_mg_levels(n, max_levels, sizes)
+    if cnt < 1:
+        raise ValueError("bad multigrid level request")
+    return [sizes[k] for k in range(cnt)]
+
+
+def mg_default_coarse_sweeps(nc):
+    """Sweeps on the coarsest level when the caller leaves the count at 0:
+    one when it is a single point (exact), else 2 (nc + 1)^2, enough to bring
+    a coarse error down by about e^-20 (Gauss-Seidel's rate 1 - pi^2 h^2)."""
+    return 1 if nc == 1 else 2 * (nc + 1) * (nc + 1)
+
+
+def mg_restrict(r):
+    """Full weighting of an (n_f+2)^2 natural-layout field onto a new
+    (n_c+2)^2 array (zero ring), n_f = 2 n_c + 1."""
+    nf = r.shape[0] - 2
+    if nf < 3 or nf % 2 == 0:
+        raise ValueError("fine size must be 2 n_c + 1")
+    nc = (nf - 1) // 2
+    r = np.ascontiguousarray(r, np.float64)
+    out = np.zeros((nc + 2, nc + 2))
+    _check(_load().rbgs_ref_mg_restrict_f64(nc, _ptr(r), r.shape[1], _ptr(out), out.shape[1]),
+           "mg_restrict")
+    return out
+
+
+def mg_prolong_add(ec, u):
+    """u += bilinear prolongation of the coarse array ec (ring included), in
+    place at the interior of u."""
+    nc = ec.shape[0] - 2
+    ec = np.ascontiguousarray(ec, np.float64)
+    n, ld = _grid(u)
+    if n != 2 * nc + 1:
+        raise ValueError("fine size must be 2 n_c + 1")
+    assert u.dtype == np.float64
+    _check(_load().rbgs_ref_mg_prolong_add_f64(nc, _ptr(ec), ec.shape[1], _ptr(u), ld),
+           "mg_prolong_add")
+    return u
+
+
+def mg_solve(u, f, h, nu1, nu2, max_cycles, rel_tol, max_levels=0, coarse_sweeps=0):
+    """V-cycles with red-black Gauss-Seidel smoothing until rel <= rel_tol
+    (checked before the first cycle and after each).  coarse_sweeps = 0 takes
+    mg_default_coarse_sweeps of the coarsest size.  Returns (status, cycles,
+    rel)."""
+    n, ld = _grid(u)
+    assert u.dtype == np.float64 and f.dtype == np.float64 and f.shape == u.shape
+    if coarse_sweeps == 0:
+        coarse_sweeps = mg_default_coarse_sweeps(mg_levels(n, max_levels)[-1])
+    cyc = _i32()
+    rel = _f64()
+    rc = _check(_load().rbgs_ref_mg_solve_f64(n, ld, h, _ptr(u), _ptr(f), nu1, nu2, max_levels,
+                                              coarse_sweeps, max_cycles, rel_tol,
+                                              ctypes.byref(cyc), ctypes.byref(rel)),
+                "mg_solve_f64")
+    return rc, cyc.value, rel.value
 
 
 def round_bf16(x):

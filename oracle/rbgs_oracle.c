@@ -385,5 +385,178 @@ int rbgs_ref_ir_solve(int32_t n, int64_t ld, double h, double *u,
     return rel <= rel_tol ? RBGS_REF_OK : RBGS_REF_ENOCONV;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Multigrid with red-black Gauss-Seidel as the smoother (an extension: the   */
+/* conclusion, Section 5, names odd-even and related multilevel techniques as  */
+/* future work; the paper itself runs Gauss-Seidel alone).  The textbook       */
+/* V-cycle for the vertex-centred grid hierarchy:                               */
+/*   - level sizes n_0 = n and n_{l+1} = (n_l - 1) / 2 while n_l is odd and   */
+/*     n_l >= 3 (and fewer than max_levels levels, if max_levels > 0);         */
+/*     h_{l+1} = 2 h_l; coarse point (I, J) lies on fine point (2I, 2J);       */
+/*   - the coarse problems are the same 5-point Poisson system on the coarser  */
+/*     grid (rediscretised, not Galerkin), for the error, with a zero ring;    */
+/*   - on a level above the coarsest: nu1 sweeps; the residual field r of the  */
+/*     residual function above; coarse right-hand side = full weighting of r;  */
+/*     coarse iterate = 0; the cycle on the coarser level; u += bilinear        */
+/*     prolongation of the coarse iterate; nu2 sweeps;                          */
+/*   - on the coarsest level: coarse_sweeps sweeps (one sweep is exact when    */
+/*     n = 1: the single point is red and its neighbours are ring values).     */
+/* Rounding order of the transfers (each + and * rounded once, no FMA):        */
+/*   full weighting, per fine row a in {2I-1, 2I, 2I+1}:                       */
+/*       row_a = (r[a][2J-1] + 2 r[a][2J]) + r[a][2J+1],                       */
+/*       f_c[I][J] = ((row_{2I-1} + 2 row_{2I}) + row_{2I+1}) * 0.0625;        */
+/*   bilinear prolongation at fine (i, j), e = coarse iterate (ring included), */
+/*   I = i >> 1, J = j >> 1:                                                   */
+/*       i, j even: v = e[I][J];                                               */
+/*       i odd, j even: v = (e[I][J] + e[I+1][J]) * 0.5;                       */
+/*       i even, j odd: v = (e[I][J] + e[I][J+1]) * 0.5;                       */
+/*       i, j odd: v = ((e[I][J] + e[I][J+1]) + (e[I+1][J] + e[I+1][J+1])) * 0.25; */
+/*       u[i][j] = u[i][j] + v.                                                */
+/* ------------------------------------------------------------------------- */
+
+#define RBGS_REF_MG_MAX_LEVELS 32
+
+/* Level sizes of the hierarchy for grid size n; returns the level count and  */
+/* writes the sizes to `sizes` (capacity RBGS_REF_MG_MAX_LEVELS) if given.     */
+int32_t rbgs_ref_mg_levels(int32_t n, int32_t max_levels, int32_t *sizes)
+{
+    if (n < 1 || max_levels < 0) return 0;
+    int32_t cnt = 1;
+    int32_t m = n;
+    if (sizes) sizes[0] = m;
+    while (m >= 3 && (m % 2) == 1 && cnt < RBGS_REF_MG_MAX_LEVELS &&
+           (max_levels == 0 || cnt < max_levels)) {
+        m = (m - 1) / 2;
+        if (sizes) sizes[cnt] = m;
+        ++cnt;
+    }
+    return cnt;
+}
+
+/* Full weighting of the fine interior field r (n_f = 2 nc + 1 points per      */
+/* side, natural layout, row length ld) onto the interior of fc (row length    */
+/* ldc); the ring of fc is left as it is.                                      */
+int rbgs_ref_mg_restrict_f64(int32_t nc, const double *r, int64_t ld, double *fc, int64_t ldc)
+{
+    if (nc < 1 || !r || !fc || ld < 2 * (int64_t)nc + 3 || ldc < (int64_t)nc + 2)
+        return RBGS_REF_EINVAL;
+    for (int64_t I = 1; I <= nc; ++I) {
+        for (int64_t J = 1; J <= nc; ++J) {
+            double row[3];
+            for (int a = 0; a < 3; ++a) {
+                const int64_t i = 2 * I - 1 + a;
+                row[a] = (AT(r, i, 2 * J - 1) + 2.0 * AT(r, i, 2 * J)) + AT(r, i, 2 * J + 1);
+            }
+            fc[(size_t)I * (size_t)ldc + (size_t)J] = ((row[0] + 2.0 * row[1]) + row[2]) * 0.0625;
+        }
+    }
+    return RBGS_REF_OK;
+}
+
+/* u += bilinear prolongation of ec (nc interior points per side, ring        */
+/* included, row length ldc) at the interior points of u (n_f = 2 nc + 1,     */
+/* row length ld); the ring of u is not written.                               */
+int rbgs_ref_mg_prolong_add_f64(int32_t nc, const double *ec, int64_t ldc, double *u, int64_t ld)
+{
+    if (nc < 1 || !ec || !u || ld < 2 * (int64_t)nc + 3 || ldc < (int64_t)nc + 2)
+        return RBGS_REF_EINVAL;
+    const int64_t nf = 2 * (int64_t)nc + 1;
+#define EC(I, J) ec[(size_t)(I) * (size_t)ldc + (size_t)(J)]
+    for (int64_t i = 1; i <= nf; ++i) {
+        for (int64_t j = 1; j <= nf; ++j) {
+            const int64_t I = i >> 1, J = j >> 1;
+            double v;
+            if (i % 2 == 0 && j % 2 == 0)
+                v = EC(I, J);
+            else if (i % 2 == 1 && j % 2 == 0)
+                v = (EC(I, J) + EC(I + 1, J)) * 0.5;
+            else if (i % 2 == 0 && j % 2 == 1)
+                v = (EC(I, J) + EC(I, J + 1)) * 0.5;
+            else
+                v = ((EC(I, J) + EC(I, J + 1)) + (EC(I + 1, J) + EC(I + 1, J + 1))) * 0.25;
+            AT(u, i, j) = AT(u, i, j) + v;
+        }
+    }
+#undef EC
+    return RBGS_REF_OK;
+}
+
+typedef struct {
+    int32_t n;
+    int64_t ld;
+    double h;
+    double *u, *f, *r;
+} mg_level;
+
+static void mg_cycle(mg_level *lv, int32_t l, int32_t nlev, int32_t nu1, int32_t nu2,
+                     int32_t coarse_sweeps)
+{
+    mg_level *a = &lv[l];
+    if (l == nlev - 1) {
+        rbgs_ref_sweep_f64(a->n, a->ld, a->h, a->u, a->f, coarse_sweeps);
+        return;
+    }
+    mg_level *c = &lv[l + 1];
+    rbgs_ref_sweep_f64(a->n, a->ld, a->h, a->u, a->f, nu1);
+    rbgs_ref_residual_f64(a->n, a->ld, a->h, a->u, a->f, NULL, NULL, a->r);
+    rbgs_ref_mg_restrict_f64(c->n, a->r, a->ld, c->f, c->ld);
+    memset(c->u, 0, (size_t)(c->n + 2) * (size_t)c->ld * sizeof(double));
+    mg_cycle(lv, l + 1, nlev, nu1, nu2, coarse_sweeps);
+    rbgs_ref_mg_prolong_add_f64(c->n, c->u, c->ld, a->u, a->ld);
+    rbgs_ref_sweep_f64(a->n, a->ld, a->h, a->u, a->f, nu2);
+}
+
+/* V-cycles until rel <= rel_tol or max_cycles cycles; the residual is checked */
+/* before the first cycle and after each (rel_tol <= 0: exactly max_cycles     */
+/* cycles, one residual at the end), as in rbgs_ref_solve_f64.  u, f: the      */
+/* finest level in the natural layout with ring g; coarse levels are held      */
+/* here.  Returns 0, RBGS_REF_ENOCONV or an error.                             */
+int rbgs_ref_mg_solve_f64(int32_t n, int64_t ld, double h, double *u, const double *f,
+                          int32_t nu1, int32_t nu2, int32_t max_levels, int32_t coarse_sweeps,
+                          int32_t max_cycles, double rel_tol, int32_t *cycles_done,
+                          double *rel_out)
+{
+    if (bad_grid(n, ld, h) || !u || !f || nu1 < 0 || nu2 < 0 || max_levels < 0 ||
+        coarse_sweeps < 0 || max_cycles < 0)
+        return RBGS_REF_EINVAL;
+    int32_t sizes[RBGS_REF_MG_MAX_LEVELS];
+    const int32_t nlev = rbgs_ref_mg_levels(n, max_levels, sizes);
+    mg_level lv[RBGS_REF_MG_MAX_LEVELS];
+    int ok = 1;
+    for (int32_t l = 0; l < nlev; ++l) {
+        lv[l].n = sizes[l];
+        lv[l].ld = l == 0 ? ld : (int64_t)sizes[l] + 2;
+        lv[l].h = l == 0 ? h : 2.0 * lv[l - 1].h;
+        const size_t cells = (size_t)(lv[l].n + 2) * (size_t)lv[l].ld;
+        lv[l].u = l == 0 ? u : (double *)calloc(cells, sizeof(double));
+        lv[l].f = l == 0 ? (double *)f : (double *)calloc(cells, sizeof(double));
+        lv[l].r = l + 1 < nlev ? (double *)calloc(cells, sizeof(double)) : NULL;
+        if (!lv[l].u || !lv[l].f || (l + 1 < nlev && !lv[l].r)) ok = 0;
+    }
+    int32_t cycles = 0;
+    double rel = 0.0;
+    if (ok) {
+        if (rel_tol <= 0.0) {
+            for (; cycles < max_cycles; ++cycles) mg_cycle(lv, 0, nlev, nu1, nu2, coarse_sweeps);
+        } else {
+            rbgs_ref_residual_f64(n, ld, h, u, f, NULL, &rel, NULL);
+            while (!(rel <= rel_tol) && cycles < max_cycles) {
+                mg_cycle(lv, 0, nlev, nu1, nu2, coarse_sweeps);
+                ++cycles;
+                rbgs_ref_residual_f64(n, ld, h, u, f, NULL, &rel, NULL);
+            }
+        }
+        if (rel_tol <= 0.0) rbgs_ref_residual_f64(n, ld, h, u, f, NULL, &rel, NULL);
+    }
+    for (int32_t l = 0; l < nlev; ++l) {
+        if (l > 0) { free(lv[l].u); free(lv[l].f); }
+        free(lv[l].r);
+    }
+    if (!ok) return RBGS_REF_ENOMEM;
+    if (cycles_done) *cycles_done = cycles;
+    if (rel_out) *rel_out = rel;
+    return (rel_tol <= 0.0 || rel <= rel_tol) ? RBGS_REF_OK : RBGS_REF_ENOCONV;
+}
+
 /* Colour query used by the tests to check the colouring convention. */
 int32_t rbgs_ref_colour(int64_t i, int64_t j) { return colour_of(i, j); }

@@ -10,6 +10,7 @@ import oracle
 import workloads as W
 from oracle import build as obuild
 from tests import closed_form as cf
+from tests import test_oracle_mg_pins as mg_pins
 from tests import test_oracle_pins as pins
 
 MUTANTS = {
@@ -25,6 +26,20 @@ MUTANTS = {
                                 "double lap = (s - 2.0 * (double)AT(u, i, j)) * inv_h2;"),
     "h_not_squared": ("const double h2 = h * h;\n#pragma omp parallel for schedule(static)\n    for (int64_t i = 1; i <= n; ++i) {\n        /* red",
                       "const double h2 = h;\n#pragma omp parallel for schedule(static)\n    for (int64_t i = 1; i <= n; ++i) {\n        /* red"),
+    # multigrid cycle
+    "mg_correction_subtracted": ("AT(u, i, j) = AT(u, i, j) + v;", "AT(u, i, j) = AT(u, i, j) - v;"),
+    "mg_coarse_h_not_doubled": ("lv[l].h = l == 0 ? h : 2.0 * lv[l - 1].h;",
+                                "lv[l].h = l == 0 ? h : lv[l - 1].h;"),
+    "mg_full_weighting_centre": ("((row[0] + 2.0 * row[1]) + row[2]) * 0.0625",
+                                 "((row[0] + row[1]) + row[2]) * 0.0625"),
+    "mg_restrict_column_shift": ("2.0 * AT(r, i, 2 * J)) + AT(r, i, 2 * J + 1);",
+                                 "2.0 * AT(r, i, 2 * J)) + AT(r, i, 2 * J - 1);"),
+    "mg_prolong_corner_weight": ("(EC(I + 1, J) + EC(I + 1, J + 1))) * 0.25;",
+                                 "(EC(I + 1, J) + EC(I + 1, J + 1))) * 0.5;"),
+    "mg_prolong_row_shift": ("v = (EC(I, J) + EC(I + 1, J)) * 0.5;",
+                             "v = (EC(I, J) + EC(I - 1, J)) * 0.5;"),
+    "mg_postsmoothing_dropped": ("rbgs_ref_sweep_f64(a->n, a->ld, a->h, a->u, a->f, nu2);",
+                                 "rbgs_ref_sweep_f64(a->n, a->ld, a->h, a->u, a->f, 0);"),
 }
 
 
@@ -49,6 +64,11 @@ def _pins_that_run():
     yield lambda: pins.test_multi_mode_iterate(oracle)
     yield lambda: pins.test_converges_to_dense_solve(oracle, 9)
     yield lambda: pins.test_residual_special_cases(oracle)
+    yield lambda: mg_pins.test_restrict_constant_and_bilinear(oracle, 3)
+    yield lambda: mg_pins.test_prolong_bilinear_exact_and_additive(oracle, 3)
+    yield lambda: mg_pins.test_restrict_is_quarter_adjoint_of_prolong(oracle)
+    yield lambda: mg_pins.test_converges_to_dense_solve(oracle, 15, (1, 1))
+    yield lambda: mg_pins.test_vcycle_factor_is_textbook_and_h_independent(oracle, 63)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
