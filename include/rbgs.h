@@ -374,6 +374,68 @@ int rbgs_prolong(int32_t batch, rbgs_dtype dt, const rbgs_grid *coarse,
                  const rbgs_grid *fine, void *x_fine, int64_t fine_stride,
                  void *stream);
 
+/* ---------------------------------------------------------------------
+ * Multigrid with red-black Gauss-Seidel as the smoother (an extension: the
+ * conclusion, Section 5, names multilevel odd-even techniques as future
+ * work).  The textbook V-cycle on the vertex-centred hierarchy
+ *   n_0 = n, n_{l+1} = (n_l - 1) / 2 while n_l is odd and >= 3
+ *   (and fewer than max_levels levels when max_levels > 0), h_{l+1} = 2 h_l;
+ * each coarse level is the same 5-point system (rediscretised) for the error
+ * of the level above, with a zero ring.  On a level above the coarsest:
+ * pre_sweeps sweeps (Eq. (1), red then black), r = f - A_h u, coarse
+ * right-hand side = full weighting (1,2,1) x (1,2,1) / 16 of r, coarse
+ * iterate = 0, the cycle on the coarser level, u += bilinear interpolation
+ * of the coarse iterate, post_sweeps sweeps.  On the coarsest level:
+ * coarse_sweeps sweeps (0 = 1 when it is a single point, which one sweep
+ * solves exactly, else 2 (n_L + 1)^2).  The transfers' rounding order is
+ * fixed (see the multigrid kernels' source), so the iterate after any
+ * number of cycles is bitwise that of the CPU definition.  FP64 only.
+ * --------------------------------------------------------------------- */
+typedef struct {
+    int32_t max_cycles;    /* cap on V-cycles, >= 0                            */
+    double rel_tol;        /* stop at ||r||_2/||b||_2 <= rel_tol, checked before
+                              the first cycle and after each; <= 0: run
+                              exactly max_cycles cycles                       */
+    int32_t pre_sweeps;    /* sweeps before the coarse correction, >= 0       */
+    int32_t post_sweeps;   /* sweeps after it, >= 0; pre + post >= 1          */
+    int32_t max_levels;    /* 0 = coarsen as far as the sizes allow, else at
+                              most this many levels (1 = plain sweeps)         */
+    int32_t coarse_sweeps; /* sweeps on the coarsest level; 0 = the default    */
+    rbgs_sweep_opts sweep; /* kernel for every level's sweeps: AUTO picks per
+                              level; RESIDENT needs every level to fit it;
+                              timing is not supported (must be NULL)          */
+} rbgs_mg_opts;
+
+typedef struct {
+    int32_t cycles;        /* V-cycles performed                              */
+    int32_t levels;        /* levels of the hierarchy                         */
+    int32_t coarsest_n;    /* size of the coarsest level                      */
+    int32_t coarse_sweeps; /* sweeps used on it                               */
+    double rel_residual;   /* final ||r||_2/||b||_2 (||r||_2 if ||b||_2 = 0)  */
+    double abs_residual;   /* final ||r||_2                                   */
+    int32_t graph;         /* 1 if the cycles ran as replays of a captured
+                              graph, 0 if launched one by one                 */
+    int32_t status;        /* same value as the return code                   */
+} rbgs_mg_info;
+
+/* Workspace bytes for rbgs_mg_solve (all levels' split arrays and kernel
+ * state); 0 for invalid arguments.  opts may be NULL (max_levels = 0). */
+size_t rbgs_mg_workspace_size(const rbgs_grid *g, rbgs_dtype dt,
+                              const rbgs_mg_opts *opts);
+
+/* V-cycles until rel <= opts->rel_tol or opts->max_cycles cycles.  u, f:
+ * DEVICE arrays in the natural layout (as rbgs_solve); the ring of u is the
+ * Dirichlet data and is not written.  dt must be RBGS_F64 (else
+ * RBGS_EUNSUPPORTED).  The cycles run as replays of a captured HIP graph
+ * (cycle, residual and a device-side convergence test), with a launch-by-
+ * launch fallback.  info (HOST, may be NULL) receives the statistics.
+ * Returns RBGS_OK, RBGS_ENOCONV (u holds the last iterate), RBGS_ENONFINITE,
+ * RBGS_ETIMEOUT (a persistent smoother's bounded wait expired) or an error.
+ * Synchronises `stream`. */
+int rbgs_mg_solve(const rbgs_grid *g, rbgs_dtype dt, void *u, const void *f,
+                  const rbgs_mg_opts *opts, rbgs_mg_info *info,
+                  void *workspace, size_t workspace_bytes, void *stream);
+
 /* Device-memory bandwidth probe: the copy (kind 0: b = a) and triad
  * (kind 1: a = b + s*c) kernels of the STREAM benchmark, which the paper
  * uses for the attainable memory bandwidth in its roofline (Section 3,

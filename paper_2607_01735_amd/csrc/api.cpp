@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <functional>
+#include <vector>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -455,6 +457,91 @@ int check_transfer(int32_t batch, rbgs_dtype dt, const rbgs_grid* coarse, const 
     return RBGS_OK;
 }
 
+// ----- multigrid (red-black Gauss-Seidel as the smoother) ----------------
+
+constexpr int kMgMaxLevels = 32;
+
+// Level sizes n_0 = n, n_{l+1} = (n_l - 1) / 2 while n_l is odd and >= 3
+// (and fewer than max_levels levels when max_levels > 0).
+int mg_level_sizes(int n, int max_levels, int* sizes) {
+    int cnt = 1, m = n;
+    sizes[0] = m;
+    while (m >= 3 && (m & 1) && cnt < kMgMaxLevels && (max_levels == 0 || cnt < max_levels)) {
+        m = (m - 1) / 2;
+        sizes[cnt++] = m;
+    }
+    return cnt;
+}
+
+// One Workspace per level, back to back: level 0 holds the caller's grid
+// (packed), the others the coarse iterate and right-hand side; h doubles
+// from level to level (exactly, a power-of-two scaling).
+struct MgPlan {
+    int levels = 0;
+    rbgs_grid g[kMgMaxLevels];
+    Workspace w[kMgMaxLevels];
+    size_t total = 0;
+};
+
+MgPlan plan_mg(const rbgs_grid* g, int max_levels, char* base) {
+    MgPlan p;
+    int sizes[kMgMaxLevels];
+    p.levels = mg_level_sizes(g->n, max_levels, sizes);
+    size_t off = 0;
+    double h = g->h;
+    for (int l = 0; l < p.levels; ++l) {
+        p.g[l] = l == 0 ? *g : rbgs_grid{sizes[l], int64_t(sizes[l]) + 2, h};
+        p.w[l] = plan_workspace(&p.g[l], RBGS_F64, false, base ? base + off : nullptr);
+        off += p.w[l].total;
+        h = 2.0 * h;
+    }
+    p.total = off;
+    return p;
+}
+
+int mg_default_coarse_sweeps(int nc) { return nc == 1 ? 1 : 2 * (nc + 1) * (nc + 1); }
+
+struct MgParams {
+    int nu1, nu2, coarse_sweeps;
+    rbgs_sweep_opts sweep;
+};
+
+// Enqueues one V-cycle from level l down; *states collects the persistent
+// kernels' state blocks whose error words must be checked.
+int mg_cycle(const MgPlan& p, int l, const MgParams& mp, hipStream_t s, const int* stop,
+             std::vector<void*>* states) {
+    const Workspace& a = p.w[l];
+    auto smooth = [&](int k) -> int {
+        if (k <= 0) return RBGS_OK;
+        int launches = 0;
+        void* es = nullptr;
+        int rc = run_sweeps<double>(&p.g[l], a, k, &mp.sweep, s, &launches, &es, nullptr, stop);
+        if (rc) return rc;
+        if (es && std::find(states->begin(), states->end(), es) == states->end())
+            states->push_back(es);
+        return RBGS_OK;
+    };
+    if (l == p.levels - 1) return smooth(mp.coarse_sweeps);
+    int rc = smooth(mp.nu1);
+    if (rc) return rc;
+    const Workspace& c = p.w[l + 1];
+    const double hl = p.g[l].h;
+    HIP_TRY(launch_mg_restrict(static_cast<const double*>(a.u_red),
+                               static_cast<const double*>(a.u_black),
+                               static_cast<const double*>(a.f_red),
+                               static_cast<const double*>(a.f_black), a.pitch, 1.0 / (hl * hl),
+                               static_cast<double*>(c.f_red), static_cast<double*>(c.f_black),
+                               static_cast<double*>(c.u_red), static_cast<double*>(c.u_black),
+                               p.g[l + 1].n, c.pitch, stop, s),
+            "multigrid restriction");
+    if ((rc = mg_cycle(p, l + 1, mp, s, stop, states))) return rc;
+    HIP_TRY(launch_mg_prolong_add(static_cast<double*>(a.u_red), static_cast<double*>(a.u_black),
+                                  a.pitch, p.g[l].n, static_cast<const double*>(c.u_red),
+                                  static_cast<const double*>(c.u_black), c.pitch, stop, s),
+            "multigrid prolongation");
+    return smooth(mp.nu2);
+}
+
 }  // namespace
 
 extern "C" {
@@ -758,6 +845,122 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         *o->sweep.timing = gt.acc;
     }
     if (err_state && (rc = blocked_check_error(err_state, s, &g_last_error))) out.status = rc;
+    if (info) *info = out;
+    if (out.status == RBGS_ENONFINITE) g_last_error = "residual is not finite";
+    if (out.status == RBGS_ENOCONV) g_last_error = "tolerance not reached";
+    return out.status;
+}
+
+size_t rbgs_mg_workspace_size(const rbgs_grid* g, rbgs_dtype dt, const rbgs_mg_opts* o) {
+    std::string why;
+    if (!valid_grid(g, &why) || dt != RBGS_F64) return 0;
+    const int ml = o ? o->max_levels : 0;
+    if (ml < 0) return 0;
+    return plan_mg(g, ml, nullptr).total;
+}
+
+int rbgs_mg_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
+                  const rbgs_mg_opts* o, rbgs_mg_info* info, void* workspace,
+                  size_t workspace_bytes, void* stream) {
+    std::string why;
+    if (!valid_grid(g, &why)) return fail(RBGS_EINVAL, why);
+    if (!valid_dtype(dt)) return fail(RBGS_EINVAL, "unknown dtype");
+    if (dt != RBGS_F64) return fail(RBGS_EUNSUPPORTED, "multigrid runs in FP64");
+    if (!o) return fail(RBGS_EINVAL, "multigrid options are NULL");
+    if (o->max_cycles < 0) return fail(RBGS_EINVAL, "max_cycles must be >= 0");
+    if (std::isnan(o->rel_tol)) return fail(RBGS_EINVAL, "rel_tol is NaN");
+    if (o->pre_sweeps < 0 || o->post_sweeps < 0)
+        return fail(RBGS_EINVAL, "pre_sweeps and post_sweeps must be >= 0");
+    if (int64_t(o->pre_sweeps) + o->post_sweeps < 1)
+        return fail(RBGS_EINVAL, "pre_sweeps + post_sweeps must be >= 1");
+    if (o->max_levels < 0) return fail(RBGS_EINVAL, "max_levels must be >= 0");
+    if (o->coarse_sweeps < 0) return fail(RBGS_EINVAL, "coarse_sweeps must be >= 0");
+    int rc = validate_sweep_opts(&o->sweep);
+    if (rc) return rc;
+    if (o->sweep.timing) return fail(RBGS_EUNSUPPORTED, "multigrid does not take sweep timing");
+    MgPlan plan = plan_mg(g, o->max_levels, nullptr);
+    if ((rc = check_workspace(workspace, workspace_bytes, plan.total))) return rc;
+    if ((rc = check_device_range(u, grid_bytes(g, dt), "u"))) return rc;
+    if ((rc = check_device_range(f, grid_bytes(g, dt), "f"))) return rc;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    MgPlan p = plan_mg(g, o->max_levels, static_cast<char*>(workspace));
+    const Workspace& w0 = p.w[0];
+    MgParams mp;
+    mp.nu1 = o->pre_sweeps;
+    mp.nu2 = o->post_sweeps;
+    const int nL = p.g[p.levels - 1].n;
+    mp.coarse_sweeps = o->coarse_sweeps > 0 ? o->coarse_sweeps : mg_default_coarse_sweeps(nL);
+    mp.sweep = o->sweep;
+    HIP_TRY(launch_pack(u, g->ld, w0.u_red, w0.u_black, g->n, w0.pitch, 8, s), "pack u");
+    HIP_TRY(launch_pack(f, g->ld, w0.f_red, w0.f_black, g->n, w0.pitch, 8, s), "pack f");
+    for (int l = 0; l < p.levels; ++l) {
+        const Workspace& wl = p.w[l];
+        if (l > 0) {  // coarse iterates: zero ring (and interior, rewritten per cycle)
+            const size_t colour = align256(size_t(p.g[l].n + 2) * size_t(wl.pitch) * 8);
+            HIP_TRY(launch_zero(wl.u_red, colour, s), "zero coarse iterate");
+            HIP_TRY(launch_zero(wl.u_black, colour, s), "zero coarse iterate");
+        }
+        // persistent smoothers' error words start clear once per solve
+        HIP_TRY(launch_zero(static_cast<char*>(wl.blocked) + 64, 4, s), "clear error word");
+        if (wl.resident)
+            HIP_TRY(launch_zero(static_cast<char*>(wl.resident) + 64, 4, s), "clear error word");
+    }
+
+    rbgs_mg_info out{0, p.levels, nL, mp.coarse_sweeps, 0.0, 0.0, 0, RBGS_OK};
+    std::vector<void*> states;
+    double rel = 0.0, ab = 0.0;
+    int32_t cycles = 0;
+    const bool fixed = o->rel_tol <= 0.0;  // exactly max_cycles cycles
+    if (!fixed) {
+        if ((rc = split_residual<double>(&p.g[0], w0, s, nullptr, nullptr, 0))) return rc;
+        if ((rc = fetch_norms(w0, s, &ab, &rel))) return rc;
+    }
+    if ((fixed || (!(rel <= o->rel_tol) && std::isfinite(rel))) && o->max_cycles > 0) {
+        RoundBody body = [&](hipStream_t cs, const int* stop, void** es) -> int {
+            states.clear();
+            int r = mg_cycle(p, 0, mp, cs, stop, &states);
+            if (r) return r;
+            *es = states.empty() ? nullptr : states[0];
+            return split_residual<double>(&p.g[0], w0, cs, nullptr, nullptr, 0);
+        };
+        int rounds = 0;
+        bool used = false;
+        void* es = nullptr;
+        if ((rc = solve_rounds_graph(w0, body, o->max_cycles, fixed ? -1.0 : o->rel_tol, s, &es,
+                                     &rounds, &used)))
+            return rc;
+        if (used) {
+            out.graph = 1;
+            cycles = rounds;
+            if ((rc = fetch_norms(w0, s, &ab, &rel))) return rc;
+        } else {
+            states.clear();
+            while (cycles < o->max_cycles && (fixed || (!(rel <= o->rel_tol) && std::isfinite(rel)))) {
+                if ((rc = mg_cycle(p, 0, mp, s, nullptr, &states))) return rc;
+                ++cycles;
+                if (!fixed || cycles == o->max_cycles) {
+                    if ((rc = split_residual<double>(&p.g[0], w0, s, nullptr, nullptr, 0)))
+                        return rc;
+                    if ((rc = fetch_norms(w0, s, &ab, &rel))) return rc;
+                }
+            }
+        }
+    } else if (fixed) {  // zero cycles: the residual of the start
+        if ((rc = split_residual<double>(&p.g[0], w0, s, nullptr, nullptr, 0))) return rc;
+        if ((rc = fetch_norms(w0, s, &ab, &rel))) return rc;
+    }
+    HIP_TRY(launch_unpack(u, g->ld, w0.u_red, w0.u_black, g->n, w0.pitch, 8, s), "unpack u");
+    HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+    out.cycles = cycles;
+    out.rel_residual = rel;
+    out.abs_residual = ab;
+    if (!std::isfinite(rel))
+        out.status = RBGS_ENONFINITE;
+    else
+        out.status = (fixed || rel <= o->rel_tol) ? RBGS_OK : RBGS_ENOCONV;
+    for (void* st : states)
+        if ((rc = blocked_check_error(st, s, &g_last_error))) out.status = rc;
     if (info) *info = out;
     if (out.status == RBGS_ENONFINITE) g_last_error = "residual is not finite";
     if (out.status == RBGS_ENOCONV) g_last_error = "tolerance not reached";

@@ -109,13 +109,26 @@ hipError_t launch_prolong(const T* coarse, int64_t coarse_ld, int64_t coarse_str
                           int64_t fine_ld, int64_t fine_stride, int nf, int batch,
                           hipStream_t s);
 
-// Zero a device range with a kernel (usable inside graph capture).
+// Multigrid transfers on split FP64 arrays (fine n_f = 2 n_c + 1, pitch /
+// cpitch the fine / coarse split pitches).  restrict: coarse f <- full
+// weighting of the fine residual f - A_h u (inv_h2 = 1 / h_f^2), coarse u
+// interior rows <- 0.  prolong_add: fine u += bilinear interpolation of the
+// coarse iterate.  Both do nothing when stop != nullptr and *stop != 0.
+hipError_t launch_mg_restrict(const double* u_red, const double* u_black, const double* f_red,
+                              const double* f_black, int64_t pitch, double inv_h2,
+                              double* fc_red, double* fc_black, double* uc_red, double* uc_black,
+                              int nc, int64_t cpitch, const int* stop, hipStream_t s);
+hipError_t launch_mg_prolong_add(double* u_red, double* u_black, int64_t pitch, int nf,
+                                 const double* e_red, const double* e_black, int64_t cpitch,
+                                 const int* stop, hipStream_t s);
+
 // Copies the Dirichlet ring (and nothing that a pass would not overwrite
 // before reading) of split grid src into dst; n + 2 rows of `pitch` elements.
 hipError_t launch_copy_ring(void* dst_red, void* dst_black, const void* src_red,
                             const void* src_black, int n, int64_t pitch, int elem_bytes,
                             hipStream_t s);
 
+// Zero a device range with a kernel (usable inside graph capture).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
 // dst <- src for `bytes` (a multiple of 16, 16-byte aligned buffers) unless

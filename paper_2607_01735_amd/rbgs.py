@@ -71,8 +71,27 @@ class rbgs_solve_info(ctypes.Structure):
                 ("status", ctypes.c_int32)]
 
 
+class rbgs_mg_opts(ctypes.Structure):
+    _fields_ = [("max_cycles", ctypes.c_int32), ("rel_tol", ctypes.c_double),
+                ("pre_sweeps", ctypes.c_int32), ("post_sweeps", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32),
+                ("sweep", rbgs_sweep_opts)]
+
+
+class rbgs_mg_info(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("coarsest_n", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("abs_residual", ctypes.c_double),
+                ("graph", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
 _P = ctypes.POINTER
 _vp = ctypes.c_void_p
+_lib.rbgs_mg_workspace_size.argtypes = [_P(rbgs_grid), ctypes.c_int, _P(rbgs_mg_opts)]
+_lib.rbgs_mg_workspace_size.restype = ctypes.c_size_t
+_lib.rbgs_mg_solve.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, _P(rbgs_mg_opts),
+                               _P(rbgs_mg_info), _vp, ctypes.c_size_t, _vp]
+_lib.rbgs_mg_solve.restype = ctypes.c_int
 _lib.rbgs_workspace_size.argtypes = [_P(rbgs_grid), ctypes.c_int, _P(rbgs_solve_opts)]
 _lib.rbgs_workspace_size.restype = ctypes.c_size_t
 _lib.rbgs_sweep.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, ctypes.c_int32,
@@ -123,7 +142,7 @@ EXPORTED = ("rbgs_workspace_size", "rbgs_sweep", "rbgs_residual", "rbgs_solve",
             "rbgs_unet_get_params", "rbgs_unet_get_grads", "rbgs_unet_forward",
             "rbgs_unet_train_step", "rbgs_solve_learned", "rbgs_unet_last_error",
             "rbgs_restrict", "rbgs_prolong", "rbgs_batch_solve_workspace_size",
-            "rbgs_solve_batched")
+            "rbgs_solve_batched", "rbgs_mg_workspace_size", "rbgs_mg_solve")
 
 
 class RbgsError(RuntimeError):
@@ -281,6 +300,48 @@ def rbgs_solve(u, f, max_sweeps, rel_tol, check_every=100, h=None, precision="f6
     if timing:
         out["timing"] = _timing_dict(t)
     return out
+
+
+def _mg_opts(max_cycles, rel_tol, pre_sweeps, post_sweeps, max_levels, coarse_sweeps, kernel,
+             **tuning):
+    o = rbgs_mg_opts()
+    o.max_cycles, o.rel_tol = int(max_cycles), float(rel_tol)
+    o.pre_sweeps, o.post_sweeps = int(pre_sweeps), int(post_sweeps)
+    o.max_levels, o.coarse_sweeps = int(max_levels), int(coarse_sweeps)
+    o.sweep = _sweep_opts(kernel=kernel, **tuning)
+    return o
+
+
+def rbgs_mg_workspace_size(grid, dtype_code, max_levels=0):
+    opts = rbgs_mg_opts()
+    opts.max_levels = max_levels
+    return int(_lib.rbgs_mg_workspace_size(ctypes.byref(grid), dtype_code, ctypes.byref(opts)))
+
+
+def rbgs_mg_solve(u, f, max_cycles, rel_tol, pre_sweeps=2, post_sweeps=2, max_levels=0,
+                  coarse_sweeps=0, h=None, kernel="auto", workspace=None, stream=None,
+                  raise_on_noconv=False, **tuning):
+    """V-cycles with red-black Gauss-Seidel smoothing on the GPU (FP64);
+    returns a dict with cycles, levels, coarsest_n, coarse_sweeps,
+    rel_residual, abs_residual, graph and status."""
+    _same_layout(u, f)
+    grid = make_grid(u, h)
+    code = _dtype_code(u)
+    opts = _mg_opts(max_cycles, rel_tol, pre_sweeps, post_sweeps, max_levels, coarse_sweeps,
+                    kernel, **tuning)
+    if workspace is None:
+        import torch
+        need = int(_lib.rbgs_mg_workspace_size(ctypes.byref(grid), code, ctypes.byref(opts)))
+        # need == 0 (an invalid request): the library names the problem below
+        workspace = torch.empty(need, dtype=torch.uint8, device=u.device) if need else None
+    info = rbgs_mg_info()
+    wsp = _vp(workspace.data_ptr()) if workspace is not None else None
+    rc = _lib.rbgs_mg_solve(ctypes.byref(grid), code, _vp(u.data_ptr()), _vp(f.data_ptr()),
+                            ctypes.byref(opts), ctypes.byref(info), wsp,
+                            workspace.numel() if workspace is not None else 0,
+                            _stream_ptr(stream, u.device))
+    _check(rc, allow=(OK,) if raise_on_noconv else (OK, ENOCONV, ENONFINITE))
+    return {k: getattr(info, k) for k, _ in rbgs_mg_info._fields_}
 
 
 def rbgs_stream_probe(kind, a, b, c=None, s=3.0, stream=None):

@@ -218,3 +218,57 @@ def test_solve_batched_validation_before_device_work(lib, bad):
     assert rc == expect, lib.rbgs_batch_last_error()
     assert lib._lib.rbgs_batch_solve_workspace_size(0, grids) == 0
     assert lib._lib.rbgs_batch_solve_workspace_size(2, grids) > 0
+
+
+def test_mg_workspace_size(lib):
+    g = _grid(lib, 255)
+    full = lib.rbgs_mg_workspace_size(g, lib.F64)
+    one = lib.rbgs_mg_workspace_size(g, lib.F64, max_levels=1)
+    # every level holds a full single-grid workspace; the coarse levels add
+    # about a third of the finest one
+    assert one == lib.rbgs_workspace_size(g, lib.F64)
+    assert one < full < 1.5 * one
+    assert full % 256 == 0
+    assert lib.rbgs_mg_workspace_size(g, lib.F32) == 0
+    assert lib.rbgs_mg_workspace_size(_grid(lib, 0), lib.F64) == 0
+    assert lib.rbgs_mg_workspace_size(g, lib.F64, max_levels=-1) == 0
+
+
+@pytest.mark.parametrize("bad", ["f32", "dtype", "null_opts", "cycles", "pre", "nosmooth",
+                                 "levels", "coarse", "nan_tol", "kernel", "timing", "ws_null"])
+def test_mg_validation_before_device_work(lib, bad):
+    g = _grid(lib, 63)
+    o = lib.rbgs_mg_opts()
+    o.max_cycles, o.rel_tol, o.pre_sweeps, o.post_sweeps = 5, 1e-8, 2, 2
+    dtype, expect, opts = lib.F64, lib.EINVAL, ctypes.byref(o)
+    if bad == "f32":
+        dtype, expect = lib.F32, lib.EUNSUPPORTED
+    elif bad == "dtype":
+        dtype = 9
+    elif bad == "null_opts":
+        opts = None
+    elif bad == "cycles":
+        o.max_cycles = -1
+    elif bad == "pre":
+        o.pre_sweeps = -1
+    elif bad == "nosmooth":
+        o.pre_sweeps = o.post_sweeps = 0
+    elif bad == "levels":
+        o.max_levels = -2
+    elif bad == "coarse":
+        o.coarse_sweeps = -5
+    elif bad == "nan_tol":
+        o.rel_tol = float("nan")
+    elif bad == "kernel":
+        o.sweep.kernel = 11
+    elif bad == "timing":
+        t = lib.rbgs_timing()
+        o.sweep.timing = ctypes.pointer(t)
+        expect = lib.EUNSUPPORTED
+    elif bad == "ws_null":
+        expect = lib.EWORKSPACE
+    info = lib.rbgs_mg_info()
+    rc = lib._lib.rbgs_mg_solve(ctypes.byref(g), dtype, None, None, opts, ctypes.byref(info),
+                                None, 0, None)
+    assert rc == expect, lib.rbgs_last_error()
+    assert lib.rbgs_last_error()
