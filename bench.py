@@ -52,6 +52,8 @@ def kernel_source_hash(names):
 KERNEL_SOURCES = {
     "half_sweep_f64": ("sweep_plain.hip", "rbgs_internal.h"),
     "blocked_f64": ("sweep_blocked.hip", "blocked_pipeline.h", "rbgs_blocked.h", "rbgs_internal.h"),
+    "mg_restrict_f64": ("multigrid.hip", "rbgs_internal.h"),
+    "mg_prolong_add_f64": ("multigrid.hip", "rbgs_internal.h"),
 }
 
 
@@ -174,6 +176,78 @@ def time_to_tolerance_fourier(torch, rb, W, n=1023, tol=1e-8):
     base = out["plain_f64"]["seconds"]
     for name, _ in forms[1:]:
         out[name]["speedup_vs_plain_f64"] = round(base / out[name]["seconds"], 3)
+    return out
+
+
+MG_TRANSFER_BYTES = 38.0  # per fine point: restriction 16 + 4 (coarse f, zero coarse u), prolongation 16 + 2
+
+
+def mg_model_bytes(sizes, nu1, nu2, coarse_sweeps):
+    """Algorithmic HBM bytes of one V-cycle plus the finest-level residual
+    check: on each level above the coarsest, nu1 + nu2 sweeps at 24 B per
+    point and the two transfers (MG_TRANSFER_BYTES per fine point); the
+    coarsest level's sweeps; the residual reads u and f once (16 B/point)."""
+    total = 0.0
+    for n in sizes[:-1]:
+        total += n * n * ((nu1 + nu2) * BYTES_PER_LUP["f64"] + MG_TRANSFER_BYTES)
+    total += sizes[-1] ** 2 * coarse_sweeps * BYTES_PER_LUP["f64"]
+    return total + 16.0 * sizes[0] ** 2
+
+
+def multigrid_to_tolerance(torch, rb, W, tol=1e-8, sizes=(1023, 8191, 16383)):
+    """Red-black Gauss-Seidel as the smoother of a V-cycle (the multilevel
+    extension): wall time and cycles to rel <= tol from u = 0 on the 64-mode
+    Fourier right-hand side (seed 0), V(2,2) and V(1,1) on the plain
+    smoother, and the time per cycle from 10 fixed cycles with the model
+    bytes of a cycle per that time."""
+    out = {"problem": f"n x n FP64, 64 Fourier modes seed 0, u0=0, rel<={tol:g}"}
+    for n in sizes:
+        h = W.spacing(n)
+        f = torch.from_numpy(W.fourier_rhs(n, seed=0)).to("cuda")
+        grid = rb.make_grid(f, h)
+        ws = torch.empty(rb.rbgs_mg_workspace_size(grid, rb.rbgs.F64), dtype=torch.uint8,
+                         device="cuda")
+        levels = []
+        m = n
+        while True:
+            levels.append(m)
+            if m < 3 or m % 2 == 0:
+                break
+            m = (m - 1) // 2
+        for nu in ((2, 2), (1, 1)):
+            u = torch.zeros_like(f)
+            rb.rbgs_mg_solve(u, f, 1, -1.0, pre_sweeps=nu[0], post_sweeps=nu[1], h=h,
+                             kernel="plain", workspace=ws)  # warm-up
+            best, info = None, None
+            for _ in range(3):
+                u.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = rb.rbgs_mg_solve(u, f, 40, tol, pre_sweeps=nu[0], post_sweeps=nu[1], h=h,
+                                        kernel="plain", workspace=ws)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            u.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rb.rbgs_mg_solve(u, f, 10, -1.0, pre_sweeps=nu[0], post_sweeps=nu[1], h=h,
+                             kernel="plain", workspace=ws)
+            torch.cuda.synchronize()
+            per_cycle = (time.perf_counter() - t0) / 10
+            model = mg_model_bytes(levels, nu[0], nu[1], info["coarse_sweeps"])
+            key = f"n{n}_V{nu[0]}{nu[1]}"
+            out[key] = {"seconds": round(best, 5), "cycles": info["cycles"],
+                        "rel_residual": info["rel_residual"], "status": info["status"],
+                        "levels": info["levels"], "graph": info["graph"],
+                        "ms_per_cycle": round(per_cycle * 1e3, 3),
+                        "model_bytes_per_cycle": model,
+                        "model_GBs": round(model / per_cycle / 1e9, 1)}
+            log(f"multigrid {key}: {best * 1e3:.2f} ms, {info['cycles']} cycles, "
+                f"rel={info['rel_residual']:.3e}, {per_cycle * 1e3:.3f} ms/cycle, "
+                f"{model / per_cycle / 1e9:.0f} GB/s model")
+        del f, ws, u
+        torch.cuda.empty_cache()
     return out
 
 
@@ -409,6 +483,9 @@ def main():
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the refinement (16383^2), batched and learned-guess workloads")
+    ap.add_argument("--mg-only", action="store_true",
+                    help="run only the 8191^2 multigrid section (and the STREAM probe unless "
+                         "--no-probe), print its JSON and exit: the multigrid kernels' profile run")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -425,6 +502,11 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.mg_only:
+        mg = multigrid_to_tolerance(torch, rb, W, sizes=(8191,))
+        probe = None if args.no_probe else stream_probe(torch, rb)
+        print(json.dumps({"multigrid_to_1e-8": mg, "stream_probe": probe}), flush=True)
+        return
     n, sweeps = args.n, args.sweeps
     h = W.spacing(n)
     log(f"device {torch.cuda.get_device_name(0)}; building inputs n={n}")
@@ -499,6 +581,11 @@ def main():
     torch.cuda.empty_cache()
     ttt = None if args.no_time_to_tol else time_to_tolerance(torch, rb, W)
     ttt_1023 = None if args.no_time_to_tol else time_to_tolerance_fourier(torch, rb, W)
+    multigrid = None if args.no_time_to_tol else multigrid_to_tolerance(torch, rb, W)
+    if multigrid and ttt_1023:
+        base_1023 = ttt_1023["plain_f64"]["seconds"]
+        for key in ("n1023_V22", "n1023_V11"):
+            multigrid[key]["speedup_vs_plain_f64"] = round(base_1023 / multigrid[key]["seconds"], 1)
     refine = None if args.no_extras else refinement_throughput(torch, rb, W)
     batched = None if args.no_extras else batched_throughput(torch, rb, W)
     batched_tol = None if args.no_extras else batched_to_tolerance(torch, rb, W)
@@ -525,6 +612,7 @@ def main():
         "plain_kernel": plain,
         "time_to_1e-8": ttt,
         "time_to_1e-8_fourier_1023": ttt_1023,
+        "multigrid_to_1e-8": multigrid,
         "refinement_16383": refine,
         "batched_512": batched,
         "batched_to_1e-8": batched_tol,
