@@ -53,6 +53,11 @@ def _load(path=None):
         "rbgs_ref_sor_sweep_f64": [_i32, _i64, _f64, _f64, _vp, _vp, _i32],
         "rbgs_ref_sor_solve_f64": [_i32, _i64, _f64, _f64, _vp, _vp, _i32, _f64, _i32, _vp, _vp],
         "rbgs_ref_mg_levels": [_i32, _i32, _vp],
+        "rbgs_ref_mc9_colour": [_i64, _i64],
+        "rbgs_ref_mc9_quarter_sweep_f64": [_i32, _i64, _f64, _vp, _vp, _i32],
+        "rbgs_ref_mc9_sweep_f64": [_i32, _i64, _f64, _vp, _vp, _i32],
+        "rbgs_ref_mc9_residual_f64": [_i32, _i64, _f64, _vp, _vp, _vp, _vp, _vp],
+        "rbgs_ref_mc9_solve_f64": [_i32, _i64, _f64, _vp, _vp, _i32, _f64, _i32, _vp, _vp],
         "rbgs_ref_mg_restrict_f64": [_i32, _vp, _i64, _vp, _i64],
         "rbgs_ref_mg_prolong_add_f64": [_i32, _vp, _i64, _vp, _i64],
         "rbgs_ref_mg_solve_f64": [_i32, _i64, _f64, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _f64,
@@ -273,6 +278,51 @@ def mg_solve(u, f, h, nu1, nu2, max_cycles, rel_tol, max_levels=0, coarse_sweeps
                                               ctypes.byref(cyc), ctypes.byref(rel)),
                 "mg_solve_f64")
     return rc, cyc.value, rel.value
+
+
+def mc9_colour(i, j):
+    """Colour of point (i, j) for the 9-point stencil: (i & 1) + 2 (j & 1)."""
+    return _load().rbgs_ref_mc9_colour(i, j)
+
+
+def mc9_quarter_sweep(u, f, h, colour):
+    """Update every interior point of one of the four colours, in place."""
+    n, ld = _grid(u)
+    assert u.dtype == np.float64 and f.dtype == np.float64 and f.shape == u.shape
+    _check(_load().rbgs_ref_mc9_quarter_sweep_f64(n, ld, h, _ptr(u), _ptr(f), colour),
+           "mc9_quarter_sweep")
+    return u
+
+
+def mc9_sweep(u, f, h, nsweeps):
+    """nsweeps 4-colour 9-point Gauss-Seidel sweeps (colours 0..3) in place."""
+    n, ld = _grid(u)
+    assert u.dtype == np.float64 and f.dtype == np.float64 and f.shape == u.shape
+    _check(_load().rbgs_ref_mc9_sweep_f64(n, ld, h, _ptr(u), _ptr(f), nsweeps), "mc9_sweep")
+    return u
+
+
+def mc9_residual(u, f, h, want_field=False):
+    """(||r||_2, ||r||_2/||b||_2[, r]) of the 9-point system in FP64."""
+    n, ld = _grid(u)
+    assert u.dtype == np.float64 and f.dtype == np.float64 and f.shape == u.shape
+    a, r = _f64(), _f64()
+    field = np.zeros(u.shape, np.float64) if want_field else None
+    _check(_load().rbgs_ref_mc9_residual_f64(n, ld, h, _ptr(u), _ptr(f), ctypes.byref(a),
+                                             ctypes.byref(r), _ptr(field) if want_field else None),
+           "mc9_residual")
+    return (a.value, r.value, field) if want_field else (a.value, r.value)
+
+
+def mc9_solve(u, f, h, max_sweeps, rel_tol, check_every):
+    """4-colour 9-point sweeps until rel <= rel_tol.  Returns (status, sweeps, rel)."""
+    n, ld = _grid(u)
+    assert u.dtype == np.float64 and f.dtype == np.float64
+    done, rel = _i32(), _f64()
+    rc = _check(_load().rbgs_ref_mc9_solve_f64(n, ld, h, _ptr(u), _ptr(f), max_sweeps, rel_tol,
+                                               check_every, ctypes.byref(done),
+                                               ctypes.byref(rel)), "mc9_solve")
+    return rc, done.value, rel.value
 
 
 def round_bf16(x):

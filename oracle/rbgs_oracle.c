@@ -558,5 +558,124 @@ int rbgs_ref_mg_solve_f64(int32_t n, int64_t ld, double h, double *u, const doub
     return (rel_tol <= 0.0 || rel <= rel_tol) ? RBGS_REF_OK : RBGS_REF_ENOCONV;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Multi-colour Gauss-Seidel for a wider stencil (an extension: the           */
+/* conclusion, Section 5, names multi-colour variants, whose extra colours     */
+/* add synchronisation, as future work).  The 9-point Laplacian               */
+/*     lap9(u)_ij = (4 e_ij + c_ij - 20 u_ij) / (6 h^2),                       */
+/* e = sum of the four edge neighbours, c = sum of the four corner neighbours, */
+/* couples diagonal neighbours, which red-black colouring puts in one colour,  */
+/* so four colours are needed: colour (i & 1) + 2 (j & 1); no two points of    */
+/* one colour are neighbours.  The Gauss-Seidel update solves point (i, j)'s   */
+/* equation lap9(u) = f for u_ij:                                             */
+/*     u_ij <- (4 e + c - 6 h^2 f) / 20,                                       */
+/* with, in this order (each operation rounded once, no FMA):                  */
+/*     e = ((u[i+1][j] + u[i-1][j]) + u[i][j+1]) + u[i][j-1],                  */
+/*     c = ((u[i+1][j+1] + u[i+1][j-1]) + u[i-1][j+1]) + u[i-1][j-1],          */
+/*     s = 4 e + c;  s = s - (6 (h h)) f;  u = s / 20.                          */
+/* One sweep updates colours 0, 1, 2, 3 in turn.                               */
+/* ------------------------------------------------------------------------- */
+int32_t rbgs_ref_mc9_colour(int64_t i, int64_t j) { return (int32_t)((i & 1) + 2 * (j & 1)); }
+
+int rbgs_ref_mc9_quarter_sweep_f64(int32_t n, int64_t ld, double h, double *u, const double *f,
+                                   int32_t colour)
+{
+    if (bad_grid(n, ld, h) || !u || !f || colour < 0 || colour > 3) return RBGS_REF_EINVAL;
+    const double c6 = 6.0 * (h * h);
+    const int64_t i0 = (colour & 1) ? 1 : 2, j0 = (colour & 2) ? 1 : 2;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = i0; i <= n; i += 2) {
+        for (int64_t j = j0; j <= n; j += 2) {
+            double e = AT(u, i + 1, j) + AT(u, i - 1, j);
+            e = e + AT(u, i, j + 1);
+            e = e + AT(u, i, j - 1);
+            double c = AT(u, i + 1, j + 1) + AT(u, i + 1, j - 1);
+            c = c + AT(u, i - 1, j + 1);
+            c = c + AT(u, i - 1, j - 1);
+            double s = 4.0 * e + c;
+            const double t = c6 * AT(f, i, j);
+            s = s - t;
+            AT(u, i, j) = s / 20.0;
+        }
+    }
+    return RBGS_REF_OK;
+}
+
+int rbgs_ref_mc9_sweep_f64(int32_t n, int64_t ld, double h, double *u, const double *f,
+                           int32_t nsweeps)
+{
+    if (bad_grid(n, ld, h) || !u || !f || nsweeps < 0) return RBGS_REF_EINVAL;
+    for (int32_t it = 0; it < nsweeps; ++it)
+        for (int32_t colour = 0; colour < 4; ++colour)
+            rbgs_ref_mc9_quarter_sweep_f64(n, ld, h, u, f, colour);
+    return RBGS_REF_OK;
+}
+
+/* Residual of the 9-point system: r = f - lap9(u) over the interior with    */
+/* lap9(u) = ((4 e + c) - 20 u) * (1 / (6 h h)) in FP64 (e, c summed as in    */
+/* the update), b = f - (4 e_g + c_g) * (1 / (6 h h)) with only the ring's    */
+/* values (b = f for g = 0); ||r||_2 and ||r||_2/||b||_2 with compensated     */
+/* sums, as rbgs_ref_residual_f64.                                            */
+int rbgs_ref_mc9_residual_f64(int32_t n, int64_t ld, double h, const double *u, const double *f,
+                              double *abs_norm, double *rel_norm, double *r_out)
+{
+    if (bad_grid(n, ld, h) || !u || !f) return RBGS_REF_EINVAL;
+    const double inv6h2 = 1.0 / (6.0 * (h * h));
+    double rs = 0.0, rc = 0.0, bs = 0.0, bc = 0.0;
+    for (int64_t i = 1; i <= n; ++i) {
+        for (int64_t j = 1; j <= n; ++j) {
+            double e = AT(u, i + 1, j) + AT(u, i - 1, j);
+            e = e + AT(u, i, j + 1);
+            e = e + AT(u, i, j - 1);
+            double c = AT(u, i + 1, j + 1) + AT(u, i + 1, j - 1);
+            c = c + AT(u, i - 1, j + 1);
+            c = c + AT(u, i - 1, j - 1);
+            const double lap = ((4.0 * e + c) - 20.0 * AT(u, i, j)) * inv6h2;
+            const double r = AT(f, i, j) - lap;
+            double eb = RING_ONLY(u, i + 1, j) + RING_ONLY(u, i - 1, j);
+            eb = eb + RING_ONLY(u, i, j + 1);
+            eb = eb + RING_ONLY(u, i, j - 1);
+            double cb = RING_ONLY(u, i + 1, j + 1) + RING_ONLY(u, i + 1, j - 1);
+            cb = cb + RING_ONLY(u, i - 1, j + 1);
+            cb = cb + RING_ONLY(u, i - 1, j - 1);
+            const double b = AT(f, i, j) - (4.0 * eb + cb) * inv6h2;
+            if (r_out) AT(r_out, i, j) = r;
+            neumaier_add(&rs, &rc, r * r);
+            neumaier_add(&bs, &bc, b * b);
+        }
+    }
+    const double rn = sqrt(rs + rc), bn = sqrt(bs + bc);
+    if (abs_norm) *abs_norm = rn;
+    if (rel_norm) *rel_norm = (bn > 0.0) ? rn / bn : rn;
+    return RBGS_REF_OK;
+}
+
+/* The solve loop of rbgs_ref_solve_f64 around 4-colour 9-point sweeps. */
+int rbgs_ref_mc9_solve_f64(int32_t n, int64_t ld, double h, double *u, const double *f,
+                           int32_t max_sweeps, double rel_tol, int32_t check_every,
+                           int32_t *sweeps_done, double *rel_out)
+{
+    if (bad_grid(n, ld, h) || !u || !f || max_sweeps < 0 || check_every < 1)
+        return RBGS_REF_EINVAL;
+    int32_t done = 0;
+    double rel = 0.0;
+    if (rel_tol <= 0.0) {
+        rbgs_ref_mc9_sweep_f64(n, ld, h, u, f, max_sweeps);
+        done = max_sweeps;
+        rbgs_ref_mc9_residual_f64(n, ld, h, u, f, NULL, &rel, NULL);
+    } else {
+        rbgs_ref_mc9_residual_f64(n, ld, h, u, f, NULL, &rel, NULL);
+        while (!(rel <= rel_tol) && done < max_sweeps) {
+            int32_t k = max_sweeps - done < check_every ? max_sweeps - done : check_every;
+            rbgs_ref_mc9_sweep_f64(n, ld, h, u, f, k);
+            done += k;
+            rbgs_ref_mc9_residual_f64(n, ld, h, u, f, NULL, &rel, NULL);
+        }
+    }
+    if (sweeps_done) *sweeps_done = done;
+    if (rel_out) *rel_out = rel;
+    return (rel_tol <= 0.0 || rel <= rel_tol) ? RBGS_REF_OK : RBGS_REF_ENOCONV;
+}
+
 /* Colour query used by the tests to check the colouring convention. */
 int32_t rbgs_ref_colour(int64_t i, int64_t j) { return colour_of(i, j); }

@@ -10,6 +10,7 @@ import oracle
 import workloads as W
 from oracle import build as obuild
 from tests import closed_form as cf
+from tests import test_oracle_mc9_pins as mc9_pins
 from tests import test_oracle_mg_pins as mg_pins
 from tests import test_oracle_pins as pins
 
@@ -40,6 +41,16 @@ MUTANTS = {
                              "v = (EC(I, J) + EC(I - 1, J)) * 0.5;"),
     "mg_postsmoothing_dropped": ("rbgs_ref_sweep_f64(a->n, a->ld, a->h, a->u, a->f, nu2);",
                                  "rbgs_ref_sweep_f64(a->n, a->ld, a->h, a->u, a->f, 0);"),
+    # 4-colour 9-point Gauss-Seidel
+    "mc9_dropped_corner": ("c = c + AT(u, i - 1, j - 1);\n            double s = 4.0 * e + c;",
+                           "double s = 4.0 * e + c;"),
+    "mc9_edge_weight": ("double s = 4.0 * e + c;", "double s = 2.0 * e + c;"),
+    "mc9_divisor": ("AT(u, i, j) = s / 20.0;", "AT(u, i, j) = s / 16.0;"),
+    "mc9_h_scale": ("const double c6 = 6.0 * (h * h);", "const double c6 = 4.0 * (h * h);"),
+    "mc9_colour_order": ("for (int32_t colour = 0; colour < 4; ++colour)\n            rbgs_ref_mc9_quarter_sweep_f64",
+                         "for (int32_t colour = 3; colour >= 0; --colour)\n            rbgs_ref_mc9_quarter_sweep_f64"),
+    "mc9_colour_parity": ("const int64_t i0 = (colour & 1) ? 1 : 2, j0 = (colour & 2) ? 1 : 2;",
+                          "const int64_t i0 = (colour & 2) ? 1 : 2, j0 = (colour & 1) ? 1 : 2;"),
 }
 
 
@@ -69,6 +80,10 @@ def _pins_that_run():
     yield lambda: mg_pins.test_restrict_is_quarter_adjoint_of_prolong(oracle)
     yield lambda: mg_pins.test_converges_to_dense_solve(oracle, 15, (1, 1))
     yield lambda: mg_pins.test_vcycle_factor_is_textbook_and_h_independent(oracle, 63)
+    yield lambda: mc9_pins.test_quarter_sweep_touches_exactly_its_colour(oracle)
+    yield lambda: mc9_pins.test_one_point(oracle)
+    yield lambda: mc9_pins.test_converges_to_dense_solve(oracle, 7)
+    yield lambda: mc9_pins.test_updated_colour_has_zero_residual(oracle)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
