@@ -54,6 +54,7 @@ KERNEL_SOURCES = {
     "blocked_f64": ("sweep_blocked.hip", "blocked_pipeline.h", "rbgs_blocked.h", "rbgs_internal.h"),
     "mg_restrict_f64": ("multigrid.hip", "rbgs_internal.h"),
     "mg_prolong_add_f64": ("multigrid.hip", "rbgs_internal.h"),
+    "mc9_quarter_f64": ("multicolour9.hip", "rbgs_internal.h"),
 }
 
 
@@ -248,6 +249,62 @@ def multigrid_to_tolerance(torch, rb, W, tol=1e-8, sizes=(1023, 8191, 16383)):
                 f"{model / per_cycle / 1e9:.0f} GB/s model")
         del f, ws, u
         torch.cuda.empty_cache()
+    return out
+
+
+MC9_BYTES_PER_LUP = 40.0  # per sweep: four quarter-sweeps, each 5 words per updated point
+
+
+def multicolour9_throughput(torch, rb, W, n=8191, sweeps=100, with_solve=True):
+    """Four-colour Gauss-Seidel for the 9-point Laplacian (the multi-colour
+    extension) on the 8191^2 FP64 grid: time of `sweeps` sweeps as the
+    difference of a (sweeps + 1)-sweep call and a 1-sweep call (both pack and
+    unpack once), GLUP/s and model bytes (40 B per point per sweep); and the
+    time to rel <= 1e-8 at 255^2 from u = 0 (sine right-hand side)."""
+    h = W.spacing(n)
+    f = torch.from_numpy(W.uniform_rhs(n, seed=0)).to("cuda")
+    u = torch.zeros_like(f)
+    ws = torch.empty(rb.rbgs_mc9_workspace_size(rb.make_grid(f, h)), dtype=torch.uint8,
+                     device="cuda")
+
+    def timed(k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rb.rbgs_mc9_sweep(u, f, k, h=h, workspace=ws)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    timed(3)
+    one = min(timed(1) for _ in range(3))
+    many = min(timed(sweeps + 1) for _ in range(2))
+    per_sweep = (many - one) / sweeps
+    glups = n * n / per_sweep / 1e9
+    out = {"workload": f"{n}x{n} FP64, f~U[-1,1) seed 0, {sweeps} sweeps",
+           "ms_per_sweep": round(per_sweep * 1e3, 4), "GLUP/s": round(glups, 2),
+           "model_bytes_per_lup": MC9_BYTES_PER_LUP,
+           "model_GBs": round(glups * MC9_BYTES_PER_LUP, 1),
+           "frac_of_8TBs": round(glups * MC9_BYTES_PER_LUP / HBM_PEAK_GBS, 4)}
+    log(f"multicolour 9-point {n}: {per_sweep * 1e3:.3f} ms/sweep, {glups:.1f} GLUP/s, "
+        f"{glups * MC9_BYTES_PER_LUP:.0f} GB/s model")
+    del u, f, ws
+    torch.cuda.empty_cache()
+    if not with_solve:
+        return out
+    m = 255
+    hm = W.spacing(m)
+    fm = torch.from_numpy(W.sine_rhs(m)).to("cuda")
+    um = torch.zeros_like(fm)
+    rb.rbgs_mc9_solve(um, fm, 8, -1.0, check_every=8, h=hm)
+    um.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = rb.rbgs_mc9_solve(um, fm, 4_000_000, 1e-8, check_every=1000, h=hm)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["time_to_1e-8_255_sine"] = {"seconds": round(dt, 4), "sweeps": info["sweeps"],
+                                    "rel_residual": info["rel_residual"],
+                                    "status": info["status"]}
+    log(f"multicolour 9-point time-to-tol 255: {dt:.3f} s, {info['sweeps']} sweeps")
     return out
 
 
@@ -483,6 +540,8 @@ def main():
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the refinement (16383^2), batched and learned-guess workloads")
+    ap.add_argument("--mc9-only", action="store_true",
+                    help="run only the 9-point four-colour section, print its JSON and exit")
     ap.add_argument("--mg-only", action="store_true",
                     help="run only the 8191^2 multigrid section (and the STREAM probe unless "
                          "--no-probe), print its JSON and exit: the multigrid kernels' profile run")
@@ -502,6 +561,10 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.mc9_only:
+        mc9 = multicolour9_throughput(torch, rb, W, with_solve=not args.no_time_to_tol)
+        print(json.dumps({"multicolour9": mc9}), flush=True)
+        return
     if args.mg_only:
         mg = multigrid_to_tolerance(torch, rb, W, sizes=(8191,))
         probe = None if args.no_probe else stream_probe(torch, rb)
@@ -586,6 +649,7 @@ def main():
         base_1023 = ttt_1023["plain_f64"]["seconds"]
         for key in ("n1023_V22", "n1023_V11"):
             multigrid[key]["speedup_vs_plain_f64"] = round(base_1023 / multigrid[key]["seconds"], 1)
+    mc9 = None if args.no_extras else multicolour9_throughput(torch, rb, W)
     refine = None if args.no_extras else refinement_throughput(torch, rb, W)
     batched = None if args.no_extras else batched_throughput(torch, rb, W)
     batched_tol = None if args.no_extras else batched_to_tolerance(torch, rb, W)
@@ -613,6 +677,7 @@ def main():
         "time_to_1e-8": ttt,
         "time_to_1e-8_fourier_1023": ttt_1023,
         "multigrid_to_1e-8": multigrid,
+        "multicolour9": mc9,
         "refinement_16383": refine,
         "batched_512": batched,
         "batched_to_1e-8": batched_tol,

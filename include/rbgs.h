@@ -436,6 +436,47 @@ int rbgs_mg_solve(const rbgs_grid *g, rbgs_dtype dt, void *u, const void *f,
                   const rbgs_mg_opts *opts, rbgs_mg_info *info,
                   void *workspace, size_t workspace_bytes, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Four-colour Gauss-Seidel for the 9-point Laplacian (an extension: the
+ * conclusion, Section 5, names multi-colour variants for wider stencils).
+ * The system is lap9(u) = f with
+ *   lap9(u)_ij = (4 e_ij + c_ij - 20 u_ij) / (6 h^2),
+ * e = sum of the four edge neighbours, c = sum of the four corner
+ * neighbours; points are coloured (i & 1) + 2 (j & 1), which separates all
+ * eight neighbours, and one sweep updates colours 0, 1, 2, 3 in turn, each
+ * point by u_ij = ((4 e + c) - 6 (h h) f_ij) / 20 (e and c summed in the
+ * order N, S, E, W and NE, NW, SE, SW; no FMA): bitwise the CPU definition.
+ * FP64 only.  u, f: DEVICE arrays in the natural layout (as rbgs_sweep);
+ * the ring of u is the Dirichlet data.  The residual is r = f - lap9(u),
+ * b = r with the interior of u set to zero (b = f for g = 0).
+ * --------------------------------------------------------------------- */
+
+/* Workspace bytes (four colour arrays each of u and f, reduction space);
+ * 0 for an invalid grid. */
+size_t rbgs_mc9_workspace_size(const rbgs_grid *g);
+
+/* nsweeps sweeps of u in place.  Asynchronous on `stream`. */
+int rbgs_mc9_sweep(const rbgs_grid *g, double *u, const double *f,
+                   int32_t nsweeps, void *workspace, size_t workspace_bytes,
+                   void *stream);
+
+/* ||r||_2 and ||r||_2/||b||_2 (HOST pointers, may be NULL), FP64, fixed
+ * reduction order.  Synchronises `stream`. */
+int rbgs_mc9_residual(const rbgs_grid *g, const double *u, const double *f,
+                      double *abs_norm, double *rel_norm, void *workspace,
+                      size_t workspace_bytes, void *stream);
+
+/* Sweeps until rel <= rel_tol (checked before the first sweep and after
+ * every check_every sweeps; rel_tol <= 0: exactly max_sweeps sweeps), as
+ * rbgs_solve, with the rounds captured in a HIP graph.  info (HOST, may be
+ * NULL): sweeps, rel_residual, abs_residual, status (outer_iters = 0).
+ * Returns RBGS_OK, RBGS_ENOCONV, RBGS_ENONFINITE or an error.  Synchronises
+ * `stream`. */
+int rbgs_mc9_solve(const rbgs_grid *g, double *u, const double *f,
+                   int32_t max_sweeps, double rel_tol, int32_t check_every,
+                   rbgs_solve_info *info, void *workspace,
+                   size_t workspace_bytes, void *stream);
+
 /* Device-memory bandwidth probe: the copy (kind 0: b = a) and triad
  * (kind 1: a = b + s*c) kernels of the STREAM benchmark, which the paper
  * uses for the attainable memory bandwidth in its roofline (Section 3,

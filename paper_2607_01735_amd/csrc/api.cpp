@@ -542,6 +542,67 @@ int mg_cycle(const MgPlan& p, int l, const MgParams& mp, hipStream_t s, const in
     return smooth(mp.nu2);
 }
 
+// ----- four-colour Gauss-Seidel for the 9-point Laplacian -----------------
+
+struct Mc9Workspace {
+    double* u[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* f[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* partials = nullptr;
+    double* sums = nullptr;  // sum r^2, sum b^2; the graph rounds' state at +64 bytes
+    size_t total = 0;
+};
+
+Mc9Workspace plan_mc9(const rbgs_grid* g, char* base) {
+    Mc9Workspace w;
+    const size_t colour = align256(size_t(mc9_rows(g->n)) * size_t(mc9_pitch(g->n)) * 8);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return reinterpret_cast<double*>(p);
+    };
+    for (auto& c : w.u) c = take(colour);
+    for (auto& c : w.f) c = take(colour);
+    w.partials = take(size_t(mc9_residual_blocks(g->n)) * 2 * sizeof(double));
+    w.sums = take(256);
+    w.total = off;
+    return w;
+}
+
+int mc9_prepare(const rbgs_grid* g, const void* u, const void* f, void* ws, size_t ws_bytes,
+                Mc9Workspace* w) {
+    std::string why;
+    if (!valid_grid(g, &why)) return fail(RBGS_EINVAL, why);
+    Mc9Workspace plan = plan_mc9(g, nullptr);
+    int rc;
+    if ((rc = check_workspace(ws, ws_bytes, plan.total))) return rc;
+    if ((rc = check_device_range(u, grid_bytes(g, RBGS_F64), "u"))) return rc;
+    if ((rc = check_device_range(f, grid_bytes(g, RBGS_F64), "f"))) return rc;
+    *w = plan_mc9(g, static_cast<char*>(ws));
+    return RBGS_OK;
+}
+
+int mc9_sweeps(const rbgs_grid* g, const Mc9Workspace& w, int nsweeps, hipStream_t s,
+               const int* stop) {
+    const double c6 = 6.0 * (g->h * g->h);
+    for (int it = 0; it < nsweeps; ++it)
+        for (int colour = 0; colour < 4; ++colour)
+            HIP_TRY(launch_mc9_quarter(w.u, w.f, g->n, c6, colour, stop, s), "quarter-sweep");
+    return RBGS_OK;
+}
+
+int mc9_residual_sums(const rbgs_grid* g, const Mc9Workspace& w, hipStream_t s) {
+    HIP_TRY(launch_mc9_residual(w.u, w.f, g->n, 1.0 / (6.0 * (g->h * g->h)), w.partials, w.sums, s),
+            "9-point residual");
+    return RBGS_OK;
+}
+
+int mc9_fetch(const Mc9Workspace& w, hipStream_t s, double* abs_norm, double* rel_norm) {
+    Workspace v;
+    v.sums = w.sums;
+    return fetch_norms(v, s, abs_norm, rel_norm);
+}
+
 }  // namespace
 
 extern "C" {
@@ -961,6 +1022,100 @@ int rbgs_mg_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         out.status = (fixed || rel <= o->rel_tol) ? RBGS_OK : RBGS_ENOCONV;
     for (void* st : states)
         if ((rc = blocked_check_error(st, s, &g_last_error))) out.status = rc;
+    if (info) *info = out;
+    if (out.status == RBGS_ENONFINITE) g_last_error = "residual is not finite";
+    if (out.status == RBGS_ENOCONV) g_last_error = "tolerance not reached";
+    return out.status;
+}
+
+size_t rbgs_mc9_workspace_size(const rbgs_grid* g) {
+    std::string why;
+    if (!valid_grid(g, &why)) return 0;
+    return plan_mc9(g, nullptr).total;
+}
+
+int rbgs_mc9_sweep(const rbgs_grid* g, double* u, const double* f, int32_t nsweeps,
+                   void* workspace, size_t workspace_bytes, void* stream) {
+    if (nsweeps < 0) return fail(RBGS_EINVAL, "nsweeps must be >= 0");
+    Mc9Workspace w;
+    int rc = mc9_prepare(g, u, f, workspace, workspace_bytes, &w);
+    if (rc) return rc;
+    if (nsweeps == 0) return RBGS_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(launch_mc9_pack(u, g->ld, w.u, g->n, s), "pack u");
+    HIP_TRY(launch_mc9_pack(f, g->ld, w.f, g->n, s), "pack f");
+    if ((rc = mc9_sweeps(g, w, nsweeps, s, nullptr))) return rc;
+    HIP_TRY(launch_mc9_unpack(u, g->ld, w.u, g->n, s), "unpack u");
+    return RBGS_OK;
+}
+
+int rbgs_mc9_residual(const rbgs_grid* g, const double* u, const double* f, double* abs_norm,
+                      double* rel_norm, void* workspace, size_t workspace_bytes, void* stream) {
+    Mc9Workspace w;
+    int rc = mc9_prepare(g, u, f, workspace, workspace_bytes, &w);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(launch_mc9_pack(u, g->ld, w.u, g->n, s), "pack u");
+    HIP_TRY(launch_mc9_pack(f, g->ld, w.f, g->n, s), "pack f");
+    if ((rc = mc9_residual_sums(g, w, s))) return rc;
+    return mc9_fetch(w, s, abs_norm, rel_norm);
+}
+
+int rbgs_mc9_solve(const rbgs_grid* g, double* u, const double* f, int32_t max_sweeps,
+                   double rel_tol, int32_t check_every, rbgs_solve_info* info, void* workspace,
+                   size_t workspace_bytes, void* stream) {
+    if (max_sweeps < 0) return fail(RBGS_EINVAL, "max_sweeps must be >= 0");
+    if (check_every < 1) return fail(RBGS_EINVAL, "check_every must be >= 1");
+    if (std::isnan(rel_tol)) return fail(RBGS_EINVAL, "rel_tol is NaN");
+    Mc9Workspace w;
+    int rc = mc9_prepare(g, u, f, workspace, workspace_bytes, &w);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(launch_mc9_pack(u, g->ld, w.u, g->n, s), "pack u");
+    HIP_TRY(launch_mc9_pack(f, g->ld, w.f, g->n, s), "pack f");
+    double rel = 0.0, ab = 0.0;
+    int32_t done = 0;
+    if (rel_tol <= 0.0) {
+        if ((rc = mc9_sweeps(g, w, max_sweeps, s, nullptr))) return rc;
+        done = max_sweeps;
+        if ((rc = mc9_residual_sums(g, w, s))) return rc;
+        if ((rc = mc9_fetch(w, s, &ab, &rel))) return rc;
+    } else {
+        if ((rc = mc9_residual_sums(g, w, s))) return rc;
+        if ((rc = mc9_fetch(w, s, &ab, &rel))) return rc;
+        const int cap = max_sweeps / check_every;
+        if (!(rel <= rel_tol) && std::isfinite(rel) && cap > 0) {
+            Workspace v;
+            v.sums = w.sums;
+            RoundBody body = [&](hipStream_t cs, const int* stop, void** es) -> int {
+                *es = nullptr;
+                int r = mc9_sweeps(g, w, check_every, cs, stop);
+                return r ? r : mc9_residual_sums(g, w, cs);
+            };
+            int rounds = 0;
+            bool used = false;
+            void* es = nullptr;
+            if ((rc = solve_rounds_graph(v, body, cap, rel_tol, s, &es, &rounds, &used))) return rc;
+            if (used) {
+                done = rounds * check_every;
+                if ((rc = mc9_fetch(w, s, &ab, &rel))) return rc;
+            }
+        }
+        while (!(rel <= rel_tol) && done < max_sweeps && std::isfinite(rel)) {
+            const int32_t k = max_sweeps - done < check_every ? max_sweeps - done : check_every;
+            if ((rc = mc9_sweeps(g, w, k, s, nullptr))) return rc;
+            done += k;
+            if ((rc = mc9_residual_sums(g, w, s))) return rc;
+            if ((rc = mc9_fetch(w, s, &ab, &rel))) return rc;
+        }
+    }
+    HIP_TRY(launch_mc9_unpack(u, g->ld, w.u, g->n, s), "unpack u");
+    HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+    rbgs_solve_info out{done, 0, rel, ab, RBGS_OK};
+    if (!std::isfinite(rel))
+        out.status = RBGS_ENONFINITE;
+    else
+        out.status = (rel_tol <= 0.0 || rel <= rel_tol) ? RBGS_OK : RBGS_ENOCONV;
     if (info) *info = out;
     if (out.status == RBGS_ENONFINITE) g_last_error = "residual is not finite";
     if (out.status == RBGS_ENOCONV) g_last_error = "tolerance not reached";

@@ -122,6 +122,23 @@ hipError_t launch_mg_prolong_add(double* u_red, double* u_black, int64_t pitch, 
                                  const double* e_red, const double* e_black, int64_t cpitch,
                                  const int* stop, hipStream_t s);
 
+// Four-colour 9-point Gauss-Seidel on one array per colour (colour
+// (i & 1) + 2 (j & 1), point (i, j) at [i >> 1][j >> 1]; mc9_rows(n) rows of
+// mc9_pitch(n) doubles each).  quarter: one colour's update, c6 = 6 (h h);
+// nothing when stop != nullptr and *stop != 0.  residual: sums of r^2 and
+// b^2 into out[0..1] through mc9_residual_blocks(n) partial pairs.
+int mc9_rows(int n);
+int64_t mc9_pitch(int n);
+int mc9_residual_blocks(int n);
+hipError_t launch_mc9_pack(const double* nat, int64_t ld, double* const colours[4], int n,
+                           hipStream_t s);
+hipError_t launch_mc9_unpack(double* nat, int64_t ld, double* const colours[4], int n,
+                             hipStream_t s);
+hipError_t launch_mc9_quarter(double* const u[4], double* const f[4], int n, double c6,
+                              int colour, const int* stop, hipStream_t s);
+hipError_t launch_mc9_residual(double* const u[4], double* const f[4], int n, double inv6h2,
+                               double* partials, double* out, hipStream_t s);
+
 // Copies the Dirichlet ring (and nothing that a pass would not overwrite
 // before reading) of split grid src into dst; n + 2 rows of `pitch` elements.
 hipError_t launch_copy_ring(void* dst_red, void* dst_black, const void* src_red,

@@ -92,6 +92,16 @@ _lib.rbgs_mg_workspace_size.restype = ctypes.c_size_t
 _lib.rbgs_mg_solve.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, _P(rbgs_mg_opts),
                                _P(rbgs_mg_info), _vp, ctypes.c_size_t, _vp]
 _lib.rbgs_mg_solve.restype = ctypes.c_int
+_lib.rbgs_mc9_workspace_size.argtypes = [_P(rbgs_grid)]
+_lib.rbgs_mc9_workspace_size.restype = ctypes.c_size_t
+_lib.rbgs_mc9_sweep.argtypes = [_P(rbgs_grid), _vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+_lib.rbgs_mc9_sweep.restype = ctypes.c_int
+_lib.rbgs_mc9_residual.argtypes = [_P(rbgs_grid), _vp, _vp, _P(ctypes.c_double),
+                                   _P(ctypes.c_double), _vp, ctypes.c_size_t, _vp]
+_lib.rbgs_mc9_residual.restype = ctypes.c_int
+_lib.rbgs_mc9_solve.argtypes = [_P(rbgs_grid), _vp, _vp, ctypes.c_int32, ctypes.c_double,
+                                ctypes.c_int32, _P(rbgs_solve_info), _vp, ctypes.c_size_t, _vp]
+_lib.rbgs_mc9_solve.restype = ctypes.c_int
 _lib.rbgs_workspace_size.argtypes = [_P(rbgs_grid), ctypes.c_int, _P(rbgs_solve_opts)]
 _lib.rbgs_workspace_size.restype = ctypes.c_size_t
 _lib.rbgs_sweep.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, ctypes.c_int32,
@@ -142,7 +152,8 @@ EXPORTED = ("rbgs_workspace_size", "rbgs_sweep", "rbgs_residual", "rbgs_solve",
             "rbgs_unet_get_params", "rbgs_unet_get_grads", "rbgs_unet_forward",
             "rbgs_unet_train_step", "rbgs_solve_learned", "rbgs_unet_last_error",
             "rbgs_restrict", "rbgs_prolong", "rbgs_batch_solve_workspace_size",
-            "rbgs_solve_batched", "rbgs_mg_workspace_size", "rbgs_mg_solve")
+            "rbgs_solve_batched", "rbgs_mg_workspace_size", "rbgs_mg_solve",
+            "rbgs_mc9_workspace_size", "rbgs_mc9_sweep", "rbgs_mc9_residual", "rbgs_mc9_solve")
 
 
 class RbgsError(RuntimeError):
@@ -342,6 +353,56 @@ def rbgs_mg_solve(u, f, max_cycles, rel_tol, pre_sweeps=2, post_sweeps=2, max_le
                             _stream_ptr(stream, u.device))
     _check(rc, allow=(OK,) if raise_on_noconv else (OK, ENOCONV, ENONFINITE))
     return {k: getattr(info, k) for k, _ in rbgs_mg_info._fields_}
+
+
+def _mc9_args(u, f, h, workspace):
+    import torch
+    _same_layout(u, f)
+    if u.dtype != torch.float64:
+        raise RbgsError(EUNSUPPORTED, "the 9-point sweep runs in FP64")
+    grid = make_grid(u, h)
+    if workspace is None:
+        need = int(_lib.rbgs_mc9_workspace_size(ctypes.byref(grid)))
+        if need == 0:
+            raise RbgsError(EINVAL, "invalid grid")
+        workspace = torch.empty(need, dtype=torch.uint8, device=u.device)
+    return grid, workspace
+
+
+def rbgs_mc9_workspace_size(grid):
+    return int(_lib.rbgs_mc9_workspace_size(ctypes.byref(grid)))
+
+
+def rbgs_mc9_sweep(u, f, nsweeps, h=None, workspace=None, stream=None):
+    """nsweeps four-colour sweeps of the 9-point system, in place (FP64)."""
+    grid, ws = _mc9_args(u, f, h, workspace)
+    _check(_lib.rbgs_mc9_sweep(ctypes.byref(grid), _vp(u.data_ptr()), _vp(f.data_ptr()),
+                               int(nsweeps), _vp(ws.data_ptr()), ws.numel(),
+                               _stream_ptr(stream, u.device)))
+
+
+def rbgs_mc9_residual(u, f, h=None, workspace=None, stream=None):
+    """(||r||_2, ||r||_2/||b||_2) of the 9-point system, on the GPU."""
+    grid, ws = _mc9_args(u, f, h, workspace)
+    a, r = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.rbgs_mc9_residual(ctypes.byref(grid), _vp(u.data_ptr()), _vp(f.data_ptr()),
+                                  ctypes.byref(a), ctypes.byref(r), _vp(ws.data_ptr()), ws.numel(),
+                                  _stream_ptr(stream, u.device)))
+    return a.value, r.value
+
+
+def rbgs_mc9_solve(u, f, max_sweeps, rel_tol, check_every=100, h=None, workspace=None,
+                   stream=None, raise_on_noconv=False):
+    """Four-colour 9-point sweeps until rel <= rel_tol; returns a dict with
+    sweeps, rel_residual, abs_residual and status."""
+    grid, ws = _mc9_args(u, f, h, workspace)
+    info = rbgs_solve_info()
+    rc = _lib.rbgs_mc9_solve(ctypes.byref(grid), _vp(u.data_ptr()), _vp(f.data_ptr()),
+                             int(max_sweeps), float(rel_tol), int(check_every), ctypes.byref(info),
+                             _vp(ws.data_ptr()), ws.numel(), _stream_ptr(stream, u.device))
+    _check(rc, allow=(OK,) if raise_on_noconv else (OK, ENOCONV, ENONFINITE))
+    return {"sweeps": info.sweeps, "rel_residual": info.rel_residual,
+            "abs_residual": info.abs_residual, "status": info.status}
 
 
 def rbgs_stream_probe(kind, a, b, c=None, s=3.0, stream=None):

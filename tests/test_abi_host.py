@@ -272,3 +272,23 @@ def test_mg_validation_before_device_work(lib, bad):
                                 None, 0, None)
     assert rc == expect, lib.rbgs_last_error()
     assert lib.rbgs_last_error()
+
+
+def test_mc9_workspace_and_validation(lib):
+    g = _grid(lib, 255)
+    size = lib.rbgs_mc9_workspace_size(g)
+    # eight colour arrays of 129 rows x 160 doubles at least
+    assert size >= 8 * 129 * 128 * 8 and size % 256 == 0
+    assert lib.rbgs_mc9_workspace_size(_grid(lib, 0)) == 0
+    raw = lib._lib
+    gp = ctypes.byref(g)
+    assert raw.rbgs_mc9_sweep(gp, None, None, -1, None, 0, None) == lib.EINVAL
+    assert raw.rbgs_mc9_sweep(gp, None, None, 1, None, 0, None) == lib.EWORKSPACE
+    info = lib.rbgs_solve_info()
+    assert raw.rbgs_mc9_solve(gp, None, None, 10, 1e-8, 0, ctypes.byref(info), None, 0,
+                              None) == lib.EINVAL
+    assert raw.rbgs_mc9_solve(gp, None, None, 10, float("nan"), 5, ctypes.byref(info), None, 0,
+                              None) == lib.EINVAL
+    bad = _grid(lib, 31, ld=30)
+    assert raw.rbgs_mc9_residual(ctypes.byref(bad), None, None, None, None, None, 0,
+                                 None) == lib.EINVAL
