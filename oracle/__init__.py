@@ -54,6 +54,10 @@ def _load(path=None):
         "rbgs_ref_sor_solve_f64": [_i32, _i64, _f64, _f64, _vp, _vp, _i32, _f64, _i32, _vp, _vp],
         "rbgs_ref_mg_levels": [_i32, _i32, _vp],
         "rbgs_ref_mc9_colour": [_i64, _i64],
+        "rbgs_ref_rb3_half_sweep_f64": [_i32, _i64, _f64, _vp, _vp, _i32],
+        "rbgs_ref_rb3_sweep_f64": [_i32, _i64, _f64, _vp, _vp, _i32],
+        "rbgs_ref_rb3_residual_f64": [_i32, _i64, _f64, _vp, _vp, _vp, _vp, _vp],
+        "rbgs_ref_rb3_solve_f64": [_i32, _i64, _f64, _vp, _vp, _i32, _f64, _i32, _vp, _vp],
         "rbgs_ref_mc9_quarter_sweep_f64": [_i32, _i64, _f64, _vp, _vp, _i32],
         "rbgs_ref_mc9_sweep_f64": [_i32, _i64, _f64, _vp, _vp, _i32],
         "rbgs_ref_mc9_residual_f64": [_i32, _i64, _f64, _vp, _vp, _vp, _vp, _vp],
@@ -322,6 +326,52 @@ def mc9_solve(u, f, h, max_sweeps, rel_tol, check_every):
     rc = _check(_load().rbgs_ref_mc9_solve_f64(n, ld, h, _ptr(u), _ptr(f), max_sweeps, rel_tol,
                                                check_every, ctypes.byref(done),
                                                ctypes.byref(rel)), "mc9_solve")
+    return rc, done.value, rel.value
+
+
+def _grid3(a):
+    if a.ndim != 3 or a.shape[0] < 3 or a.shape[1] != a.shape[0] or a.shape[2] < a.shape[0]:
+        raise ValueError("expected an (n+2) x (n+2) x ld array with ld >= n+2")
+    if not a.flags.c_contiguous or a.dtype != np.float64:
+        raise ValueError("array must be C-contiguous float64")
+    return a.shape[0] - 2, a.shape[2]
+
+
+def rb3_half_sweep(u, f, h, colour):
+    """One 3D red-black half-sweep in place; colour 0 = red (i+j+k even)."""
+    n, ld = _grid3(u)
+    assert f.shape == u.shape
+    _check(_load().rbgs_ref_rb3_half_sweep_f64(n, ld, h, _ptr(u), _ptr(f), colour), "rb3_half")
+    return u
+
+
+def rb3_sweep(u, f, h, nsweeps):
+    """nsweeps 3D red-black sweeps (7-point Laplacian) in place."""
+    n, ld = _grid3(u)
+    assert f.shape == u.shape
+    _check(_load().rbgs_ref_rb3_sweep_f64(n, ld, h, _ptr(u), _ptr(f), nsweeps), "rb3_sweep")
+    return u
+
+
+def rb3_residual(u, f, h, want_field=False):
+    """(||r||_2, ||r||_2/||b||_2[, r]) of the 3D 7-point system in FP64."""
+    n, ld = _grid3(u)
+    assert f.shape == u.shape and f.dtype == np.float64
+    a, r = _f64(), _f64()
+    field = np.zeros(u.shape, np.float64) if want_field else None
+    _check(_load().rbgs_ref_rb3_residual_f64(n, ld, h, _ptr(u), _ptr(f), ctypes.byref(a),
+                                             ctypes.byref(r), _ptr(field) if want_field else None),
+           "rb3_residual")
+    return (a.value, r.value, field) if want_field else (a.value, r.value)
+
+
+def rb3_solve(u, f, h, max_sweeps, rel_tol, check_every):
+    """3D red-black sweeps until rel <= rel_tol.  Returns (status, sweeps, rel)."""
+    n, ld = _grid3(u)
+    done, rel = _i32(), _f64()
+    rc = _check(_load().rbgs_ref_rb3_solve_f64(n, ld, h, _ptr(u), _ptr(f), max_sweeps, rel_tol,
+                                               check_every, ctypes.byref(done),
+                                               ctypes.byref(rel)), "rb3_solve")
     return rc, done.value, rel.value
 
 

@@ -677,5 +677,128 @@ int rbgs_ref_mc9_solve_f64(int32_t n, int64_t ld, double h, double *u, const dou
     return (rel_tol <= 0.0 || rel <= rel_tol) ? RBGS_REF_OK : RBGS_REF_ENOCONV;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Red-black Gauss-Seidel in three dimensions (an extension: the conclusion,  */
+/* Section 5, names higher dimensions as future work).  Poisson's equation    */
+/* lap(u) = f on the unit cube, N^3 interior points, h = 1/(N+1), the 7-point */
+/* Laplacian (sum of the six neighbours - 6 u) / h^2; red points have i+j+k   */
+/* even.  The point update solves point (i, j, k)'s equation for u_ijk:       */
+/*     s = ((((u[i+1] + u[i-1]) + u[j+1]) + u[j-1]) + u[k+1]) + u[k-1],       */
+/*     s = s - (h h) f,  u_ijk = s / 6                                         */
+/* (each operation rounded once, no FMA; u[i+1] means u[i+1][j][k], etc.).   */
+/* Storage: (n+2) planes (index i) of (n+2) rows (index j) of ld >= n+2       */
+/* elements (index k); element (i, j, k) is a[(i (n+2) + j) ld + k]; the      */
+/* ring (any index 0 or n+1) holds the Dirichlet data g.                       */
+/* ------------------------------------------------------------------------- */
+#define AT3(a, i, j, k) ((a)[((size_t)(i) * (size_t)(n + 2) + (size_t)(j)) * (size_t)ld + (size_t)(k)])
+
+static int on_ring3(int32_t n, int64_t i, int64_t j, int64_t k)
+{
+    return i == 0 || j == 0 || k == 0 || i == (int64_t)n + 1 || j == (int64_t)n + 1 ||
+           k == (int64_t)n + 1;
+}
+
+int rbgs_ref_rb3_half_sweep_f64(int32_t n, int64_t ld, double h, double *u, const double *f,
+                                int32_t colour)
+{
+    if (bad_grid(n, ld, h) || !u || !f || (colour != 0 && colour != 1)) return RBGS_REF_EINVAL;
+    const double h2 = h * h;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 1; i <= n; ++i) {
+        for (int64_t j = 1; j <= n; ++j) {
+            /* first k >= 1 with (i + j + k) & 1 == colour */
+            const int64_t k0 = ((i + j + 1) & 1) == colour ? 1 : 2;
+            for (int64_t k = k0; k <= n; k += 2) {
+                double s = AT3(u, i + 1, j, k) + AT3(u, i - 1, j, k);
+                s = s + AT3(u, i, j + 1, k);
+                s = s + AT3(u, i, j - 1, k);
+                s = s + AT3(u, i, j, k + 1);
+                s = s + AT3(u, i, j, k - 1);
+                const double t = h2 * AT3(f, i, j, k);
+                s = s - t;
+                AT3(u, i, j, k) = s / 6.0;
+            }
+        }
+    }
+    return RBGS_REF_OK;
+}
+
+int rbgs_ref_rb3_sweep_f64(int32_t n, int64_t ld, double h, double *u, const double *f,
+                           int32_t nsweeps)
+{
+    if (bad_grid(n, ld, h) || !u || !f || nsweeps < 0) return RBGS_REF_EINVAL;
+    for (int32_t it = 0; it < nsweeps; ++it) {
+        rbgs_ref_rb3_half_sweep_f64(n, ld, h, u, f, 0);
+        rbgs_ref_rb3_half_sweep_f64(n, ld, h, u, f, 1);
+    }
+    return RBGS_REF_OK;
+}
+
+/* r = f - (s6 - 6 u) * (1 / (h h)) with s6 summed as in the update; b = f -  */
+/* (ring-only s6) * (1 / (h h)); norms with compensated sums.                 */
+int rbgs_ref_rb3_residual_f64(int32_t n, int64_t ld, double h, const double *u, const double *f,
+                              double *abs_norm, double *rel_norm, double *r_out)
+{
+    if (bad_grid(n, ld, h) || !u || !f) return RBGS_REF_EINVAL;
+    const double inv_h2 = 1.0 / (h * h);
+    double rs = 0.0, rc = 0.0, bs = 0.0, bc = 0.0;
+#define R3(i, j, k) (on_ring3(n, (i), (j), (k)) ? AT3(u, i, j, k) : 0.0)
+    for (int64_t i = 1; i <= n; ++i) {
+        for (int64_t j = 1; j <= n; ++j) {
+            for (int64_t k = 1; k <= n; ++k) {
+                double s = AT3(u, i + 1, j, k) + AT3(u, i - 1, j, k);
+                s = s + AT3(u, i, j + 1, k);
+                s = s + AT3(u, i, j - 1, k);
+                s = s + AT3(u, i, j, k + 1);
+                s = s + AT3(u, i, j, k - 1);
+                const double lap = (s - 6.0 * AT3(u, i, j, k)) * inv_h2;
+                const double r = AT3(f, i, j, k) - lap;
+                double sb = R3(i + 1, j, k) + R3(i - 1, j, k);
+                sb = sb + R3(i, j + 1, k);
+                sb = sb + R3(i, j - 1, k);
+                sb = sb + R3(i, j, k + 1);
+                sb = sb + R3(i, j, k - 1);
+                const double b = AT3(f, i, j, k) - sb * inv_h2;
+                if (r_out) AT3(r_out, i, j, k) = r;
+                neumaier_add(&rs, &rc, r * r);
+                neumaier_add(&bs, &bc, b * b);
+            }
+        }
+    }
+#undef R3
+    const double rn = sqrt(rs + rc), bn = sqrt(bs + bc);
+    if (abs_norm) *abs_norm = rn;
+    if (rel_norm) *rel_norm = (bn > 0.0) ? rn / bn : rn;
+    return RBGS_REF_OK;
+}
+
+/* The solve loop of rbgs_ref_solve_f64 around 3D red-black sweeps. */
+int rbgs_ref_rb3_solve_f64(int32_t n, int64_t ld, double h, double *u, const double *f,
+                           int32_t max_sweeps, double rel_tol, int32_t check_every,
+                           int32_t *sweeps_done, double *rel_out)
+{
+    if (bad_grid(n, ld, h) || !u || !f || max_sweeps < 0 || check_every < 1)
+        return RBGS_REF_EINVAL;
+    int32_t done = 0;
+    double rel = 0.0;
+    if (rel_tol <= 0.0) {
+        rbgs_ref_rb3_sweep_f64(n, ld, h, u, f, max_sweeps);
+        done = max_sweeps;
+        rbgs_ref_rb3_residual_f64(n, ld, h, u, f, NULL, &rel, NULL);
+    } else {
+        rbgs_ref_rb3_residual_f64(n, ld, h, u, f, NULL, &rel, NULL);
+        while (!(rel <= rel_tol) && done < max_sweeps) {
+            int32_t kk = max_sweeps - done < check_every ? max_sweeps - done : check_every;
+            rbgs_ref_rb3_sweep_f64(n, ld, h, u, f, kk);
+            done += kk;
+            rbgs_ref_rb3_residual_f64(n, ld, h, u, f, NULL, &rel, NULL);
+        }
+    }
+    if (sweeps_done) *sweeps_done = done;
+    if (rel_out) *rel_out = rel;
+    return (rel_tol <= 0.0 || rel <= rel_tol) ? RBGS_REF_OK : RBGS_REF_ENOCONV;
+}
+#undef AT3
+
 /* Colour query used by the tests to check the colouring convention. */
 int32_t rbgs_ref_colour(int64_t i, int64_t j) { return colour_of(i, j); }

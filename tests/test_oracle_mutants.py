@@ -12,6 +12,7 @@ from oracle import build as obuild
 from tests import closed_form as cf
 from tests import test_oracle_mc9_pins as mc9_pins
 from tests import test_oracle_mg_pins as mg_pins
+from tests import test_oracle_rb3_pins as rb3_pins
 from tests import test_oracle_pins as pins
 
 MUTANTS = {
@@ -49,6 +50,13 @@ MUTANTS = {
     "mc9_h_scale": ("const double c6 = 6.0 * (h * h);", "const double c6 = 4.0 * (h * h);"),
     "mc9_colour_order": ("for (int32_t colour = 0; colour < 4; ++colour)\n            rbgs_ref_mc9_quarter_sweep_f64",
                          "for (int32_t colour = 3; colour >= 0; --colour)\n            rbgs_ref_mc9_quarter_sweep_f64"),
+    "rb3_dropped_k_minus": ("s = s + AT3(u, i, j, k - 1);\n                const double t = h2",
+                            "const double t = h2"),
+    "rb3_divisor": ("AT3(u, i, j, k) = s / 6.0;", "AT3(u, i, j, k) = s / 4.0;"),
+    "rb3_colour_parity": ("const int64_t k0 = ((i + j + 1) & 1) == colour ? 1 : 2;",
+                          "const int64_t k0 = ((i + j) & 1) == colour ? 1 : 2;"),
+    "rb3_wrong_plane": ("double s = AT3(u, i + 1, j, k) + AT3(u, i - 1, j, k);\n                s = s + AT3(u, i, j + 1, k);\n                s = s + AT3(u, i, j - 1, k);\n                s = s + AT3(u, i, j, k + 1);\n                s = s + AT3(u, i, j, k - 1);\n                const double t",
+                        "double s = AT3(u, i + 1, j, k) + AT3(u, i + 1, j, k);\n                s = s + AT3(u, i, j + 1, k);\n                s = s + AT3(u, i, j - 1, k);\n                s = s + AT3(u, i, j, k + 1);\n                s = s + AT3(u, i, j, k - 1);\n                const double t"),
     "mc9_colour_parity": ("const int64_t i0 = (colour & 1) ? 1 : 2, j0 = (colour & 2) ? 1 : 2;",
                           "const int64_t i0 = (colour & 2) ? 1 : 2, j0 = (colour & 1) ? 1 : 2;"),
 }
@@ -84,6 +92,9 @@ def _pins_that_run():
     yield lambda: mc9_pins.test_one_point(oracle)
     yield lambda: mc9_pins.test_converges_to_dense_solve(oracle, 7)
     yield lambda: mc9_pins.test_updated_colour_has_zero_residual(oracle)
+    yield lambda: rb3_pins.test_half_sweep_touches_exactly_its_colour(oracle)
+    yield lambda: rb3_pins.test_one_point(oracle)
+    yield lambda: rb3_pins.test_converges_to_dense_solve(oracle, 4)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
