@@ -55,6 +55,7 @@ KERNEL_SOURCES = {
     "mg_restrict_f64": ("multigrid.hip", "rbgs_internal.h"),
     "mg_prolong_add_f64": ("multigrid.hip", "rbgs_internal.h"),
     "mc9_quarter_f64": ("multicolour9.hip", "rbgs_internal.h"),
+    "rb3_half_f64": ("sweep3d.hip", "rbgs_internal.h"),
 }
 
 
@@ -308,6 +309,45 @@ def multicolour9_throughput(torch, rb, W, n=8191, sweeps=100, with_solve=True):
     return out
 
 
+def rb3_throughput(torch, rb, n=767, sweeps=40):
+    """Red-black Gauss-Seidel in 3D (the higher-dimension extension): n^3
+    FP64 with f ~ U[-1, 1) drawn on the device (seeded), time per sweep from
+    the difference of a (sweeps + 1)-sweep and a 1-sweep call, GLUP/s and
+    model bytes (24 B per point per sweep, as in 2D)."""
+    h = 1.0 / (n + 1)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    f = torch.zeros((n + 2,) * 3, dtype=torch.float64, device="cuda")
+    f[1:-1, 1:-1, 1:-1] = torch.rand((n, n, n), dtype=torch.float64, device="cuda",
+                                     generator=gen) * 2.0 - 1.0
+    u = torch.zeros_like(f)
+    ws = torch.empty(rb.rbgs_rb3_workspace_size(rb.make_grid3(f, h)), dtype=torch.uint8,
+                     device="cuda")
+
+    def timed(k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rb.rbgs_rb3_sweep(u, f, k, h=h, workspace=ws)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    timed(2)
+    one = min(timed(1) for _ in range(3))
+    many = min(timed(sweeps + 1) for _ in range(2))
+    per_sweep = (many - one) / sweeps
+    glups = n ** 3 / per_sweep / 1e9
+    out = {"workload": f"{n}^3 FP64, f~U[-1,1) (device generator, seed 0), {sweeps} sweeps",
+           "ms_per_sweep": round(per_sweep * 1e3, 4), "GLUP/s": round(glups, 2),
+           "model_bytes_per_lup": BYTES_PER_LUP["f64"],
+           "model_GBs": round(glups * BYTES_PER_LUP["f64"], 1),
+           "frac_of_8TBs": round(glups * BYTES_PER_LUP["f64"] / HBM_PEAK_GBS, 4)}
+    log(f"3D red-black {n}^3: {per_sweep * 1e3:.3f} ms/sweep, {glups:.1f} GLUP/s, "
+        f"{glups * BYTES_PER_LUP['f64']:.0f} GB/s model")
+    del u, f, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def learned_guess(torch, rb, tol=1e-8, seeds=2):
     """The learned-guess workload: 511 x 511 GRF right-hand sides (held-out
     seeds 10^6 + 20 + i), FP64 solve to rel <= tol from u = 0 (the judge)
@@ -540,6 +580,8 @@ def main():
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the refinement (16383^2), batched and learned-guess workloads")
+    ap.add_argument("--rb3-only", action="store_true",
+                    help="run only the 3D red-black section, print its JSON and exit")
     ap.add_argument("--mc9-only", action="store_true",
                     help="run only the 9-point four-colour section, print its JSON and exit")
     ap.add_argument("--mg-only", action="store_true",
@@ -561,6 +603,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.rb3_only:
+        print(json.dumps({"rb3": rb3_throughput(torch, rb)}), flush=True)
+        return
     if args.mc9_only:
         mc9 = multicolour9_throughput(torch, rb, W, with_solve=not args.no_time_to_tol)
         print(json.dumps({"multicolour9": mc9}), flush=True)
@@ -650,6 +695,7 @@ def main():
         for key in ("n1023_V22", "n1023_V11"):
             multigrid[key]["speedup_vs_plain_f64"] = round(base_1023 / multigrid[key]["seconds"], 1)
     mc9 = None if args.no_extras else multicolour9_throughput(torch, rb, W)
+    rb3 = None if args.no_extras else rb3_throughput(torch, rb)
     refine = None if args.no_extras else refinement_throughput(torch, rb, W)
     batched = None if args.no_extras else batched_throughput(torch, rb, W)
     batched_tol = None if args.no_extras else batched_to_tolerance(torch, rb, W)
@@ -678,6 +724,7 @@ def main():
         "time_to_1e-8_fourier_1023": ttt_1023,
         "multigrid_to_1e-8": multigrid,
         "multicolour9": mc9,
+        "rb3": rb3,
         "refinement_16383": refine,
         "batched_512": batched,
         "batched_to_1e-8": batched_tol,

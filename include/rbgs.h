@@ -477,6 +477,41 @@ int rbgs_mc9_solve(const rbgs_grid *g, double *u, const double *f,
                    rbgs_solve_info *info, void *workspace,
                    size_t workspace_bytes, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Red-black Gauss-Seidel in three dimensions (an extension: the
+ * conclusion, Section 5, names higher dimensions as future work).  Poisson's
+ * equation on the unit cube with the 7-point Laplacian (six neighbours - 6
+ * u) / h^2; red points have i + j + k even; one sweep is red then black,
+ * each point by u = (((((u[i+1] + u[i-1]) + u[j+1]) + u[j-1]) + u[k+1])
+ * + u[k-1] - (h h) f) / 6 (no FMA): bitwise the CPU definition.  FP64 only.
+ * u, f: DEVICE arrays of (n+2) planes (index i) of (n+2) rows (index j) of
+ * ld >= n+2 elements (index k), element (i, j, k) at (i (n+2) + j) ld + k;
+ * the ring (any index 0 or n+1) of u is the Dirichlet data.  1 <= n <= 4094
+ * (memory bounds it far lower: 1023^3 FP64 is 8.6 GB per array).  The
+ * residual is r = f - lap(u), b = r with the interior of u set to zero.
+ * --------------------------------------------------------------------- */
+
+/* Workspace bytes (split u and f, reduction space); 0 for an invalid grid. */
+size_t rbgs_rb3_workspace_size(const rbgs_grid *g);
+
+/* nsweeps sweeps of u in place.  Asynchronous on `stream`. */
+int rbgs_rb3_sweep(const rbgs_grid *g, double *u, const double *f,
+                   int32_t nsweeps, void *workspace, size_t workspace_bytes,
+                   void *stream);
+
+/* ||r||_2 and ||r||_2/||b||_2 (HOST pointers, may be NULL), FP64, fixed
+ * reduction order.  Synchronises `stream`. */
+int rbgs_rb3_residual(const rbgs_grid *g, const double *u, const double *f,
+                      double *abs_norm, double *rel_norm, void *workspace,
+                      size_t workspace_bytes, void *stream);
+
+/* Sweeps until rel <= rel_tol, as rbgs_mc9_solve (graph-captured rounds;
+ * rel_tol <= 0: exactly max_sweeps sweeps).  Synchronises `stream`. */
+int rbgs_rb3_solve(const rbgs_grid *g, double *u, const double *f,
+                   int32_t max_sweeps, double rel_tol, int32_t check_every,
+                   rbgs_solve_info *info, void *workspace,
+                   size_t workspace_bytes, void *stream);
+
 /* Device-memory bandwidth probe: the copy (kind 0: b = a) and triad
  * (kind 1: a = b + s*c) kernels of the STREAM benchmark, which the paper
  * uses for the attainable memory bandwidth in its roofline (Section 3,

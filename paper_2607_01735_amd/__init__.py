@@ -10,10 +10,12 @@ from .rbgs import (  # noqa: F401
     rbgs_strerror, rbgs_sweep, rbgs_sweep_batched, rbgs_workspace_size, UNet,
     rbgs_unet_param_count, rbgs_restrict, rbgs_prolong, rbgs_solve_batched,
     rbgs_mg_solve, rbgs_mg_workspace_size, rbgs_mc9_workspace_size, rbgs_mc9_sweep,
-    rbgs_mc9_residual, rbgs_mc9_solve,
+    rbgs_mc9_residual, rbgs_mc9_solve, rbgs_rb3_workspace_size, rbgs_rb3_sweep,
+    rbgs_rb3_residual, rbgs_rb3_solve, make_grid3,
 )
 
-__all__ = ["rbgs_mc9_workspace_size", "rbgs_mc9_sweep", "rbgs_mc9_residual", "rbgs_mc9_solve",
+__all__ = ["rbgs_rb3_workspace_size", "rbgs_rb3_sweep", "rbgs_rb3_residual", "rbgs_rb3_solve",
+           "make_grid3", "rbgs_mc9_workspace_size", "rbgs_mc9_sweep", "rbgs_mc9_residual", "rbgs_mc9_solve",
            "rbgs_mg_solve", "rbgs_mg_workspace_size", "rbgs_restrict", "rbgs_prolong", "rbgs_solve_batched", "UNet", "rbgs_unet_param_count", "rbgs_sweep_batched", "BatchPlan", "rbgs_autotune_batched",
            "rbgs_batch_workspace_size", "rbgs_batch_last_error",
            "rbgs_sweep", "rbgs_residual", "rbgs_solve", "rbgs_workspace_size",

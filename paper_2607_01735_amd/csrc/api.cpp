@@ -603,6 +603,92 @@ int mc9_fetch(const Mc9Workspace& w, hipStream_t s, double* abs_norm, double* re
     return fetch_norms(v, s, abs_norm, rel_norm);
 }
 
+// ----- red-black Gauss-Seidel in 3D -----------------------------------------
+
+constexpr int kMaxN3 = 4094;  // (n+2) planes and rows must fit the grid's y and z
+
+struct Rb3Workspace {
+    int64_t pitch = 0;
+    double* u_red = nullptr;
+    double* u_black = nullptr;
+    double* f_red = nullptr;
+    double* f_black = nullptr;
+    double* partials = nullptr;
+    double* sums = nullptr;  // sum r^2, sum b^2; the graph rounds' state at +64 bytes
+    size_t total = 0;
+};
+
+bool valid_grid3(const rbgs_grid* g, std::string* why) {
+    if (!g) { *why = "grid is NULL"; return false; }
+    if (g->n < 1 || g->n > kMaxN3) { *why = "3D n must be in [1, 4094]"; return false; }
+    if (g->ld < int64_t(g->n) + 2) { *why = "ld must be >= n + 2"; return false; }
+    if (!(g->h > 0.0) || !std::isfinite(g->h)) { *why = "h must be finite and > 0"; return false; }
+    return true;
+}
+
+size_t grid3_bytes(const rbgs_grid* g) {
+    return size_t(g->n + 2) * size_t(g->n + 2) * size_t(g->ld) * sizeof(double);
+}
+
+Rb3Workspace plan_rb3(const rbgs_grid* g, char* base) {
+    Rb3Workspace w;
+    w.pitch = split_pitch(g->n, 8);
+    const size_t colour = align256(size_t(g->n + 2) * size_t(g->n + 2) * size_t(w.pitch) * 8);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return reinterpret_cast<double*>(p);
+    };
+    w.u_red = take(colour);
+    w.u_black = take(colour);
+    w.f_red = take(colour);
+    w.f_black = take(colour);
+    w.partials = take(size_t(rb3_residual_blocks(g->n)) * 2 * sizeof(double));
+    w.sums = take(256);
+    w.total = off;
+    return w;
+}
+
+int rb3_prepare(const rbgs_grid* g, const void* u, const void* f, void* ws, size_t ws_bytes,
+                Rb3Workspace* w) {
+    std::string why;
+    if (!valid_grid3(g, &why)) return fail(RBGS_EINVAL, why);
+    Rb3Workspace plan = plan_rb3(g, nullptr);
+    int rc;
+    if ((rc = check_workspace(ws, ws_bytes, plan.total))) return rc;
+    if ((rc = check_device_range(u, grid3_bytes(g), "u"))) return rc;
+    if ((rc = check_device_range(f, grid3_bytes(g), "f"))) return rc;
+    *w = plan_rb3(g, static_cast<char*>(ws));
+    return RBGS_OK;
+}
+
+int rb3_pack_both(const rbgs_grid* g, const Rb3Workspace& w, const double* u, const double* f,
+                  hipStream_t s) {
+    HIP_TRY(launch_rb3_pack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, s), "pack u");
+    HIP_TRY(launch_rb3_pack(f, g->ld, w.f_red, w.f_black, g->n, w.pitch, s), "pack f");
+    return RBGS_OK;
+}
+
+int rb3_sweeps(const rbgs_grid* g, const Rb3Workspace& w, int nsweeps, hipStream_t s,
+               const int* stop) {
+    const double h2 = g->h * g->h;
+    for (int it = 0; it < nsweeps; ++it) {
+        HIP_TRY(launch_rb3_half(w.u_red, w.u_black, w.f_red, g->n, w.pitch, h2, 0, stop, s),
+                "red half-sweep");
+        HIP_TRY(launch_rb3_half(w.u_black, w.u_red, w.f_black, g->n, w.pitch, h2, 1, stop, s),
+                "black half-sweep");
+    }
+    return RBGS_OK;
+}
+
+int rb3_residual_sums(const rbgs_grid* g, const Rb3Workspace& w, hipStream_t s) {
+    HIP_TRY(launch_rb3_residual(w.u_red, w.u_black, w.f_red, w.f_black, g->n, w.pitch,
+                                1.0 / (g->h * g->h), w.partials, w.sums, s),
+            "3D residual");
+    return RBGS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1110,6 +1196,99 @@ int rbgs_mc9_solve(const rbgs_grid* g, double* u, const double* f, int32_t max_s
         }
     }
     HIP_TRY(launch_mc9_unpack(u, g->ld, w.u, g->n, s), "unpack u");
+    HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+    rbgs_solve_info out{done, 0, rel, ab, RBGS_OK};
+    if (!std::isfinite(rel))
+        out.status = RBGS_ENONFINITE;
+    else
+        out.status = (rel_tol <= 0.0 || rel <= rel_tol) ? RBGS_OK : RBGS_ENOCONV;
+    if (info) *info = out;
+    if (out.status == RBGS_ENONFINITE) g_last_error = "residual is not finite";
+    if (out.status == RBGS_ENOCONV) g_last_error = "tolerance not reached";
+    return out.status;
+}
+
+size_t rbgs_rb3_workspace_size(const rbgs_grid* g) {
+    std::string why;
+    if (!valid_grid3(g, &why)) return 0;
+    return plan_rb3(g, nullptr).total;
+}
+
+int rbgs_rb3_sweep(const rbgs_grid* g, double* u, const double* f, int32_t nsweeps,
+                   void* workspace, size_t workspace_bytes, void* stream) {
+    if (nsweeps < 0) return fail(RBGS_EINVAL, "nsweeps must be >= 0");
+    Rb3Workspace w;
+    int rc = rb3_prepare(g, u, f, workspace, workspace_bytes, &w);
+    if (rc) return rc;
+    if (nsweeps == 0) return RBGS_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = rb3_pack_both(g, w, u, f, s))) return rc;
+    if ((rc = rb3_sweeps(g, w, nsweeps, s, nullptr))) return rc;
+    HIP_TRY(launch_rb3_unpack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, s), "unpack u");
+    return RBGS_OK;
+}
+
+int rbgs_rb3_residual(const rbgs_grid* g, const double* u, const double* f, double* abs_norm,
+                      double* rel_norm, void* workspace, size_t workspace_bytes, void* stream) {
+    Rb3Workspace w;
+    int rc = rb3_prepare(g, u, f, workspace, workspace_bytes, &w);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = rb3_pack_both(g, w, u, f, s))) return rc;
+    if ((rc = rb3_residual_sums(g, w, s))) return rc;
+    Workspace v;
+    v.sums = w.sums;
+    return fetch_norms(v, s, abs_norm, rel_norm);
+}
+
+int rbgs_rb3_solve(const rbgs_grid* g, double* u, const double* f, int32_t max_sweeps,
+                   double rel_tol, int32_t check_every, rbgs_solve_info* info, void* workspace,
+                   size_t workspace_bytes, void* stream) {
+    if (max_sweeps < 0) return fail(RBGS_EINVAL, "max_sweeps must be >= 0");
+    if (check_every < 1) return fail(RBGS_EINVAL, "check_every must be >= 1");
+    if (std::isnan(rel_tol)) return fail(RBGS_EINVAL, "rel_tol is NaN");
+    Rb3Workspace w;
+    int rc = rb3_prepare(g, u, f, workspace, workspace_bytes, &w);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = rb3_pack_both(g, w, u, f, s))) return rc;
+    Workspace v;
+    v.sums = w.sums;
+    double rel = 0.0, ab = 0.0;
+    int32_t done = 0;
+    if (rel_tol <= 0.0) {
+        if ((rc = rb3_sweeps(g, w, max_sweeps, s, nullptr))) return rc;
+        done = max_sweeps;
+        if ((rc = rb3_residual_sums(g, w, s))) return rc;
+        if ((rc = fetch_norms(v, s, &ab, &rel))) return rc;
+    } else {
+        if ((rc = rb3_residual_sums(g, w, s))) return rc;
+        if ((rc = fetch_norms(v, s, &ab, &rel))) return rc;
+        const int cap = max_sweeps / check_every;
+        if (!(rel <= rel_tol) && std::isfinite(rel) && cap > 0) {
+            RoundBody body = [&](hipStream_t cs, const int* stop, void** es) -> int {
+                *es = nullptr;
+                int r = rb3_sweeps(g, w, check_every, cs, stop);
+                return r ? r : rb3_residual_sums(g, w, cs);
+            };
+            int rounds = 0;
+            bool used = false;
+            void* es = nullptr;
+            if ((rc = solve_rounds_graph(v, body, cap, rel_tol, s, &es, &rounds, &used))) return rc;
+            if (used) {
+                done = rounds * check_every;
+                if ((rc = fetch_norms(v, s, &ab, &rel))) return rc;
+            }
+        }
+        while (!(rel <= rel_tol) && done < max_sweeps && std::isfinite(rel)) {
+            const int32_t k = max_sweeps - done < check_every ? max_sweeps - done : check_every;
+            if ((rc = rb3_sweeps(g, w, k, s, nullptr))) return rc;
+            done += k;
+            if ((rc = rb3_residual_sums(g, w, s))) return rc;
+            if ((rc = fetch_norms(v, s, &ab, &rel))) return rc;
+        }
+    }
+    HIP_TRY(launch_rb3_unpack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, s), "unpack u");
     HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
     rbgs_solve_info out{done, 0, rel, ab, RBGS_OK};
     if (!std::isfinite(rel))

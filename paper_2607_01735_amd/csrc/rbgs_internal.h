@@ -139,6 +139,22 @@ hipError_t launch_mc9_quarter(double* const u[4], double* const f[4], int n, dou
 hipError_t launch_mc9_residual(double* const u[4], double* const f[4], int n, double inv6h2,
                                double* partials, double* out, hipStream_t s);
 
+// Red-black Gauss-Seidel in 3D (7-point): split arrays with a row per (i, j)
+// pair, (n+2)^2 rows of `pitch` (split_pitch(n, 8)) doubles.  half: colour
+// `colour`'s update with h2 = h h; nothing when stop != nullptr and *stop
+// != 0.  residual: sums of r^2 and b^2 into out[0..1] through
+// rb3_residual_blocks(n) partial pairs.
+int rb3_residual_blocks(int n);
+hipError_t launch_rb3_pack(const double* nat, int64_t ld, double* red, double* black, int n,
+                           int64_t pitch, hipStream_t s);
+hipError_t launch_rb3_unpack(double* nat, int64_t ld, const double* red, const double* black,
+                             int n, int64_t pitch, hipStream_t s);
+hipError_t launch_rb3_half(double* self, const double* other, const double* f, int n,
+                           int64_t pitch, double h2, int colour, const int* stop, hipStream_t s);
+hipError_t launch_rb3_residual(const double* ur, const double* ub, const double* fr,
+                               const double* fb, int n, int64_t pitch, double inv_h2,
+                               double* partials, double* out, hipStream_t s);
+
 // Copies the Dirichlet ring (and nothing that a pass would not overwrite
 // before reading) of split grid src into dst; n + 2 rows of `pitch` elements.
 hipError_t launch_copy_ring(void* dst_red, void* dst_black, const void* src_red,

@@ -1,0 +1,243 @@
+// Red-black Gauss-Seidel in three dimensions, 7-point Laplacian (an
+// extension: the conclusion, Section 5, names higher dimensions as future
+// work).  Red points have i + j + k even.
+//
+// Layout: the 2D split layout with a row per (i, j) pair: point (i, j, k) of
+// colour C = (i + j + k) & 1 sits at C[(i (n+2) + j) pitch + (k >> 1)].  In
+// row (i, j) the points of colour C have k = 2q + p, p = (i + j + C) & 1, and
+// the neighbours of C[i][j][q] (all of the other colour O) are
+//     (i +- 1, j, k) -> O[i +- 1][j][q]      (i, j +- 1, k) -> O[i][j +- 1][q]
+//     (i, j, k + 1)  -> O[i][j][q + p]       (i, j, k - 1)  -> O[i][j][q - 1 + p]
+// so a half-sweep streams the other colour, its own f and its own colour
+// once: 24 B per grid point and sweep, as in 2D.
+//
+// The half-sweep marches each thread down kPlanes planes (2.5D streaming):
+// O[i-1][j][q], O[i][j][q] and O[i+1][j][q] stay in registers, so each step
+// loads one new element of that column; the j +- 1 rows and the other k
+// neighbour are mostly loads of the same workgroup (cache hits).
+//
+// Update (each operation rounded once, no contraction):
+//   s = ((((u[i+1] + u[i-1]) + u[j+1]) + u[j-1]) + u[k+1]) + u[k-1]
+//   u = (s - (h h) f) / 6.
+#include "rbgs_internal.h"
+
+namespace rbgs {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPlanes = 16;
+constexpr int kResidualBlocks = 2048;
+
+__global__ __launch_bounds__(kThreads) void k_rb3_pack(const double* __restrict__ nat, int64_t ld,
+                                                       double* __restrict__ red,
+                                                       double* __restrict__ black, int n,
+                                                       int64_t pitch) {
+    const int64_t q = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t j = blockIdx.y, i = blockIdx.z;
+    if (q >= pitch) return;
+    const int64_t row = i * (n + 2) + j;
+    // (i, j, 2q) has colour (i + j) & 1, (i, j, 2q + 1) the other
+    double* even_dst = ((i + j) & 1) ? black : red;
+    double* odd_dst = ((i + j) & 1) ? red : black;
+    const double* src = nat + row * ld;
+    const int64_t k0 = 2 * q, k1 = 2 * q + 1;
+    even_dst[row * pitch + q] = k0 <= n + 1 ? src[k0] : 0.0;
+    odd_dst[row * pitch + q] = k1 <= n + 1 ? src[k1] : 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_rb3_unpack(double* __restrict__ nat, int64_t ld,
+                                                         const double* __restrict__ red,
+                                                         const double* __restrict__ black, int n,
+                                                         int64_t pitch) {
+    const int64_t q = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t j = int64_t(blockIdx.y) + 1, i = int64_t(blockIdx.z) + 1;
+    if (q >= pitch) return;
+    const int64_t row = i * (n + 2) + j;
+    const double* even_src = ((i + j) & 1) ? black : red;
+    const double* odd_src = ((i + j) & 1) ? red : black;
+    double* dst = nat + row * ld;
+    const int64_t k0 = 2 * q, k1 = 2 * q + 1;
+    if (k0 >= 1 && k0 <= n) dst[k0] = even_src[row * pitch + q];
+    if (k1 >= 1 && k1 <= n) dst[k1] = odd_src[row * pitch + q];
+}
+
+// Workgroups of kQ x kJ threads (kQ columns q of kJ consecutive rows j), so
+// that most j +- 1 loads hit rows the same workgroup loads; the 1-D grid is
+// remapped so that each XCD receives a contiguous range of workgroups (rows
+// next to each other share that XCD's L2).
+constexpr int kQ = 64, kJ = 8;
+
+__global__ __launch_bounds__(kQ * kJ) void k_rb3_half(double* __restrict__ self,
+                                                      const double* __restrict__ other,
+                                                      const double* __restrict__ f, int n,
+                                                      int64_t pitch, double h2, int colour,
+                                                      int qblocks, int jblocks, const int* stop) {
+    if (stop && *stop) return;
+    const int nb = int(gridDim.x);
+    const int b = xcd_logical_block(int(blockIdx.x), nb);
+    const int bq = b % qblocks, bj = (b / qblocks) % jblocks, bz = b / (qblocks * jblocks);
+    const int64_t q = int64_t(bq) * kQ + (threadIdx.x % kQ);
+    const int64_t j = int64_t(bj) * kJ + (threadIdx.x / kQ) + 1;
+    const int64_t i0 = int64_t(bz) * kPlanes + 1;
+    if (j > n || q >= pitch || 2 * q > n) return;  // no interior point of either parity beyond
+    const int64_t i1 = i0 + kPlanes - 1 < n ? i0 + kPlanes - 1 : n;
+    const int64_t np2 = int64_t(n) + 2;
+    auto row = [&](int64_t i, int64_t jj) { return (i * np2 + jj) * pitch; };
+    double o_dn = other[row(i0 - 1, j) + q];
+    double o_c = other[row(i0, j) + q];
+    for (int64_t i = i0; i <= i1; ++i) {
+        const double o_up = other[row(i + 1, j) + q];
+        const int64_t p = (i + j + colour) & 1;
+        const int64_t k = 2 * q + p;
+        if (k >= 1 && k <= n) {
+            const int64_t r = row(i, j);
+            const double jp = other[row(i, j + 1) + q];
+            const double jm = other[row(i, j - 1) + q];
+            const double kp = p ? other[r + q + 1] : o_c;
+            const double km = p ? o_c : other[r + q - 1];
+            double s = o_up + o_dn;
+            s = s + jp;
+            s = s + jm;
+            s = s + kp;
+            s = s + km;
+            const double t = h2 * f[r + q];
+            s = s - t;
+            self[r + q] = s / 6.0;
+        }
+        o_dn = o_c;
+        o_c = o_up;
+    }
+}
+
+__device__ __forceinline__ double rb3_at(const double* red, const double* black, int64_t i,
+                                         int64_t j, int64_t k, int64_t np2, int64_t pitch) {
+    const double* a = ((i + j + k) & 1) ? black : red;
+    return a[(i * np2 + j) * pitch + (k >> 1)];
+}
+
+// Residual norms: block b takes (i, j) rows b, b + gridDim.x, ... of the
+// interior; each thread the points k = 2q and 2q + 1 of its column.
+__global__ __launch_bounds__(kThreads) void k_rb3_residual(
+    const double* __restrict__ ur, const double* __restrict__ ub, const double* __restrict__ fr,
+    const double* __restrict__ fb, int n, int64_t pitch, double inv_h2, double* partials) {
+    __shared__ double sr[kThreads], sb[kThreads];
+    double acc_r = 0.0, acc_b = 0.0;
+    const int64_t np2 = int64_t(n) + 2, n1 = int64_t(n) + 1;
+    const int64_t rows = int64_t(n) * n;
+    for (int64_t rr = blockIdx.x; rr < rows; rr += gridDim.x) {
+        const int64_t i = rr / n + 1, j = rr % n + 1;
+        for (int64_t q = threadIdx.x; q < pitch; q += kThreads) {
+            for (int e = 0; e < 2; ++e) {
+                const int64_t k = 2 * q + e;
+                if (k < 1 || k > n) continue;
+                auto at = [&](int64_t a, int64_t b, int64_t c) {
+                    return rb3_at(ur, ub, a, b, c, np2, pitch);
+                };
+                auto ring = [&](int64_t a, int64_t b, int64_t c) {
+                    return (a == 0 || b == 0 || c == 0 || a == n1 || b == n1 || c == n1)
+                               ? at(a, b, c)
+                               : 0.0;
+                };
+                double s = at(i + 1, j, k) + at(i - 1, j, k);
+                s = s + at(i, j + 1, k);
+                s = s + at(i, j - 1, k);
+                s = s + at(i, j, k + 1);
+                s = s + at(i, j, k - 1);
+                const double fc = rb3_at(fr, fb, i, j, k, np2, pitch);
+                const double lap = (s - 6.0 * at(i, j, k)) * inv_h2;
+                const double r = fc - lap;
+                double sbv = ring(i + 1, j, k) + ring(i - 1, j, k);
+                sbv = sbv + ring(i, j + 1, k);
+                sbv = sbv + ring(i, j - 1, k);
+                sbv = sbv + ring(i, j, k + 1);
+                sbv = sbv + ring(i, j, k - 1);
+                const double b = fc - sbv * inv_h2;
+                acc_r += r * r;
+                acc_b += b * b;
+            }
+        }
+    }
+    sr[threadIdx.x] = acc_r;
+    sb[threadIdx.x] = acc_b;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sr[threadIdx.x] += sr[threadIdx.x + w];
+            sb[threadIdx.x] += sb[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = sr[0];
+        partials[2 * blockIdx.x + 1] = sb[0];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_rb3_reduce(const double* __restrict__ partials,
+                                                         int count, double* __restrict__ out) {
+    __shared__ double sr[kThreads], sb[kThreads];
+    double r = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < count; k += kThreads) {
+        r += partials[2 * k];
+        b += partials[2 * k + 1];
+    }
+    sr[threadIdx.x] = r;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sr[threadIdx.x] += sr[threadIdx.x + w];
+            sb[threadIdx.x] += sb[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sr[0];
+        out[1] = sb[0];
+    }
+}
+
+}  // namespace
+
+int rb3_residual_blocks(int n) {
+    const int64_t rows = int64_t(n) * n;
+    return rows < kResidualBlocks ? int(rows) : kResidualBlocks;
+}
+
+hipError_t launch_rb3_pack(const double* nat, int64_t ld, double* red, double* black, int n,
+                           int64_t pitch, hipStream_t s) {
+    const dim3 grid(unsigned((pitch + kThreads - 1) / kThreads), unsigned(n + 2), unsigned(n + 2));
+    hipLaunchKernelGGL(k_rb3_pack, grid, dim3(kThreads), 0, s, nat, ld, red, black, n, pitch);
+    return hipGetLastError();
+}
+
+hipError_t launch_rb3_unpack(double* nat, int64_t ld, const double* red, const double* black,
+                             int n, int64_t pitch, hipStream_t s) {
+    const dim3 grid(unsigned((pitch + kThreads - 1) / kThreads), unsigned(n), unsigned(n));
+    hipLaunchKernelGGL(k_rb3_unpack, grid, dim3(kThreads), 0, s, nat, ld, red, black, n, pitch);
+    return hipGetLastError();
+}
+
+hipError_t launch_rb3_half(double* self, const double* other, const double* f, int n,
+                           int64_t pitch, double h2, int colour, const int* stop, hipStream_t s) {
+    const int64_t qs = int64_t(n) / 2 + 1;  // q = 0 .. n / 2
+    const int qblocks = int((qs + kQ - 1) / kQ), jblocks = (n + kJ - 1) / kJ;
+    const int64_t blocks = int64_t(qblocks) * jblocks * ((n + kPlanes - 1) / kPlanes);
+    hipLaunchKernelGGL(k_rb3_half, dim3(unsigned(blocks)), dim3(kQ * kJ), 0, s, self, other, f,
+                       n, pitch, h2, colour, qblocks, jblocks, stop);
+    return hipGetLastError();
+}
+
+hipError_t launch_rb3_residual(const double* ur, const double* ub, const double* fr,
+                               const double* fb, int n, int64_t pitch, double inv_h2,
+                               double* partials, double* out, hipStream_t s) {
+    const int blocks = rb3_residual_blocks(n);
+    hipLaunchKernelGGL(k_rb3_residual, dim3(blocks), dim3(kThreads), 0, s, ur, ub, fr, fb, n,
+                       pitch, inv_h2, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rb3_reduce, dim3(1), dim3(kThreads), 0, s, partials, blocks, out);
+    return hipGetLastError();
+}
+
+}  // namespace rbgs

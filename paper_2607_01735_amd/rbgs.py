@@ -102,6 +102,16 @@ _lib.rbgs_mc9_residual.restype = ctypes.c_int
 _lib.rbgs_mc9_solve.argtypes = [_P(rbgs_grid), _vp, _vp, ctypes.c_int32, ctypes.c_double,
                                 ctypes.c_int32, _P(rbgs_solve_info), _vp, ctypes.c_size_t, _vp]
 _lib.rbgs_mc9_solve.restype = ctypes.c_int
+_lib.rbgs_rb3_workspace_size.argtypes = [_P(rbgs_grid)]
+_lib.rbgs_rb3_workspace_size.restype = ctypes.c_size_t
+_lib.rbgs_rb3_sweep.argtypes = [_P(rbgs_grid), _vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+_lib.rbgs_rb3_sweep.restype = ctypes.c_int
+_lib.rbgs_rb3_residual.argtypes = [_P(rbgs_grid), _vp, _vp, _P(ctypes.c_double),
+                                   _P(ctypes.c_double), _vp, ctypes.c_size_t, _vp]
+_lib.rbgs_rb3_residual.restype = ctypes.c_int
+_lib.rbgs_rb3_solve.argtypes = [_P(rbgs_grid), _vp, _vp, ctypes.c_int32, ctypes.c_double,
+                                ctypes.c_int32, _P(rbgs_solve_info), _vp, ctypes.c_size_t, _vp]
+_lib.rbgs_rb3_solve.restype = ctypes.c_int
 _lib.rbgs_workspace_size.argtypes = [_P(rbgs_grid), ctypes.c_int, _P(rbgs_solve_opts)]
 _lib.rbgs_workspace_size.restype = ctypes.c_size_t
 _lib.rbgs_sweep.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, ctypes.c_int32,
@@ -153,7 +163,8 @@ EXPORTED = ("rbgs_workspace_size", "rbgs_sweep", "rbgs_residual", "rbgs_solve",
             "rbgs_unet_train_step", "rbgs_solve_learned", "rbgs_unet_last_error",
             "rbgs_restrict", "rbgs_prolong", "rbgs_batch_solve_workspace_size",
             "rbgs_solve_batched", "rbgs_mg_workspace_size", "rbgs_mg_solve",
-            "rbgs_mc9_workspace_size", "rbgs_mc9_sweep", "rbgs_mc9_residual", "rbgs_mc9_solve")
+            "rbgs_mc9_workspace_size", "rbgs_mc9_sweep", "rbgs_mc9_residual", "rbgs_mc9_solve",
+            "rbgs_rb3_workspace_size", "rbgs_rb3_sweep", "rbgs_rb3_residual", "rbgs_rb3_solve")
 
 
 class RbgsError(RuntimeError):
@@ -398,6 +409,66 @@ def rbgs_mc9_solve(u, f, max_sweeps, rel_tol, check_every=100, h=None, workspace
     grid, ws = _mc9_args(u, f, h, workspace)
     info = rbgs_solve_info()
     rc = _lib.rbgs_mc9_solve(ctypes.byref(grid), _vp(u.data_ptr()), _vp(f.data_ptr()),
+                             int(max_sweeps), float(rel_tol), int(check_every), ctypes.byref(info),
+                             _vp(ws.data_ptr()), ws.numel(), _stream_ptr(stream, u.device))
+    _check(rc, allow=(OK,) if raise_on_noconv else (OK, ENOCONV, ENONFINITE))
+    return {"sweeps": info.sweeps, "rel_residual": info.rel_residual,
+            "abs_residual": info.abs_residual, "status": info.status}
+
+
+def make_grid3(u, h=None):
+    """rbgs_grid for a 3-D tensor of shape (n+2, n+2, m >= n+2), contiguous
+    planes and rows (the row pitch is the last dimension's length)."""
+    if (u.dim() != 3 or u.shape[0] < 3 or u.shape[1] != u.shape[0] or u.shape[2] < u.shape[0]
+            or not u.is_contiguous()):
+        raise ValueError("expected a contiguous (n+2, n+2, m>=n+2) tensor")
+    n = u.shape[0] - 2
+    return rbgs_grid(n, u.shape[2], 1.0 / (n + 1) if h is None else float(h))
+
+
+def _rb3_args(u, f, h, workspace):
+    import torch
+    _same_layout(u, f)
+    if u.dtype != torch.float64:
+        raise RbgsError(EUNSUPPORTED, "the 3D sweep runs in FP64")
+    grid = make_grid3(u, h)
+    if workspace is None:
+        need = int(_lib.rbgs_rb3_workspace_size(ctypes.byref(grid)))
+        if need == 0:
+            raise RbgsError(EINVAL, "invalid grid")
+        workspace = torch.empty(need, dtype=torch.uint8, device=u.device)
+    return grid, workspace
+
+
+def rbgs_rb3_workspace_size(grid):
+    return int(_lib.rbgs_rb3_workspace_size(ctypes.byref(grid)))
+
+
+def rbgs_rb3_sweep(u, f, nsweeps, h=None, workspace=None, stream=None):
+    """nsweeps 3D red-black sweeps (7-point Laplacian), in place (FP64)."""
+    grid, ws = _rb3_args(u, f, h, workspace)
+    _check(_lib.rbgs_rb3_sweep(ctypes.byref(grid), _vp(u.data_ptr()), _vp(f.data_ptr()),
+                               int(nsweeps), _vp(ws.data_ptr()), ws.numel(),
+                               _stream_ptr(stream, u.device)))
+
+
+def rbgs_rb3_residual(u, f, h=None, workspace=None, stream=None):
+    """(||r||_2, ||r||_2/||b||_2) of the 3D 7-point system, on the GPU."""
+    grid, ws = _rb3_args(u, f, h, workspace)
+    a, r = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.rbgs_rb3_residual(ctypes.byref(grid), _vp(u.data_ptr()), _vp(f.data_ptr()),
+                                  ctypes.byref(a), ctypes.byref(r), _vp(ws.data_ptr()), ws.numel(),
+                                  _stream_ptr(stream, u.device)))
+    return a.value, r.value
+
+
+def rbgs_rb3_solve(u, f, max_sweeps, rel_tol, check_every=100, h=None, workspace=None,
+                   stream=None, raise_on_noconv=False):
+    """3D red-black sweeps until rel <= rel_tol; returns a dict with sweeps,
+    rel_residual, abs_residual and status."""
+    grid, ws = _rb3_args(u, f, h, workspace)
+    info = rbgs_solve_info()
+    rc = _lib.rbgs_rb3_solve(ctypes.byref(grid), _vp(u.data_ptr()), _vp(f.data_ptr()),
                              int(max_sweeps), float(rel_tol), int(check_every), ctypes.byref(info),
                              _vp(ws.data_ptr()), ws.numel(), _stream_ptr(stream, u.device))
     _check(rc, allow=(OK,) if raise_on_noconv else (OK, ENOCONV, ENONFINITE))

@@ -292,3 +292,20 @@ def test_mc9_workspace_and_validation(lib):
     bad = _grid(lib, 31, ld=30)
     assert raw.rbgs_mc9_residual(ctypes.byref(bad), None, None, None, None, None, 0,
                                  None) == lib.EINVAL
+
+
+def test_rb3_workspace_and_validation(lib):
+    g = _grid(lib, 63)
+    size = lib.rbgs_rb3_workspace_size(g)
+    assert size >= 4 * 65 * 65 * 64 * 8 and size % 256 == 0
+    assert lib.rbgs_rb3_workspace_size(lib.rbgs_grid(5000, 5002, 1e-3)) == 0
+    raw = lib._lib
+    gp = ctypes.byref(g)
+    assert raw.rbgs_rb3_sweep(gp, None, None, -1, None, 0, None) == lib.EINVAL
+    assert raw.rbgs_rb3_sweep(gp, None, None, 1, None, 0, None) == lib.EWORKSPACE
+    info = lib.rbgs_solve_info()
+    assert raw.rbgs_rb3_solve(gp, None, None, 10, 1e-8, 0, ctypes.byref(info), None, 0,
+                              None) == lib.EINVAL
+    bad = _grid(lib, 31, h=0.0)
+    assert raw.rbgs_rb3_residual(ctypes.byref(bad), None, None, None, None, None, 0,
+                                 None) == lib.EINVAL
