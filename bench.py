@@ -52,9 +52,9 @@ def kernel_source_hash(names):
 KERNEL_SOURCES = {
     "half_sweep_f64": ("sweep_plain.hip", "rbgs_internal.h"),
     "blocked_f64": ("sweep_blocked.hip", "blocked_pipeline.h", "rbgs_blocked.h", "rbgs_internal.h"),
-    "mg_restrict_f64": ("multigrid.hip", "rbgs_internal.h"),
-    "mg_prolong_add_f64": ("multigrid.hip", "rbgs_internal.h"),
-    "mc9_quarter_f64": ("multicolour9.hip", "rbgs_internal.h"),
+    "mg_restrict_f64": ("multigrid.hip",),
+    "mg_prolong_add_f64": ("multigrid.hip",),
+    "mc9_quarter_f64": ("multicolour9.hip",),
     "rb3_half_f64": ("sweep3d.hip", "rbgs_internal.h"),
 }
 
