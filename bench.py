@@ -181,17 +181,26 @@ def time_to_tolerance_fourier(torch, rb, W, n=1023, tol=1e-8):
     return out
 
 
-MG_TRANSFER_BYTES = 38.0  # per fine point: restriction 16 + 4 (coarse f, zero coarse u), prolongation 16 + 2
+MG_RESTRICT_BYTES = 20.0  # per fine point: u and f read, coarse f written, coarse u zeroed
+MG_PROLONG_RED_BYTES = 13.0  # black and red f read, red written (interpolant fused into the red half-sweep)
 
 
 def mg_model_bytes(sizes, nu1, nu2, coarse_sweeps):
     """Algorithmic HBM bytes of one V-cycle plus the finest-level residual
-    check: on each level above the coarsest, nu1 + nu2 sweeps at 24 B per
-    point and the two transfers (MG_TRANSFER_BYTES per fine point); the
-    coarsest level's sweeps; the residual reads u and f once (16 B/point)."""
+    check, as the library runs it: on each level above the coarsest, nu1 +
+    nu2 sweeps at 24 B per point, of which the first post-smoothing red half
+    (12 B) is replaced by the fused prolongation (13 B), and the restriction
+    (20 B); the coarsest level's sweeps; the residual reads u and f once
+    (16 B/point).  Levels of at most 127^2 run in one workgroup from the L2
+    and are counted the same way (they are a rounding error here)."""
     total = 0.0
     for n in sizes[:-1]:
-        total += n * n * ((nu1 + nu2) * BYTES_PER_LUP["f64"] + MG_TRANSFER_BYTES)
+        per = (nu1 + nu2) * BYTES_PER_LUP["f64"] + MG_RESTRICT_BYTES
+        if nu2 >= 1:
+            per += MG_PROLONG_RED_BYTES - BYTES_PER_LUP["f64"] / 2
+        else:
+            per += 18.0
+        total += n * n * per
     total += sizes[-1] ** 2 * coarse_sweeps * BYTES_PER_LUP["f64"]
     return total + 16.0 * sizes[0] ** 2
 
@@ -611,7 +620,7 @@ def main():
         print(json.dumps({"multicolour9": mc9}), flush=True)
         return
     if args.mg_only:
-        mg = multigrid_to_tolerance(torch, rb, W, sizes=(8191,))
+        mg = multigrid_to_tolerance(torch, rb, W, sizes=(1023, 8191))
         probe = None if args.no_probe else stream_probe(torch, rb)
         print(json.dumps({"multigrid_to_1e-8": mg, "stream_probe": probe}), flush=True)
         return

@@ -511,6 +511,23 @@ struct MgParams {
 int mg_cycle(const MgPlan& p, int l, const MgParams& mp, hipStream_t s, const int* stop,
              std::vector<void*>* states) {
     const Workspace& a = p.w[l];
+    if (p.g[l].n <= kMgCoarseN && p.levels - l <= kMgMaxCoarseLevels) {
+        // this level and all below: one workgroup, one launch
+        MgCoarseLevels lv;
+        lv.count = p.levels - l;
+        for (int k = 0; k < lv.count; ++k) {
+            const Workspace& wk = p.w[l + k];
+            const double h = p.g[l + k].h;
+            lv.level[k] = MgCoarseLevel{static_cast<double*>(wk.u_red),
+                                        static_cast<double*>(wk.u_black),
+                                        static_cast<double*>(wk.f_red),
+                                        static_cast<double*>(wk.f_black), wk.pitch, p.g[l + k].n,
+                                        h * h, 1.0 / (h * h)};
+        }
+        HIP_TRY(launch_mg_coarse_vcycle(lv, mp.nu1, mp.nu2, mp.coarse_sweeps, stop, s),
+                "multigrid coarse cycle");
+        return RBGS_OK;
+    }
     auto smooth = [&](int k) -> int {
         if (k <= 0) return RBGS_OK;
         int launches = 0;
@@ -535,6 +552,23 @@ int mg_cycle(const MgPlan& p, int l, const MgParams& mp, hipStream_t s, const in
                                p.g[l + 1].n, c.pitch, stop, s),
             "multigrid restriction");
     if ((rc = mg_cycle(p, l + 1, mp, s, stop, states))) return rc;
+    if (mp.nu2 >= 1) {
+        // the first post-smoothing sweep: interpolant fused into its red
+        // half, then its black half; the other nu2 - 1 sweeps as usual
+        const double h2 = hl * hl;
+        HIP_TRY(launch_mg_prolong_red(static_cast<double*>(a.u_red),
+                                      static_cast<const double*>(a.u_black),
+                                      static_cast<const double*>(a.f_red), a.pitch, p.g[l].n, h2,
+                                      static_cast<const double*>(c.u_red),
+                                      static_cast<const double*>(c.u_black), c.pitch, stop, s),
+                "multigrid prolongation");
+        HIP_TRY(launch_half_sweep<double>(static_cast<double*>(a.u_black),
+                                          static_cast<const double*>(a.u_red),
+                                          static_cast<const double*>(a.f_black), p.g[l].n,
+                                          a.pitch, h2, 1, 0, s, stop),
+                "black half-sweep");
+        return smooth(mp.nu2 - 1);
+    }
     HIP_TRY(launch_mg_prolong_add(static_cast<double*>(a.u_red), static_cast<double*>(a.u_black),
                                   a.pitch, p.g[l].n, static_cast<const double*>(c.u_red),
                                   static_cast<const double*>(c.u_black), c.pitch, stop, s),

@@ -176,7 +176,202 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_prolong_add(
     if (2 * q + 1 <= nf) *od = *od + v_odd;
 }
 
+// ----- prolongation fused into the first post-smoothing red half-sweep ------
+// The red half-sweep after the coarse correction overwrites every red value
+// without reading it, and the black half-sweep after it overwrites every
+// black value without reading it; so "u += P e, red half-sweep" needs the
+// corrected values of the black neighbours only, formed on the fly (black +
+// interpolant, ring values unchanged) and never stored.  The red values and,
+// after the black half-sweep, the black values are bitwise those of the
+// unfused sequence.  13 B per fine point (black and red f read, red written,
+// the coarse grid through the cache) instead of 18 + 12.
+
+__device__ __forceinline__ double prolong_value(const double* __restrict__ e_red,
+                                                const double* __restrict__ e_black,
+                                                int64_t cpitch, int64_t i, int64_t j) {
+    const int64_t I = i >> 1, J = j >> 1;
+    const double e00 = coarse_at(e_red, e_black, I, J, cpitch);
+    if ((i & 1) == 0 && (j & 1) == 0) return e00;
+    if ((i & 1) == 1 && (j & 1) == 0) return (e00 + coarse_at(e_red, e_black, I + 1, J, cpitch)) * 0.5;
+    if ((i & 1) == 0) return (e00 + coarse_at(e_red, e_black, I, J + 1, cpitch)) * 0.5;
+    const double e01 = coarse_at(e_red, e_black, I, J + 1, cpitch);
+    const double e10 = coarse_at(e_red, e_black, I + 1, J, cpitch);
+    const double e11 = coarse_at(e_red, e_black, I + 1, J + 1, cpitch);
+    return ((e00 + e01) + (e10 + e11)) * 0.25;
+}
+
+// Black point (i, j) after u += P e: interior points get the interpolant,
+// ring points keep their value.
+__device__ __forceinline__ double corrected_black(const double* __restrict__ u_black,
+                                                  int64_t pitch, int nf,
+                                                  const double* __restrict__ e_red,
+                                                  const double* __restrict__ e_black,
+                                                  int64_t cpitch, int64_t i, int64_t j) {
+    const double u = u_black[i * pitch + (j >> 1)];
+    if (i < 1 || i > nf || j < 1 || j > nf) return u;
+    return u + prolong_value(e_red, e_black, cpitch, i, j);
+}
+
+// One thread per red point (i, 2q + (i & 1)).
+__global__ __launch_bounds__(kMgThreads) void k_mg_prolong_red(
+    double* __restrict__ u_red, const double* __restrict__ u_black,
+    const double* __restrict__ f_red, int64_t pitch, int nf, double h2,
+    const double* __restrict__ e_red, const double* __restrict__ e_black, int64_t cpitch,
+    const int* stop) {
+    if (stop && *stop) return;
+    const int64_t q = int64_t(blockIdx.x) * kMgThreads + threadIdx.x;
+    const int64_t i = int64_t(blockIdx.y) + 1;
+    const int64_t p = i & 1;
+    if (q < 1 - p || q > ((int64_t(nf) - p) >> 1)) return;
+    const int64_t j = 2 * q + p;
+    const double dn = corrected_black(u_black, pitch, nf, e_red, e_black, cpitch, i + 1, j);
+    const double up = corrected_black(u_black, pitch, nf, e_red, e_black, cpitch, i - 1, j);
+    const double right = corrected_black(u_black, pitch, nf, e_red, e_black, cpitch, i, j + 1);
+    const double left = corrected_black(u_black, pitch, nf, e_red, e_black, cpitch, i, j - 1);
+    double s = dn + up;
+    s = s + right;
+    s = s + left;
+    const double t = h2 * f_red[i * pitch + q];
+    s = s - t;
+    u_red[i * pitch + q] = 0.25 * s;
+}
+
+// ----- the coarse end of the cycle in one workgroup ------------------------
+// Levels of at most kMgCoarseN points per side cost little work but two
+// launches per sweep; below that size the rest of the V-cycle (its smoothing,
+// transfers and coarsest sweeps, in the order of the level-by-level cycle)
+// runs in one workgroup of kCoarseThreads threads with a barrier between
+// phases; the arrays stay in the level workspaces (L2-resident at these
+// sizes).  Every point's arithmetic is the kernels' above, so the iterate is
+// the same bit for bit.
+
+constexpr int kCoarseThreads = 1024;
+
+__device__ __forceinline__ double split_at(const double* red, const double* black, int64_t i,
+                                           int64_t j, int64_t pitch) {
+    return (((i + j) & 1) ? black : red)[i * pitch + (j >> 1)];
+}
+
+__device__ void cw_half_sweep(const MgCoarseLevel& L, int colour) {
+    double* self = colour ? L.u_black : L.u_red;
+    const double* other = colour ? L.u_red : L.u_black;
+    const double* f = colour ? L.f_black : L.f_red;
+    const int64_t pitch = L.pitch;
+    const int W = (L.n >> 1) + 1;
+    for (int idx = threadIdx.x; idx < L.n * W; idx += kCoarseThreads) {
+        const int64_t i = idx / W + 1, q = idx % W;
+        const int64_t p = (i + colour) & 1;
+        if (q < 1 - p || q > ((int64_t(L.n) - p) >> 1)) continue;
+        const double* orow = other + i * pitch;
+        double s = other[(i + 1) * pitch + q] + other[(i - 1) * pitch + q];
+        s = s + orow[q + p];
+        s = s + orow[q - 1 + p];
+        const double t = L.h2 * f[i * pitch + q];
+        s = s - t;
+        self[i * pitch + q] = 0.25 * s;
+    }
+}
+
+__device__ __forceinline__ double cw_residual(const MgCoarseLevel& L, int64_t i, int64_t j) {
+    const int64_t pitch = L.pitch;
+    double s = split_at(L.u_red, L.u_black, i + 1, j, pitch) +
+               split_at(L.u_red, L.u_black, i - 1, j, pitch);
+    s = s + split_at(L.u_red, L.u_black, i, j + 1, pitch);
+    s = s + split_at(L.u_red, L.u_black, i, j - 1, pitch);
+    const double lap = (s - 4.0 * split_at(L.u_red, L.u_black, i, j, pitch)) * L.inv_h2;
+    return split_at(L.f_red, L.f_black, i, j, pitch) - lap;
+}
+
+__device__ void cw_restrict(const MgCoarseLevel& F, const MgCoarseLevel& C) {
+    const int nc = C.n;
+    for (int idx = threadIdx.x; idx < nc * nc; idx += kCoarseThreads) {
+        const int64_t I = idx / nc + 1, J = idx % nc + 1;
+        double row[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int64_t i = 2 * I - 1 + a;
+            row[a] = weight_row(cw_residual(F, i, 2 * J - 1), cw_residual(F, i, 2 * J),
+                                cw_residual(F, i, 2 * J + 1));
+        }
+        double* fdst = ((I + J) & 1) ? C.f_black : C.f_red;
+        double* udst = ((I + J) & 1) ? C.u_black : C.u_red;
+        fdst[I * C.pitch + (J >> 1)] = ((row[0] + 2.0 * row[1]) + row[2]) * 0.0625;
+        udst[I * C.pitch + (J >> 1)] = 0.0;
+    }
+}
+
+__device__ void cw_prolong_add(const MgCoarseLevel& C, const MgCoarseLevel& F) {
+    const int nf = F.n;
+    for (int idx = threadIdx.x; idx < nf * nf; idx += kCoarseThreads) {
+        const int64_t i = idx / nf + 1, j = idx % nf + 1;
+        const int64_t I = i >> 1, J = j >> 1;
+        const double e00 = split_at(C.u_red, C.u_black, I, J, C.pitch);
+        double v;
+        if ((i & 1) == 0 && (j & 1) == 0) {
+            v = e00;
+        } else if ((i & 1) == 1 && (j & 1) == 0) {
+            v = (e00 + split_at(C.u_red, C.u_black, I + 1, J, C.pitch)) * 0.5;
+        } else if ((i & 1) == 0) {
+            v = (e00 + split_at(C.u_red, C.u_black, I, J + 1, C.pitch)) * 0.5;
+        } else {
+            const double e01 = split_at(C.u_red, C.u_black, I, J + 1, C.pitch);
+            const double e10 = split_at(C.u_red, C.u_black, I + 1, J, C.pitch);
+            const double e11 = split_at(C.u_red, C.u_black, I + 1, J + 1, C.pitch);
+            v = ((e00 + e01) + (e10 + e11)) * 0.25;
+        }
+        double* dst = (((i + j) & 1) ? F.u_black : F.u_red) + i * F.pitch + (j >> 1);
+        *dst = *dst + v;
+    }
+}
+
+__device__ void cw_sweeps(const MgCoarseLevel& L, int count) {
+    for (int s = 0; s < count; ++s) {
+        cw_half_sweep(L, 0);
+        __syncthreads();
+        cw_half_sweep(L, 1);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse_vcycle(MgCoarseLevels lv, int nu1,
+                                                                    int nu2, int coarse_sweeps,
+                                                                    const int* stop) {
+    if (stop && *stop) return;
+    const int m = lv.count;
+    for (int l = 0; l + 1 < m; ++l) {
+        cw_sweeps(lv.level[l], nu1);
+        cw_restrict(lv.level[l], lv.level[l + 1]);
+        __syncthreads();
+    }
+    cw_sweeps(lv.level[m - 1], coarse_sweeps);
+    for (int l = m - 2; l >= 0; --l) {
+        cw_prolong_add(lv.level[l + 1], lv.level[l]);
+        __syncthreads();
+        cw_sweeps(lv.level[l], nu2);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_mg_coarse_vcycle(const MgCoarseLevels& levels, int nu1, int nu2,
+                                   int coarse_sweeps, const int* stop, hipStream_t s) {
+    if (levels.count < 1 || levels.count > kMgMaxCoarseLevels) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mg_coarse_vcycle, dim3(1), dim3(kCoarseThreads), 0, s, levels, nu1, nu2,
+                       coarse_sweeps, stop);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_prolong_red(double* u_red, const double* u_black, const double* f_red,
+                                 int64_t pitch, int nf, double h2, const double* e_red,
+                                 const double* e_black, int64_t cpitch, const int* stop,
+                                 hipStream_t s) {
+    if (nf < 3) return hipSuccess;
+    const int64_t qs = int64_t(nf) / 2 + 1;
+    const dim3 grid(unsigned((qs + kMgThreads - 1) / kMgThreads), unsigned(nf));
+    hipLaunchKernelGGL(k_mg_prolong_red, grid, dim3(kMgThreads), 0, s, u_red, u_black, f_red,
+                       pitch, nf, h2, e_red, e_black, cpitch, stop);
+    return hipGetLastError();
+}
 
 hipError_t launch_mg_restrict(const double* u_red, const double* u_black, const double* f_red,
                               const double* f_black, int64_t pitch, double inv_h2,

@@ -121,6 +121,37 @@ hipError_t launch_mg_restrict(const double* u_red, const double* u_black, const 
 hipError_t launch_mg_prolong_add(double* u_red, double* u_black, int64_t pitch, int nf,
                                  const double* e_red, const double* e_black, int64_t cpitch,
                                  const int* stop, hipStream_t s);
+// The interpolant's correction fused into the red half-sweep that follows
+// it (h2 = h * h of the fine level): red <- Gauss-Seidel with the corrected
+// black neighbours; black is left uncorrected, for a black half-sweep that
+// overwrites it next.
+hipError_t launch_mg_prolong_red(double* u_red, const double* u_black, const double* f_red,
+                                 int64_t pitch, int nf, double h2, const double* e_red,
+                                 const double* e_black, int64_t cpitch, const int* stop,
+                                 hipStream_t s);
+
+// The coarse end of a multigrid cycle in one workgroup: levels[0] (at most
+// kMgCoarseN points per side) down to the coarsest, each with its split u
+// and f arrays; pre/post smoothing counts nu1/nu2 and the coarsest level's
+// sweeps; nothing when stop != nullptr and *stop != 0.
+constexpr int kMgCoarseN = 127;
+constexpr int kMgMaxCoarseLevels = 8;
+struct MgCoarseLevel {
+    double* u_red;
+    double* u_black;
+    double* f_red;
+    double* f_black;
+    int64_t pitch;
+    int n;
+    double h2;      // h * h (the smoother's)
+    double inv_h2;  // 1 / (h * h) (the residual's)
+};
+struct MgCoarseLevels {
+    MgCoarseLevel level[kMgMaxCoarseLevels];
+    int count;
+};
+hipError_t launch_mg_coarse_vcycle(const MgCoarseLevels& levels, int nu1, int nu2,
+                                   int coarse_sweeps, const int* stop, hipStream_t s);
 
 // Four-colour 9-point Gauss-Seidel on one array per colour (colour
 // (i & 1) + 2 (j & 1), point (i, j) at [i >> 1][j >> 1]; mc9_rows(n) rows of
