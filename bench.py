@@ -53,7 +53,8 @@ KERNEL_SOURCES = {
     "half_sweep_f64": ("sweep_plain.hip", "rbgs_internal.h"),
     "blocked_f64": ("sweep_blocked.hip", "blocked_pipeline.h", "rbgs_blocked.h", "rbgs_internal.h"),
     "mg_restrict_f64": ("multigrid.hip",),
-    "mg_prolong_add_f64": ("multigrid.hip",),
+    "mg_prolong_red_f64": ("multigrid.hip",),
+    "residual_f64": ("residual.hip",),
     "mc9_quarter_f64": ("multicolour9.hip",),
     "rb3_half_f64": ("sweep3d.hip", "rbgs_internal.h"),
 }

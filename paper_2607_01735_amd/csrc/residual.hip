@@ -50,19 +50,18 @@ __device__ __forceinline__ void block_reduce_store(double r2, double b2, double*
     }
 }
 
-// Split layout: one thread = one q column of one colour, marching kRows
-// rows.  blockIdx.y = colour.  Blocks of 256 threads.
+// Split layout: one thread = one split column q (one point of each colour
+// per row), marching kRows rows with the column's red and black values of
+// rows i-1, i, i+1 in registers, so u and f are each read once (16 B per
+// point in FP64); the other in-row neighbour is the next or previous
+// column's value (a cache hit).  Per row the red point's terms are added
+// before the black point's.  Blocks of 256 threads.
 template <typename T>
 __global__ __launch_bounds__(256) void k_residual_split(
     const T* __restrict__ u_red, const T* __restrict__ u_black, const T* __restrict__ f_red,
     const T* __restrict__ f_black, int n, int64_t pitch, double inv_h2, double* partials,
     int col_blocks, float* __restrict__ r_red, float* __restrict__ r_black, int64_t r_pitch,
     int rhs_bf16) {
-    const int colour = blockIdx.y;
-    const T* self = colour ? u_black : u_red;
-    const T* other = colour ? u_red : u_black;
-    const T* fs = colour ? f_black : f_red;
-    float* r_out = colour ? r_black : r_red;
     const int strip = blockIdx.x / col_blocks;
     const int cb = blockIdx.x - strip * col_blocks;
     const int64_t q = int64_t(cb) * 256 + threadIdx.x;
@@ -70,35 +69,54 @@ __global__ __launch_bounds__(256) void k_residual_split(
     const int i1 = min(n, i0 + kRows - 1);
     double r2 = 0.0, b2 = 0.0;
     if (q <= (n >> 1)) {
+        // [colour][row i-1, i, i+1] of column q
+        double col[2][3];
+        col[0][0] = double(u_red[int64_t(i0 - 1) * pitch + q]);
+        col[1][0] = double(u_black[int64_t(i0 - 1) * pitch + q]);
+        col[0][1] = double(u_red[int64_t(i0) * pitch + q]);
+        col[1][1] = double(u_black[int64_t(i0) * pitch + q]);
         for (int i = i0; i <= i1; ++i) {
-            const int p = (i + colour) & 1;
-            const int64_t q_lo = 1 - p, q_hi = (int64_t(n) - p) >> 1;
-            if (q < q_lo || q > q_hi) continue;
-            const int64_t j = p + 2 * q;
-            const T* orow = other + int64_t(i) * pitch;
-            double dn = double(other[int64_t(i + 1) * pitch + q]);
-            double up = double(other[int64_t(i - 1) * pitch + q]);
-            double right = double(orow[q + p]);
-            double left = double(orow[q - 1 + p]);
-            double c = double(self[int64_t(i) * pitch + q]);
-            double f = double(fs[int64_t(i) * pitch + q]);
-            double s = dn + up;
-            s = s + right;
-            s = s + left;
-            double r = f - (s - 4.0 * c) * inv_h2;
-            double sbv = (i + 1 == n + 1 ? dn : 0.0) + (i - 1 == 0 ? up : 0.0);
-            sbv = sbv + (j + 1 == n + 1 ? right : 0.0);
-            sbv = sbv + (j - 1 == 0 ? left : 0.0);
-            double b = f - sbv * inv_h2;
-            r2 = r2 + r * r;
-            b2 = b2 + b * b;
-            if (r_out) {
-                float r32 = float(r);
-                r_out[int64_t(i) * r_pitch + q] = rhs_bf16 ? round_to_bf16(r32) : r32;
+            col[0][2] = double(u_red[int64_t(i + 1) * pitch + q]);
+            col[1][2] = double(u_black[int64_t(i + 1) * pitch + q]);
+#pragma unroll
+            for (int colour = 0; colour < 2; ++colour) {
+                const int p = (i + colour) & 1;
+                const int64_t q_lo = 1 - p, q_hi = (int64_t(n) - p) >> 1;
+                if (q < q_lo || q > q_hi) continue;
+                const T* other = colour ? u_red : u_black;
+                const double(&o)[3] = col[1 - colour];
+                const int64_t j = p + 2 * q;
+                const double dn = o[2];
+                const double up = o[0];
+                // in-row neighbours: other[i][q + p] and other[i][q - 1 + p]
+                const double right = p ? double(other[int64_t(i) * pitch + q + 1]) : o[1];
+                const double left = p ? o[1] : double(other[int64_t(i) * pitch + q - 1]);
+                const double c = col[colour][1];
+                const double f = double((colour ? f_black : f_red)[int64_t(i) * pitch + q]);
+                double s = dn + up;
+                s = s + right;
+                s = s + left;
+                double r = f - (s - 4.0 * c) * inv_h2;
+                double sbv = (i + 1 == n + 1 ? dn : 0.0) + (i - 1 == 0 ? up : 0.0);
+                sbv = sbv + (j + 1 == n + 1 ? right : 0.0);
+                sbv = sbv + (j - 1 == 0 ? left : 0.0);
+                double b = f - sbv * inv_h2;
+                r2 = r2 + r * r;
+                b2 = b2 + b * b;
+                float* r_out = colour ? r_black : r_red;
+                if (r_out) {
+                    float r32 = float(r);
+                    r_out[int64_t(i) * r_pitch + q] = rhs_bf16 ? round_to_bf16(r32) : r32;
+                }
+            }
+#pragma unroll
+            for (int colour = 0; colour < 2; ++colour) {
+                col[colour][0] = col[colour][1];
+                col[colour][1] = col[colour][2];
             }
         }
     }
-    block_reduce_store<256>(r2, b2, partials, blockIdx.y * gridDim.x + blockIdx.x);
+    block_reduce_store<256>(r2, b2, partials, blockIdx.x);
 }
 
 // Natural layout: one thread = one column j, marching kRows rows.
@@ -169,7 +187,7 @@ int strips(int n) { return (n + kRows - 1) / kRows; }
 
 }  // namespace
 
-int residual_partial_slots(int n, int64_t, size_t) { return 2 * split_col_blocks(n) * strips(n); }
+int residual_partial_slots(int n, int64_t, size_t) { return split_col_blocks(n) * strips(n); }
 int residual_natural_partial_slots(int n) { return natural_col_blocks(n) * strips(n); }
 
 template <typename T>
@@ -179,7 +197,7 @@ hipError_t launch_residual_split(const T* u_red, const T* u_black, const T* f_re
                                  float* r_out_black, int64_t r_pitch, int rhs_bf16,
                                  hipStream_t s) {
     const int cb = split_col_blocks(n);
-    dim3 grid(unsigned(cb * strips(n)), 2u);
+    dim3 grid(unsigned(cb * strips(n)));
     hipLaunchKernelGGL((k_residual_split<T>), grid, dim3(256), 0, s, u_red, u_black, f_red,
                        f_black, n, pitch, inv_h2, partials, cb, r_out_red, r_out_black, r_pitch,
                        rhs_bf16);
