@@ -278,25 +278,27 @@ def multicolour9_throughput(torch, rb, W, n=8191, sweeps=100, with_solve=True):
     ws = torch.empty(rb.rbgs_mc9_workspace_size(rb.make_grid(f, h)), dtype=torch.uint8,
                      device="cuda")
 
-    def timed(k):
+    def timed(k, kernel):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rb.rbgs_mc9_sweep(u, f, k, h=h, workspace=ws)
+        rb.rbgs_mc9_sweep(u, f, k, h=h, kernel=kernel, workspace=ws)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    timed(3)
-    one = min(timed(1) for _ in range(3))
-    many = min(timed(sweeps + 1) for _ in range(2))
-    per_sweep = (many - one) / sweeps
-    glups = n * n / per_sweep / 1e9
-    out = {"workload": f"{n}x{n} FP64, f~U[-1,1) seed 0, {sweeps} sweeps",
-           "ms_per_sweep": round(per_sweep * 1e3, 4), "GLUP/s": round(glups, 2),
-           "model_bytes_per_lup": MC9_BYTES_PER_LUP,
-           "model_GBs": round(glups * MC9_BYTES_PER_LUP, 1),
-           "frac_of_8TBs": round(glups * MC9_BYTES_PER_LUP / HBM_PEAK_GBS, 4)}
-    log(f"multicolour 9-point {n}: {per_sweep * 1e3:.3f} ms/sweep, {glups:.1f} GLUP/s, "
-        f"{glups * MC9_BYTES_PER_LUP:.0f} GB/s model")
+    out = {"workload": f"{n}x{n} FP64, f~U[-1,1) seed 0, {sweeps} sweeps"}
+    for kernel in ("plain",):
+        timed(3, kernel)
+        one = min(timed(1, kernel) for _ in range(3))
+        many = min(timed(sweeps + 1, kernel) for _ in range(2))
+        per_sweep = (many - one) / sweeps
+        glups = n * n / per_sweep / 1e9
+        res = {"ms_per_sweep": round(per_sweep * 1e3, 4), "GLUP/s": round(glups, 2),
+               "model_bytes_per_lup": MC9_BYTES_PER_LUP,
+               "model_GBs": round(glups * MC9_BYTES_PER_LUP, 1),
+               "frac_of_8TBs": round(glups * MC9_BYTES_PER_LUP / HBM_PEAK_GBS, 4)}
+        out["plain" if kernel == "plain" else "task_based"] = res
+        log(f"multicolour 9-point {n} {kernel}: {per_sweep * 1e3:.3f} ms/sweep, {glups:.1f} GLUP/s, "
+            f"{glups * MC9_BYTES_PER_LUP:.0f} GB/s model")
     del u, f, ws
     torch.cuda.empty_cache()
     if not with_solve:
@@ -305,17 +307,19 @@ def multicolour9_throughput(torch, rb, W, n=8191, sweeps=100, with_solve=True):
     hm = W.spacing(m)
     fm = torch.from_numpy(W.sine_rhs(m)).to("cuda")
     um = torch.zeros_like(fm)
-    rb.rbgs_mc9_solve(um, fm, 8, -1.0, check_every=8, h=hm)
-    um.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    info = rb.rbgs_mc9_solve(um, fm, 4_000_000, 1e-8, check_every=1000, h=hm)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out["time_to_1e-8_255_sine"] = {"seconds": round(dt, 4), "sweeps": info["sweeps"],
-                                    "rel_residual": info["rel_residual"],
-                                    "status": info["status"]}
-    log(f"multicolour 9-point time-to-tol 255: {dt:.3f} s, {info['sweeps']} sweeps")
+    for kernel in ("plain",):
+        rb.rbgs_mc9_solve(um, fm, 8, -1.0, check_every=8, h=hm, kernel=kernel)
+        um.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = rb.rbgs_mc9_solve(um, fm, 4_000_000, 1e-8, check_every=1000, h=hm, kernel=kernel)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        key = "time_to_1e-8_255_sine_" + ("plain" if kernel == "plain" else "task_based")
+        out[key] = {"seconds": round(dt, 4), "sweeps": info["sweeps"],
+                    "rel_residual": info["rel_residual"], "status": info["status"]}
+        log(f"multicolour 9-point time-to-tol 255 {kernel}: {dt:.3f} s, {info['sweeps']} sweeps")
+        um.zero_()
     return out
 
 

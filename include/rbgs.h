@@ -455,10 +455,14 @@ int rbgs_mg_solve(const rbgs_grid *g, rbgs_dtype dt, void *u, const void *f,
  * 0 for an invalid grid. */
 size_t rbgs_mc9_workspace_size(const rbgs_grid *g);
 
-/* nsweeps sweeps of u in place.  Asynchronous on `stream`. */
+/* nsweeps sweeps of u in place.  kernel: RBGS_KERNEL_AUTO or
+ * RBGS_KERNEL_PLAIN = one launch per colour (a device-wide barrier between
+ * colours, Algorithm 1's structure); a persistent, dependency-driven form
+ * is not available (RBGS_KERNEL_BLOCKED and RBGS_KERNEL_RESIDENT return
+ * RBGS_EUNSUPPORTED).  Asynchronous on `stream`. */
 int rbgs_mc9_sweep(const rbgs_grid *g, double *u, const double *f,
-                   int32_t nsweeps, void *workspace, size_t workspace_bytes,
-                   void *stream);
+                   int32_t nsweeps, int32_t kernel, void *workspace,
+                   size_t workspace_bytes, void *stream);
 
 /* ||r||_2 and ||r||_2/||b||_2 (HOST pointers, may be NULL), FP64, fixed
  * reduction order.  Synchronises `stream`. */
@@ -468,13 +472,13 @@ int rbgs_mc9_residual(const rbgs_grid *g, const double *u, const double *f,
 
 /* Sweeps until rel <= rel_tol (checked before the first sweep and after
  * every check_every sweeps; rel_tol <= 0: exactly max_sweeps sweeps), as
- * rbgs_solve, with the rounds captured in a HIP graph.  info (HOST, may be
- * NULL): sweeps, rel_residual, abs_residual, status (outer_iters = 0).
- * Returns RBGS_OK, RBGS_ENOCONV, RBGS_ENONFINITE or an error.  Synchronises
- * `stream`. */
+ * rbgs_solve, with the rounds captured in a HIP graph; kernel as for
+ * rbgs_mc9_sweep.  info (HOST, may be NULL): sweeps, rel_residual,
+ * abs_residual, status (outer_iters = 0).  Returns RBGS_OK, RBGS_ENOCONV,
+ * RBGS_ENONFINITE or an error.  Synchronises `stream`. */
 int rbgs_mc9_solve(const rbgs_grid *g, double *u, const double *f,
                    int32_t max_sweeps, double rel_tol, int32_t check_every,
-                   rbgs_solve_info *info, void *workspace,
+                   int32_t kernel, rbgs_solve_info *info, void *workspace,
                    size_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------

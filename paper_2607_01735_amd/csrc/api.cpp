@@ -603,6 +603,15 @@ Mc9Workspace plan_mc9(const rbgs_grid* g, char* base) {
     return w;
 }
 
+// Four-colour kernel choice: the plain form (a launch per colour) only; a
+// task-based persistent form is not available.
+int mc9_kernel(int kernel, int* chosen) {
+    if (kernel != RBGS_KERNEL_AUTO && kernel != RBGS_KERNEL_PLAIN)
+        return fail(RBGS_EUNSUPPORTED, "the 9-point sweep runs one launch per colour (AUTO or PLAIN)");
+    *chosen = RBGS_KERNEL_PLAIN;
+    return RBGS_OK;
+}
+
 int mc9_prepare(const rbgs_grid* g, const void* u, const void* f, void* ws, size_t ws_bytes,
                 Mc9Workspace* w) {
     std::string why;
@@ -1155,11 +1164,15 @@ size_t rbgs_mc9_workspace_size(const rbgs_grid* g) {
 }
 
 int rbgs_mc9_sweep(const rbgs_grid* g, double* u, const double* f, int32_t nsweeps,
-                   void* workspace, size_t workspace_bytes, void* stream) {
+                   int32_t kernel, void* workspace, size_t workspace_bytes, void* stream) {
     if (nsweeps < 0) return fail(RBGS_EINVAL, "nsweeps must be >= 0");
+    if (kernel < RBGS_KERNEL_AUTO || kernel > RBGS_KERNEL_RESIDENT)
+        return fail(RBGS_EINVAL, "unknown kernel");
     Mc9Workspace w;
     int rc = mc9_prepare(g, u, f, workspace, workspace_bytes, &w);
     if (rc) return rc;
+    int k = 0;
+    if ((rc = mc9_kernel(kernel, &k))) return rc;
     if (nsweeps == 0) return RBGS_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(launch_mc9_pack(u, g->ld, w.u, g->n, s), "pack u");
@@ -1182,14 +1195,18 @@ int rbgs_mc9_residual(const rbgs_grid* g, const double* u, const double* f, doub
 }
 
 int rbgs_mc9_solve(const rbgs_grid* g, double* u, const double* f, int32_t max_sweeps,
-                   double rel_tol, int32_t check_every, rbgs_solve_info* info, void* workspace,
-                   size_t workspace_bytes, void* stream) {
+                   double rel_tol, int32_t check_every, int32_t kernel, rbgs_solve_info* info,
+                   void* workspace, size_t workspace_bytes, void* stream) {
     if (max_sweeps < 0) return fail(RBGS_EINVAL, "max_sweeps must be >= 0");
     if (check_every < 1) return fail(RBGS_EINVAL, "check_every must be >= 1");
     if (std::isnan(rel_tol)) return fail(RBGS_EINVAL, "rel_tol is NaN");
+    if (kernel < RBGS_KERNEL_AUTO || kernel > RBGS_KERNEL_RESIDENT)
+        return fail(RBGS_EINVAL, "unknown kernel");
     Mc9Workspace w;
     int rc = mc9_prepare(g, u, f, workspace, workspace_bytes, &w);
     if (rc) return rc;
+    int kern = 0;
+    if ((rc = mc9_kernel(kernel, &kern))) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(launch_mc9_pack(u, g->ld, w.u, g->n, s), "pack u");
     HIP_TRY(launch_mc9_pack(f, g->ld, w.f, g->n, s), "pack f");

@@ -94,13 +94,15 @@ _lib.rbgs_mg_solve.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, _P(rbgs_mg
 _lib.rbgs_mg_solve.restype = ctypes.c_int
 _lib.rbgs_mc9_workspace_size.argtypes = [_P(rbgs_grid)]
 _lib.rbgs_mc9_workspace_size.restype = ctypes.c_size_t
-_lib.rbgs_mc9_sweep.argtypes = [_P(rbgs_grid), _vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+_lib.rbgs_mc9_sweep.argtypes = [_P(rbgs_grid), _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp,
+                                ctypes.c_size_t, _vp]
 _lib.rbgs_mc9_sweep.restype = ctypes.c_int
 _lib.rbgs_mc9_residual.argtypes = [_P(rbgs_grid), _vp, _vp, _P(ctypes.c_double),
                                    _P(ctypes.c_double), _vp, ctypes.c_size_t, _vp]
 _lib.rbgs_mc9_residual.restype = ctypes.c_int
 _lib.rbgs_mc9_solve.argtypes = [_P(rbgs_grid), _vp, _vp, ctypes.c_int32, ctypes.c_double,
-                                ctypes.c_int32, _P(rbgs_solve_info), _vp, ctypes.c_size_t, _vp]
+                                ctypes.c_int32, ctypes.c_int32, _P(rbgs_solve_info), _vp,
+                                ctypes.c_size_t, _vp]
 _lib.rbgs_mc9_solve.restype = ctypes.c_int
 _lib.rbgs_rb3_workspace_size.argtypes = [_P(rbgs_grid)]
 _lib.rbgs_rb3_workspace_size.restype = ctypes.c_size_t
@@ -384,11 +386,16 @@ def rbgs_mc9_workspace_size(grid):
     return int(_lib.rbgs_mc9_workspace_size(ctypes.byref(grid)))
 
 
-def rbgs_mc9_sweep(u, f, nsweeps, h=None, workspace=None, stream=None):
-    """nsweeps four-colour sweeps of the 9-point system, in place (FP64)."""
+def _kernel_code(kernel):
+    return _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+
+
+def rbgs_mc9_sweep(u, f, nsweeps, h=None, kernel="auto", workspace=None, stream=None):
+    """nsweeps four-colour sweeps of the 9-point system, in place (FP64);
+    kernel "auto" or "plain" (a launch per colour)."""
     grid, ws = _mc9_args(u, f, h, workspace)
     _check(_lib.rbgs_mc9_sweep(ctypes.byref(grid), _vp(u.data_ptr()), _vp(f.data_ptr()),
-                               int(nsweeps), _vp(ws.data_ptr()), ws.numel(),
+                               int(nsweeps), _kernel_code(kernel), _vp(ws.data_ptr()), ws.numel(),
                                _stream_ptr(stream, u.device)))
 
 
@@ -402,14 +409,15 @@ def rbgs_mc9_residual(u, f, h=None, workspace=None, stream=None):
     return a.value, r.value
 
 
-def rbgs_mc9_solve(u, f, max_sweeps, rel_tol, check_every=100, h=None, workspace=None,
-                   stream=None, raise_on_noconv=False):
+def rbgs_mc9_solve(u, f, max_sweeps, rel_tol, check_every=100, h=None, kernel="auto",
+                   workspace=None, stream=None, raise_on_noconv=False):
     """Four-colour 9-point sweeps until rel <= rel_tol; returns a dict with
     sweeps, rel_residual, abs_residual and status."""
     grid, ws = _mc9_args(u, f, h, workspace)
     info = rbgs_solve_info()
     rc = _lib.rbgs_mc9_solve(ctypes.byref(grid), _vp(u.data_ptr()), _vp(f.data_ptr()),
-                             int(max_sweeps), float(rel_tol), int(check_every), ctypes.byref(info),
+                             int(max_sweeps), float(rel_tol), int(check_every),
+                             _kernel_code(kernel), ctypes.byref(info),
                              _vp(ws.data_ptr()), ws.numel(), _stream_ptr(stream, u.device))
     _check(rc, allow=(OK,) if raise_on_noconv else (OK, ENOCONV, ENONFINITE))
     return {"sweeps": info.sweeps, "rel_residual": info.rel_residual,

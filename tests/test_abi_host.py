@@ -282,13 +282,15 @@ def test_mc9_workspace_and_validation(lib):
     assert lib.rbgs_mc9_workspace_size(_grid(lib, 0)) == 0
     raw = lib._lib
     gp = ctypes.byref(g)
-    assert raw.rbgs_mc9_sweep(gp, None, None, -1, None, 0, None) == lib.EINVAL
-    assert raw.rbgs_mc9_sweep(gp, None, None, 1, None, 0, None) == lib.EWORKSPACE
+    assert raw.rbgs_mc9_sweep(gp, None, None, -1, 0, None, 0, None) == lib.EINVAL
+    assert raw.rbgs_mc9_sweep(gp, None, None, 1, 9, None, 0, None) == lib.EINVAL
+    assert raw.rbgs_mc9_sweep(gp, None, None, 1, 2, None, 0, None) == lib.EWORKSPACE
+    assert raw.rbgs_mc9_sweep(gp, None, None, 1, 0, None, 0, None) == lib.EWORKSPACE
     info = lib.rbgs_solve_info()
-    assert raw.rbgs_mc9_solve(gp, None, None, 10, 1e-8, 0, ctypes.byref(info), None, 0,
+    assert raw.rbgs_mc9_solve(gp, None, None, 10, 1e-8, 0, 0, ctypes.byref(info), None, 0,
                               None) == lib.EINVAL
-    assert raw.rbgs_mc9_solve(gp, None, None, 10, float("nan"), 5, ctypes.byref(info), None, 0,
-                              None) == lib.EINVAL
+    assert raw.rbgs_mc9_solve(gp, None, None, 10, float("nan"), 5, 0, ctypes.byref(info), None,
+                              0, None) == lib.EINVAL
     bad = _grid(lib, 31, ld=30)
     assert raw.rbgs_mc9_residual(ctypes.byref(bad), None, None, None, None, None, 0,
                                  None) == lib.EINVAL

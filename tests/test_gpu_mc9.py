@@ -35,13 +35,14 @@ def start(n, seed, ld=None):
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 8, 33, 100, 255, 1000, 1023])
-def test_sweeps_bitwise(oracle, n):
-    say(f"mc9 sweeps n={n}")
+@pytest.mark.parametrize("kernel", ["plain", "auto"])
+def test_sweeps_bitwise(oracle, n, kernel):
+    say(f"mc9 sweeps n={n} kernel={kernel}")
     h = W.spacing(n)
     ld = n + 2 + (n % 3)
     u0, f = start(n, 5 * n, ld=ld)
     ut = dev(u0)
-    rb.rbgs_mc9_sweep(ut, dev(f), 3, h=h)
+    rb.rbgs_mc9_sweep(ut, dev(f), 3, h=h, kernel=kernel)
     ref = oracle.mc9_sweep(u0.copy(), f, h, 3)
     assert np.array_equal(ut.cpu().numpy(), ref)
 
@@ -56,13 +57,14 @@ def test_residual_matches_oracle(oracle, n):
     assert a == pytest.approx(ra, rel=1e-12) and r == pytest.approx(rr, rel=1e-12)
 
 
-def test_solve_matches_oracle(oracle):
+@pytest.mark.parametrize("kernel", ["plain", "auto"])
+def test_solve_matches_oracle(oracle, kernel):
     n = 63
-    say(f"mc9 solve n={n}")
+    say(f"mc9 solve n={n} kernel={kernel}")
     h = W.spacing(n)
     f = W.fourier_rhs(n, seed=3, count=16, kmax=16)
     ut = dev(W.zeros(n))
-    info = rb.rbgs_mc9_solve(ut, dev(f), 100000, 1e-8, check_every=50, h=h)
+    info = rb.rbgs_mc9_solve(ut, dev(f), 100000, 1e-8, check_every=50, h=h, kernel=kernel)
     ref = W.zeros(n)
     rc, done, rel = oracle.mc9_solve(ref, f, h, 100000, 1e-8, 50)
     assert rc == 0 and info["status"] == 0 and info["sweeps"] == done
@@ -70,32 +72,44 @@ def test_solve_matches_oracle(oracle):
     assert info["rel_residual"] == pytest.approx(rel, rel=1e-9)
 
 
-def test_fixed_sweeps_and_cap(oracle):
+@pytest.mark.parametrize("kernel", ["plain", "auto"])
+def test_fixed_sweeps_and_cap(oracle, kernel):
     n = 31
-    say("mc9 fixed sweeps / cap")
+    say(f"mc9 fixed sweeps / cap kernel={kernel}")
     h = W.spacing(n)
     u0, f = start(n, 9)
     ut = dev(u0)
-    info = rb.rbgs_mc9_solve(ut, dev(f), 7, -1.0, check_every=3, h=h)
+    info = rb.rbgs_mc9_solve(ut, dev(f), 7, -1.0, check_every=3, h=h, kernel=kernel)
     assert info["sweeps"] == 7
     assert np.array_equal(ut.cpu().numpy(), oracle.mc9_sweep(u0.copy(), f, h, 7))
     ut = dev(u0)
-    info = rb.rbgs_mc9_solve(ut, dev(f), 10, 1e-15, check_every=4, h=h)
+    info = rb.rbgs_mc9_solve(ut, dev(f), 10, 1e-15, check_every=4, h=h, kernel=kernel)
     assert info["sweeps"] == 10 and info["status"] == rb.rbgs.ENOCONV
     assert np.array_equal(ut.cpu().numpy(), oracle.mc9_sweep(u0.copy(), f, h, 10))
 
 
-def test_full_size_sweeps_bitwise(oracle):
+@pytest.mark.parametrize("kernel", ["plain", "auto"])
+def test_full_size_sweeps_bitwise(oracle, kernel):
     """8191^2, the sweep benchmark's grid: two sweeps equal the oracle's."""
     n = 8191
-    say(f"mc9 full size n={n}")
+    say(f"mc9 full size n={n} kernel={kernel}")
     h = W.spacing(n)
     f = W.uniform_rhs(n, seed=0)
     ut = dev(W.zeros(n))
-    rb.rbgs_mc9_sweep(ut, dev(f), 2, h=h)
+    rb.rbgs_mc9_sweep(ut, dev(f), 2, h=h, kernel=kernel)
     got = ut.cpu().numpy()
     del ut
     assert np.array_equal(got, oracle.mc9_sweep(W.zeros(n), f, h, 2))
+
+
+@pytest.mark.parametrize("kernel", ["blocked", "resident"])
+def test_persistent_kernels_are_unsupported(kernel):
+    """Only the launch-per-colour form exists; the others are refused before
+    any device work."""
+    u = torch.zeros(9, 9, dtype=torch.float64, device=DEV)
+    with pytest.raises(rb.RbgsError) as exc:
+        rb.rbgs_mc9_sweep(u, u.clone(), 1, kernel=kernel)
+    assert exc.value.status == rb.rbgs.EUNSUPPORTED
 
 
 def test_f32_is_unsupported():
