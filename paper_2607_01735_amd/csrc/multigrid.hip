@@ -186,33 +186,12 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_prolong_add(
 // unfused sequence.  13 B per fine point (black and red f read, red written,
 // the coarse grid through the cache) instead of 18 + 12.
 
-__device__ __forceinline__ double prolong_value(const double* __restrict__ e_red,
-                                                const double* __restrict__ e_black,
-                                                int64_t cpitch, int64_t i, int64_t j) {
-    const int64_t I = i >> 1, J = j >> 1;
-    const double e00 = coarse_at(e_red, e_black, I, J, cpitch);
-    if ((i & 1) == 0 && (j & 1) == 0) return e00;
-    if ((i & 1) == 1 && (j & 1) == 0) return (e00 + coarse_at(e_red, e_black, I + 1, J, cpitch)) * 0.5;
-    if ((i & 1) == 0) return (e00 + coarse_at(e_red, e_black, I, J + 1, cpitch)) * 0.5;
-    const double e01 = coarse_at(e_red, e_black, I, J + 1, cpitch);
-    const double e10 = coarse_at(e_red, e_black, I + 1, J, cpitch);
-    const double e11 = coarse_at(e_red, e_black, I + 1, J + 1, cpitch);
-    return ((e00 + e01) + (e10 + e11)) * 0.25;
-}
-
-// Black point (i, j) after u += P e: interior points get the interpolant,
-// ring points keep their value.
-__device__ __forceinline__ double corrected_black(const double* __restrict__ u_black,
-                                                  int64_t pitch, int nf,
-                                                  const double* __restrict__ e_red,
-                                                  const double* __restrict__ e_black,
-                                                  int64_t cpitch, int64_t i, int64_t j) {
-    const double u = u_black[i * pitch + (j >> 1)];
-    if (i < 1 || i > nf || j < 1 || j > nf) return u;
-    return u + prolong_value(e_red, e_black, cpitch, i, j);
-}
-
-// One thread per red point (i, 2q + (i & 1)).
+// One thread per red point (i, j), i + j even.  The interpolants of its four
+// black neighbours need five coarse values when i and j are even (the cross
+// around (I, J) = (i/2, j/2)) and four when both are odd (the block (I, J) ..
+// (I+1, J+1), I = i >> 1, J = j >> 1); each is loaded once and every
+// interpolant is formed exactly as k_mg_prolong_add forms it for that
+// point's parity.  Neighbours on the ring take no correction.
 __global__ __launch_bounds__(kMgThreads) void k_mg_prolong_red(
     double* __restrict__ u_red, const double* __restrict__ u_black,
     const double* __restrict__ f_red, int64_t pitch, int nf, double h2,
@@ -224,10 +203,38 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_prolong_red(
     const int64_t p = i & 1;
     if (q < 1 - p || q > ((int64_t(nf) - p) >> 1)) return;
     const int64_t j = 2 * q + p;
-    const double dn = corrected_black(u_black, pitch, nf, e_red, e_black, cpitch, i + 1, j);
-    const double up = corrected_black(u_black, pitch, nf, e_red, e_black, cpitch, i - 1, j);
-    const double right = corrected_black(u_black, pitch, nf, e_red, e_black, cpitch, i, j + 1);
-    const double left = corrected_black(u_black, pitch, nf, e_red, e_black, cpitch, i, j - 1);
+    const int64_t I = i >> 1, J = j >> 1;
+    // black neighbours: (i+1, j), (i-1, j), (i, j+1), (i, j-1); black (i', j')
+    // sits at u_black[i' pitch + (j' >> 1)]
+    const double b_dn = u_black[(i + 1) * pitch + (j >> 1)];
+    const double b_up = u_black[(i - 1) * pitch + (j >> 1)];
+    const double b_rt = u_black[i * pitch + ((j + 1) >> 1)];
+    const double b_lt = u_black[i * pitch + ((j - 1) >> 1)];
+    double v_dn, v_up, v_rt, v_lt;
+    if (p == 0) {  // i, j even
+        const double c = coarse_at(e_red, e_black, I, J, cpitch);
+        const double cn = coarse_at(e_red, e_black, I + 1, J, cpitch);
+        const double cs = coarse_at(e_red, e_black, I - 1, J, cpitch);
+        const double ce = coarse_at(e_red, e_black, I, J + 1, cpitch);
+        const double cw = coarse_at(e_red, e_black, I, J - 1, cpitch);
+        v_dn = (c + cn) * 0.5;   // (i+1, j): i+1 odd, j even, I' = I
+        v_up = (cs + c) * 0.5;   // (i-1, j): I' = I - 1
+        v_rt = (c + ce) * 0.5;   // (i, j+1): i even, j+1 odd, J' = J
+        v_lt = (cw + c) * 0.5;   // (i, j-1): J' = J - 1
+    } else {  // i, j odd
+        const double e00 = coarse_at(e_red, e_black, I, J, cpitch);
+        const double e01 = coarse_at(e_red, e_black, I, J + 1, cpitch);
+        const double e10 = coarse_at(e_red, e_black, I + 1, J, cpitch);
+        const double e11 = coarse_at(e_red, e_black, I + 1, J + 1, cpitch);
+        v_dn = (e10 + e11) * 0.5;  // (i+1, j): i+1 even, j odd, I' = I + 1, J' = J
+        v_up = (e00 + e01) * 0.5;  // (i-1, j): I' = I
+        v_rt = (e01 + e11) * 0.5;  // (i, j+1): i odd, j+1 even, J' = J + 1
+        v_lt = (e00 + e10) * 0.5;  // (i, j-1): J' = J
+    }
+    const double dn = i + 1 <= nf ? b_dn + v_dn : b_dn;
+    const double up = i - 1 >= 1 ? b_up + v_up : b_up;
+    const double right = j + 1 <= nf ? b_rt + v_rt : b_rt;
+    const double left = j - 1 >= 1 ? b_lt + v_lt : b_lt;
     double s = dn + up;
     s = s + right;
     s = s + left;
