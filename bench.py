@@ -131,7 +131,8 @@ def time_to_tolerance(torch, rb, W, n=255, tol=1e-8):
                                       check_every=4000)),
              ("bf16rhs_ir_resident", dict(kernel="resident", precision="bf16rhs_ir",
                                           inner_sweeps=1000, check_every=1000)),
-             ("sor_f64", dict(kernel="plain", omega=0.0, check_every=10))]
+             ("sor_f64", dict(kernel="plain", omega=0.0, check_every=10)),
+             ("sor_resident_f64", dict(kernel="resident", omega=0.0, check_every=100))]
     for name, kw in forms:
         u = torch.zeros((n + 2, n + 2), dtype=torch.float64, device="cuda")
         warm = {k: v for k, v in kw.items() if k not in ("inner_sweeps", "check_every")}

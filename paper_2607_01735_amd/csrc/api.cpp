@@ -262,8 +262,9 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
     const T* fr = static_cast<const T*>(w.f_red);
     const T* fb = static_cast<const T*>(w.f_black);
     int kernel = o ? o->kernel : RBGS_KERNEL_AUTO;
-    if (omega != 1.0) kernel = RBGS_KERNEL_PLAIN;  // SOR: the plain kernel only (checked by the caller)
     if (kernel == RBGS_KERNEL_AUTO) kernel = auto_kernel(n, sizeof(T), nsweeps);
+    // SOR: the plain and resident kernels (an explicit BLOCKED was refused by the caller)
+    if (omega != 1.0 && kernel == RBGS_KERNEL_BLOCKED) kernel = RBGS_KERNEL_PLAIN;
     *launches = 0;
     if (kernel == RBGS_KERNEL_BLOCKED) {
         BlockedParams bp = blocked_params(n, sizeof(T), o);
@@ -298,7 +299,7 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
         if (timed) HIP_TRY(hipEventRecord(pt->ev[0], s), "event record");
         HIP_TRY(resident::run<T>(ur, ub, fr, fb, n, w.pitch, h2, nsweeps, spin,
                                  o ? o->debug_delay : 0, o ? o->debug_stall_tile : 0, w.resident,
-                                 s, stop, stop != nullptr),
+                                 s, stop, stop != nullptr, T(omega)),
                 "resident sweep");
         if (timed) {
             HIP_TRY(hipEventRecord(pt->ev[1], s), "event record");
@@ -854,8 +855,8 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
             return fail(RBGS_EINVAL, "omega must be in (0, 2), or 0 for the optimum");
         if (dt != RBGS_F64 || ir)
             return fail(RBGS_EUNSUPPORTED, "SOR (omega != 1) runs in FP64 without refinement");
-        if (o->sweep.kernel != RBGS_KERNEL_AUTO && o->sweep.kernel != RBGS_KERNEL_PLAIN)
-            return fail(RBGS_EUNSUPPORTED, "SOR (omega != 1) runs on the plain kernel");
+        if (o->sweep.kernel == RBGS_KERNEL_BLOCKED)
+            return fail(RBGS_EUNSUPPORTED, "SOR (omega != 1) runs on the plain or resident kernel");
     }
     if (ir && dt != RBGS_F64)
         return fail(RBGS_EINVAL, "refinement modes need FP64 storage of u and f");

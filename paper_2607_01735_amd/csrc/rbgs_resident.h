@@ -32,6 +32,9 @@ struct Args {
     int delay;       // debug: pseudo-random stalls between epochs
     int stall_band;  // debug: band b+1 = stall_band never publishes
     const int* stop; // converged flag of a graph-captured solve (nullptr: none)
+    T omega;         // relaxation factor when sor != 0
+    int sor;         // 1: red-black SOR, u <- u + omega (g - u) (its own kernel
+                     // instance); 0: Gauss-Seidel, u <- g
 };
 
 // Bands for an n x n grid: ceil(n / kR), so every band owns between kH + 1
@@ -58,10 +61,12 @@ size_t state_bytes(int n, size_t elem_bytes);
 // state's header and flags first, with a kernel).  Fails with
 // hipErrorInvalidValue when n is above max_n<T>(), and with the cooperative
 // launch's error when the bands do not fit on the device at once.
+// omega != 1: red-black SOR (the Gauss-Seidel value g relaxes the old value,
+// difference, product and sum each rounded once).
 template <typename T>
 hipError_t run(T* u_red, T* u_black, const T* f_red, const T* f_black, int n, int64_t pitch, T h2,
                int nsweeps, int spin_limit, int delay, int stall_band, void* state, hipStream_t s,
-               const int* stop = nullptr, bool keep_error = false);
+               const int* stop = nullptr, bool keep_error = false, T omega = T(1));
 
 template <typename T>
 hipError_t launch_resident(const Args<T>& a, hipStream_t s);

@@ -98,7 +98,7 @@ __device__ __forceinline__ T load_u(const Args<T>& a, int i, int j) {
 // One half-sweep of colour C over the window (rows 1 .. W-2).  EDGE: the
 // window contains a ring row or rows outside the grid, so updates are
 // restricted to 1 <= i <= n.
-template <typename T, int C, bool EDGE>
+template <typename T, int C, bool EDGE, bool SOR>
 __device__ __forceinline__ void half_sweep(const Args<T>& a, const Band<T>& bd, T (&P)[kW],
                                            const T (&F)[kW], Lds<T>& lds) {
     // The exports read only rows of the other colour, which this half-sweep
@@ -127,7 +127,13 @@ __device__ __forceinline__ void half_sweep(const Args<T>& a, const Band<T>& bd, 
         sum = sum + left;
         const T t = a.h2 * F[w];
         sum = sum - t;
-        const T nv = T(0.25) * sum;
+        const T g = T(0.25) * sum;
+        T nv = g;
+        if constexpr (SOR) {  // red-black SOR relaxes the old value towards g
+            const T d = g - P[w];
+            const T wd = a.omega * d;
+            nv = P[w] + wd;
+        }
         if constexpr (EDGE) {
             const int i = bd.base + w + bd.s;
             P[w] = pick(i >= 1 && i <= bd.n, nv, P[w]);
@@ -137,12 +143,12 @@ __device__ __forceinline__ void half_sweep(const Args<T>& a, const Band<T>& bd, 
     }
 }
 
-template <typename T, bool EDGE>
+template <typename T, bool EDGE, bool SOR>
 __device__ __forceinline__ void epoch(const Args<T>& a, const Band<T>& bd, T (&P)[kW],
                                       const T (&F)[kW], Lds<T>& lds, int sweeps) {
     for (int k = 0; k < sweeps; ++k) {
-        half_sweep<T, 0, EDGE>(a, bd, P, F, lds);
-        half_sweep<T, 1, EDGE>(a, bd, P, F, lds);
+        half_sweep<T, 0, EDGE, SOR>(a, bd, P, F, lds);
+        half_sweep<T, 1, EDGE, SOR>(a, bd, P, F, lds);
     }
 }
 
@@ -243,14 +249,14 @@ __device__ bool wait_neighbours(const Args<T>& a, const Band<T>& bd, Lds<T>& lds
     return ok;
 }
 
-template <typename T, bool EDGE>
+template <typename T, bool EDGE, bool SOR>
 __device__ __forceinline__ void run_band(const Args<T>& a, const Band<T>& bd, T (&P)[kW],
                                          const T (&F)[kW], Lds<T>& lds) {
     int left = a.sweeps;
     int e = 0;
     while (true) {
         const int k = left < kK ? left : kK;
-        epoch<T, EDGE>(a, bd, P, F, lds, k);
+        epoch<T, EDGE, SOR>(a, bd, P, F, lds, k);
         left -= k;
         if (left == 0) break;
         if (a.delay > 0) {
@@ -278,7 +284,7 @@ __device__ __forceinline__ void run_band(const Args<T>& a, const Band<T>& bd, T 
 
 // One workgroup per band, one lane per interior column; MAXT threads at
 // most (the register budget: u and f of the window live in registers).
-template <typename T, int MAXT>
+template <typename T, int MAXT, bool SOR>
 __global__ __launch_bounds__(MAXT) void k_resident(Args<T> a) {
     // a converged graph-captured solve: every workgroup leaves before any
     // exchange (the flag was written by an earlier kernel of the stream)
@@ -329,9 +335,9 @@ __global__ __launch_bounds__(MAXT) void k_resident(Args<T> a) {
     publish(a, bd, 1);  // also makes the ring columns visible to the whole workgroup
     const bool edge = bd.base < 1 || bd.base + kW > a.n;
     if (edge)
-        run_band<T, true>(a, bd, P, F, lds);
+        run_band<T, true, SOR>(a, bd, P, F, lds);
     else
-        run_band<T, false>(a, bd, P, F, lds);
+        run_band<T, false, SOR>(a, bd, P, F, lds);
 }
 
 }  // namespace
@@ -344,8 +350,9 @@ hipError_t launch_resident(const Args<T>& a, hipStream_t s) {
     const int threads = (a.n + 63) / 64 * 64;
     if (threads > max_threads<T>()) return hipErrorInvalidValue;
     void* args[] = {const_cast<Args<T>*>(&a)};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_resident<T, max_threads<T>()>),
-                                      dim3(a.bands), dim3(threads), args, 0, s);
+    const void* kernel = a.sor ? reinterpret_cast<const void*>(&k_resident<T, max_threads<T>(), true>)
+                               : reinterpret_cast<const void*>(&k_resident<T, max_threads<T>(), false>);
+    return hipLaunchCooperativeKernel(kernel, dim3(a.bands), dim3(threads), args, 0, s);
 }
 
 template <typename T>
@@ -360,7 +367,7 @@ int max_resident_bands(int n) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(&k_resident<T, max_threads<T>()>), threads, 0) !=
+            &per_cu, reinterpret_cast<const void*>(&k_resident<T, max_threads<T>(), false>), threads, 0) !=
         hipSuccess)
         return 0;
     return per_cu * cus;
@@ -374,7 +381,7 @@ size_t state_bytes(int n, size_t elem_bytes) {
 template <typename T>
 hipError_t run(T* u_red, T* u_black, const T* f_red, const T* f_black, int n, int64_t pitch, T h2,
                int nsweeps, int spin_limit, int delay, int stall_band, void* state, hipStream_t s,
-               const int* stop, bool keep_error) {
+               const int* stop, bool keep_error, T omega) {
     if (nsweeps <= 0) return hipSuccess;
     char* base = static_cast<char*>(state);
     const int bands = bands_for(n);
@@ -403,15 +410,18 @@ hipError_t run(T* u_red, T* u_black, const T* f_red, const T* f_black, int n, in
     a.delay = delay;
     a.stall_band = stall_band;
     a.stop = stop;
+    a.omega = omega;
+    a.sor = omega != T(1) ? 1 : 0;
     return launch_resident<T>(a, s);
 }
 
 template hipError_t launch_resident<double>(const Args<double>&, hipStream_t);
 template hipError_t launch_resident<float>(const Args<float>&, hipStream_t);
 template hipError_t run<double>(double*, double*, const double*, const double*, int, int64_t,
-                                double, int, int, int, int, void*, hipStream_t, const int*, bool);
+                                double, int, int, int, int, void*, hipStream_t, const int*, bool,
+                                double);
 template hipError_t run<float>(float*, float*, const float*, const float*, int, int64_t, float,
-                               int, int, int, int, void*, hipStream_t, const int*, bool);
+                               int, int, int, int, void*, hipStream_t, const int*, bool, float);
 template int max_resident_bands<double>(int);
 template int max_resident_bands<float>(int);
 template int max_n<double>();

@@ -77,3 +77,30 @@ def test_sor_omega_zero_is_the_optimum():
     assert ia["status"] == ib["status"] == 0
     assert ia["sweeps"] == ib["sweeps"] < 2000
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("n", [1, 7, 63, 100, 255, 512])
+@pytest.mark.parametrize("omega", [0.7, 1.6])
+def test_sor_resident_kernel_bitwise(oracle, n, omega):
+    """SOR on the resident band kernel (rows in registers, redundant halo
+    epochs): the same bits as the oracle's SOR sweeps."""
+    say(f"SOR resident n={n} omega={omega}")
+    h = W.spacing(n)
+    u0, f = start(n, 7 * n + 3)
+    ut = dev(u0)
+    info = rb.rbgs_solve(ut, dev(f), 13, 0.0, check_every=13, h=h, omega=omega, kernel="resident")
+    assert info["sweeps"] == 13
+    ref = oracle.sor_sweep(u0.copy(), f, h, omega, 13)
+    assert np.array_equal(ut.cpu().numpy(), ref)
+
+
+def test_sor_resident_solve_matches_plain():
+    n = 255
+    say("SOR resident vs plain solve")
+    h = W.spacing(n)
+    f = dev(W.sine_rhs(n))
+    a, b = dev(W.zeros(n)), dev(W.zeros(n))
+    ia = rb.rbgs_solve(a, f, 20000, 1e-8, check_every=10, h=h, omega=0.0, kernel="resident")
+    ib = rb.rbgs_solve(b, f, 20000, 1e-8, check_every=10, h=h, omega=0.0, kernel="plain")
+    assert ia["status"] == ib["status"] == 0 and ia["sweeps"] == ib["sweeps"]
+    assert torch.equal(a, b)
