@@ -183,6 +183,40 @@ int rbgs_sweep(const rbgs_grid *g, rbgs_dtype dt, void *u, const void *f,
                int32_t nsweeps, const rbgs_sweep_opts *opts, void *workspace,
                size_t workspace_bytes, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Split colour layout at the boundary, for callers that keep u and f in
+ * it between calls (the paper stores the colours apart, Section 2.1):
+ * colour C of point (i, j) is (i + j) & 1 (0 = red) and the point sits at
+ * element (i * pitch + (j >> 1)) of that colour's array of n + 2 rows,
+ * pitch = rbgs_split_pitch(g, dt) = ceil((n + 2) / 2) rounded up to 256
+ * bytes.  Every sweep call otherwise packs u and f into this layout and
+ * unpacks u, one pass each.
+ * --------------------------------------------------------------------- */
+
+/* Elements per row of a colour array; 0 for invalid arguments. */
+int64_t rbgs_split_pitch(const rbgs_grid *g, rbgs_dtype dt);
+
+/* natural (n+2) x ld array -> red and black arrays (DEVICE, each (n+2) x
+ * pitch elements; entries past column n+1 are set to 0).  Asynchronous. */
+int rbgs_pack(const rbgs_grid *g, rbgs_dtype dt, const void *nat, void *red,
+              void *black, void *stream);
+
+/* red and black arrays -> the interior of the natural array (its ring is
+ * not written).  Asynchronous. */
+int rbgs_unpack(const rbgs_grid *g, rbgs_dtype dt, void *nat, const void *red,
+                const void *black, void *stream);
+
+/* nsweeps sweeps of the split iterate (u_red, u_black) in place with the
+ * split right-hand side (f_red, f_black): the same kernels and the same
+ * bits as rbgs_sweep, without its pack and unpack.  The workspace
+ * (rbgs_workspace_size) holds the persistent kernels' second buffer and
+ * state.  opts->timing must be NULL.  Synchronises `stream` when a
+ * persistent kernel ran (its error word is read), else asynchronous. */
+int rbgs_sweep_split(const rbgs_grid *g, rbgs_dtype dt, void *u_red,
+                     void *u_black, const void *f_red, const void *f_black,
+                     int32_t nsweeps, const rbgs_sweep_opts *opts,
+                     void *workspace, size_t workspace_bytes, void *stream);
+
 /* Residual of the discrete system whose Gauss-Seidel step is Eq. (1):
  *   r_ij = f_ij - (u_{i+1,j} + u_{i-1,j} + u_{i,j+1} + u_{i,j-1} - 4 u_ij)/h^2
  * over the interior, and b = r evaluated with the interior of u set to zero

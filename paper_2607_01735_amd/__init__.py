@@ -11,10 +11,12 @@ from .rbgs import (  # noqa: F401
     rbgs_unet_param_count, rbgs_restrict, rbgs_prolong, rbgs_solve_batched,
     rbgs_mg_solve, rbgs_mg_workspace_size, rbgs_mc9_workspace_size, rbgs_mc9_sweep,
     rbgs_mc9_residual, rbgs_mc9_solve, rbgs_rb3_workspace_size, rbgs_rb3_sweep,
-    rbgs_rb3_residual, rbgs_rb3_solve, make_grid3,
+    rbgs_rb3_residual, rbgs_rb3_solve, make_grid3, rbgs_split_pitch, rbgs_pack, rbgs_unpack,
+    rbgs_sweep_split,
 )
 
-__all__ = ["rbgs_rb3_workspace_size", "rbgs_rb3_sweep", "rbgs_rb3_residual", "rbgs_rb3_solve",
+__all__ = ["rbgs_split_pitch", "rbgs_pack", "rbgs_unpack", "rbgs_sweep_split",
+           "rbgs_rb3_workspace_size", "rbgs_rb3_sweep", "rbgs_rb3_residual", "rbgs_rb3_solve",
            "make_grid3", "rbgs_mc9_workspace_size", "rbgs_mc9_sweep", "rbgs_mc9_residual", "rbgs_mc9_solve",
            "rbgs_mg_solve", "rbgs_mg_workspace_size", "rbgs_restrict", "rbgs_prolong", "rbgs_solve_batched", "UNet", "rbgs_unet_param_count", "rbgs_sweep_batched", "BatchPlan", "rbgs_autotune_batched",
            "rbgs_batch_workspace_size", "rbgs_batch_last_error",

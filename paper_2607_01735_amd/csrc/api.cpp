@@ -759,6 +759,80 @@ size_t rbgs_workspace_size(const rbgs_grid* g, rbgs_dtype dt, const rbgs_solve_o
     return plan_workspace(g, dt, is_ir(opts) && dt == RBGS_F64, nullptr).total;
 }
 
+int64_t rbgs_split_pitch(const rbgs_grid* g, rbgs_dtype dt) {
+    std::string why;
+    if (!valid_grid(g, &why) || !valid_dtype(dt)) return 0;
+    return split_pitch(g->n, elem_size(dt));
+}
+
+int rbgs_pack(const rbgs_grid* g, rbgs_dtype dt, const void* nat, void* red, void* black,
+              void* stream) {
+    std::string why;
+    if (!valid_grid(g, &why)) return fail(RBGS_EINVAL, why);
+    if (!valid_dtype(dt)) return fail(RBGS_EINVAL, "unknown dtype");
+    const int64_t pitch = split_pitch(g->n, elem_size(dt));
+    const size_t colour = size_t(g->n + 2) * size_t(pitch) * elem_size(dt);
+    int rc;
+    if ((rc = check_device_range(nat, grid_bytes(g, dt), "natural array"))) return rc;
+    if ((rc = check_device_range(red, colour, "red array"))) return rc;
+    if ((rc = check_device_range(black, colour, "black array"))) return rc;
+    HIP_TRY(launch_pack(nat, g->ld, red, black, g->n, pitch, int(elem_size(dt)),
+                        static_cast<hipStream_t>(stream)),
+            "pack");
+    return RBGS_OK;
+}
+
+int rbgs_unpack(const rbgs_grid* g, rbgs_dtype dt, void* nat, const void* red, const void* black,
+                void* stream) {
+    std::string why;
+    if (!valid_grid(g, &why)) return fail(RBGS_EINVAL, why);
+    if (!valid_dtype(dt)) return fail(RBGS_EINVAL, "unknown dtype");
+    const int64_t pitch = split_pitch(g->n, elem_size(dt));
+    const size_t colour = size_t(g->n + 2) * size_t(pitch) * elem_size(dt);
+    int rc;
+    if ((rc = check_device_range(nat, grid_bytes(g, dt), "natural array"))) return rc;
+    if ((rc = check_device_range(red, colour, "red array"))) return rc;
+    if ((rc = check_device_range(black, colour, "black array"))) return rc;
+    HIP_TRY(launch_unpack(nat, g->ld, red, black, g->n, pitch, int(elem_size(dt)),
+                          static_cast<hipStream_t>(stream)),
+            "unpack");
+    return RBGS_OK;
+}
+
+int rbgs_sweep_split(const rbgs_grid* g, rbgs_dtype dt, void* u_red, void* u_black,
+                     const void* f_red, const void* f_black, int32_t nsweeps,
+                     const rbgs_sweep_opts* opts, void* workspace, size_t workspace_bytes,
+                     void* stream) {
+    std::string why;
+    if (!valid_grid(g, &why)) return fail(RBGS_EINVAL, why);
+    if (!valid_dtype(dt)) return fail(RBGS_EINVAL, "unknown dtype");
+    if (nsweeps < 0) return fail(RBGS_EINVAL, "nsweeps must be >= 0");
+    int rc = validate_sweep_opts(opts);
+    if (rc) return fail(rc, g_last_error);
+    if (opts && opts->timing) return fail(RBGS_EUNSUPPORTED, "the split-layout sweep takes no timing");
+    Workspace plan = plan_workspace(g, dt, false, nullptr);
+    if ((rc = check_workspace(workspace, workspace_bytes, plan.total))) return rc;
+    const size_t colour = size_t(g->n + 2) * size_t(plan.pitch) * elem_size(dt);
+    if ((rc = check_device_range(u_red, colour, "u_red"))) return rc;
+    if ((rc = check_device_range(u_black, colour, "u_black"))) return rc;
+    if ((rc = check_device_range(f_red, colour, "f_red"))) return rc;
+    if ((rc = check_device_range(f_black, colour, "f_black"))) return rc;
+    if (nsweeps == 0) return RBGS_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // the caller's colour arrays take the place of the packed copies; the
+    // workspace still holds the persistent kernels' second buffer and state
+    Workspace w = plan_workspace(g, dt, false, static_cast<char*>(workspace));
+    w.u_red = u_red;
+    w.u_black = u_black;
+    w.f_red = const_cast<void*>(f_red);
+    w.f_black = const_cast<void*>(f_black);
+    int launches = 0;
+    void* err_state = nullptr;
+    if ((rc = run_sweeps_dt(dt, g, w, nsweeps, opts, s, &launches, &err_state, nullptr))) return rc;
+    if (err_state) return blocked_check_error(err_state, s, &g_last_error);
+    return RBGS_OK;
+}
+
 int rbgs_sweep(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f, int32_t nsweeps,
                const rbgs_sweep_opts* opts, void* workspace, size_t workspace_bytes,
                void* stream) {

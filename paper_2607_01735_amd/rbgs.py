@@ -104,6 +104,15 @@ _lib.rbgs_mc9_solve.argtypes = [_P(rbgs_grid), _vp, _vp, ctypes.c_int32, ctypes.
                                 ctypes.c_int32, ctypes.c_int32, _P(rbgs_solve_info), _vp,
                                 ctypes.c_size_t, _vp]
 _lib.rbgs_mc9_solve.restype = ctypes.c_int
+_lib.rbgs_split_pitch.argtypes = [_P(rbgs_grid), ctypes.c_int]
+_lib.rbgs_split_pitch.restype = ctypes.c_int64
+_lib.rbgs_pack.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, _vp, _vp]
+_lib.rbgs_pack.restype = ctypes.c_int
+_lib.rbgs_unpack.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, _vp, _vp]
+_lib.rbgs_unpack.restype = ctypes.c_int
+_lib.rbgs_sweep_split.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int32,
+                                  _P(rbgs_sweep_opts), _vp, ctypes.c_size_t, _vp]
+_lib.rbgs_sweep_split.restype = ctypes.c_int
 _lib.rbgs_rb3_workspace_size.argtypes = [_P(rbgs_grid)]
 _lib.rbgs_rb3_workspace_size.restype = ctypes.c_size_t
 _lib.rbgs_rb3_sweep.argtypes = [_P(rbgs_grid), _vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
@@ -166,7 +175,8 @@ EXPORTED = ("rbgs_workspace_size", "rbgs_sweep", "rbgs_residual", "rbgs_solve",
             "rbgs_restrict", "rbgs_prolong", "rbgs_batch_solve_workspace_size",
             "rbgs_solve_batched", "rbgs_mg_workspace_size", "rbgs_mg_solve",
             "rbgs_mc9_workspace_size", "rbgs_mc9_sweep", "rbgs_mc9_residual", "rbgs_mc9_solve",
-            "rbgs_rb3_workspace_size", "rbgs_rb3_sweep", "rbgs_rb3_residual", "rbgs_rb3_solve")
+            "rbgs_rb3_workspace_size", "rbgs_rb3_sweep", "rbgs_rb3_residual", "rbgs_rb3_solve",
+            "rbgs_split_pitch", "rbgs_pack", "rbgs_unpack", "rbgs_sweep_split")
 
 
 class RbgsError(RuntimeError):
@@ -482,6 +492,45 @@ def rbgs_rb3_solve(u, f, max_sweeps, rel_tol, check_every=100, h=None, workspace
     _check(rc, allow=(OK,) if raise_on_noconv else (OK, ENOCONV, ENONFINITE))
     return {"sweeps": info.sweeps, "rel_residual": info.rel_residual,
             "abs_residual": info.abs_residual, "status": info.status}
+
+
+def rbgs_split_pitch(grid, dtype_code):
+    return int(_lib.rbgs_split_pitch(ctypes.byref(grid), dtype_code))
+
+
+def rbgs_pack(u, h=None, stream=None):
+    """Natural (n+2, ld) tensor -> (red, black) tensors of shape (n+2, pitch)."""
+    import torch
+    grid = make_grid(u, h)
+    code = _dtype_code(u)
+    pitch = rbgs_split_pitch(grid, code)
+    red = torch.empty((grid.n + 2, pitch), dtype=u.dtype, device=u.device)
+    black = torch.empty_like(red)
+    _check(_lib.rbgs_pack(ctypes.byref(grid), code, _vp(u.data_ptr()), _vp(red.data_ptr()),
+                          _vp(black.data_ptr()), _stream_ptr(stream, u.device)))
+    return red, black
+
+
+def rbgs_unpack(u, red, black, h=None, stream=None):
+    """(red, black) -> the interior of the natural tensor u, in place."""
+    grid = make_grid(u, h)
+    code = _dtype_code(u)
+    _check(_lib.rbgs_unpack(ctypes.byref(grid), code, _vp(u.data_ptr()), _vp(red.data_ptr()),
+                            _vp(black.data_ptr()), _stream_ptr(stream, u.device)))
+    return u
+
+
+def rbgs_sweep_split(n, u_red, u_black, f_red, f_black, nsweeps, h=None, kernel="auto",
+                     workspace=None, stream=None, **tuning):
+    """nsweeps sweeps of split arrays (as rbgs_pack makes them) in place."""
+    code = _dtype_code(u_red)
+    grid = rbgs_grid(int(n), int(n) + 2, 1.0 / (n + 1) if h is None else float(h))
+    ws = _workspace(grid, code, u_red.device, workspace=workspace)
+    opts = _sweep_opts(kernel=kernel, **tuning)
+    _check(_lib.rbgs_sweep_split(ctypes.byref(grid), code, _vp(u_red.data_ptr()),
+                                 _vp(u_black.data_ptr()), _vp(f_red.data_ptr()),
+                                 _vp(f_black.data_ptr()), int(nsweeps), ctypes.byref(opts),
+                                 _vp(ws.data_ptr()), ws.numel(), _stream_ptr(stream, u_red.device)))
 
 
 def rbgs_stream_probe(kind, a, b, c=None, s=3.0, stream=None):

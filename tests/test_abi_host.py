@@ -311,3 +311,24 @@ def test_rb3_workspace_and_validation(lib):
     bad = _grid(lib, 31, h=0.0)
     assert raw.rbgs_rb3_residual(ctypes.byref(bad), None, None, None, None, None, 0,
                                  None) == lib.EINVAL
+
+
+def test_split_layout_entry_points_validate(lib):
+    g = _grid(lib, 255)
+    assert lib.rbgs_split_pitch(g, lib.F64) == 160  # ceil(257 / 2) = 129 -> 5 x 32
+    assert lib.rbgs_split_pitch(g, lib.F32) == 192  # 129 -> 3 x 64
+    assert lib.rbgs_split_pitch(_grid(lib, 0), lib.F64) == 0
+    raw = lib._lib
+    gp = ctypes.byref(g)
+    assert raw.rbgs_pack(gp, 7, None, None, None, None) == lib.EINVAL
+    assert raw.rbgs_pack(ctypes.byref(_grid(lib, 31, ld=3)), 0, None, None, None, None) == lib.EINVAL
+    assert raw.rbgs_unpack(gp, 7, None, None, None, None) == lib.EINVAL
+    o = lib.rbgs_sweep_opts()
+    assert raw.rbgs_sweep_split(gp, 0, None, None, None, None, -1, ctypes.byref(o), None, 0,
+                                None) == lib.EINVAL
+    assert raw.rbgs_sweep_split(gp, 0, None, None, None, None, 3, ctypes.byref(o), None, 0,
+                                None) == lib.EWORKSPACE
+    t = lib.rbgs_timing()
+    o.timing = ctypes.pointer(t)
+    assert raw.rbgs_sweep_split(gp, 0, None, None, None, None, 3, ctypes.byref(o), None, 0,
+                                None) == lib.EUNSUPPORTED
