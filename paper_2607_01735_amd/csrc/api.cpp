@@ -233,7 +233,7 @@ struct PersistentTimer {
 // every group is followed by a synchronising residual fetch).
 struct GroupTimer {
     EventTimer t;
-    rbgs_timing acc{0.f, 0.f, 0.f, 0};
+    rbgs_timing acc{};
     hipError_t begin(hipStream_t s) { return t.mark(1, s); }
     hipError_t end(hipStream_t s) { return t.mark(2, s); }
     hipError_t collect(int launches) {
@@ -606,10 +606,9 @@ Mc9Workspace plan_mc9(const rbgs_grid* g, char* base) {
 
 // Four-colour kernel choice: the plain form (a launch per colour) only; a
 // task-based persistent form is not available.
-int mc9_kernel(int kernel, int* chosen) {
+int mc9_check_kernel(int kernel) {
     if (kernel != RBGS_KERNEL_AUTO && kernel != RBGS_KERNEL_PLAIN)
         return fail(RBGS_EUNSUPPORTED, "the 9-point sweep runs one launch per colour (AUTO or PLAIN)");
-    *chosen = RBGS_KERNEL_PLAIN;
     return RBGS_OK;
 }
 
@@ -847,7 +846,7 @@ int rbgs_sweep(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f, int32_
     if ((rc = check_device_range(u, grid_bytes(g, dt), "u"))) return rc;
     if ((rc = check_device_range(f, grid_bytes(g, dt), "f"))) return rc;
     if (nsweeps == 0) {
-        if (opts && opts->timing) *opts->timing = rbgs_timing{0.f, 0.f, 0.f, 0};
+        if (opts && opts->timing) *opts->timing = rbgs_timing{};
         return RBGS_OK;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -869,7 +868,8 @@ int rbgs_sweep(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f, int32_
     HIP_TRY(tm.mark(3, s), "event record");
     if (tm.on) {
         HIP_TRY(hipEventSynchronize(tm.ev[3]), "event synchronise");
-        rbgs_timing t{0.f, 0.f, 0.f, launches};
+        rbgs_timing t{};
+        t.sweep_launches = launches;
         HIP_TRY(hipEventElapsedTime(&t.pack_ms, tm.ev[0], tm.ev[1]), "event time");
         HIP_TRY(hipEventElapsedTime(&t.sweep_ms, tm.ev[1], tm.ev[2]), "event time");
         HIP_TRY(hipEventElapsedTime(&t.unpack_ms, tm.ev[2], tm.ev[3]), "event time");
@@ -1246,8 +1246,7 @@ int rbgs_mc9_sweep(const rbgs_grid* g, double* u, const double* f, int32_t nswee
     Mc9Workspace w;
     int rc = mc9_prepare(g, u, f, workspace, workspace_bytes, &w);
     if (rc) return rc;
-    int k = 0;
-    if ((rc = mc9_kernel(kernel, &k))) return rc;
+    if ((rc = mc9_check_kernel(kernel))) return rc;
     if (nsweeps == 0) return RBGS_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(launch_mc9_pack(u, g->ld, w.u, g->n, s), "pack u");
@@ -1280,8 +1279,7 @@ int rbgs_mc9_solve(const rbgs_grid* g, double* u, const double* f, int32_t max_s
     Mc9Workspace w;
     int rc = mc9_prepare(g, u, f, workspace, workspace_bytes, &w);
     if (rc) return rc;
-    int kern = 0;
-    if ((rc = mc9_kernel(kernel, &kern))) return rc;
+    if ((rc = mc9_check_kernel(kernel))) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(launch_mc9_pack(u, g->ld, w.u, g->n, s), "pack u");
     HIP_TRY(launch_mc9_pack(f, g->ld, w.f, g->n, s), "pack f");

@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_mc9_residual(ConstColours u, Const
     sb[threadIdx.x] = acc_b;
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
+        if (int(threadIdx.x) < w) {
             sr[threadIdx.x] += sr[threadIdx.x + w];
             sb[threadIdx.x] += sb[threadIdx.x + w];
         }
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kThreads) void k_mc9_reduce(const double* __restric
     sb[threadIdx.x] = b;
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
+        if (int(threadIdx.x) < w) {
             sr[threadIdx.x] += sr[threadIdx.x + w];
             sb[threadIdx.x] += sb[threadIdx.x + w];
         }
