@@ -23,7 +23,11 @@ namespace rbgs {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRowsPerThread = 8;
+// Colour rows one thread marches (the rows of the i-flipped colours are
+// reused from registers): measured on MI355X, two rows per thread is the
+// fastest at 8191^2 (0.489 ms per sweep against 0.540 with one row and 0.502
+// with four), one row at 255^2 (more threads for a small grid).
+inline int rows_per_thread(int n) { return n <= 1024 ? 1 : 2; }
 constexpr int kResidualBlocks = 1024;
 
 struct Colours {
@@ -68,19 +72,19 @@ __global__ __launch_bounds__(kThreads) void k_mc9_unpack(double* __restrict__ na
     }
 }
 
-// One quarter-sweep of colour (pi, pj): thread J of a strip of
-// kRowsPerThread colour rows updates points (2I + pi, 2J + pj).  The rows of
+// One quarter-sweep of colour (pi, pj): thread J of a strip of rpt colour
+// rows updates points (2I + pi, 2J + pj).  The rows of
 // the i-flipped colours it needs are I - 1 + pi and I + pi; each step loads
 // the new row I + pi of both and reuses I - 1 + pi from the last step.
 __global__ __launch_bounds__(kThreads) void k_mc9_quarter(
     double* __restrict__ self, const double* __restrict__ ns, const double* __restrict__ ew,
     const double* __restrict__ cc, const double* __restrict__ f, int n, int64_t pitch, int pi,
-    int pj, double c6, const int* stop) {
+    int pj, double c6, int rpt, const int* stop) {
     if (stop && *stop) return;
     const int64_t J = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     const int64_t j = 2 * J + pj;
     if (j < 1 || j > n) return;
-    const int64_t I0 = int64_t(blockIdx.y) * kRowsPerThread;
+    const int64_t I0 = int64_t(blockIdx.y) * rpt;
     const int64_t Jw = J - 1 + pj, Je = J + pj;  // columns of j - 1 and j + 1
     // row I0 - 1 + pi of the i-flipped colours (clamped; only read when i >= 1)
     int64_t Iu = I0 - 1 + pi;
@@ -90,7 +94,7 @@ __global__ __launch_bounds__(kThreads) void k_mc9_quarter(
         up_w = cc[Iu * pitch + Jw];
         up_e = cc[Iu * pitch + Je];
     }
-    for (int k = 0; k < kRowsPerThread; ++k) {
+    for (int k = 0; k < rpt; ++k) {
         const int64_t I = I0 + k;
         const int64_t i = 2 * I + pi;
         if (i > n) break;
@@ -244,10 +248,10 @@ hipError_t launch_mc9_quarter(double* const u[4], double* const f[4], int n, dou
     const int64_t pitch = mc9_pitch(n);
     const int rows = mc9_rows(n);
     const int pi = colour & 1, pj = (colour >> 1) & 1;
-    const dim3 grid(unsigned((pitch + kThreads - 1) / kThreads),
-                    unsigned((rows + kRowsPerThread - 1) / kRowsPerThread));
+    const int rpt = rows_per_thread(n);
+    const dim3 grid(unsigned((pitch + kThreads - 1) / kThreads), unsigned((rows + rpt - 1) / rpt));
     hipLaunchKernelGGL(k_mc9_quarter, grid, dim3(kThreads), 0, s, u[colour], u[colour ^ 1],
-                       u[colour ^ 2], u[colour ^ 3], f[colour], n, pitch, pi, pj, c6, stop);
+                       u[colour ^ 2], u[colour ^ 3], f[colour], n, pitch, pi, pj, c6, rpt, stop);
     return hipGetLastError();
 }
 
