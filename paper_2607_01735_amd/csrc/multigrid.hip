@@ -25,7 +25,7 @@ namespace rbgs {
 namespace {
 
 constexpr int kMgThreads = 256;
-constexpr int kRestrictRows = 8;  // coarse rows one thread marches down
+constexpr int kRestrictRows = 4;  // coarse rows one thread marches down
 
 // Element k of a split row, 0 outside [0, pitch): only ever used for points
 // whose values are discarded.
