@@ -13,7 +13,7 @@
 namespace rbgs {
 namespace {
 
-constexpr int kRows = 16;  // rows marched per workgroup
+constexpr int kRows = 8;  // rows marched per workgroup
 
 __device__ __forceinline__ float round_to_bf16(float x) {
     // bfloat16 keeps the top 16 bits of binary32; round to nearest, ties to
