@@ -371,10 +371,16 @@ int split_residual_dt(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w, hip
 // including the residual (sums in w.sums); the judge follows it.
 using RoundBody = std::function<int(hipStream_t, const int*, void**)>;
 
+// Rounds of more launches than this are not captured (a graph holds one
+// node per launch); the caller's launch-by-launch loop runs them instead.
+constexpr int64_t kGraphMaxLaunchesPerRound = int64_t(1) << 16;
+
 int solve_rounds_graph(const Workspace& w, const RoundBody& body_fn, int cap, double rel_tol,
-                       hipStream_t s, void** err_state, int* rounds_done, bool* used) {
+                       hipStream_t s, void** err_state, int* rounds_done, bool* used,
+                       int64_t launches_per_round) {
     *used = false;
     *rounds_done = 0;
+    if (launches_per_round > kGraphMaxLaunchesPerRound) return RBGS_OK;
     int* state = reinterpret_cast<int*>(reinterpret_cast<char*>(w.sums) + 64);  // {flag, rounds}
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
@@ -509,6 +515,18 @@ struct MgParams {
 
 // Enqueues one V-cycle from level l down; *states collects the persistent
 // kernels' state blocks whose error words must be checked.
+// Launches one V-cycle enqueues (an upper bound: the plain smoother's two
+// per sweep), for the decision to capture the cycles as a graph.
+int64_t mg_launches_per_cycle(const MgPlan& p, const MgParams& mp) {
+    int64_t total = 0;
+    for (int l = 0; l < p.levels; ++l) {
+        if (p.g[l].n <= kMgCoarseN && p.levels - l <= kMgMaxCoarseLevels) return total + 1;
+        if (l == p.levels - 1) return total + 2 * int64_t(mp.coarse_sweeps);
+        total += 2 * (int64_t(mp.nu1) + mp.nu2) + 2;
+    }
+    return total;
+}
+
 int mg_cycle(const MgPlan& p, int l, const MgParams& mp, hipStream_t s, const int* stop,
              std::vector<void*>* states) {
     const Workspace& a = p.w[l];
@@ -992,7 +1010,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
                     return r ? r : split_residual_dt(dt, g, w, cs);
                 };
                 if ((rc = solve_rounds_graph(w, body, cap, o->rel_tol, s, &err_state, &rounds,
-                                             &used)))
+                                             &used, 2 * int64_t(k) + 3)))
                     return rc;
                 if (used) {
                     done = rounds * o->check_every;
@@ -1061,7 +1079,8 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
             };
             int rounds = 0;
             bool used = false;
-            if ((rc = solve_rounds_graph(w, body, cap, o->rel_tol, s, &err_state, &rounds, &used)))
+            if ((rc = solve_rounds_graph(w, body, cap, o->rel_tol, s, &err_state, &rounds, &used,
+                                         2 * int64_t(inner) + 6)))
                 return rc;
             if (used) {
                 done = rounds * inner;
@@ -1193,7 +1212,7 @@ int rbgs_mg_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         bool used = false;
         void* es = nullptr;
         if ((rc = solve_rounds_graph(w0, body, o->max_cycles, fixed ? -1.0 : o->rel_tol, s, &es,
-                                     &rounds, &used)))
+                                     &rounds, &used, mg_launches_per_cycle(p, mp) + 3)))
             return rc;
         if (used) {
             out.graph = 1;
@@ -1305,7 +1324,9 @@ int rbgs_mc9_solve(const rbgs_grid* g, double* u, const double* f, int32_t max_s
             int rounds = 0;
             bool used = false;
             void* es = nullptr;
-            if ((rc = solve_rounds_graph(v, body, cap, rel_tol, s, &es, &rounds, &used))) return rc;
+            if ((rc = solve_rounds_graph(v, body, cap, rel_tol, s, &es, &rounds, &used,
+                                         4 * int64_t(check_every) + 3)))
+                return rc;
             if (used) {
                 done = rounds * check_every;
                 if ((rc = mc9_fetch(w, s, &ab, &rel))) return rc;
@@ -1398,7 +1419,9 @@ int rbgs_rb3_solve(const rbgs_grid* g, double* u, const double* f, int32_t max_s
             int rounds = 0;
             bool used = false;
             void* es = nullptr;
-            if ((rc = solve_rounds_graph(v, body, cap, rel_tol, s, &es, &rounds, &used))) return rc;
+            if ((rc = solve_rounds_graph(v, body, cap, rel_tol, s, &es, &rounds, &used,
+                                         2 * int64_t(check_every) + 3)))
+                return rc;
             if (used) {
                 done = rounds * check_every;
                 if ((rc = fetch_norms(v, s, &ab, &rel))) return rc;

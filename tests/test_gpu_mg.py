@@ -182,3 +182,20 @@ def test_full_size_reaches_tolerance(oracle):
     _, rel = oracle.residual(got, f, h)
     assert rel <= 1e-8 * (1 + 1e-6)
     assert rel == pytest.approx(info["rel_residual"], rel=1e-6)
+
+
+def test_large_rounds_run_uncaptured(oracle):
+    """A cycle of more launches than a graph is allowed to hold (here a
+    255^2 coarsest level with 40 000 sweeps) runs launch by launch, with the
+    same bits."""
+    n = 511
+    say(f"mg uncaptured cycle n={n}")
+    h = W.spacing(n)
+    f = W.uniform_rhs(n, seed=12)
+    ut = dev(W.zeros(n))
+    info = rb.rbgs_mg_solve(ut, dev(f), 1, -1.0, pre_sweeps=1, post_sweeps=1, max_levels=2,
+                            coarse_sweeps=40000, h=h, kernel="plain")
+    assert info["graph"] == 0 and info["cycles"] == 1 and info["coarsest_n"] == 255
+    ref = W.zeros(n)
+    oracle.mg_solve(ref, f, h, 1, 1, 1, -1.0, max_levels=2, coarse_sweeps=40000)
+    assert np.array_equal(ut.cpu().numpy(), ref)

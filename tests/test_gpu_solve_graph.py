@@ -112,3 +112,19 @@ def test_graph_refinement_equals_host_loop(oracle, kernel, precision):
     rc, outer, rel = oracle.ir_solve(ref, f, h, inner, 40, tol, rhs_bf16=precision == "bf16rhs_ir")
     assert rc == 0 and outer == a["outer_iters"]
     assert np.array_equal(a_u.cpu().numpy(), ref)
+
+
+def test_oversized_round_runs_uncaptured(oracle):
+    """check_every = 40 000 plain sweeps is more launches than one captured
+    round may hold: the solve runs them launch by launch, same bits."""
+    import workloads as W
+    n = 31
+    h = W.spacing(n)
+    f = W.uniform_rhs(n, seed=4)
+    ut = torch.from_numpy(W.zeros(n)).to("cuda")
+    info = rb.rbgs_solve(ut, torch.from_numpy(f).to("cuda"), 40000, 1e-30, check_every=40000,
+                         h=h, kernel="plain")
+    assert info["sweeps"] == 40000
+    ref = W.zeros(n)
+    oracle.solve(ref, f, h, 40000, 1e-30, 40000)
+    assert np.array_equal(ut.cpu().numpy(), ref)
