@@ -235,9 +235,14 @@ int rbgs_residual(const rbgs_grid *g, rbgs_dtype dt, const void *u,
  * RBGS_PREC_F64: plain sweeps in dt.  IR modes (dt must be RBGS_F64): each
  * outer step computes r = f - A_h u in FP64, stops if rel <= rel_tol, rounds
  * r to FP32 (or bfloat16), runs inner_sweeps FP32 sweeps of A_h e = r from
- * e = 0 with a zero ring, and adds e to u in FP64.  info (HOST, may be NULL)
- * receives the statistics.  Returns RBGS_OK, RBGS_ENOCONV (u holds the last
- * iterate), RBGS_ENONFINITE, or an error.  Synchronises `stream`. */
+ * e = 0 with a zero ring, and adds e to u in FP64.  The whole rounds (sweeps
+ * or an outer step, the residual, a device-side convergence test) run as
+ * replays of a captured HIP graph, four per host poll; rounds of more than
+ * 65536 launches, the sweeps after the last whole round and calls with
+ * timing requested run launch by launch instead (same results).  info
+ * (HOST, may be NULL) receives the statistics.  Returns RBGS_OK,
+ * RBGS_ENOCONV (u holds the last iterate), RBGS_ENONFINITE, or an error.
+ * Synchronises `stream`. */
 int rbgs_solve(const rbgs_grid *g, rbgs_dtype dt, void *u, const void *f,
                const rbgs_solve_opts *opts, rbgs_solve_info *info,
                void *workspace, size_t workspace_bytes, void *stream);
@@ -462,7 +467,9 @@ size_t rbgs_mg_workspace_size(const rbgs_grid *g, rbgs_dtype dt,
  * Dirichlet data and is not written.  dt must be RBGS_F64 (else
  * RBGS_EUNSUPPORTED).  The cycles run as replays of a captured HIP graph
  * (cycle, residual and a device-side convergence test), with a launch-by-
- * launch fallback.  info (HOST, may be NULL) receives the statistics.
+ * launch fallback (also taken when a cycle has more than 65536 launches,
+ * e.g. tens of thousands of sweeps on a large coarsest level; info->graph
+ * says which ran).  info (HOST, may be NULL) receives the statistics.
  * Returns RBGS_OK, RBGS_ENOCONV (u holds the last iterate), RBGS_ENONFINITE,
  * RBGS_ETIMEOUT (a persistent smoother's bounded wait expired) or an error.
  * Synchronises `stream`. */
