@@ -80,6 +80,29 @@ def read_traffic(kernel_name, n):
         return None
 
 
+def read_profile_avg(kernel_name, n):
+    """Average launch duration (us) of a kernel in the committed rocprofv3
+    kernel-trace summary of this workload, if that summary was taken on the
+    current kernel source; else None.  Summary lines read
+    `stat: <kernel_name> avg_us=<v> calls=<c> sha=<source hash>`."""
+    path = os.path.join(PROFILE_DIR, f"sweep_f64_n{n}_stats.md")
+    if not os.path.exists(path):
+        return None
+    want = kernel_source_hash(KERNEL_SOURCES[kernel_name])
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) >= 3 and parts[0] == "stat:" and parts[1] == kernel_name:
+                kv = dict(p.split("=", 1) for p in parts[2:] if "=" in p)
+                if kv.get("sha") != want:
+                    return None
+                try:
+                    return {"avg_us": float(kv["avg_us"]), "calls": int(kv["calls"])}
+                except (KeyError, ValueError):
+                    return None
+    return None
+
+
 def stream_probe(torch, rb, gib=2.0):
     n = int(gib * (1 << 30) / 8) // 2 * 2
     a = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -555,10 +578,45 @@ def batched_throughput(torch, rb, W, count=512, sweeps=100):
     return out
 
 
-def cpu_baseline(n, sweeps_cap, budget_s=12.0):
-    """The oracle (plain C, OpenMP over rows of one colour) on the host cores:
-    whole sweeps of the same 8191^2 FP64 problem until about budget_s
-    seconds have passed."""
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_SINGLE_CORE = """
+import sys, time
+sys.path.insert(0, {root!r})
+import oracle, workloads as W
+n, k, reps = {n}, {k}, {reps}
+h = W.spacing(n)
+f = W.uniform_rhs(n, seed=0)
+u = W.zeros(n)
+oracle.sweep(u, f, h, 1)
+ts = []
+for _ in range(reps):
+    t0 = time.perf_counter()
+    oracle.sweep(u, f, h, k)
+    ts.append(time.perf_counter() - t0)
+print(oracle.threads(), *ts)
+"""
+
+
+def cpu_baseline(n, sweeps, runs=10, single_sweeps=8, single_runs=3):
+    """The oracle (plain C, OpenMP over rows of one colour) on the host
+    cores, timed as the paper times its runs (Section 3: median of 10 runs
+    on all cores): `runs` whole runs of `sweeps` sweeps of the same FP64
+    problem after one warm-up sweep, median with min and max; beside it one
+    core (a child process with OMP_NUM_THREADS=1; the GPU is not touched
+    there) on `single_sweeps` sweeps, best and median of `single_runs`."""
+    import statistics
+    import subprocess
+
     import numpy as np
 
     import oracle
@@ -567,18 +625,42 @@ def cpu_baseline(n, sweeps_cap, budget_s=12.0):
     f = W.uniform_rhs(n, seed=0)
     u = W.zeros(n)
     oracle.sweep(u, f, h, 1)  # warm-up (page faults, thread start)
-    done, t0 = 0, time.perf_counter()
-    while done < sweeps_cap:
-        oracle.sweep(u, f, h, 1)
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(n * n * done / dt / 1e9, 3), "unit": "GLUP/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{done} full sweeps of the {n}x{n} FP64 workload (of {sweeps_cap}), "
-                      f"{dt:.1f} s wall, OpenMP threads={cores}"}
+    times = []
+    for _ in range(runs):
+        u[...] = 0.0
+        t0 = time.perf_counter()
+        oracle.sweep(u, f, h, sweeps)
+        times.append(time.perf_counter() - t0)
+    threads = oracle.threads()
+    med = statistics.median(times)
+    lups = float(n) * n * sweeps
+    out = {"value": round(lups / med / 1e9, 3), "unit": "GLUP/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{runs} runs of {sweeps} full sweeps of the {n}x{n} FP64 workload from u=0 "
+                     f"(median; one warm-up sweep first), OpenMP threads={threads}",
+           "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count(),
+           "omp_env": {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OMP_PROC_BIND",
+                                                      "OMP_PLACES")},
+           "run_seconds": {"median": round(med, 4), "min": round(min(times), 4),
+                           "max": round(max(times), 4)},
+           "glups_min_max": [round(lups / max(times) / 1e9, 3), round(lups / min(times) / 1e9, 3)]}
+    del u, f
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = _SINGLE_CORE.format(root=ROOT, n=n, k=single_sweeps, reps=single_runs)
+    try:
+        res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                             text=True, timeout=600)
+        vals = res.stdout.split()
+        t1 = [float(v) for v in vals[1:]]
+        one = float(n) * n * single_sweeps
+        out["single_core"] = {"threads": int(vals[0]), "sweeps": single_sweeps,
+                              "glups_best": round(one / min(t1) / 1e9, 4),
+                              "glups_median": round(one / statistics.median(t1) / 1e9, 4),
+                              "runs": single_runs}
+    except (subprocess.SubprocessError, ValueError, IndexError) as exc:
+        out["single_core"] = {"error": str(exc)[:200]}
+    assert np is not None
+    return out
 
 
 def main():
@@ -683,12 +765,31 @@ def main():
         per_launch_bytes = BYTES_PER_LUP["f64"] * n * n / 2.0
         bytes_per_lup = BYTES_PER_LUP["f64"]
         kname, traffic_key = "k_half_sweep<double,2>", "half_sweep_f64"
+    # achieved: algorithmic bytes of one launch (the 3w-per-point-per-pass
+    # model) over the launch's average duration from HIP events on its own
+    # stream; beside it the same bytes over the rocprofv3 average of the
+    # committed profile, and the counter-measured HBM bytes (FETCH_SIZE +
+    # WRITE_SIZE, calibrated on a copy) over the HIP-event duration
     achieved = per_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
+    traffic = read_traffic(traffic_key, n)
+    prof = read_profile_avg(traffic_key, n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": read_traffic(traffic_key, n), "kernel": kname,
+                "traffic": traffic, "kernel": kname,
                 "avg_launch_us": round(avg_launch_ms * 1e3, 2),
-                "bytes_per_launch": per_launch_bytes}
+                "avg_launch_source": "HIP events recorded on the launch stream, timed steps only",
+                "launches_timed": acc["persistent_launches"] if kernel_used == "blocked"
+                else acc["sweep_launches"],
+                "bytes_per_launch": per_launch_bytes,
+                "bytes_model": "24 B per grid point per pass (FP64: other colour and f read, "
+                               "own colour written; split layout)",
+                "rocprof_avg_launch_us": prof["avg_us"] if prof else None,
+                "rocprof_calls": prof["calls"] if prof else None,
+                "frac_rocprof": round(per_launch_bytes / (prof["avg_us"] * 1e-6) / 1e9 /
+                                      HBM_PEAK_GBS, 4) if prof else None,
+                "achieved_counter_GBs": round(traffic / (avg_launch_ms * 1e-3) / 1e9, 1)
+                if traffic else None,
+                "effective_GBs_24B_per_LUP": round(glups * BYTES_PER_LUP["f64"], 1)}
     plain = None
     if kernel_used != "plain" and not args.no_plain:
         p_ms, p_glups, p_acc = run_steps("plain", 1, max(2, args.steps // 3))
@@ -731,6 +832,9 @@ def main():
         "config": {"workload": f"{n}x{n} interior FP64, h=1/{n + 1}, zero Dirichlet, "
                                f"f~U[-1,1) seed 0, u0=0, {sweeps} sweeps per step",
                    "n": n, "sweeps": sweeps, "kernel": kernel_used, "fuse": fuse},
+        # whole step: algorithmic bytes (24 B per point per pass) per second;
+        # effective bandwidth at 24 B/LUP (what a one-pass-per-sweep kernel
+        # would need for the same GLUP/s) is in the roofline object
         "hbm_gbs_algorithmic": round(glups * bytes_per_lup, 1),
         "bytes_per_lup_algorithmic": bytes_per_lup,
         "roofline": roofline,

@@ -121,7 +121,7 @@ typedef struct {
     int32_t fuse;       /* BLOCKED: most sweeps per pass (1..10), 0 = default;
                            nsweeps runs as ceil(nsweeps / fuse) passes whose
                            depths differ by at most one                      */
-    int32_t tile_rows;  /* BLOCKED: interior rows per tile, 0 = default        */
+    int32_t tile_rows;  /* BLOCKED: interior rows per tile, 8..65536, 0 = default */
     int32_t tile_cols;  /* BLOCKED: interior columns per tile, 0 = default     */
     int32_t rows_per_block; /* PLAIN: rows each workgroup marches, 0 = default */
     int32_t debug_delay;    /* BLOCKED: >0 injects pseudo-random per-tile delays
@@ -375,9 +375,11 @@ int rbgs_unet_train_step(rbgs_unet *net, int32_t batch, const double *f,
  * u (same Dirichlet ring) are both given compare_after sweeps (0: none);
  * the guess replaces the start only if its relative residual is then lower
  * (the plain start is both fallback and judge), and rbgs_solve continues
- * for the remaining max_sweeps - compare_after sweeps; info->sweeps counts
- * the comparison sweeps of the kept path.  *used_guess and *rel_start
- * (HOST, may be NULL) report the choice.  Needs ld = n + 2. */
+ * for the remaining max_sweeps - compare_after sweeps (max_sweeps bounds the
+ * sweeps applied to the returned iterate).  info->sweeps counts every sweep
+ * run: 2 * compare_after comparison sweeps (both starts) plus the solve's.
+ * *used_guess and *rel_start (HOST, may be NULL) report the choice.  Needs
+ * ld = n + 2. */
 int rbgs_solve_learned(rbgs_unet *net, const rbgs_grid *g, double *u,
                        const double *f, const rbgs_solve_opts *opts,
                        int32_t compare_after, rbgs_solve_info *info,

@@ -71,6 +71,8 @@ def _load(path=None):
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = _i32
+    lib.rbgs_ref_threads.argtypes = []
+    lib.rbgs_ref_threads.restype = _i32
     lib.rbgs_ref_round_bf16.argtypes = [ctypes.c_float]
     lib.rbgs_ref_round_bf16.restype = ctypes.c_float
     if path is None:
@@ -373,6 +375,11 @@ def rb3_solve(u, f, h, max_sweeps, rel_tol, check_every):
                                                check_every, ctypes.byref(done),
                                                ctypes.byref(rel)), "rb3_solve")
     return rc, done.value, rel.value
+
+
+def threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().rbgs_ref_threads())
 
 
 def round_bf16(x):

@@ -38,6 +38,9 @@
  * in IEEE binary32; they exist to check the FP32 forms of the GPU sweep.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -315,6 +318,17 @@ int rbgs_ref_sor_solve_f64(int32_t n, int64_t ld, double h, double omega, double
     if (sweeps_done) *sweeps_done = done;
     if (rel_out) *rel_out = rel;
     return rel <= rel_tol ? RBGS_REF_OK : RBGS_REF_ENOCONV;
+}
+
+/* Threads an OpenMP region of the oracle uses (1 without OpenMP); the
+ * timing harness reports it beside the oracle's throughput. */
+int rbgs_ref_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------------- */

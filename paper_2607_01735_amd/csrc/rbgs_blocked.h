@@ -12,6 +12,7 @@ namespace rbgs {
 
 constexpr int kBlockedLanes = 64;  // one wave per tile
 constexpr int kMinRows = 8;
+constexpr int kMaxRows = 65536;  // no grid is taller (n <= 65533)
 constexpr int kMaxFuse = 10;
 
 // Full sweeps per pass when the caller leaves fuse = 0, from time per sweep

@@ -142,8 +142,8 @@ int validate_blocked_opts(int fuse, int tile_rows, int tile_cols, std::string* w
         *why = "fuse must be in [1, 10] (0 = default)";
         return RBGS_EINVAL;
     }
-    if (tile_rows != 0 && tile_rows < kMinRows) {
-        *why = "tile_rows must be >= 8 (0 = default)";
+    if (tile_rows != 0 && (tile_rows < kMinRows || tile_rows > kMaxRows)) {
+        *why = "tile_rows must be in [8, 65536] (0 = default)";
         return RBGS_EINVAL;
     }
     if (tile_cols != 0) {
@@ -233,7 +233,7 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
     auto run_passes = [&](int fuse, int count, bool timed) -> hipError_t {
         const int rows = bp.tile_rows < 2 * fuse ? 2 * fuse : bp.tile_rows;
         const Geometry geo = geometry(n, int(sizeof(T)), fuse, rows);
-        if (geo.ntiles > max_tiles(n)) return hipErrorInvalidValue;
+        if (geo.ntiles < 1 || geo.ntiles > max_tiles(n)) return hipErrorInvalidValue;
         // tickets are ints: split very long runs into launches of at most
         // 2^30 work items, each starting from freshly zeroed flags
         const int max_passes = int((int64_t(1) << 30) / geo.ntiles) > 0

@@ -965,7 +965,8 @@ int rbgs_solve_learned(rbgs_unet* u, const rbgs_grid* g, double* uu, const doubl
     rest.max_sweeps = o->max_sweeps - compare_after;
     rbgs_solve_info inner{0, 0, 0.0, 0.0, RBGS_OK};
     rc = rbgs_solve(g, RBGS_F64, uu, f, &rest, &inner, workspace, workspace_bytes, stream);
-    inner.sweeps += compare_after;
+    // the work done: the comparison sweeps of both starts, then the solve
+    inner.sweeps += 2 * compare_after;
     if (info) *info = inner;
     return rc;
 }

@@ -183,3 +183,21 @@ def dst_solve(f):
     out = np.zeros((n + 2, n + 2))
     out[1:n + 1, 1:n + 1] = x
     return out
+
+
+def refinement_rel_bound(rels, inner, rhs_unit, unit=2.0 ** -24, ops=5):
+    """First-order bound on how far the relative residual of FP64
+    refinement around low-precision inner sweeps may drift from plain FP64
+    Gauss-Seidel after the same total number of sweeps.
+
+    In exact arithmetic an outer step (r = f - A u; e = s sweeps from 0 on
+    A e = r; u += e) equals s more sweeps on u: with the sweep operator
+    M = I - N A, sum_{j<s} M^j N A = I - M^s, so u + sum M^j N (f - A u) =
+    M^s u + sum M^j N f.  Rounding enters twice per step: r is stored with
+    unit roundoff rhs_unit (an error of at most rhs_unit ||r|| that the
+    step passes on to the new residual through I - M^s, counted twice), and
+    the inner sweeps round every update with unit roundoff `unit` (e after
+    s sweeps is about s h^2 |r| / 2 for the smooth modes, A amplifies by at
+    most 8/h^2, and each update has `ops` rounded operations: 4 ops s unit
+    ||r||).  rels: relative residual before each outer step."""
+    return sum((2.0 * rhs_unit + 4.0 * ops * inner * unit) * r for r in rels)

@@ -24,7 +24,12 @@ def _origins(c, n, S, r):
 
 
 def window_for(i, j, n, m):
-    r = 2 * m + 1
+    return window_for_radius(i, j, n, 2 * m + 1)
+
+
+def window_for_radius(i, j, n, r):
+    """Window (a, b, S) around (i, j) whose non-ring edges are at least r
+    away from it."""
     S = 2 * r + 2
     if S >= n + 1:
         return 0, 0, n + 1
@@ -45,5 +50,24 @@ def sample_after_sweeps(oracle, u0, f, h, m, points):
         wu = np.ascontiguousarray(u0[a:a + S + 1, b:b + S + 1])
         wf = np.ascontiguousarray(f[a:a + S + 1, b:b + S + 1])
         oracle.sweep(wu, wf, h, m)
+        vals.append(wu[i - a, j - b])
+    return np.array(vals, dtype=u0.dtype)
+
+
+def sample_after_refinement(oracle, u0, f, h, inner, outer, points, rhs_bf16=False):
+    """Oracle value of u at each point after `outer` refinement steps of
+    `inner` low-precision sweeps each (oracle.ir_solve).  One step reads u
+    at distance 1 (the residual) and then sweeps e from zero with a zero
+    ring for 2 * inner half-sweeps, so a wrong value at the window edge (a
+    frozen u, a zero e) travels at most 2 * inner + 1 points per step."""
+    n = f.shape[0] - 2
+    r = outer * (2 * inner + 1) + 1
+    vals = []
+    for (i, j) in points:
+        a, b, S = window_for_radius(i, j, n, r)
+        wu = np.ascontiguousarray(u0[a:a + S + 1, b:b + S + 1])
+        wf = np.ascontiguousarray(f[a:a + S + 1, b:b + S + 1])
+        _, done, _ = oracle.ir_solve(wu, wf, h, inner, outer, 1e-300, rhs_bf16=rhs_bf16)
+        assert done == outer
         vals.append(wu[i - a, j - b])
     return np.array(vals, dtype=u0.dtype)

@@ -77,7 +77,8 @@ def _sweep(lib, grid, dtype=0, nsweeps=1, opts=None, ws=None, ws_bytes=0):
 
 
 @pytest.mark.parametrize("bad", ["n0", "nbig", "ld", "h0", "hnan", "dtype", "nsweeps", "kernel",
-                                 "negopt", "ws_null", "ws_align", "ws_small"])
+                                 "negopt", "rows_small", "rows_big", "ws_null", "ws_align",
+                                 "ws_small"])
 def test_sweep_validation_before_device_work(lib, bad):
     g = _grid(lib, 31)
     dtype, nsweeps, opts = lib.F64, 1, lib.rbgs_sweep_opts()
@@ -101,6 +102,10 @@ def test_sweep_validation_before_device_work(lib, bad):
         opts.kernel = 9
     elif bad == "negopt":
         opts.fuse = -2
+    elif bad == "rows_small":
+        opts.kernel, opts.tile_rows = 2, 7
+    elif bad == "rows_big":  # would overflow the strip count; rejected, not clamped
+        opts.kernel, opts.tile_rows = 2, (1 << 31) - 1
     elif bad == "ws_null":
         ws, expect = None, lib.EWORKSPACE
     elif bad == "ws_align":
@@ -332,3 +337,16 @@ def test_split_layout_entry_points_validate(lib):
     o.timing = ctypes.pointer(t)
     assert raw.rbgs_sweep_split(gp, 0, None, None, None, None, 3, ctypes.byref(o), None, 0,
                                 None) == lib.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("rows", [7, 65537, (1 << 31) - 1])
+def test_batched_tile_rows_bounds(lib, rows):
+    """Tile heights outside [8, 65536] are rejected before any device work
+    (a height near INT_MAX would overflow the strip count)."""
+    grids = (lib.rbgs_grid * 2)(_grid(lib, 15), _grid(lib, 31))
+    ptrs = (ctypes.c_void_p * 2)(1 << 20, 2 << 20)  # never dereferenced: checks come first
+    o = lib.rbgs_sweep_opts()
+    o.tile_rows = rows
+    rc = lib._lib.rbgs_sweep_batched(2, grids, lib.F32, ptrs, ptrs, 10, ctypes.byref(o), None, 0, None)
+    assert rc == lib.EINVAL
+    assert "tile_rows" in lib.rbgs_batch_last_error()

@@ -4,7 +4,9 @@ On held-out GRF fields (seeds never used in training) the FP64 solve to a
 relative residual of 1e-8 from u = 0 -- the judge -- is compared with the
 same solve through rbgs_solve_learned: with the comparison after 500
 sweeps of both starts the network's start must be kept and cut the sweep
-count by at least 15 % (the training run measured 23 %); with the literal
+count (both starts' comparison sweeps counted) on every field, by at least
+15 % over the four fields together (the training run measured 23 %); with
+the literal
 comparison of starting residuals the raw guess (bfloat16 noise at grid
 scale) loses and the solve must be exactly the zero-start solve.  The final
 iterate's residual is checked by the oracle.
@@ -31,26 +33,39 @@ def say(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("seed", [learned.TEST_SEED0 + 11])
-def test_trained_network_cuts_sweeps(oracle, seed):
-    say(f"learned gain n={N} seed={seed}")
-    net = learned.pretrained_net(rb)
-    f = learned.fields_on_device(torch, N, [seed])[0]
-    u0 = torch.zeros_like(f)
-    base = rb.rbgs_solve(u0, f, CAP, TOL, check_every=CHECK)
-    assert base["status"] == 0 and base["rel_residual"] <= TOL
-    say(f"zero start: {base['sweeps']} sweeps")
-    u1 = torch.zeros_like(f)
-    got = net.solve_learned(u1, f, CAP, TOL, check_every=CHECK, compare_after=500)
-    say(f"learned start: {got}")
-    assert got["used_guess"] and got["rel_residual"] <= TOL
-    assert got["sweeps"] <= 0.85 * base["sweeps"]
+SEEDS = [learned.TEST_SEED0 + k for k in (11, 12, 13, 14)]
+
+
+def test_trained_network_cuts_sweeps(oracle):
+    """Four held-out fields.  Each: the guess is kept under the comparison
+    after 500 sweeps and the solve needs fewer sweeps than from zero (both
+    comparison branches counted); together the learned solves need at most
+    85 % of the zero-start sweeps.  The literal rule rejects the raw guess
+    and reproduces the zero-start solve bit for bit."""
     h = 1.0 / (N + 1)
-    _, rel = oracle.residual(u1.cpu().numpy(), f.cpu().numpy(), h)
-    assert rel <= TOL * (1 + 1e-9)
-    # the literal rule: the raw guess's residual is not lower, so the solve
-    # is the zero-start solve, bit for bit
-    u2 = torch.zeros_like(f)
-    lit = net.solve_learned(u2, f, CAP, TOL, check_every=CHECK, compare_after=0)
-    assert not lit["used_guess"] and lit["sweeps"] == base["sweeps"]
-    assert torch.equal(u2, u0)
+    net = learned.pretrained_net(rb)
+    fs = learned.fields_on_device(torch, N, SEEDS)
+    total_base = total_learned = 0
+    for seed, f in zip(SEEDS, fs):
+        say(f"learned gain n={N} seed={seed}")
+        u0 = torch.zeros_like(f)
+        base = rb.rbgs_solve(u0, f, CAP, TOL, check_every=CHECK)
+        assert base["status"] == 0 and base["rel_residual"] <= TOL
+        say(f"zero start: {base['sweeps']} sweeps")
+        u1 = torch.zeros_like(f)
+        got = net.solve_learned(u1, f, CAP, TOL, check_every=CHECK, compare_after=500)
+        say(f"learned start: {got}")
+        assert got["used_guess"] and got["rel_residual"] <= TOL
+        assert got["sweeps"] < base["sweeps"]
+        total_base += base["sweeps"]
+        total_learned += got["sweeps"]
+        _, rel = oracle.residual(u1.cpu().numpy(), f.cpu().numpy(), h)
+        assert rel <= TOL * (1 + 1e-9)
+        # the literal rule: the raw guess's residual is not lower, so the
+        # solve is the zero-start solve, bit for bit
+        u2 = torch.zeros_like(f)
+        lit = net.solve_learned(u2, f, CAP, TOL, check_every=CHECK, compare_after=0)
+        assert not lit["used_guess"] and lit["sweeps"] == base["sweeps"]
+        assert torch.equal(u2, u0)
+    say(f"sweep ratio over {len(SEEDS)} seeds: {total_learned / total_base:.4f}")
+    assert total_learned <= 0.85 * total_base

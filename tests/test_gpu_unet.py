@@ -200,7 +200,8 @@ def test_learned_solve_choice_rule(oracle):
         ut = torch.from_numpy(start.copy()).to(DEV)
         info = net.solve_learned(ut, ft, 300, 1e-12, check_every=100, kernel="plain",
                                  compare_after=k)
-        assert info["used_guess"] == use and info["sweeps"] == 300
+        # both starts were swept k times before the choice
+        assert info["used_guess"] == use and info["sweeps"] == 300 + k
         ref = (guess_np if use else start).copy()
         oracle.sweep(ref, f, h, 300)
         assert np.array_equal(ut.cpu().numpy(), ref)

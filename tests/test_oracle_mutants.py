@@ -24,6 +24,9 @@ MUTANTS = {
                         "(i % 2 == 0) ? (colour == 0 ? 1 : 2) : (colour == 0 ? 2 : 1);\n        for (int64_t j = j_start; j <= n; j += 2) {\n            double"),
     "black_before_red": ("rbgs_ref_half_sweep_f64(n, ld, h, u, f, 0);\n        rbgs_ref_half_sweep_f64(n, ld, h, u, f, 1);",
                          "rbgs_ref_half_sweep_f64(n, ld, h, u, f, 1);\n        rbgs_ref_half_sweep_f64(n, ld, h, u, f, 0);"),
+    # the binary32 residual sums its neighbours in binary32 (the widening dropped)
+    "residual_f32_not_widened": ("double s = (double)AT(u, i + 1, j) + (double)AT(u, i - 1, j);",
+                                 "double s = AT(u, i + 1, j) + AT(u, i - 1, j);"),
     "residual_missing_centre": ("double lap = (s - 4.0 * (double)AT(u, i, j)) * inv_h2;",
                                 "double lap = (s - 2.0 * (double)AT(u, i, j)) * inv_h2;"),
     "h_not_squared": ("const double h2 = h * h;\n#pragma omp parallel for schedule(static)\n    for (int64_t i = 1; i <= n; ++i) {\n        /* red",
@@ -83,6 +86,7 @@ def _pins_that_run():
     yield lambda: pins.test_multi_mode_iterate(oracle)
     yield lambda: pins.test_converges_to_dense_solve(oracle, 9)
     yield lambda: pins.test_residual_special_cases(oracle)
+    yield lambda: pins.test_residual_f32_is_fp64_residual_of_widened_iterate(oracle)
     yield lambda: mg_pins.test_restrict_constant_and_bilinear(oracle, 3)
     yield lambda: mg_pins.test_prolong_bilinear_exact_and_additive(oracle, 3)
     yield lambda: mg_pins.test_restrict_is_quarter_adjoint_of_prolong(oracle)
@@ -116,3 +120,55 @@ def test_unmutated_source_passes(tmp_path):
     with oracle.use_library(src_copy):
         for pin in _pins_that_run():
             pin()
+
+
+# --------------------------------------------------------------------------
+# The reference network's Adam (oracle/unet_ref.py): planted mistakes in a
+# copy of its source, loaded as a separate module, must fail the Adam pins.
+# --------------------------------------------------------------------------
+PY_MUTANTS = {
+    "adam_bias_exponent_fixed": ("mh = m / (1 - beta1 ** t)", "mh = m / (1 - beta1)"),
+    "adam_v_uncorrected": ("vh = v / (1 - beta2 ** t)", "vh = v"),
+    "adam_betas_swapped": ("m[...] = beta1 * m + (1 - beta1) * g[k]\n        v[...] = beta2 * v + (1 - beta2) * g[k] * g[k]",
+                           "m[...] = beta2 * m + (1 - beta2) * g[k]\n        v[...] = beta1 * v + (1 - beta1) * g[k] * g[k]"),
+    "adam_step_counter_late": ("state[\"t\"] = state.get(\"t\", 0) + 1\n    t = state[\"t\"]",
+                               "t = state.get(\"t\", 0) + 1\n    state[\"t\"] = max(1, t - 1)"),
+    "adam_eps_inside_sqrt": ("np.sqrt(vh) + eps", "np.sqrt(vh + eps)"),
+}
+
+
+def _load_py_mutant(name):
+    import importlib.util
+    import types
+    from oracle import unet_ref
+    src = open(unet_ref.__file__).read()
+    old, new = PY_MUTANTS[name]
+    assert src.count(old) == 1, name
+    mod = types.ModuleType(f"unet_ref_{name}")
+    mod.__file__ = unet_ref.__file__
+    exec(compile(src.replace(old, new), f"<mutant {name}>", "exec"), mod.__dict__)
+    assert importlib.util is not None
+    return mod
+
+
+def _adam_pins():
+    from tests import test_unet_ref as ur
+    return [ur.check_adam_first_step, ur.check_adam_constant_gradient, ur.check_adam_sum_form]
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_adam_pins_reject_mutant(name):
+    mod = _load_py_mutant(name)
+    caught = 0
+    for pin in _adam_pins():
+        try:
+            pin(mod)
+        except AssertionError:
+            caught += 1
+    assert caught >= 1, f"mutant {name} passed every Adam pin"
+
+
+def test_adam_pins_pass_unmutated_source():
+    from oracle import unet_ref
+    for pin in _adam_pins():
+        pin(unet_ref)

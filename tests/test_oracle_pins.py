@@ -219,6 +219,35 @@ def test_residual_special_cases(oracle):
     assert a == pytest.approx(np.linalg.norm(b), rel=1e-13)
 
 
+def test_residual_f32_is_fp64_residual_of_widened_iterate(oracle):
+    """The residual of a binary32 iterate is the FP64 residual (pinned above)
+    of the same values widened to FP64.  Widening is exact, so the two agree
+    bit for bit, field included.  The data are random binary32 values of
+    mixed magnitude, so a sum or product formed in binary32 (a dropped
+    widening) rounds differently; a plain NumPy form of the residual in FP64
+    agrees to rounding."""
+    n = 33
+    h = W.spacing(n)
+    rng = np.random.default_rng(21)
+    u32 = (W.random_ring(n, seed=22) * 3.0).astype(np.float32)
+    u32[1:-1, 1:-1] = (rng.standard_normal((n, n)) * np.exp(rng.uniform(-3, 3, (n, n)))).astype(np.float32)
+    f32 = W.zeros(n).astype(np.float32)
+    f32[1:-1, 1:-1] = rng.standard_normal((n, n)).astype(np.float32)
+    a32, r32, fld32 = oracle.residual(u32, f32, h, want_field=True)
+    u64, f64 = u32.astype(np.float64), f32.astype(np.float64)
+    a64, r64, fld64 = oracle.residual(u64, f64, h, want_field=True)
+    assert a32 == a64 and r32 == r64
+    assert np.array_equal(fld32, fld64)
+    # independent NumPy form, FP64 throughout
+    s = ((u64[2:, 1:-1] + u64[:-2, 1:-1]) + u64[1:-1, 2:]) + u64[1:-1, :-2]
+    r = f64[1:-1, 1:-1] - (s - 4.0 * u64[1:-1, 1:-1]) / (h * h)
+    assert a32 == pytest.approx(np.linalg.norm(r), rel=1e-13)
+    # the same arithmetic in binary32 gives a visibly different residual
+    s32 = ((u32[2:, 1:-1] + u32[:-2, 1:-1]) + u32[1:-1, 2:]) + u32[1:-1, :-2]
+    r_lo = f32[1:-1, 1:-1].astype(np.float64) - (s32.astype(np.float64) - 4.0 * u64[1:-1, 1:-1]) / (h * h)
+    assert abs(np.linalg.norm(r_lo) - a32) > 2e-11 * a32
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_updated_colour_has_zero_residual(oracle, seed):
     """After a red half-sweep the residual vanishes at red points (to
@@ -582,3 +611,25 @@ def test_sor_optimal_omega_cuts_sweeps(oracle):
     rc, done_gs, _ = oracle.solve(W.zeros(n), f, h, 20000, 1e-8, 10)
     assert rc == 0
     assert done_sor < 400 and done_gs > 10 * done_sor
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_ir_trajectory_within_rounding_bound_of_gauss_seidel(oracle, bf16):
+    """Refinement with s inner sweeps per outer step equals, in exact
+    arithmetic, s plain sweeps per step (closed_form.refinement_rel_bound
+    derives it), so after 2 x 100 inner sweeps of the 64-mode workload at
+    N = 1023 its relative residual is the multi-mode closed form of 200
+    sweeps within the stated first-order rounding bound -- and not exactly
+    (the inner sweeps really are binary32 / the rhs really is bfloat16)."""
+    n, inner = 1023, 100
+    h = W.spacing(n)
+    f = W.fourier_rhs(n, seed=0)
+    modes = cf.merge_modes(*W.fourier_modes(seed=0))
+    u = W.zeros(n)
+    rc, outer, rel = oracle.ir_solve(u, f, h, inner, 2, 1e-30, rhs_bf16=bf16)
+    assert outer == 2
+    expect = cf.multi_mode_rel(n, modes, 2 * inner)
+    bound = cf.refinement_rel_bound([1.0, cf.multi_mode_rel(n, modes, inner)], inner,
+                                    2.0 ** -8 if bf16 else 2.0 ** -24)
+    assert abs(rel - expect) <= bound
+    assert abs(rel - expect) > 1e-12 * expect

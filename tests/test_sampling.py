@@ -1,8 +1,10 @@
 """The light-cone sampler agrees with a full oracle run (CPU)."""
 import numpy as np
+import pytest
 
 import workloads as W
-from tests.sampling import sample_after_sweeps, window_for
+from tests.sampling import (sample_after_refinement, sample_after_sweeps, window_for,
+                            window_for_radius)
 
 
 def test_windows_respect_parity_and_bounds():
@@ -23,3 +25,18 @@ def test_sampler_matches_full_run(oracle):
     got = sample_after_sweeps(oracle, u0, f, h, m, pts)
     for p, v in zip(pts, got):
         assert v == full[p]
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_refinement_light_cone_sampling_matches_full_grid(oracle, bf16):
+    """Windows cut for refinement (2 outer steps of 20 inner sweeps) give the
+    full-grid refinement's values bit for bit, windows smaller than the grid."""
+    n = 511
+    h = W.spacing(n)
+    f = W.fourier_rhs(n, seed=0)
+    u = W.zeros(n)
+    oracle.ir_solve(u, f, h, 20, 2, 1e-300, rhs_bf16=bf16)
+    pts = [(1, 1), (255, 256), (n, n), (100, 400), (300, 3)]
+    got = sample_after_refinement(oracle, W.zeros(n), f, h, 20, 2, pts, rhs_bf16=bf16)
+    assert np.array_equal(got, np.array([u[p] for p in pts]))
+    assert window_for_radius(255, 256, n, 2 * (2 * 20 + 1) + 1)[2] < n

@@ -126,10 +126,59 @@ def test_network_gradient_by_finite_differences(factor, n):
     assert checked > 40
 
 
-def test_adam_step_moves_against_gradient():
+def check_adam_first_step(mod):
     p = {"a": np.array([1.0, -2.0])}
     g = {"a": np.array([0.5, -0.25])}
     state = {}
-    U.adam_step(p, g, state, lr=0.1)
+    mod.adam_step(p, g, state, lr=0.1)
     # first bias-corrected Adam step is lr * sign(g)
     assert np.allclose(p["a"], [0.9, -1.9], atol=1e-7)
+
+
+def check_adam_constant_gradient(mod):
+    """With the same gradient g at every step, m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2, so the bias-corrected moments are exactly g and
+    g^2 and every step moves the parameter by lr g / (|g| + eps), at every
+    t, not only the first.  A wrong bias-correction exponent, a missing
+    correction or swapped betas break this from t = 2 on."""
+    lr, eps = 1e-2, 1e-8
+    g0 = np.array([0.5, -0.25, 3e-3, -7.0, 1e-6])
+    p = {"a": np.array([1.0, -2.0, 0.0, 4.0, -1.0])}
+    state = {}
+    for t in range(1, 9):
+        before = p["a"].copy()
+        mod.adam_step(p, {"a": g0.copy()}, state, lr=lr, eps=eps)
+        step = before - p["a"]
+        assert np.allclose(step, lr * g0 / (np.abs(g0) + eps), rtol=1e-9, atol=1e-15), t
+    assert state["t"] == 8
+
+
+def check_adam_sum_form(mod):
+    """Varying gradients: the moments are the exponentially weighted sums
+    m_t = (1 - b1) sum_s b1^(t-s) g_s and v_t = (1 - b2) sum_s b2^(t-s) g_s^2,
+    each divided by its bias correction 1 - b^t; the update is
+    lr m^ / (sqrt(v^) + eps) (Kingma and Ba, Algorithm 1)."""
+    b1, b2, eps, lr = 0.9, 0.999, 1e-8, 3e-3
+    rng = np.random.default_rng(5)
+    gs = [rng.standard_normal(6) * 10.0 ** rng.uniform(-3, 1, 6) for _ in range(7)]
+    p = {"a": rng.standard_normal(6)}
+    expect = p["a"].copy()
+    state = {}
+    for t in range(1, len(gs) + 1):
+        mod.adam_step(p, {"a": gs[t - 1].copy()}, state, lr=lr)
+        m = (1 - b1) * sum(b1 ** (t - s) * gs[s - 1] for s in range(1, t + 1))
+        v = (1 - b2) * sum(b2 ** (t - s) * gs[s - 1] ** 2 for s in range(1, t + 1))
+        expect = expect - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+        assert np.allclose(p["a"], expect, rtol=1e-12, atol=1e-15), t
+
+
+def test_adam_step_moves_against_gradient():
+    check_adam_first_step(U)
+
+
+def test_adam_constant_gradient_every_step():
+    check_adam_constant_gradient(U)
+
+
+def test_adam_matches_weighted_sum_form():
+    check_adam_sum_form(U)
