@@ -229,6 +229,22 @@ int rbgs_residual(const rbgs_grid *g, rbgs_dtype dt, const void *u,
                   const void *f, double *abs_norm, double *rel_norm,
                   void *workspace, size_t workspace_bytes, void *stream);
 
+/* rbgs_residual for callers that cannot allocate device memory or pass a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels, the same results bit for bit,
+ * but the partial sums live in a static device array of 4 MiB that the
+ * library holds on each GPU it runs on until the process ends, so no
+ * workspace argument.  Grids whose partial sums do not fit (n above about
+ * 23 000; 256 + 16 * ceil(n/256) * ceil(n/8) bytes) return RBGS_EINVAL
+ * before any device work.  Calls no hipMalloc, hipFree or allocating
+ * library routine.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (different streams or host threads) race and
+ * must be serialised by the caller.  u, f, abs_norm, rel_norm as for
+ * rbgs_residual; synchronises `stream`. */
+int rbgs_residual_noalloc(const rbgs_grid *g, rbgs_dtype dt, const void *u,
+                          const void *f, double *abs_norm, double *rel_norm,
+                          void *stream);
+
 /* Sweeps until rel <= opts->rel_tol or opts->max_sweeps sweeps.  The
  * residual is evaluated before the first sweep and after every check_every
  * sweeps (the last group is shortened to end exactly at max_sweeps).

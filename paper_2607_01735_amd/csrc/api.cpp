@@ -925,6 +925,40 @@ int rbgs_residual(const rbgs_grid* g, rbgs_dtype dt, const void* u, const void* 
     return fetch_norms(w, s, abs_norm, rel_norm);
 }
 
+int rbgs_residual_noalloc(const rbgs_grid* g, rbgs_dtype dt, const void* u, const void* f,
+                          double* abs_norm, double* rel_norm, void* stream) {
+    std::string why;
+    if (!valid_grid(g, &why)) return fail(RBGS_EINVAL, why);
+    if (!valid_dtype(dt)) return fail(RBGS_EINVAL, "unknown dtype");
+    const size_t need = residual_noalloc_bytes(g->n);
+    if (need > kStaticScratchBytes)
+        return fail(RBGS_EINVAL, "grid too large for the static scratch of rbgs_residual_noalloc (" +
+                                     std::to_string(need) + " bytes needed, " +
+                                     std::to_string(kStaticScratchBytes) + " available)");
+    int rc;
+    if ((rc = check_device_range(u, grid_bytes(g, dt), "u"))) return rc;
+    if ((rc = check_device_range(f, grid_bytes(g, dt), "f"))) return rc;
+    void* base = nullptr;
+    HIP_TRY(static_scratch(&base), "static scratch address");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* sums = static_cast<double*>(base);
+    double* partials = reinterpret_cast<double*>(static_cast<char*>(base) + 256);
+    const double inv_h2 = 1.0 / (g->h * g->h);
+    if (dt == RBGS_F64)
+        HIP_TRY(launch_residual_natural<double>(static_cast<const double*>(u),
+                                                static_cast<const double*>(f), g->n, g->ld,
+                                                inv_h2, partials, sums, s),
+                "residual");
+    else
+        HIP_TRY(launch_residual_natural<float>(static_cast<const float*>(u),
+                                               static_cast<const float*>(f), g->n, g->ld, inv_h2,
+                                               partials, sums, s),
+                "residual");
+    Workspace w;
+    w.sums = sums;
+    return fetch_norms(w, s, abs_norm, rel_norm);
+}
+
 int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
                const rbgs_solve_opts* o, rbgs_solve_info* info, void* workspace,
                size_t workspace_bytes, void* stream) {

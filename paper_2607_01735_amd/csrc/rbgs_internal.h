@@ -91,6 +91,14 @@ hipError_t launch_residual_natural(const T* u, const T* f, int n, int64_t ld, do
                                    double* partials, double* out, hipStream_t s);
 int residual_natural_partial_slots(int n);
 
+// Static scratch of the no-allocation residual: a file-scope device array
+// of kStaticScratchBytes per device.  static_scratch gives the current
+// device's address of it (looked up once per device); residual_noalloc_bytes
+// is what a grid of size n needs there (sums, then the partial sums).
+constexpr size_t kStaticScratchBytes = size_t(4) << 20;
+hipError_t static_scratch(void** ptr);
+size_t residual_noalloc_bytes(int n);
+
 // u <- u + e at the interior points (split layouts; u FP64, e FP32);
 // nothing when stop != nullptr and *stop != 0.
 hipError_t launch_add_correction(double* u_red, double* u_black, int64_t pitch,

@@ -8,6 +8,8 @@
 // binary tree in each workgroup, then one workgroup over the per-workgroup
 // partials in slot order.  No floating-point atomics, so the result is
 // bitwise reproducible for a given grid size.
+#include <mutex>
+
 #include "rbgs_internal.h"
 
 namespace rbgs {
@@ -189,6 +191,43 @@ int strips(int n) { return (n + kRows - 1) / kRows; }
 
 int residual_partial_slots(int n, int64_t, size_t) { return split_col_blocks(n) * strips(n); }
 int residual_natural_partial_slots(int n) { return natural_col_blocks(n) * strips(n); }
+
+// ---------------------------------------------------------------------------
+// Scratch for the entry point that allocates nothing (rbgs_residual_noalloc):
+// the natural-layout residual's partial sums and final sums live in this
+// file-scope device array instead of a caller workspace.  Each device holds
+// its own copy at its own address, looked up once per device with
+// hipGetSymbolAddress (the array's name is not a device address in host
+// code).  Every call on a device shares that device's array.
+// ---------------------------------------------------------------------------
+namespace {
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void** ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+size_t residual_noalloc_bytes(int n) {
+    return 256 + size_t(residual_natural_partial_slots(n)) * 2 * sizeof(double);
+}
 
 template <typename T>
 hipError_t launch_residual_split(const T* u_red, const T* u_black, const T* f_red,

@@ -131,6 +131,9 @@ _lib.rbgs_sweep.restype = ctypes.c_int
 _lib.rbgs_residual.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, _P(ctypes.c_double),
                                _P(ctypes.c_double), _vp, ctypes.c_size_t, _vp]
 _lib.rbgs_residual.restype = ctypes.c_int
+_lib.rbgs_residual_noalloc.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp,
+                                       _P(ctypes.c_double), _P(ctypes.c_double), _vp]
+_lib.rbgs_residual_noalloc.restype = ctypes.c_int
 _lib.rbgs_solve.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, _P(rbgs_solve_opts),
                             _P(rbgs_solve_info), _vp, ctypes.c_size_t, _vp]
 _lib.rbgs_solve.restype = ctypes.c_int
@@ -164,7 +167,8 @@ _lib.rbgs_autotune_batched.restype = ctypes.c_int
 _lib.rbgs_batch_last_error.argtypes = []
 _lib.rbgs_batch_last_error.restype = ctypes.c_char_p
 
-EXPORTED = ("rbgs_workspace_size", "rbgs_sweep", "rbgs_residual", "rbgs_solve",
+EXPORTED = ("rbgs_workspace_size", "rbgs_sweep", "rbgs_residual", "rbgs_residual_noalloc",
+            "rbgs_solve",
             "rbgs_stream_probe", "rbgs_strerror", "rbgs_last_error", "rbgs_batch_workspace_size",
             "rbgs_sweep_batched", "rbgs_batch_plan_create", "rbgs_batch_plan_launch",
             "rbgs_batch_plan_check", "rbgs_batch_plan_destroy", "rbgs_autotune_batched",
@@ -305,6 +309,21 @@ def rbgs_residual(u, f, h=None, workspace=None, stream=None):
     _check(_lib.rbgs_residual(ctypes.byref(grid), code, _vp(u.data_ptr()), _vp(f.data_ptr()),
                               ctypes.byref(a), ctypes.byref(r), _vp(ws.data_ptr()), ws.numel(),
                               _stream_ptr(stream, u.device)))
+    return a.value, r.value
+
+
+def rbgs_residual_noalloc(u, f, h=None, stream=None):
+    """(||r||_2, ||r||_2/||b||_2) in FP64 without a workspace: the library's
+    static per-GPU scratch holds the partial sums (no device allocation, not
+    even by this binding).  Calls overlapping on one GPU race."""
+    _same_layout(u, f)
+    grid = make_grid(u, h)
+    a = ctypes.c_double()
+    r = ctypes.c_double()
+    rc = _lib.rbgs_residual_noalloc(ctypes.byref(grid), _dtype_code(u), _vp(u.data_ptr()),
+                                    _vp(f.data_ptr()), ctypes.byref(a), ctypes.byref(r),
+                                    _stream_ptr(stream, u.device))
+    _check(rc)
     return a.value, r.value
 
 

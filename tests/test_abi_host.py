@@ -350,3 +350,21 @@ def test_batched_tile_rows_bounds(lib, rows):
     rc = lib._lib.rbgs_sweep_batched(2, grids, lib.F32, ptrs, ptrs, 10, ctypes.byref(o), None, 0, None)
     assert rc == lib.EINVAL
     assert "tile_rows" in lib.rbgs_batch_last_error()
+
+
+@pytest.mark.parametrize("case", ["n0", "dtype", "too_big"])
+def test_residual_noalloc_validation_before_device_work(lib, case):
+    """The no-allocation residual checks its arguments, and that the grid's
+    partial sums fit its static scratch, before touching the device."""
+    g, dtype = _grid(lib, 31), lib.F64
+    if case == "n0":
+        g = _grid(lib, 0)
+    elif case == "dtype":
+        dtype = 9
+    elif case == "too_big":
+        g = lib.rbgs_grid(32767, 32769, 1.0 / 32768)
+    rc = lib._lib.rbgs_residual_noalloc(ctypes.byref(g), dtype, ctypes.c_void_p(256),
+                                        ctypes.c_void_p(256), None, None, None)
+    assert rc == lib.EINVAL
+    if case == "too_big":
+        assert "static scratch" in lib.rbgs_last_error()
