@@ -97,7 +97,13 @@ struct StepIn {
 // (four was no better than two); FP32 and the deepest pipelines (L > 14),
 // short of registers, keep two.
 template <typename T, int L>
-constexpr int prefetch_steps() { return sizeof(T) == 8 && L <= 14 ? 3 : 2; }
+constexpr int prefetch_steps() {
+#ifdef RBGS_EMU_PREFETCH_STEPS  // the CPU emulation replays other depths (1..5)
+    return RBGS_EMU_PREFETCH_STEPS;
+#else
+    return sizeof(T) == 8 && L <= 14 ? 3 : 2;
+#endif
+}
 
 // Whole-wave lane shifts through DPP (register to register, no LDS trip):
 // from_next_lane gives lane i the value of lane i+1 (wave_shl:1), and
@@ -164,20 +170,25 @@ struct FRing {
     Vec<T, V> row[2][fring_rows<L>()][kLanes];
 };
 
-// Loads never branch: row and column indices are clamped into the grid.
-// A clamped load only ever feeds rows or columns outside the region the
-// tile writes (the warm-up rows above xs, the drain rows below xe, lanes
-// beyond the grid edge), whose values are recomputed garbage anyway.
+// Loads never branch: row and column indices are clamped into the grid,
+// and rows of the iterate into the tile's loaded region [lo, hi] = [xs, xe]
+// (its rows plus L halo rows each side, inside the dependency region that
+// the tile waited for), so that no load touches rows another tile may be
+// writing.  A clamped load only ever feeds rows or columns outside the
+// region the tile writes (the warm-up rows above xs, the drain rows below
+// xe, lanes beyond the grid edge), whose values are recomputed garbage
+// anyway.
 __device__ __forceinline__ int clamp_row(int x, int lo, int hi) {
     return x < lo ? lo : (x > hi ? hi : x);
 }
 
 template <typename T, int V, bool EDGE>
 __device__ __forceinline__ StepIn<T, V> load_in(const GridDesc<T>& a, const T* __restrict__ xr,
-                                                const T* __restrict__ xb, int x, int64_t qv) {
+                                                const T* __restrict__ xb, int x, int lo, int hi,
+                                                int64_t qv) {
     StepIn<T, V> in;
     const int64_t P = a.pitch;
-    const int64_t row = int64_t(clamp_row(x, 0, a.n + 1)) * P + qv;
+    const int64_t row = int64_t(clamp_row(x, lo, hi)) * P + qv;
     in.b = vload<T, V>(xb + row);
     // red input values matter only where they pass through unchanged
     // (the ring); interior tiles never see the ring
@@ -219,7 +230,7 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, FRing<T, V, L>& fr,
     constexpr int D = prefetch_steps<T, L>();
     const StepIn<T, V> cur = st.in[S];
     // prefetch: step x+D's rows into a slot no pending step holds
-    st.in[(S + D) % 6] = load_in<T, V, EDGE>(a, xr, xb, x + D, qv);
+    st.in[(S + D) % 6] = load_in<T, V, EDGE>(a, xr, xb, x + D, xs, xe, qv);
     // this step's right-hand-side rows join the ring (red row x-1, black
     // row x-2) as the products h^2 f that Eq. (1) subtracts: each is formed
     // once here, not once per fused level (the same product, so the same
@@ -344,7 +355,7 @@ __device__ __forceinline__ void run_tile(FRing<T, V, L>& fr, const GridDesc<T>& 
     const int x0 = xs - xs % 6;
 #pragma unroll
     for (int d = 0; d < prefetch_steps<T, L>(); ++d)
-        st.in[d] = load_in<T, V, EDGE>(a, xr, xb, x0 + d, qv);
+        st.in[d] = load_in<T, V, EDGE>(a, xr, xb, x0 + d, xs, xe, qv);
     for (int x = x0; x <= x_last; x += 6) {
         pipe_step<T, V, L, 0, EDGE>(st, fr, a, xr, xb, yr, yb, x + 0, xs, xe, r0, r1, q0, qv, qc0, qc1,
                                     in_core, store_red);

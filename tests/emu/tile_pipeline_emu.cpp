@@ -1,15 +1,21 @@
 // Runs the persistent tile pipeline of the blocked sweep (the device code in
-// paper_2607_01735_amd/csrc/blocked_pipeline.h, unchanged) on the CPU: one
-// emulated wave of 64 fibers takes every (pass, tile) ticket in order,
-// exactly as one wave of the persistent kernel would.  Every array the
+// paper_2607_01735_amd/csrc/blocked_pipeline.h, and with EMU_WAVES=2 the
+// two-wave tiles of blocked_split.h, unchanged) on the CPU.  Each emulated
+// workgroup (64 lanes, or 128 with EMU_WAVES=2, as fibers) runs on its own
+// host thread and takes (pass, tile) tickets from the shared counter exactly
+// as a workgroup of the persistent kernel would; the progress flags,
+// tickets and grid arrays are shared between the threads through the same
+// atomic operations and fences the device code uses.  Every array the
 // pipeline touches is its own heap block of exactly the size the library
-// allocates, so an AddressSanitizer build reports any access outside them.
-// Test infrastructure only: tests/test_tile_pipeline_emu.py builds it and
-// compares the result with the oracle bit for bit.
+// allocates, so an AddressSanitizer build reports any access outside them;
+// a ThreadSanitizer build reports any grid access that the dependency
+// protocol does not order.  Test infrastructure only:
+// tests/test_tile_pipeline_emu.py builds it and compares the result with the
+// oracle bit for bit.
 //
-// Build: g++ -std=c++17 -DEMU_T=double -DEMU_FUSE=7 -I tests/emu
+// Build: g++ -std=c++17 -DEMU_T=double -DEMU_FUSE=7 [-DEMU_WAVES=2] -I tests/emu
 //            -I paper_2607_01735_amd/csrc -I include ...
-// Run:   emu n rows passes h in.bin out.bin
+// Run:   emu n rows passes h in.bin out.bin [workgroups [yield_every]]
 //   in.bin  = u then f, natural (n+2) x (n+2) arrays of EMU_T, row major
 //   out.bin = u after passes x fuse full sweeps, same layout
 #include <hip/hip_runtime.h>
@@ -17,23 +23,37 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <thread>
 #include <vector>
 
 #include "blocked_pipeline.h"
+#include "blocked_split.h"
 #include "rbgs_blocked.h"
 
+#ifndef EMU_WAVES
+#define EMU_WAVES 1
+#endif
+
 namespace emu {
-int current = 0;
-jmp_buf lane_jmp[kLanes];
-bool lane_done[kLanes];
-uint64_t lane_slot[kLanes];
+thread_local int nthreads = kLanes;
+thread_local int current = 0;
+thread_local jmp_buf lane_jmp[kMaxThreads];
+thread_local bool lane_done[kMaxThreads];
+thread_local uint64_t lane_slot[kMaxThreads];
+thread_local int bar_arrived = 0, bar_generation = 0;
+int yield_every = 0;
+thread_local unsigned switches = 0;
+#ifdef EMU_TSAN
+thread_local void* lane_fiber[kMaxThreads];
+thread_local void* host_fiber;
+#endif
 }  // namespace emu
 
 // Fibers: each lane's stack is entered once through makecontext/swapcontext
 // (lane_start parks it with _setjmp and returns to the host); from then on
 // lanes switch with _setjmp/_longjmp.
-static ucontext_t g_host_ctx, g_start_ctx[emu::kLanes];
-static jmp_buf g_host_jmp;
+static thread_local ucontext_t g_host_ctx, g_start_ctx[emu::kMaxThreads];
+static thread_local jmp_buf g_host_jmp;
 
 using namespace rbgs;
 using namespace rbgs::blocked;
@@ -45,10 +65,26 @@ constexpr int kV = 16 / int(sizeof(T));
 static GridDesc<T> g_grid;
 static Queue g_queue;
 
-// The body of the persistent kernel for one wave, run by every lane fiber;
-// a finished lane hands over to the next live one, the last to the host.
+static void to_host() {
+#ifdef EMU_TSAN
+    __tsan_switch_to_fiber(emu::host_fiber, 0);
+#endif
+    _longjmp(g_host_jmp, 1);
+}
+
+// The body of the persistent kernel for one workgroup, run by every lane
+// fiber; a finished lane hands over to the next live one, the last to the
+// host.
 static void lane_start(int lane) {
-    if (_setjmp(emu::lane_jmp[lane]) == 0) swapcontext(&g_start_ctx[lane], &g_host_ctx);
+    if (_setjmp(emu::lane_jmp[lane]) == 0) {
+#ifdef EMU_TSAN
+        __tsan_switch_to_fiber(emu::host_fiber, 0);
+#endif
+        swapcontext(&g_start_ctx[lane], &g_host_ctx);
+    }
+#if EMU_WAVES == 2
+    persistent_split<T, kV, kL>(g_grid, g_queue);
+#else
     const int total = g_queue.passes * g_grid.ntiles;
     for (;;) {
         const int tk = next_ticket(g_queue);
@@ -56,15 +92,41 @@ static void lane_start(int lane) {
         const int pass = tk / g_grid.ntiles;
         if (!run_item<T, kV, kL>(g_grid, g_queue, pass, tk - pass * g_grid.ntiles)) break;
     }
+#endif
     emu::lane_done[lane] = true;
-    for (int k = 1; k < emu::kLanes; ++k) {
-        const int nx = (lane + k) % emu::kLanes;
-        if (!emu::lane_done[nx]) {
-            emu::current = nx;
-            _longjmp(emu::lane_jmp[nx], 1);
-        }
+    for (int k = 1; k < emu::nthreads; ++k) {
+        const int nx = (lane + k) % emu::nthreads;
+        if (!emu::lane_done[nx]) emu::jump_to_lane(nx);
     }
-    _longjmp(g_host_jmp, 1);
+    to_host();
+}
+
+// One workgroup on this host thread: park every lane, then run them.
+static void run_workgroup() {
+    emu::nthreads = 64 * EMU_WAVES;
+    emu::current = 0;
+    emu::bar_arrived = emu::bar_generation = 0;
+#ifdef EMU_TSAN
+    emu::host_fiber = __tsan_get_current_fiber();
+#endif
+    const size_t stack_bytes = size_t(1) << 20;
+    std::vector<char*> stacks(emu::nthreads);
+    for (int l = 0; l < emu::nthreads; ++l) {
+        stacks[l] = static_cast<char*>(malloc(stack_bytes));
+        if (!stacks[l] || getcontext(&g_start_ctx[l]) != 0) abort();
+        g_start_ctx[l].uc_stack.ss_sp = stacks[l];
+        g_start_ctx[l].uc_stack.ss_size = stack_bytes;
+        g_start_ctx[l].uc_link = nullptr;
+        makecontext(&g_start_ctx[l], reinterpret_cast<void (*)()>(lane_start), 1, l);
+        emu::lane_done[l] = false;
+#ifdef EMU_TSAN
+        emu::lane_fiber[l] = __tsan_create_fiber(0);
+        __tsan_switch_to_fiber(emu::lane_fiber[l], 0);
+#endif
+        if (swapcontext(&g_host_ctx, &g_start_ctx[l]) != 0) abort();  // parks lane l
+    }
+    if (_setjmp(g_host_jmp) == 0) emu::jump_to_lane(0);
+    for (int l = 0; l < emu::nthreads; ++l) free(stacks[l]);
 }
 
 static T* block_of(size_t count) {
@@ -75,8 +137,9 @@ static T* block_of(size_t count) {
 }
 
 int main(int argc, char** argv) {
-    if (argc != 7) {
-        fprintf(stderr, "usage: %s n rows passes h in.bin out.bin\n", argv[0]);
+    if (argc < 7 || argc > 9) {
+        fprintf(stderr, "usage: %s n rows passes h in.bin out.bin [workgroups [yield_every]]\n",
+                argv[0]);
         return 2;
     }
     const int n = atoi(argv[1]), rows = atoi(argv[2]), passes = atoi(argv[3]);
@@ -147,23 +210,16 @@ int main(int argc, char** argv) {
     qu.stall_tile = 0;
     qu.buf_offset = 0;
     qu.stop = nullptr;
-    const size_t stack_bytes = size_t(1) << 20;
-    std::vector<char*> stacks(emu::kLanes);
-    for (int l = 0; l < emu::kLanes; ++l) {
-        stacks[l] = static_cast<char*>(malloc(stack_bytes));
-        if (!stacks[l] || getcontext(&g_start_ctx[l]) != 0) abort();
-        g_start_ctx[l].uc_stack.ss_sp = stacks[l];
-        g_start_ctx[l].uc_stack.ss_size = stack_bytes;
-        g_start_ctx[l].uc_link = nullptr;
-        makecontext(&g_start_ctx[l], reinterpret_cast<void (*)()>(lane_start), 1, l);
-        emu::lane_done[l] = false;
-        if (swapcontext(&g_host_ctx, &g_start_ctx[l]) != 0) abort();  // parks lane l
+    const int workgroups = argc > 7 ? atoi(argv[7]) : 1;
+    emu::yield_every = argc > 8 ? atoi(argv[8]) : 0;
+    if (workgroups > 1) qu.spin_limit = 1 << 28;
+    if (workgroups <= 1) {
+        run_workgroup();  // on the main thread
+    } else {
+        std::vector<std::thread> threads;
+        for (int w = 0; w < workgroups; ++w) threads.emplace_back(run_workgroup);
+        for (auto& t : threads) t.join();
     }
-    if (_setjmp(g_host_jmp) == 0) {
-        emu::current = 0;
-        _longjmp(emu::lane_jmp[0], 1);
-    }
-    for (int l = 0; l < emu::kLanes; ++l) free(stacks[l]);
     if (*qu.error != 0) {
         fprintf(stderr, "the pipeline raised its error word\n");
         return 4;
@@ -177,8 +233,8 @@ int main(int argc, char** argv) {
     FILE* fout = fopen(argv[6], "wb");
     if (!fout || fwrite(u.data(), sizeof(T), u.size(), fout) != u.size()) return 2;
     fclose(fout);
-    printf("n=%d rows=%d passes=%d fuse=%d tiles=%d halo_q=%d q_core=%d\n", n, geo.rows, passes,
-           kFuse, geo.ntiles, geo.halo_q, geo.q_core);
+    printf("n=%d rows=%d passes=%d fuse=%d waves=%d workgroups=%d tiles=%d halo_q=%d q_core=%d\n",
+           n, geo.rows, passes, kFuse, EMU_WAVES, workgroups, geo.ntiles, geo.halo_q, geo.q_core);
     for (int b = 0; b < 2; ++b) {
         free(red[b]);
         free(black[b]);

@@ -60,13 +60,15 @@ CASES = [  # n, sweeps, fuse, tile_rows (0 = default)
 
 @pytest.mark.parametrize("n,sweeps,fuse,rows", CASES)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_blocked_sweep_bitwise(oracle, n, sweeps, fuse, rows, dtype):
-    say(f"blocked n={n} sweeps={sweeps} fuse={fuse} rows={rows} {dtype.__name__}")
+@pytest.mark.parametrize("waves", [1, 2])
+def test_blocked_sweep_bitwise(oracle, n, sweeps, fuse, rows, dtype, waves):
+    say(f"blocked n={n} sweeps={sweeps} fuse={fuse} rows={rows} {dtype.__name__} waves={waves}")
     h = W.spacing(n)
     ld = n + 2 + (n % 5)
     u0, f = start(n, n, ld=ld, dtype=dtype)
     ut, ft = dev(u0), dev(f)
-    rb.rbgs_sweep(ut, ft, sweeps, h=h, kernel="blocked", fuse=fuse, tile_rows=rows)
+    rb.rbgs_sweep(ut, ft, sweeps, h=h, kernel="blocked", fuse=fuse, tile_rows=rows,
+                  tile_waves=waves)
     got = host(ut)
     ref = u0.copy()
     oracle.sweep(ref, f, h, sweeps)
@@ -75,16 +77,17 @@ def test_blocked_sweep_bitwise(oracle, n, sweeps, fuse, rows, dtype):
 
 
 @pytest.mark.parametrize("delay", [3, 25])
-def test_blocked_delay_injection(oracle, delay):
+@pytest.mark.parametrize("waves", [1, 2])
+def test_blocked_delay_injection(oracle, delay, waves):
     """Pseudo-random stalls per work item reorder the execution; the bits
     must not change (the GPU form of the paper's hardware asynchronicity)."""
     n, sweeps = 700, 24
-    say(f"blocked delay={delay} n={n}")
+    say(f"blocked delay={delay} n={n} waves={waves}")
     h = W.spacing(n)
     u0, f = start(n, 5)
     ut, ft = dev(u0), dev(f)
     rb.rbgs_sweep(ut, ft, sweeps, h=h, kernel="blocked", fuse=4, tile_rows=16,
-                  debug_delay=delay)
+                  debug_delay=delay, tile_waves=waves)
     ref = u0.copy()
     oracle.sweep(ref, f, h, sweeps)
     assert np.array_equal(host(ut), ref)
@@ -101,16 +104,17 @@ def test_blocked_equals_plain_large():
     assert torch.equal(a, b)
 
 
-def test_watchdog_returns_timeout():
+@pytest.mark.parametrize("fuse,waves", [(1, 1), (2, 2)])
+def test_watchdog_returns_timeout(fuse, waves):
     """Tile 0 never publishes its progress; its neighbours' bounded waits
     expire, every wave leaves the kernel and the call reports a timeout."""
     n = 255
-    say("blocked watchdog (stalled tile, bounded waits)")
+    say(f"blocked watchdog (stalled tile, bounded waits) waves={waves}")
     u0, f = start(n, 3)
     ut, ft = dev(u0), dev(f)
     with pytest.raises(rb.RbgsError) as e:
-        rb.rbgs_sweep(ut, ft, 8, kernel="blocked", fuse=1, tile_rows=8, debug_stall_tile=1,
-                      debug_spin_limit=2000)
+        rb.rbgs_sweep(ut, ft, 4 * fuse, kernel="blocked", fuse=fuse, tile_rows=8,
+                      debug_stall_tile=1, debug_spin_limit=2000, tile_waves=waves)
     assert e.value.status == rb.rbgs.ETIMEOUT
     # the library stays usable afterwards
     ut, ft = dev(u0), dev(f)
