@@ -141,14 +141,6 @@ typedef struct {
                                for this batch shape (127 FP32 / 63 FP64, or
                                never), else never; -1 = never.  Ignored
                                elsewhere.                                       */
-    int32_t tile_waves;     /* BLOCKED, single grids: waves per tile.  1 = one
-                               wave runs all fused levels of a tile; 2 = the
-                               levels are split over the two waves of a
-                               workgroup (the front wave loads and runs the
-                               first half, the back wave the second half and
-                               stores), which leaves each wave half the
-                               registers; 0 = the library's choice.  Same
-                               results bit for bit.  Batches take 0 or 1.   */
 } rbgs_sweep_opts;
 
 /* Solve options.  Zero-initialise, then set what is needed. */

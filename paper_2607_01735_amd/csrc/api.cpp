@@ -168,8 +168,6 @@ int validate_sweep_opts(const rbgs_sweep_opts* o) {
         return fail(RBGS_EINVAL, "sweep options must be >= 0");
     if (o->rows_per_block > 4096) return fail(RBGS_EINVAL, "rows_per_block must be <= 4096");
     if (o->debug_delay > 1000) return fail(RBGS_EINVAL, "debug_delay must be <= 1000");
-    if (o->tile_waves < 0 || o->tile_waves > 2)
-        return fail(RBGS_EINVAL, "tile_waves must be 0, 1 or 2");
     return validate_blocked_opts(o->fuse, o->tile_rows, o->tile_cols, &g_last_error);
 }
 

@@ -497,8 +497,6 @@ int validate_batch(int32_t count, const rbgs_grid* grids, int dt, void* const* u
         if (o->tile_rows != 0 && (o->tile_rows < kMinRows || o->tile_rows > kMaxRows))
             return bfail(RBGS_EINVAL, "tile_rows must be in [8, 65536] (0 = default)");
         if (o->tile_cols != 0) return bfail(RBGS_EINVAL, "tile_cols must be 0");
-        if (o->tile_waves != 0 && o->tile_waves != 1)
-            return bfail(RBGS_EINVAL, "tile_waves must be 0 or 1 for batches");
         if (o->lds_max_n < -1) return bfail(RBGS_EINVAL, "lds_max_n must be >= -1");
         if (o->debug_delay < 0 || o->debug_delay > 1000 || o->debug_spin_limit < 0 ||
             o->debug_stall_tile < 0)

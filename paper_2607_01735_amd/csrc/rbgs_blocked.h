@@ -89,9 +89,8 @@ inline int single_grid_rows(int n, int L, int elem_bytes, int wave_slots) {
     return best;
 }
 
-// Resident workgroups per CU for a persistent kernel of `threads` threads
-// per workgroup (one wave by default), and CU count.
-hipError_t persistent_occupancy(const void* kernel, int* per_cu, int* cus, int threads = 64);
+// Resident one-wave workgroups per CU for a persistent kernel, and CU count.
+hipError_t persistent_occupancy(const void* kernel, int* per_cu, int* cus);
 // Waves the single-grid persistent kernel of this depth runs at once on the
 // current device (CUs x resident waves per CU); 1024 if the query fails.
 int blocked_wave_slots(size_t elem_bytes, int fuse);
@@ -103,7 +102,6 @@ struct BlockedParams {
     int delay = 0;      // debug: per-tile delay injection
     int spin_limit = 0; // debug: bound on each flag wait
     int stall_tile = 0; // debug: tile + 1 that never publishes its progress
-    int tile_waves = 1; // 1: one wave per tile; 2: levels split over two waves
     const int* stop = nullptr;  // converged flag of a graph-captured solve
     bool keep_error = false;    // the caller cleared the error word (graph rounds)
 };

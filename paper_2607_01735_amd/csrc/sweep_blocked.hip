@@ -40,7 +40,6 @@
 // order, from exactly the neighbour values a sequential red-black sweep
 // would use, so the result equals the plain kernel bit for bit.
 #include "blocked_pipeline.h"
-#include "blocked_split.h"
 #include "rbgs_blocked.h"
 #include "rbgs_internal.h"
 
@@ -61,32 +60,9 @@ __global__ __launch_bounds__(kLanes) void k_blocked(GridDesc<T> g, Queue qu) {
     }
 }
 
-// Two waves per tile: the fused levels split over the waves of a workgroup
-// (blocked_split.h).
-template <typename T, int V, int L>
-__global__ __launch_bounds__(kSplitThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_blocked_split(GridDesc<T> g, Queue qu) {
-    if (stopped(qu)) return;
-    persistent_split<T, V, L>(g, qu);
-}
-
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-template <typename T, int V, int L>
-hipError_t launch_split(const GridDesc<T>& g, const Queue& qu, hipStream_t s) {
-    int per_cu = 0, cus = 0;
-    hipError_t e = persistent_occupancy(reinterpret_cast<const void*>(&k_blocked_split<T, V, L>),
-                                        &per_cu, &cus, kSplitThreads);
-    if (e != hipSuccess) return e;
-    int64_t total = int64_t(qu.passes) * g.ntiles;
-    int64_t grid = int64_t(cus) * per_cu;
-    if (grid > total) grid = total;
-    if (grid < 1) grid = 1;
-    hipLaunchKernelGGL((k_blocked_split<T, V, L>), dim3(unsigned(grid)), dim3(kSplitThreads), 0, s,
-                       g, qu);
-    return hipGetLastError();
-}
-
 template <typename T, int V, int L>
 hipError_t launch_k(const GridDesc<T>& g, const Queue& qu, hipStream_t s) {
     int per_cu = 0, cus = 0;
@@ -101,22 +77,7 @@ hipError_t launch_k(const GridDesc<T>& g, const Queue& qu, hipStream_t s) {
 }
 
 template <typename T, int V>
-hipError_t launch_by_fuse(int fuse, int waves, const GridDesc<T>& g, const Queue& qu,
-                          hipStream_t s) {
-    if (waves == 2) {
-        switch (fuse) {  // a split needs at least two levels per wave
-            case 2: return launch_split<T, V, 4>(g, qu, s);
-            case 3: return launch_split<T, V, 6>(g, qu, s);
-            case 4: return launch_split<T, V, 8>(g, qu, s);
-            case 5: return launch_split<T, V, 10>(g, qu, s);
-            case 6: return launch_split<T, V, 12>(g, qu, s);
-            case 7: return launch_split<T, V, 14>(g, qu, s);
-            case 8: return launch_split<T, V, 16>(g, qu, s);
-            case 9: return launch_split<T, V, 18>(g, qu, s);
-            case 10: return launch_split<T, V, 20>(g, qu, s);
-            default: break;
-        }
-    }
+hipError_t launch_by_fuse(int fuse, const GridDesc<T>& g, const Queue& qu, hipStream_t s) {
     switch (fuse) {
         case 1: return launch_k<T, V, 2>(g, qu, s);
         case 2: return launch_k<T, V, 4>(g, qu, s);
@@ -133,13 +94,13 @@ hipError_t launch_by_fuse(int fuse, int waves, const GridDesc<T>& g, const Queue
 
 }  // namespace
 
-hipError_t persistent_occupancy(const void* kernel, int* per_cu, int* cus, int threads) {
+hipError_t persistent_occupancy(const void* kernel, int* per_cu, int* cus) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kernel, threads, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kernel, kLanes, 0);
     if (e != hipSuccess) return e;
     if (*per_cu < 1) *per_cu = 1;
     return hipSuccess;
@@ -216,7 +177,6 @@ BlockedParams blocked_params(int n, size_t elem_bytes, const rbgs_sweep_opts* o)
     bp.delay = o ? o->debug_delay : 0;
     bp.spin_limit = (o && o->debug_spin_limit > 0) ? o->debug_spin_limit : kDefaultSpinLimit;
     bp.stall_tile = o ? o->debug_stall_tile : 0;
-    bp.tile_waves = (o && o->tile_waves > 0) ? o->tile_waves : 1;
     return bp;
 }
 
@@ -317,7 +277,7 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
                 if (r != hipSuccess) return r;
                 started = true;
             }
-            r = launch_by_fuse<T, V>(fuse, bp.tile_waves, g, qu, s);
+            r = launch_by_fuse<T, V>(fuse, g, qu, s);
             if (r != hipSuccess) return r;
             *launches += 1;
             if (timed) {

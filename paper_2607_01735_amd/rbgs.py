@@ -55,8 +55,7 @@ class rbgs_sweep_opts(ctypes.Structure):
                 ("tile_rows", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
                 ("rows_per_block", ctypes.c_int32), ("debug_delay", ctypes.c_int32),
                 ("debug_spin_limit", ctypes.c_int32), ("debug_stall_tile", ctypes.c_int32),
-                ("timing", ctypes.POINTER(rbgs_timing)), ("lds_max_n", ctypes.c_int32),
-                ("tile_waves", ctypes.c_int32)]
+                ("timing", ctypes.POINTER(rbgs_timing)), ("lds_max_n", ctypes.c_int32)]
 
 
 class rbgs_solve_opts(ctypes.Structure):
@@ -269,11 +268,9 @@ def _workspace(grid, code, device, precision=PREC_F64, workspace=None):
 
 
 def _sweep_opts(kernel="auto", fuse=0, tile_rows=0, tile_cols=0, rows_per_block=0,
-                debug_delay=0, debug_spin_limit=0, debug_stall_tile=0, timing=None, lds_max_n=0,
-                tile_waves=0):
+                debug_delay=0, debug_spin_limit=0, debug_stall_tile=0, timing=None, lds_max_n=0):
     o = rbgs_sweep_opts()
     o.lds_max_n = lds_max_n
-    o.tile_waves = tile_waves
     o.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     o.fuse, o.tile_rows, o.tile_cols = fuse, tile_rows, tile_cols
     o.rows_per_block, o.debug_delay, o.debug_spin_limit = rows_per_block, debug_delay, debug_spin_limit

@@ -1,10 +1,9 @@
 // Host stand-in for the few HIP device features the persistent tile
-// pipelines (paper_2607_01735_amd/csrc/blocked_pipeline.h and
-// blocked_split.h) use, so that their indexing, data flow and dependency
-// protocol can be compiled for the CPU and checked with a sanitizer against
-// the oracle.
+// pipeline (paper_2607_01735_amd/csrc/blocked_pipeline.h) uses, so that its
+// indexing, data flow and dependency protocol can be compiled for the CPU
+// and checked with a sanitizer against the oracle.
 //
-// One workgroup = 64 or 128 lanes (one or two waves) run as cooperative
+// One workgroup = up to 128 lanes (one or two waves) run as cooperative
 // fibers on one host thread; several workgroups are several host threads
 // that share the grid arrays, tickets and progress flags through real
 // atomics.  Inside a workgroup a cross-lane operation (DPP shift, vote,

@@ -1,8 +1,7 @@
 // Runs the persistent tile pipeline of the blocked sweep (the device code in
-// paper_2607_01735_amd/csrc/blocked_pipeline.h, and with EMU_WAVES=2 the
-// two-wave tiles of blocked_split.h, unchanged) on the CPU.  Each emulated
-// workgroup (64 lanes, or 128 with EMU_WAVES=2, as fibers) runs on its own
-// host thread and takes (pass, tile) tickets from the shared counter exactly
+// paper_2607_01735_amd/csrc/blocked_pipeline.h, unchanged) on the CPU.  Each
+// emulated workgroup (one wave: 64 lanes as fibers) runs on its own host
+// thread and takes (pass, tile) tickets from the shared counter exactly
 // as a workgroup of the persistent kernel would; the progress flags,
 // tickets and grid arrays are shared between the threads through the same
 // atomic operations and fences the device code uses.  Every array the
@@ -13,7 +12,7 @@
 // tests/test_tile_pipeline_emu.py builds it and compares the result with the
 // oracle bit for bit.
 //
-// Build: g++ -std=c++17 -DEMU_T=double -DEMU_FUSE=7 [-DEMU_WAVES=2] -I tests/emu
+// Build: g++ -std=c++17 -DEMU_T=double -DEMU_FUSE=7 -I tests/emu
 //            -I paper_2607_01735_amd/csrc -I include ...
 // Run:   emu n rows passes h in.bin out.bin [workgroups [yield_every]]
 //   in.bin  = u then f, natural (n+2) x (n+2) arrays of EMU_T, row major
@@ -27,12 +26,7 @@
 #include <vector>
 
 #include "blocked_pipeline.h"
-#include "blocked_split.h"
 #include "rbgs_blocked.h"
-
-#ifndef EMU_WAVES
-#define EMU_WAVES 1
-#endif
 
 namespace emu {
 thread_local int nthreads = kLanes;
@@ -82,9 +76,6 @@ static void lane_start(int lane) {
 #endif
         swapcontext(&g_start_ctx[lane], &g_host_ctx);
     }
-#if EMU_WAVES == 2
-    persistent_split<T, kV, kL>(g_grid, g_queue);
-#else
     const int total = g_queue.passes * g_grid.ntiles;
     for (;;) {
         const int tk = next_ticket(g_queue);
@@ -92,7 +83,6 @@ static void lane_start(int lane) {
         const int pass = tk / g_grid.ntiles;
         if (!run_item<T, kV, kL>(g_grid, g_queue, pass, tk - pass * g_grid.ntiles)) break;
     }
-#endif
     emu::lane_done[lane] = true;
     for (int k = 1; k < emu::nthreads; ++k) {
         const int nx = (lane + k) % emu::nthreads;
@@ -103,7 +93,7 @@ static void lane_start(int lane) {
 
 // One workgroup on this host thread: park every lane, then run them.
 static void run_workgroup() {
-    emu::nthreads = 64 * EMU_WAVES;
+    emu::nthreads = emu::kLanes;
     emu::current = 0;
     emu::bar_arrived = emu::bar_generation = 0;
 #ifdef EMU_TSAN
@@ -233,8 +223,8 @@ int main(int argc, char** argv) {
     FILE* fout = fopen(argv[6], "wb");
     if (!fout || fwrite(u.data(), sizeof(T), u.size(), fout) != u.size()) return 2;
     fclose(fout);
-    printf("n=%d rows=%d passes=%d fuse=%d waves=%d workgroups=%d tiles=%d halo_q=%d q_core=%d\n",
-           n, geo.rows, passes, kFuse, EMU_WAVES, workgroups, geo.ntiles, geo.halo_q, geo.q_core);
+    printf("n=%d rows=%d passes=%d fuse=%d workgroups=%d tiles=%d halo_q=%d q_core=%d\n", n,
+           geo.rows, passes, kFuse, workgroups, geo.ntiles, geo.halo_q, geo.q_core);
     for (int b = 0; b < 2; ++b) {
         free(red[b]);
         free(black[b]);

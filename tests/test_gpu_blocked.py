@@ -60,15 +60,13 @@ CASES = [  # n, sweeps, fuse, tile_rows (0 = default)
 
 @pytest.mark.parametrize("n,sweeps,fuse,rows", CASES)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-@pytest.mark.parametrize("waves", [1, 2])
-def test_blocked_sweep_bitwise(oracle, n, sweeps, fuse, rows, dtype, waves):
-    say(f"blocked n={n} sweeps={sweeps} fuse={fuse} rows={rows} {dtype.__name__} waves={waves}")
+def test_blocked_sweep_bitwise(oracle, n, sweeps, fuse, rows, dtype):
+    say(f"blocked n={n} sweeps={sweeps} fuse={fuse} rows={rows} {dtype.__name__}")
     h = W.spacing(n)
     ld = n + 2 + (n % 5)
     u0, f = start(n, n, ld=ld, dtype=dtype)
     ut, ft = dev(u0), dev(f)
-    rb.rbgs_sweep(ut, ft, sweeps, h=h, kernel="blocked", fuse=fuse, tile_rows=rows,
-                  tile_waves=waves)
+    rb.rbgs_sweep(ut, ft, sweeps, h=h, kernel="blocked", fuse=fuse, tile_rows=rows)
     got = host(ut)
     ref = u0.copy()
     oracle.sweep(ref, f, h, sweeps)
@@ -77,17 +75,16 @@ def test_blocked_sweep_bitwise(oracle, n, sweeps, fuse, rows, dtype, waves):
 
 
 @pytest.mark.parametrize("delay", [3, 25])
-@pytest.mark.parametrize("waves", [1, 2])
-def test_blocked_delay_injection(oracle, delay, waves):
+def test_blocked_delay_injection(oracle, delay):
     """Pseudo-random stalls per work item reorder the execution; the bits
     must not change (the GPU form of the paper's hardware asynchronicity)."""
     n, sweeps = 700, 24
-    say(f"blocked delay={delay} n={n} waves={waves}")
+    say(f"blocked delay={delay} n={n}")
     h = W.spacing(n)
     u0, f = start(n, 5)
     ut, ft = dev(u0), dev(f)
     rb.rbgs_sweep(ut, ft, sweeps, h=h, kernel="blocked", fuse=4, tile_rows=16,
-                  debug_delay=delay, tile_waves=waves)
+                  debug_delay=delay)
     ref = u0.copy()
     oracle.sweep(ref, f, h, sweeps)
     assert np.array_equal(host(ut), ref)
@@ -104,17 +101,17 @@ def test_blocked_equals_plain_large():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("fuse,waves", [(1, 1), (2, 2)])
-def test_watchdog_returns_timeout(fuse, waves):
+@pytest.mark.parametrize("fuse", [1, 2])
+def test_watchdog_returns_timeout(fuse):
     """Tile 0 never publishes its progress; its neighbours' bounded waits
     expire, every wave leaves the kernel and the call reports a timeout."""
     n = 255
-    say(f"blocked watchdog (stalled tile, bounded waits) waves={waves}")
+    say(f"blocked watchdog (stalled tile, bounded waits) fuse={fuse}")
     u0, f = start(n, 3)
     ut, ft = dev(u0), dev(f)
     with pytest.raises(rb.RbgsError) as e:
         rb.rbgs_sweep(ut, ft, 4 * fuse, kernel="blocked", fuse=fuse, tile_rows=8,
-                      debug_stall_tile=1, debug_spin_limit=2000, tile_waves=waves)
+                      debug_stall_tile=1, debug_spin_limit=2000)
     assert e.value.status == rb.rbgs.ETIMEOUT
     # the library stays usable afterwards
     ut, ft = dev(u0), dev(f)

@@ -1,13 +1,11 @@
 """The blocked sweep's tile pipelines, run on the CPU, against the oracle.
 
-The persistent kernels' device code (`csrc/blocked_pipeline.h`: tiles,
+The persistent kernel's device code (`csrc/blocked_pipeline.h`: tiles,
 overlapped halos, the row pipeline of L half-sweeps, the LDS ring of h^2 f,
-ping-pong buffers, progress flags and tickets; `csrc/blocked_split.h`: the
-same levels split over the two waves of a workgroup) is compiled unchanged
-for the host against a small stand-in for HIP's device features
-(`tests/emu/hip/hip_runtime.h`: a workgroup = 64 or 128 lanes as fibers,
-cross-lane operations and fences as wave barriers, __syncthreads as a
-workgroup barrier).  Since any schedule that honours the tile dependencies
+ping-pong buffers, progress flags and tickets) is compiled unchanged for
+the host against a small stand-in for HIP's device features
+(`tests/emu/hip/hip_runtime.h`: a workgroup = a wave of 64 lanes as fibers,
+cross-lane operations and fences as wave barriers).  Since any schedule that honours the tile dependencies
 computes the sequential red-black sweep (Section 2.3), the result must
 equal the oracle's sweeps bit for bit.
 
@@ -42,28 +40,25 @@ SRC = os.path.join(ROOT, "tests", "emu", "tile_pipeline_emu.cpp")
 INCLUDES = [os.path.join(ROOT, "tests", "emu"), os.path.join(ROOT, "paper_2607_01735_amd", "csrc"),
             os.path.join(ROOT, "include")]
 
-# dtype, fuse, n, rows, passes, waves per tile, workgroups, sanitizer, prefetch (0 = library's)
+# dtype, fuse, n, rows, passes, workgroups, sanitizer, prefetch steps (0 = the library's)
 CASES = [
-    (np.float64, 7, 63, 64, 2, 1, 1, "address", 0),     # one edge tile, taller than the grid
-    (np.float64, 7, 520, 16, 2, 1, 1, "address", 0),    # 33 strips x 3 bands, interior tiles
-    (np.float64, 1, 37, 8, 3, 1, 1, "address", 0),      # shallowest pipeline (L = 2), smallest ring
-    (np.float32, 4, 1030, 16, 2, 1, 1, "address", 0),   # FP32 vectors of 4, interior tiles
-    (np.float64, 7, 63, 64, 2, 2, 1, "address", 0),     # two-wave tiles: one edge tile
-    (np.float64, 7, 300, 16, 2, 2, 1, "address", 0),    # two-wave tiles, interior tiles
-    (np.float32, 4, 300, 16, 2, 2, 1, "address", 0),    # two-wave tiles in FP32
-    (np.float64, 2, 40, 8, 3, 1, 3, "thread", 0),       # three workgroups, short tiles
-    (np.float64, 2, 40, 8, 3, 2, 3, "thread", 0),       # the same with two-wave tiles
-    (np.float64, 3, 150, 8, 3, 1, 4, "thread", 0),      # 19 strips x 2 bands, four workgroups
-    (np.float32, 5, 7, 10, 3, 1, 3, "thread", 4),       # removed four-step prefetch, one tile
-    (np.float32, 5, 7, 10, 3, 1, 3, "thread", 0),       # the kept depth on the same grid
+    (np.float64, 7, 63, 64, 2, 1, "address", 0),     # one edge tile, taller than the grid
+    (np.float64, 7, 520, 16, 2, 1, "address", 0),    # 33 strips x 3 bands, interior tiles
+    (np.float64, 1, 37, 8, 3, 1, "address", 0),      # shallowest pipeline (L = 2), smallest ring
+    (np.float32, 4, 1030, 16, 2, 1, "address", 0),   # FP32 vectors of 4, interior tiles
+    (np.float64, 2, 40, 8, 3, 3, "thread", 0),       # three workgroups, short tiles
+    (np.float64, 3, 150, 8, 3, 4, "thread", 0),      # 19 strips x 2 bands, four workgroups
+    (np.float64, 7, 130, 16, 3, 3, "thread", 0),     # the 8191^2 depth, 9 strips x 2 bands
+    (np.float32, 5, 7, 10, 3, 3, "thread", 4),       # removed four-step prefetch, one tile
+    (np.float32, 5, 7, 10, 3, 3, "thread", 0),       # the kept depth on the same grid
 ]
 
 pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 
 
 def _key(case):
-    dtype, fuse, _, _, _, waves, _, san, pre = case
-    return (np.dtype(dtype).name, fuse, waves, san, pre)
+    dtype, fuse, _, _, _, _, san, pre = case
+    return (np.dtype(dtype).name, fuse, san, pre)
 
 
 @pytest.fixture(scope="module")
@@ -74,13 +69,12 @@ def emulators(tmp_path_factory):
         key = _key(case)
         if key in built:
             continue
-        name, fuse, waves, san, pre = key
-        exe = out / f"emu_{name}_{fuse}_{waves}_{san}_{pre}"
+        name, fuse, san, pre = key
+        exe = out / f"emu_{name}_{fuse}_{san}_{pre}"
         # no _FORTIFY_SOURCE: its longjmp check rejects the jumps between fiber stacks
         cmd = ["g++", "-std=c++17", "-O1", "-g", "-ffp-contract=off", "-U_FORTIFY_SOURCE",
                f"-fsanitize={san}", "-fno-omit-frame-pointer",
-               f"-DEMU_T={'double' if name == 'float64' else 'float'}", f"-DEMU_FUSE={fuse}",
-               f"-DEMU_WAVES={waves}"]
+               f"-DEMU_T={'double' if name == 'float64' else 'float'}", f"-DEMU_FUSE={fuse}"]
         if pre:
             cmd.append(f"-DRBGS_EMU_PREFETCH_STEPS={pre}")
         cmd += [f"-I{d}" for d in INCLUDES] + [SRC, "-o", str(exe), "-lpthread"]
@@ -92,9 +86,9 @@ def emulators(tmp_path_factory):
 
 @pytest.mark.slow
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(str(x) for x in _key(c)) +
-                         f"-n{c[2]}-r{c[3]}-p{c[4]}-wg{c[6]}")
+                         f"-n{c[2]}-r{c[3]}-p{c[4]}-wg{c[5]}")
 def test_tile_pipeline_matches_oracle(oracle, emulators, case):
-    dtype, fuse, n, rows, passes, waves, wgs, san, pre = case
+    dtype, fuse, n, rows, passes, wgs, san, pre = case
     out, built = emulators
     h = W.spacing(n)
     u0 = W.random_ring(n, seed=n)
