@@ -131,69 +131,86 @@ def param_names(channels=CHANNELS):
     return names
 
 
-def forward(p, x0, channels=CHANNELS, factor=2):
+def _keep(x):
+    return x
+
+
+def forward(p, x0, channels=CHANNELS, factor=2, rnd=None):
     """Normalised network output y (N x N) for normalised input x0 (N x N);
-    returns (y, cache) where cache holds what the backward pass needs."""
+    returns (y, cache) where cache holds what the backward pass needs.
+
+    rnd (optional): a rounding applied to every stored activation (each
+    layer's ReLU output, each restriction and prolongation), for comparing
+    with an implementation that stores activations in a narrower format;
+    the arithmetic itself stays FP64.  None keeps every value."""
+    rnd = rnd or _keep
     L = len(channels)
     cache = {"x0": x0}
     inp = x0[None]
     enc = []
     for l in range(L):
         z0 = conv3x3(inp, p[f"enc{l}.0.w"], p[f"enc{l}.0.b"])
-        a0 = np.maximum(z0, 0.0)
+        a0 = rnd(np.maximum(z0, 0.0))
         z1 = conv3x3(a0, p[f"enc{l}.1.w"], p[f"enc{l}.1.b"])
-        a1 = np.maximum(z1, 0.0)
+        a1 = rnd(np.maximum(z1, 0.0))
         cache[f"enc{l}"] = (inp, z0, a0, z1)
         enc.append(a1)
         if l + 1 < L:
-            inp = restrict(a1, factor)
+            inp = rnd(restrict(a1, factor))
     d = enc[-1]
     for l in range(L - 2, -1, -1):
-        up = prolong(d, enc[l].shape[1], factor)
+        up = rnd(prolong(d, enc[l].shape[1], factor))
         cat = np.concatenate([up, enc[l]], axis=0)
         z0 = conv3x3(cat, p[f"dec{l}.0.w"], p[f"dec{l}.0.b"])
-        a0 = np.maximum(z0, 0.0)
+        a0 = rnd(np.maximum(z0, 0.0))
         z1 = conv3x3(a0, p[f"dec{l}.1.w"], p[f"dec{l}.1.b"])
-        d = np.maximum(z1, 0.0)
+        d = rnd(np.maximum(z1, 0.0))
         cache[f"dec{l}"] = (cat, z0, a0, z1, up.shape[0])
     y = np.tensordot(p["head.w"][0, :, 0, 0], d, axes=(0, 0)) + p["head.b"][0]
     cache["d0"] = d
     return y, cache
 
 
-def backward(p, cache, dy, channels=CHANNELS, factor=2):
-    """Gradients of a loss with dL/dy = dy with respect to every parameter."""
+def backward(p, cache, dy, channels=CHANNELS, factor=2, rnd=None):
+    """Gradients of a loss with dL/dy = dy with respect to every parameter.
+
+    rnd (optional): a rounding applied to every stored activation gradient
+    (the gradients reaching each layer's input, each restriction's output,
+    and a skip connection's gradient once the path from the level below is
+    added to it), matching forward's rnd; the arithmetic stays FP64."""
+    rnd = rnd or _keep
     L = len(channels)
     g = {}
     d0 = cache["d0"]
     g["head.w"] = np.tensordot(dy, d0, axes=([0, 1], [1, 2]))[None, :, None, None]
     g["head.b"] = np.array([dy.sum()])
-    grad_d = p["head.w"][0, :, 0, 0][:, None, None] * dy[None]
+    grad_d = rnd(p["head.w"][0, :, 0, 0][:, None, None] * dy[None])
     denc = [0.0] * L  # gradients reaching e_l through the skip connections
     # the decoder ran from level L-2 down to 0: walk it back from level 0 up
     for l in range(0, L - 1):
         cat, z0, a0, z1, cup = cache[f"dec{l}"]
         dz1 = grad_d * (z1 > 0)
         da0, g[f"dec{l}.1.w"], g[f"dec{l}.1.b"] = conv3x3_backward(a0, p[f"dec{l}.1.w"], dz1)
-        dz0 = da0 * (z0 > 0)
+        dz0 = rnd(da0) * (z0 > 0)
         dcat, g[f"dec{l}.0.w"], g[f"dec{l}.0.b"] = conv3x3_backward(cat, p[f"dec{l}.0.w"], dz0)
+        dcat = rnd(dcat)
         dup, denc_l = dcat[:cup], dcat[cup:]
         denc[l] = denc[l] + denc_l
         # up = P(d_{l+1}) with P = F^2 R^T, so dL/dd_{l+1} = F^2 R(dup)
-        grad_d = float(factor * factor) * restrict(dup, factor)
+        grad_d = rnd(float(factor * factor) * restrict(dup, factor))
     denc[L - 1] = grad_d
     # encoder, from the bottom level up
     carry = None
     for l in range(L - 1, -1, -1):
         inp, z0, a0, z1 = cache[f"enc{l}"]
-        da1 = denc[l] + (carry if carry is not None else 0.0)
+        da1 = denc[l] if carry is None else rnd(denc[l] + carry)
         dz1 = da1 * (z1 > 0)
         da0, g[f"enc{l}.1.w"], g[f"enc{l}.1.b"] = conv3x3_backward(a0, p[f"enc{l}.1.w"], dz1)
-        dz0 = da0 * (z0 > 0)
+        dz0 = rnd(da0) * (z0 > 0)
         dinp, g[f"enc{l}.0.w"], g[f"enc{l}.0.b"] = conv3x3_backward(inp, p[f"enc{l}.0.w"], dz0)
         if l > 0:
             # inp = R(e_{l-1})
-            carry = restrict_transpose(dinp, cache[f"enc{l - 1}"][1].shape[1], factor)
+            carry = restrict_transpose(rnd(dinp), cache[f"enc{l - 1}"][1].shape[1], factor)
     return g
 
 

@@ -20,6 +20,7 @@
 // BF16 MFMA: pixels x output channels, K = 9 taps x input channels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -129,10 +130,12 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
     }
 }
 
-// Weight gradient dW[co][ci][tap] += sum_p dZ[p][co] * X[p + off(tap)][ci],
+// Weight gradient dW[co][ci][tap] = sum_p dZ[p][co] * X[p + off(tap)][ci],
 // dZ = dY masked by (Y > 0).  MFMA with M = 16 output channels, N = 16
-// input channels, K = 16 pixels of a row; one wave per (row block, tap,
-// ci tile, co tile), partial sums added atomically in FP32.
+// input channels, K = 16 pixels of a row; one wave per (sample, row block,
+// tap, ci tile, co tile).  Each wave stores its partial sums in its own slot
+// (part[sample * rblocks + row block][co][ci][tap]); k_reduce_parts adds the
+// slots in a fixed order, so the gradient has the same bits on every run.
 struct WGradArgs {
     const bf16* x;
     int64_t xs;
@@ -140,7 +143,7 @@ struct WGradArgs {
     int64_t dys;
     const bf16* y;  // layer output (mask), stride ys
     int64_t ys;
-    float* dw;      // [cout][cin_w][9]
+    float* part;    // [batch * row blocks][cout][cin_w][9] partial sums
     int batch, h, wd, cin, cout, rows_per_wave;
     int cin_w;      // input channels of the weight tensor (cin is padded to 16)
 };
@@ -191,14 +194,16 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(WGradArgs a) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int co = co_t * 16 + mq + i, ci = ci_t * 16 + n;
-        if (ci < a.cin_w) atomicAdd(a.dw + (int64_t(co) * a.cin_w + ci) * 9 + tap, acc[i]);
+        const int64_t slot = int64_t(b) * rblocks + rb;
+        if (ci < a.cin_w)
+            a.part[((slot * a.cout + co) * a.cin_w + ci) * 9 + tap] = acc[i];
     }
 }
 
-// Bias gradient db[c] += sum_p dY[p][c] (Y[p][c] > 0); one block per row.
+// Bias gradient: per row (one block each) part[row][c] = sum over the row
+// of dY[p][c] where Y[p][c] > 0; k_reduce_parts adds the rows in order.
 __global__ __launch_bounds__(256) void k_bias_grad(const bf16* dy, int64_t dys, const bf16* y,
-                                                   int64_t ys, float* db, int rows, int wd,
-                                                   int c) {
+                                                   int64_t ys, float* part, int wd, int c) {
     const int64_t row = blockIdx.x;
     for (int ch = threadIdx.x; ch < c; ch += 256) {
         float s = 0.f;
@@ -206,9 +211,28 @@ __global__ __launch_bounds__(256) void k_bias_grad(const bf16* dy, int64_t dys, 
             const int64_t p = row * wd + x;
             if (bf2f(y[p * ys + ch]) > 0.f) s += bf2f(dy[p * dys + ch]);
         }
-        atomicAdd(db + ch, s);
+        part[row * c + ch] = s;
     }
-    (void)rows;
+}
+
+// out[e] = sum over slots k = 0 .. nparts-1 of part[k * count + e], in a
+// fixed order: one block per element, thread t adds slots t, t + 256, ...
+// in turn, then a fixed tree over the block (no atomics: the same bits on
+// every run).
+__global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ part,
+                                                      int64_t nparts, int64_t count,
+                                                      float* __restrict__ out) {
+    const int64_t e = blockIdx.x;
+    float s = 0.f;
+    for (int64_t k = threadIdx.x; k < nparts; k += 256) s += part[k * count + e];
+    __shared__ float sh[256];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (int(threadIdx.x) < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[e] = sh[0];
 }
 
 // Grid transfers between levels coarsened by a factor F (2 or 4): fine
@@ -345,7 +369,7 @@ __global__ __launch_bounds__(256) void k_output(const float* y, const float* rms
 // MSE against u*/rms: dy = 2 (y - t) / count, loss accumulated in FP32.
 __global__ __launch_bounds__(256) void k_mse(const float* y, const double* u, const float* rms,
                                              int n, int64_t ld, int64_t gstride, int batch,
-                                             float* dy, float* loss) {
+                                             float* dy, float* loss_part) {
     const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
     const int64_t count = int64_t(batch) * n * n;
     float d = 0.f;
@@ -364,13 +388,15 @@ __global__ __launch_bounds__(256) void k_mse(const float* y, const double* u, co
         if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(loss, sh[0] / float(count));
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = sh[0] / float(count);
 }
 
-// Head backward: dd[p][c] = w[c] dy[p] (BF16); dw[c] += sum dy d; db += sum dy.
+// Head backward: dd[p][c] = w[c] dy[p] (BF16); per block, the partial sums
+// of dy d[c] (c < 16) and of dy go to part[block][0..16] (k_reduce_parts
+// adds the blocks in order into dw[0..15], db = dw[16]).
 __global__ __launch_bounds__(256) void k_head_grad(const bf16* d, int64_t ds, const float* w,
                                                    const float* dy, bf16* dd, int64_t dds,
-                                                   float* dw, float* db, int64_t npix, int c) {
+                                                   float* part, int64_t npix, int c) {
     const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
     __shared__ float sw[17][256];
     const bool ok = p < npix;
@@ -387,8 +413,8 @@ __global__ __launch_bounds__(256) void k_head_grad(const bf16* d, int64_t ds, co
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        for (int ch = 0; ch < c; ++ch) atomicAdd(dw + ch, sw[ch][0]);
-        atomicAdd(db, sw[16][0]);
+        for (int ch = 0; ch < 16; ++ch) part[int64_t(blockIdx.x) * 17 + ch] = ch < c ? sw[ch][0] : 0.f;
+        part[int64_t(blockIdx.x) * 17 + 16] = sw[16][0];
     }
 }
 
@@ -407,14 +433,17 @@ __global__ __launch_bounds__(256) void k_prep_weights(const float* w, int cout, 
     if (wb && ci < cin) wb[(int64_t(ci) * 9 + (8 - tap)) * cout + co] = f2bf(v);
 }
 
+// Adam: b1, b2 and their complements 1 - b1, 1 - b2 and the bias corrections
+// c1 = 1 - b1^t, c2 = 1 - b2^t are formed in FP64 on the host and rounded
+// once (1 - b2^t in binary32 loses four digits to cancellation at small t).
 __global__ __launch_bounds__(256) void k_adam(float* p, const float* g, float* m, float* v,
-                                              int64_t count, float lr, float b1, float b2,
-                                              float eps, float c1, float c2) {
+                                              int64_t count, float lr, float b1, float omb1,
+                                              float b2, float omb2, float eps, float c1, float c2) {
     const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (k >= count) return;
     const float gk = g[k];
-    const float mk = b1 * m[k] + (1.f - b1) * gk;
-    const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+    const float mk = b1 * m[k] + omb1 * gk;
+    const float vk = b2 * v[k] + omb2 * gk * gk;
     m[k] = mk;
     v[k] = vk;
     p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
@@ -493,6 +522,8 @@ struct Net {
     std::vector<Layer> layers;
     size_t nparam;
     float *param, *grad, *m, *v, *rms, *loss, *y, *dy;
+    float* parts = nullptr;  // partial sums of the fixed-order gradient reductions
+    size_t parts_floats = 0;
     double* guess;  // natural-layout scratch grid for the learned solve
     int adam_t = 0;
     // activations (level-indexed) and their gradients
@@ -506,6 +537,25 @@ namespace {
 
 int cat_channels(int l) { return kC[l + 1] + kC[l]; }
 int in_channels(int l) { return l == 0 ? 16 : kC[l - 1]; }
+
+int wgrad_rows_per_wave(int h) { return h >= 128 ? 4 : (h >= 64 ? 8 : 16); }
+
+// Floats of partial sums the largest fixed-order reduction needs: weight
+// gradients (batch x row blocks slots of cout x cin x 9), bias gradients
+// (batch x rows slots of cout), the head (blocks of 17) and the loss.
+size_t parts_floats(const Net& net) {
+    size_t most = 0;
+    const size_t B = size_t(net.batch);
+    for (const auto& l : net.layers) {
+        const int h = net.n[l.level];
+        const size_t rb = size_t((h + wgrad_rows_per_wave(h) - 1) / wgrad_rows_per_wave(h));
+        most = std::max(most, B * rb * size_t(l.cout) * size_t(l.cin) * 9);
+        most = std::max(most, B * size_t(h) * size_t(l.cout));
+    }
+    const size_t px0 = B * size_t(net.n[0]) * size_t(net.n[0]);
+    most = std::max(most, (px0 + 255) / 256 * 17);
+    return most;
+}
 
 // Carves every buffer; with base == nullptr only computes the size.
 size_t carve(Net& net, char* base) {
@@ -529,6 +579,8 @@ size_t carve(Net& net, char* base) {
     const int64_t px0 = int64_t(net.n[0]) * net.n[0];
     net.y = reinterpret_cast<float*>(take(B * px0 * 4));
     net.dy = reinterpret_cast<float*>(take(B * px0 * 4));
+    net.parts_floats = parts_floats(net);
+    net.parts = reinterpret_cast<float*>(take(net.parts_floats * 4));
     net.guess = reinterpret_cast<double*>(take(size_t(net.n[0] + 2) * (net.n[0] + 2) * 8));
     for (int l = 0; l < kLevels; ++l) {
         const int64_t px = B * net.n[l] * net.n[l];
@@ -598,16 +650,23 @@ hipError_t wgrad(const Net& net, const Layer& L, const bf16* x, int64_t xs, cons
     a.h = a.wd = net.n[L.level];
     a.cin = L.cin_p;
     a.cout = L.cout;
-    a.rows_per_wave = a.h >= 128 ? 4 : (a.h >= 64 ? 8 : 16);
+    a.rows_per_wave = wgrad_rows_per_wave(a.h);
     a.cin_w = L.cin;  // the first layer's padded input channels feed no weight
-    a.dw = net.grad + L.w_off;
+    a.part = net.parts;
     const int rb = (a.h + a.rows_per_wave - 1) / a.rows_per_wave;
     const int64_t waves = int64_t(batch) * rb * 9 * (a.cin / 16) * (a.cout / 16);
     hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const int64_t wcount = int64_t(L.cout) * L.cin * 9;
+    hipLaunchKernelGGL(k_reduce_parts, dim3(unsigned(wcount)), dim3(256), 0, s, net.parts,
+                       int64_t(batch) * rb, wcount, net.grad + L.w_off);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_bias_grad, dim3(unsigned(int64_t(batch) * a.h)), dim3(256), 0, s, dy, dys,
-                       y, ys, net.grad + L.b_off, batch * a.h, a.wd, L.cout);
+                       y, ys, net.parts, a.wd, L.cout);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_parts, dim3(unsigned(L.cout)), dim3(256), 0, s, net.parts,
+                       int64_t(batch) * a.h, int64_t(L.cout), net.grad + L.b_off);
     return hipGetLastError();
 }
 
@@ -705,9 +764,13 @@ hipError_t backward(Net& net, int batch, hipStream_t s) {
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(int64_t(net.nparam))), dim3(256), 0, s,
                        reinterpret_cast<uint32_t*>(net.grad), int64_t(net.nparam));
     NN_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_head_grad, dim3(blocks_for(int64_t(batch) * n0 * n0)), dim3(256), 0, s,
-                       net.d[0], kC[0], net.param + hw, net.dy, net.gd[0], kC[0], net.grad + hw,
-                       net.grad + hw + 16, int64_t(batch) * n0 * n0, kC[0]);
+    const unsigned hblocks = blocks_for(int64_t(batch) * n0 * n0);
+    hipLaunchKernelGGL(k_head_grad, dim3(hblocks), dim3(256), 0, s, net.d[0], kC[0],
+                       net.param + hw, net.dy, net.gd[0], kC[0], net.parts,
+                       int64_t(batch) * n0 * n0, kC[0]);
+    NN_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_parts, dim3(17), dim3(256), 0, s, net.parts, int64_t(hblocks),
+                       int64_t(17), net.grad + hw);
     NN_TRY(hipGetLastError());
     // decoder, from level 0 (computed last) up
     for (int l = 0; l < kLevels - 1; ++l) {
@@ -753,10 +816,11 @@ hipError_t backward(Net& net, int batch, hipStream_t s) {
 
 hipError_t adam(Net& net, float lr, hipStream_t s) {
     net.adam_t += 1;
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.f - std::pow(b1, float(net.adam_t)), c2 = 1.f - std::pow(b2, float(net.adam_t));
+    const double b1 = 0.9, b2 = 0.999, t = double(net.adam_t);
+    const double c1 = -std::expm1(t * std::log(b1)), c2 = -std::expm1(t * std::log(b2));
     hipLaunchKernelGGL(k_adam, dim3(blocks_for(int64_t(net.nparam))), dim3(256), 0, s, net.param,
-                       net.grad, net.m, net.v, int64_t(net.nparam), lr, b1, b2, 1e-8f, c1, c2);
+                       net.grad, net.m, net.v, int64_t(net.nparam), lr, float(b1), float(1.0 - b1),
+                       float(b2), float(1.0 - b2), 1e-8f, float(c1), float(c2));
     NN_TRY(hipGetLastError());
     return prep_weights(net, s);
 }
@@ -907,10 +971,12 @@ int rbgs_unet_train_step(rbgs_unet* u, int32_t batch, const double* f, const dou
     const int n0 = net.n[0];
     int rc = nn::nn_hip(nn::forward(net, batch, f, ld, gs, s), "forward");
     if (rc) return rc;
-    hipLaunchKernelGGL(nn::k_fill, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t*>(net.loss),
-                       int64_t(1));
-    hipLaunchKernelGGL(nn::k_mse, dim3(nn::blocks_for(int64_t(batch) * n0 * n0)), dim3(256), 0, s,
-                       net.y, target, net.rms, n0, ld, gs, batch, net.dy, net.loss);
+    const unsigned mblocks = nn::blocks_for(int64_t(batch) * n0 * n0);
+    hipLaunchKernelGGL(nn::k_mse, dim3(mblocks), dim3(256), 0, s, net.y, target, net.rms, n0, ld,
+                       gs, batch, net.dy, net.parts);
+    if ((rc = nn::nn_hip(hipGetLastError(), "loss"))) return rc;
+    hipLaunchKernelGGL(nn::k_reduce_parts, dim3(1), dim3(256), 0, s, net.parts, int64_t(mblocks),
+                       int64_t(1), net.loss);
     if ((rc = nn::nn_hip(hipGetLastError(), "loss"))) return rc;
     if ((rc = nn::nn_hip(nn::backward(net, batch, s), "backward"))) return rc;
     if (update && (rc = nn::nn_hip(nn::adam(net, lr, s), "adam"))) return rc;

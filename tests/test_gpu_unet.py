@@ -1,12 +1,15 @@
 """GPU U-Net kernels against the FP64 reference network (oracle/unet_ref.py).
 
-The GPU path keeps weights and activations in bfloat16 and accumulates in
-FP32, so it is compared with the reference run on bfloat16-rounded weights
-and inputs, within tolerances set by bfloat16 rounding through ~15 layers:
-forward relative L2 error <= 3e-2, gradients per parameter tensor with
-cosine >= 0.99 and relative norm error <= 0.1.  The learned solve's choice
-rule is checked exactly: the final iterate is the oracle's solve from the
-chosen start, bit for bit.
+The GPU path keeps conv weights and activations in bfloat16 and accumulates
+in FP32 (FP32 masters, biases and head).  The reference runs in FP64 on the
+same stored values: conv weights rounded to bfloat16, and every activation
+and activation gradient rounded to bfloat16 where the kernels store one
+(unet_ref's rnd).  What remains is FP32 against FP64 accumulation; the
+tolerances (FWD_TOL, GRAD_TOL, LOSS_TOL below) are the measured errors with
+a margin.  Gradients are reproducible bit for bit (fixed-order reductions);
+Adam is checked over five steps; the learned solve's choice rule is checked
+exactly: the final iterate is the oracle's solve from the chosen start, bit
+for bit.
 """
 import sys
 
@@ -25,6 +28,13 @@ if not torch.cuda.is_available():
 import paper_2607_01735_amd as rb  # noqa: E402
 
 DEV = torch.device("cuda:0")
+# Measured on MI355X against the reference that rounds to bfloat16 where the
+# kernels store bfloat16 (tests print the measured values); the remaining
+# difference is FP32 against FP64 accumulation, which moves an occasional
+# stored value across a bfloat16 rounding boundary.
+FWD_TOL = {2: 2e-3, 4: 1e-2}   # by coarsening factor
+GRAD_TOL = 5e-3
+LOSS_TOL = 1e-4
 N = 127     # the factor-4 network (levels 127, 31, 7, 1)
 FACTOR = 4
 CONFIGS = [(2, 63), (4, 127)]  # (coarsening factor, N)
@@ -73,12 +83,23 @@ def batch_fields(seeds, n=N):
     return np.stack(fs)
 
 
+def round_weights(p):
+    """The kernels' operands: 3x3 conv weights in bfloat16; biases and the
+    1x1 head stay in FP32 (their masters)."""
+    return {k: (bf16_round(v) if k.endswith(".w") and not k.startswith("head") else v)
+            for k, v in p.items()}
+
+
 def ref_forward(p, f_nat, factor=FACTOR):
-    """Reference output u0 (interior) with bfloat16-rounded weights/input."""
-    pr = {k: bf16_round(v) for k, v in p.items()}
+    """Reference output u0 (interior), FP64 arithmetic on the kernels'
+    stored values: bfloat16 conv weights, the input f/rms (rms in FP32)
+    rounded to bfloat16, every stored activation rounded to bfloat16."""
+    pr = round_weights(p)
     n = f_nat.shape[0] - 2
-    x0, rms = U.normalise(f_nat[1:n + 1, 1:n + 1])
-    y, cache = U.forward(pr, bf16_round(x0), factor=factor)
+    fi = f_nat[1:n + 1, 1:n + 1]
+    rms = float(np.float32(np.sqrt(np.mean(fi * fi))))
+    x0 = bf16_round((fi / rms).astype(np.float32))
+    y, cache = U.forward(pr, x0, factor=factor, rnd=bf16_round)
     return y * rms, y, cache, pr, rms
 
 
@@ -98,7 +119,8 @@ def test_forward_matches_reference(factor, n):
         ref, *_ = ref_forward(p, f[b], factor)
         g = got[b, 1:n + 1, 1:n + 1]
         err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
-        assert err < 3e-2, f"sample {b}: relative error {err}"
+        say(f"forward n={n} F={factor} sample {b}: relative L2 error {err:.3e}")
+        assert err < FWD_TOL[factor], f"sample {b}: relative error {err}"
         assert not np.any(got[b, 0]) and not np.any(got[b, :, 0])  # ring untouched
 
 
@@ -123,17 +145,69 @@ def test_gradients_match_reference(factor, n):
         t = target[b, 1:n + 1, 1:n + 1] / rms
         lb, dy = U.mse_loss(y, t)
         loss_ref += lb / 2
-        gb = U.backward(pr, cache, dy / 2, factor=factor)
+        gb = U.backward(pr, cache, dy / 2, factor=factor, rnd=bf16_round)
         for k in g_ref:
             g_ref[k] += gb[k]
-    assert loss == pytest.approx(loss_ref, rel=3e-2)
+    say(f"loss {loss!r} reference {loss_ref!r}")
+    assert loss == pytest.approx(loss_ref, rel=LOSS_TOL)
+    worst = (0.0, "")
     for k in g_ref:
         a, r = g_gpu[k].ravel(), g_ref[k].ravel()
         if np.linalg.norm(r) < 1e-6 * max(1.0, np.abs(loss_ref)):
             continue
-        cos = a @ r / (np.linalg.norm(a) * np.linalg.norm(r))
         rel = np.linalg.norm(a - r) / np.linalg.norm(r)
-        assert cos > 0.99 and rel < 0.1, f"{k}: cos={cos:.4f} rel={rel:.4f}"
+        worst = max(worst, (rel, k))
+        assert rel < GRAD_TOL, f"{k}: relative L2 error {rel:.3e}"
+    say(f"gradients n={n} F={factor}: worst tensor {worst[1]} relative L2 error {worst[0]:.3e}")
+
+
+def test_gradients_are_reproducible():
+    """The gradient reductions add partial sums in a fixed order (no
+    floating-point atomics): two backward passes give the same bits."""
+    say("unet gradient reproducibility")
+    p = make_params(seed=8)
+    net = rb.UNet(N, 2)
+    net.set_params(flatten(p).astype(np.float32))
+    f = torch.from_numpy(batch_fields([3, 4])).to(DEV)
+    target = torch.zeros_like(f)
+    l1 = net.train_step(f, target, 0.0, update=False)
+    g1 = net.get_grads()
+    l2 = net.train_step(f, target, 0.0, update=False)
+    g2 = net.get_grads()
+    assert l1 == l2
+    assert np.array_equal(g1.view(np.uint32), g2.view(np.uint32))
+
+
+def test_adam_matches_reference_over_steps():
+    """Five Adam updates on the GPU against the reference Adam (FP64)
+    applied to the same FP32 parameters with the GPU's gradients of each
+    step: bias correction, both moments and the step count are exercised
+    beyond the first step."""
+    say("unet adam over 5 steps")
+    p = make_params(seed=9)
+    vec = flatten(p).astype(np.float32)
+    net = rb.UNet(N, 2)
+    net.set_params(vec)
+    f = torch.from_numpy(batch_fields([13, 14])).to(DEV)
+    u = np.zeros(tuple(f.shape))
+    for b in range(2):
+        u[b, 1:N + 1, 1:N + 1] = -W.grf_rhs(N, seed=13 + b)[0][1:N + 1, 1:N + 1] * 0.02
+    ut = torch.from_numpy(u).to(DEV)
+    lr = 2e-3
+    ref = {"a": vec.astype(np.float64)}
+    state = {}
+    for t in range(1, 6):
+        before = net.get_params()
+        net.train_step(f, ut, lr, update=True)
+        g = net.get_grads().astype(np.float64)
+        after = net.get_params()
+        ref = {"a": before.astype(np.float64)}
+        U.adam_step(ref, {"a": g}, state, lr=lr)
+        tol = 4 * np.spacing(np.abs(after)).astype(np.float64) + 2e-6 * lr
+        err = np.abs(after.astype(np.float64) - ref["a"])
+        say(f"adam step {t}: max |gpu - ref| {err.max():.3e}")
+        assert np.all(err <= tol), f"step {t}: {int(np.sum(err > tol))} parameters off"
+        assert not np.array_equal(after, before)
 
 
 def test_adam_step_and_training_decreases_loss():
