@@ -169,6 +169,10 @@ def time_to_tolerance(torch, rb, W, n=255, tol=1e-8):
     base = out["plain_f64"]["seconds"]
     for name, _ in forms[1:]:
         out[name]["speedup_vs_plain_f64"] = round(base / out[name]["seconds"], 3)
+    # precision and relaxation against the same kernel in FP64 Gauss-Seidel
+    same = out["resident_f64"]["seconds"]
+    for name in ("f32_ir_resident", "bf16rhs_ir_resident", "sor_resident_f64"):
+        out[name]["speedup_vs_same_kernel_f64"] = round(same / out[name]["seconds"], 3)
     return out
 
 
@@ -183,6 +187,7 @@ def time_to_tolerance_fourier(torch, rb, W, n=1023, tol=1e-8):
     out = {"problem": f"{n}x{n} FP64, 64 Fourier modes seed 0, u0=0, rel<={tol:g}"}
     forms = [("plain_f64", dict(kernel="plain", check_every=1000)),
              ("auto_f64", dict(kernel="auto", check_every=1000)),
+             ("blocked_f64", dict(kernel="blocked", check_every=4000)),
              ("f32_ir", dict(kernel="auto", precision="f32_ir", inner_sweeps=4000,
                              check_every=4000)),
              ("f32_ir_blocked", dict(kernel="blocked", precision="f32_ir", inner_sweeps=4000,
@@ -203,6 +208,10 @@ def time_to_tolerance_fourier(torch, rb, W, n=1023, tol=1e-8):
     base = out["plain_f64"]["seconds"]
     for name, _ in forms[1:]:
         out[name]["speedup_vs_plain_f64"] = round(base / out[name]["seconds"], 3)
+    # each precision against the same kernel choice in FP64
+    for name, ref in (("f32_ir", "auto_f64"), ("bf16rhs_ir", "auto_f64"),
+                      ("f32_ir_blocked", "blocked_f64")):
+        out[name]["speedup_vs_same_kernel_f64"] = round(out[ref]["seconds"] / out[name]["seconds"], 3)
     return out
 
 
@@ -386,7 +395,7 @@ def rb3_throughput(torch, rb, n=767, sweeps=40):
     return out
 
 
-def learned_guess(torch, rb, tol=1e-8, seeds=2):
+def learned_guess(torch, rb, tol=1e-8, seeds=4):
     """The learned-guess workload: 511 x 511 GRF right-hand sides (held-out
     seeds 10^6 + 20 + i), FP64 solve to rel <= tol from u = 0 (the judge)
     against the same solve started from the shipped network's guess, kept
@@ -527,6 +536,18 @@ def refinement_throughput(torch, rb, W, n=16383, inner=100, outer=2):
                      "whole_glups": round(n * n * info["sweeps"] / dt / 1e9, 1),
                      "rel_residual": info["rel_residual"]}
         log(f"refinement {name}: {out[name]}")
+    # the closed form of 2 x 100 = 200 plain sweeps (refinement equals plain
+    # sweeping in exact arithmetic): the runs' distance from it
+    import numpy as np
+
+    from tests import closed_form as cf
+    modes = cf.merge_modes(*W.fourier_modes(seed=0))
+    expect = cf.multi_mode_rel(n, modes, outer * inner)
+    out["closed_form_rel_after_sweeps"] = expect
+    for name in ("f32_ir", "bf16rhs_ir", "f64"):
+        out[name]["rel_minus_closed_form"] = float(np.float64(out[name]["rel_residual"]) - expect)
+    for name in ("f32_ir", "bf16rhs_ir"):
+        out[name]["inner_glups_vs_f64"] = round(out[name]["inner_glups"] / out["f64"]["inner_glups"], 3)
     del u, f
     torch.cuda.empty_cache()
     return out

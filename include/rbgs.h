@@ -158,6 +158,16 @@ typedef struct {
                               RBGS_EUNSUPPORTED); 0.0 = the model problem's
                               optimum 2 / (1 + sin(pi h)) for this grid's h   */
     rbgs_sweep_opts sweep; /* kernel choice for the (inner) sweeps             */
+    int32_t fallback;      /* IR: 1 = widen the inner precision when it stops
+                              helping (not in the paper; the build's rule): a
+                              value of r that the inner right-hand-side format
+                              cannot hold switches to FP64 sweeps of u at once;
+                              an outer step after the first that leaves rel no
+                              lower turns a bfloat16 right-hand side into FP32,
+                              FP32 inner sweeps into FP64 sweeps of u
+                              (inner_sweeps at a time, residual after each).
+                              info->precision reports where it ended.  0 = off.
+                              Not available for batches (RBGS_EUNSUPPORTED).  */
 } rbgs_solve_opts;
 
 typedef struct {
@@ -166,6 +176,9 @@ typedef struct {
     double rel_residual;   /* final ||r||_2/||b||_2 (||r||_2 if ||b||_2 = 0)   */
     double abs_residual;   /* final ||r||_2                                    */
     int32_t status;        /* same value as the return code                    */
+    int32_t precision;     /* rbgs_precision of the sweeps at the end: the
+                              requested one, or a wider one after a fallback
+                              (RBGS_PREC_F64 for plain solves)                */
 } rbgs_solve_info;
 
 /* Size in bytes of the workspace that rbgs_sweep, rbgs_residual and

@@ -48,6 +48,8 @@ def _load(path=None):
         "rbgs_ref_residual_f32": [_i32, _i64, _f64, _vp, _vp, _vp, _vp, _vp],
         "rbgs_ref_solve_f64": [_i32, _i64, _f64, _vp, _vp, _i32, _f64, _i32, _vp, _vp],
         "rbgs_ref_ir_solve": [_i32, _i64, _f64, _vp, _vp, _i32, _i32, _i32, _f64, _vp, _vp],
+        "rbgs_ref_ir_solve_fallback": [_i32, _i64, _f64, _vp, _vp, _i32, _i32, _i32, _f64, _vp,
+                                       _vp, _vp, _vp],
         "rbgs_ref_colour": [_i64, _i64],
         "rbgs_ref_sor_half_sweep_f64": [_i32, _i64, _f64, _f64, _vp, _vp, _i32],
         "rbgs_ref_sor_sweep_f64": [_i32, _i64, _f64, _f64, _vp, _vp, _i32],
@@ -192,6 +194,23 @@ def ir_solve(u, f, h, inner_sweeps, max_outer, rel_tol, rhs_bf16=False):
                                           ctypes.byref(outer), ctypes.byref(rel)),
                 "ir_solve")
     return rc, outer.value, rel.value
+
+
+def ir_solve_fallback(u, f, h, inner_sweeps, max_sweeps, rel_tol, rhs_bf16=False):
+    """Refinement whose inner precision widens when it stalls or overflows
+    (bfloat16 rhs -> binary32 -> FP64 sweeps).
+
+    Returns (status, outer_steps, sweeps, rel, precision) with precision
+    0 = FP64 sweeps, 1 = binary32, 2 = bfloat16 rhs at the end."""
+    n, ld = _grid(u)
+    assert u.dtype == np.float64 and f.dtype == np.float64
+    outer, done, prec = _i32(), _i32(), _i32()
+    rel = _f64()
+    rc = _check(_load().rbgs_ref_ir_solve_fallback(
+        n, ld, h, _ptr(u), _ptr(f), 1 if rhs_bf16 else 0, inner_sweeps, max_sweeps, rel_tol,
+        ctypes.byref(outer), ctypes.byref(done), ctypes.byref(rel), ctypes.byref(prec)),
+        "ir_solve_fallback")
+    return rc, outer.value, done.value, rel.value, prec.value
 
 
 def omega_opt(n):

@@ -399,6 +399,91 @@ int rbgs_ref_ir_solve(int32_t n, int64_t ld, double h, double *u,
     return rel <= rel_tol ? RBGS_REF_OK : RBGS_REF_ENOCONV;
 }
 
+
+/* ------------------------------------------------------------------------- */
+/* Refinement with a precision fallback (not in the paper; the build's own    */
+/* rule).  The outer steps are those of rbgs_ref_ir_solve, with a budget of    */
+/* max_sweeps sweeps in all, and the inner precision widens when it stops     */
+/* helping:                                                                   */
+/*   - range: when the FP64 residual holds a value that the inner right-hand  */
+/*     side format cannot hold (binary32 or bfloat16 rounding gives an        */
+/*     infinity), the solve switches to FP64 sweeps of u at once;             */
+/*   - stall: when an outer step after the first leaves the relative residual */
+/*     no lower than before it (the first step of a solve from a smooth start */
+/*     raises it: Gauss-Seidel's first sweep leaves the residual on one       */
+/*     colour), a bfloat16 right-hand side becomes binary32, and binary32    */
+/*     inner sweeps become FP64 sweeps of u.                                  */
+/* In FP64 the sweeps run inner_sweeps at a time with the residual after      */
+/* each group.  *prec_out: the precision in use at the end (0 = FP64 sweeps,  */
+/* 1 = binary32 inner, 2 = bfloat16 right-hand side).                         */
+/* ------------------------------------------------------------------------- */
+static int ir_residual_rounded(int32_t n, int64_t ld, double h, const double *u,
+                               const double *f, double *r, float *r32, int32_t prec,
+                               double *rel)
+{
+    rbgs_ref_residual_f64(n, ld, h, u, f, NULL, rel, r);
+    int overflow = 0;
+    for (int64_t i = 1; i <= n; ++i)
+        for (int64_t j = 1; j <= n; ++j) {
+            double x = AT(r, i, j);
+            float v = (float)x;
+            if (prec == 2) v = rbgs_ref_round_bf16(v);
+            if (isinf(v) && isfinite(x)) overflow = 1;
+            AT(r32, i, j) = v;
+        }
+    return overflow;
+}
+
+int rbgs_ref_ir_solve_fallback(int32_t n, int64_t ld, double h, double *u, const double *f,
+                               int32_t rhs_bf16, int32_t inner_sweeps, int32_t max_sweeps,
+                               double rel_tol, int32_t *outer_done, int32_t *sweeps_done,
+                               double *rel_out, int32_t *prec_out)
+{
+    if (bad_grid(n, ld, h) || !u || !f || inner_sweeps < 1 || max_sweeps < 0)
+        return RBGS_REF_EINVAL;
+    size_t cells = (size_t)(n + 2) * (size_t)ld;
+    double *r = (double *)calloc(cells, sizeof(double));
+    float *r32 = (float *)calloc(cells, sizeof(float));
+    float *e = (float *)calloc(cells, sizeof(float));
+    if (!r || !r32 || !e) {
+        free(r); free(r32); free(e);
+        return RBGS_REF_ENOMEM;
+    }
+    int32_t prec = rhs_bf16 ? 2 : 1, outer = 0, done = 0;
+    double rel = 0.0;
+    if (ir_residual_rounded(n, ld, h, u, f, r, r32, prec, &rel)) prec = 0;
+    while (!(rel <= rel_tol) && done < max_sweeps && isfinite(rel)) {
+        int32_t k = max_sweeps - done < inner_sweeps ? max_sweeps - done : inner_sweeps;
+        if (prec == 0) {
+            rbgs_ref_sweep_f64(n, ld, h, u, f, k);
+            done += k;
+            rbgs_ref_residual_f64(n, ld, h, u, f, NULL, &rel, NULL);
+            continue;
+        }
+        memset(e, 0, cells * sizeof(float));
+        rbgs_ref_sweep_f32(n, ld, h, e, r32, k);
+        for (int64_t i = 1; i <= n; ++i)
+            for (int64_t j = 1; j <= n; ++j)
+                AT(u, i, j) = AT(u, i, j) + (double)AT(e, i, j);
+        done += k;
+        ++outer;
+        const double before = rel;
+        int overflow = ir_residual_rounded(n, ld, h, u, f, r, r32, prec, &rel);
+        if (outer >= 2 && rel >= before) {
+            prec = prec == 2 ? 1 : 0;
+            if (prec == 1) overflow = ir_residual_rounded(n, ld, h, u, f, r, r32, prec, &rel);
+        }
+        if (overflow) prec = 0;
+    }
+    free(r); free(r32); free(e);
+    if (outer_done) *outer_done = outer;
+    if (sweeps_done) *sweeps_done = done;
+    if (rel_out) *rel_out = rel;
+    if (prec_out) *prec_out = prec;
+    if (!isfinite(rel)) return RBGS_REF_ENOCONV;
+    return rel <= rel_tol ? RBGS_REF_OK : RBGS_REF_ENOCONV;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Multigrid with red-black Gauss-Seidel as the smoother (an extension: the   */
 /* conclusion, Section 5, names odd-even and related multilevel techniques as  */

@@ -341,15 +341,21 @@ int fetch_norms(const Workspace& w, hipStream_t s, double* abs_norm, double* rel
     return RBGS_OK;
 }
 
+// The graph rounds' device state: {converged flag, rounds, overflow flag,
+// stall flag, previous rel (double)}, 64 bytes after the residual sums.
+int* round_state(const Workspace& w) {
+    return reinterpret_cast<int*>(reinterpret_cast<char*>(w.sums) + 64);
+}
+
 template <typename T>
 int split_residual(const rbgs_grid* g, const Workspace& w, hipStream_t s, float* r_red,
-                   float* r_black, int rhs_bf16) {
+                   float* r_black, int rhs_bf16, int* overflow = nullptr) {
     HIP_TRY(launch_residual_split<T>(static_cast<const T*>(w.u_red),
                                      static_cast<const T*>(w.u_black),
                                      static_cast<const T*>(w.f_red),
                                      static_cast<const T*>(w.f_black), g->n, w.pitch,
                                      1.0 / (g->h * g->h), w.partials, w.sums, r_red, r_black,
-                                     w.pitch32, rhs_bf16, s),
+                                     w.pitch32, rhs_bf16, s, overflow),
             "residual");
     return RBGS_OK;
 }
@@ -375,13 +381,16 @@ using RoundBody = std::function<int(hipStream_t, const int*, void**)>;
 // node per launch); the caller's launch-by-launch loop runs them instead.
 constexpr int64_t kGraphMaxLaunchesPerRound = int64_t(1) << 16;
 
+// watch, first_check, prev_rel: a refinement with the precision fallback
+// (launch_judge); *flags (optional) receives the overflow and stall flags.
 int solve_rounds_graph(const Workspace& w, const RoundBody& body_fn, int cap, double rel_tol,
                        hipStream_t s, void** err_state, int* rounds_done, bool* used,
-                       int64_t launches_per_round) {
+                       int64_t launches_per_round, int watch = 0, int first_check = 0,
+                       double prev_rel = 0.0, int* flags = nullptr) {
     *used = false;
     *rounds_done = 0;
     if (launches_per_round > kGraphMaxLaunchesPerRound) return RBGS_OK;
-    int* state = reinterpret_cast<int*>(reinterpret_cast<char*>(w.sums) + 64);  // {flag, rounds}
+    int* state = round_state(w);
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -399,7 +408,8 @@ int solve_rounds_graph(const Workspace& w, const RoundBody& body_fn, int cap, do
     if (ok) {
         const std::string saved = g_last_error;
         bool body = body_fn(cs, state, &es) == RBGS_OK;
-        body = body && launch_judge(w.sums, rel_tol, state, cap, cs) == hipSuccess;
+        body = body && launch_judge(w.sums, rel_tol, state, cap, cs, watch, first_check,
+                                    prev_rel) == hipSuccess;
         const bool ended = hipStreamEndCapture(cs, &graph) == hipSuccess;
         ok = body && ended &&
              hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
@@ -416,7 +426,7 @@ int solve_rounds_graph(const Workspace& w, const RoundBody& body_fn, int cap, do
     hipError_t e = launch_zero(state, 16, s);
     if (e == hipSuccess && es) e = launch_zero(static_cast<char*>(es) + 64, 4, s);
     const int per_poll = cap < 4 ? cap : 4;
-    int host[2] = {0, 0};
+    int host[4] = {0, 0, 0, 0};
     while (e == hipSuccess) {
         for (int r = 0; r < per_poll && e == hipSuccess; ++r) e = hipGraphLaunch(exec, s);
         if (e == hipSuccess) e = hipMemcpyAsync(host, state, sizeof host, hipMemcpyDeviceToHost, s);
@@ -433,6 +443,10 @@ int solve_rounds_graph(const Workspace& w, const RoundBody& body_fn, int cap, do
     cleanup();
     if (e != hipSuccess) return fail(RBGS_EHIP, std::string("solve graph: ") + hipGetErrorString(e));
     *rounds_done = host[1];
+    if (flags) {
+        flags[0] = host[2];
+        flags[1] = host[3];
+    }
     return RBGS_OK;
 }
 
@@ -972,6 +986,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
     if (o->precision < RBGS_PREC_F64 || o->precision > RBGS_PREC_BF16RHS_IR)
         return fail(RBGS_EINVAL, "unknown precision");
     if (o->inner_sweeps < 0) return fail(RBGS_EINVAL, "inner_sweeps must be >= 0");
+    if (o->fallback != 0 && o->fallback != 1) return fail(RBGS_EINVAL, "fallback must be 0 or 1");
     const bool ir = is_ir(o);
     // omega: 1 = Gauss-Seidel; (0, 2) = red-black SOR; 0 = the model
     // problem's optimum 2 / (1 + sin(pi h)) for this grid's h
@@ -1009,7 +1024,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         HIP_TRY(hipEventElapsedTime(&gt.acc.pack_ms, gt.t.ev[0], gt.t.ev[3]), "event time");
     }
 
-    rbgs_solve_info out{0, 0, 0.0, 0.0, RBGS_OK};
+    rbgs_solve_info out{0, 0, 0.0, 0.0, RBGS_OK, RBGS_PREC_F64};
     int launches = 0;
     void* err_state = nullptr;
     rbgs_sweep_opts sw = o->sweep;
@@ -1078,9 +1093,16 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         else
             out.status = (o->rel_tol <= 0.0 || rel <= o->rel_tol) ? RBGS_OK : RBGS_ENOCONV;
     } else {
-        // Iterative refinement: FP64 residual and correction, FP32 inner sweeps.
+        // Iterative refinement: FP64 residual and correction, FP32 inner
+        // sweeps (bfloat16 right-hand side in the BF16RHS mode).  With
+        // opts.fallback the inner precision widens when it stops helping: a
+        // value of r that its format cannot hold switches to FP64 sweeps at
+        // once; an outer step after the first that leaves rel no lower turns
+        // a bfloat16 right-hand side into FP32, and FP32 inner sweeps into
+        // FP64 sweeps of u (inner_sweeps at a time, residual after each).
         const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : o->check_every;
-        const int bf16 = o->precision == RBGS_PREC_BF16RHS_IR;
+        const bool fb = o->fallback != 0;
+        int prec = o->precision;
         Workspace inner_w = w;  // FP32 view: e is the iterate, r the right-hand side
         inner_w.pitch = w.pitch32;
         inner_w.u_red = w.e_red;
@@ -1093,39 +1115,95 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         rbgs_grid gi = *g;
         double rel = 0.0, ab = 0.0;
         int32_t done = 0, outer = 0;
-        if ((rc = split_residual<double>(g, w, s, w.r_red, w.r_black, bf16))) return rc;
-        if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
-        const int cap = o->max_sweeps / inner;
-        if (!gt.t.on && !(rel <= o->rel_tol) && std::isfinite(rel) && cap > 0) {
-            // whole outer steps as a captured graph (zero e, inner sweeps,
-            // correction, residual with r for the next step, the judge)
-            RoundBody body = [&](hipStream_t cs, const int* stop, void** es) -> int {
-                int l = 0;
-                HIP_TRY(launch_zero(w.e_red, c32, cs), "zero correction");
-                HIP_TRY(launch_zero(w.e_black, c32, cs), "zero correction");
-                int r = run_sweeps<float>(&gi, inner_w, inner, &sw, cs, &l, es, nullptr, stop);
-                if (r) return r;
-                HIP_TRY(launch_add_correction(static_cast<double*>(w.u_red),
-                                              static_cast<double*>(w.u_black), w.pitch, w.e_red,
-                                              w.e_black, w.pitch32, g->n, cs, stop),
-                        "correction");
-                return split_residual<double>(g, w, cs, w.r_red, w.r_black, bf16);
-            };
-            int rounds = 0;
-            bool used = false;
-            if ((rc = solve_rounds_graph(w, body, cap, o->rel_tol, s, &err_state, &rounds, &used,
-                                         2 * int64_t(inner) + 6)))
-                return rc;
-            if (used) {
-                done = rounds * inner;
-                outer = rounds;
+        int* state = round_state(w);
+        int* ovf = fb ? state + 2 : nullptr;  // set by the residual kernel
+        if (fb) HIP_TRY(launch_zero(state, 16, s), "zero flags");
+        // the overflow flag of the last residual (0 without the fallback)
+        auto overflowed = [&](int* flag) -> int {
+            *flag = 0;
+            if (!fb) return RBGS_OK;
+            HIP_TRY(hipMemcpyAsync(flag, ovf, sizeof *flag, hipMemcpyDeviceToHost, s), "flag copy");
+            HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+            return RBGS_OK;
+        };
+        // r rounded to the current right-hand-side format, rel, and the switch
+        // to FP64 sweeps when a value does not fit
+        auto residual_now = [&]() -> int {
+            int r = split_residual<double>(g, w, s, w.r_red, w.r_black,
+                                           prec == RBGS_PREC_BF16RHS_IR, ovf);
+            if (r || (r = fetch_norms(w, s, &ab, &rel))) return r;
+            int flag = 0;
+            if ((r = overflowed(&flag))) return r;
+            if (flag) prec = RBGS_PREC_F64;
+            return RBGS_OK;
+        };
+        // after an outer step from rel `before`: widen on a stall
+        auto after_step = [&](double before) -> int {
+            int flag = 0;
+            int r = overflowed(&flag);
+            if (r) return r;
+            if (flag) {
+                prec = RBGS_PREC_F64;
+            } else if (fb && outer >= 2 && rel >= before) {
+                prec = prec == RBGS_PREC_BF16RHS_IR ? RBGS_PREC_F32_IR : RBGS_PREC_F64;
+                if (prec == RBGS_PREC_F32_IR) return residual_now();
+            }
+            return RBGS_OK;
+        };
+        if ((rc = residual_now())) return rc;
+        while (!(rel <= o->rel_tol) && done < o->max_sweeps && std::isfinite(rel)) {
+            const int32_t k = o->max_sweeps - done < inner ? o->max_sweeps - done : inner;
+            if (prec == RBGS_PREC_F64) {  // after a fallback: FP64 sweeps of u
+                HIP_TRY(gt.begin(s), "event record");
+                if ((rc = run_sweeps<double>(g, w, k, &sw, s, &launches, &err_state, &pt))) return rc;
+                HIP_TRY(gt.end(s), "event record");
+                HIP_TRY(gt.collect(launches), "event time");
+                HIP_TRY(pt.collect(), "event time");
+                done += k;
+                if ((rc = split_residual<double>(g, w, s, nullptr, nullptr, 0))) return rc;
                 if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
                 if (err_state && (rc = blocked_check_error(err_state, s, &g_last_error)))
                     return rc;
+                continue;
             }
-        }
-        while (!(rel <= o->rel_tol) && done < o->max_sweeps && std::isfinite(rel)) {
-            int32_t k = o->max_sweeps - done < inner ? o->max_sweeps - done : inner;
+            const int bf16 = prec == RBGS_PREC_BF16RHS_IR;
+            const int cap = (o->max_sweeps - done) / inner;
+            if (!gt.t.on && cap > 0) {
+                // whole outer steps as a captured graph (zero e, inner sweeps,
+                // correction, residual with r for the next step, the judge)
+                RoundBody body = [&, bf16](hipStream_t cs, const int* stop, void** es) -> int {
+                    int l = 0;
+                    HIP_TRY(launch_zero(w.e_red, c32, cs), "zero correction");
+                    HIP_TRY(launch_zero(w.e_black, c32, cs), "zero correction");
+                    int r = run_sweeps<float>(&gi, inner_w, inner, &sw, cs, &l, es, nullptr, stop);
+                    if (r) return r;
+                    HIP_TRY(launch_add_correction(static_cast<double*>(w.u_red),
+                                                  static_cast<double*>(w.u_black), w.pitch,
+                                                  w.e_red, w.e_black, w.pitch32, g->n, cs, stop),
+                            "correction");
+                    return split_residual<double>(g, w, cs, w.r_red, w.r_black, bf16, ovf);
+                };
+                int rounds = 0, flags[2] = {0, 0};
+                bool used = false;
+                if ((rc = solve_rounds_graph(w, body, cap, o->rel_tol, s, &err_state, &rounds,
+                                             &used, 2 * int64_t(inner) + 6, fb ? 1 : 0,
+                                             outer >= 1 ? 1 : 2, rel, flags)))
+                    return rc;
+                if (used) {
+                    done += rounds * inner;
+                    outer += rounds;
+                    if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+                    if (err_state && (rc = blocked_check_error(err_state, s, &g_last_error)))
+                        return rc;
+                    if (flags[0]) {
+                        prec = RBGS_PREC_F64;
+                    } else if (flags[1]) {
+                        prec = bf16 ? RBGS_PREC_F32_IR : RBGS_PREC_F64;
+                        if (prec == RBGS_PREC_F32_IR && (rc = residual_now())) return rc;
+                    }
+                    continue;
+                }
+            }
             HIP_TRY(launch_zero(w.e_red, c32, s), "zero correction");
             HIP_TRY(launch_zero(w.e_black, c32, s), "zero correction");
             HIP_TRY(gt.begin(s), "event record");
@@ -1139,15 +1217,18 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
                     "correction");
             done += k;
             ++outer;
-            if ((rc = split_residual<double>(g, w, s, w.r_red, w.r_black, bf16))) return rc;
+            const double before = rel;
+            if ((rc = split_residual<double>(g, w, s, w.r_red, w.r_black, bf16, ovf))) return rc;
             if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
             if (err_state && (rc = blocked_check_error(err_state, s, &g_last_error)))
                 return rc;
+            if ((rc = after_step(before))) return rc;
         }
         out.sweeps = done;
         out.outer_iters = outer;
         out.rel_residual = rel;
         out.abs_residual = ab;
+        out.precision = prec;
         if (!std::isfinite(rel))
             out.status = RBGS_ENONFINITE;
         else

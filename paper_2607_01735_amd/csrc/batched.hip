@@ -1039,6 +1039,8 @@ int rbgs_solve_batched(int32_t count, const rbgs_grid* grids, double* const* u,
                        rbgs_solve_info* infos, void* workspace, size_t workspace_bytes,
                        void* stream) {
     if (!opts) return bfail(RBGS_EINVAL, "opts is NULL");
+    if (opts->fallback != 0)
+        return bfail(RBGS_EUNSUPPORTED, "the precision fallback is for single-grid solves");
     if (opts->precision != RBGS_PREC_F32_IR && opts->precision != RBGS_PREC_BF16RHS_IR)
         return bfail(RBGS_EUNSUPPORTED,
                      "batched solves refine in FP64 around FP32 sweeps: precision must be "

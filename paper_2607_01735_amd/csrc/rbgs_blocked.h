@@ -68,15 +68,18 @@ inline int default_rows(int n, int L) {
 // fewer tiles, and fewer tiles than the launch has wave slots leave waves
 // idle.  The height (a power of two from kMinRows to 1024, at least L)
 // maximises the product of the two, with 0.8 x wave_slots as the tile count
-// that keeps the chip busy (waves finish their tiles at different times).
-// On MI355X this picks the measured best power-of-two height at 1023..8191
-// in FP64 and FP32; at 16383 (FP64) it picks 1024 rows, 6% slower than the
-// best height measured there (768) and 9% faster than 256.
+// that keeps the chip busy (waves finish their tiles at different times),
+// up to 512 rows in FP64 and 256 in FP32.  On MI355X this picks the measured
+// best power-of-two height at 1023..8191 in FP64 and FP32.  The caps come
+// from 16383^2 (fuse 7), where every height fills the chip and the score
+// alone would take 1024 rows: FP64 1253 GLUP/s at 1024 rows, 1353 at 512,
+// 1371 at 768; FP32 1814 at 1024, 1819 at 512, 2234 at 256, 1962 at 128.
 inline int single_grid_rows(int n, int L, int elem_bytes, int wave_slots) {
     const double busy = 0.8 * (wave_slots > 0 ? wave_slots : 1024);
+    const int cap = elem_bytes == 8 ? 512 : 256;
     int best = 0;
     double best_score = -1.0;
-    for (int r = kMinRows; r <= 1024; r <<= 1) {
+    for (int r = kMinRows; r <= cap; r <<= 1) {
         const int rows = r < L ? L : r;
         const Geometry g = geometry(n, elem_bytes, L / 2, rows);
         const double fill = g.ntiles >= busy ? 1.0 : g.ntiles / busy;

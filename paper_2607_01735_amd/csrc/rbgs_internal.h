@@ -71,19 +71,25 @@ int residual_partial_slots(int n, int64_t pitch, size_t elem_bytes);
 // Residual norms of a split-layout iterate.  partials: residual_partial_slots
 // * 2 doubles; out: 2 doubles (sum r^2, sum b^2) in device memory.
 // r_out_red/black (optional): store r rounded to FP32 (or bfloat16 when
-// rhs_bf16) in a split FP32 array of pitch r_pitch, for refinement.
+// rhs_bf16) in a split FP32 array of pitch r_pitch, for refinement;
+// overflow (optional) is set to 1 when a finite r becomes infinite there.
 template <typename T>
 hipError_t launch_residual_split(const T* u_red, const T* u_black, const T* f_red,
                                  const T* f_black, int n, int64_t pitch, double inv_h2,
                                  double* partials, double* out, float* r_out_red,
                                  float* r_out_black, int64_t r_pitch, int rhs_bf16,
-                                 hipStream_t s);
+                                 hipStream_t s, int* overflow = nullptr);
 
 // Convergence test of a graph-captured solve round (device-side): from the
 // residual kernel's sums, sets state[0] (the converged flag the sweep
 // kernels' `stop` reads) when rel <= rel_tol, rel is not finite or
-// state[1] (rounds done, incremented here) reaches cap.
-hipError_t launch_judge(const double* sums, double rel_tol, int* state, int cap, hipStream_t s);
+// state[1] (rounds done, incremented here) reaches cap.  watch != 0 (a
+// refinement with the precision fallback): also when state[2] (the residual
+// kernel's overflow flag) is set, or when round first_check or later leaves
+// rel no lower than the previous rel (init_prev before the first round, then
+// a double at state + 4; state[3] = 1).
+hipError_t launch_judge(const double* sums, double rel_tol, int* state, int cap, hipStream_t s,
+                        int watch = 0, int first_check = 0, double init_prev = 0.0);
 
 // Residual norms of a natural-layout iterate (no packing).
 template <typename T>

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_residual_split(
     const T* __restrict__ u_red, const T* __restrict__ u_black, const T* __restrict__ f_red,
     const T* __restrict__ f_black, int n, int64_t pitch, double inv_h2, double* partials,
     int col_blocks, float* __restrict__ r_red, float* __restrict__ r_black, int64_t r_pitch,
-    int rhs_bf16) {
+    int rhs_bf16, int* __restrict__ overflow) {
     const int strip = blockIdx.x / col_blocks;
     const int cb = blockIdx.x - strip * col_blocks;
     const int64_t q = int64_t(cb) * 256 + threadIdx.x;
@@ -108,7 +108,11 @@ __global__ __launch_bounds__(256) void k_residual_split(
                 float* r_out = colour ? r_black : r_red;
                 if (r_out) {
                     float r32 = float(r);
-                    r_out[int64_t(i) * r_pitch + q] = rhs_bf16 ? round_to_bf16(r32) : r32;
+                    if (rhs_bf16) r32 = round_to_bf16(r32);
+                    r_out[int64_t(i) * r_pitch + q] = r32;
+                    // a finite residual that its binary32 / bfloat16 form
+                    // cannot hold (every writer stores the same 1)
+                    if (overflow && isinf(r32) && isfinite(r)) *overflow = 1;
                 }
             }
 #pragma unroll
@@ -234,12 +238,12 @@ hipError_t launch_residual_split(const T* u_red, const T* u_black, const T* f_re
                                  const T* f_black, int n, int64_t pitch, double inv_h2,
                                  double* partials, double* out, float* r_out_red,
                                  float* r_out_black, int64_t r_pitch, int rhs_bf16,
-                                 hipStream_t s) {
+                                 hipStream_t s, int* overflow) {
     const int cb = split_col_blocks(n);
     dim3 grid(unsigned(cb * strips(n)));
     hipLaunchKernelGGL((k_residual_split<T>), grid, dim3(256), 0, s, u_red, u_black, f_red,
                        f_black, n, pitch, inv_h2, partials, cb, r_out_red, r_out_black, r_pitch,
-                       rhs_bf16);
+                       rhs_bf16, overflow);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partials,
@@ -264,32 +268,52 @@ namespace {
 // The convergence test of a graph-captured solve, after each round's
 // residual: rel = ||r|| / ||b|| (||r|| when b = 0), formed exactly as the
 // host forms it; the flag stops the later rounds' sweeps.  state = {flag,
-// rounds done}; cap = rounds the sweep budget allows.
+// rounds done, overflow, stall, previous rel (double at byte 16)}; cap =
+// rounds the sweep budget allows.  With watch (a refinement that may widen
+// its inner precision) the rounds also stop when the residual kernel found
+// a value its right-hand-side format cannot hold (state[2]), or when round
+// first_check or a later one leaves rel no lower than the round before
+// (init_prev before the first round; state[3] = 1): the host then widens
+// the precision.
 __global__ __launch_bounds__(64) void k_judge(const double* __restrict__ sums, double rel_tol,
-                                              int* __restrict__ state, int cap) {
+                                              int* __restrict__ state, int cap, int watch,
+                                              int first_check, double init_prev) {
     if (threadIdx.x != 0 || state[0] != 0) return;
     const double rn = sqrt(sums[0]);
     const double bn = sqrt(sums[1]);
     const double rel = bn > 0.0 ? rn / bn : rn;
     const int rounds = state[1] + 1;
     state[1] = rounds;
-    if (rel <= rel_tol || !isfinite(rel) || rounds >= cap) state[0] = 1;
+    bool stop = rel <= rel_tol || !isfinite(rel) || rounds >= cap;
+    if (watch) {
+        double* prev = reinterpret_cast<double*>(state + 4);
+        const double before = rounds == 1 ? init_prev : *prev;
+        if (state[2] != 0) stop = true;
+        if (rounds >= first_check && rel >= before) {
+            state[3] = 1;
+            stop = true;
+        }
+        *prev = rel;
+    }
+    if (stop) state[0] = 1;
 }
 }  // namespace
 
-hipError_t launch_judge(const double* sums, double rel_tol, int* state, int cap, hipStream_t s) {
-    hipLaunchKernelGGL(k_judge, dim3(1), dim3(64), 0, s, sums, rel_tol, state, cap);
+hipError_t launch_judge(const double* sums, double rel_tol, int* state, int cap, hipStream_t s,
+                        int watch, int first_check, double init_prev) {
+    hipLaunchKernelGGL(k_judge, dim3(1), dim3(64), 0, s, sums, rel_tol, state, cap, watch,
+                       first_check, init_prev);
     return hipGetLastError();
 }
 
 template hipError_t launch_residual_split<double>(const double*, const double*, const double*,
                                                   const double*, int, int64_t, double, double*,
                                                   double*, float*, float*, int64_t, int,
-                                                  hipStream_t);
+                                                  hipStream_t, int*);
 template hipError_t launch_residual_split<float>(const float*, const float*, const float*,
                                                  const float*, int, int64_t, double, double*,
                                                  double*, float*, float*, int64_t, int,
-                                                 hipStream_t);
+                                                 hipStream_t, int*);
 template hipError_t launch_residual_natural<double>(const double*, const double*, int, int64_t,
                                                     double, double*, double*, hipStream_t);
 template hipError_t launch_residual_natural<float>(const float*, const float*, int, int64_t,

@@ -62,13 +62,13 @@ class rbgs_solve_opts(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int32), ("rel_tol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("inner_sweeps", ctypes.c_int32), ("omega", ctypes.c_double),
-                ("sweep", rbgs_sweep_opts)]
+                ("sweep", rbgs_sweep_opts), ("fallback", ctypes.c_int32)]
 
 
 class rbgs_solve_info(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("abs_residual", ctypes.c_double),
-                ("status", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 class rbgs_mg_opts(ctypes.Structure):
@@ -329,7 +329,7 @@ def rbgs_residual_noalloc(u, f, h=None, stream=None):
 
 def rbgs_solve(u, f, max_sweeps, rel_tol, check_every=100, h=None, precision="f64",
                inner_sweeps=0, omega=1.0, kernel="auto", workspace=None, stream=None,
-               raise_on_noconv=False, timing=False, **tuning):
+               raise_on_noconv=False, timing=False, fallback=False, **tuning):
     """Solve to rel_tol on the GPU; returns a dict with sweeps, outer_iters,
     rel_residual, abs_residual and status."""
     _same_layout(u, f)
@@ -340,6 +340,7 @@ def rbgs_solve(u, f, max_sweeps, rel_tol, check_every=100, h=None, precision="f6
     opts = rbgs_solve_opts()
     opts.max_sweeps, opts.rel_tol, opts.check_every = int(max_sweeps), float(rel_tol), int(check_every)
     opts.precision, opts.inner_sweeps, opts.omega = prec, int(inner_sweeps), float(omega)
+    opts.fallback = 1 if fallback else 0
     t = rbgs_timing() if timing else None
     opts.sweep = _sweep_opts(kernel=kernel, timing=t, **tuning)
     info = rbgs_solve_info()
@@ -349,7 +350,7 @@ def rbgs_solve(u, f, max_sweeps, rel_tol, check_every=100, h=None, precision="f6
     _check(rc, allow=(OK,) if raise_on_noconv else (OK, ENOCONV, ENONFINITE))
     out = {"sweeps": info.sweeps, "outer_iters": info.outer_iters,
            "rel_residual": info.rel_residual, "abs_residual": info.abs_residual,
-           "status": info.status}
+           "status": info.status, "precision": info.precision}
     if timing:
         out["timing"] = _timing_dict(t)
     return out

@@ -368,3 +368,19 @@ def test_residual_noalloc_validation_before_device_work(lib, case):
     assert rc == lib.EINVAL
     if case == "too_big":
         assert "static scratch" in lib.rbgs_last_error()
+
+
+def test_fallback_option_validation(lib):
+    """The refinement's fallback flag is 0 or 1, and batches refuse it."""
+    g = _grid(lib, 31)
+    o = lib.rbgs_solve_opts()
+    o.max_sweeps, o.rel_tol, o.check_every, o.omega = 10, 1e-8, 5, 1.0
+    o.precision, o.fallback = lib.PREC_F32_IR, 2
+    rc = lib._lib.rbgs_solve(ctypes.byref(g), lib.F64, None, None, ctypes.byref(o), None, None, 0,
+                             None)
+    assert rc == lib.EINVAL and "fallback" in lib.rbgs_last_error()
+    grids = (lib.rbgs_grid * 2)(_grid(lib, 15), _grid(lib, 31))
+    ptrs = (ctypes.c_void_p * 2)(1 << 20, 2 << 20)
+    o.fallback, o.inner_sweeps = 1, 10
+    rc = lib._lib.rbgs_solve_batched(2, grids, ptrs, ptrs, ctypes.byref(o), None, None, 0, None)
+    assert rc == lib.EUNSUPPORTED and "fallback" in lib.rbgs_batch_last_error()

@@ -633,3 +633,47 @@ def test_ir_trajectory_within_rounding_bound_of_gauss_seidel(oracle, bf16):
                                     2.0 ** -8 if bf16 else 2.0 ** -24)
     assert abs(rel - expect) <= bound
     assert abs(rel - expect) > 1e-12 * expect
+
+
+# --------------------------------------------------------------------------
+# Refinement with the precision fallback (the build's rule, not the paper's)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("bf16", [False, True])
+def test_fallback_on_overflow_is_fp64_sweeping(oracle, bf16):
+    """A Dirichlet ring of 1e36 puts residuals of ~1e36/h^2 next to it, beyond
+    binary32 and bfloat16: the solve switches to FP64 sweeps before any
+    inner solve, so it equals the (pinned) FP64 sweep bit for bit; without
+    the fallback the refinement runs into non-finite values."""
+    n, inner, cap = 63, 50, 400
+    h = W.spacing(n)
+    f = W.uniform_rhs(n, seed=1)
+    u0 = W.random_ring(n, seed=2) * 1e36
+    u = u0.copy()
+    rc, outer, done, rel, prec = oracle.ir_solve_fallback(u, f, h, inner, cap, 1e-12, rhs_bf16=bf16)
+    assert (outer, done, prec) == (0, cap, 0)
+    ref = u0.copy()
+    oracle.sweep(ref, f, h, cap)
+    assert np.array_equal(u, ref)
+    assert rel == oracle.residual(ref, f, h)[1]
+    plain = u0.copy()
+    oracle.ir_solve(plain, f, h, inner, cap // inner, 1e-12, rhs_bf16=bf16)
+    assert not np.all(np.isfinite(plain))
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_fallback_on_stall_reaches_what_refinement_cannot(oracle, bf16):
+    """At 63^2 with 2000 inner sweeps per step the refinement stalls near
+    1e-15 (the binary32 correction cannot resolve less); with the fallback
+    the solve widens to FP64 sweeps and reaches rel <= 1e-15 within the
+    budget, while the plain refinement with the same sweep budget does not."""
+    n, inner, tol = 63, 2000, 1e-15
+    h = W.spacing(n)
+    f = W.uniform_rhs(n, seed=3)
+    u = W.zeros(n)
+    rc, outer, done, rel, prec = oracle.ir_solve_fallback(u, f, h, inner, 200 * inner, tol,
+                                                          rhs_bf16=bf16)
+    assert rc == 0 and rel <= tol and prec == 0 and outer >= 2
+    assert done % inner == 0 and done < 200 * inner
+    plain = W.zeros(n)
+    rc2, _, rel2 = oracle.ir_solve(plain, f, h, inner, done // inner, tol, rhs_bf16=bf16)
+    assert rc2 != 0 and rel2 > tol
