@@ -356,6 +356,71 @@ def multicolour9_throughput(torch, rb, W, n=8191, sweeps=100, with_solve=True):
     return out
 
 
+UNET_CHANNELS = (16, 32, 64, 128)
+
+
+def unet_flops(n, factor=4, channels=UNET_CHANNELS):
+    """Multiply-add FLOPs (2 per MAC) of the U-Net's 3x3 convolutions for one
+    n x n sample: forward, and a training step (forward, input gradients of
+    every layer but the first, weight gradients); the first layer counts
+    its input as the 16 channels the kernel pads it to."""
+    sizes = [n]
+    for _ in channels[1:]:
+        sizes.append((sizes[-1] + 1) // factor - 1)
+    layers = []  # (cin, cout, level)
+    cin = 16
+    for l, c in enumerate(channels):
+        layers += [(cin, c, l), (c, c, l)]
+        cin = c
+    for l in range(len(channels) - 2, -1, -1):
+        layers += [(channels[l + 1] + channels[l], channels[l], l), (channels[l], channels[l], l)]
+    fwd = sum(2.0 * 9 * ci * co * sizes[l] ** 2 for ci, co, l in layers)
+    first = 2.0 * 9 * layers[0][0] * layers[0][1] * sizes[0] ** 2
+    return fwd, 3.0 * fwd - first
+
+
+def unet_throughput(torch, rb, n=511, batch=8, steps=10):
+    """The learned part's network on its workload: the shipped factor-4 U-Net
+    on 511 x 511 GRF inputs (held-out seeds), `steps` training steps at batch
+    8 (forward, backward, Adam; lr tiny so the weights barely move) and
+    `steps` forward passes, with achieved TFLOP/s of the 3x3 convolutions
+    against the bfloat16 dense MFMA peak."""
+    from paper_2607_01735_amd import learned
+    shipped = learned.pretrained_net(rb)
+    f = learned.fields_on_device(torch, n, [learned.TEST_SEED0 + 100 + i for i in range(batch)])
+    net = rb.UNet(n, batch, factor=4)
+    net.set_params(shipped.get_params())
+    target = torch.zeros_like(f)
+    for _ in range(2):
+        net.train_step(f, target, 1e-7)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(f, target, 1e-7)
+    torch.cuda.synchronize()
+    train_ms = (time.perf_counter() - t0) * 1e3 / steps
+    u0 = torch.zeros_like(f)
+    net.forward(f, u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.forward(f, u0)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) * 1e3 / steps
+    fwd, train = unet_flops(n)
+    out = {"workload": f"factor-4 U-Net on {n}x{n}, batch {batch}, shipped weights",
+           "train_step_ms": round(train_ms, 3), "forward_ms": round(fwd_ms, 3),
+           "conv_gflop_forward_per_sample": round(fwd / 1e9, 3),
+           "conv_gflop_train_per_sample": round(train / 1e9, 3),
+           "train_tflops": round(batch * train / (train_ms * 1e-3) / 1e12, 2),
+           "forward_tflops": round(batch * fwd / (fwd_ms * 1e-3) / 1e12, 2),
+           "peak_tflops_bf16_dense": 2500.0}
+    log(f"unet: {out}")
+    del f, u0, target
+    torch.cuda.empty_cache()
+    return out
+
+
 def rb3_throughput(torch, rb, n=767, sweeps=40):
     """Red-black Gauss-Seidel in 3D (the higher-dimension extension): n^3
     FP64 with f ~ U[-1, 1) drawn on the device (seeded), time per sweep from
@@ -702,6 +767,8 @@ def main():
                     help="run only the 3D red-black section, print its JSON and exit")
     ap.add_argument("--mc9-only", action="store_true",
                     help="run only the 9-point four-colour section, print its JSON and exit")
+    ap.add_argument("--unet-only", action="store_true",
+                    help="run only the U-Net training/inference timing, print its JSON and exit")
     ap.add_argument("--mg-only", action="store_true",
                     help="run only the 8191^2 multigrid section (and the STREAM probe unless "
                          "--no-probe), print its JSON and exit: the multigrid kernels' profile run")
@@ -727,6 +794,9 @@ def main():
     if args.mc9_only:
         mc9 = multicolour9_throughput(torch, rb, W, with_solve=not args.no_time_to_tol)
         print(json.dumps({"multicolour9": mc9}), flush=True)
+        return
+    if args.unet_only:
+        print(json.dumps({"unet": unet_throughput(torch, rb)}), flush=True)
         return
     if args.mg_only:
         mg = multigrid_to_tolerance(torch, rb, W, sizes=(1023, 8191))
@@ -837,6 +907,7 @@ def main():
     batched = None if args.no_extras else batched_throughput(torch, rb, W)
     batched_tol = None if args.no_extras else batched_to_tolerance(torch, rb, W)
     learned_511 = None if args.no_extras else learned_guess(torch, rb)
+    unet = None if args.no_extras else unet_throughput(torch, rb)
     probe = None if args.no_probe else stream_probe(torch, rb)
     if probe:
         log(f"STREAM probe: {probe}")
@@ -869,6 +940,7 @@ def main():
         "batched_512": batched,
         "batched_to_1e-8": batched_tol,
         "learned_guess_511": learned_511,
+        "unet_511": unet,
         "stream_probe": probe,
         "cpu_baseline": base,
     }

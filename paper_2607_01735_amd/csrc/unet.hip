@@ -200,19 +200,30 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(WGradArgs a) {
     }
 }
 
-// Bias gradient: per row (one block each) part[row][c] = sum over the row
-// of dY[p][c] where Y[p][c] > 0; k_reduce_parts adds the rows in order.
+// Bias gradient: per row (one block each) part[row][ch] = sum over the row
+// of dY[p][ch] where Y[p][ch] > 0, in a fixed order: thread t takes channel
+// t % c of the pixels x = t / c, t / c + g, ... (g = 256 / c pixel groups;
+// c is a power of two up to 256), then a fixed tree over the groups;
+// k_reduce_parts adds the rows in order.
 __global__ __launch_bounds__(256) void k_bias_grad(const bf16* dy, int64_t dys, const bf16* y,
                                                    int64_t ys, float* part, int wd, int c) {
     const int64_t row = blockIdx.x;
-    for (int ch = threadIdx.x; ch < c; ch += 256) {
-        float s = 0.f;
-        for (int x = 0; x < wd; ++x) {
-            const int64_t p = row * wd + x;
-            if (bf2f(y[p * ys + ch]) > 0.f) s += bf2f(dy[p * dys + ch]);
-        }
-        part[row * c + ch] = s;
+    const int t = threadIdx.x;
+    const int g = 256 / c;
+    const int ch = t % c, x0 = t / c;
+    float s = 0.f;
+    for (int x = x0; x < wd; x += g) {
+        const int64_t p = row * wd + x;
+        if (bf2f(y[p * ys + ch]) > 0.f) s += bf2f(dy[p * dys + ch]);
     }
+    __shared__ float sh[256];
+    sh[t] = s;
+    __syncthreads();
+    for (int st = g / 2; st > 0; st >>= 1) {
+        if (x0 < st) sh[t] += sh[t + st * c];
+        __syncthreads();
+    }
+    if (x0 == 0) part[row * c + ch] = sh[t];
 }
 
 // out[e] = sum over slots k = 0 .. nparts-1 of part[k * count + e], in a
@@ -246,14 +257,16 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ 
 __global__ __launch_bounds__(256) void k_restrict(const bf16* in, int64_t is, bf16* out, int64_t os,
                                                   int batch, int nc, int c, int F, float scale,
                                                   int accumulate) {
-    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    const int64_t total = int64_t(batch) * nc * nc * c;
+    // the host keeps batch nc^2 c (and the grid) below 2^32: 32-bit indexing
+    const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t total = uint32_t(batch) * uint32_t(nc) * uint32_t(nc) * uint32_t(c);
     if (idx >= total) return;
-    const int ch = int(idx % c);
-    int64_t r = idx / c;
-    const int J = int(r % nc); r /= nc;
-    const int I = int(r % nc);
-    const int b = int(r / nc);
+    const int ch = int(idx % uint32_t(c));
+    uint32_t r = idx / uint32_t(c);
+    const int J = int(r % uint32_t(nc));
+    r /= uint32_t(nc);
+    const int I = int(r % uint32_t(nc));
+    const int b = int(r / uint32_t(nc));
     const int nf = F * nc + F - 1;
     const int ci = F * I + F - 1, cj = F * J + F - 1;
     float s = 0.f;
@@ -275,14 +288,16 @@ __global__ __launch_bounds__(256) void k_prolong(const bf16* in, int64_t is, bf1
                                                  int batch, int nc, int c, int F, float scale,
                                                  int accumulate) {
     const int nf = F * nc + F - 1;
-    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    const int64_t total = int64_t(batch) * nf * nf * c;
+    // the host keeps batch nf^2 c (and the grid) below 2^32: 32-bit indexing
+    const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t total = uint32_t(batch) * uint32_t(nf) * uint32_t(nf) * uint32_t(c);
     if (idx >= total) return;
-    const int ch = int(idx % c);
-    int64_t r = idx / c;
-    const int j = int(r % nf); r /= nf;
-    const int i = int(r % nf);
-    const int b = int(r / nf);
+    const int ch = int(idx % uint32_t(c));
+    uint32_t r = idx / uint32_t(c);
+    const int j = int(r % uint32_t(nf));
+    r /= uint32_t(nf);
+    const int i = int(r % uint32_t(nf));
+    const int b = int(r / uint32_t(nf));
     // the coarse points within F - 1 of fine i are I = (i + 1) / F - 1 and
     // the next one; weight (F - |d|) / F with d = i - (F I + F - 1)
     const float invF = 1.f / float(F);
@@ -304,26 +319,45 @@ __global__ __launch_bounds__(256) void k_prolong(const bf16* in, int64_t is, bf1
     *o = f2bf(s);
 }
 
-// Per-sample rms of f over the interior (FP64 sums, one block per sample).
-__global__ __launch_bounds__(256) void k_rms(const double* f, int n, int64_t ld, int64_t gstride,
-                                             float* rms) {
-    const int b = blockIdx.x;
-    const double* fb = f + int64_t(b) * gstride;
-    double s = 0.0;
-    for (int64_t k = threadIdx.x; k < int64_t(n) * n; k += 256) {
-        const int64_t i = k / n + 1, j = k % n + 1;
-        const double v = fb[i * ld + j];
-        s += v * v;
-    }
+// Sum of one double per thread over a block of 256, by a fixed tree; every
+// thread gets the total.
+__device__ __forceinline__ double block_sum_f64(double v) {
     __shared__ double sh[256];
-    sh[threadIdx.x] = s;
+    sh[threadIdx.x] = v;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
-        if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        if (int(threadIdx.x) < st) sh[threadIdx.x] += sh[threadIdx.x + st];
         __syncthreads();
     }
+    const double total = sh[0];
+    __syncthreads();
+    return total;
+}
+
+// Per-sample rms of f over the interior, FP64 sums in a fixed order: one
+// block per (sample, interior row) adds the row's squares (thread t takes
+// columns t, t + 256, ..., then a tree), then one block per sample adds its
+// rows' sums the same way.
+__global__ __launch_bounds__(256) void k_rms_rows(const double* f, int n, int64_t ld,
+                                                  int64_t gstride, double* part) {
+    const int b = int(blockIdx.x) / n, row = int(blockIdx.x) % n;
+    const double* fr = f + int64_t(b) * gstride + int64_t(row + 1) * ld + 1;
+    double s = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const double v = fr[j];
+        s += v * v;
+    }
+    s = block_sum_f64(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_rms_final(const double* part, int n, float* rms) {
+    const int b = blockIdx.x;
+    double s = 0.0;
+    for (int r = threadIdx.x; r < n; r += 256) s += part[int64_t(b) * n + r];
+    s = block_sum_f64(s);
     if (threadIdx.x == 0) {
-        double r = sqrt(sh[0] / (double(n) * n));
+        const double r = sqrt(s / (double(n) * n));
         rms[b] = r > 0.0 ? float(r) : 1.f;
     }
 }
@@ -542,7 +576,8 @@ int wgrad_rows_per_wave(int h) { return h >= 128 ? 4 : (h >= 64 ? 8 : 16); }
 
 // Floats of partial sums the largest fixed-order reduction needs: weight
 // gradients (batch x row blocks slots of cout x cin x 9), bias gradients
-// (batch x rows slots of cout), the head (blocks of 17) and the loss.
+// (batch x rows slots of cout), the head (blocks of 17), the loss and the
+// rms row sums.
 size_t parts_floats(const Net& net) {
     size_t most = 0;
     const size_t B = size_t(net.batch);
@@ -554,6 +589,7 @@ size_t parts_floats(const Net& net) {
     }
     const size_t px0 = B * size_t(net.n[0]) * size_t(net.n[0]);
     most = std::max(most, (px0 + 255) / 256 * 17);
+    most = std::max(most, 2 * B * size_t(net.n[0]));  // the rms row sums (doubles)
     return most;
 }
 
@@ -662,6 +698,7 @@ hipError_t wgrad(const Net& net, const Layer& L, const bf16* x, int64_t xs, cons
     hipLaunchKernelGGL(k_reduce_parts, dim3(unsigned(wcount)), dim3(256), 0, s, net.parts,
                        int64_t(batch) * rb, wcount, net.grad + L.w_off);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (L.cout > 256 || (256 % L.cout) != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_bias_grad, dim3(unsigned(int64_t(batch) * a.h)), dim3(256), 0, s, dy, dys,
                        y, ys, net.parts, a.wd, L.cout);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -686,6 +723,7 @@ namespace {
 
 hipError_t restrict_op(const Net& net, const bf16* in, int64_t is, bf16* out, int64_t os, int batch,
                        int nc, int c, float scale, int acc, hipStream_t s) {
+    if (int64_t(batch) * nc * nc * c > (int64_t(1) << 32) - 256) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_restrict, dim3(blocks_for(int64_t(batch) * nc * nc * c)), dim3(256), 0, s,
                        in, is, out, os, batch, nc, c, net.factor, scale, acc);
     return hipGetLastError();
@@ -694,6 +732,7 @@ hipError_t restrict_op(const Net& net, const bf16* in, int64_t is, bf16* out, in
 hipError_t prolong_op(const Net& net, const bf16* in, int64_t is, bf16* out, int64_t os, int batch,
                       int nc, int c, float scale, int acc, hipStream_t s) {
     const int nf = net.factor * nc + net.factor - 1;
+    if (int64_t(batch) * nf * nf * c > (int64_t(1) << 32) - 256) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_prolong, dim3(blocks_for(int64_t(batch) * nf * nf * c)), dim3(256), 0, s,
                        in, is, out, os, batch, nc, c, net.factor, scale, acc);
     return hipGetLastError();
@@ -719,7 +758,12 @@ const Layer& layer(const Net& net, const char* name) {
 hipError_t forward(Net& net, int batch, const double* f, int64_t ld, int64_t gstride,
                    hipStream_t s) {
     const int n0 = net.n[0];
-    hipLaunchKernelGGL(k_rms, dim3(batch), dim3(256), 0, s, f, n0, ld, gstride, net.rms);
+    // the row sums sit in the gradient partials, which are free during a forward pass
+    double* rows = reinterpret_cast<double*>(net.parts);
+    hipLaunchKernelGGL(k_rms_rows, dim3(unsigned(batch * n0)), dim3(256), 0, s, f, n0, ld, gstride,
+                       rows);
+    NN_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_rms_final, dim3(batch), dim3(256), 0, s, rows, n0, net.rms);
     NN_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_input, dim3(blocks_for(int64_t(batch) * n0 * n0)), dim3(256), 0, s, f, n0,
                        ld, gstride, net.rms, net.in[0], batch);
