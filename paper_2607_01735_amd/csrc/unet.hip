@@ -132,10 +132,15 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
 
 // Weight gradient dW[co][ci][tap] = sum_p dZ[p][co] * X[p + off(tap)][ci],
 // dZ = dY masked by (Y > 0).  MFMA with M = 16 output channels, N = 16
-// input channels, K = 16 pixels of a row; one wave per (sample, row block,
-// tap, ci tile, co tile).  Each wave stores its partial sums in its own slot
-// (part[sample * rblocks + row block][co][ci][tap]); k_reduce_parts adds the
-// slots in a fixed order, so the gradient has the same bits on every run.
+// input channels, K = 16 pixels of a row.  A workgroup of four waves takes
+// four consecutive rows of one sample (one row per wave) for one (ci tile,
+// co tile) pair and all nine taps: per 16-pixel chunk a wave loads its dZ
+// operand once and, for each of the three X rows, the six pixels its lane
+// group spans once, and issues the nine taps' MFMAs from them.  The four
+// waves' sums meet in LDS and are added in a fixed order ((w0 + w1) + (w2 +
+// w3)) into the workgroup's slot (part[sample * row quads + quad][co][ci]
+// [tap]); k_reduce_parts adds the slots in a fixed order, so the gradient
+// has the same bits on every run.
 struct WGradArgs {
     const bf16* x;
     int64_t xs;
@@ -143,60 +148,84 @@ struct WGradArgs {
     int64_t dys;
     const bf16* y;  // layer output (mask), stride ys
     int64_t ys;
-    float* part;    // [batch * row blocks][cout][cin_w][9] partial sums
-    int batch, h, wd, cin, cout, rows_per_wave;
+    float* part;    // [batch * row quads][cout][cin_w][9] partial sums
+    int batch, h, wd, cin, cout;
     int cin_w;      // input channels of the weight tensor (cin is padded to 16)
 };
 
+constexpr int kWgradRows = 4;  // rows per workgroup (one per wave)
+
 __global__ __launch_bounds__(256) void k_conv3x3_wgrad(WGradArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int cit = a.cin / 16, cot = a.cout / 16;
-    const int rblocks = (a.h + a.rows_per_wave - 1) / a.rows_per_wave;
-    const int64_t total = int64_t(a.batch) * rblocks * 9 * cit * cot;
-    if (wave >= total) return;
-    int64_t r = wave;
-    const int co_t = int(r % cot); r /= cot;
-    const int ci_t = int(r % cit); r /= cit;
-    const int tap = int(r % 9); r /= 9;
-    const int rb = int(r % rblocks); r /= rblocks;
-    const int b = int(r);
-    const int dyo = tap / 3 - 1, dxo = tap % 3 - 1;
+    const int quads = (a.h + kWgradRows - 1) / kWgradRows;
+    int64_t r = blockIdx.x;  // the grid is exactly batch x quads x cit x cot
+    const int co_t = int(r % cot);
+    r /= cot;
+    const int ci_t = int(r % cit);
+    r /= cit;
+    const int qd = int(r % quads);
+    const int b = int(r / quads);
+    const int row = qd * kWgradRows + wv;
     const int l16 = lane & 15, kq = (lane >> 4) * 4;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    const int r0 = rb * a.rows_per_wave, r1 = min(a.h, r0 + a.rows_per_wave);
-    for (int row = r0; row < r1; ++row) {
-        const int yy = row + dyo;
+    f32x4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (row < a.h) {
+        const int64_t prow = (int64_t(b) * a.h + row) * a.wd;  // first pixel of the row
+        const bf16* ym = a.y + prow * a.ys + co_t * 16 + l16;
+        const bf16* dym = a.dy + prow * a.dys + co_t * 16 + l16;
+        const bf16* xr[3];
+        bool rok[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int yy = row + d - 1;
+            rok[d] = yy >= 0 && yy < a.h;
+            xr[d] = a.x + ((int64_t(b) * a.h + (rok[d] ? yy : row)) * a.wd) * a.xs + ci_t * 16 + l16;
+        }
         for (int x0 = 0; x0 < a.wd; x0 += 16) {
-            bf16x4 av, bv;
+            const int xb = x0 + kq;  // this lane group's first pixel
+            bf16x4 av;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int xx = x0 + kq + j;
-                float g = 0.f;
-                float xv = 0.f;
-                if (xx < a.wd) {
-                    const int64_t p = (int64_t(b) * a.h + row) * a.wd + xx;
-                    const int co = co_t * 16 + l16;
-                    if (bf2f(a.y[p * a.ys + co]) > 0.f) g = bf2f(a.dy[p * a.dys + co]);
-                    const int xs2 = xx + dxo;
-                    if (yy >= 0 && yy < a.h && xs2 >= 0 && xs2 < a.wd) {
-                        const int64_t q = (int64_t(b) * a.h + yy) * a.wd + xs2;
-                        xv = bf2f(a.x[q * a.xs + ci_t * 16 + l16]);
-                    }
-                }
-                av[j] = short(f2bf(g));
-                bv[j] = short(f2bf(xv));
+                const int xx = xb + j;
+                bf16 g = 0;
+                if (xx < a.wd && bf2f(ym[int64_t(xx) * a.ys]) > 0.f) g = dym[int64_t(xx) * a.dys];
+                av[j] = short(g);
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                // X at pixels xb - 1 .. xb + 4 of row `row + d - 1` (0 outside)
+                bf16 xv[6];
+#pragma unroll
+                for (int m = 0; m < 6; ++m) {
+                    const int xs2 = xb - 1 + m;
+                    xv[m] = (rok[d] && xs2 >= 0 && xs2 < a.wd) ? xr[d][int64_t(xs2) * a.xs] : bf16(0);
+                }
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    bf16x4 bv;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) bv[j] = xb + j < a.wd ? short(xv[j + dx]) : short(0);
+                    acc[d * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[d * 3 + dx], 0, 0, 0);
+                }
+            }
         }
     }
+    // [wave][tap][co][ci] in LDS, then the fixed-order sum over the waves
+    __shared__ float sh[kWgradRows][9][16][16];
     const int n = lane & 15, mq = (lane >> 4) * 4;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int co = co_t * 16 + mq + i, ci = ci_t * 16 + n;
-        const int64_t slot = int64_t(b) * rblocks + rb;
-        if (ci < a.cin_w)
-            a.part[((slot * a.cout + co) * a.cin_w + ci) * 9 + tap] = acc[i];
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sh[wv][t][mq + i][n] = acc[t][i];
+    __syncthreads();
+    const int64_t slot = int64_t(b) * quads + qd;
+    for (int e = threadIdx.x; e < 16 * 16 * 9; e += 256) {
+        const int tap = e % 9, ci = (e / 9) % 16, co = e / 144;
+        const float v = (sh[0][tap][co][ci] + sh[1][tap][co][ci]) + (sh[2][tap][co][ci] + sh[3][tap][co][ci]);
+        const int ci_g = ci_t * 16 + ci, co_g = co_t * 16 + co;
+        if (ci_g < a.cin_w) a.part[((slot * a.cout + co_g) * a.cin_w + ci_g) * 9 + tap] = v;
     }
 }
 
@@ -572,7 +601,7 @@ namespace {
 int cat_channels(int l) { return kC[l + 1] + kC[l]; }
 int in_channels(int l) { return l == 0 ? 16 : kC[l - 1]; }
 
-int wgrad_rows_per_wave(int h) { return h >= 128 ? 4 : (h >= 64 ? 8 : 16); }
+int wgrad_quads(int h) { return (h + kWgradRows - 1) / kWgradRows; }
 
 // Floats of partial sums the largest fixed-order reduction needs: weight
 // gradients (batch x row blocks slots of cout x cin x 9), bias gradients
@@ -583,7 +612,7 @@ size_t parts_floats(const Net& net) {
     const size_t B = size_t(net.batch);
     for (const auto& l : net.layers) {
         const int h = net.n[l.level];
-        const size_t rb = size_t((h + wgrad_rows_per_wave(h) - 1) / wgrad_rows_per_wave(h));
+        const size_t rb = size_t(wgrad_quads(h));
         most = std::max(most, B * rb * size_t(l.cout) * size_t(l.cin) * 9);
         most = std::max(most, B * size_t(h) * size_t(l.cout));
     }
@@ -686,12 +715,11 @@ hipError_t wgrad(const Net& net, const Layer& L, const bf16* x, int64_t xs, cons
     a.h = a.wd = net.n[L.level];
     a.cin = L.cin_p;
     a.cout = L.cout;
-    a.rows_per_wave = wgrad_rows_per_wave(a.h);
     a.cin_w = L.cin;  // the first layer's padded input channels feed no weight
     a.part = net.parts;
-    const int rb = (a.h + a.rows_per_wave - 1) / a.rows_per_wave;
-    const int64_t waves = int64_t(batch) * rb * 9 * (a.cin / 16) * (a.cout / 16);
-    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
+    const int rb = wgrad_quads(a.h);
+    const int64_t blocks = int64_t(batch) * rb * (a.cin / 16) * (a.cout / 16);
+    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(unsigned(blocks)), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t wcount = int64_t(L.cout) * L.cin * 9;
