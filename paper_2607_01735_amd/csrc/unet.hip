@@ -48,10 +48,16 @@ __device__ __forceinline__ bf16 f2bf(float x) {
 
 // ---------------------------------------------------------------------------
 // 3x3 convolution, stride 1, zero padding 1, as an implicit GEMM.
-// One wave computes 16 consecutive pixels of one row for all output
-// channels.  MFMA 16x16x16 lane layout (checked on the device):
+// One wave computes kConvGroups x 16 consecutive pixels of one row for all
+// output channels (NT tiles of 16), as D[co][pixel] = sum_k W[co][k]
+// X[k][pixel], K = 9 taps x input channels.  MFMA 16x16x16 lane layout
+// (checked on the device):
 //   A[m][k]: lane l holds m = l%16, k = 4(l/16)+j;  B[k][n]: n = l%16,
 //   k = 4(l/16)+j;  D[m][n]: lane l holds m = 4(l/16)+i, n = l%16.
+// So a lane loads four consecutive input channels of one pixel (B) and of
+// one output channel's weights (A), 8 bytes each, and stores four
+// consecutive output channels of one pixel, 8 bytes.  Each weight operand
+// is loaded once per wave and used for every pixel group.
 // X may be masked: an input element counts as 0 where mask <= 0 (this is
 // how the backward pass applies the ReLU derivative of the layer output).
 // ---------------------------------------------------------------------------
@@ -67,65 +73,91 @@ struct ConvArgs {
     int batch, h, wd, cin, cout, relu;
 };
 
-constexpr int kMaxCoutTiles = 12;  // up to 192 output channels
+constexpr int kConvGroups = 2;  // 16-pixel groups per wave
 
+__device__ __forceinline__ bf16x4 load4(const bf16* p) {
+    // four consecutive channels: 8 bytes, 8-byte aligned (channel strides
+    // and offsets are multiples of 4)
+    return *reinterpret_cast<const bf16x4*>(p);
+}
+
+template <int NT, bool MASK>
 __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
+    constexpr int PG = kConvGroups;
     const int lane = threadIdx.x & 63;
-    const int64_t wave = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    const int segs = (a.wd + 15) / 16;
-    const int64_t total = int64_t(a.batch) * a.h * segs;
-    if (wave >= total) return;
-    const int seg = int(wave % segs);
-    const int row = int((wave / segs) % a.h);
-    const int b = int(wave / (int64_t(segs) * a.h));
-    const int x0 = seg * 16;
-    const int ntiles = a.cout / 16;
-    f32x4 acc[kMaxCoutTiles];
+    const int wave = int(blockIdx.x) * 4 + int(threadIdx.x >> 6);
+    const int segs = (a.wd + 16 * PG - 1) / (16 * PG);
+    if (wave >= a.batch * a.h * segs) return;
+    const int seg = wave % segs;
+    const int rowb = wave / segs;  // sample * h + row
+    const int row = rowb % a.h;
+    const int b = rowb / a.h;
+    const int x0 = seg * 16 * PG;
+    f32x4 acc[PG][NT];
 #pragma unroll
-    for (int t = 0; t < kMaxCoutTiles; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int m = lane & 15, kq = (lane >> 4) * 4;
-    for (int tap = 0; tap < 9; ++tap) {
-        const int yy = row + tap / 3 - 1, xx = x0 + m + tap % 3 - 1;
-        const bool inside = yy >= 0 && yy < a.h && xx >= 0 && xx < a.wd;
-        const int64_t pix = (int64_t(b) * a.h + yy) * a.wd + xx;
-        for (int c0 = 0; c0 < a.cin; c0 += 16) {
-            bf16x4 av = {0, 0, 0, 0};
-            if (inside) {
-                const bf16* px = a.x + pix * a.xs + c0 + kq;
+    for (int g = 0; g < PG; ++g)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) av[j] = short(px[j]);
-                if (a.mask) {
-                    const bf16* pm = a.mask + pix * a.ms + c0 + kq;
+        for (int t = 0; t < NT; ++t) acc[g][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int n = lane & 15, kq = (lane >> 4) * 4;
+    // Per 16-channel chunk and kernel row: the three taps' input operands
+    // are loaded first (pixels outside the grid read a pixel inside and are
+    // zeroed after the load, so no load sits behind a branch and they are in
+    // flight together), then each output tile's three weight operands and
+    // MFMAs.
+    for (int c0 = 0; c0 < a.cin; c0 += 16) {
+#pragma unroll 1
+        for (int d = 0; d < 3; ++d) {
+            const int yy = row + d - 1;
+            const bool rowok = yy >= 0 && yy < a.h;
+            const int64_t rbase = int64_t(b * a.h + (rowok ? yy : row)) * a.wd;
+            bf16x4 xv[3][PG];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (!(bf2f(pm[j]) > 0.f)) av[j] = 0;
+            for (int dx = 0; dx < 3; ++dx) {
+#pragma unroll
+                for (int g = 0; g < PG; ++g) {
+                    const int xx = x0 + g * 16 + n + dx - 1;
+                    const bool ok = rowok && xx >= 0 && xx < a.wd;
+                    const int64_t pix = rbase + (ok ? xx : 0);
+                    bf16x4 v = load4(a.x + pix * a.xs + c0 + kq);
+                    if (MASK) {
+                        const bf16x4 mv = load4(a.mask + pix * a.ms + c0 + kq);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (!(bf2f(bf16(mv[j])) > 0.f)) v[j] = 0;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) xv[dx][g][j] = ok ? v[j] : short(0);
                 }
             }
 #pragma unroll
-            for (int t = 0; t < kMaxCoutTiles; ++t) {
-                if (t < ntiles) {
-                    const bf16* pw = a.w + (int64_t(t * 16 + m) * 9 + tap) * a.cin + c0 + kq;
-                    bf16x4 bv;
+            for (int t = 0; t < NT; ++t) {
+                const bf16* pw = a.w + (int64_t(t * 16 + n) * 9 + d * 3) * a.cin + c0 + kq;
+                bf16x4 wv[3];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) bv[j] = short(pw[j]);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
-                }
+                for (int dx = 0; dx < 3; ++dx) wv[dx] = load4(pw + dx * a.cin);
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                    for (int g = 0; g < PG; ++g)
+                        acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wv[dx], xv[dx][g], acc[g][t], 0, 0, 0);
             }
         }
     }
-    const int n = lane & 15, mq = (lane >> 4) * 4;
 #pragma unroll
-    for (int t = 0; t < kMaxCoutTiles; ++t) {
-        if (t < ntiles) {
-            const int co = t * 16 + n;
-            const float bias = a.bias ? a.bias[co] : 0.f;
+    for (int g = 0; g < PG; ++g) {
+        const int xx = x0 + g * 16 + n;
+        if (xx >= a.wd) continue;
+        bf16* py = a.y + (int64_t(b * a.h + row) * a.wd + xx) * a.ys + kq;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            bf16x4 out;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int xx = x0 + mq + i;
-                float v = acc[t][i] + bias;
+                float v = acc[g][t][i] + (a.bias ? a.bias[t * 16 + kq + i] : 0.f);
                 if (a.relu) v = v > 0.f ? v : 0.f;
-                if (xx < a.wd) a.y[((int64_t(b) * a.h + row) * a.wd + xx) * a.ys + co] = f2bf(v);
+                out[i] = short(f2bf(v));
             }
+            *reinterpret_cast<bf16x4*>(py + t * 16) = out;
         }
     }
 }
@@ -275,6 +307,41 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ 
     if (threadIdx.x == 0) out[e] = sh[0];
 }
 
+// The same sums for many slots, in two coalesced passes: pass 1 splits the
+// slots into kReduceChunks contiguous chunks; a block takes 64 consecutive
+// elements and one chunk, its four waves add slots g, g + 4, ... of the
+// chunk (each wave reading 64 consecutive floats of a slot), and the four
+// wave sums are added as (w0 + w1) + (w2 + w3) into stage[chunk][e];
+// pass 2 adds the chunks in order.  A fixed order again.
+constexpr int kReduceChunks = 16;
+
+__global__ __launch_bounds__(256) void k_reduce_chunks(const float* __restrict__ part,
+                                                       int64_t nparts, int64_t count,
+                                                       float* __restrict__ stage) {
+    const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t e = int64_t(blockIdx.x) * 64 + l;
+    const int64_t per = (nparts + kReduceChunks - 1) / kReduceChunks;
+    const int64_t k0 = int64_t(blockIdx.y) * per;
+    const int64_t k1 = k0 + per < nparts ? k0 + per : nparts;
+    float acc = 0.f;
+    if (e < count)
+        for (int64_t k = k0 + g; k < k1; k += 4) acc += part[k * count + e];
+    __shared__ float sh[4][64];
+    sh[g][l] = acc;
+    __syncthreads();
+    if (g == 0 && e < count)
+        stage[int64_t(blockIdx.y) * count + e] = (sh[0][l] + sh[1][l]) + (sh[2][l] + sh[3][l]);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_stage(const float* __restrict__ stage,
+                                                      int64_t count, float* __restrict__ out) {
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= count) return;
+    float s = 0.f;
+    for (int c = 0; c < kReduceChunks; ++c) s += stage[int64_t(c) * count + e];
+    out[e] = s;
+}
+
 // Grid transfers between levels coarsened by a factor F (2 or 4): fine
 // n_f = F n_c + F - 1, and coarse interior point (I, J) (0-based) sits on
 // fine interior point (F I + F - 1, F J + F - 1).  Restriction averages the
@@ -283,46 +350,81 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ 
 // prolongation is bilinear interpolation, P = F^2 R^T (1-D weights
 // (F - |d|) / F).  Per channel, scaled by `scale`; accumulate != 0 adds into
 // the output instead of overwriting.
+// One thread per (pixel, group of 8 channels): 16-byte loads and stores,
+// the index split and the weights formed once per 8 channels.  The host
+// keeps batch x pixels x c / 8 (and the grid) below 2^32 (32-bit indexing)
+// and c, the pixel strides and the base addresses in whole groups of 8.
+struct bf16x8 {
+    uint4 v;
+    __device__ float get(int k) const {
+        const uint32_t w = (&v.x)[k >> 1];
+        return __uint_as_float((k & 1) ? (w & 0xffff0000u) : (w << 16));
+    }
+    __device__ void set(int k, bf16 h) {
+        uint32_t& w = (&v.x)[k >> 1];
+        w = (k & 1) ? ((w & 0x0000ffffu) | (uint32_t(h) << 16)) : ((w & 0xffff0000u) | h);
+    }
+};
+
+__device__ __forceinline__ bf16x8 load8(const bf16* p) {
+    return bf16x8{*reinterpret_cast<const uint4*>(p)};
+}
+
 __global__ __launch_bounds__(256) void k_restrict(const bf16* in, int64_t is, bf16* out, int64_t os,
                                                   int batch, int nc, int c, int F, float scale,
                                                   int accumulate) {
-    // the host keeps batch nc^2 c (and the grid) below 2^32: 32-bit indexing
+    const int c8 = c / 8;
     const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
-    const uint32_t total = uint32_t(batch) * uint32_t(nc) * uint32_t(nc) * uint32_t(c);
+    const uint32_t total = uint32_t(batch) * uint32_t(nc) * uint32_t(nc) * uint32_t(c8);
     if (idx >= total) return;
-    const int ch = int(idx % uint32_t(c));
-    uint32_t r = idx / uint32_t(c);
+    const int ch = int(idx % uint32_t(c8)) * 8;
+    uint32_t r = idx / uint32_t(c8);
     const int J = int(r % uint32_t(nc));
     r /= uint32_t(nc);
     const int I = int(r % uint32_t(nc));
     const int b = int(r / uint32_t(nc));
     const int nf = F * nc + F - 1;
     const int ci = F * I + F - 1, cj = F * J + F - 1;
-    float s = 0.f;
+    float s[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] = 0.f;
     for (int di = 1 - F; di < F; ++di) {
         const float wi = float(F - (di < 0 ? -di : di));
         const bf16* row = in + ((int64_t(b) * nf + ci + di) * nf + cj) * is + ch;
-        float t = 0.f;
-        for (int dj = 1 - F; dj < F; ++dj)
-            t += float(F - (dj < 0 ? -dj : dj)) * bf2f(row[dj * is]);
-        s += wi * t;
+        float t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t[k] = 0.f;
+        for (int dj = 1 - F; dj < F; ++dj) {
+            const float wj = float(F - (dj < 0 ? -dj : dj));
+            const bf16x8 x = load8(row + dj * is);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) t[k] += wj * x.get(k);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[k] += wi * t[k];
     }
-    s *= scale / float(F * F * F * F);
     bf16* o = out + ((int64_t(b) * nc + I) * nc + J) * os + ch;
-    if (accumulate) s += bf2f(*o);
-    *o = f2bf(s);
+    bf16x8 prev = accumulate ? load8(o) : bf16x8{make_uint4(0, 0, 0, 0)};
+    bf16x8 res;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        float v = s[k] * (scale / float(F * F * F * F));
+        if (accumulate) v += prev.get(k);
+        res.set(k, f2bf(v));
+    }
+    *reinterpret_cast<uint4*>(o) = res.v;
 }
 
 __global__ __launch_bounds__(256) void k_prolong(const bf16* in, int64_t is, bf16* out, int64_t os,
                                                  int batch, int nc, int c, int F, float scale,
                                                  int accumulate) {
     const int nf = F * nc + F - 1;
-    // the host keeps batch nf^2 c (and the grid) below 2^32: 32-bit indexing
+    const int c8 = c / 8;
     const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
-    const uint32_t total = uint32_t(batch) * uint32_t(nf) * uint32_t(nf) * uint32_t(c);
+    const uint32_t total = uint32_t(batch) * uint32_t(nf) * uint32_t(nf) * uint32_t(c8);
     if (idx >= total) return;
-    const int ch = int(idx % uint32_t(c));
-    uint32_t r = idx / uint32_t(c);
+    const int ch = int(idx % uint32_t(c8)) * 8;
+    uint32_t r = idx / uint32_t(c8);
     const int j = int(r % uint32_t(nf));
     r /= uint32_t(nf);
     const int i = int(r % uint32_t(nf));
@@ -330,7 +432,9 @@ __global__ __launch_bounds__(256) void k_prolong(const bf16* in, int64_t is, bf1
     // the coarse points within F - 1 of fine i are I = (i + 1) / F - 1 and
     // the next one; weight (F - |d|) / F with d = i - (F I + F - 1)
     const float invF = 1.f / float(F);
-    float s = 0.f;
+    float s[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] = 0.f;
     for (int I = (i + 1) / F - 1; I <= (i + 1) / F; ++I) {
         const int di = i - (F * I + F - 1);
         if (I < 0 || I >= nc || di <= -F || di >= F) continue;
@@ -339,13 +443,21 @@ __global__ __launch_bounds__(256) void k_prolong(const bf16* in, int64_t is, bf1
             const int dj = j - (F * J + F - 1);
             if (J < 0 || J >= nc || dj <= -F || dj >= F) continue;
             const float wj = float(F - (dj < 0 ? -dj : dj)) * invF;
-            s += wi * wj * bf2f(in[((int64_t(b) * nc + I) * nc + J) * is + ch]);
+            const bf16x8 x = load8(in + ((int64_t(b) * nc + I) * nc + J) * is + ch);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s[k] += wi * wj * x.get(k);
         }
     }
-    s *= scale;
     bf16* o = out + ((int64_t(b) * nf + i) * nf + j) * os + ch;
-    if (accumulate) s += bf2f(*o);
-    *o = f2bf(s);
+    bf16x8 prev = accumulate ? load8(o) : bf16x8{make_uint4(0, 0, 0, 0)};
+    bf16x8 res;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        float v = s[k] * scale;
+        if (accumulate) v += prev.get(k);
+        res.set(k, f2bf(v));
+    }
+    *reinterpret_cast<uint4*>(o) = res.v;
 }
 
 // Sum of one double per thread over a block of 256, by a fixed tree; every
@@ -408,13 +520,16 @@ __global__ __launch_bounds__(256) void k_input(const double* f, int n, int64_t l
     for (int c = 1; c < 16; ++c) px[c] = 0;
 }
 
-// Head: y[p] = sum_c w[c] d[p][c] + b (FP32 out).
+// Head: y[p] = sum_c w[c] d[p][c] + b (FP32 out).  c = 16 channels at
+// pixel stride ds (a multiple of 8, 16-byte aligned rows): two 16-byte
+// loads per pixel.
 __global__ __launch_bounds__(256) void k_head(const bf16* d, int64_t ds, const float* w,
                                               const float* bias, float* y, int64_t npix, int c) {
     const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (p >= npix) return;
+    const bf16x8 lo = load8(d + p * ds), hi = load8(d + p * ds + 8);
     float s = bias[0];
-    for (int ch = 0; ch < c; ++ch) s += w[ch] * bf2f(d[p * ds + ch]);
+    for (int ch = 0; ch < c; ++ch) s += w[ch] * (ch < 8 ? lo.get(ch) : hi.get(ch - 8));
     y[p] = s;
 }
 
@@ -456,29 +571,47 @@ __global__ __launch_bounds__(256) void k_mse(const float* y, const double* u, co
 
 // Head backward: dd[p][c] = w[c] dy[p] (BF16); per block, the partial sums
 // of dy d[c] (c < 16) and of dy go to part[block][0..16] (k_reduce_parts
-// adds the blocks in order into dw[0..15], db = dw[16]).
+// adds the blocks in order into dw[0..15], db = dw[16]).  Within a block:
+// a fixed butterfly over each wave's 64 lanes, then the four waves in
+// order.  d and dd: 16 channels at pixel strides that are multiples of 8,
+// moved as two 16-byte accesses per pixel.
 __global__ __launch_bounds__(256) void k_head_grad(const bf16* d, int64_t ds, const float* w,
                                                    const float* dy, bf16* dd, int64_t dds,
                                                    float* part, int64_t npix, int c) {
     const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    __shared__ float sw[17][256];
     const bool ok = p < npix;
     const float g = ok ? dy[p] : 0.f;
-    for (int ch = 0; ch < c; ++ch) {
-        if (ok) dd[p * dds + ch] = f2bf(w[ch] * g);
-        sw[ch][threadIdx.x] = ok ? g * bf2f(d[p * ds + ch]) : 0.f;
+    float v[17];
+    if (ok) {
+        const bf16x8 lo = load8(d + p * ds), hi = load8(d + p * ds + 8);
+        bf16x8 olo{make_uint4(0, 0, 0, 0)}, ohi{make_uint4(0, 0, 0, 0)};
+#pragma unroll
+        for (int ch = 0; ch < 16; ++ch) {
+            const float dv = ch < 8 ? lo.get(ch) : hi.get(ch - 8);
+            const bf16 o = ch < c ? f2bf(w[ch] * g) : bf16(0);
+            if (ch < 8) olo.set(ch, o); else ohi.set(ch - 8, o);
+            v[ch] = ch < c ? g * dv : 0.f;
+        }
+        *reinterpret_cast<uint4*>(dd + p * dds) = olo.v;
+        *reinterpret_cast<uint4*>(dd + p * dds + 8) = ohi.v;
+    } else {
+#pragma unroll
+        for (int ch = 0; ch < 16; ++ch) v[ch] = 0.f;
     }
-    sw[16][threadIdx.x] = g;
+    v[16] = g;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < 17; ++k) v[k] += __shfl_xor(v[k], off, 64);
+    __shared__ float sw[4][17];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 17; ++k) sw[wv][k] = v[k];
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if (threadIdx.x < st)
-            for (int ch = 0; ch <= 16; ++ch) sw[ch][threadIdx.x] += sw[ch][threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        for (int ch = 0; ch < 16; ++ch) part[int64_t(blockIdx.x) * 17 + ch] = ch < c ? sw[ch][0] : 0.f;
-        part[int64_t(blockIdx.x) * 17 + 16] = sw[16][0];
-    }
+    if (threadIdx.x < 17)
+        part[int64_t(blockIdx.x) * 17 + threadIdx.x] =
+            ((sw[0][threadIdx.x] + sw[1][threadIdx.x]) + sw[2][threadIdx.x]) + sw[3][threadIdx.x];
 }
 
 // Master FP32 weights [co][ci][9] -> forward BF16 [co][9][cin_p] (zero-padded
@@ -587,6 +720,8 @@ struct Net {
     float *param, *grad, *m, *v, *rms, *loss, *y, *dy;
     float* parts = nullptr;  // partial sums of the fixed-order gradient reductions
     size_t parts_floats = 0;
+    float* stage = nullptr;  // per-chunk sums of the two-pass reduction
+    size_t stage_floats = 0;
     double* guess;  // natural-layout scratch grid for the learned solve
     int adam_t = 0;
     // activations (level-indexed) and their gradients
@@ -646,6 +781,10 @@ size_t carve(Net& net, char* base) {
     net.dy = reinterpret_cast<float*>(take(B * px0 * 4));
     net.parts_floats = parts_floats(net);
     net.parts = reinterpret_cast<float*>(take(net.parts_floats * 4));
+    size_t most = 0;
+    for (const auto& l : net.layers) most = std::max(most, size_t(l.cout) * size_t(l.cin) * 9);
+    net.stage_floats = size_t(kReduceChunks) * most;
+    net.stage = reinterpret_cast<float*>(take(net.stage_floats * 4));
     net.guess = reinterpret_cast<double*>(take(size_t(net.n[0] + 2) * (net.n[0] + 2) * 8));
     for (int l = 0; l < kLevels; ++l) {
         const int64_t px = B * net.n[l] * net.n[l];
@@ -673,6 +812,21 @@ unsigned blocks_for(int64_t items, int per_block = 256) {
     return unsigned((items + per_block - 1) / per_block);
 }
 
+template <bool MASK>
+hipError_t launch_conv(const ConvArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+    switch (a.cout / 16) {
+        case 1: hipLaunchKernelGGL((k_conv3x3<1, MASK>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_conv3x3<2, MASK>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_conv3x3<3, MASK>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_conv3x3<4, MASK>), grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_conv3x3<6, MASK>), grid, block, 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_conv3x3<8, MASK>), grid, block, 0, s, a); break;
+        case 12: hipLaunchKernelGGL((k_conv3x3<12, MASK>), grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t conv(const Net& net, const Layer& L, const bf16* x, int64_t xs, const bf16* mask,
                 int64_t ms, bool forward, bf16* y, int64_t ys, int batch, hipStream_t s) {
     ConvArgs a;
@@ -697,8 +851,27 @@ hipError_t conv(const Net& net, const Layer& L, const bf16* x, int64_t xs, const
     }
     a.y = y;
     a.ys = ys;
-    const int64_t waves = int64_t(batch) * a.h * ((a.wd + 15) / 16);
-    hipLaunchKernelGGL(k_conv3x3, dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
+    const int64_t waves = int64_t(batch) * a.h * ((a.wd + 16 * kConvGroups - 1) / (16 * kConvGroups));
+    if (waves > (int64_t(1) << 31) - 4 || int64_t(batch) * a.h * a.wd >= (int64_t(1) << 31))
+        return hipErrorInvalidValue;
+    // 8-byte operand loads and stores: channel strides, counts and base
+    // addresses in whole groups of four channels
+    if ((a.xs | a.ys | a.cin | (a.mask ? a.ms : 0)) % 4 != 0 || a.cout % 16 != 0 ||
+        (reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.y) |
+         reinterpret_cast<uintptr_t>(a.w) | reinterpret_cast<uintptr_t>(a.mask)) % 8 != 0)
+        return hipErrorInvalidValue;
+    const dim3 grid(blocks_for(waves, 4)), block(256);
+    return a.mask ? launch_conv<true>(a, grid, block, s) : launch_conv<false>(a, grid, block, s);
+}
+
+// out[e] = sum over the nparts slots of net.parts[k * count + e] (two passes).
+hipError_t reduce_slots(const Net& net, int64_t nparts, int64_t count, float* out, hipStream_t s) {
+    if (size_t(count) * kReduceChunks > net.stage_floats) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(unsigned((count + 63) / 64), kReduceChunks), dim3(256), 0,
+                       s, net.parts, nparts, count, net.stage);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_stage, dim3(blocks_for(count)), dim3(256), 0, s, net.stage, count, out);
     return hipGetLastError();
 }
 
@@ -723,16 +896,13 @@ hipError_t wgrad(const Net& net, const Layer& L, const bf16* x, int64_t xs, cons
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t wcount = int64_t(L.cout) * L.cin * 9;
-    hipLaunchKernelGGL(k_reduce_parts, dim3(unsigned(wcount)), dim3(256), 0, s, net.parts,
-                       int64_t(batch) * rb, wcount, net.grad + L.w_off);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = reduce_slots(net, int64_t(batch) * rb, wcount, net.grad + L.w_off, s)) != hipSuccess)
+        return e;
     if (L.cout > 256 || (256 % L.cout) != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_bias_grad, dim3(unsigned(int64_t(batch) * a.h)), dim3(256), 0, s, dy, dys,
                        y, ys, net.parts, a.wd, L.cout);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_parts, dim3(unsigned(L.cout)), dim3(256), 0, s, net.parts,
-                       int64_t(batch) * a.h, int64_t(L.cout), net.grad + L.b_off);
-    return hipGetLastError();
+    return reduce_slots(net, int64_t(batch) * a.h, int64_t(L.cout), net.grad + L.b_off, s);
 }
 
 }  // namespace
@@ -749,10 +919,17 @@ namespace {
         if (_e != hipSuccess) return _e;     \
     } while (0)
 
+// The transfers move whole groups of 8 channels with 16-byte accesses.
+bool transfer_ok(const bf16* in, int64_t is, const bf16* out, int64_t os, int c) {
+    return c > 0 && c % 8 == 0 && is % 8 == 0 && os % 8 == 0 &&
+           (reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) % 16 == 0;
+}
+
 hipError_t restrict_op(const Net& net, const bf16* in, int64_t is, bf16* out, int64_t os, int batch,
                        int nc, int c, float scale, int acc, hipStream_t s) {
-    if (int64_t(batch) * nc * nc * c > (int64_t(1) << 32) - 256) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_restrict, dim3(blocks_for(int64_t(batch) * nc * nc * c)), dim3(256), 0, s,
+    if (!transfer_ok(in, is, out, os, c) || int64_t(batch) * nc * nc * (c / 8) > (int64_t(1) << 32) - 256)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_restrict, dim3(blocks_for(int64_t(batch) * nc * nc * (c / 8))), dim3(256), 0, s,
                        in, is, out, os, batch, nc, c, net.factor, scale, acc);
     return hipGetLastError();
 }
@@ -760,8 +937,9 @@ hipError_t restrict_op(const Net& net, const bf16* in, int64_t is, bf16* out, in
 hipError_t prolong_op(const Net& net, const bf16* in, int64_t is, bf16* out, int64_t os, int batch,
                       int nc, int c, float scale, int acc, hipStream_t s) {
     const int nf = net.factor * nc + net.factor - 1;
-    if (int64_t(batch) * nf * nf * c > (int64_t(1) << 32) - 256) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_prolong, dim3(blocks_for(int64_t(batch) * nf * nf * c)), dim3(256), 0, s,
+    if (!transfer_ok(in, is, out, os, c) || int64_t(batch) * nf * nf * (c / 8) > (int64_t(1) << 32) - 256)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_prolong, dim3(blocks_for(int64_t(batch) * nf * nf * (c / 8))), dim3(256), 0, s,
                        in, is, out, os, batch, nc, c, net.factor, scale, acc);
     return hipGetLastError();
 }
