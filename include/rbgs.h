@@ -57,7 +57,10 @@ typedef enum {
     RBGS_ETIMEOUT = -4,     /* a bounded wait in the persistent kernel expired */
     RBGS_ENONFINITE = -5,   /* the residual became NaN or infinite         */
     RBGS_EUNSUPPORTED = -6, /* valid but not implemented (e.g. SOR in FP32)  */
-    RBGS_EWORKSPACE = -8    /* workspace missing, too small or misaligned  */
+    RBGS_EWORKSPACE = -8,   /* workspace missing, too small or misaligned  */
+    RBGS_EORDER = -9        /* debug_stamp_check: a persistent-kernel work item
+                               saw a neighbour tile more than one pass ahead
+                               (the dependency rule of Algorithm 2 broken)  */
 } rbgs_status;
 
 typedef enum {
@@ -141,6 +144,34 @@ typedef struct {
                                for this batch shape (127 FP32 / 63 FP64, or
                                never), else never; -1 = never.  Ignored
                                elsewhere.                                       */
+    /* Verification modes of the single-grid persistent (BLOCKED) kernel, for
+     * tests of the dependency rule (Section 2.3, Algorithm 2); results must
+     * not change.  RBGS_EUNSUPPORTED in batched sweeps.                     */
+    int32_t debug_tile_order;  /* order of the tiles within a pass: 0 as
+                                  numbered, 1 reversed, 2 a permutation per
+                                  pass drawn from debug_seed (tickets stay
+                                  pass-major, so no order can deadlock)      */
+    uint32_t debug_seed;       /* seed of debug_tile_order 2                  */
+    int32_t debug_stamp_check; /* 1: before and after each work item (pass p,
+                                  tile t), every tile of t's 3 x 3
+                                  neighbourhood must have completed p or p + 1
+                                  passes (p + 2 would mean it overwrote the
+                                  buffer t reads); else RBGS_EORDER          */
+    int32_t debug_trace_items; /* records debug_trace holds (0: no trace)      */
+    uint64_t *debug_trace;     /* DEVICE array of debug_trace_items records of
+                                  4 words, or NULL: for the work items of the
+                                  deeper passes (those rbgs_timing's
+                                  persistent_ms covers), record k = ticket k
+                                  of those launches in order (pass-major):
+                                  {start, end, (pass << 32) | tile,
+                                  (workgroup << 32) | ticket within its
+                                  launch}; start and end read the device's
+                                  constant-rate real-time counter (100 MHz)
+                                  after the dependency wait and after the
+                                  item's writes were released.  Records past
+                                  debug_trace_items are dropped; the caller
+                                  zero-fills the array to spot unwritten ones.
+                                  The array is owned by the caller.          */
 } rbgs_sweep_opts;
 
 /* Solve options.  Zero-initialise, then set what is needed. */

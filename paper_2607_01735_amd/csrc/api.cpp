@@ -168,7 +168,12 @@ int validate_sweep_opts(const rbgs_sweep_opts* o) {
         return fail(RBGS_EINVAL, "sweep options must be >= 0");
     if (o->rows_per_block > 4096) return fail(RBGS_EINVAL, "rows_per_block must be <= 4096");
     if (o->debug_delay > 1000) return fail(RBGS_EINVAL, "debug_delay must be <= 1000");
-    return validate_blocked_opts(o->fuse, o->tile_rows, o->tile_cols, &g_last_error);
+    int rc = validate_blocked_opts(o->fuse, o->tile_rows, o->tile_cols, &g_last_error);
+    if (rc != RBGS_OK) return rc;
+    if ((rc = validate_blocked_debug(o, &g_last_error)) != RBGS_OK) return rc;
+    if (o->debug_trace)
+        return check_device_range(o->debug_trace, size_t(o->debug_trace_items) * 32, "debug_trace");
+    return RBGS_OK;
 }
 
 struct EventTimer {
@@ -778,6 +783,7 @@ const char* rbgs_strerror(int status) {
         case RBGS_ENONFINITE: return "RBGS_ENONFINITE: non-finite residual";
         case RBGS_EUNSUPPORTED: return "RBGS_EUNSUPPORTED: unsupported option";
         case RBGS_EWORKSPACE: return "RBGS_EWORKSPACE: bad workspace";
+        case RBGS_EORDER: return "RBGS_EORDER: dependency stamp check failed";
         default: return "unknown rbgs status";
     }
 }

@@ -501,6 +501,10 @@ int validate_batch(int32_t count, const rbgs_grid* grids, int dt, void* const* u
         if (o->debug_delay < 0 || o->debug_delay > 1000 || o->debug_spin_limit < 0 ||
             o->debug_stall_tile < 0)
             return bfail(RBGS_EINVAL, "bad debug option");
+        if (o->debug_tile_order != 0 || o->debug_stamp_check != 0 || o->debug_trace != nullptr ||
+            o->debug_trace_items != 0)
+            return bfail(RBGS_EUNSUPPORTED,
+                         "tile orders, stamp checks and traces are for single-grid sweeps");
     }
     return RBGS_OK;
 }

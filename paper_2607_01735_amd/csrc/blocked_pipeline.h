@@ -62,6 +62,65 @@ struct Queue {
     const int* stop;  // converged flag of a graph-captured solve (nullptr: none)
 };
 
+// Verification modes of the single-grid kernel.  They run in a separate
+// instantiation (DBG = true), so the production kernel carries none of
+// their code or arguments.
+struct DebugModes {
+    int order = 0;          // tiles of a pass in ticket order: 0 as numbered,
+                            // 1 reversed, 2 a pseudo-random permutation per pass
+    uint32_t seed = 0;      // of the order-2 permutations
+    int stamp_check = 0;    // 1: check the neighbours' pass counts around each item
+    unsigned long long* trace = nullptr;  // per-item records (kTraceWords each), or none
+    long long trace_items = 0;            // records the array holds
+    long long trace_base = 0;             // record index of this launch's first ticket
+};
+
+// Error-word values: a bounded wait expired / the stamp check failed.
+constexpr int kErrTimeout = 1;
+constexpr int kErrOrder = 2;
+
+// A trace record: start and end of the item (the device's constant-rate
+// real-time counter, read after the dependency wait and after the item's
+// writes were released), (pass << 32) | tile, and (workgroup << 32) |
+// ticket-within-launch.
+constexpr int kTraceWords = 4;
+
+__device__ __forceinline__ uint32_t mix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    return h;
+}
+
+__device__ __forceinline__ int gcd_int(int a, int b) {
+    while (b != 0) {
+        const int t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Tile of the t-th ticket of a pass.  Tickets stay in pass-major order, so
+// every order is a topological order of the dependency graph (a pass-p item
+// waits only on pass p-1 items, all ticketed before any of pass p) and no
+// order can deadlock.  Order 2 maps t to (a t + b) mod ntiles with a coprime
+// to ntiles, a and b drawn from the seed and the pass.
+__device__ __forceinline__ int tile_of_ticket(const DebugModes& dm, int ntiles, int pass, int t) {
+    if (dm.order == 1) return ntiles - 1 - t;
+    if (dm.order == 2 && ntiles > 1) {
+        const uint32_t h = mix32(dm.seed * 0x9e3779b9u + uint32_t(pass) * 0x85ebca6bu + 1u);
+        int a = int(h % uint32_t(ntiles));
+        if (a == 0) a = 1;
+        while (gcd_int(a, ntiles) != 1) a = a + 1 < ntiles ? a + 1 : 1;
+        const int b = int(mix32(h ^ 0x68e31da4u) % uint32_t(ntiles));
+        return int((int64_t(a) * t + b) % ntiles);
+    }
+    return t;
+}
+
 // True when a graph-captured solve has converged before this launch (the
 // flag is written by an earlier kernel of the stream, so every wave reads
 // the same value and leaves together).
@@ -404,6 +463,9 @@ __device__ __forceinline__ void process_tile(const GridDesc<T>& a, int pass, int
 // Returns false when the wait timed out or another wave reported an error.
 template <typename T>
 __device__ bool wait_deps(const GridDesc<T>& a, const Queue& qu, int pass, int tile) {
+#ifdef RBGS_EMU_NO_WAIT  // the CPU emulation's planted mistake for the stamp check's own test
+    return true;
+#endif
     if (pass == 0) return true;
     const int lane = threadIdx.x;
     const int strip = tile / a.bands;
@@ -416,7 +478,7 @@ __device__ bool wait_deps(const GridDesc<T>& a, const Queue& qu, int pass, int t
         int v = mine ? __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : INT_MAX;
         if (__all(v >= pass)) break;
         if (polls >= qu.spin_limit) {
-            if (lane == 0) __hip_atomic_store(qu.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0) __hip_atomic_store(qu.error, kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
         if ((polls & 255) == 255) {
@@ -429,21 +491,49 @@ __device__ bool wait_deps(const GridDesc<T>& a, const Queue& qu, int pass, int t
     return true;
 }
 
-__device__ __forceinline__ uint32_t mix32(uint32_t h) {
-    h ^= h >> 16;
-    h *= 0x7feb352du;
-    h ^= h >> 15;
-    h *= 0x846ca68bu;
-    h ^= h >> 16;
-    return h;
+// Stamp check: every tile of the 3 x 3 neighbourhood has completed at least
+// `pass` passes (the dependency wait saw that) and at most pass + 1: a
+// neighbour at pass + 2 would have finished a pass that needs this item's
+// output, i.e. written the buffer this item reads.  Called after the wait and
+// again after the item's last write; false (and the error word set to
+// kErrOrder) on a violation.
+template <typename T>
+__device__ bool stamps_ok(const GridDesc<T>& a, const Queue& qu, int pass, int tile) {
+    const int lane = threadIdx.x;
+    const int strip = tile / a.bands;
+    const int band = tile - strip * a.bands;
+    const int ns = strip + lane / 3 - 1;
+    const int nb = band + lane % 3 - 1;
+    const bool mine = lane < 9 && ns >= 0 && ns < a.strips && nb >= 0 && nb < a.bands &&
+                      !(ns == strip && nb == band);
+    const int* flag = qu.progress + a.flag_base + (mine ? ns * a.bands + nb : 0);
+    const int v = mine ? __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : pass;
+    const bool bad = v < pass || v > pass + 1;
+    if (__any(bad)) {
+        if (lane == 0) __hip_atomic_store(qu.error, kErrOrder, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ unsigned long long realtime() {
+    return (unsigned long long)__builtin_amdgcn_s_memrealtime();
 }
 
 // Runs one work item after its dependencies are met and publishes it.
 // Returns false when the wave must leave (timeout or error elsewhere).
-template <typename T, int V, int L>
+// DBG: the verification modes of `dm` apply (ticket: the item's ticket
+// within the launch, for the trace).
+template <typename T, int V, int L, bool DBG = false>
 __device__ __forceinline__ bool run_item(const GridDesc<T>& g, const Queue& qu, int pass,
-                                         int tile) {
+                                         int tile, const DebugModes& dm = DebugModes(),
+                                         int ticket = 0) {
     if (!wait_deps(g, qu, pass, tile)) return false;
+    unsigned long long t0 = 0ull;
+    if constexpr (DBG) {
+        if (dm.trace) t0 = realtime();
+        if (dm.stamp_check && !stamps_ok(g, qu, pass, tile)) return false;
+    }
     if (qu.delay > 0) {
         // debug: a pseudo-random stall per work item (schedule stress)
         uint32_t loops = mix32(uint32_t(pass) * 0x9e3779b9u + uint32_t(g.flag_base + tile)) %
@@ -452,6 +542,19 @@ __device__ __forceinline__ bool run_item(const GridDesc<T>& g, const Queue& qu, 
     }
     process_tile<T, V, L>(g, pass + qu.buf_offset, tile, pass == qu.passes - 1);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if constexpr (DBG) {
+        if (dm.stamp_check && !stamps_ok(g, qu, pass, tile)) return false;
+        if (dm.trace && threadIdx.x == 0) {
+            const long long k = dm.trace_base + ticket;
+            if (k >= 0 && k < dm.trace_items) {
+                unsigned long long* rec = dm.trace + k * kTraceWords;
+                rec[0] = t0;
+                rec[1] = realtime();
+                rec[2] = ((unsigned long long)uint32_t(pass) << 32) | uint32_t(tile);
+                rec[3] = ((unsigned long long)blockIdx.x << 32) | uint32_t(ticket);
+            }
+        }
+    }
     if (threadIdx.x == 0 && g.flag_base + tile + 1 != qu.stall_tile)
         __hip_atomic_store(qu.progress + g.flag_base + tile, pass + 1, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);

@@ -107,12 +107,19 @@ struct BlockedParams {
     int stall_tile = 0; // debug: tile + 1 that never publishes its progress
     const int* stop = nullptr;  // converged flag of a graph-captured solve
     bool keep_error = false;    // the caller cleared the error word (graph rounds)
+    int order = 0;              // debug: tile order within a pass (0, 1, 2)
+    uint32_t seed = 0;          // debug: seed of order 2
+    int stamp_check = 0;        // debug: neighbour pass-count check per item
+    unsigned long long* trace = nullptr;  // debug: per-item trace records
+    int64_t trace_items = 0;
 };
 
 // Bytes of device state (flags, ticket counter, error word) for grid size n.
 size_t blocked_state_bytes(int n, int elem_bytes);
 // Checks fuse / tile options; writes a message to *why on failure.
 int validate_blocked_opts(int fuse, int tile_rows, int tile_cols, std::string* why);
+// Checks the debug tile order, stamp check and trace options.
+int validate_blocked_debug(const rbgs_sweep_opts* o, std::string* why);
 // Kernel the library picks for RBGS_KERNEL_AUTO.
 int auto_kernel(int n, size_t elem_bytes, int nsweeps);
 BlockedParams blocked_params(int n, size_t elem_bytes, const rbgs_sweep_opts* o);

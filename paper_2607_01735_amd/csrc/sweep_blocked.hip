@@ -60,35 +60,56 @@ __global__ __launch_bounds__(kLanes) void k_blocked(GridDesc<T> g, Queue qu) {
     }
 }
 
+// The same kernel with the verification modes (tile order, stamp check,
+// trace); launched only when a caller asks for one of them.
+template <typename T, int V, int L>
+__global__ __launch_bounds__(kLanes) void k_blocked_dbg(GridDesc<T> g, Queue qu, DebugModes dm) {
+    if (stopped(qu)) return;
+    const int total = qu.passes * g.ntiles;
+    for (;;) {
+        const int tk = next_ticket(qu);
+        if (tk >= total) break;
+        const int pass = tk / g.ntiles;
+        const int tile = tile_of_ticket(dm, g.ntiles, pass, tk - pass * g.ntiles);
+        if (!run_item<T, V, L, true>(g, qu, pass, tile, dm, tk)) break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 template <typename T, int V, int L>
-hipError_t launch_k(const GridDesc<T>& g, const Queue& qu, hipStream_t s) {
+hipError_t launch_k(const GridDesc<T>& g, const Queue& qu, const DebugModes* dm, hipStream_t s) {
     int per_cu = 0, cus = 0;
-    hipError_t e = persistent_occupancy(reinterpret_cast<const void*>(&k_blocked<T, V, L>), &per_cu, &cus);
+    const void* k = dm ? reinterpret_cast<const void*>(&k_blocked_dbg<T, V, L>)
+                       : reinterpret_cast<const void*>(&k_blocked<T, V, L>);
+    hipError_t e = persistent_occupancy(k, &per_cu, &cus);
     if (e != hipSuccess) return e;
     int64_t total = int64_t(qu.passes) * g.ntiles;
     int64_t grid = int64_t(cus) * per_cu;
     if (grid > total) grid = total;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL((k_blocked<T, V, L>), dim3(unsigned(grid)), dim3(kLanes), 0, s, g, qu);
+    if (dm)
+        hipLaunchKernelGGL((k_blocked_dbg<T, V, L>), dim3(unsigned(grid)), dim3(kLanes), 0, s, g, qu, *dm);
+    else
+        hipLaunchKernelGGL((k_blocked<T, V, L>), dim3(unsigned(grid)), dim3(kLanes), 0, s, g, qu);
     return hipGetLastError();
 }
 
 template <typename T, int V>
-hipError_t launch_by_fuse(int fuse, const GridDesc<T>& g, const Queue& qu, hipStream_t s) {
+hipError_t launch_by_fuse(int fuse, const GridDesc<T>& g, const Queue& qu, const DebugModes* dm,
+                          hipStream_t s) {
     switch (fuse) {
-        case 1: return launch_k<T, V, 2>(g, qu, s);
-        case 2: return launch_k<T, V, 4>(g, qu, s);
-        case 3: return launch_k<T, V, 6>(g, qu, s);
-        case 4: return launch_k<T, V, 8>(g, qu, s);
-        case 5: return launch_k<T, V, 10>(g, qu, s);
-        case 6: return launch_k<T, V, 12>(g, qu, s);
-        case 7: return launch_k<T, V, 14>(g, qu, s);
-        case 8: return launch_k<T, V, 16>(g, qu, s);
-        case 9: return launch_k<T, V, 18>(g, qu, s);
-        default: return launch_k<T, V, 20>(g, qu, s);
+        case 1: return launch_k<T, V, 2>(g, qu, dm, s);
+        case 2: return launch_k<T, V, 4>(g, qu, dm, s);
+        case 3: return launch_k<T, V, 6>(g, qu, dm, s);
+        case 4: return launch_k<T, V, 8>(g, qu, dm, s);
+        case 5: return launch_k<T, V, 10>(g, qu, dm, s);
+        case 6: return launch_k<T, V, 12>(g, qu, dm, s);
+        case 7: return launch_k<T, V, 14>(g, qu, dm, s);
+        case 8: return launch_k<T, V, 16>(g, qu, dm, s);
+        case 9: return launch_k<T, V, 18>(g, qu, dm, s);
+        default: return launch_k<T, V, 20>(g, qu, dm, s);
     }
 }
 
@@ -153,6 +174,27 @@ int validate_blocked_opts(int fuse, int tile_rows, int tile_cols, std::string* w
     return RBGS_OK;
 }
 
+int validate_blocked_debug(const rbgs_sweep_opts* o, std::string* why) {
+    if (!o) return RBGS_OK;
+    if (o->debug_tile_order < 0 || o->debug_tile_order > 2) {
+        *why = "debug_tile_order must be 0 (as numbered), 1 (reversed) or 2 (seeded permutation)";
+        return RBGS_EINVAL;
+    }
+    if (o->debug_stamp_check != 0 && o->debug_stamp_check != 1) {
+        *why = "debug_stamp_check must be 0 or 1";
+        return RBGS_EINVAL;
+    }
+    if (o->debug_trace_items < 0 || (o->debug_trace_items > 0) != (o->debug_trace != nullptr)) {
+        *why = "debug_trace and debug_trace_items > 0 go together (both unset: no trace)";
+        return RBGS_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(o->debug_trace) % 8 != 0) {
+        *why = "debug_trace must be 8-byte aligned";
+        return RBGS_EINVAL;
+    }
+    return RBGS_OK;
+}
+
 // Kernel choice measured on MI355X (time per sweep over thousands of
 // sweeps): the resident band kernel up to n = 384 (FP64) or 768 (FP32),
 // where it holds the grid in registers; above that the persistent blocked
@@ -177,6 +219,13 @@ BlockedParams blocked_params(int n, size_t elem_bytes, const rbgs_sweep_opts* o)
     bp.delay = o ? o->debug_delay : 0;
     bp.spin_limit = (o && o->debug_spin_limit > 0) ? o->debug_spin_limit : kDefaultSpinLimit;
     bp.stall_tile = o ? o->debug_stall_tile : 0;
+    if (o) {
+        bp.order = o->debug_tile_order;
+        bp.seed = o->debug_seed;
+        bp.stamp_check = o->debug_stamp_check;
+        bp.trace = reinterpret_cast<unsigned long long*>(o->debug_trace);
+        bp.trace_items = o->debug_trace_items;
+    }
     return bp;
 }
 
@@ -272,12 +321,21 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
             qu.stall_tile = bp.stall_tile;
             qu.buf_offset = 0;
             qu.stop = bp.stop;
+            DebugModes dm;
+            dm.order = bp.order;
+            dm.seed = bp.seed;
+            dm.stamp_check = bp.stamp_check;
+            // the trace holds the deeper passes' items, launch after launch
+            dm.trace = timed ? bp.trace : nullptr;
+            dm.trace_items = bp.trace_items;
+            dm.trace_base = int64_t(done) * geo.ntiles;
+            const bool debug = dm.order != 0 || dm.stamp_check != 0 || dm.trace != nullptr;
             if (timed && ev_begin && !started) {
                 r = hipEventRecord(ev_begin, s);
                 if (r != hipSuccess) return r;
                 started = true;
             }
-            r = launch_by_fuse<T, V>(fuse, g, qu, s);
+            r = launch_by_fuse<T, V>(fuse, g, qu, debug ? &dm : nullptr, s);
             if (r != hipSuccess) return r;
             *launches += 1;
             if (timed) {
@@ -324,6 +382,10 @@ int blocked_check_error(void* state, hipStream_t s, std::string* why) {
     if (e != hipSuccess) {
         *why = std::string("reading the persistent kernel's error word: ") + hipGetErrorString(e);
         return RBGS_EHIP;
+    }
+    if (err == kErrOrder) {
+        *why = "the stamp check saw a neighbour more than one pass ahead of a tile's work item";
+        return RBGS_EORDER;
     }
     if (err != 0) {
         *why = "a dependency wait in a persistent kernel timed out";

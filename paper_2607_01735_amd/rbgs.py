@@ -25,7 +25,8 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-OK, EINVAL, EHIP, ENOCONV, ETIMEOUT, ENONFINITE, EUNSUPPORTED, EWORKSPACE = 0, -1, -2, -3, -4, -5, -6, -8
+OK, EINVAL, EHIP, ENOCONV, ETIMEOUT, ENONFINITE, EUNSUPPORTED, EWORKSPACE, EORDER = \
+    0, -1, -2, -3, -4, -5, -6, -8, -9
 F64, F32 = 0, 1
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BLOCKED, KERNEL_RESIDENT = 0, 1, 2, 3
 PREC_F64, PREC_F32_IR, PREC_BF16RHS_IR = 0, 1, 2
@@ -55,7 +56,10 @@ class rbgs_sweep_opts(ctypes.Structure):
                 ("tile_rows", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
                 ("rows_per_block", ctypes.c_int32), ("debug_delay", ctypes.c_int32),
                 ("debug_spin_limit", ctypes.c_int32), ("debug_stall_tile", ctypes.c_int32),
-                ("timing", ctypes.POINTER(rbgs_timing)), ("lds_max_n", ctypes.c_int32)]
+                ("timing", ctypes.POINTER(rbgs_timing)), ("lds_max_n", ctypes.c_int32),
+                ("debug_tile_order", ctypes.c_int32), ("debug_seed", ctypes.c_uint32),
+                ("debug_stamp_check", ctypes.c_int32), ("debug_trace_items", ctypes.c_int32),
+                ("debug_trace", ctypes.c_void_p)]
 
 
 class rbgs_solve_opts(ctypes.Structure):
@@ -268,9 +272,18 @@ def _workspace(grid, code, device, precision=PREC_F64, workspace=None):
 
 
 def _sweep_opts(kernel="auto", fuse=0, tile_rows=0, tile_cols=0, rows_per_block=0,
-                debug_delay=0, debug_spin_limit=0, debug_stall_tile=0, timing=None, lds_max_n=0):
+                debug_delay=0, debug_spin_limit=0, debug_stall_tile=0, timing=None, lds_max_n=0,
+                debug_tile_order=0, debug_seed=0, debug_stamp_check=0, debug_trace=None):
+    """debug_trace: a device tensor of int64 (any shape; its element count / 4
+    records) that receives the persistent kernel's per-item trace."""
     o = rbgs_sweep_opts()
     o.lds_max_n = lds_max_n
+    o.debug_tile_order, o.debug_seed, o.debug_stamp_check = debug_tile_order, debug_seed, debug_stamp_check
+    if debug_trace is not None:
+        if debug_trace.dtype.itemsize != 8 or not debug_trace.is_contiguous():
+            raise ValueError("debug_trace must be a contiguous 8-byte integer tensor")
+        o.debug_trace = debug_trace.data_ptr()
+        o.debug_trace_items = debug_trace.numel() // 4
     o.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     o.fuse, o.tile_rows, o.tile_cols = fuse, tile_rows, tile_cols
     o.rows_per_block, o.debug_delay, o.debug_spin_limit = rows_per_block, debug_delay, debug_spin_limit

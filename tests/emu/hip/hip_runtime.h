@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 
 #if defined(__SANITIZE_THREAD__)
 #define EMU_TSAN 1
@@ -73,7 +74,10 @@ extern thread_local void* lane_fiber[kMaxThreads];
 extern thread_local void* host_fiber;
 #endif
 
+extern thread_local int workgroup;  // this host thread's workgroup index
+
 inline Dim thread_idx() { return Dim{unsigned(current), 0, 0}; }
+inline Dim block_idx() { return Dim{unsigned(workgroup), 0, 0}; }
 
 inline void jump_to_lane(int nx) {
 #ifdef EMU_TSAN
@@ -101,6 +105,11 @@ inline void switch_to_next() {
 }
 
 inline void wave_barrier() { switch_to_next(); }
+
+// The device's constant-rate counter, as a host steady clock (10 ns ticks).
+inline unsigned long long realtime_ticks() {
+    return (unsigned long long)(std::chrono::steady_clock::now().time_since_epoch().count() / 10);
+}
 
 inline int wave_base() { return current & ~(kLanes - 1); }
 
@@ -166,12 +175,14 @@ inline void fence(int order) {
 }  // namespace emu
 
 #define threadIdx (emu::thread_idx())
+#define blockIdx (emu::block_idx())
 #define __syncthreads() emu::block_barrier()
 #define __builtin_amdgcn_update_dpp(o, s, c, rm, bm, bc) emu::dpp(o, s, c, bc)
 #define __builtin_amdgcn_mov_dpp(s, c, rm, bm, bc) emu::dpp(0, s, c, bc)
 #define __builtin_amdgcn_readfirstlane(v) int(uint32_t(emu::from_lane(uint32_t(v), emu::wave_base())))
 #define __builtin_amdgcn_sched_barrier(m) ((void)0)
 #define __builtin_amdgcn_s_sleep(n) ((void)0)
+#define __builtin_amdgcn_s_memrealtime() emu::realtime_ticks()
 #define __builtin_amdgcn_fence(order, scope) emu::fence(order)
 #define __all(p) emu::vote(p, true)
 #define __any(p) emu::vote(p, false)

@@ -37,6 +37,7 @@ thread_local uint64_t lane_slot[kMaxThreads];
 thread_local int bar_arrived = 0, bar_generation = 0;
 int yield_every = 0;
 thread_local unsigned switches = 0;
+thread_local int workgroup = 0;
 #ifdef EMU_TSAN
 thread_local void* lane_fiber[kMaxThreads];
 thread_local void* host_fiber;
@@ -58,6 +59,9 @@ constexpr int kV = 16 / int(sizeof(T));
 
 static GridDesc<T> g_grid;
 static Queue g_queue;
+static DebugModes g_debug;  // tile order / stamp check (environment EMU_TILE_ORDER,
+                            // EMU_SEED, EMU_STAMP_CHECK), as the verification kernel runs them
+static bool g_debug_on = false;
 
 static void to_host() {
 #ifdef EMU_TSAN
@@ -81,7 +85,12 @@ static void lane_start(int lane) {
         const int tk = next_ticket(g_queue);
         if (tk >= total) break;
         const int pass = tk / g_grid.ntiles;
-        if (!run_item<T, kV, kL>(g_grid, g_queue, pass, tk - pass * g_grid.ntiles)) break;
+        if (g_debug_on) {
+            const int tile = tile_of_ticket(g_debug, g_grid.ntiles, pass, tk - pass * g_grid.ntiles);
+            if (!run_item<T, kV, kL, true>(g_grid, g_queue, pass, tile, g_debug, tk)) break;
+        } else if (!run_item<T, kV, kL>(g_grid, g_queue, pass, tk - pass * g_grid.ntiles)) {
+            break;
+        }
     }
     emu::lane_done[lane] = true;
     for (int k = 1; k < emu::nthreads; ++k) {
@@ -92,7 +101,8 @@ static void lane_start(int lane) {
 }
 
 // One workgroup on this host thread: park every lane, then run them.
-static void run_workgroup() {
+static void run_workgroup(int wg) {
+    emu::workgroup = wg;
     emu::nthreads = emu::kLanes;
     emu::current = 0;
     emu::bar_arrived = emu::bar_generation = 0;
@@ -200,18 +210,22 @@ int main(int argc, char** argv) {
     qu.stall_tile = 0;
     qu.buf_offset = 0;
     qu.stop = nullptr;
+    if (const char* e = getenv("EMU_TILE_ORDER")) g_debug.order = atoi(e);
+    if (const char* e = getenv("EMU_SEED")) g_debug.seed = uint32_t(strtoul(e, nullptr, 10));
+    if (const char* e = getenv("EMU_STAMP_CHECK")) g_debug.stamp_check = atoi(e);
+    g_debug_on = g_debug.order != 0 || g_debug.stamp_check != 0;
     const int workgroups = argc > 7 ? atoi(argv[7]) : 1;
     emu::yield_every = argc > 8 ? atoi(argv[8]) : 0;
     if (workgroups > 1) qu.spin_limit = 1 << 28;
     if (workgroups <= 1) {
-        run_workgroup();  // on the main thread
+        run_workgroup(0);  // on the main thread
     } else {
         std::vector<std::thread> threads;
-        for (int w = 0; w < workgroups; ++w) threads.emplace_back(run_workgroup);
+        for (int w = 0; w < workgroups; ++w) threads.emplace_back(run_workgroup, w);
         for (auto& t : threads) t.join();
     }
     if (*qu.error != 0) {
-        fprintf(stderr, "the pipeline raised its error word\n");
+        fprintf(stderr, "the pipeline raised its error word (%d)\n", *qu.error);
         return 4;
     }
     const int out = passes & 1;
@@ -223,8 +237,9 @@ int main(int argc, char** argv) {
     FILE* fout = fopen(argv[6], "wb");
     if (!fout || fwrite(u.data(), sizeof(T), u.size(), fout) != u.size()) return 2;
     fclose(fout);
-    printf("n=%d rows=%d passes=%d fuse=%d workgroups=%d tiles=%d halo_q=%d q_core=%d\n", n,
-           geo.rows, passes, kFuse, workgroups, geo.ntiles, geo.halo_q, geo.q_core);
+    printf("n=%d rows=%d passes=%d fuse=%d workgroups=%d tiles=%d halo_q=%d q_core=%d order=%d "
+           "stamp_check=%d\n", n, geo.rows, passes, kFuse, workgroups, geo.ntiles, geo.halo_q,
+           geo.q_core, g_debug.order, g_debug.stamp_check);
     for (int b = 0; b < 2; ++b) {
         free(red[b]);
         free(black[b]);

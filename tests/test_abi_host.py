@@ -78,7 +78,7 @@ def _sweep(lib, grid, dtype=0, nsweeps=1, opts=None, ws=None, ws_bytes=0):
 
 @pytest.mark.parametrize("bad", ["n0", "nbig", "ld", "h0", "hnan", "dtype", "nsweeps", "kernel",
                                  "negopt", "rows_small", "rows_big", "ws_null", "ws_align",
-                                 "ws_small"])
+                                 "ws_small", "order", "stamp", "trace_items", "trace_null"])
 def test_sweep_validation_before_device_work(lib, bad):
     g = _grid(lib, 31)
     dtype, nsweeps, opts = lib.F64, 1, lib.rbgs_sweep_opts()
@@ -112,6 +112,14 @@ def test_sweep_validation_before_device_work(lib, bad):
         ws, expect = ctypes.c_void_p((1 << 20) + 8), lib.EWORKSPACE
     elif bad == "ws_small":
         ws_bytes, expect = 100, lib.EWORKSPACE
+    elif bad == "order":
+        opts.kernel, opts.debug_tile_order = 2, 3
+    elif bad == "stamp":
+        opts.kernel, opts.debug_stamp_check = 2, 2
+    elif bad == "trace_items":  # a trace array without a record count
+        opts.kernel, opts.debug_trace = 2, 1 << 20
+    elif bad == "trace_null":   # a record count without an array
+        opts.kernel, opts.debug_trace_items = 2, 16
     rc = _sweep(lib, g, dtype, nsweeps, opts, ws, ws_bytes)
     assert rc == expect, lib.rbgs_last_error()
     assert lib.rbgs_last_error()
@@ -384,3 +392,21 @@ def test_fallback_option_validation(lib):
     o.fallback, o.inner_sweeps = 1, 10
     rc = lib._lib.rbgs_solve_batched(2, grids, ptrs, ptrs, ctypes.byref(o), None, None, 0, None)
     assert rc == lib.EUNSUPPORTED and "fallback" in lib.rbgs_batch_last_error()
+
+
+@pytest.mark.parametrize("field", ["debug_tile_order", "debug_stamp_check"])
+def test_batched_rejects_verification_modes(lib, field):
+    """The tile orders, stamp check and trace are single-grid modes."""
+    grids = (lib.rbgs_grid * 2)(_grid(lib, 15), _grid(lib, 31))
+    ptrs = (ctypes.c_void_p * 2)(1 << 20, 2 << 20)  # never dereferenced: checks come first
+    o = lib.rbgs_sweep_opts()
+    setattr(o, field, 1)
+    rc = lib._lib.rbgs_sweep_batched(2, grids, lib.F32, ptrs, ptrs, 10, ctypes.byref(o), None, 0, None)
+    assert rc == lib.EUNSUPPORTED
+    assert "single-grid" in lib.rbgs_batch_last_error()
+
+
+def test_status_strings_cover_every_code(lib):
+    for code in (lib.OK, lib.EINVAL, lib.EHIP, lib.ENOCONV, lib.ETIMEOUT, lib.ENONFINITE,
+                 lib.EUNSUPPORTED, lib.EWORKSPACE, lib.EORDER):
+        assert "unknown" not in lib.rbgs_strerror(code)

@@ -176,3 +176,86 @@ def test_blocked_pass_split(nsweeps, fuse, deep, passes):
     ut, ft = dev(u0), dev(f)
     t = rb.rbgs_sweep(ut, ft, nsweeps, h=W.spacing(n), kernel="blocked", fuse=fuse, timing=True)
     assert t["fuse"] == deep and t["passes"] == passes, t
+
+
+# The verification modes of the persistent kernel (Section 2.3's dependency
+# rule under other schedules): tiles of a pass taken reversed or in a seeded
+# pseudo-random order, with the stamp check on; the bits must not change.
+ORDER_CASES = [  # n, sweeps, fuse, tile_rows, order, seed
+    (63, 9, 1, 8, 1, 0), (255, 24, 4, 8, 1, 0), (255, 24, 4, 8, 2, 1), (700, 30, 5, 16, 2, 2),
+    (1023, 40, 7, 0, 1, 0), (1023, 40, 7, 24, 2, 3), (2049, 21, 7, 64, 2, 4), (7, 11, 5, 8, 2, 5),
+]
+
+
+@pytest.mark.parametrize("n,sweeps,fuse,rows,order,seed", ORDER_CASES)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_blocked_tile_orders_bitwise(oracle, n, sweeps, fuse, rows, order, seed, dtype):
+    say(f"blocked tile order={order} seed={seed} n={n} sweeps={sweeps} fuse={fuse} rows={rows} "
+        f"{dtype.__name__}")
+    h = W.spacing(n)
+    u0, f = start(n, n + 1, dtype=dtype)
+    ut, ft = dev(u0), dev(f)
+    rb.rbgs_sweep(ut, ft, sweeps, h=h, kernel="blocked", fuse=fuse, tile_rows=rows,
+                  debug_tile_order=order, debug_seed=seed, debug_stamp_check=1, debug_delay=3)
+    got = host(ut)
+    ref = u0.copy()
+    oracle.sweep(ref, f, h, sweeps)
+    assert np.array_equal(got.view(np.uint8), ref.view(np.uint8)), \
+        f"max |diff| {np.max(np.abs(got.astype(np.float64) - ref))}"
+
+
+def _neighbours(tile, strips, bands):
+    s, b = divmod(tile, bands)
+    return [ns * bands + nb for ns in (s - 1, s, s + 1) for nb in (b - 1, b, b + 1)
+            if 0 <= ns < strips and 0 <= nb < bands]
+
+
+@pytest.mark.parametrize("order", [0, 2])
+def test_blocked_trace_follows_dependency_rule(oracle, order):
+    """Per-item trace of one launch (real-time counter): every (pass, tile)
+    runs exactly once, and no pass-p item starts before every tile of its
+    3 x 3 neighbourhood has ended pass p - 1 (the rule of Algorithm 2 seen
+    in execution).  Items of different passes overlap in time: the passes
+    are not separated by a barrier.  The result stays bitwise."""
+    n, sweeps, fuse, rows = 1023, 70, 7, 32
+    say(f"blocked trace order={order} n={n} sweeps={sweeps} fuse={fuse} rows={rows}")
+    h = W.spacing(n)
+    u0, f = start(n, 11)
+    ut, ft = dev(u0), dev(f)
+    rows_eff = max(rows, 2 * fuse)
+    strips = (n + rows_eff - 1) // rows_eff
+    cap = 4 * 4096
+    trace = torch.zeros(cap * 4, dtype=torch.int64, device=DEV)
+    t = rb.rbgs_sweep(ut, ft, sweeps, h=h, kernel="blocked", fuse=fuse, tile_rows=rows,
+                      debug_tile_order=order, debug_seed=9, debug_trace=trace, timing=True)
+    got = host(ut)
+    ref = u0.copy()
+    oracle.sweep(ref, f, h, sweeps)
+    assert np.array_equal(got, ref)
+    rec = host(trace).reshape(cap, 4).view(np.uint64)
+    passes = t["passes"]
+    items = int(np.count_nonzero(rec[:, 0]))  # start times are never 0; unwritten records are
+    assert items % passes == 0
+    ntiles = items // passes
+    bands = ntiles // strips
+    assert bands * strips == ntiles, (ntiles, strips)
+    rec = rec[:items]
+    pas = (rec[:, 2] >> np.uint64(32)).astype(np.int64)
+    tile = (rec[:, 2] & np.uint64(0xffffffff)).astype(np.int64)
+    key = pas * ntiles + tile
+    assert np.array_equal(np.sort(key), np.arange(items)), "each (pass, tile) once"
+    start_t = np.zeros(items, dtype=np.int64)
+    end_t = np.zeros(items, dtype=np.int64)
+    start_t[key] = rec[:, 0].astype(np.int64)
+    end_t[key] = rec[:, 1].astype(np.int64)
+    assert np.all(end_t >= start_t)
+    for p in range(1, passes):
+        for tl in range(ntiles):
+            need = max(end_t[(p - 1) * ntiles + nb] for nb in _neighbours(tl, strips, bands))
+            assert start_t[p * ntiles + tl] >= need, (p, tl)
+    # overlap of consecutive passes: some pass-p item starts before the last
+    # pass-(p-1) item ends
+    overlapped = sum(int(start_t[p * ntiles:(p + 1) * ntiles].min() <
+                         end_t[(p - 1) * ntiles:p * ntiles].max()) for p in range(1, passes))
+    say(f"  {passes} passes x {ntiles} tiles; {overlapped} of {passes - 1} pass boundaries overlap")
+    assert overlapped >= 1
