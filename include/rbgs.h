@@ -185,7 +185,9 @@ typedef struct {
     double omega;          /* relaxation: 1.0 = Gauss-Seidel (the paper's method);
                               in (0, 2) = red-black SOR, u <- u + omega (g - u)
                               with g the Gauss-Seidel value (an extension: FP64,
-                              plain or resident kernel, no refinement; else
+                              plain, resident or blocked kernel (the blocked
+                              one reads and writes red every pass), no
+                              refinement, no sweep verification modes; else
                               RBGS_EUNSUPPORTED); 0.0 = the model problem's
                               optimum 2 / (1 + sin(pi h)) for this grid's h   */
     rbgs_sweep_opts sweep; /* kernel choice for the (inner) sweeps             */

@@ -268,8 +268,6 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
     const T* fb = static_cast<const T*>(w.f_black);
     int kernel = o ? o->kernel : RBGS_KERNEL_AUTO;
     if (kernel == RBGS_KERNEL_AUTO) kernel = auto_kernel(n, sizeof(T), nsweeps);
-    // SOR: the plain and resident kernels (an explicit BLOCKED was refused by the caller)
-    if (omega != 1.0 && kernel == RBGS_KERNEL_BLOCKED) kernel = RBGS_KERNEL_PLAIN;
     *launches = 0;
     if (kernel == RBGS_KERNEL_BLOCKED) {
         BlockedParams bp = blocked_params(n, sizeof(T), o);
@@ -281,7 +279,8 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
         int plaunches = 0, passes = 0, depth = 0;
         HIP_TRY(run_blocked<T>(bred, bblack, fr, fb, n, w.pitch, h2, nsweeps, bp, w.blocked,
                                w.blocked_bytes, s, launches, timed ? pt->ev[0] : nullptr,
-                               timed ? pt->ev[1] : nullptr, &plaunches, &passes, &depth),
+                               timed ? pt->ev[1] : nullptr, &plaunches, &passes, &depth,
+                               T(omega)),
                 "blocked sweep");
         if (timed && plaunches > 0) {
             pt->armed = true;
@@ -1002,8 +1001,9 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
             return fail(RBGS_EINVAL, "omega must be in (0, 2), or 0 for the optimum");
         if (dt != RBGS_F64 || ir)
             return fail(RBGS_EUNSUPPORTED, "SOR (omega != 1) runs in FP64 without refinement");
-        if (o->sweep.kernel == RBGS_KERNEL_BLOCKED)
-            return fail(RBGS_EUNSUPPORTED, "SOR (omega != 1) runs on the plain or resident kernel");
+        if (o->sweep.debug_tile_order != 0 || o->sweep.debug_stamp_check != 0 ||
+            o->sweep.debug_trace != nullptr)
+            return fail(RBGS_EUNSUPPORTED, "SOR (omega != 1) runs without the verification modes");
     }
     if (ir && dt != RBGS_F64)
         return fail(RBGS_EINVAL, "refinement modes need FP64 storage of u and f");

@@ -241,7 +241,7 @@ __device__ __forceinline__ int clamp_row(int x, int lo, int hi) {
     return x < lo ? lo : (x > hi ? hi : x);
 }
 
-template <typename T, int V, bool EDGE>
+template <typename T, int V, bool EDGE, bool SOR = false>
 __device__ __forceinline__ StepIn<T, V> load_in(const GridDesc<T>& a, const T* __restrict__ xr,
                                                 const T* __restrict__ xb, int x, int lo, int hi,
                                                 int64_t qv) {
@@ -250,8 +250,9 @@ __device__ __forceinline__ StepIn<T, V> load_in(const GridDesc<T>& a, const T* _
     const int64_t row = int64_t(clamp_row(x, lo, hi)) * P + qv;
     in.b = vload<T, V>(xb + row);
     // red input values matter only where they pass through unchanged
-    // (the ring); interior tiles never see the ring
-    if constexpr (EDGE)
+    // (the ring); interior tiles never see the ring.  SOR relaxes every
+    // red point from its old value, so it reads them everywhere.
+    if constexpr (EDGE || SOR)
         in.r = vload<T, V>(xr + row);
     else
         in.r = vzero<T, V>();
@@ -277,19 +278,23 @@ __device__ __forceinline__ void store_core(T* row, const Vec<T, V>& v, int64_t q
 }
 
 // One pipeline step at input row x; S = x mod 6 fixes, at compile time, the
-// ring-buffer slots (period 3) and the row parities (period 2).
-template <typename T, int V, int L, int S, bool EDGE>
+// ring-buffer slots (period 3) and the row parities (period 2).  SOR: each
+// level relaxes the Gauss-Seidel value g of a point from its previous
+// version u, u + omega (g - u), each operation rounded once (as the plain
+// kernel does).
+template <typename T, int V, int L, int S, bool EDGE, bool SOR = false>
 __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, FRing<T, V, L>& fr, const GridDesc<T>& a,
                                           const T* __restrict__ xr, const T* __restrict__ xb,
                                           T* __restrict__ yr, T* __restrict__ yb, int x, int xs,
                                           int xe, int r0, int r1, int64_t q0, int64_t qv,
-                                          int64_t qc0, int64_t qc1, bool in_core, bool store_red) {
+                                          int64_t qc0, int64_t qc1, bool in_core, bool store_red,
+                                          T omega = T(1)) {
     const int n = a.n;
     const int64_t P = a.pitch;
     constexpr int D = prefetch_steps<T, L>();
     const StepIn<T, V> cur = st.in[S];
     // prefetch: step x+D's rows into a slot no pending step holds
-    st.in[(S + D) % 6] = load_in<T, V, EDGE>(a, xr, xb, x + D, xs, xe, qv);
+    st.in[(S + D) % 6] = load_in<T, V, EDGE, SOR>(a, xr, xb, x + D, xs, xe, qv);
     // this step's right-hand-side rows join the ring (red row x-1, black
     // row x-2) as the products h^2 f that Eq. (1) subtracts: each is formed
     // once here, not once per fused level (the same product, so the same
@@ -357,6 +362,11 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, FRing<T, V, L>& fr,
                 s = s + left;
                 s = s - fl.v[e];
                 T nv = T(0.25) * s;
+                if constexpr (SOR) {
+                    const T d = nv - prev.v[e];
+                    const T w = omega * d;
+                    nv = prev.v[e] + w;
+                }
                 if constexpr (EDGE) {
                     const int64_t q = q0 + e;
                     out.v[e] = blend(row_in && q >= q_lo && q <= q_hi, nv, prev.v[e]);
@@ -371,7 +381,7 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, FRing<T, V, L>& fr,
             update(st.win[l - 1][pmod(S - l - 1, 3)]);
         carry = out;
     });
-    if constexpr (EDGE) st.red_in[S & 1] = rin;
+    if constexpr (EDGE || SOR) st.red_in[S & 1] = rin;
     const int y = x - L;
     if (y >= r0 && y <= r1) {
         // black (level L-1) and red (level L-2, still in level L-1's window)
@@ -389,9 +399,10 @@ __device__ __forceinline__ void pipe_step(Pipe<T, V, L>& st, FRing<T, V, L>& fr,
     }
 }
 
-template <typename T, int V, int L, bool EDGE>
+template <typename T, int V, int L, bool EDGE, bool SOR = false>
 __device__ __forceinline__ void run_tile(FRing<T, V, L>& fr, const GridDesc<T>& a, int pass, int r0,
-                                         int r1, int64_t qc0, int64_t qc1, bool store_red) {
+                                         int r1, int64_t qc0, int64_t qc1, bool store_red,
+                                         T omega = T(1)) {
     const int lane = threadIdx.x;
     const int64_t q0 = qc0 - a.halo_q + int64_t(lane) * V;
     // column actually loaded: q0 clamped into the row (lanes past the grid
@@ -414,20 +425,20 @@ __device__ __forceinline__ void run_tile(FRing<T, V, L>& fr, const GridDesc<T>& 
     const int x0 = xs - xs % 6;
 #pragma unroll
     for (int d = 0; d < prefetch_steps<T, L>(); ++d)
-        st.in[d] = load_in<T, V, EDGE>(a, xr, xb, x0 + d, xs, xe, qv);
+        st.in[d] = load_in<T, V, EDGE, SOR>(a, xr, xb, x0 + d, xs, xe, qv);
     for (int x = x0; x <= x_last; x += 6) {
-        pipe_step<T, V, L, 0, EDGE>(st, fr, a, xr, xb, yr, yb, x + 0, xs, xe, r0, r1, q0, qv, qc0, qc1,
-                                    in_core, store_red);
-        pipe_step<T, V, L, 1, EDGE>(st, fr, a, xr, xb, yr, yb, x + 1, xs, xe, r0, r1, q0, qv, qc0, qc1,
-                                    in_core, store_red);
-        pipe_step<T, V, L, 2, EDGE>(st, fr, a, xr, xb, yr, yb, x + 2, xs, xe, r0, r1, q0, qv, qc0, qc1,
-                                    in_core, store_red);
-        pipe_step<T, V, L, 3, EDGE>(st, fr, a, xr, xb, yr, yb, x + 3, xs, xe, r0, r1, q0, qv, qc0, qc1,
-                                    in_core, store_red);
-        pipe_step<T, V, L, 4, EDGE>(st, fr, a, xr, xb, yr, yb, x + 4, xs, xe, r0, r1, q0, qv, qc0, qc1,
-                                    in_core, store_red);
-        pipe_step<T, V, L, 5, EDGE>(st, fr, a, xr, xb, yr, yb, x + 5, xs, xe, r0, r1, q0, qv, qc0, qc1,
-                                    in_core, store_red);
+        pipe_step<T, V, L, 0, EDGE, SOR>(st, fr, a, xr, xb, yr, yb, x + 0, xs, xe, r0, r1, q0, qv,
+                                         qc0, qc1, in_core, store_red, omega);
+        pipe_step<T, V, L, 1, EDGE, SOR>(st, fr, a, xr, xb, yr, yb, x + 1, xs, xe, r0, r1, q0, qv,
+                                         qc0, qc1, in_core, store_red, omega);
+        pipe_step<T, V, L, 2, EDGE, SOR>(st, fr, a, xr, xb, yr, yb, x + 2, xs, xe, r0, r1, q0, qv,
+                                         qc0, qc1, in_core, store_red, omega);
+        pipe_step<T, V, L, 3, EDGE, SOR>(st, fr, a, xr, xb, yr, yb, x + 3, xs, xe, r0, r1, q0, qv,
+                                         qc0, qc1, in_core, store_red, omega);
+        pipe_step<T, V, L, 4, EDGE, SOR>(st, fr, a, xr, xb, yr, yb, x + 4, xs, xe, r0, r1, q0, qv,
+                                         qc0, qc1, in_core, store_red, omega);
+        pipe_step<T, V, L, 5, EDGE, SOR>(st, fr, a, xr, xb, yr, yb, x + 5, xs, xe, r0, r1, q0, qv,
+                                         qc0, qc1, in_core, store_red, omega);
     }
 }
 
@@ -438,9 +449,9 @@ __device__ __forceinline__ void run_tile(FRing<T, V, L>& fr, const GridDesc<T>& 
 // recomputes every interior red point from black), so the red colour is
 // written only by the launch's last pass, whose output leaves the kernel;
 // the Dirichlet ring, the only red input that is read, is never written.
-template <typename T, int V, int L>
+template <typename T, int V, int L, bool SOR = false>
 __device__ __forceinline__ void process_tile(const GridDesc<T>& a, int pass, int tile,
-                                             bool store_red) {
+                                             bool store_red, T omega = T(1)) {
     const int strip = tile / a.bands;
     const int band = tile - strip * a.bands;
     const int r0 = 1 + strip * a.rows;
@@ -454,9 +465,9 @@ __device__ __forceinline__ void process_tile(const GridDesc<T>& a, int pass, int
                           qc1 - qc0 == a.q_core;
     __shared__ FRing<T, V, L> fr;
     if (interior)
-        run_tile<T, V, L, false>(fr, a, pass, r0, r1, qc0, qc1, store_red);
+        run_tile<T, V, L, false, SOR>(fr, a, pass, r0, r1, qc0, qc1, store_red, omega);
     else
-        run_tile<T, V, L, true>(fr, a, pass, r0, r1, qc0, qc1, store_red);
+        run_tile<T, V, L, true, SOR>(fr, a, pass, r0, r1, qc0, qc1, store_red, omega);
 }
 
 // Waits until the 3 x 3 neighbourhood of `tile` has finished pass-1.
@@ -523,11 +534,12 @@ __device__ __forceinline__ unsigned long long realtime() {
 // Runs one work item after its dependencies are met and publishes it.
 // Returns false when the wave must leave (timeout or error elsewhere).
 // DBG: the verification modes of `dm` apply (ticket: the item's ticket
-// within the launch, for the trace).
-template <typename T, int V, int L, bool DBG = false>
+// within the launch, for the trace).  SOR: the over-relaxed sweep with
+// `omega`; it relaxes red from its old value, so every pass writes red.
+template <typename T, int V, int L, bool DBG = false, bool SOR = false>
 __device__ __forceinline__ bool run_item(const GridDesc<T>& g, const Queue& qu, int pass,
                                          int tile, const DebugModes& dm = DebugModes(),
-                                         int ticket = 0) {
+                                         int ticket = 0, T omega = T(1)) {
     if (!wait_deps(g, qu, pass, tile)) return false;
     unsigned long long t0 = 0ull;
     if constexpr (DBG) {
@@ -540,7 +552,7 @@ __device__ __forceinline__ bool run_item(const GridDesc<T>& g, const Queue& qu, 
                          uint32_t(qu.delay + 1);
         for (uint32_t i = 0; i < loops; ++i) __builtin_amdgcn_s_sleep(127);
     }
-    process_tile<T, V, L>(g, pass + qu.buf_offset, tile, pass == qu.passes - 1);
+    process_tile<T, V, L, SOR>(g, pass + qu.buf_offset, tile, SOR || pass == qu.passes - 1, omega);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if constexpr (DBG) {
         if (dm.stamp_check && !stamps_ok(g, qu, pass, tile)) return false;

@@ -130,13 +130,15 @@ BlockedParams blocked_params(int n, size_t elem_bytes, const rbgs_sweep_opts* o)
 // passes, then one of the shallower ones); a single sweep runs with the
 // plain kernel.  When ev_begin/ev_end are given they are recorded around the
 // launch(es) of the deeper passes; *persistent_launches, *passes_done and
-// *timed_fuse receive what those launches did.
+// *timed_fuse receive what those launches did.  omega != 1: red-black SOR
+// (FP64 only; not with the verification modes).
 template <typename T>
 hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_red,
                        const T* f_black, int n, int64_t pitch, T h2, int nsweeps,
                        const BlockedParams& bp, void* state, size_t state_bytes, hipStream_t s,
                        int* launches, hipEvent_t ev_begin, hipEvent_t ev_end,
-                       int* persistent_launches, int* passes_done, int* timed_fuse);
+                       int* persistent_launches, int* passes_done, int* timed_fuse,
+                       T omega = T(1));
 // Reads the persistent kernel's error word (synchronising the stream when
 // the kernel ran); returns RBGS_OK or RBGS_ETIMEOUT.
 int blocked_check_error(void* state, hipStream_t s, std::string* why);

@@ -39,6 +39,8 @@
 // Each point receives exactly the operations of Eq. (1) in the canonical
 // order, from exactly the neighbour values a sequential red-black sweep
 // would use, so the result equals the plain kernel bit for bit.
+#include <type_traits>
+
 #include "blocked_pipeline.h"
 #include "rbgs_blocked.h"
 #include "rbgs_internal.h"
@@ -60,6 +62,22 @@ __global__ __launch_bounds__(kLanes) void k_blocked(GridDesc<T> g, Queue qu) {
     }
 }
 
+// Red-black SOR (an extension: the paper's method is omega = 1) through the
+// same tiles: every level relaxes from the point's previous version, so red
+// is read and written by every pass (32 B per point and pass in FP64).
+template <typename T, int V, int L>
+__global__ __launch_bounds__(kLanes) void k_blocked_sor(GridDesc<T> g, Queue qu, T omega) {
+    if (stopped(qu)) return;
+    const int total = qu.passes * g.ntiles;
+    for (;;) {
+        const int tk = next_ticket(qu);
+        if (tk >= total) break;
+        const int pass = tk / g.ntiles;
+        if (!run_item<T, V, L, false, true>(g, qu, pass, tk - pass * g.ntiles, DebugModes(), 0, omega))
+            break;
+    }
+}
+
 // The same kernel with the verification modes (tile order, stamp check,
 // trace); launched only when a caller asks for one of them.
 template <typename T, int V, int L>
@@ -78,38 +96,51 @@ __global__ __launch_bounds__(kLanes) void k_blocked_dbg(GridDesc<T> g, Queue qu,
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+// omega != 1 launches the SOR kernel (FP64 only: the callers refuse FP32
+// SOR), dm the verification kernel; else the production kernel.
 template <typename T, int V, int L>
-hipError_t launch_k(const GridDesc<T>& g, const Queue& qu, const DebugModes* dm, hipStream_t s) {
+hipError_t launch_k(const GridDesc<T>& g, const Queue& qu, const DebugModes* dm, T omega,
+                    hipStream_t s) {
+    constexpr bool kSor = std::is_same<T, double>::value;
+    const bool sor = omega != T(1);
+    if (sor && (!kSor || dm)) return hipErrorInvalidValue;
     int per_cu = 0, cus = 0;
     const void* k = dm ? reinterpret_cast<const void*>(&k_blocked_dbg<T, V, L>)
                        : reinterpret_cast<const void*>(&k_blocked<T, V, L>);
+    if constexpr (kSor)
+        if (sor) k = reinterpret_cast<const void*>(&k_blocked_sor<T, V, L>);
     hipError_t e = persistent_occupancy(k, &per_cu, &cus);
     if (e != hipSuccess) return e;
     int64_t total = int64_t(qu.passes) * g.ntiles;
     int64_t grid = int64_t(cus) * per_cu;
     if (grid > total) grid = total;
     if (grid < 1) grid = 1;
-    if (dm)
+    if (dm) {
         hipLaunchKernelGGL((k_blocked_dbg<T, V, L>), dim3(unsigned(grid)), dim3(kLanes), 0, s, g, qu, *dm);
-    else
+    } else if (sor) {
+        if constexpr (kSor)
+            hipLaunchKernelGGL((k_blocked_sor<T, V, L>), dim3(unsigned(grid)), dim3(kLanes), 0, s, g,
+                               qu, omega);
+    } else {
         hipLaunchKernelGGL((k_blocked<T, V, L>), dim3(unsigned(grid)), dim3(kLanes), 0, s, g, qu);
+    }
     return hipGetLastError();
 }
 
 template <typename T, int V>
 hipError_t launch_by_fuse(int fuse, const GridDesc<T>& g, const Queue& qu, const DebugModes* dm,
-                          hipStream_t s) {
+                          T omega, hipStream_t s) {
     switch (fuse) {
-        case 1: return launch_k<T, V, 2>(g, qu, dm, s);
-        case 2: return launch_k<T, V, 4>(g, qu, dm, s);
-        case 3: return launch_k<T, V, 6>(g, qu, dm, s);
-        case 4: return launch_k<T, V, 8>(g, qu, dm, s);
-        case 5: return launch_k<T, V, 10>(g, qu, dm, s);
-        case 6: return launch_k<T, V, 12>(g, qu, dm, s);
-        case 7: return launch_k<T, V, 14>(g, qu, dm, s);
-        case 8: return launch_k<T, V, 16>(g, qu, dm, s);
-        case 9: return launch_k<T, V, 18>(g, qu, dm, s);
-        default: return launch_k<T, V, 20>(g, qu, dm, s);
+        case 1: return launch_k<T, V, 2>(g, qu, dm, omega, s);
+        case 2: return launch_k<T, V, 4>(g, qu, dm, omega, s);
+        case 3: return launch_k<T, V, 6>(g, qu, dm, omega, s);
+        case 4: return launch_k<T, V, 8>(g, qu, dm, omega, s);
+        case 5: return launch_k<T, V, 10>(g, qu, dm, omega, s);
+        case 6: return launch_k<T, V, 12>(g, qu, dm, omega, s);
+        case 7: return launch_k<T, V, 14>(g, qu, dm, omega, s);
+        case 8: return launch_k<T, V, 16>(g, qu, dm, omega, s);
+        case 9: return launch_k<T, V, 18>(g, qu, dm, omega, s);
+        default: return launch_k<T, V, 20>(g, qu, dm, omega, s);
     }
 }
 
@@ -234,7 +265,7 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
                        const T* f_black, int n, int64_t pitch, T h2, int nsweeps,
                        const BlockedParams& bp, void* state, size_t state_bytes, hipStream_t s,
                        int* launches, hipEvent_t ev_begin, hipEvent_t ev_end,
-                       int* persistent_launches, int* passes_done, int* timed_fuse) {
+                       int* persistent_launches, int* passes_done, int* timed_fuse, T omega) {
     constexpr int V = 16 / int(sizeof(T));
     *persistent_launches = 0;
     *passes_done = 0;
@@ -251,10 +282,10 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
     if (nsweeps < 2) {  // a single sweep does not pay for a persistent launch
         for (int it = 0; it < nsweeps; ++it) {
             e = launch_half_sweep<T>(buf_red[0], buf_black[0], f_red, n, pitch, h2, 0, 0, s,
-                                     bp.stop);
+                                     bp.stop, omega);
             if (e != hipSuccess) return e;
             e = launch_half_sweep<T>(buf_black[0], buf_red[0], f_black, n, pitch, h2, 1, 0, s,
-                                     bp.stop);
+                                     bp.stop, omega);
             if (e != hipSuccess) return e;
             *launches += 2;
         }
@@ -335,7 +366,7 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
                 if (r != hipSuccess) return r;
                 started = true;
             }
-            r = launch_by_fuse<T, V>(fuse, g, qu, debug ? &dm : nullptr, s);
+            r = launch_by_fuse<T, V>(fuse, g, qu, debug ? &dm : nullptr, omega, s);
             if (r != hipSuccess) return r;
             *launches += 1;
             if (timed) {
@@ -368,11 +399,11 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
 template hipError_t run_blocked<double>(double* const[2], double* const[2], const double*,
                                         const double*, int, int64_t, double, int,
                                         const BlockedParams&, void*, size_t, hipStream_t, int*,
-                                        hipEvent_t, hipEvent_t, int*, int*, int*);
+                                        hipEvent_t, hipEvent_t, int*, int*, int*, double);
 template hipError_t run_blocked<float>(float* const[2], float* const[2], const float*,
                                        const float*, int, int64_t, float, int,
                                        const BlockedParams&, void*, size_t, hipStream_t, int*,
-                                       hipEvent_t, hipEvent_t, int*, int*, int*);
+                                       hipEvent_t, hipEvent_t, int*, int*, int*, float);
 
 int blocked_check_error(void* state, hipStream_t s, std::string* why) {
     int err = 0;

@@ -62,6 +62,7 @@ static Queue g_queue;
 static DebugModes g_debug;  // tile order / stamp check (environment EMU_TILE_ORDER,
                             // EMU_SEED, EMU_STAMP_CHECK), as the verification kernel runs them
 static bool g_debug_on = false;
+static T g_omega = T(1);  // != 1: the SOR pipeline (environment EMU_OMEGA)
 
 static void to_host() {
 #ifdef EMU_TSAN
@@ -85,7 +86,11 @@ static void lane_start(int lane) {
         const int tk = next_ticket(g_queue);
         if (tk >= total) break;
         const int pass = tk / g_grid.ntiles;
-        if (g_debug_on) {
+        if (g_omega != T(1)) {
+            if (!run_item<T, kV, kL, false, true>(g_grid, g_queue, pass, tk - pass * g_grid.ntiles,
+                                                  DebugModes(), 0, g_omega))
+                break;
+        } else if (g_debug_on) {
             const int tile = tile_of_ticket(g_debug, g_grid.ntiles, pass, tk - pass * g_grid.ntiles);
             if (!run_item<T, kV, kL, true>(g_grid, g_queue, pass, tile, g_debug, tk)) break;
         } else if (!run_item<T, kV, kL>(g_grid, g_queue, pass, tk - pass * g_grid.ntiles)) {
@@ -214,6 +219,7 @@ int main(int argc, char** argv) {
     if (const char* e = getenv("EMU_SEED")) g_debug.seed = uint32_t(strtoul(e, nullptr, 10));
     if (const char* e = getenv("EMU_STAMP_CHECK")) g_debug.stamp_check = atoi(e);
     g_debug_on = g_debug.order != 0 || g_debug.stamp_check != 0;
+    if (const char* e = getenv("EMU_OMEGA")) g_omega = T(atof(e));
     const int workgroups = argc > 7 ? atoi(argv[7]) : 1;
     emu::yield_every = argc > 8 ? atoi(argv[8]) : 0;
     if (workgroups > 1) qu.spin_limit = 1 << 28;

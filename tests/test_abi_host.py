@@ -133,8 +133,9 @@ def test_solve_validation_before_device_work(lib, bad):
     o.max_sweeps, o.rel_tol, o.check_every, o.omega = 10, 1e-8, 5, 1.0
     dtype = lib.F64
     expect = lib.EINVAL
-    if bad == "omega":  # SOR runs on the plain kernel only
+    if bad == "omega":  # SOR runs without the persistent kernel's verification modes
         o.omega, o.sweep.kernel, expect = 1.5, lib._KERNELS["blocked"], lib.EUNSUPPORTED
+        o.sweep.debug_tile_order = 1
     elif bad == "omega_range":
         o.omega = 2.5
     elif bad == "sor_f32":

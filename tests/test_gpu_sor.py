@@ -104,3 +104,41 @@ def test_sor_resident_solve_matches_plain():
     ib = rb.rbgs_solve(b, f, 20000, 1e-8, check_every=10, h=h, omega=0.0, kernel="plain")
     assert ia["status"] == ib["status"] == 0 and ia["sweeps"] == ib["sweeps"]
     assert torch.equal(a, b)
+
+
+BLOCKED_CASES = [  # n, sweeps, fuse, tile_rows (0 = default)
+    (1, 5, 4, 0), (7, 11, 5, 8), (63, 9, 1, 8), (100, 16, 4, 16), (255, 24, 4, 0),
+    (511, 43, 6, 14), (1023, 40, 7, 0), (1500, 21, 7, 32), (2049, 16, 4, 128), (300, 13, 4, 8),
+]
+
+
+@pytest.mark.parametrize("n,sweeps,fuse,rows", BLOCKED_CASES)
+@pytest.mark.parametrize("omega", [0.7, 1.6])
+def test_sor_blocked_kernel_bitwise(oracle, n, sweeps, fuse, rows, omega):
+    """SOR on the persistent blocked kernel (levels relax from each point's
+    previous version; red read and written every pass): the oracle's SOR
+    sweeps bit for bit, ragged tiles and passes of two depths included."""
+    say(f"SOR blocked n={n} sweeps={sweeps} fuse={fuse} rows={rows} omega={omega}")
+    h = W.spacing(n)
+    ld = n + 2 + (n % 5)
+    u0, f = start(n, 3 * n + 1, ld=ld)
+    ut = dev(u0)
+    info = rb.rbgs_solve(ut, dev(f), sweeps, 0.0, check_every=sweeps, h=h, omega=omega,
+                         kernel="blocked", fuse=fuse, tile_rows=rows)
+    assert info["sweeps"] == sweeps
+    ref = oracle.sor_sweep(u0.copy(), f, h, omega, sweeps)
+    got = ut.cpu().numpy()
+    assert np.array_equal(got.view(np.uint8), ref.view(np.uint8)), \
+        f"max |diff| {np.max(np.abs(got - ref))}"
+
+
+def test_sor_blocked_solve_matches_plain():
+    n = 1023
+    say("SOR blocked vs plain solve")
+    h = W.spacing(n)
+    f = dev(W.sine_rhs(n))
+    a, b = dev(W.zeros(n)), dev(W.zeros(n))
+    ia = rb.rbgs_solve(a, f, 40000, 1e-8, check_every=50, h=h, omega=0.0, kernel="blocked")
+    ib = rb.rbgs_solve(b, f, 40000, 1e-8, check_every=50, h=h, omega=0.0, kernel="plain")
+    assert ia["status"] == ib["status"] == 0 and ia["sweeps"] == ib["sweeps"]
+    assert torch.equal(a, b)

@@ -158,3 +158,27 @@ def test_stamp_check_catches_a_missing_wait(tmp_path):
                          env=_env(2), timeout=600)
     assert res.returncode == 4, (res.stdout + res.stderr)[-2000:]
     assert "error word (2)" in res.stderr
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("n,omega", [(150, 1.6), (7, 0.7)])
+def test_sor_pipeline_matches_oracle(oracle, tmp_path, n, omega):
+    """The SOR form of the pipeline (levels relax from each point's previous
+    version; red read and written by every pass, the second buffer's
+    interior poisoned with NaN) on four workgroups under ThreadSanitizer:
+    the oracle's SOR sweeps bit for bit."""
+    fuse, rows, passes = 3, 8, 3
+    exe = _build(tmp_path, "float64", fuse, "thread", 0)
+    u0, f = _inputs(n, np.float64)
+    fin, fout = tmp_path / "in.bin", tmp_path / "out.bin"
+    with open(fin, "wb") as fh:
+        fh.write(np.ascontiguousarray(u0).tobytes())
+        fh.write(np.ascontiguousarray(f).tobytes())
+    h = W.spacing(n)
+    res = subprocess.run([str(exe), str(n), str(rows), str(passes), repr(h), str(fin), str(fout), "4"],
+                         capture_output=True, text=True, env=dict(_env(0), EMU_OMEGA=repr(omega)),
+                         timeout=900)
+    assert res.returncode == 0, (res.stdout + res.stderr)[-4000:]
+    got = np.fromfile(fout, dtype=np.float64).reshape(n + 2, n + 2)
+    ref = oracle.sor_sweep(u0.copy(), f, h, omega, passes * fuse)
+    assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
