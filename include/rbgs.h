@@ -421,6 +421,18 @@ int rbgs_unet_get_params(rbgs_unet *net, float *params, size_t count,
                          void *stream);
 int rbgs_unet_get_grads(rbgs_unet *net, float *grads, size_t count,
                         void *stream);
+/* Adam's state, to save and resume a training run (the optimiser of Kingma
+ * and Ba that the learned part is trained with; not in the paper): the
+ * first and second moment estimates m and v, count = rbgs_unet_param_count()
+ * FP32 values each in the parameter order (HOST arrays), and *step / step,
+ * the number of Adam steps taken (its bias corrections use it).  get copies
+ * them out; set restores them, after rbgs_unet_set_params (which restarts
+ * Adam), so that the next update continues the saved run bit for bit.
+ * RBGS_EINVAL on a NULL array, a wrong count or step < 0.  Synchronise. */
+int rbgs_unet_get_adam(rbgs_unet *net, float *m, float *v, size_t count,
+                       int32_t *step, void *stream);
+int rbgs_unet_set_adam(rbgs_unet *net, const float *m, const float *v,
+                       size_t count, int32_t step, void *stream);
 /* u0 (device) interior <- network guess for f (device); u0's ring is left
  * untouched.  batch <= the batch given at creation.  Asynchronous. */
 int rbgs_unet_forward(rbgs_unet *net, int32_t batch, const double *f,

@@ -1193,6 +1193,32 @@ int rbgs_unet_get_grads(rbgs_unet* u, float* host, size_t count, void* stream) {
     return copy_out(host, u->net.grad, count, static_cast<hipStream_t>(stream));
 }
 
+int rbgs_unet_get_adam(rbgs_unet* u, float* m, float* v, size_t count, int32_t* step,
+                       void* stream) {
+    if (!u || !m || !v || !step || count != u->net.nparam)
+        return nn::nnfail(RBGS_EINVAL, "bad Adam state arrays");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = copy_out(m, u->net.m, count, s);
+    if (rc) return rc;
+    if ((rc = copy_out(v, u->net.v, count, s))) return rc;
+    *step = int32_t(u->net.adam_t);
+    return RBGS_OK;
+}
+
+int rbgs_unet_set_adam(rbgs_unet* u, const float* m, const float* v, size_t count, int32_t step,
+                       void* stream) {
+    if (!u || !m || !v || count != u->net.nparam || step < 0)
+        return nn::nnfail(RBGS_EINVAL, "bad Adam state arrays or step");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    nn::Net& net = u->net;
+    int rc = nn::nn_hip(hipMemcpyAsync(net.m, m, count * 4, hipMemcpyHostToDevice, s), "upload");
+    if (rc) return rc;
+    if ((rc = nn::nn_hip(hipMemcpyAsync(net.v, v, count * 4, hipMemcpyHostToDevice, s), "upload")))
+        return rc;
+    net.adam_t = step;
+    return nn::nn_hip(hipStreamSynchronize(s), "synchronise");
+}
+
 int rbgs_unet_forward(rbgs_unet* u, int32_t batch, const double* f, int64_t ld, double* u0,
                       void* stream) {
     if (!u || !f || !u0) return nn::nnfail(RBGS_EINVAL, "NULL argument");

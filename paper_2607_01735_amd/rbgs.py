@@ -178,7 +178,8 @@ EXPORTED = ("rbgs_workspace_size", "rbgs_sweep", "rbgs_residual", "rbgs_residual
             "rbgs_batch_plan_check", "rbgs_batch_plan_destroy", "rbgs_autotune_batched",
             "rbgs_batch_last_error", "rbgs_unet_param_count", "rbgs_unet_workspace_size",
             "rbgs_unet_create", "rbgs_unet_destroy", "rbgs_unet_set_params",
-            "rbgs_unet_get_params", "rbgs_unet_get_grads", "rbgs_unet_forward",
+            "rbgs_unet_get_params", "rbgs_unet_get_grads", "rbgs_unet_get_adam",
+            "rbgs_unet_set_adam", "rbgs_unet_forward",
             "rbgs_unet_train_step", "rbgs_solve_learned", "rbgs_unet_last_error",
             "rbgs_restrict", "rbgs_prolong", "rbgs_batch_solve_workspace_size",
             "rbgs_solve_batched", "rbgs_mg_workspace_size", "rbgs_mg_solve",
@@ -765,6 +766,10 @@ _lib.rbgs_unet_destroy.restype = ctypes.c_int
 for _name in ("rbgs_unet_set_params", "rbgs_unet_get_params", "rbgs_unet_get_grads"):
     getattr(_lib, _name).argtypes = [_vp, _vp, ctypes.c_size_t, _vp]
     getattr(_lib, _name).restype = ctypes.c_int
+_lib.rbgs_unet_get_adam.argtypes = [_vp, _vp, _vp, ctypes.c_size_t, _P(ctypes.c_int32), _vp]
+_lib.rbgs_unet_get_adam.restype = ctypes.c_int
+_lib.rbgs_unet_set_adam.argtypes = [_vp, _vp, _vp, ctypes.c_size_t, ctypes.c_int32, _vp]
+_lib.rbgs_unet_set_adam.restype = ctypes.c_int
 _lib.rbgs_unet_forward.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp]
 _lib.rbgs_unet_forward.restype = ctypes.c_int
 _lib.rbgs_unet_train_step.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int64, ctypes.c_float,
@@ -830,6 +835,25 @@ class UNet:
 
     def get_grads(self, stream=None):
         return self._get(_lib.rbgs_unet_get_grads, stream)
+
+    def get_adam(self, stream=None):
+        """Adam's state for resuming training: (m, v, step)."""
+        import numpy as np
+        m, v = np.empty(self.count, np.float32), np.empty(self.count, np.float32)
+        step = ctypes.c_int32()
+        _ncheck(_lib.rbgs_unet_get_adam(self._h, _vp(m.ctypes.data), _vp(v.ctypes.data), self.count,
+                                        ctypes.byref(step), self._stream(stream)))
+        return m, v, step.value
+
+    def set_adam(self, m, v, step, stream=None):
+        """Restore Adam's state (after set_params, which restarts it)."""
+        import numpy as np
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        if m.size != self.count or v.size != self.count:
+            raise ValueError(f"expected {self.count} values in m and in v")
+        _ncheck(_lib.rbgs_unet_set_adam(self._h, _vp(m.ctypes.data), _vp(v.ctypes.data), self.count,
+                                        int(step), self._stream(stream)))
 
     def _check_batch(self, f):
         if f.dim() != 3 or f.shape[1] != self.n + 2 or f.stride(2) != 1 or f.dtype.itemsize != 8:

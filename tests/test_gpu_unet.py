@@ -210,6 +210,43 @@ def test_adam_matches_reference_over_steps():
         assert not np.array_equal(after, before)
 
 
+def test_adam_state_resumes_training_bit_for_bit():
+    """Save parameters and Adam's state after three steps, restore both into a
+    fresh network, and take two more steps on each: the same bits.  Without
+    the Adam state (parameters only, a restarted Adam) the run differs."""
+    say("unet adam save / resume")
+    p = make_params(seed=15)
+    vec = flatten(p).astype(np.float32)
+    f = torch.from_numpy(batch_fields([21, 22])).to(DEV)
+    u = np.zeros(tuple(f.shape))
+    for b in range(2):
+        u[b, 1:N + 1, 1:N + 1] = -W.grf_rhs(N, seed=21 + b)[0][1:N + 1, 1:N + 1] * 0.02
+    ut = torch.from_numpy(u).to(DEV)
+    lr = 1e-3
+    a = rb.UNet(N, 2)
+    a.set_params(vec)
+    for _ in range(3):
+        a.train_step(f, ut, lr, update=True)
+    params = a.get_params()
+    m, v, step = a.get_adam()
+    assert step == 3 and np.any(m != 0) and np.all(v >= 0)
+    b, c = rb.UNet(N, 2), rb.UNet(N, 2)
+    b.set_params(params)
+    b.set_adam(m, v, step)
+    c.set_params(params)  # restarts Adam
+    m0, v0, s0 = c.get_adam()
+    assert s0 == 0 and not np.any(m0) and not np.any(v0)
+    for net in (a, b, c):
+        for _ in range(2):
+            net.train_step(f, ut, lr, update=True)
+    pa, pb, pc = a.get_params(), b.get_params(), c.get_params()
+    assert np.array_equal(pa.view(np.uint32), pb.view(np.uint32))
+    assert a.get_adam()[2] == b.get_adam()[2] == 5
+    assert not np.array_equal(pa, pc)
+    with pytest.raises(rb.RbgsError):
+        b.set_adam(m, v, -1)
+
+
 def test_adam_step_and_training_decreases_loss():
     say("unet adam + short training")
     p = make_params(seed=3)
