@@ -421,6 +421,48 @@ def unet_throughput(torch, rb, n=511, batch=8, steps=10):
     return out
 
 
+def pass_overlap(torch, rb, W, n=8191, sweeps=200):
+    """The GPU form of the paper's red/black overlap traces (Section 4): the
+    headline workload once more through the verification kernel with the
+    per-item trace on (not timed with the headline; the trace adds a store
+    and two counter reads per item).  From the records (device real-time
+    counter, 10 ns): the wall time of each pass (first start to last end),
+    how far consecutive passes overlap, and how many passes have items in
+    flight at once, sampled over the launch."""
+    import numpy as np
+    h = W.spacing(n)
+    f = torch.from_numpy(W.uniform_rhs(n, seed=0)).to("cuda")
+    u = torch.zeros_like(f)
+    cap = 1 << 16
+    trace = torch.zeros(cap * 4, dtype=torch.int64, device="cuda")
+    t = rb.rbgs_sweep(u, f, sweeps, h=h, kernel="blocked", debug_trace=trace, timing=True)
+    rec = trace.view(cap, 4).cpu().numpy().view(np.uint64)
+    items = int(np.count_nonzero(rec[:, 0]))
+    passes = int(t["passes"])
+    if items == 0 or items % passes:
+        return {"error": f"{items} trace records for {passes} passes"}
+    ntiles = items // passes
+    rec = rec[:items].astype(np.int64)
+    pas = rec[:, 2] >> 32
+    t0 = rec[:, 0].min()
+    start, end = rec[:, 0] - t0, rec[:, 1] - t0
+    first = np.array([start[pas == p].min() for p in range(passes)])
+    last = np.array([end[pas == p].max() for p in range(passes)])
+    span = last - first
+    overlap = [(last[p - 1] - first[p]) / span[p] for p in range(1, passes)]
+    grid = np.linspace(0, end.max(), 400, endpoint=False)
+    in_flight = [len(np.unique(pas[(start <= x) & (end > x)])) for x in grid]
+    ticks_us = 0.01
+    return {"workload": f"{n}x{n} FP64, {sweeps} sweeps, fuse {t['fuse']}: the deeper "
+                        f"passes' launch, {passes} passes x {ntiles} tiles",
+            "launch_us": round(float(end.max()) * ticks_us, 1),
+            "pass_wall_us_median": round(float(np.median(span)) * ticks_us, 1),
+            "item_us_median": round(float(np.median(end - start)) * ticks_us, 1),
+            "consecutive_pass_overlap_median": round(float(np.median(overlap)), 3),
+            "passes_in_flight_mean": round(float(np.mean(in_flight)), 2),
+            "passes_in_flight_max": int(np.max(in_flight))}
+
+
 def rb3_throughput(torch, rb, n=767, sweeps=40):
     """Red-black Gauss-Seidel in 3D (the higher-dimension extension): n^3
     FP64 with f ~ U[-1, 1) drawn on the device (seeded), time per sweep from
@@ -767,6 +809,8 @@ def main():
                     help="run only the 3D red-black section, print its JSON and exit")
     ap.add_argument("--mc9-only", action="store_true",
                     help="run only the 9-point four-colour section, print its JSON and exit")
+    ap.add_argument("--overlap-only", action="store_true",
+                    help="only the traced pass overlap of the 8191^2 workload")
     ap.add_argument("--unet-only", action="store_true",
                     help="run only the U-Net training/inference timing, print its JSON and exit")
     ap.add_argument("--mg-only", action="store_true",
@@ -794,6 +838,9 @@ def main():
     if args.mc9_only:
         mc9 = multicolour9_throughput(torch, rb, W, with_solve=not args.no_time_to_tol)
         print(json.dumps({"multicolour9": mc9}), flush=True)
+        return
+    if args.overlap_only:
+        print(json.dumps({"pass_overlap_8191": pass_overlap(torch, rb, W)}), flush=True)
         return
     if args.unet_only:
         print(json.dumps({"unet": unet_throughput(torch, rb)}), flush=True)
@@ -908,6 +955,7 @@ def main():
     batched_tol = None if args.no_extras else batched_to_tolerance(torch, rb, W)
     learned_511 = None if args.no_extras else learned_guess(torch, rb)
     unet = None if args.no_extras else unet_throughput(torch, rb)
+    overlap = None if args.no_extras else pass_overlap(torch, rb, W)
     probe = None if args.no_probe else stream_probe(torch, rb)
     if probe:
         log(f"STREAM probe: {probe}")
@@ -941,6 +989,7 @@ def main():
         "batched_to_1e-8": batched_tol,
         "learned_guess_511": learned_511,
         "unet_511": unet,
+        "pass_overlap_8191": overlap,
         "stream_probe": probe,
         "cpu_baseline": base,
     }
