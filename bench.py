@@ -655,6 +655,30 @@ def refinement_throughput(torch, rb, W, n=16383, inner=100, outer=2):
         out[name]["rel_minus_closed_form"] = float(np.float64(out[name]["rel_residual"]) - expect)
     for name in ("f32_ir", "bf16rhs_ir"):
         out[name]["inner_glups_vs_f64"] = round(out[name]["inner_glups"] / out["f64"]["inner_glups"], 3)
+    # PROJECTION, not a run: full sweeps to reach rel 1e-8 and 1e-10 from
+    # u0 = 0 by the same closed form (the smallest m with rel(m) <= tol; the
+    # slowest mode decays by cos^2(k pi h)-like factors, so this is ~1e8
+    # sweeps at this size), times each form's measured time per sweep
+    def sweeps_to(tol):
+        lo, hi = 1, 1
+        while cf.multi_mode_rel(n, modes, hi) > tol:
+            lo, hi = hi, hi * 2
+        while hi - lo > 1:
+            mid = (lo + hi) // 2
+            if cf.multi_mode_rel(n, modes, mid) > tol:
+                lo = mid
+            else:
+                hi = mid
+        return hi
+    proj = {"kind": "projection: closed-form sweep count x measured seconds per sweep (not run)"}
+    for tol in (1e-8, 1e-10):
+        m = sweeps_to(tol)
+        row = {"sweeps_closed_form": m}
+        for name in ("f64", "f32_ir", "bf16rhs_ir"):
+            per_sweep = out[name]["seconds"] / out[name]["sweeps"]
+            row[f"{name}_hours"] = round(m * per_sweep / 3600.0, 2)
+        proj[f"{tol:g}"] = row
+    out["projection_to_tol"] = proj
     del u, f
     torch.cuda.empty_cache()
     return out
