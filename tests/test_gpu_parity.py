@@ -178,9 +178,13 @@ def test_error_paths_on_device():
     with pytest.raises(rb.RbgsError) as e:
         rb.rbgs_sweep(u, f, 1, workspace=ws)
     assert e.value.status == rb.rbgs.EWORKSPACE
-    # SOR (omega != 1) runs on the plain kernel only
+    # SOR (omega != 1) runs in FP64 and without the persistent kernel's
+    # verification modes
     with pytest.raises(rb.RbgsError) as e:
-        rb.rbgs_solve(u, f, 10, 1e-6, omega=1.5, kernel="blocked")
+        rb.rbgs_solve(u, f, 10, 1e-6, omega=1.5, kernel="blocked", debug_tile_order=1)
+    assert e.value.status == rb.rbgs.EUNSUPPORTED
+    with pytest.raises(rb.RbgsError) as e:
+        rb.rbgs_solve(u.float(), f.float(), 10, 1e-6, omega=1.5)
     assert e.value.status == rb.rbgs.EUNSUPPORTED
     # a NaN right-hand side gives a non-finite residual
     fn = f.clone()
