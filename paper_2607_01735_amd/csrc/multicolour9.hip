@@ -110,9 +110,12 @@ __global__ __launch_bounds__(kThreads) void k_mc9_quarter(
             c = c + up_e;
             c = c + up_w;
             double s = 4.0 * e + c;
-            const double t = c6 * f[I * pitch + J];
+            // f is read once per sweep and the new value is not read again
+            // before the next quarter-sweep has streamed its colours: both
+            // go through the caches as streaming (non-temporal)
+            const double t = c6 * __builtin_nontemporal_load(f + I * pitch + J);
             s = s - t;
-            self[I * pitch + J] = s / 20.0;
+            __builtin_nontemporal_store(s / 20.0, self + I * pitch + J);
         }
         up_ns = dn_ns;
         up_w = dn_w;

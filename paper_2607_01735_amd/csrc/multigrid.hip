@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_prolong_red(
     double s = dn + up;
     s = s + right;
     s = s + left;
-    const double t = h2 * f_red[i * pitch + q];
+    const double t = h2 * __builtin_nontemporal_load(f_red + i * pitch + q);  // read once
     s = s - t;
     u_red[i * pitch + q] = 0.25 * s;
 }

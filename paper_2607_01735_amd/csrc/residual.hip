@@ -94,7 +94,9 @@ __global__ __launch_bounds__(256) void k_residual_split(
                 const double right = p ? double(other[int64_t(i) * pitch + q + 1]) : o[1];
                 const double left = p ? o[1] : double(other[int64_t(i) * pitch + q - 1]);
                 const double c = col[colour][1];
-                const double f = double((colour ? f_black : f_red)[int64_t(i) * pitch + q]);
+                // f is read once (streaming, non-temporal)
+                const double f = double(__builtin_nontemporal_load(
+                    (colour ? f_black : f_red) + int64_t(i) * pitch + q));
                 double s = dn + up;
                 s = s + right;
                 s = s + left;

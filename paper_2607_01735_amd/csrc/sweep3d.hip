@@ -100,9 +100,12 @@ __global__ __launch_bounds__(kQ * kJ) void k_rb3_half(double* __restrict__ self,
             s = s + jm;
             s = s + kp;
             s = s + km;
-            const double t = h2 * f[r + q];
+            // f is read once per sweep and the new value is not read again
+            // before the other colour's half-sweep has streamed the whole
+            // grid: both go through the caches as streaming (non-temporal)
+            const double t = h2 * __builtin_nontemporal_load(f + r + q);
             s = s - t;
-            self[r + q] = s / 6.0;
+            __builtin_nontemporal_store(s / 6.0, self + r + q);
         }
         o_dn = o_c;
         o_c = o_up;
