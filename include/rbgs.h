@@ -215,9 +215,12 @@ typedef struct {
 } rbgs_solve_info;
 
 /* Size in bytes of the workspace that rbgs_sweep, rbgs_residual and
- * rbgs_solve need for grid g and storage type dt; `opts` (may be NULL)
- * selects the solve mode (IR modes need more).  Returns 0 for invalid
- * arguments. */
+ * rbgs_solve need for grid g and storage type dt: the red and black arrays
+ * of u and f (the separate colour arrays of Section 2.1), the persistent
+ * kernels' second buffer and state, the residual's partial sums, and for
+ * the IR modes the FP32 right-hand side and correction (the refinement
+ * reading of "BF16 where its error allows", C11).  `opts` (may be NULL)
+ * selects the solve mode.  Returns 0 for invalid arguments. */
 size_t rbgs_workspace_size(const rbgs_grid *g, rbgs_dtype dt,
                            const rbgs_solve_opts *opts);
 
@@ -291,7 +294,12 @@ int rbgs_residual_noalloc(const rbgs_grid *g, rbgs_dtype dt, const void *u,
                           const void *f, double *abs_norm, double *rel_norm,
                           void *stream);
 
-/* Sweeps until rel <= opts->rel_tol or opts->max_sweeps sweeps.  The
+/* Sweeps until rel <= opts->rel_tol or opts->max_sweeps sweeps.
+ * Algorithms 1 and 2 repeat Eq. (1)'s sweep a given number of times and
+ * return the converged solution; the paper states no stopping test, so the
+ * residual, norm and test are the reading C6 that rbgs_residual computes
+ * (rel = ||r||_2 / ||b||_2), and max_sweeps with rel_tol <= 0 is the
+ * paper's fixed iteration count.  The
  * residual is evaluated before the first sweep and after every check_every
  * sweeps (the last group is shortened to end exactly at max_sweeps).
  * RBGS_PREC_F64: plain sweeps in dt.  IR modes (dt must be RBGS_F64): each
@@ -642,7 +650,8 @@ int rbgs_rb3_solve(const rbgs_grid *g, double *u, const double *f,
 int rbgs_stream_probe(int32_t kind, double *a, double *b, double *c,
                       int64_t n_elems, double s, void *stream);
 
-/* Human-readable name of a status code (static string). */
+/* Human-readable name of a status code (static string; the codes are the
+ * library's, not the paper's).  Unknown codes give "unknown rbgs status". */
 const char *rbgs_strerror(int status);
 
 /* Message describing the calling thread's last failure (static per thread). */
