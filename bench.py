@@ -907,18 +907,26 @@ def main():
 
     ms_per_step, glups, acc = run_steps(args.kernel, args.warmup, args.steps)
     if acc["persistent_launches"] > 0:
-        # The persistent blocked kernel: each launch runs `passes` passes of
-        # `fuse` fused sweeps; per pass the algorithmic traffic is one read of
-        # u and f and one write of u, 3 words per point.  Its duration comes
-        # from HIP events around the launch of the deeper passes alone (the
-        # passes one sweep shallower and the ring copies are outside).
+        # The persistent blocked kernel: a step runs ceil(sweeps / fuse)
+        # passes whose depths differ by at most one; per pass the algorithmic
+        # traffic is one read of u and f and one write of u, 3 words per
+        # point.  Its duration comes from HIP events around the timed launch:
+        # all passes when both depths run in one launch (k_blocked2), else
+        # the deeper passes alone (the shallower launch and the ring copies
+        # are outside).
         kernel_used, fuse = "blocked", acc["fuse"]
         launches = acc["persistent_launches"]
         avg_launch_ms = acc["persistent_ms"] / launches
         per_launch_bytes = BYTES_PER_LUP["f64"] * n * n * acc["passes"] / launches
-        # a step runs ceil(sweeps / fuse) passes (depths differ by at most one)
-        bytes_per_lup = BYTES_PER_LUP["f64"] * (-(-sweeps // fuse)) / sweeps
-        kname = f"k_blocked<double,2,{2 * fuse}> (persistent, fuse {fuse})"
+        total_passes = -(-sweeps // fuse)
+        bytes_per_lup = BYTES_PER_LUP["f64"] * total_passes / sweeps
+        passes_per_launch = acc["passes"] // launches
+        if sweeps % fuse and passes_per_launch == total_passes:
+            n_hi = sweeps - total_passes * (fuse - 1)
+            kname = (f"k_blocked2<double,2,{2 * fuse},{2 * fuse - 2}> (persistent, {n_hi} passes "
+                     f"of {fuse} + {total_passes - n_hi} of {fuse - 1} in one launch)")
+        else:
+            kname = f"k_blocked<double,2,{2 * fuse}> (persistent, fuse {fuse})"
         traffic_key = "blocked_f64"
     else:
         # One launch updates one colour: half the points, 3 words each.

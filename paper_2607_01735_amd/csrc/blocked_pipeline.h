@@ -224,10 +224,22 @@ struct Pipe {
 template <int L>
 constexpr int fring_rows() { return L <= 2 ? 4 : L <= 6 ? 8 : L <= 14 ? 16 : L + 2; }
 
-template <typename T, int V, int L>
-struct FRing {
-    Vec<T, V> row[2][fring_rows<L>()][kLanes];
+template <typename T, int V, int R>
+struct FRingRows {
+    Vec<T, V> row[2][R][kLanes];
 };
+
+template <typename T, int V, int L>
+using FRing = FRingRows<T, V, fring_rows<L>()>;
+
+// The wave's ring in LDS, one allocation per (type, vector, ring height):
+// pipelines of different depth with the same ring height (the passes of one
+// launch whose depths differ by one sweep) share it.
+template <typename T, int V, int R>
+__device__ __forceinline__ FRingRows<T, V, R>& wave_fring() {
+    __shared__ FRingRows<T, V, R> fr;
+    return fr;
+}
 
 // Loads never branch: row and column indices are clamped into the grid,
 // and rows of the iterate into the tile's loaded region [lo, hi] = [xs, xe]
@@ -463,7 +475,7 @@ __device__ __forceinline__ void process_tile(const GridDesc<T>& a, int pass, int
     const bool interior = r0 - L >= 1 && r1 + L <= a.n && qa >= 1 &&
                           qa + int64_t(kLanes) * V - 1 <= (int64_t(a.n) - 1) >> 1 &&
                           qc1 - qc0 == a.q_core;
-    __shared__ FRing<T, V, L> fr;
+    FRing<T, V, L>& fr = wave_fring<T, V, fring_rows<L>()>();
     if (interior)
         run_tile<T, V, L, false, SOR>(fr, a, pass, r0, r1, qc0, qc1, store_red, omega);
     else

@@ -62,6 +62,30 @@ __global__ __launch_bounds__(kLanes) void k_blocked(GridDesc<T> g, Queue qu) {
     }
 }
 
+// A launch whose passes differ in depth by one sweep: passes [0, n_hi) run
+// L1 / 2 fused sweeps, the rest L2 / 2 = L1 / 2 - 1, over the same tiles
+// (the host merges only when both depths give the same tile geometry), so
+// the shallower passes follow the deeper ones without a launch boundary:
+// the first of them start while the last deeper ones drain, instead of the
+// second launch ramping up from an idle GPU.  The dependency rule is the
+// same for every pass (3 x 3 neighbourhood, pass p - 1), and both pipelines
+// share the wave's LDS ring.
+template <typename T, int V, int L1, int L2>
+__global__ __launch_bounds__(kLanes) void k_blocked2(GridDesc<T> g, Queue qu, int n_hi) {
+    static_assert(fring_rows<L1>() == fring_rows<L2>(), "the two depths share one LDS ring");
+    if (stopped(qu)) return;
+    const int total = qu.passes * g.ntiles;
+    for (;;) {
+        const int tk = next_ticket(qu);
+        if (tk >= total) break;
+        const int pass = tk / g.ntiles;
+        const int tile = tk - pass * g.ntiles;
+        const bool ok = pass < n_hi ? run_item<T, V, L1>(g, qu, pass, tile)
+                                    : run_item<T, V, L2>(g, qu, pass, tile);
+        if (!ok) break;
+    }
+}
+
 // Red-black SOR (an extension: the paper's method is omega = 1) through the
 // same tiles: every level relaxes from the point's previous version, so red
 // is read and written by every pass (32 B per point and pass in FP64).
@@ -125,6 +149,36 @@ hipError_t launch_k(const GridDesc<T>& g, const Queue& qu, const DebugModes* dm,
         hipLaunchKernelGGL((k_blocked<T, V, L>), dim3(unsigned(grid)), dim3(kLanes), 0, s, g, qu);
     }
     return hipGetLastError();
+}
+
+template <typename T, int V, int L1, int L2>
+hipError_t launch_k2(const GridDesc<T>& g, const Queue& qu, int n_hi, hipStream_t s) {
+    int per_cu = 0, cus = 0;
+    hipError_t e = persistent_occupancy(reinterpret_cast<const void*>(&k_blocked2<T, V, L1, L2>),
+                                        &per_cu, &cus);
+    if (e != hipSuccess) return e;
+    int64_t total = int64_t(qu.passes) * g.ntiles;
+    int64_t grid = int64_t(cus) * per_cu;
+    if (grid > total) grid = total;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((k_blocked2<T, V, L1, L2>), dim3(unsigned(grid)), dim3(kLanes), 0, s, g, qu,
+                       n_hi);
+    return hipGetLastError();
+}
+
+// Depth pairs (fuse, fuse - 1) whose pipelines share a ring height; the
+// others run as two launches.
+bool mergeable_fuse(int fuse) { return fuse == 3 || fuse == 5 || fuse == 6 || fuse == 7; }
+
+template <typename T, int V>
+hipError_t launch_by_fuse2(int fuse, const GridDesc<T>& g, const Queue& qu, int n_hi, hipStream_t s) {
+    switch (fuse) {
+        case 3: return launch_k2<T, V, 6, 4>(g, qu, n_hi, s);
+        case 5: return launch_k2<T, V, 10, 8>(g, qu, n_hi, s);
+        case 6: return launch_k2<T, V, 12, 10>(g, qu, n_hi, s);
+        case 7: return launch_k2<T, V, 14, 12>(g, qu, n_hi, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T, int V>
@@ -309,8 +363,10 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
     int cur = 0;  // buffer holding the current iterate
     bool started = false;
     // `count` passes of `fuse` sweeps starting from buffer cur; `timed`
-    // launches are bracketed by the events and counted
-    auto run_passes = [&](int fuse, int count, bool timed) -> hipError_t {
+    // launches are bracketed by the events and counted.  split >= 0: one
+    // merged launch of `count` passes, the first `split` of depth `fuse`,
+    // the rest one sweep shallower (the caller checked it applies).
+    auto run_passes = [&](int fuse, int count, bool timed, int split = -1) -> hipError_t {
         const int rows = bp.tile_rows < 2 * fuse ? 2 * fuse : bp.tile_rows;
         const Geometry geo = geometry(n, int(sizeof(T)), fuse, rows);
         if (geo.ntiles < 1 || geo.ntiles > max_tiles(n)) return hipErrorInvalidValue;
@@ -318,6 +374,7 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
         // 2^30 work items, each starting from freshly zeroed flags
         const int max_passes = int((int64_t(1) << 30) / geo.ntiles) > 0
                                    ? int((int64_t(1) << 30) / geo.ntiles) : 1;
+        if (split >= 0 && count > max_passes) return hipErrorInvalidValue;
         int done = 0;
         while (done < count) {
             const int chunk = count - done < max_passes ? count - done : max_passes;
@@ -366,7 +423,8 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
                 if (r != hipSuccess) return r;
                 started = true;
             }
-            r = launch_by_fuse<T, V>(fuse, g, qu, debug ? &dm : nullptr, omega, s);
+            r = split >= 0 ? launch_by_fuse2<T, V>(fuse, g, qu, split, s)
+                           : launch_by_fuse<T, V>(fuse, g, qu, debug ? &dm : nullptr, omega, s);
             if (r != hipSuccess) return r;
             *launches += 1;
             if (timed) {
@@ -378,15 +436,36 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
         }
         return hipSuccess;
     };
-    // the events time the n_hi passes of depth d_hi, so that their duration
-    // is that of one kernel
-    if ((e = run_passes(d_hi, n_hi, true)) != hipSuccess) return e;
-    if (ev_end && started) {
-        e = hipEventRecord(ev_end, s);
-        if (e != hipSuccess) return e;
+    // Passes of both depths in one launch when their tiles are the same
+    // (the production kernel only: not with SOR or a verification mode);
+    // else the n_hi passes of depth d_hi, timed by the events so that their
+    // duration is that of one kernel, then the n_lo shallower ones.
+    bool merge = false;
+    if (n_lo > 0 && omega == T(1) && bp.order == 0 && bp.stamp_check == 0 && !bp.trace &&
+        mergeable_fuse(d_hi)) {
+        const int rows = bp.tile_rows < 2 * d_hi ? 2 * d_hi : bp.tile_rows;
+        const Geometry a = geometry(n, int(sizeof(T)), d_hi, rows);
+        const Geometry b = geometry(n, int(sizeof(T)), d_hi - 1, rows);
+        merge = a.halo_q == b.halo_q && a.q_core == b.q_core && a.rows == b.rows &&
+                a.strips == b.strips && a.bands == b.bands && a.ntiles >= 1 &&
+                int64_t(total_passes) * a.ntiles < (int64_t(1) << 30);
     }
-    *timed_fuse = d_hi;
-    if (n_lo > 0 && (e = run_passes(d_hi - 1, n_lo, false)) != hipSuccess) return e;
+    if (merge) {
+        if ((e = run_passes(d_hi, total_passes, true, n_hi)) != hipSuccess) return e;
+        if (ev_end && started) {
+            e = hipEventRecord(ev_end, s);
+            if (e != hipSuccess) return e;
+        }
+        *timed_fuse = d_hi;
+    } else {
+        if ((e = run_passes(d_hi, n_hi, true)) != hipSuccess) return e;
+        if (ev_end && started) {
+            e = hipEventRecord(ev_end, s);
+            if (e != hipSuccess) return e;
+        }
+        *timed_fuse = d_hi;
+        if (n_lo > 0 && (e = run_passes(d_hi - 1, n_lo, false)) != hipSuccess) return e;
+    }
     if (cur != 0) {  // a kernel, so that a converged graph-captured solve skips it too
         e = launch_copy_unless(buf_red[0], buf_red[1], colour_bytes, bp.stop, s);
         if (e != hipSuccess) return e;

@@ -63,6 +63,8 @@ static DebugModes g_debug;  // tile order / stamp check (environment EMU_TILE_OR
                             // EMU_SEED, EMU_STAMP_CHECK), as the verification kernel runs them
 static bool g_debug_on = false;
 static T g_omega = T(1);  // != 1: the SOR pipeline (environment EMU_OMEGA)
+static int g_split = 1 << 30;  // EMU_MERGED: passes from g_split on run one sweep shallower
+                               // (environment EMU_SPLIT), as the merged launch does
 
 static void to_host() {
 #ifdef EMU_TSAN
@@ -86,6 +88,12 @@ static void lane_start(int lane) {
         const int tk = next_ticket(g_queue);
         if (tk >= total) break;
         const int pass = tk / g_grid.ntiles;
+#ifdef EMU_MERGED
+        if (pass >= g_split) {  // the shallower passes of a merged launch
+            if (!run_item<T, kV, kL - 2>(g_grid, g_queue, pass, tk - pass * g_grid.ntiles)) break;
+            continue;
+        }
+#endif
         if (g_omega != T(1)) {
             if (!run_item<T, kV, kL, false, true>(g_grid, g_queue, pass, tk - pass * g_grid.ntiles,
                                                   DebugModes(), 0, g_omega))
@@ -220,6 +228,16 @@ int main(int argc, char** argv) {
     if (const char* e = getenv("EMU_STAMP_CHECK")) g_debug.stamp_check = atoi(e);
     g_debug_on = g_debug.order != 0 || g_debug.stamp_check != 0;
     if (const char* e = getenv("EMU_OMEGA")) g_omega = T(atof(e));
+    if (const char* e = getenv("EMU_SPLIT")) g_split = atoi(e);
+#ifdef EMU_MERGED
+    {  // the merged launch needs the same tiles at both depths
+        const Geometry lo = geometry(n, int(sizeof(T)), kFuse - 1, rows < kL ? kL : rows);
+        if (lo.halo_q != geo.halo_q || lo.q_core != geo.q_core || lo.ntiles != geo.ntiles) {
+            fprintf(stderr, "depths %d and %d give different tiles\n", kFuse, kFuse - 1);
+            return 3;
+        }
+    }
+#endif
     const int workgroups = argc > 7 ? atoi(argv[7]) : 1;
     emu::yield_every = argc > 8 ? atoi(argv[8]) : 0;
     if (workgroups > 1) qu.spin_limit = 1 << 28;

@@ -55,6 +55,7 @@ CASES = [  # n, sweeps, fuse, tile_rows (0 = default)
     (9, 17, 8, 16), (333, 40, 8, 0), (1023, 27, 9, 24), (1200, 50, 10, 20), (4095, 30, 10, 0),
     (100, 3, 7, 16), (700, 9, 5, 0), (2048, 11, 9, 0),  # passes of two depths
     (300, 13, 4, 8), (255, 200, 7, 0),                 # 4 + 3 x 3; 26 x 7 + 3 x 6
+    (1023, 41, 7, 0), (4095, 33, 6, 0), (150, 7, 3, 8), (1500, 14, 5, 40),  # one launch, two depths
 ]
 
 
@@ -165,11 +166,14 @@ def test_blocked_large_grid_sampled(oracle):
     assert np.all(np.isfinite(got))
 
 
-@pytest.mark.parametrize("nsweeps,fuse,deep,passes", [(200, 7, 7, 26), (14, 7, 7, 2), (13, 7, 7, 1),
-                                                      (8, 7, 4, 2), (3, 7, 3, 1)])
+@pytest.mark.parametrize("nsweeps,fuse,deep,passes", [(200, 7, 7, 29), (14, 7, 7, 2), (13, 7, 7, 2),
+                                                      (8, 7, 4, 2), (3, 7, 3, 1), (12, 4, 4, 3),
+                                                      (11, 4, 4, 2)])
 def test_blocked_pass_split(nsweeps, fuse, deep, passes):
     """nsweeps run as ceil(nsweeps / fuse) passes whose depths differ by at
-    most one; the timing reports the launch of the deeper ones."""
+    most one; the timing reports the timed launch: all passes when both
+    depths run in one launch (fuse pairs 7/6, 6/5, 5/4, 3/2 with the same
+    tiles), else the deeper passes alone (4/3: 11 sweeps = 2 x 4 + 1 x 3)."""
     say(f"blocked pass split nsweeps={nsweeps} fuse={fuse}")
     n = 127
     u0, f = start(n, 5)

@@ -182,3 +182,26 @@ def test_sor_pipeline_matches_oracle(oracle, tmp_path, n, omega):
     got = np.fromfile(fout, dtype=np.float64).reshape(n + 2, n + 2)
     ref = oracle.sor_sweep(u0.copy(), f, h, omega, passes * fuse)
     assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("fuse,n,rows,passes,split", [(7, 130, 16, 4, 2), (3, 150, 8, 3, 1)])
+def test_merged_depths_match_oracle(oracle, tmp_path, fuse, n, rows, passes, split):
+    """One launch whose passes differ in depth by one sweep (the first
+    `split` passes fuse `fuse` sweeps, the rest one fewer, sharing the
+    wave's LDS ring), three workgroups under ThreadSanitizer: the oracle's
+    sweeps bit for bit."""
+    exe = _build(tmp_path, "float64", fuse, "thread", 0, extra=("EMU_MERGED",))
+    u0, f = _inputs(n, np.float64)
+    fin, fout = tmp_path / "in.bin", tmp_path / "out.bin"
+    with open(fin, "wb") as fh:
+        fh.write(np.ascontiguousarray(u0).tobytes())
+        fh.write(np.ascontiguousarray(f).tobytes())
+    h = W.spacing(n)
+    res = subprocess.run([str(exe), str(n), str(rows), str(passes), repr(h), str(fin), str(fout), "3"],
+                         capture_output=True, text=True, env=dict(_env(0), EMU_SPLIT=str(split)),
+                         timeout=1200)
+    assert res.returncode == 0, (res.stdout + res.stderr)[-4000:]
+    got = np.fromfile(fout, dtype=np.float64).reshape(n + 2, n + 2)
+    ref = oracle.sweep(u0.copy(), f, h, split * fuse + (passes - split) * (fuse - 1))
+    assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
