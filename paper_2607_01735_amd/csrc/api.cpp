@@ -177,7 +177,7 @@ int validate_sweep_opts(const rbgs_sweep_opts* o) {
 }
 
 struct EventTimer {
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool on = false;
     hipError_t init(bool enable) {
         on = enable;
@@ -1021,20 +1021,23 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
     HIP_TRY(gt.t.init(o->sweep.timing != nullptr), "event create");
     PersistentTimer pt;
     HIP_TRY(pt.init(o->sweep.timing != nullptr), "event create");
+    // Timing never waits for the device on its own: every interval is read
+    // after a synchronisation the solve makes anyway (a residual readback or
+    // the final one), so a timed solve keeps the GPU as busy as an untimed one.
     HIP_TRY(gt.t.mark(0, s), "event record");
     HIP_TRY(launch_pack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, es, s), "pack u");
     HIP_TRY(launch_pack(f, g->ld, w.f_red, w.f_black, g->n, w.pitch, es, s), "pack f");
     HIP_TRY(gt.t.mark(3, s), "event record");
-    if (gt.t.on) {
-        HIP_TRY(hipEventSynchronize(gt.t.ev[3]), "event synchronise");
-        HIP_TRY(hipEventElapsedTime(&gt.acc.pack_ms, gt.t.ev[0], gt.t.ev[3]), "event time");
-    }
 
     rbgs_solve_info out{0, 0, 0.0, 0.0, RBGS_OK, RBGS_PREC_F64};
     int launches = 0;
     void* err_state = nullptr;
     rbgs_sweep_opts sw = o->sweep;
     sw.timing = nullptr;
+    // a fixed sweep count reads its norms back only after the unpack is
+    // enqueued (one synchronisation for the whole call)
+    bool norms_pending = false;
+    int pending_launches = 0;
     if (!ir) {
         double rel = 0.0, ab = 0.0;
         int32_t done = 0;
@@ -1044,11 +1047,10 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
                                     nullptr, omega)))
                 return rc;
             HIP_TRY(gt.end(s), "event record");
-            HIP_TRY(gt.collect(launches), "event time");
-            HIP_TRY(pt.collect(), "event time");
             done = o->max_sweeps;
             if ((rc = split_residual_dt(dt, g, w, s))) return rc;
-            if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+            norms_pending = true;
+            pending_launches = launches;
         } else {
             if ((rc = split_residual_dt(dt, g, w, s))) return rc;
             if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
@@ -1082,11 +1084,11 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
                                         omega)))
                     return rc;
                 HIP_TRY(gt.end(s), "event record");
-                HIP_TRY(gt.collect(launches), "event time");
-                HIP_TRY(pt.collect(), "event time");
                 done += k;
                 if ((rc = split_residual_dt(dt, g, w, s))) return rc;
                 if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+                HIP_TRY(gt.collect(launches), "event time");
+                HIP_TRY(pt.collect(), "event time");
                 if (err_state && (rc = blocked_check_error(err_state, s, &g_last_error)))
                     return rc;
             }
@@ -1163,11 +1165,11 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
                 HIP_TRY(gt.begin(s), "event record");
                 if ((rc = run_sweeps<double>(g, w, k, &sw, s, &launches, &err_state, &pt))) return rc;
                 HIP_TRY(gt.end(s), "event record");
-                HIP_TRY(gt.collect(launches), "event time");
-                HIP_TRY(pt.collect(), "event time");
                 done += k;
                 if ((rc = split_residual<double>(g, w, s, nullptr, nullptr, 0))) return rc;
                 if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+                HIP_TRY(gt.collect(launches), "event time");
+                HIP_TRY(pt.collect(), "event time");
                 if (err_state && (rc = blocked_check_error(err_state, s, &g_last_error)))
                     return rc;
                 continue;
@@ -1215,8 +1217,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
             HIP_TRY(gt.begin(s), "event record");
             if ((rc = run_sweeps<float>(&gi, inner_w, k, &sw, s, &launches, &err_state, &pt))) return rc;
             HIP_TRY(gt.end(s), "event record");
-            HIP_TRY(gt.collect(launches), "event time");
-            HIP_TRY(pt.collect(), "event time");
+            const int step_launches = launches;
             HIP_TRY(launch_add_correction(static_cast<double*>(w.u_red),
                                           static_cast<double*>(w.u_black), w.pitch, w.e_red,
                                           w.e_black, w.pitch32, g->n, s),
@@ -1226,6 +1227,8 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
             const double before = rel;
             if ((rc = split_residual<double>(g, w, s, w.r_red, w.r_black, bf16, ovf))) return rc;
             if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+            HIP_TRY(gt.collect(step_launches), "event time");
+            HIP_TRY(pt.collect(), "event time");
             if (err_state && (rc = blocked_check_error(err_state, s, &g_last_error)))
                 return rc;
             if ((rc = after_step(before))) return rc;
@@ -1240,12 +1243,22 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         else
             out.status = rel <= o->rel_tol ? RBGS_OK : RBGS_ENOCONV;
     }
-    HIP_TRY(gt.t.mark(0, s), "event record");
+    HIP_TRY(gt.t.mark(4, s), "event record");
     HIP_TRY(launch_unpack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, es, s), "unpack u");
-    HIP_TRY(gt.t.mark(3, s), "event record");
+    HIP_TRY(gt.t.mark(5, s), "event record");
+    if (norms_pending) {
+        double rel = 0.0, ab = 0.0;
+        if ((rc = fetch_norms(w, s, &ab, &rel))) return rc;
+        HIP_TRY(gt.collect(pending_launches), "event time");
+        HIP_TRY(pt.collect(), "event time");
+        out.rel_residual = rel;
+        out.abs_residual = ab;
+        out.status = std::isfinite(rel) ? RBGS_OK : RBGS_ENONFINITE;
+    }
     HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
     if (gt.t.on) {
-        HIP_TRY(hipEventElapsedTime(&gt.acc.unpack_ms, gt.t.ev[0], gt.t.ev[3]), "event time");
+        HIP_TRY(hipEventElapsedTime(&gt.acc.pack_ms, gt.t.ev[0], gt.t.ev[3]), "event time");
+        HIP_TRY(hipEventElapsedTime(&gt.acc.unpack_ms, gt.t.ev[4], gt.t.ev[5]), "event time");
         pt.fill(&gt.acc);
         *o->sweep.timing = gt.acc;
     }
