@@ -259,7 +259,7 @@ struct GroupTimer {
 template <typename T>
 int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rbgs_sweep_opts* o,
                hipStream_t s, int* launches, void** err_state, PersistentTimer* pt,
-               const int* stop = nullptr, double omega = 1.0) {
+               const int* stop = nullptr, double omega = 1.0, int start = 0) {
     const int n = g->n;
     const T h2 = T(g->h * g->h);
     T* ur = static_cast<T*>(w.u_red);
@@ -269,18 +269,24 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
     int kernel = o ? o->kernel : RBGS_KERNEL_AUTO;
     if (kernel == RBGS_KERNEL_AUTO) kernel = auto_kernel(n, sizeof(T), nsweeps);
     *launches = 0;
+    if (start != 0 && kernel != RBGS_KERNEL_BLOCKED)
+        return fail(RBGS_EINVAL, "internal: only the blocked kernel starts in the second buffer");
     if (kernel == RBGS_KERNEL_BLOCKED) {
         BlockedParams bp = blocked_params(n, sizeof(T), o);
         bp.stop = stop;
         bp.keep_error = stop != nullptr;
-        T* const bred[2] = {ur, static_cast<T*>(w.u2_red)};
-        T* const bblack[2] = {ub, static_cast<T*>(w.u2_black)};
+        // start = 1: the caller packed u into the second buffer, so that an
+        // odd number of passes ends in the first without a copy back
+        T* const u2r = static_cast<T*>(w.u2_red);
+        T* const u2b = static_cast<T*>(w.u2_black);
+        T* const bred[2] = {start ? u2r : ur, start ? ur : u2r};
+        T* const bblack[2] = {start ? u2b : ub, start ? ub : u2b};
         const bool timed = pt && pt->on;
         int plaunches = 0, passes = 0, depth = 0;
         HIP_TRY(run_blocked<T>(bred, bblack, fr, fb, n, w.pitch, h2, nsweeps, bp, w.blocked,
                                w.blocked_bytes, s, launches, timed ? pt->ev[0] : nullptr,
                                timed ? pt->ev[1] : nullptr, &plaunches, &passes, &depth,
-                               T(omega)),
+                               T(omega), start != 0),
                 "blocked sweep");
         if (timed && plaunches > 0) {
             pt->armed = true;
@@ -327,10 +333,22 @@ int run_sweeps(const rbgs_grid* g, const Workspace& w, int32_t nsweeps, const rb
 
 int run_sweeps_dt(rbgs_dtype dt, const rbgs_grid* g, const Workspace& w, int32_t nsweeps,
                   const rbgs_sweep_opts* o, hipStream_t s, int* launches, void** err_state,
-                  PersistentTimer* pt, const int* stop = nullptr, double omega = 1.0) {
+                  PersistentTimer* pt, const int* stop = nullptr, double omega = 1.0,
+                  int start = 0) {
     return dt == RBGS_F64
-               ? run_sweeps<double>(g, w, nsweeps, o, s, launches, err_state, pt, stop, omega)
-               : run_sweeps<float>(g, w, nsweeps, o, s, launches, err_state, pt, stop, omega);
+               ? run_sweeps<double>(g, w, nsweeps, o, s, launches, err_state, pt, stop, omega, start)
+               : run_sweeps<float>(g, w, nsweeps, o, s, launches, err_state, pt, stop, omega, start);
+}
+
+// Where a call that sweeps nsweeps times straight after packing should pack
+// u: the second buffer (1) when the persistent kernel will run an odd number
+// of passes, whose result then lands in the first buffer with no copy back;
+// else the first (0).
+int pack_buffer(const rbgs_grid* g, rbgs_dtype dt, int32_t nsweeps, const rbgs_sweep_opts* o) {
+    int kernel = o ? o->kernel : RBGS_KERNEL_AUTO;
+    if (kernel == RBGS_KERNEL_AUTO) kernel = auto_kernel(g->n, elem_size(dt), nsweeps);
+    if (kernel != RBGS_KERNEL_BLOCKED) return 0;
+    return blocked_pass_parity(g->n, elem_size(dt), nsweeps, o);
 }
 
 // Reads the two device sums, synchronising the stream.
@@ -893,13 +911,18 @@ int rbgs_sweep(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f, int32_
     HIP_TRY(tm.init(opts && opts->timing), "event create");
     PersistentTimer pt;
     HIP_TRY(pt.init(opts && opts->timing), "event create");
+    const int start = pack_buffer(g, dt, nsweeps, opts);
     HIP_TRY(tm.mark(0, s), "event record");
-    HIP_TRY(launch_pack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, es, s), "pack u");
+    HIP_TRY(launch_pack(u, g->ld, start ? w.u2_red : w.u_red, start ? w.u2_black : w.u_black, g->n,
+                        w.pitch, es, s),
+            "pack u");
     HIP_TRY(launch_pack(f, g->ld, w.f_red, w.f_black, g->n, w.pitch, es, s), "pack f");
     HIP_TRY(tm.mark(1, s), "event record");
     int launches = 0;
     void* err_state = nullptr;
-    if ((rc = run_sweeps_dt(dt, g, w, nsweeps, opts, s, &launches, &err_state, &pt))) return rc;
+    if ((rc = run_sweeps_dt(dt, g, w, nsweeps, opts, s, &launches, &err_state, &pt, nullptr, 1.0,
+                            start)))
+        return rc;
     HIP_TRY(tm.mark(2, s), "event record");
     HIP_TRY(launch_unpack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, es, s), "unpack u");
     HIP_TRY(tm.mark(3, s), "event record");
@@ -1024,8 +1047,12 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
     // Timing never waits for the device on its own: every interval is read
     // after a synchronisation the solve makes anyway (a residual readback or
     // the final one), so a timed solve keeps the GPU as busy as an untimed one.
+    // a fixed sweep count (no refinement) packs u where its sweeps end
+    const int start = (!ir && o->rel_tol <= 0.0) ? pack_buffer(g, dt, o->max_sweeps, &o->sweep) : 0;
     HIP_TRY(gt.t.mark(0, s), "event record");
-    HIP_TRY(launch_pack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, es, s), "pack u");
+    HIP_TRY(launch_pack(u, g->ld, start ? w.u2_red : w.u_red, start ? w.u2_black : w.u_black, g->n,
+                        w.pitch, es, s),
+            "pack u");
     HIP_TRY(launch_pack(f, g->ld, w.f_red, w.f_black, g->n, w.pitch, es, s), "pack f");
     HIP_TRY(gt.t.mark(3, s), "event record");
 
@@ -1044,7 +1071,7 @@ int rbgs_solve(const rbgs_grid* g, rbgs_dtype dt, void* u, const void* f,
         if (o->rel_tol <= 0.0) {
             HIP_TRY(gt.begin(s), "event record");
             if ((rc = run_sweeps_dt(dt, g, w, o->max_sweeps, &sw, s, &launches, &err_state, &pt,
-                                    nullptr, omega)))
+                                    nullptr, omega, start)))
                 return rc;
             HIP_TRY(gt.end(s), "event record");
             done = o->max_sweeps;

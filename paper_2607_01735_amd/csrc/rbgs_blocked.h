@@ -131,14 +131,20 @@ BlockedParams blocked_params(int n, size_t elem_bytes, const rbgs_sweep_opts* o)
 // plain kernel.  When ev_begin/ev_end are given they are recorded around the
 // launch(es) of the deeper passes; *persistent_launches, *passes_done and
 // *timed_fuse receive what those launches did.  omega != 1: red-black SOR
-// (FP64 only; not with the verification modes).
+// (FP64 only; not with the verification modes).  result_in_last: after an
+// odd number of passes leave the result in buffer 1 (the caller packed the
+// input into buffer 0 knowing the parity, so buffer 1 is where it wants
+// it) instead of copying it back into buffer 0.
 template <typename T>
 hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_red,
                        const T* f_black, int n, int64_t pitch, T h2, int nsweeps,
                        const BlockedParams& bp, void* state, size_t state_bytes, hipStream_t s,
                        int* launches, hipEvent_t ev_begin, hipEvent_t ev_end,
                        int* persistent_launches, int* passes_done, int* timed_fuse,
-                       T omega = T(1));
+                       T omega = T(1), bool result_in_last = false);
+// 1 when nsweeps sweeps with these options run an odd number of persistent
+// passes (the result then lands in the second buffer), else 0.
+int blocked_pass_parity(int n, size_t elem_bytes, int nsweeps, const rbgs_sweep_opts* o);
 // Reads the persistent kernel's error word (synchronising the stream when
 // the kernel ran); returns RBGS_OK or RBGS_ETIMEOUT.
 int blocked_check_error(void* state, hipStream_t s, std::string* why);

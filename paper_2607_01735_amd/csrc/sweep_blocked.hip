@@ -319,7 +319,8 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
                        const T* f_black, int n, int64_t pitch, T h2, int nsweeps,
                        const BlockedParams& bp, void* state, size_t state_bytes, hipStream_t s,
                        int* launches, hipEvent_t ev_begin, hipEvent_t ev_end,
-                       int* persistent_launches, int* passes_done, int* timed_fuse, T omega) {
+                       int* persistent_launches, int* passes_done, int* timed_fuse, T omega,
+                       bool result_in_last) {
     constexpr int V = 16 / int(sizeof(T));
     *persistent_launches = 0;
     *passes_done = 0;
@@ -466,7 +467,13 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
         *timed_fuse = d_hi;
         if (n_lo > 0 && (e = run_passes(d_hi - 1, n_lo, false)) != hipSuccess) return e;
     }
-    if (cur != 0) {  // a kernel, so that a converged graph-captured solve skips it too
+    if (result_in_last && cur == 0) {  // an even count after all: move it to where the caller wants it
+        e = launch_copy_unless(buf_red[1], buf_red[0], colour_bytes, bp.stop, s);
+        if (e != hipSuccess) return e;
+        e = launch_copy_unless(buf_black[1], buf_black[0], colour_bytes, bp.stop, s);
+        if (e != hipSuccess) return e;
+    }
+    if (cur != 0 && !result_in_last) {  // a kernel, so that a converged graph-captured solve skips it too
         e = launch_copy_unless(buf_red[0], buf_red[1], colour_bytes, bp.stop, s);
         if (e != hipSuccess) return e;
         e = launch_copy_unless(buf_black[0], buf_black[1], colour_bytes, bp.stop, s);
@@ -478,11 +485,17 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
 template hipError_t run_blocked<double>(double* const[2], double* const[2], const double*,
                                         const double*, int, int64_t, double, int,
                                         const BlockedParams&, void*, size_t, hipStream_t, int*,
-                                        hipEvent_t, hipEvent_t, int*, int*, int*, double);
+                                        hipEvent_t, hipEvent_t, int*, int*, int*, double, bool);
 template hipError_t run_blocked<float>(float* const[2], float* const[2], const float*,
                                        const float*, int, int64_t, float, int,
                                        const BlockedParams&, void*, size_t, hipStream_t, int*,
-                                       hipEvent_t, hipEvent_t, int*, int*, int*, float);
+                                       hipEvent_t, hipEvent_t, int*, int*, int*, float, bool);
+
+int blocked_pass_parity(int n, size_t elem_bytes, int nsweeps, const rbgs_sweep_opts* o) {
+    if (nsweeps < 2) return 0;  // the plain kernel runs a single sweep in place
+    const int k = blocked_params(n, elem_bytes, o).fuse;
+    return ((nsweeps + k - 1) / k) & 1;
+}
 
 int blocked_check_error(void* state, hipStream_t s, std::string* why) {
     int err = 0;

@@ -263,3 +263,23 @@ def test_blocked_trace_follows_dependency_rule(oracle, order):
                          end_t[(p - 1) * ntiles:p * ntiles].max()) for p in range(1, passes))
     say(f"  {passes} passes x {ntiles} tiles; {overlapped} of {passes - 1} pass boundaries overlap")
     assert overlapped >= 1
+
+
+@pytest.mark.parametrize("nsweeps,fuse", [(200, 7), (41, 7), (9, 1), (12, 4)])
+def test_fixed_count_solve_parity_of_passes(oracle, nsweeps, fuse):
+    """A fixed sweep count packs u into the buffer its passes end in (the
+    second one for an odd pass count), so no copy back is needed: the result
+    and the residual are the oracle's for odd and even counts alike."""
+    n = 1023
+    say(f"fixed-count solve n={n} sweeps={nsweeps} fuse={fuse}")
+    h = W.spacing(n)
+    u0, f = start(n, 21)
+    ut = dev(u0)
+    info = rb.rbgs_solve(ut, dev(f), nsweeps, 0.0, check_every=nsweeps, h=h, kernel="blocked",
+                         fuse=fuse)
+    assert info["status"] == 0 and info["sweeps"] == nsweeps
+    ref = u0.copy()
+    oracle.sweep(ref, f, h, nsweeps)
+    assert np.array_equal(host(ut), ref)
+    a_ref, r_ref = oracle.residual(ref, f, h)
+    assert info["rel_residual"] == pytest.approx(r_ref, rel=1e-12)
