@@ -688,7 +688,9 @@ def batched_throughput(torch, rb, W, count=512, sweeps=100):
     """The batched workload: 512 grids, sizes uniform on {63,127,255,511,1023}
     (seed 0), f i.i.d. N(0,1) (seed 1+g), FP32, 100 sweeps each, one
     graph-captured persistent launch after autotuning; beside it the same
-    grids swept one by one with the plain FP64 kernel."""
+    grids swept one by one with the plain FP64 kernel (the judge), and in
+    FP32 with the plain kernel and with the automatic single-grid choice
+    (the same precision)."""
     sizes = W.batch_sizes(count, seed=0)
     log(f"batched workload: {count} grids, building f")
     fs64 = [torch.from_numpy(W.normal_rhs(n, seed=1 + g)) for g, n in enumerate(sizes)]
@@ -724,8 +726,25 @@ def batched_throughput(torch, rb, W, count=512, sweeps=100):
     dt64 = time.perf_counter() - t0
     out["plain_f64_one_by_one"] = {"seconds": round(dt64, 4), "glups": round(lups / dt64 / 1e9, 1)}
     out["speedup_vs_plain_f64"] = round(dt64 / dt, 2)
+    # same precision: the FP32 grids one by one with the plain kernel and
+    # with the library's automatic single-grid choice (resident / plain)
+    ws32 = torch.empty(rb.rbgs_workspace_size(rb.make_grid(us[sizes.index(max(sizes))]), 1),
+                       dtype=torch.uint8, device="cuda")
+    for kernel in ("plain", "auto"):
+        for u in us:
+            u.zero_()
+        rb.rbgs_sweep(us[0], fs[0], sweeps, kernel=kernel, workspace=ws32)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for u, f in zip(us, fs):
+            rb.rbgs_sweep(u, f, sweeps, kernel=kernel, workspace=ws32)
+        torch.cuda.synchronize()
+        d32 = time.perf_counter() - t0
+        out[f"{kernel}_f32_one_by_one"] = {"seconds": round(d32, 4),
+                                           "glups": round(lups / d32 / 1e9, 1)}
+        out[f"speedup_vs_{kernel}_f32_one_by_one"] = round(d32 / dt, 2)
     log(f"batched: {out}")
-    del us, fs, u64, f64, ws
+    del us, fs, u64, f64, ws, ws32
     torch.cuda.empty_cache()
     return out
 
@@ -833,6 +852,8 @@ def main():
                     help="run only the 3D red-black section, print its JSON and exit")
     ap.add_argument("--mc9-only", action="store_true",
                     help="run only the 9-point four-colour section, print its JSON and exit")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 512-grid batched workload")
     ap.add_argument("--overlap-only", action="store_true",
                     help="only the traced pass overlap of the 8191^2 workload")
     ap.add_argument("--unet-only", action="store_true",
@@ -862,6 +883,9 @@ def main():
     if args.mc9_only:
         mc9 = multicolour9_throughput(torch, rb, W, with_solve=not args.no_time_to_tol)
         print(json.dumps({"multicolour9": mc9}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched_512": batched_throughput(torch, rb, W)}), flush=True)
         return
     if args.overlap_only:
         print(json.dumps({"pass_overlap_8191": pass_overlap(torch, rb, W)}), flush=True)
