@@ -73,12 +73,15 @@ int residual_partial_slots(int n, int64_t pitch, size_t elem_bytes);
 // r_out_red/black (optional): store r rounded to FP32 (or bfloat16 when
 // rhs_bf16) in a split FP32 array of pitch r_pitch, for refinement;
 // overflow (optional) is set to 1 when a finite r becomes infinite there.
+// nat (optional): also unpack the interior of u into this natural array of
+// row pitch ld (the same values the unpack kernel writes), in the same pass.
 template <typename T>
 hipError_t launch_residual_split(const T* u_red, const T* u_black, const T* f_red,
                                  const T* f_black, int n, int64_t pitch, double inv_h2,
                                  double* partials, double* out, float* r_out_red,
                                  float* r_out_black, int64_t r_pitch, int rhs_bf16,
-                                 hipStream_t s, int* overflow = nullptr);
+                                 hipStream_t s, int* overflow = nullptr, T* nat = nullptr,
+                                 int64_t ld = 0);
 
 // Convergence test of a graph-captured solve round (device-side): from the
 // residual kernel's sums, sets state[0] (the converged flag the sweep

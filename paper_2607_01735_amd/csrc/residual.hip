@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_residual_split(
     const T* __restrict__ u_red, const T* __restrict__ u_black, const T* __restrict__ f_red,
     const T* __restrict__ f_black, int n, int64_t pitch, double inv_h2, double* partials,
     int col_blocks, float* __restrict__ r_red, float* __restrict__ r_black, int64_t r_pitch,
-    int rhs_bf16, int* __restrict__ overflow) {
+    int rhs_bf16, int* __restrict__ overflow, T* __restrict__ nat, int64_t ld) {
     const int strip = blockIdx.x / col_blocks;
     const int cb = blockIdx.x - strip * col_blocks;
     const int64_t q = int64_t(cb) * 256 + threadIdx.x;
@@ -94,6 +94,9 @@ __global__ __launch_bounds__(256) void k_residual_split(
                 const double right = p ? double(other[int64_t(i) * pitch + q + 1]) : o[1];
                 const double left = p ? o[1] : double(other[int64_t(i) * pitch + q - 1]);
                 const double c = col[colour][1];
+                // the unpack of a fixed-count solve rides along: this point's
+                // value into the natural array (interior only, as the unpack)
+                if (nat) nat[int64_t(i) * ld + j] = T(c);  // exact: c is a widened T
                 // f is read once (streaming, non-temporal)
                 const double f = double(__builtin_nontemporal_load(
                     (colour ? f_black : f_red) + int64_t(i) * pitch + q));
@@ -240,12 +243,12 @@ hipError_t launch_residual_split(const T* u_red, const T* u_black, const T* f_re
                                  const T* f_black, int n, int64_t pitch, double inv_h2,
                                  double* partials, double* out, float* r_out_red,
                                  float* r_out_black, int64_t r_pitch, int rhs_bf16,
-                                 hipStream_t s, int* overflow) {
+                                 hipStream_t s, int* overflow, T* nat, int64_t ld) {
     const int cb = split_col_blocks(n);
     dim3 grid(unsigned(cb * strips(n)));
     hipLaunchKernelGGL((k_residual_split<T>), grid, dim3(256), 0, s, u_red, u_black, f_red,
                        f_black, n, pitch, inv_h2, partials, cb, r_out_red, r_out_black, r_pitch,
-                       rhs_bf16, overflow);
+                       rhs_bf16, overflow, nat, ld);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partials,
@@ -311,11 +314,11 @@ hipError_t launch_judge(const double* sums, double rel_tol, int* state, int cap,
 template hipError_t launch_residual_split<double>(const double*, const double*, const double*,
                                                   const double*, int, int64_t, double, double*,
                                                   double*, float*, float*, int64_t, int,
-                                                  hipStream_t, int*);
+                                                  hipStream_t, int*, double*, int64_t);
 template hipError_t launch_residual_split<float>(const float*, const float*, const float*,
                                                  const float*, int, int64_t, double, double*,
                                                  double*, float*, float*, int64_t, int,
-                                                 hipStream_t, int*);
+                                                 hipStream_t, int*, float*, int64_t);
 template hipError_t launch_residual_natural<double>(const double*, const double*, int, int64_t,
                                                     double, double*, double*, hipStream_t);
 template hipError_t launch_residual_natural<float>(const float*, const float*, int, int64_t,
