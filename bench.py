@@ -550,9 +550,10 @@ def batched_to_tolerance(torch, rb, W, count=16, tol=1e-8, chunk=4000):
     """Many small grids to rel <= tol: `count` grids with sizes uniform on
     {63, 127, 255} (seed 1), f i.i.d. N(0,1) (seed 1000+g), FP64, u0 = 0.
     Batched: one graph-captured persistent launch of `chunk` sweeps for all
-    grids, then every grid's residual, until all are below tol; and the
-    batched refinement solve (FP32 inner sweeps of all grids batched, FP64
-    residual and correction per grid).  Judge: each
+    grids, then every grid's residual, until all are below tol; the batched
+    refinement solve (FP32 inner sweeps of all grids batched, FP64 residual
+    and correction per grid); and the batched FP64 solve (converged grids
+    leave the batch).  Judge: each
     grid solved alone with the plain FP64 kernel (residual every 1000
     sweeps)."""
     import numpy as np
@@ -597,6 +598,21 @@ def batched_to_tolerance(torch, rb, W, count=16, tol=1e-8, chunk=4000):
                              "max_outer": max(i["outer_iters"] for i in infos),
                              "max_rel": max(i["rel_residual"] for i in infos),
                              "all_converged": all(i["status"] == 0 for i in infos)}
+    # The batched FP64 solve: `chunk` FP64 sweeps of every unconverged grid
+    # in one batched persistent launch, then each of those grids' residual;
+    # a grid below tol drops out of the next launch.
+    rb.rbgs_solve_batched(us, fs, 10, tol, 10, precision="f64")  # warm-up
+    for u in us:
+        u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = rb.rbgs_solve_batched(us, fs, 400_000, tol, chunk, precision="f64")
+    torch.cuda.synchronize()
+    dt_f64 = time.perf_counter() - t0
+    out["batched_f64_solve"] = {"seconds": round(dt_f64, 4),
+                                "max_sweeps": max(i["sweeps"] for i in infos),
+                                "max_rel": max(i["rel_residual"] for i in infos),
+                                "all_converged": all(i["status"] == 0 for i in infos)}
     t_plain = 0.0
     sweeps_plain = 0
     for f in fs:
@@ -608,6 +624,7 @@ def batched_to_tolerance(torch, rb, W, count=16, tol=1e-8, chunk=4000):
     out["plain_f64_one_by_one"] = {"seconds": round(t_plain, 4), "max_sweeps": sweeps_plain}
     out["speedup_vs_plain_f64"] = round(t_plain / dt, 2)
     out["speedup_f32_ir_vs_plain_f64"] = round(t_plain / dt_ir, 2)
+    out["speedup_f64_solve_vs_plain_f64"] = round(t_plain / dt_f64, 2)
     log(f"batched to tolerance: {out}")
     return out
 
@@ -853,7 +870,7 @@ def main():
     ap.add_argument("--mc9-only", action="store_true",
                     help="run only the 9-point four-colour section, print its JSON and exit")
     ap.add_argument("--batched-only", action="store_true",
-                    help="only the 512-grid batched workload")
+                    help="only the batched workloads (512-grid sweeps, 16 grids to tolerance)")
     ap.add_argument("--overlap-only", action="store_true",
                     help="only the traced pass overlap of the 8191^2 workload")
     ap.add_argument("--unet-only", action="store_true",
@@ -885,7 +902,8 @@ def main():
         print(json.dumps({"multicolour9": mc9}), flush=True)
         return
     if args.batched_only:
-        print(json.dumps({"batched_512": batched_throughput(torch, rb, W)}), flush=True)
+        print(json.dumps({"batched_512": batched_throughput(torch, rb, W),
+                          "batched_to_1e-8": batched_to_tolerance(torch, rb, W)}), flush=True)
         return
     if args.overlap_only:
         print(json.dumps({"pass_overlap_8191": pass_overlap(torch, rb, W)}), flush=True)

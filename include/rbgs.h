@@ -218,8 +218,8 @@ typedef struct {
  * rbgs_solve need for grid g and storage type dt: the red and black arrays
  * of u and f (the separate colour arrays of Section 2.1), the persistent
  * kernels' second buffer and state, the residual's partial sums, and for
- * the IR modes the FP32 right-hand side and correction (the refinement
- * reading of "BF16 where its error allows", C11).  `opts` (may be NULL)
+ * the IR modes the FP32 right-hand side and correction (mixed precision
+ * read as FP64 refinement around narrower inner sweeps).  `opts` (may be NULL)
  * selects the solve mode.  Returns 0 for invalid arguments. */
 size_t rbgs_workspace_size(const rbgs_grid *g, rbgs_dtype dt,
                            const rbgs_solve_opts *opts);
@@ -297,8 +297,8 @@ int rbgs_residual_noalloc(const rbgs_grid *g, rbgs_dtype dt, const void *u,
 /* Sweeps until rel <= opts->rel_tol or opts->max_sweeps sweeps.
  * Algorithms 1 and 2 repeat Eq. (1)'s sweep a given number of times and
  * return the converged solution; the paper states no stopping test, so the
- * residual, norm and test are the reading C6 that rbgs_residual computes
- * (rel = ||r||_2 / ||b||_2), and max_sweeps with rel_tol <= 0 is the
+ * residual, norm and test are this library's choice, the ones
+ * rbgs_residual computes (rel = ||r||_2 / ||b||_2), and max_sweeps with rel_tol <= 0 is the
  * paper's fixed iteration count.  The
  * residual is evaluated before the first sweep and after every check_every
  * sweeps (the last group is shortened to end exactly at max_sweeps).
@@ -378,20 +378,29 @@ int rbgs_autotune_batched(int32_t count, const rbgs_grid *grids,
                           float *best_ms_per_sweep);
 
 /* Batched solve to a tolerance: every grid of the batch (FP64 u and f,
- * natural layout, HOST arrays of device pointers as above) is refined as
- * rbgs_solve does it with precision F32_IR or BF16RHS_IR (the mixed-
- * precision refinement the build adds to the paper's method): an FP64
- * residual, r rounded to FP32 (or bfloat16), inner_sweeps FP32 sweeps of
- * A e = r from e = 0 with a zero ring, u <- u + e in FP64, until rel <=
- * rel_tol or max_sweeps.  The inner sweeps of all grids still refining run
- * as one batched persistent launch (opts->sweep selects its tuning; the
- * autotuner's table applies); a converged grid is left alone, so each
- * grid's result is bitwise that of rbgs_solve on it alone.  infos (HOST,
- * count entries, may be NULL) receives each grid's sweeps, outer steps,
- * norms and status.  Returns RBGS_OK when every grid converged, else the
- * first failing grid's status (RBGS_ENOCONV, RBGS_ENONFINITE).  Precision
- * F64 is RBGS_EUNSUPPORTED (sweep FP64 batches with a plan and check with
- * rbgs_residual).  Synchronises `stream`. */
+ * natural layout, HOST arrays of device pointers as above) is solved as
+ * rbgs_solve solves it alone, in one of two modes.
+ *   precision F64: the solve loop around Eq. (1)'s sweeps (the paper
+ *     fixes no stopping test; the norms are rbgs_residual's): the relative
+ *     residual, then check_every FP64 sweeps (inner_sweeps when check_every
+ *     is 0; the last round of a grid near max_sweeps takes the remainder),
+ *     until rel <= rel_tol or max_sweeps.  outer_iters is 0.
+ *   precision F32_IR or BF16RHS_IR (the mixed-precision refinement the
+ *     build adds to the paper's method): an FP64 residual, r rounded to
+ *     FP32 (or bfloat16), inner_sweeps FP32 sweeps of A e = r from e = 0
+ *     with a zero ring (check_every when inner_sweeps is 0), u <- u + e in
+ *     FP64, until rel <= rel_tol or max_sweeps.
+ * The sweeps of all grids still iterating run as one batched persistent
+ * launch per round (opts->sweep selects its tuning; the autotuner's table
+ * applies); a converged grid is left alone, so each grid's result is
+ * bitwise that of rbgs_solve on it alone.  Needs rel_tol > 0, omega = 1
+ * (batched sweeps are Gauss-Seidel; else RBGS_EUNSUPPORTED) and fallback
+ * = 0 (RBGS_EUNSUPPORTED).  infos (HOST, count entries, may be NULL)
+ * receives each grid's sweeps, outer steps, norms, status and precision.
+ * Returns RBGS_OK when every grid converged, else the first failing grid's
+ * status (RBGS_ENOCONV, RBGS_ENONFINITE).  The workspace
+ * (rbgs_batch_solve_workspace_size bytes, 256-byte aligned) serves both
+ * modes.  Synchronises `stream`. */
 size_t rbgs_batch_solve_workspace_size(int32_t count, const rbgs_grid *grids);
 int rbgs_solve_batched(int32_t count, const rbgs_grid *grids, double *const *u,
                        const double *const *f, const rbgs_solve_opts *opts,

@@ -828,7 +828,162 @@ int solve_batched_ir(int32_t count, const rbgs_grid* grids, double* const* u,
     if (e != hipSuccess) return bfail(RBGS_EHIP, std::string("unpack: ") + hipGetErrorString(e));
     int status = RBGS_OK;
     for (int g = 0; g < count; ++g) {
-        rbgs_solve_info info{done[g], outer[g], rel[g], ab[g], RBGS_OK};
+        rbgs_solve_info info{done[g], outer[g], rel[g], ab[g], RBGS_OK, o->precision};
+        if (!std::isfinite(rel[g]))
+            info.status = RBGS_ENONFINITE;
+        else if (!(rel[g] <= o->rel_tol))
+            info.status = RBGS_ENOCONV;
+        if (infos) infos[g] = info;
+        if (info.status != RBGS_OK && status == RBGS_OK) status = info.status;
+    }
+    if (status == RBGS_ENOCONV) g_batch_error = "tolerance not reached by every grid";
+    if (status == RBGS_ENONFINITE) g_batch_error = "a residual is not finite";
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// Batched FP64 solve: the single-grid FP64 solve loop (residual, then
+// check_every sweeps, until rel <= rel_tol or max_sweeps), with the sweeps
+// of every grid still iterating in one batched persistent launch.
+// ---------------------------------------------------------------------------
+
+// Workspace: the FP64 batch (per grid two ping-pong buffers of u and f,
+// split layout), then per grid the residual partial sums, then two norms
+// per grid.
+struct SolveLayoutF64 {
+    BatchLayout batch;
+    std::vector<size_t> part_off;
+    size_t sums = 0;
+    size_t total = 0;
+};
+
+SolveLayoutF64 solve_layout_f64(int count, const rbgs_grid* grids) {
+    SolveLayoutF64 L;
+    L.batch = batch_layout(count, grids, RBGS_F64);
+    size_t off = align256(L.batch.total);
+    L.part_off.resize(count);
+    for (int g = 0; g < count; ++g) {
+        L.part_off[g] = off;
+        off += align256(size_t(residual_partial_slots(grids[g].n, L.batch.pitch[g], 8)) * 2 *
+                        sizeof(double));
+    }
+    L.sums = off;
+    off += align256(size_t(count) * 2 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+int solve_batched_f64(int32_t count, const rbgs_grid* grids, double* const* u,
+                      const double* const* f, const rbgs_solve_opts* o, rbgs_solve_info* infos,
+                      char* ws, hipStream_t s) {
+    const SolveLayoutF64 L = solve_layout_f64(count, grids);
+    const int check = o->check_every > 0 ? o->check_every : o->inner_sweeps;
+    double* sums = reinterpret_cast<double*>(ws + L.sums);
+    // colour array k of grid g in the order build_setup lays them out:
+    // red, black of buffer 0, red, black of buffer 1, f red, f black
+    auto arr = [&](int g, int k) {
+        const size_t colour = align256(size_t(grids[g].n + 2) * size_t(L.batch.pitch[g]) * 8);
+        return reinterpret_cast<double*>(ws + L.batch.grid_off[g] + size_t(k) * colour);
+    };
+    // u and f of every grid into the split layout (u into both buffers, so
+    // both hold the Dirichlet ring)
+    {
+        const BatchSetup su = build_setup<double>(count, grids, reinterpret_cast<void* const*>(u),
+                                                  reinterpret_cast<const void* const*>(f), L.batch,
+                                                  ws, 1, 0, 0, -1);
+        int rc = upload_setup<double>(su, L.batch, ws, count, s);
+        if (rc) return rc;
+        hipError_t e = enqueue_batch<double>(su, L.batch, ws, count, nullptr, true, false, s);
+        if (e != hipSuccess) return bfail(RBGS_EHIP, std::string("pack: ") + hipGetErrorString(e));
+    }
+    // buffer holding each grid's current iterate
+    std::vector<int> cur(count, 0), done(count, 0);
+    std::vector<double> rel(count, 0.0), ab(count, 0.0), host(2 * size_t(count));
+    auto residuals = [&](const std::vector<int>& which) -> int {
+        hipError_t r = hipSuccess;
+        for (int g : which) {
+            const int b = cur[g];
+            r = launch_residual_split<double>(arr(g, 2 * b), arr(g, 2 * b + 1), arr(g, 4), arr(g, 5),
+                                              grids[g].n, L.batch.pitch[g],
+                                              1.0 / (grids[g].h * grids[g].h),
+                                              reinterpret_cast<double*>(ws + L.part_off[g]),
+                                              sums + 2 * g, nullptr, nullptr, 0, 0, s);
+            if (r != hipSuccess) break;
+        }
+        if (r == hipSuccess)
+            r = hipMemcpyAsync(host.data(), sums, host.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, s);
+        if (r == hipSuccess) r = hipStreamSynchronize(s);
+        if (r != hipSuccess) return bfail(RBGS_EHIP, std::string("residual: ") + hipGetErrorString(r));
+        for (int g : which) {
+            const double rn = std::sqrt(host[2 * g]), bn = std::sqrt(host[2 * g + 1]);
+            ab[g] = rn;
+            rel[g] = bn > 0.0 ? rn / bn : rn;
+        }
+        return RBGS_OK;
+    };
+    std::vector<int> all(count);
+    std::iota(all.begin(), all.end(), 0);
+    int rc = residuals(all);
+    if (rc) return rc;
+    hipError_t e = hipSuccess;
+    for (;;) {
+        // grids still iterating, grouped by this round's sweep count (the
+        // last round of a grid near max_sweeps takes the remainder)
+        std::map<int, std::vector<int>> by_k;
+        for (int g = 0; g < count; ++g)
+            if (!(rel[g] <= o->rel_tol) && done[g] < o->max_sweeps && std::isfinite(rel[g]))
+                by_k[std::min(check, o->max_sweeps - done[g])].push_back(g);
+        if (by_k.empty()) break;
+        std::vector<int> stepped;
+        for (const auto& kv : by_k) {
+            const int k = kv.first;
+            const std::vector<int>& act = kv.second;
+            const int na = int(act.size());
+            BatchLayout sub = L.batch;
+            sub.grid_off.assign(na, 0);
+            sub.pitch.assign(na, 0);
+            std::vector<rbgs_grid> sg(na);
+            std::vector<void*> nu(na, nullptr);
+            std::vector<const void*> nf(na, nullptr);
+            for (int a = 0; a < na; ++a) {
+                sub.grid_off[a] = L.batch.grid_off[act[a]];
+                sub.pitch[a] = L.batch.pitch[act[a]];
+                sg[a] = grids[act[a]];
+            }
+            int fuse = 0, rows = 0, lds = 0;
+            choose_params(na, sg.data(), RBGS_F64, &o->sweep, &fuse, &rows, &lds);
+            BatchSetup su =
+                build_setup<double>(na, sg.data(), nu.data(), nf.data(), sub, ws, fuse, rows, k, lds);
+            // a grid whose iterate sits in buffer 1 runs with its buffers
+            // swapped, so that every launch starts from "buffer 0"
+            GridDesc<double>* gd = reinterpret_cast<GridDesc<double>*>(su.gdesc.data());
+            for (int a = 0; a < na; ++a)
+                if (cur[act[a]]) {
+                    std::swap(gd[a].red[0], gd[a].red[1]);
+                    std::swap(gd[a].black[0], gd[a].black[1]);
+                }
+            if ((rc = upload_setup<double>(su, sub, ws, na, s))) return rc;
+            e = enqueue_batch<double>(su, sub, ws, na, &o->sweep, false, false, s);
+            if (e != hipSuccess) return bfail(RBGS_EHIP, std::string("sweeps: ") + hipGetErrorString(e));
+            if ((rc = read_error_word(sub, ws, s))) return rc;
+            const int out = (su.passes + (su.rem > 0 ? 1 : 0)) & 1;
+            for (int g : act) {
+                cur[g] ^= out;
+                done[g] += k;
+                stepped.push_back(g);
+            }
+        }
+        if ((rc = residuals(stepped))) return rc;
+    }
+    for (int g = 0; g < count && e == hipSuccess; ++g)
+        e = launch_unpack(u[g], grids[g].ld, arr(g, 2 * cur[g]), arr(g, 2 * cur[g] + 1), grids[g].n,
+                          L.batch.pitch[g], 8, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bfail(RBGS_EHIP, std::string("unpack: ") + hipGetErrorString(e));
+    int status = RBGS_OK;
+    for (int g = 0; g < count; ++g) {
+        rbgs_solve_info info{done[g], 0, rel[g], ab[g], RBGS_OK, RBGS_PREC_F64};
         if (!std::isfinite(rel[g]))
             info.status = RBGS_ENONFINITE;
         else if (!(rel[g] <= o->rel_tol))
@@ -1035,7 +1190,7 @@ int rbgs_autotune_batched(int32_t count, const rbgs_grid* grids, rbgs_dtype dt, 
 
 size_t rbgs_batch_solve_workspace_size(int32_t count, const rbgs_grid* grids) {
     if (rbgs_batch_workspace_size(count, grids, RBGS_F32) == 0) return 0;
-    return solve_layout(count, grids).total;
+    return std::max(solve_layout(count, grids).total, solve_layout_f64(count, grids).total);
 }
 
 int rbgs_solve_batched(int32_t count, const rbgs_grid* grids, double* const* u,
@@ -1045,20 +1200,26 @@ int rbgs_solve_batched(int32_t count, const rbgs_grid* grids, double* const* u,
     if (!opts) return bfail(RBGS_EINVAL, "opts is NULL");
     if (opts->fallback != 0)
         return bfail(RBGS_EUNSUPPORTED, "the precision fallback is for single-grid solves");
-    if (opts->precision != RBGS_PREC_F32_IR && opts->precision != RBGS_PREC_BF16RHS_IR)
-        return bfail(RBGS_EUNSUPPORTED,
-                     "batched solves refine in FP64 around FP32 sweeps: precision must be "
-                     "F32_IR or BF16RHS_IR");
+    if (opts->precision != RBGS_PREC_F64 && opts->precision != RBGS_PREC_F32_IR &&
+        opts->precision != RBGS_PREC_BF16RHS_IR)
+        return bfail(RBGS_EINVAL, "unknown precision");
     if (!(opts->rel_tol > 0.0) || opts->max_sweeps < 0)
         return bfail(RBGS_EINVAL, "need rel_tol > 0 and max_sweeps >= 0");
-    if (opts->inner_sweeps < 0 || (opts->inner_sweeps == 0 && opts->check_every < 1))
+    if (opts->inner_sweeps < 0 || opts->check_every < 0 ||
+        (opts->inner_sweeps == 0 && opts->check_every == 0))
         return bfail(RBGS_EINVAL, "need inner_sweeps >= 1 (or check_every >= 1)");
+    if (opts->omega != 1.0)
+        return bfail(RBGS_EUNSUPPORTED, "batched sweeps are Gauss-Seidel: omega must be 1");
     int rc = validate_batch(count, grids, RBGS_F64, reinterpret_cast<void* const*>(u),
                             reinterpret_cast<const void* const*>(f), 0, &opts->sweep);
     if (rc) return rc;
-    if ((rc = check_ws(workspace, workspace_bytes, solve_layout(count, grids).total))) return rc;
-    return solve_batched_ir(count, grids, u, f, opts, infos, static_cast<char*>(workspace),
-                            static_cast<hipStream_t>(stream));
+    if ((rc = check_ws(workspace, workspace_bytes, rbgs_batch_solve_workspace_size(count, grids))))
+        return rc;
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return opts->precision == RBGS_PREC_F64
+               ? solve_batched_f64(count, grids, u, f, opts, infos, ws, s)
+               : solve_batched_ir(count, grids, u, f, opts, infos, ws, s);
 }
 
 }  // extern "C"

@@ -711,9 +711,11 @@ class BatchPlan:
 
 def rbgs_solve_batched(us, fs, max_sweeps, rel_tol, inner_sweeps, precision="f32_ir", hs=None,
                        workspace=None, stream=None, **tuning):
-    """Refine every FP64 grid of the batch to rel_tol (FP32 inner sweeps of
-    all unconverged grids in one batched launch per outer step); returns one
-    dict per grid like rbgs_solve's.  Synchronises."""
+    """Solve every FP64 grid of the batch to rel_tol: precision "f64" sweeps
+    in FP64 and checks the residual every inner_sweeps sweeps; "f32_ir" and
+    "bf16rhs_ir" refine in FP64 around inner_sweeps FP32 sweeps.  The sweeps
+    of all unconverged grids run in one batched launch per round; returns
+    one dict per grid like rbgs_solve's.  Synchronises."""
     b = _Batch(us, fs, hs)
     if b.code != F64:
         raise RbgsError(EINVAL, "batched solves take FP64 u and f")
@@ -735,7 +737,8 @@ def rbgs_solve_batched(us, fs, max_sweeps, rel_tol, inner_sweeps, precision="f32
     if rc not in (OK, ENOCONV, ENONFINITE):
         _bcheck(rc)
     return [{"sweeps": i.sweeps, "outer_iters": i.outer_iters, "rel_residual": i.rel_residual,
-             "abs_residual": i.abs_residual, "status": i.status} for i in infos]
+             "abs_residual": i.abs_residual, "status": i.status, "precision": i.precision}
+            for i in infos]
 
 
 def rbgs_autotune_batched(us, fs, hs=None, workspace=None, stream=None):

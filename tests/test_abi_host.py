@@ -206,18 +206,27 @@ def test_transfer_validation(lib, case):
             assert "NULL" in lib.rbgs_last_error()
 
 
-@pytest.mark.parametrize("bad", ["null_opts", "f64", "tol", "inner", "count", "null_arrays", "ws"])
+@pytest.mark.parametrize("bad", ["null_opts", "prec", "omega", "omega0", "tol", "inner",
+                                 "check", "count", "null_arrays", "ws", "ws_f64"])
 def test_solve_batched_validation_before_device_work(lib, bad):
     grids = (lib.rbgs_grid * 2)(_grid(lib, 15), _grid(lib, 31))
     ptrs = (ctypes.c_void_p * 2)(1 << 20, 2 << 20)  # never dereferenced: checks come first
     o = lib.rbgs_solve_opts()
     o.max_sweeps, o.rel_tol, o.check_every, o.inner_sweeps = 100, 1e-8, 10, 10
-    o.precision = lib.PREC_F32_IR
+    o.precision, o.omega = lib.PREC_F32_IR, 1.0
     count, opts, u, f, expect = 2, ctypes.byref(o), ptrs, ptrs, lib.EINVAL
     if bad == "null_opts":
         opts = None
-    elif bad == "f64":
-        o.precision, expect = lib.PREC_F64, lib.EUNSUPPORTED
+    elif bad == "prec":
+        o.precision = 3
+    elif bad == "omega":  # batched sweeps are Gauss-Seidel
+        o.omega, expect = 1.5, lib.EUNSUPPORTED
+    elif bad == "omega0":  # 0 asks for the optimal SOR factor
+        o.omega, expect = 0.0, lib.EUNSUPPORTED
+    elif bad == "check":
+        o.check_every = -1
+    elif bad == "ws_f64":  # FP64 solves take the same workspace
+        o.precision, expect = lib.PREC_F64, lib.EWORKSPACE
     elif bad == "tol":
         o.rel_tol = 0.0
     elif bad == "inner":

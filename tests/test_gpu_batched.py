@@ -224,6 +224,53 @@ def test_solve_batched_matches_oracle(oracle, bf16):
     assert infos[5]["outer_iters"] == 0
 
 
+@pytest.mark.parametrize("check", [300, 301])
+@pytest.mark.parametrize("lds", [0, 63])
+def test_solve_batched_f64_matches_oracle(oracle, check, lds):
+    """Batched FP64 solve: each grid follows the oracle's solve loop alone,
+    bit for bit, with the same sweep count and residual.  check = 300 at the
+    default depth (4 for these sizes) gives an odd pass count, so a grid's
+    iterate alternates between the ping-pong buffers from round to round;
+    lds = 63 sweeps the grids up to 63 in LDS instead of as tiles."""
+    sizes = [63, 31, 127, 63, 15, 7, 1]
+    tol = 1e-8
+    say(f"batched FP64 solve check_every={check} lds_max_n={lds}")
+    fs = [W.fourier_rhs(n, seed=g + 1, count=8, kmax=8) for g, n in enumerate(sizes)]
+    fs[5] = np.zeros_like(fs[5])
+    us = [W.random_ring(n, seed=50 + g) if g != 5 else W.zeros(n) for g, n in enumerate(sizes)]
+    ut = to_dev(us)
+    ft = to_dev(fs)
+    infos = rb.rbgs_solve_batched(ut, ft, 200_000, tol, check, precision="f64", lds_max_n=lds)
+    for g, n in enumerate(sizes):
+        ref = us[g].copy()
+        rc, done, rel = oracle.solve(ref, fs[g], W.spacing(n), 200_000, tol, check)
+        assert rc == 0 and infos[g]["status"] == 0, (g, infos[g], rc)
+        assert infos[g]["sweeps"] == done, (g, infos[g], done)
+        assert infos[g]["outer_iters"] == 0 and infos[g]["precision"] == rb.rbgs.PREC_F64
+        assert np.array_equal(ut[g].cpu().numpy(), ref), f"grid {g} (n={n})"
+        assert infos[g]["rel_residual"] == pytest.approx(rel, rel=1e-12, abs=1e-300)
+    assert infos[5]["sweeps"] == 0  # f = 0 and u = 0: converged before any sweep
+
+
+def test_solve_batched_f64_sweep_cap(oracle):
+    """max_sweeps not a multiple of check_every: the last round takes the
+    remainder and every grid ends at max_sweeps with RBGS_ENOCONV, each
+    iterate the oracle's."""
+    sizes = [127, 63, 255]
+    say("batched FP64 solve, sweep cap")
+    fs = [W.normal_rhs(n, seed=21 + g) for g, n in enumerate(sizes)]
+    ut = to_dev([W.zeros(n) for n in sizes])
+    ft = to_dev(fs)
+    infos = rb.rbgs_solve_batched(ut, ft, 1000, 1e-14, 300, precision="f64")
+    for g, n in enumerate(sizes):
+        ref = W.zeros(n)
+        rc, done, rel = oracle.solve(ref, fs[g], W.spacing(n), 1000, 1e-14, 300)
+        assert done == 1000 == infos[g]["sweeps"]
+        assert infos[g]["status"] == rb.rbgs.ENOCONV
+        assert np.array_equal(ut[g].cpu().numpy(), ref), f"grid {g} (n={n})"
+        assert infos[g]["rel_residual"] == pytest.approx(rel, rel=1e-12)
+
+
 def test_solve_batched_sweep_cap():
     """max_sweeps not a multiple of inner_sweeps: the last step of a grid takes
     the remaining sweeps (the single-grid solve's rule), and a grid that does
