@@ -463,11 +463,15 @@ def pass_overlap(torch, rb, W, n=8191, sweeps=200):
             "passes_in_flight_max": int(np.max(in_flight))}
 
 
-def rb3_throughput(torch, rb, n=767, sweeps=40):
+def rb3_throughput(torch, rb, n=767, sweeps=40, tol_sizes=(63, 127), tol=1e-8):
     """Red-black Gauss-Seidel in 3D (the higher-dimension extension): n^3
     FP64 with f ~ U[-1, 1) drawn on the device (seeded), time per sweep from
     the difference of a (sweeps + 1)-sweep and a 1-sweep call, GLUP/s and
-    model bytes (24 B per point per sweep, as in 2D)."""
+    model bytes (24 B per point per sweep, as in 2D), for the plain kernel
+    (one launch per half-sweep) and the flag-driven form (one launch, a
+    counter per block).  Then, per size in tol_sizes, the solve from u = 0 to
+    rel <= tol with each (residual every 500 sweeps; the plain solve's
+    rounds are graph-captured)."""
     h = 1.0 / (n + 1)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(0)
@@ -478,27 +482,58 @@ def rb3_throughput(torch, rb, n=767, sweeps=40):
     ws = torch.empty(rb.rbgs_rb3_workspace_size(rb.make_grid3(f, h)), dtype=torch.uint8,
                      device="cuda")
 
-    def timed(k):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rb.rbgs_rb3_sweep(u, f, k, h=h, workspace=ws)
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0
+    def per_sweep_of(kernel):
+        def timed(k):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rb.rbgs_rb3_sweep(u, f, k, h=h, workspace=ws, kernel=kernel)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
 
-    timed(2)
-    one = min(timed(1) for _ in range(3))
-    many = min(timed(sweeps + 1) for _ in range(2))
-    per_sweep = (many - one) / sweeps
-    glups = n ** 3 / per_sweep / 1e9
-    out = {"workload": f"{n}^3 FP64, f~U[-1,1) (device generator, seed 0), {sweeps} sweeps",
-           "ms_per_sweep": round(per_sweep * 1e3, 4), "GLUP/s": round(glups, 2),
-           "model_bytes_per_lup": BYTES_PER_LUP["f64"],
-           "model_GBs": round(glups * BYTES_PER_LUP["f64"], 1),
-           "frac_of_8TBs": round(glups * BYTES_PER_LUP["f64"] / HBM_PEAK_GBS, 4)}
-    log(f"3D red-black {n}^3: {per_sweep * 1e3:.3f} ms/sweep, {glups:.1f} GLUP/s, "
-        f"{glups * BYTES_PER_LUP['f64']:.0f} GB/s model")
+        timed(2)
+        one = min(timed(1) for _ in range(3))
+        many = min(timed(sweeps + 1) for _ in range(2))
+        return (many - one) / sweeps
+
+    def figures(per_sweep):
+        glups = n ** 3 / per_sweep / 1e9
+        return {"ms_per_sweep": round(per_sweep * 1e3, 4), "GLUP/s": round(glups, 2),
+                "model_bytes_per_lup": BYTES_PER_LUP["f64"],
+                "model_GBs": round(glups * BYTES_PER_LUP["f64"], 1),
+                "frac_of_8TBs": round(glups * BYTES_PER_LUP["f64"] / HBM_PEAK_GBS, 4)}
+
+    plain = per_sweep_of("plain")
+    flags = per_sweep_of("resident")
+    out = {"workload": f"{n}^3 FP64, f~U[-1,1) (device generator, seed 0), {sweeps} sweeps"}
+    out.update(figures(plain))
+    out["flag_driven"] = dict(figures(flags), speedup_vs_plain=round(plain / flags, 3))
+    log(f"3D red-black {n}^3: plain {plain * 1e3:.3f} ms/sweep ({n ** 3 / plain / 1e9:.1f} GLUP/s), "
+        f"flag-driven {flags * 1e3:.3f} ms/sweep ({n ** 3 / flags / 1e9:.1f} GLUP/s)")
     del u, f, ws
     torch.cuda.empty_cache()
+    for m in tol_sizes:
+        hm = 1.0 / (m + 1)
+        gen.manual_seed(1)
+        fm = torch.zeros((m + 2,) * 3, dtype=torch.float64, device="cuda")
+        fm[1:-1, 1:-1, 1:-1] = torch.rand((m, m, m), dtype=torch.float64, device="cuda",
+                                          generator=gen) * 2.0 - 1.0
+        row = {"problem": f"{m}^3 FP64, f~U[-1,1) (device generator, seed 1), u0=0, "
+                          f"rel<={tol:g}, residual every 500 sweeps"}
+        for kernel in ("plain", "resident"):
+            um = torch.zeros_like(fm)
+            rb.rbgs_rb3_solve(um, fm, 1000, tol, check_every=500, h=hm, kernel=kernel)  # warm-up
+            um.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = rb.rbgs_rb3_solve(um, fm, 2_000_000, tol, check_every=500, h=hm, kernel=kernel)
+            torch.cuda.synchronize()
+            row["plain" if kernel == "plain" else "flag_driven"] = {
+                "seconds": round(time.perf_counter() - t0, 4), "sweeps": info["sweeps"],
+                "rel_residual": info["rel_residual"], "status": info["status"]}
+        row["speedup_flag_driven_vs_plain"] = round(row["plain"]["seconds"] /
+                                                    row["flag_driven"]["seconds"], 3)
+        out[f"time_to_{tol:g}_{m}"] = row
+        log(f"3D time to {tol:g} at {m}^3: {row}")
     return out
 
 

@@ -632,7 +632,8 @@ int rbgs_mc9_solve(const rbgs_grid *g, double *u, const double *f,
 /* Workspace bytes (split u and f, reduction space); 0 for an invalid grid. */
 size_t rbgs_rb3_workspace_size(const rbgs_grid *g);
 
-/* nsweeps sweeps of u in place.  Asynchronous on `stream`. */
+/* nsweeps sweeps of u in place, one launch per half-sweep.  Asynchronous
+ * on `stream`. */
 int rbgs_rb3_sweep(const rbgs_grid *g, double *u, const double *f,
                    int32_t nsweeps, void *workspace, size_t workspace_bytes,
                    void *stream);
@@ -649,6 +650,46 @@ int rbgs_rb3_solve(const rbgs_grid *g, double *u, const double *f,
                    int32_t max_sweeps, double rel_tol, int32_t check_every,
                    rbgs_solve_info *info, void *workspace,
                    size_t workspace_bytes, void *stream);
+
+/* Kernel choice for the 3D calls (zero-initialise; NULL = all zero).
+ * kernel: RBGS_KERNEL_AUTO or RBGS_KERNEL_PLAIN = one launch per half-sweep
+ * (a device-wide barrier between colours, Algorithm 1's structure);
+ * RBGS_KERNEL_RESIDENT = the flag-driven form, the dependency rule of
+ * Algorithm 2 (Section 2.3) carried to 3D: all half-sweeps of a call in one
+ * cooperative launch of co-resident one-wave workgroups, the interior cut
+ * into blocks whose half-sweep h waits only until the block and its six
+ * face neighbours have completed h half-sweeps (a counter per block), so
+ * colours and sweeps overlap instead of waiting at barriers; same result,
+ * bit for bit.  RBGS_KERNEL_BLOCKED: RBGS_EUNSUPPORTED (no temporally
+ * blocked 3D kernel).  The debug fields apply to RESIDENT only. */
+typedef struct {
+    int32_t kernel;
+    int32_t debug_delay;       /* > 0: pseudo-random stall of up to debug_delay
+                                  sleeps per block and half-sweep (schedule
+                                  stress); results must not change            */
+    int32_t debug_spin_limit;  /* > 0: polls per dependency wait before the
+                                  call fails with RBGS_ETIMEOUT; 0 = 2^22      */
+    int32_t debug_stall_block; /* b + 1 > 0: block b never publishes its
+                                  progress, so the waits on it expire and the
+                                  call returns RBGS_ETIMEOUT (watchdog test;
+                                  every wave still exits); at most the block
+                                  count, else RBGS_EINVAL                     */
+} rbgs_rb3_opts;
+
+/* rbgs_rb3_sweep with a kernel choice.  With RESIDENT the call reads the
+ * kernel's error word at the end and so synchronises `stream`; on
+ * RBGS_ETIMEOUT u holds a partly swept iterate.  nsweeps <= 2^29. */
+int rbgs_rb3_sweep_ex(const rbgs_grid *g, double *u, const double *f,
+                      int32_t nsweeps, const rbgs_rb3_opts *opts,
+                      void *workspace, size_t workspace_bytes, void *stream);
+
+/* rbgs_rb3_solve with a kernel choice.  RESIDENT runs each group of
+ * check_every sweeps as one launch (host-driven rounds, no graph); same
+ * sweeps, residuals and result as the plain kernel. */
+int rbgs_rb3_solve_ex(const rbgs_grid *g, double *u, const double *f,
+                      int32_t max_sweeps, double rel_tol, int32_t check_every,
+                      const rbgs_rb3_opts *opts, rbgs_solve_info *info,
+                      void *workspace, size_t workspace_bytes, void *stream);
 
 /* Device-memory bandwidth probe: the copy (kind 0: b = a) and triad
  * (kind 1: a = b + s*c) kernels of the STREAM benchmark, which the paper

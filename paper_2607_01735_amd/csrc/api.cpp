@@ -641,6 +641,8 @@ struct Mc9Workspace {
     double* f[4] = {nullptr, nullptr, nullptr, nullptr};
     double* partials = nullptr;
     double* sums = nullptr;  // sum r^2, sum b^2; the graph rounds' state at +64 bytes
+    int* state = nullptr;    // flag-driven form: error word, ticket at +32 ints, block
+                             // counters from +64 ints
     size_t total = 0;
 };
 
@@ -715,6 +717,8 @@ struct Rb3Workspace {
     double* f_black = nullptr;
     double* partials = nullptr;
     double* sums = nullptr;  // sum r^2, sum b^2; the graph rounds' state at +64 bytes
+    int* state = nullptr;    // flag-driven form: error word, ticket at +32 ints, block
+                             // counters from +64 ints
     size_t total = 0;
 };
 
@@ -746,6 +750,7 @@ Rb3Workspace plan_rb3(const rbgs_grid* g, char* base) {
     w.f_black = take(colour);
     w.partials = take(size_t(rb3_residual_blocks(g->n)) * 2 * sizeof(double));
     w.sums = take(256);
+    w.state = reinterpret_cast<int*>(take(256 + size_t(kRb3MaxBlocks) * sizeof(int)));
     w.total = off;
     return w;
 }
@@ -779,6 +784,62 @@ int rb3_sweeps(const rbgs_grid* g, const Rb3Workspace& w, int nsweeps, hipStream
         HIP_TRY(launch_rb3_half(w.u_black, w.u_red, w.f_black, g->n, w.pitch, h2, 1, stop, s),
                 "black half-sweep");
     }
+    return RBGS_OK;
+}
+
+// Options of the 3D calls: plain (one launch per half-sweep) or the
+// flag-driven form (kernel RESIDENT).
+int rb3_check_opts(const rbgs_rb3_opts* o) {
+    if (!o) return RBGS_OK;
+    if (o->kernel == RBGS_KERNEL_BLOCKED)
+        return fail(RBGS_EUNSUPPORTED, "3D sweeps have no temporally blocked kernel: use PLAIN or "
+                                       "RESIDENT (the flag-driven form)");
+    if (o->kernel < RBGS_KERNEL_AUTO || o->kernel > RBGS_KERNEL_RESIDENT)
+        return fail(RBGS_EINVAL, "unknown kernel");
+    if (o->debug_delay < 0 || o->debug_spin_limit < 0 || o->debug_stall_block < 0)
+        return fail(RBGS_EINVAL, "debug options must be >= 0");
+    return RBGS_OK;
+}
+
+bool rb3_flag_driven(const rbgs_rb3_opts* o) { return o && o->kernel == RBGS_KERNEL_RESIDENT; }
+
+// nsweeps sweeps as flag-driven launches (the caller cleared the error
+// word once for the call): one launch unless the ticket count would leave
+// the int range, each starting from zeroed ticket and block counters.
+int rb3_sweeps_flags(const rbgs_grid* g, const Rb3Workspace& w, int nsweeps,
+                     const rbgs_rb3_opts* o, int capacity, hipStream_t s) {
+    const int nb = rb3_flags_blocks(g->n, capacity);
+    const int per_launch = int(((int64_t(1) << 30) / nb) / 2);  // sweeps, so levels x nb < 2^31
+    for (int done = 0; done < nsweeps;) {
+        const int k = std::min(nsweeps - done, per_launch);
+        HIP_TRY(launch_zero(w.state + 32, size_t(32 + nb) * sizeof(int), s),
+                "clear ticket and block counters");
+        HIP_TRY(launch_rb3_flags(w.u_red, w.u_black, w.f_red, w.f_black, g->n, w.pitch,
+                                 g->h * g->h, 2 * k, capacity, w.state + 32, w.state + 64,
+                                 w.state, o->debug_spin_limit > 0 ? o->debug_spin_limit : (1 << 22),
+                                 o->debug_delay, o->debug_stall_block, nullptr, s),
+                "3D flag-driven sweeps");
+        done += k;
+    }
+    return RBGS_OK;
+}
+
+int rb3_flags_error(const Rb3Workspace& w, hipStream_t s) {
+    int err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, w.state, sizeof err, hipMemcpyDeviceToHost, s), "read error word");
+    HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+    if (err) return fail(RBGS_ETIMEOUT, "a block dependency wait of the 3D flag-driven sweep "
+                                        "timed out");
+    return RBGS_OK;
+}
+
+int rb3_flags_setup(const rbgs_grid* g, const rbgs_rb3_opts* o, const Rb3Workspace& w,
+                    hipStream_t s, int* capacity) {
+    *capacity = rb3_flags_capacity();
+    if (*capacity < 64) return fail(RBGS_EHIP, "occupancy query for the 3D flag-driven kernel");
+    if (o->debug_stall_block > rb3_flags_blocks(g->n, *capacity))
+        return fail(RBGS_EINVAL, "debug_stall_block beyond the block count");
+    HIP_TRY(launch_zero(w.state, 256, s), "clear error word");
     return RBGS_OK;
 }
 
@@ -1527,16 +1588,30 @@ size_t rbgs_rb3_workspace_size(const rbgs_grid* g) {
 
 int rbgs_rb3_sweep(const rbgs_grid* g, double* u, const double* f, int32_t nsweeps,
                    void* workspace, size_t workspace_bytes, void* stream) {
-    if (nsweeps < 0) return fail(RBGS_EINVAL, "nsweeps must be >= 0");
-    Rb3Workspace w;
-    int rc = rb3_prepare(g, u, f, workspace, workspace_bytes, &w);
+    return rbgs_rb3_sweep_ex(g, u, f, nsweeps, nullptr, workspace, workspace_bytes, stream);
+}
+
+int rbgs_rb3_sweep_ex(const rbgs_grid* g, double* u, const double* f, int32_t nsweeps,
+                      const rbgs_rb3_opts* opts, void* workspace, size_t workspace_bytes,
+                      void* stream) {
+    if (nsweeps < 0 || nsweeps > (1 << 29)) return fail(RBGS_EINVAL, "nsweeps must be in [0, 2^29]");
+    int rc = rb3_check_opts(opts);
     if (rc) return rc;
+    Rb3Workspace w;
+    if ((rc = rb3_prepare(g, u, f, workspace, workspace_bytes, &w))) return rc;
     if (nsweeps == 0) return RBGS_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool flags = rb3_flag_driven(opts);
+    int capacity = 0;
+    if (flags && (rc = rb3_flags_setup(g, opts, w, s, &capacity))) return rc;
     if ((rc = rb3_pack_both(g, w, u, f, s))) return rc;
-    if ((rc = rb3_sweeps(g, w, nsweeps, s, nullptr))) return rc;
+    if (flags)
+        rc = rb3_sweeps_flags(g, w, nsweeps, opts, capacity, s);
+    else
+        rc = rb3_sweeps(g, w, nsweeps, s, nullptr);
+    if (rc) return rc;
     HIP_TRY(launch_rb3_unpack(u, g->ld, w.u_red, w.u_black, g->n, w.pitch, s), "unpack u");
-    return RBGS_OK;
+    return flags ? rb3_flags_error(w, s) : RBGS_OK;
 }
 
 int rbgs_rb3_residual(const rbgs_grid* g, const double* u, const double* f, double* abs_norm,
@@ -1555,20 +1630,41 @@ int rbgs_rb3_residual(const rbgs_grid* g, const double* u, const double* f, doub
 int rbgs_rb3_solve(const rbgs_grid* g, double* u, const double* f, int32_t max_sweeps,
                    double rel_tol, int32_t check_every, rbgs_solve_info* info, void* workspace,
                    size_t workspace_bytes, void* stream) {
+    return rbgs_rb3_solve_ex(g, u, f, max_sweeps, rel_tol, check_every, nullptr, info, workspace,
+                             workspace_bytes, stream);
+}
+
+int rbgs_rb3_solve_ex(const rbgs_grid* g, double* u, const double* f, int32_t max_sweeps,
+                      double rel_tol, int32_t check_every, const rbgs_rb3_opts* opts,
+                      rbgs_solve_info* info, void* workspace, size_t workspace_bytes,
+                      void* stream) {
     if (max_sweeps < 0) return fail(RBGS_EINVAL, "max_sweeps must be >= 0");
     if (check_every < 1) return fail(RBGS_EINVAL, "check_every must be >= 1");
     if (std::isnan(rel_tol)) return fail(RBGS_EINVAL, "rel_tol is NaN");
-    Rb3Workspace w;
-    int rc = rb3_prepare(g, u, f, workspace, workspace_bytes, &w);
+    int rc = rb3_check_opts(opts);
     if (rc) return rc;
+    const bool flags = rb3_flag_driven(opts);
+    if (flags && (max_sweeps > (1 << 29)))
+        return fail(RBGS_EINVAL, "the flag-driven form runs at most 2^29 sweeps per call");
+    Rb3Workspace w;
+    if ((rc = rb3_prepare(g, u, f, workspace, workspace_bytes, &w))) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    int capacity = 0;
+    if (flags && (rc = rb3_flags_setup(g, opts, w, s, &capacity))) return rc;
     if ((rc = rb3_pack_both(g, w, u, f, s))) return rc;
     Workspace v;
     v.sums = w.sums;
     double rel = 0.0, ab = 0.0;
     int32_t done = 0;
+    // k sweeps of whichever form was asked for; the flag-driven form checks
+    // its error word after each group (one launch per group of sweeps)
+    auto sweeps = [&](int k) -> int {
+        if (!flags) return rb3_sweeps(g, w, k, s, nullptr);
+        int r = rb3_sweeps_flags(g, w, k, opts, capacity, s);
+        return r ? r : rb3_flags_error(w, s);
+    };
     if (rel_tol <= 0.0) {
-        if ((rc = rb3_sweeps(g, w, max_sweeps, s, nullptr))) return rc;
+        if ((rc = sweeps(max_sweeps))) return rc;
         done = max_sweeps;
         if ((rc = rb3_residual_sums(g, w, s))) return rc;
         if ((rc = fetch_norms(v, s, &ab, &rel))) return rc;
@@ -1576,7 +1672,7 @@ int rbgs_rb3_solve(const rbgs_grid* g, double* u, const double* f, int32_t max_s
         if ((rc = rb3_residual_sums(g, w, s))) return rc;
         if ((rc = fetch_norms(v, s, &ab, &rel))) return rc;
         const int cap = max_sweeps / check_every;
-        if (!(rel <= rel_tol) && std::isfinite(rel) && cap > 0) {
+        if (!flags && !(rel <= rel_tol) && std::isfinite(rel) && cap > 0) {
             RoundBody body = [&](hipStream_t cs, const int* stop, void** es) -> int {
                 *es = nullptr;
                 int r = rb3_sweeps(g, w, check_every, cs, stop);
@@ -1595,7 +1691,7 @@ int rbgs_rb3_solve(const rbgs_grid* g, double* u, const double* f, int32_t max_s
         }
         while (!(rel <= rel_tol) && done < max_sweeps && std::isfinite(rel)) {
             const int32_t k = max_sweeps - done < check_every ? max_sweeps - done : check_every;
-            if ((rc = rb3_sweeps(g, w, k, s, nullptr))) return rc;
+            if ((rc = sweeps(k))) return rc;
             done += k;
             if ((rc = rb3_residual_sums(g, w, s))) return rc;
             if ((rc = fetch_norms(v, s, &ab, &rel))) return rc;

@@ -19,6 +19,10 @@
 // Update (each operation rounded once, no contraction):
 //   s = ((((u[i+1] + u[i-1]) + u[j+1]) + u[j-1]) + u[k+1]) + u[k-1]
 //   u = (s - (h h) f) / 6.
+#include <algorithm>
+#include <cmath>
+
+#include "rb3_flags.h"
 #include "rbgs_internal.h"
 
 namespace rbgs {
@@ -200,7 +204,77 @@ __global__ __launch_bounds__(kThreads) void k_rb3_reduce(const double* __restric
     }
 }
 
+// The flag-driven form (rb3_flags.h): one launch for every half-sweep.
+__global__ __launch_bounds__(rb3f::kLanes) void k_rb3_flags(rb3f::Args a) { rb3f::run(a); }
+
 }  // namespace
+
+int rb3_flags_capacity() {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(&k_rb3_flags), rb3f::kLanes, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const int64_t c = int64_t(cus) * per_cu;
+    return int(c < kRb3MaxBlocks ? c : kRb3MaxBlocks);
+}
+
+// Bound on the blocks per half-sweep.  Every item costs one ticket, and
+// tickets of the whole device go through one counter (about 40 ns each on
+// MI355X), while an item's time grows with its size; the two balance near
+// sqrt(n^3 / 10) items per half-sweep, capped at the waves the chip holds.
+int rb3_flags_target(int n, int capacity) {
+    const double items = std::sqrt(double(n) * double(n) * double(n) / 10.0);
+    return int(std::max(64.0, std::min(double(capacity), items)));
+}
+
+int rb3_flags_blocks(int n, int capacity) {
+    if (capacity < 64) return 0;
+    return rb3f::geometry(n, rb3_flags_target(n, capacity)).nblocks;
+}
+
+hipError_t launch_rb3_flags(double* red, double* black, const double* f_red,
+                            const double* f_black, int n, int64_t pitch, double h2, int levels,
+                            int capacity, int* ticket, int* progress, int* error, int spin_limit,
+                            int delay, int stall_block, const int* stop, hipStream_t s) {
+    if (capacity < 64) return hipErrorInvalidValue;
+    const rb3f::Geometry geo = rb3f::geometry(n, rb3_flags_target(n, capacity));
+    if (int64_t(levels) * geo.nblocks >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    rb3f::Args a;
+    a.red = red;
+    a.black = black;
+    a.f_red = f_red;
+    a.f_black = f_black;
+    a.n = n;
+    a.pitch = pitch;
+    a.h2 = h2;
+    a.qw = geo.qw;
+    a.rj = geo.rj;
+    a.rz = geo.rz;
+    a.qblocks = geo.qblocks;
+    a.jblocks = geo.jblocks;
+    a.zblocks = geo.zblocks;
+    a.nblocks = geo.nblocks;
+    a.levels = levels;
+    a.ticket = ticket;
+    a.progress = progress;
+    a.error = error;
+    a.spin_limit = spin_limit;
+    a.delay = delay;
+    a.stall_block = stall_block;
+    a.stop = stop;
+    // one wave per block: each takes the next level's item as it finishes
+    // one, and more waves would only wait
+    const int64_t items = int64_t(levels) * geo.nblocks;
+    int64_t waves = std::min<int64_t>(capacity, geo.nblocks);
+    if (waves > items) waves = items;
+    if (waves < 1) waves = 1;
+    hipLaunchKernelGGL(k_rb3_flags, dim3(unsigned(waves)), dim3(rb3f::kLanes), 0, s, a);
+    return hipGetLastError();
+}
 
 int rb3_residual_blocks(int n) {
     const int64_t rows = int64_t(n) * n;

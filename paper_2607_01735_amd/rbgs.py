@@ -127,6 +127,20 @@ _lib.rbgs_rb3_residual.restype = ctypes.c_int
 _lib.rbgs_rb3_solve.argtypes = [_P(rbgs_grid), _vp, _vp, ctypes.c_int32, ctypes.c_double,
                                 ctypes.c_int32, _P(rbgs_solve_info), _vp, ctypes.c_size_t, _vp]
 _lib.rbgs_rb3_solve.restype = ctypes.c_int
+
+
+class rbgs_rb3_opts(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("debug_delay", ctypes.c_int32),
+                ("debug_spin_limit", ctypes.c_int32), ("debug_stall_block", ctypes.c_int32)]
+
+
+_lib.rbgs_rb3_sweep_ex.argtypes = [_P(rbgs_grid), _vp, _vp, ctypes.c_int32, _P(rbgs_rb3_opts), _vp,
+                                   ctypes.c_size_t, _vp]
+_lib.rbgs_rb3_sweep_ex.restype = ctypes.c_int
+_lib.rbgs_rb3_solve_ex.argtypes = [_P(rbgs_grid), _vp, _vp, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.c_int32, _P(rbgs_rb3_opts), _P(rbgs_solve_info), _vp,
+                                   ctypes.c_size_t, _vp]
+_lib.rbgs_rb3_solve_ex.restype = ctypes.c_int
 _lib.rbgs_workspace_size.argtypes = [_P(rbgs_grid), ctypes.c_int, _P(rbgs_solve_opts)]
 _lib.rbgs_workspace_size.restype = ctypes.c_size_t
 _lib.rbgs_sweep.argtypes = [_P(rbgs_grid), ctypes.c_int, _vp, _vp, ctypes.c_int32,
@@ -185,6 +199,7 @@ EXPORTED = ("rbgs_workspace_size", "rbgs_sweep", "rbgs_residual", "rbgs_residual
             "rbgs_solve_batched", "rbgs_mg_workspace_size", "rbgs_mg_solve",
             "rbgs_mc9_workspace_size", "rbgs_mc9_sweep", "rbgs_mc9_residual", "rbgs_mc9_solve",
             "rbgs_rb3_workspace_size", "rbgs_rb3_sweep", "rbgs_rb3_residual", "rbgs_rb3_solve",
+            "rbgs_rb3_sweep_ex", "rbgs_rb3_solve_ex",
             "rbgs_split_pitch", "rbgs_pack", "rbgs_unpack", "rbgs_sweep_split")
 
 
@@ -496,12 +511,23 @@ def rbgs_rb3_workspace_size(grid):
     return int(_lib.rbgs_rb3_workspace_size(ctypes.byref(grid)))
 
 
-def rbgs_rb3_sweep(u, f, nsweeps, h=None, workspace=None, stream=None):
-    """nsweeps 3D red-black sweeps (7-point Laplacian), in place (FP64)."""
+def _rb3_opts(kernel="plain", debug_delay=0, debug_spin_limit=0, debug_stall_block=0):
+    o = rbgs_rb3_opts()
+    o.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    o.debug_delay, o.debug_spin_limit = int(debug_delay), int(debug_spin_limit)
+    o.debug_stall_block = int(debug_stall_block)
+    return o
+
+
+def rbgs_rb3_sweep(u, f, nsweeps, h=None, workspace=None, stream=None, kernel="plain", **debug):
+    """nsweeps 3D red-black sweeps (7-point Laplacian), in place (FP64).
+    kernel "plain": one launch per half-sweep; "resident": the flag-driven
+    form (one launch, per-block progress counters; synchronises)."""
     grid, ws = _rb3_args(u, f, h, workspace)
-    _check(_lib.rbgs_rb3_sweep(ctypes.byref(grid), _vp(u.data_ptr()), _vp(f.data_ptr()),
-                               int(nsweeps), _vp(ws.data_ptr()), ws.numel(),
-                               _stream_ptr(stream, u.device)))
+    o = _rb3_opts(kernel, **debug)
+    _check(_lib.rbgs_rb3_sweep_ex(ctypes.byref(grid), _vp(u.data_ptr()), _vp(f.data_ptr()),
+                                  int(nsweeps), ctypes.byref(o), _vp(ws.data_ptr()), ws.numel(),
+                                  _stream_ptr(stream, u.device)))
 
 
 def rbgs_rb3_residual(u, f, h=None, workspace=None, stream=None):
@@ -515,14 +541,16 @@ def rbgs_rb3_residual(u, f, h=None, workspace=None, stream=None):
 
 
 def rbgs_rb3_solve(u, f, max_sweeps, rel_tol, check_every=100, h=None, workspace=None,
-                   stream=None, raise_on_noconv=False):
+                   stream=None, raise_on_noconv=False, kernel="plain", **debug):
     """3D red-black sweeps until rel <= rel_tol; returns a dict with sweeps,
-    rel_residual, abs_residual and status."""
+    rel_residual, abs_residual and status.  kernel as in rbgs_rb3_sweep."""
     grid, ws = _rb3_args(u, f, h, workspace)
     info = rbgs_solve_info()
-    rc = _lib.rbgs_rb3_solve(ctypes.byref(grid), _vp(u.data_ptr()), _vp(f.data_ptr()),
-                             int(max_sweeps), float(rel_tol), int(check_every), ctypes.byref(info),
-                             _vp(ws.data_ptr()), ws.numel(), _stream_ptr(stream, u.device))
+    o = _rb3_opts(kernel, **debug)
+    rc = _lib.rbgs_rb3_solve_ex(ctypes.byref(grid), _vp(u.data_ptr()), _vp(f.data_ptr()),
+                                int(max_sweeps), float(rel_tol), int(check_every), ctypes.byref(o),
+                                ctypes.byref(info), _vp(ws.data_ptr()), ws.numel(),
+                                _stream_ptr(stream, u.device))
     _check(rc, allow=(OK,) if raise_on_noconv else (OK, ENOCONV, ENONFINITE))
     return {"sweeps": info.sweeps, "rel_residual": info.rel_residual,
             "abs_residual": info.abs_residual, "status": info.status}

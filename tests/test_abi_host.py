@@ -336,6 +336,41 @@ def test_rb3_workspace_and_validation(lib):
                                  None) == lib.EINVAL
 
 
+@pytest.mark.parametrize("case", ["blocked", "unknown", "delay", "spin", "stall", "sweeps",
+                                  "ws", "solve_blocked", "solve_sweeps"])
+def test_rb3_kernel_options_validate_before_device_work(lib, case):
+    """The 3D calls' kernel choice: PLAIN/AUTO or RESIDENT (the flag-driven
+    form); BLOCKED is unsupported; debug fields must be >= 0."""
+    g = _grid(lib, 63)
+    o = lib.rbgs_rb3_opts()
+    o.kernel = lib.KERNEL_RESIDENT
+    nsweeps, expect = 4, lib.EINVAL
+    if case in ("blocked", "solve_blocked"):
+        o.kernel, expect = lib.KERNEL_BLOCKED, lib.EUNSUPPORTED
+    elif case == "unknown":
+        o.kernel = 9
+    elif case == "delay":
+        o.debug_delay = -1
+    elif case == "spin":
+        o.debug_spin_limit = -2
+    elif case == "stall":
+        o.debug_stall_block = -1
+    elif case == "sweeps":
+        nsweeps = (1 << 29) + 1
+    elif case == "ws":
+        expect = lib.EWORKSPACE
+    raw = lib._lib
+    if case.startswith("solve"):
+        info = lib.rbgs_solve_info()
+        ms = (1 << 29) + 1 if case == "solve_sweeps" else 10
+        rc = raw.rbgs_rb3_solve_ex(ctypes.byref(g), None, None, ms, 1e-8, 5, ctypes.byref(o),
+                                   ctypes.byref(info), None, 0, None)
+    else:
+        rc = raw.rbgs_rb3_sweep_ex(ctypes.byref(g), None, None, nsweeps, ctypes.byref(o), None, 0,
+                                   None)
+    assert rc == expect, (case, rc, lib.rbgs_last_error())
+
+
 def test_split_layout_entry_points_validate(lib):
     g = _grid(lib, 255)
     assert lib.rbgs_split_pitch(g, lib.F64) == 160  # ceil(257 / 2) = 129 -> 5 x 32
