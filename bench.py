@@ -648,6 +648,20 @@ def batched_to_tolerance(torch, rb, W, count=16, tol=1e-8, chunk=4000):
                                 "max_sweeps": max(i["sweeps"] for i in infos),
                                 "max_rel": max(i["rel_residual"] for i in infos),
                                 "all_converged": all(i["status"] == 0 for i in infos)}
+    # The same batched FP64 solve with red-black SOR at each grid's optimum
+    # omega (the F1 extension), residual every 100 sweeps.
+    rb.rbgs_solve_batched(us, fs, 10, tol, 10, precision="f64", omega=0.0)  # warm-up
+    for u in us:
+        u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = rb.rbgs_solve_batched(us, fs, 400_000, tol, 100, precision="f64", omega=0.0)
+    torch.cuda.synchronize()
+    dt_sor = time.perf_counter() - t0
+    out["batched_sor_solve"] = {"seconds": round(dt_sor, 4),
+                                "max_sweeps": max(i["sweeps"] for i in infos),
+                                "max_rel": max(i["rel_residual"] for i in infos),
+                                "all_converged": all(i["status"] == 0 for i in infos)}
     t_plain = 0.0
     sweeps_plain = 0
     for f in fs:
@@ -660,6 +674,7 @@ def batched_to_tolerance(torch, rb, W, count=16, tol=1e-8, chunk=4000):
     out["speedup_vs_plain_f64"] = round(t_plain / dt, 2)
     out["speedup_f32_ir_vs_plain_f64"] = round(t_plain / dt_ir, 2)
     out["speedup_f64_solve_vs_plain_f64"] = round(t_plain / dt_f64, 2)
+    out["speedup_sor_solve_vs_plain_f64"] = round(t_plain / dt_sor, 2)
     log(f"batched to tolerance: {out}")
     return out
 

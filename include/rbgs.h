@@ -393,9 +393,12 @@ int rbgs_autotune_batched(int32_t count, const rbgs_grid *grids,
  * The sweeps of all grids still iterating run as one batched persistent
  * launch per round (opts->sweep selects its tuning; the autotuner's table
  * applies); a converged grid is left alone, so each grid's result is
- * bitwise that of rbgs_solve on it alone.  Needs rel_tol > 0, omega = 1
- * (batched sweeps are Gauss-Seidel; else RBGS_EUNSUPPORTED) and fallback
- * = 0 (RBGS_EUNSUPPORTED).  infos (HOST, count entries, may be NULL)
+ * bitwise that of rbgs_solve on it alone.  Needs rel_tol > 0 and fallback
+ * = 0 (RBGS_EUNSUPPORTED).  omega: 1 = Gauss-Seidel; with precision F64
+ * also red-black SOR (an extension, as in rbgs_solve), omega in (0, 2)
+ * for every grid or 0 for each grid's own optimum 2 / (1 + sin(pi h)),
+ * every grid swept by the tiled kernel (none LDS-resident); SOR with the
+ * IR precisions is RBGS_EUNSUPPORTED, omega outside [0, 2) RBGS_EINVAL.  infos (HOST, count entries, may be NULL)
  * receives each grid's sweeps, outer steps, norms, status and precision.
  * Returns RBGS_OK when every grid converged, else the first failing grid's
  * status (RBGS_ENOCONV, RBGS_ENONFINITE).  The workspace

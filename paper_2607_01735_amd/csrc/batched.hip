@@ -116,7 +116,8 @@ __global__ __launch_bounds__(256) void k_batch_unpack(const PackDesc* __restrict
     }
 }
 
-template <typename T, int V, int L>
+// SOR: red-black SOR with each grid's own omega (FP64 batched solves).
+template <typename T, int V, int L, bool SOR>
 __global__ __launch_bounds__(kLanes) void k_blocked_batched(const GridDesc<T>* __restrict__ descs,
                                                             const int* __restrict__ tile_grid,
                                                             int total_tiles, Queue qu) {
@@ -129,7 +130,9 @@ __global__ __launch_bounds__(kLanes) void k_blocked_batched(const GridDesc<T>* _
         const int idx = tk - pass * total_tiles;
         const int gi = __builtin_amdgcn_readfirstlane(tile_grid[idx]);
         const GridDesc<T> g = descs[gi];
-        if (!run_item<T, V, L>(g, qu, pass, idx - g.flag_base)) break;
+        if (!run_item<T, V, L, false, SOR>(g, qu, pass, idx - g.flag_base, DebugModes(), 0,
+                                           g.omega))
+            break;
     }
 }
 
@@ -339,6 +342,7 @@ BatchSetup build_setup(int count, const rbgs_grid* grids, void* const* u, const 
         d.strips = geo.strips;
         d.bands = geo.bands;
         d.ntiles = geo.ntiles;
+        d.omega = T(1);
         PackDesc& p = s.pdesc[g];
         p.nat_u = u[g];
         p.nat_f = f[g];
@@ -375,45 +379,58 @@ BatchSetup build_setup(int count, const rbgs_grid* grids, void* const* u, const 
     return s;
 }
 
-template <typename T, int V, int L>
+template <typename T, int V, int L, bool SOR>
 hipError_t launch_batched_k(const GridDesc<T>* d, const int* map, int total_tiles, const Queue& qu,
                             hipStream_t s) {
     int per_cu = 0, cus = 0;
-    hipError_t e = persistent_occupancy(reinterpret_cast<const void*>(&k_blocked_batched<T, V, L>),
-                                        &per_cu, &cus);
+    hipError_t e = persistent_occupancy(
+        reinterpret_cast<const void*>(&k_blocked_batched<T, V, L, SOR>), &per_cu, &cus);
     if (e != hipSuccess) return e;
     int64_t total = int64_t(qu.passes) * total_tiles;
     int64_t grid = int64_t(cus) * per_cu;
     if (grid > total) grid = total;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL((k_blocked_batched<T, V, L>), dim3(unsigned(grid)), dim3(kLanes), 0, s, d,
-                       map, total_tiles, qu);
+    hipLaunchKernelGGL((k_blocked_batched<T, V, L, SOR>), dim3(unsigned(grid)), dim3(kLanes), 0,
+                       s, d, map, total_tiles, qu);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_batched_by_fuse(int fuse, const GridDesc<T>* d, const int* map, int tiles,
-                                  const Queue& qu, hipStream_t s) {
+template <typename T, bool SOR>
+hipError_t launch_batched_depth(int fuse, const GridDesc<T>* d, const int* map, int tiles,
+                                const Queue& qu, hipStream_t s) {
     constexpr int V = 16 / int(sizeof(T));
     switch (fuse) {
-        case 1: return launch_batched_k<T, V, 2>(d, map, tiles, qu, s);
-        case 2: return launch_batched_k<T, V, 4>(d, map, tiles, qu, s);
-        case 3: return launch_batched_k<T, V, 6>(d, map, tiles, qu, s);
-        case 4: return launch_batched_k<T, V, 8>(d, map, tiles, qu, s);
-        case 5: return launch_batched_k<T, V, 10>(d, map, tiles, qu, s);
-        case 6: return launch_batched_k<T, V, 12>(d, map, tiles, qu, s);
-        case 7: return launch_batched_k<T, V, 14>(d, map, tiles, qu, s);
-        case 8: return launch_batched_k<T, V, 16>(d, map, tiles, qu, s);
-        case 9: return launch_batched_k<T, V, 18>(d, map, tiles, qu, s);
-        default: return launch_batched_k<T, V, 20>(d, map, tiles, qu, s);
+        case 1: return launch_batched_k<T, V, 2, SOR>(d, map, tiles, qu, s);
+        case 2: return launch_batched_k<T, V, 4, SOR>(d, map, tiles, qu, s);
+        case 3: return launch_batched_k<T, V, 6, SOR>(d, map, tiles, qu, s);
+        case 4: return launch_batched_k<T, V, 8, SOR>(d, map, tiles, qu, s);
+        case 5: return launch_batched_k<T, V, 10, SOR>(d, map, tiles, qu, s);
+        case 6: return launch_batched_k<T, V, 12, SOR>(d, map, tiles, qu, s);
+        case 7: return launch_batched_k<T, V, 14, SOR>(d, map, tiles, qu, s);
+        case 8: return launch_batched_k<T, V, 16, SOR>(d, map, tiles, qu, s);
+        case 9: return launch_batched_k<T, V, 18, SOR>(d, map, tiles, qu, s);
+        default: return launch_batched_k<T, V, 20, SOR>(d, map, tiles, qu, s);
     }
+}
+
+// sor: the grids' omega relax every update (FP64 only)
+template <typename T>
+hipError_t launch_batched_by_fuse(int fuse, const GridDesc<T>* d, const int* map, int tiles,
+                                  const Queue& qu, bool sor, hipStream_t s) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (sor) return launch_batched_depth<T, true>(fuse, d, map, tiles, qu, s);
+    } else {
+        if (sor) return hipErrorInvalidValue;
+    }
+    return launch_batched_depth<T, false>(fuse, d, map, tiles, qu, s);
 }
 
 // Enqueue the device work of one batched sweep: pack, persistent passes,
 // remaining sweeps as short persistent launches of fuse 1, unpack.
 template <typename T>
 hipError_t enqueue_batch(const BatchSetup& su, const BatchLayout& lay, char* ws, int count,
-                         const rbgs_sweep_opts* o, bool do_pack, bool do_unpack, hipStream_t s) {
+                         const rbgs_sweep_opts* o, bool do_pack, bool do_unpack, hipStream_t s,
+                         bool sor = false) {
     hipError_t e;
     const PackDesc* pd = reinterpret_cast<const PackDesc*>(ws + lay.pdesc);
     const GridDesc<T>* gd = reinterpret_cast<const GridDesc<T>*>(ws + lay.gdesc);
@@ -439,6 +456,7 @@ hipError_t enqueue_batch(const BatchSetup& su, const BatchLayout& lay, char* ws,
     // whose halo was sized for `fuse`
     const int launches[2][2] = {{su.fuse, su.passes}, {su.rem, su.rem > 0 ? 1 : 0}};
     const int final_parity = (su.passes + (su.rem > 0 ? 1 : 0)) & 1;
+    if (sor && !su.small_ids.empty()) return hipErrorInvalidValue;  // Gauss-Seidel only
     if (!su.small_ids.empty()) {
         // the LDS-resident grids: all their sweeps in one launch, written to
         // the buffer the unpack reads
@@ -457,7 +475,8 @@ hipError_t enqueue_batch(const BatchSetup& su, const BatchLayout& lay, char* ws,
         if ((e = launch_zero(ws + lay.flags, size_t(su.total_tiles) * 4, s)) != hipSuccess) return e;
         qu.passes = lp[1];
         qu.buf_offset = parity;
-        if ((e = launch_batched_by_fuse<T>(lp[0], gd, map, su.total_tiles, qu, s)) != hipSuccess)
+        if ((e = launch_batched_by_fuse<T>(lp[0], gd, map, su.total_tiles, qu, sor, s)) !=
+            hipSuccess)
             return e;
         parity = (parity + lp[1]) & 1;
     }
@@ -844,7 +863,8 @@ int solve_batched_ir(int32_t count, const rbgs_grid* grids, double* const* u,
 // ---------------------------------------------------------------------------
 // Batched FP64 solve: the single-grid FP64 solve loop (residual, then
 // check_every sweeps, until rel <= rel_tol or max_sweeps), with the sweeps
-// of every grid still iterating in one batched persistent launch.
+// of every grid still iterating in one batched persistent launch; with
+// omega != 1 the sweeps are red-black SOR, each grid with its own omega.
 // ---------------------------------------------------------------------------
 
 // Workspace: the FP64 batch (per grid two ping-pong buffers of u and f,
@@ -878,6 +898,11 @@ int solve_batched_f64(int32_t count, const rbgs_grid* grids, double* const* u,
                       char* ws, hipStream_t s) {
     const SolveLayoutF64 L = solve_layout_f64(count, grids);
     const int check = o->check_every > 0 ? o->check_every : o->inner_sweeps;
+    // omega 0: each grid's optimum for the model problem, 2 / (1 + sin(pi h))
+    const bool sor = o->omega != 1.0;
+    auto omega_of = [&](int g) {
+        return o->omega == 0.0 ? 2.0 / (1.0 + std::sin(M_PI * grids[g].h)) : o->omega;
+    };
     double* sums = reinterpret_cast<double*>(ws + L.sums);
     // colour array k of grid g in the order build_setup lays them out:
     // red, black of buffer 0, red, black of buffer 1, f red, f black
@@ -953,18 +978,21 @@ int solve_batched_f64(int32_t count, const rbgs_grid* grids, double* const* u,
             }
             int fuse = 0, rows = 0, lds = 0;
             choose_params(na, sg.data(), RBGS_F64, &o->sweep, &fuse, &rows, &lds);
+            if (sor) lds = -1;  // the LDS-resident sweep is Gauss-Seidel only
             BatchSetup su =
                 build_setup<double>(na, sg.data(), nu.data(), nf.data(), sub, ws, fuse, rows, k, lds);
             // a grid whose iterate sits in buffer 1 runs with its buffers
             // swapped, so that every launch starts from "buffer 0"
             GridDesc<double>* gd = reinterpret_cast<GridDesc<double>*>(su.gdesc.data());
-            for (int a = 0; a < na; ++a)
+            for (int a = 0; a < na; ++a) {
                 if (cur[act[a]]) {
                     std::swap(gd[a].red[0], gd[a].red[1]);
                     std::swap(gd[a].black[0], gd[a].black[1]);
                 }
+                gd[a].omega = omega_of(act[a]);
+            }
             if ((rc = upload_setup<double>(su, sub, ws, na, s))) return rc;
-            e = enqueue_batch<double>(su, sub, ws, na, &o->sweep, false, false, s);
+            e = enqueue_batch<double>(su, sub, ws, na, &o->sweep, false, false, s, sor);
             if (e != hipSuccess) return bfail(RBGS_EHIP, std::string("sweeps: ") + hipGetErrorString(e));
             if ((rc = read_error_word(sub, ws, s))) return rc;
             const int out = (su.passes + (su.rem > 0 ? 1 : 0)) & 1;
@@ -1208,8 +1236,13 @@ int rbgs_solve_batched(int32_t count, const rbgs_grid* grids, double* const* u,
     if (opts->inner_sweeps < 0 || opts->check_every < 0 ||
         (opts->inner_sweeps == 0 && opts->check_every == 0))
         return bfail(RBGS_EINVAL, "need inner_sweeps >= 1 (or check_every >= 1)");
-    if (opts->omega != 1.0)
-        return bfail(RBGS_EUNSUPPORTED, "batched sweeps are Gauss-Seidel: omega must be 1");
+    if (opts->omega != 1.0) {
+        if (!(opts->omega == 0.0 || (opts->omega > 0.0 && opts->omega < 2.0)))
+            return bfail(RBGS_EINVAL, "omega must be in (0, 2), or 0 for each grid's optimum");
+        if (opts->precision != RBGS_PREC_F64)
+            return bfail(RBGS_EUNSUPPORTED, "batched SOR (omega != 1) runs in FP64 without "
+                                            "refinement");
+    }
     int rc = validate_batch(count, grids, RBGS_F64, reinterpret_cast<void* const*>(u),
                             reinterpret_cast<const void* const*>(f), 0, &opts->sweep);
     if (rc) return rc;

@@ -47,6 +47,8 @@ struct GridDesc {
     int q_core;       // q-columns written per band
     int strips, bands, ntiles;
     int flag_base;    // index of this grid's first tile in the progress array
+    T omega;          // relaxation of a batched SOR launch (the single-grid
+                      // kernels take it as an argument)
 };
 
 // Work queue shared by all waves of one persistent launch.

@@ -400,6 +400,7 @@ hipError_t run_blocked(T* const buf_red[2], T* const buf_black[2], const T* f_re
             g.bands = geo.bands;
             g.ntiles = geo.ntiles;
             g.flag_base = 0;
+            g.omega = T(1);
             Queue qu;
             qu.passes = chunk;
             qu.ticket = reinterpret_cast<int*>(base);

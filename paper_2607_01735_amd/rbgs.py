@@ -738,12 +738,13 @@ class BatchPlan:
 
 
 def rbgs_solve_batched(us, fs, max_sweeps, rel_tol, inner_sweeps, precision="f32_ir", hs=None,
-                       workspace=None, stream=None, **tuning):
+                       workspace=None, stream=None, omega=1.0, **tuning):
     """Solve every FP64 grid of the batch to rel_tol: precision "f64" sweeps
     in FP64 and checks the residual every inner_sweeps sweeps; "f32_ir" and
     "bf16rhs_ir" refine in FP64 around inner_sweeps FP32 sweeps.  The sweeps
     of all unconverged grids run in one batched launch per round; returns
-    one dict per grid like rbgs_solve's.  Synchronises."""
+    one dict per grid like rbgs_solve's.  omega != 1 ("f64" only): red-black
+    SOR, 0 = each grid's optimum.  Synchronises."""
     b = _Batch(us, fs, hs)
     if b.code != F64:
         raise RbgsError(EINVAL, "batched solves take FP64 u and f")
@@ -756,7 +757,7 @@ def rbgs_solve_batched(us, fs, max_sweeps, rel_tol, inner_sweeps, precision="f32
     opts = rbgs_solve_opts()
     opts.max_sweeps, opts.rel_tol, opts.check_every = int(max_sweeps), float(rel_tol), int(inner_sweeps)
     opts.precision = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    opts.inner_sweeps, opts.omega = int(inner_sweeps), 1.0
+    opts.inner_sweeps, opts.omega = int(inner_sweeps), float(omega)
     opts.sweep = _sweep_opts(kernel=tuning.pop("kernel", "auto"), **tuning)
     infos = (rbgs_solve_info * b.count)()
     rc = _lib.rbgs_solve_batched(b.count, b.grids, b.u, b.f, ctypes.byref(opts), infos,

@@ -213,6 +213,7 @@ int main(int argc, char** argv) {
     g.bands = geo.bands;
     g.ntiles = geo.ntiles;
     g.flag_base = 0;
+    g.omega = T(1);
     Queue& qu = g_queue;
     qu.passes = passes;
     qu.progress = static_cast<int*>(calloc(size_t(geo.ntiles), sizeof(int)));

@@ -206,8 +206,9 @@ def test_transfer_validation(lib, case):
             assert "NULL" in lib.rbgs_last_error()
 
 
-@pytest.mark.parametrize("bad", ["null_opts", "prec", "omega", "omega0", "tol", "inner",
-                                 "check", "count", "null_arrays", "ws", "ws_f64"])
+@pytest.mark.parametrize("bad", ["null_opts", "prec", "omega", "omega0", "omega_range", "tol",
+                                 "inner", "check", "count", "null_arrays", "ws", "ws_f64",
+                                 "ws_sor"])
 def test_solve_batched_validation_before_device_work(lib, bad):
     grids = (lib.rbgs_grid * 2)(_grid(lib, 15), _grid(lib, 31))
     ptrs = (ctypes.c_void_p * 2)(1 << 20, 2 << 20)  # never dereferenced: checks come first
@@ -219,10 +220,14 @@ def test_solve_batched_validation_before_device_work(lib, bad):
         opts = None
     elif bad == "prec":
         o.precision = 3
-    elif bad == "omega":  # batched sweeps are Gauss-Seidel
+    elif bad == "omega":  # SOR runs without refinement
         o.omega, expect = 1.5, lib.EUNSUPPORTED
-    elif bad == "omega0":  # 0 asks for the optimal SOR factor
+    elif bad == "omega0":  # 0 asks for each grid's optimal SOR factor
         o.omega, expect = 0.0, lib.EUNSUPPORTED
+    elif bad == "omega_range":
+        o.omega, o.precision = 2.0, lib.PREC_F64
+    elif bad == "ws_sor":  # FP64 SOR passes the option checks
+        o.omega, o.precision, expect = 0.0, lib.PREC_F64, lib.EWORKSPACE
     elif bad == "check":
         o.check_every = -1
     elif bad == "ws_f64":  # FP64 solves take the same workspace

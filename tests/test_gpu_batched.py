@@ -291,3 +291,29 @@ def test_solve_batched_sweep_cap():
         assert infos[g]["sweeps"] == 1000 == single[g]["sweeps"]
         assert infos[g]["outer_iters"] == 4 == single[g]["outer_iters"]
         assert infos[g]["status"] == rb.rbgs.ENOCONV
+
+
+@pytest.mark.parametrize("omega,check", [(0.0, 50), (0.0, 51), (1.5, 40)])
+def test_solve_batched_sor_matches_oracle(oracle, omega, check):
+    """Batched red-black SOR (FP64): each grid is the oracle's SOR solve of
+    that grid alone, bit for bit, with its own optimum omega (omega = 0) or
+    a common one; odd and even pass counts per round."""
+    import math
+    sizes = [127, 63, 31, 255, 15, 63, 7]
+    tol = 1e-9
+    say(f"batched SOR solve omega={omega} check_every={check}")
+    fs = [W.fourier_rhs(n, seed=30 + g, count=8, kmax=8) for g, n in enumerate(sizes)]
+    us = [W.random_ring(n, seed=60 + g) for g, n in enumerate(sizes)]
+    ut, ft = to_dev(us), to_dev(fs)
+    infos = rb.rbgs_solve_batched(ut, ft, 100_000, tol, check, precision="f64", omega=omega)
+    for g, n in enumerate(sizes):
+        h = W.spacing(n)
+        w = 2.0 / (1.0 + math.sin(math.pi * h)) if omega == 0.0 else omega
+        ref = us[g].copy()
+        rc, done, rel = oracle.sor_solve(ref, fs[g], h, w, 100_000, tol, check)
+        assert rc == 0 and infos[g]["status"] == 0, (g, infos[g], rc)
+        assert infos[g]["sweeps"] == done, (g, infos[g], done)
+        assert np.array_equal(ut[g].cpu().numpy(), ref), f"grid {g} (n={n})"
+        assert infos[g]["rel_residual"] == pytest.approx(rel, rel=1e-12)
+    if omega == 0.0:  # SOR at the optimum needs O(n) sweeps, not O(n^2)
+        assert infos[3]["sweeps"] < 5000
