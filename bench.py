@@ -304,7 +304,9 @@ def multicolour9_throughput(torch, rb, W, n=8191, sweeps=100, with_solve=True):
     extension) on the 8191^2 FP64 grid: time of `sweeps` sweeps as the
     difference of a (sweeps + 1)-sweep call and a 1-sweep call (both pack and
     unpack once), GLUP/s and model bytes (40 B per point per sweep); and the
-    time to rel <= 1e-8 at 255^2 from u = 0 (sine right-hand side)."""
+    time to rel <= 1e-8 at 255^2 from u = 0 (sine right-hand side); each for
+    the plain kernel (a launch per colour) and the flag-driven form (one
+    launch, a counter per block)."""
     h = W.spacing(n)
     f = torch.from_numpy(W.uniform_rhs(n, seed=0)).to("cuda")
     u = torch.zeros_like(f)
@@ -319,7 +321,7 @@ def multicolour9_throughput(torch, rb, W, n=8191, sweeps=100, with_solve=True):
         return time.perf_counter() - t0
 
     out = {"workload": f"{n}x{n} FP64, f~U[-1,1) seed 0, {sweeps} sweeps"}
-    for kernel in ("plain",):
+    for kernel in ("plain", "resident"):
         timed(3, kernel)
         one = min(timed(1, kernel) for _ in range(3))
         many = min(timed(sweeps + 1, kernel) for _ in range(2))
@@ -329,7 +331,7 @@ def multicolour9_throughput(torch, rb, W, n=8191, sweeps=100, with_solve=True):
                "model_bytes_per_lup": MC9_BYTES_PER_LUP,
                "model_GBs": round(glups * MC9_BYTES_PER_LUP, 1),
                "frac_of_8TBs": round(glups * MC9_BYTES_PER_LUP / HBM_PEAK_GBS, 4)}
-        out["plain" if kernel == "plain" else "task_based"] = res
+        out["plain" if kernel == "plain" else "flag_driven"] = res
         log(f"multicolour 9-point {n} {kernel}: {per_sweep * 1e3:.3f} ms/sweep, {glups:.1f} GLUP/s, "
             f"{glups * MC9_BYTES_PER_LUP:.0f} GB/s model")
     del u, f, ws
@@ -340,7 +342,7 @@ def multicolour9_throughput(torch, rb, W, n=8191, sweeps=100, with_solve=True):
     hm = W.spacing(m)
     fm = torch.from_numpy(W.sine_rhs(m)).to("cuda")
     um = torch.zeros_like(fm)
-    for kernel in ("plain",):
+    for kernel in ("plain", "resident"):
         rb.rbgs_mc9_solve(um, fm, 8, -1.0, check_every=8, h=hm, kernel=kernel)
         um.zero_()
         torch.cuda.synchronize()
@@ -348,7 +350,7 @@ def multicolour9_throughput(torch, rb, W, n=8191, sweeps=100, with_solve=True):
         info = rb.rbgs_mc9_solve(um, fm, 4_000_000, 1e-8, check_every=1000, h=hm, kernel=kernel)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        key = "time_to_1e-8_255_sine_" + ("plain" if kernel == "plain" else "task_based")
+        key = "time_to_1e-8_255_sine_" + ("plain" if kernel == "plain" else "flag_driven")
         out[key] = {"seconds": round(dt, 4), "sweeps": info["sweeps"],
                     "rel_residual": info["rel_residual"], "status": info["status"]}
         log(f"multicolour 9-point time-to-tol 255 {kernel}: {dt:.3f} s, {info['sweeps']} sweeps")

@@ -594,9 +594,16 @@ size_t rbgs_mc9_workspace_size(const rbgs_grid *g);
 
 /* nsweeps sweeps of u in place.  kernel: RBGS_KERNEL_AUTO or
  * RBGS_KERNEL_PLAIN = one launch per colour (a device-wide barrier between
- * colours, Algorithm 1's structure); a persistent, dependency-driven form
- * is not available (RBGS_KERNEL_BLOCKED and RBGS_KERNEL_RESIDENT return
- * RBGS_EUNSUPPORTED).  Asynchronous on `stream`. */
+ * colours, Algorithm 1's structure); RBGS_KERNEL_RESIDENT = the
+ * flag-driven form, the dependency rule of Algorithm 2 (Section 2.3)
+ * carried to four colours: all quarter-sweeps of the call in one launch,
+ * the (i >> 1, j >> 1) index grid cut into blocks whose quarter-sweep h
+ * waits only until the block and its eight neighbours have completed h
+ * quarter-sweeps (a counter per block; bounded waits), same result bit
+ * for bit; this form reads its error word at the end, so it synchronises
+ * `stream` and may return RBGS_ETIMEOUT; nsweeps <= 2^29.
+ * RBGS_KERNEL_BLOCKED: RBGS_EUNSUPPORTED.  Asynchronous on `stream` with
+ * PLAIN. */
 int rbgs_mc9_sweep(const rbgs_grid *g, double *u, const double *f,
                    int32_t nsweeps, int32_t kernel, void *workspace,
                    size_t workspace_bytes, void *stream);
@@ -609,8 +616,8 @@ int rbgs_mc9_residual(const rbgs_grid *g, const double *u, const double *f,
 
 /* Sweeps until rel <= rel_tol (checked before the first sweep and after
  * every check_every sweeps; rel_tol <= 0: exactly max_sweeps sweeps), as
- * rbgs_solve, with the rounds captured in a HIP graph; kernel as for
- * rbgs_mc9_sweep.  info (HOST, may be NULL): sweeps, rel_residual,
+ * rbgs_solve, with the rounds captured in a HIP graph (PLAIN) or one
+ * flag-driven launch per round (RESIDENT); kernel as for rbgs_mc9_sweep.  info (HOST, may be NULL): sweeps, rel_residual,
  * abs_residual, status (outer_iters = 0).  Returns RBGS_OK, RBGS_ENOCONV,
  * RBGS_ENONFINITE or an error.  Synchronises `stream`. */
 int rbgs_mc9_solve(const rbgs_grid *g, double *u, const double *f,

@@ -659,15 +659,54 @@ Mc9Workspace plan_mc9(const rbgs_grid* g, char* base) {
     for (auto& c : w.f) c = take(colour);
     w.partials = take(size_t(mc9_residual_blocks(g->n)) * 2 * sizeof(double));
     w.sums = take(256);
+    w.state = reinterpret_cast<int*>(take(256 + size_t(kMc9MaxBlocks) * sizeof(int)));
     w.total = off;
     return w;
 }
 
-// Four-colour kernel choice: the plain form (a launch per colour) only; a
-// task-based persistent form is not available.
+// Four-colour kernel choice: AUTO or PLAIN (a launch per colour), RESIDENT
+// (the flag-driven form, one launch for all quarter-sweeps); no temporally
+// blocked form.
 int mc9_check_kernel(int kernel) {
-    if (kernel != RBGS_KERNEL_AUTO && kernel != RBGS_KERNEL_PLAIN)
-        return fail(RBGS_EUNSUPPORTED, "the 9-point sweep runs one launch per colour (AUTO or PLAIN)");
+    if (kernel == RBGS_KERNEL_BLOCKED)
+        return fail(RBGS_EUNSUPPORTED, "the 9-point sweep has no temporally blocked kernel: use "
+                                       "PLAIN or RESIDENT (the flag-driven form)");
+    if (kernel < RBGS_KERNEL_AUTO || kernel > RBGS_KERNEL_RESIDENT)
+        return fail(RBGS_EINVAL, "unknown kernel");
+    return RBGS_OK;
+}
+
+// nsweeps sweeps as flag-driven launches (the caller cleared the error
+// word): one launch unless the ticket count would leave the int range.
+int mc9_sweeps_flags(const rbgs_grid* g, const Mc9Workspace& w, int nsweeps, int capacity,
+                     hipStream_t s) {
+    const int nb = mc9_flags_blocks(g->n, capacity);
+    const int per_launch = int(((int64_t(1) << 30) / nb) / 4);  // levels x nb < 2^31
+    for (int done = 0; done < nsweeps;) {
+        const int k = std::min(nsweeps - done, per_launch);
+        HIP_TRY(launch_zero(w.state + 32, size_t(32 + nb) * sizeof(int), s),
+                "clear ticket and block counters");
+        HIP_TRY(launch_mc9_flags(w.u, w.f, g->n, 6.0 * (g->h * g->h), 4 * k, capacity,
+                                 w.state + 32, w.state + 64, w.state, 1 << 22, 0, 0, s),
+                "9-point flag-driven sweeps");
+        done += k;
+    }
+    return RBGS_OK;
+}
+
+int mc9_flags_error(const Mc9Workspace& w, hipStream_t s) {
+    int err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, w.state, sizeof err, hipMemcpyDeviceToHost, s), "read error word");
+    HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+    if (err) return fail(RBGS_ETIMEOUT, "a block dependency wait of the 9-point flag-driven sweep "
+                                        "timed out");
+    return RBGS_OK;
+}
+
+int mc9_flags_setup(const Mc9Workspace& w, hipStream_t s, int* capacity) {
+    *capacity = mc9_flags_capacity();
+    if (*capacity < 64) return fail(RBGS_EHIP, "occupancy query for the 9-point flag-driven kernel");
+    HIP_TRY(launch_zero(w.state, 256, s), "clear error word");
     return RBGS_OK;
 }
 
@@ -1493,13 +1532,18 @@ int rbgs_mc9_sweep(const rbgs_grid* g, double* u, const double* f, int32_t nswee
     int rc = mc9_prepare(g, u, f, workspace, workspace_bytes, &w);
     if (rc) return rc;
     if ((rc = mc9_check_kernel(kernel))) return rc;
+    if (nsweeps > (1 << 29)) return fail(RBGS_EINVAL, "nsweeps must be <= 2^29");
     if (nsweeps == 0) return RBGS_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool flags = kernel == RBGS_KERNEL_RESIDENT;
+    int capacity = 0;
+    if (flags && (rc = mc9_flags_setup(w, s, &capacity))) return rc;
     HIP_TRY(launch_mc9_pack(u, g->ld, w.u, g->n, s), "pack u");
     HIP_TRY(launch_mc9_pack(f, g->ld, w.f, g->n, s), "pack f");
-    if ((rc = mc9_sweeps(g, w, nsweeps, s, nullptr))) return rc;
+    rc = flags ? mc9_sweeps_flags(g, w, nsweeps, capacity, s) : mc9_sweeps(g, w, nsweeps, s, nullptr);
+    if (rc) return rc;
     HIP_TRY(launch_mc9_unpack(u, g->ld, w.u, g->n, s), "unpack u");
-    return RBGS_OK;
+    return flags ? mc9_flags_error(w, s) : RBGS_OK;
 }
 
 int rbgs_mc9_residual(const rbgs_grid* g, const double* u, const double* f, double* abs_norm,
@@ -1526,13 +1570,25 @@ int rbgs_mc9_solve(const rbgs_grid* g, double* u, const double* f, int32_t max_s
     int rc = mc9_prepare(g, u, f, workspace, workspace_bytes, &w);
     if (rc) return rc;
     if ((rc = mc9_check_kernel(kernel))) return rc;
+    const bool flags = kernel == RBGS_KERNEL_RESIDENT;
+    if (flags && max_sweeps > (1 << 29))
+        return fail(RBGS_EINVAL, "the flag-driven form runs at most 2^29 sweeps per call");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    int capacity = 0;
+    if (flags && (rc = mc9_flags_setup(w, s, &capacity))) return rc;
     HIP_TRY(launch_mc9_pack(u, g->ld, w.u, g->n, s), "pack u");
     HIP_TRY(launch_mc9_pack(f, g->ld, w.f, g->n, s), "pack f");
     double rel = 0.0, ab = 0.0;
     int32_t done = 0;
+    // k sweeps of the asked-for form; the flag-driven form checks its error
+    // word after each group (one launch per group of sweeps)
+    auto sweeps = [&](int k) -> int {
+        if (!flags) return mc9_sweeps(g, w, k, s, nullptr);
+        int r = mc9_sweeps_flags(g, w, k, capacity, s);
+        return r ? r : mc9_flags_error(w, s);
+    };
     if (rel_tol <= 0.0) {
-        if ((rc = mc9_sweeps(g, w, max_sweeps, s, nullptr))) return rc;
+        if ((rc = sweeps(max_sweeps))) return rc;
         done = max_sweeps;
         if ((rc = mc9_residual_sums(g, w, s))) return rc;
         if ((rc = mc9_fetch(w, s, &ab, &rel))) return rc;
@@ -1540,7 +1596,7 @@ int rbgs_mc9_solve(const rbgs_grid* g, double* u, const double* f, int32_t max_s
         if ((rc = mc9_residual_sums(g, w, s))) return rc;
         if ((rc = mc9_fetch(w, s, &ab, &rel))) return rc;
         const int cap = max_sweeps / check_every;
-        if (!(rel <= rel_tol) && std::isfinite(rel) && cap > 0) {
+        if (!flags && !(rel <= rel_tol) && std::isfinite(rel) && cap > 0) {
             Workspace v;
             v.sums = w.sums;
             RoundBody body = [&](hipStream_t cs, const int* stop, void** es) -> int {
@@ -1561,7 +1617,7 @@ int rbgs_mc9_solve(const rbgs_grid* g, double* u, const double* f, int32_t max_s
         }
         while (!(rel <= rel_tol) && done < max_sweeps && std::isfinite(rel)) {
             const int32_t k = max_sweeps - done < check_every ? max_sweeps - done : check_every;
-            if ((rc = mc9_sweeps(g, w, k, s, nullptr))) return rc;
+            if ((rc = sweeps(k))) return rc;
             done += k;
             if ((rc = mc9_residual_sums(g, w, s))) return rc;
             if ((rc = mc9_fetch(w, s, &ab, &rel))) return rc;

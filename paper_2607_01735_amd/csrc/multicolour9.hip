@@ -17,6 +17,10 @@
 //   e = ((u[i+1][j] + u[i-1][j]) + u[i][j+1]) + u[i][j-1]
 //   c = ((u[i+1][j+1] + u[i+1][j-1]) + u[i-1][j+1]) + u[i-1][j-1]
 //   u[i][j] = ((4 e + c) - c6 f[i][j]) / 20,   c6 = 6 (h h).
+#include <algorithm>
+#include <cmath>
+
+#include "mc9_flags.h"
 #include "rbgs_internal.h"
 
 namespace rbgs {
@@ -215,7 +219,73 @@ __global__ __launch_bounds__(kThreads) void k_mc9_reduce(const double* __restric
     }
 }
 
+// The flag-driven form (mc9_flags.h): one launch for every quarter-sweep.
+__global__ __launch_bounds__(mc9f::kLanes) void k_mc9_flags(mc9f::Args a) { mc9f::run(a); }
+
+// Bound on the blocks per quarter-sweep: every item costs a ticket on one
+// device-wide counter while an item's time grows with its size; as in the
+// 3D form about sqrt(points / 10), capped at the waves the chip holds.
+int mc9_flags_target(int n, int capacity) {
+    const double items = std::sqrt(double(n) * double(n) / 10.0);
+    return int(std::max(64.0, std::min(double(capacity), items)));
+}
+
 }  // namespace
+
+int mc9_flags_capacity() {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(&k_mc9_flags), mc9f::kLanes, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const int64_t c = int64_t(cus) * per_cu;
+    return int(c < kMc9MaxBlocks ? c : kMc9MaxBlocks);
+}
+
+int mc9_flags_blocks(int n, int capacity) {
+    if (capacity < 64) return 0;
+    return mc9f::geometry(n, mc9_flags_target(n, capacity)).nblocks;
+}
+
+hipError_t launch_mc9_flags(double* const u[4], double* const f[4], int n, double c6, int levels,
+                            int capacity, int* ticket, int* progress, int* error, int spin_limit,
+                            int delay, int stall_block, hipStream_t s) {
+    if (capacity < 64) return hipErrorInvalidValue;
+    const mc9f::Geometry geo = mc9f::geometry(n, mc9_flags_target(n, capacity));
+    if (int64_t(levels) * geo.nblocks >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    mc9f::Args a;
+    for (int c = 0; c < 4; ++c) {
+        a.u[c] = u[c];
+        a.f[c] = f[c];
+    }
+    a.n = n;
+    a.pitch = mc9_pitch(n);
+    a.rows = geo.rows;
+    a.cols = geo.cols;
+    a.c6 = c6;
+    a.qw = geo.qw;
+    a.ri = geo.ri;
+    a.qblocks = geo.qblocks;
+    a.iblocks = geo.iblocks;
+    a.nblocks = geo.nblocks;
+    a.levels = levels;
+    a.ticket = ticket;
+    a.progress = progress;
+    a.error = error;
+    a.spin_limit = spin_limit;
+    a.delay = delay;
+    a.stall_block = stall_block;
+    // one wave per block: each takes the next level's item as it finishes one
+    int64_t waves = std::min<int64_t>(capacity, geo.nblocks);
+    const int64_t items = int64_t(levels) * geo.nblocks;
+    if (waves > items) waves = items;
+    if (waves < 1) waves = 1;
+    hipLaunchKernelGGL(k_mc9_flags, dim3(unsigned(waves)), dim3(mc9f::kLanes), 0, s, a);
+    return hipGetLastError();
+}
 
 int mc9_rows(int n) { return ((n + 1) >> 1) + 1; }
 

@@ -186,6 +186,17 @@ hipError_t launch_mc9_quarter(double* const u[4], double* const f[4], int n, dou
                               int colour, const int* stop, hipStream_t s);
 hipError_t launch_mc9_residual(double* const u[4], double* const f[4], int n, double inv6h2,
                                double* partials, double* out, hipStream_t s);
+// The flag-driven 9-point form: `levels` quarter-sweeps (colour 0 first) in
+// one launch (levels x mc9_flags_blocks(n, capacity) < 2^31).  capacity:
+// resident workgroups of the kernel (mc9_flags_capacity()); ticket and
+// progress: a zeroed counter and mc9_flags_blocks(n, capacity) zeroed block
+// counters; error: a zeroed word, raised when a bounded wait expires.
+constexpr int kMc9MaxBlocks = 65536;
+int mc9_flags_capacity();
+int mc9_flags_blocks(int n, int capacity);
+hipError_t launch_mc9_flags(double* const u[4], double* const f[4], int n, double c6, int levels,
+                            int capacity, int* ticket, int* progress, int* error, int spin_limit,
+                            int delay, int stall_block, hipStream_t s);
 
 // Red-black Gauss-Seidel in 3D (7-point): split arrays with a row per (i, j)
 // pair, (n+2)^2 rows of `pitch` (split_pitch(n, 8)) doubles.  half: colour

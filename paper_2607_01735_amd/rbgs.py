@@ -451,7 +451,8 @@ def _kernel_code(kernel):
 
 def rbgs_mc9_sweep(u, f, nsweeps, h=None, kernel="auto", workspace=None, stream=None):
     """nsweeps four-colour sweeps of the 9-point system, in place (FP64);
-    kernel "auto" or "plain" (a launch per colour)."""
+    kernel "auto" or "plain" (a launch per colour), or "resident" (the
+    flag-driven form: one launch, a counter per block; synchronises)."""
     grid, ws = _mc9_args(u, f, h, workspace)
     _check(_lib.rbgs_mc9_sweep(ctypes.byref(grid), _vp(u.data_ptr()), _vp(f.data_ptr()),
                                int(nsweeps), _kernel_code(kernel), _vp(ws.data_ptr()), ws.numel(),

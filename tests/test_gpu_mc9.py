@@ -1,6 +1,8 @@
 """Four-colour Gauss-Seidel for the 9-point Laplacian on the GPU (the
 multi-colour extension): sweeps and solves must equal the oracle bit for
-bit, and the residual must agree with the oracle's to rounding."""
+bit, and the residual must agree with the oracle's to rounding.  Kernel
+"resident" is the flag-driven form (all quarter-sweeps in one launch, each
+block waiting on its eight neighbours' counters)."""
 import sys
 
 import numpy as np
@@ -35,7 +37,7 @@ def start(n, seed, ld=None):
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 8, 33, 100, 255, 1000, 1023])
-@pytest.mark.parametrize("kernel", ["plain", "auto"])
+@pytest.mark.parametrize("kernel", ["plain", "auto", "resident"])
 def test_sweeps_bitwise(oracle, n, kernel):
     say(f"mc9 sweeps n={n} kernel={kernel}")
     h = W.spacing(n)
@@ -57,7 +59,7 @@ def test_residual_matches_oracle(oracle, n):
     assert a == pytest.approx(ra, rel=1e-12) and r == pytest.approx(rr, rel=1e-12)
 
 
-@pytest.mark.parametrize("kernel", ["plain", "auto"])
+@pytest.mark.parametrize("kernel", ["plain", "auto", "resident"])
 def test_solve_matches_oracle(oracle, kernel):
     n = 63
     say(f"mc9 solve n={n} kernel={kernel}")
@@ -72,7 +74,7 @@ def test_solve_matches_oracle(oracle, kernel):
     assert info["rel_residual"] == pytest.approx(rel, rel=1e-9)
 
 
-@pytest.mark.parametrize("kernel", ["plain", "auto"])
+@pytest.mark.parametrize("kernel", ["plain", "auto", "resident"])
 def test_fixed_sweeps_and_cap(oracle, kernel):
     n = 31
     say(f"mc9 fixed sweeps / cap kernel={kernel}")
@@ -88,7 +90,7 @@ def test_fixed_sweeps_and_cap(oracle, kernel):
     assert np.array_equal(ut.cpu().numpy(), oracle.mc9_sweep(u0.copy(), f, h, 10))
 
 
-@pytest.mark.parametrize("kernel", ["plain", "auto"])
+@pytest.mark.parametrize("kernel", ["plain", "auto", "resident"])
 def test_full_size_sweeps_bitwise(oracle, kernel):
     """8191^2, the sweep benchmark's grid: two sweeps equal the oracle's."""
     n = 8191
@@ -102,10 +104,10 @@ def test_full_size_sweeps_bitwise(oracle, kernel):
     assert np.array_equal(got, oracle.mc9_sweep(W.zeros(n), f, h, 2))
 
 
-@pytest.mark.parametrize("kernel", ["blocked", "resident"])
+@pytest.mark.parametrize("kernel", ["blocked"])
 def test_persistent_kernels_are_unsupported(kernel):
-    """Only the launch-per-colour form exists; the others are refused before
-    any device work."""
+    """There is no temporally blocked 9-point kernel (the flag-driven form
+    is kernel "resident"); it is refused before any device work."""
     u = torch.zeros(9, 9, dtype=torch.float64, device=DEV)
     with pytest.raises(rb.RbgsError) as exc:
         rb.rbgs_mc9_sweep(u, u.clone(), 1, kernel=kernel)
