@@ -947,7 +947,8 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     if args.rb3_only:
-        print(json.dumps({"rb3": rb3_throughput(torch, rb)}), flush=True)
+        tol_sizes = () if args.no_time_to_tol else (63, 127)
+        print(json.dumps({"rb3": rb3_throughput(torch, rb, tol_sizes=tol_sizes)}), flush=True)
         return
     if args.mc9_only:
         mc9 = multicolour9_throughput(torch, rb, W, with_solve=not args.no_time_to_tol)
