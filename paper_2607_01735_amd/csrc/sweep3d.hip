@@ -65,11 +65,44 @@ __global__ __launch_bounds__(kThreads) void k_rb3_unpack(double* __restrict__ na
     if (k1 >= 1 && k1 <= n) dst[k1] = odd_src[row * pitch + q];
 }
 
-// Workgroups of kQ x kJ threads (kQ columns q of kJ consecutive rows j), so
-// that most j +- 1 loads hit rows the same workgroup loads; the 1-D grid is
-// remapped so that each XCD receives a contiguous range of workgroups (rows
-// next to each other share that XCD's L2).
+// Workgroups of kQ x kJ threads (kQ threads of two q-columns each along kJ
+// consecutive rows j), so that most j +- 1 loads hit rows the same
+// workgroup loads; the 1-D grid is remapped so that each XCD receives a
+// contiguous range of workgroups (rows next to each other share that XCD's
+// L2).  A thread loads the other colour and f as 16-byte pairs (q, q + 1):
+// twice the bytes in flight per load of a one-column thread; the one k
+// neighbour outside the pair (q + 2 or q - 1) is a separate 8-byte load.
 constexpr int kQ = 64, kJ = 8;
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+struct D2 {
+    double x, y;
+};
+
+__device__ __forceinline__ D2 load2(const double* p) {
+    const dvec2 v = *reinterpret_cast<const dvec2*>(p);
+    return D2{v.x, v.y};
+}
+
+__device__ __forceinline__ D2 load2_nt(const double* p) {
+    const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
+    return D2{v.x, v.y};
+}
+
+// Gauss-Seidel value of one point from its six neighbours, in the order the
+// update fixes (each operation rounded once).
+__device__ __forceinline__ double rb3_update(double up, double dn, double jp, double jm, double kp,
+                                             double km, double h2, double fv) {
+    double s = up + dn;
+    s = s + jp;
+    s = s + jm;
+    s = s + kp;
+    s = s + km;
+    const double t = h2 * fv;
+    s = s - t;
+    return s / 6.0;
+}
 
 __global__ __launch_bounds__(kQ * kJ) void k_rb3_half(double* __restrict__ self,
                                                       const double* __restrict__ other,
@@ -80,36 +113,44 @@ __global__ __launch_bounds__(kQ * kJ) void k_rb3_half(double* __restrict__ self,
     const int nb = int(gridDim.x);
     const int b = xcd_logical_block(int(blockIdx.x), nb);
     const int bq = b % qblocks, bj = (b / qblocks) % jblocks, bz = b / (qblocks * jblocks);
-    const int64_t q = int64_t(bq) * kQ + (threadIdx.x % kQ);
+    const int64_t q = 2 * (int64_t(bq) * kQ + (threadIdx.x % kQ));  // pair (q, q + 1)
     const int64_t j = int64_t(bj) * kJ + (threadIdx.x / kQ) + 1;
     const int64_t i0 = int64_t(bz) * kPlanes + 1;
     if (j > n || q >= pitch || 2 * q > n) return;  // no interior point of either parity beyond
     const int64_t i1 = i0 + kPlanes - 1 < n ? i0 + kPlanes - 1 : n;
     const int64_t np2 = int64_t(n) + 2;
     auto row = [&](int64_t i, int64_t jj) { return (i * np2 + jj) * pitch; };
-    double o_dn = other[row(i0 - 1, j) + q];
-    double o_c = other[row(i0, j) + q];
+    D2 o_dn = load2(other + row(i0 - 1, j) + q);
+    D2 o_c = load2(other + row(i0, j) + q);
     for (int64_t i = i0; i <= i1; ++i) {
-        const double o_up = other[row(i + 1, j) + q];
+        const D2 o_up = load2(other + row(i + 1, j) + q);
         const int64_t p = (i + j + colour) & 1;
-        const int64_t k = 2 * q + p;
-        if (k >= 1 && k <= n) {
+        const int64_t k0 = 2 * q + p, k1 = k0 + 2;  // the points of q and q + 1
+        const bool v0 = k0 >= 1 && k0 <= n, v1 = k1 <= n;
+        if (v0 || v1) {
             const int64_t r = row(i, j);
-            const double jp = other[row(i, j + 1) + q];
-            const double jm = other[row(i, j - 1) + q];
-            const double kp = p ? other[r + q + 1] : o_c;
-            const double km = p ? o_c : other[r + q - 1];
-            double s = o_up + o_dn;
-            s = s + jp;
-            s = s + jm;
-            s = s + kp;
-            s = s + km;
-            // f is read once per sweep and the new value is not read again
+            const D2 jp = load2(other + r + pitch + q);  // row j + 1 of plane i
+            const D2 jm = load2(other + r - pitch + q);
+            // p = 1: q's k neighbours are o_c.y (k + 1) and o_c.x (k - 1), and
+            // q + 1's are other[q + 2] and o_c.y; p = 0: q's are o_c.x and
+            // other[q - 1], q + 1's are o_c.y and o_c.x
+            const double outer = p ? (v1 ? other[r + q + 2] : 0.0) : (v0 ? other[r + q - 1] : 0.0);
+            // f is read once per sweep and the new values are not read again
             // before the other colour's half-sweep has streamed the whole
             // grid: both go through the caches as streaming (non-temporal)
-            const double t = h2 * __builtin_nontemporal_load(f + r + q);
-            s = s - t;
-            __builtin_nontemporal_store(s / 6.0, self + r + q);
+            const D2 fv = load2_nt(f + r + q);
+            const double kp0 = p ? o_c.y : o_c.x, km0 = p ? o_c.x : outer;
+            const double kp1 = p ? outer : o_c.y, km1 = p ? o_c.y : o_c.x;
+            const double u0 = rb3_update(o_up.x, o_dn.x, jp.x, jm.x, kp0, km0, h2, fv.x);
+            const double u1 = rb3_update(o_up.y, o_dn.y, jp.y, jm.y, kp1, km1, h2, fv.y);
+            if (v0 && v1) {
+                const dvec2 w = {u0, u1};
+                __builtin_nontemporal_store(w, reinterpret_cast<dvec2*>(self + r + q));
+            } else if (v0) {
+                __builtin_nontemporal_store(u0, self + r + q);
+            } else {
+                __builtin_nontemporal_store(u1, self + r + q + 1);
+            }
         }
         o_dn = o_c;
         o_c = o_up;
@@ -297,8 +338,8 @@ hipError_t launch_rb3_unpack(double* nat, int64_t ld, const double* red, const d
 
 hipError_t launch_rb3_half(double* self, const double* other, const double* f, int n,
                            int64_t pitch, double h2, int colour, const int* stop, hipStream_t s) {
-    const int64_t qs = int64_t(n) / 2 + 1;  // q = 0 .. n / 2
-    const int qblocks = int((qs + kQ - 1) / kQ), jblocks = (n + kJ - 1) / kJ;
+    const int64_t qs = int64_t(n) / 2 + 1;  // q = 0 .. n / 2, two per thread
+    const int qblocks = int((qs + 2 * kQ - 1) / (2 * kQ)), jblocks = (n + kJ - 1) / kJ;
     const int64_t blocks = int64_t(qblocks) * jblocks * ((n + kPlanes - 1) / kPlanes);
     hipLaunchKernelGGL(k_rb3_half, dim3(unsigned(blocks)), dim3(kQ * kJ), 0, s, self, other, f,
                        n, pitch, h2, colour, qblocks, jblocks, stop);
