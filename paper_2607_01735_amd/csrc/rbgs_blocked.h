@@ -74,6 +74,12 @@ inline int default_rows(int n, int L) {
 // from 16383^2 (fuse 7), where every height fills the chip and the score
 // alone would take 1024 rows: FP64 1253 GLUP/s at 1024 rows, 1353 at 512,
 // 1371 at 768; FP32 1814 at 1024, 1819 at 512, 2234 at 256, 1962 at 128.
+// FP64 then takes one more strip of equal height when the chosen height
+// gives fewer tiles than 1.2 x wave_slots: waves drain a pass's tiles
+// unevenly, and a few more tiles than slots pay.  Measured at 8191^2 (fuse
+// 7, 1024 slots, 37 bands), a whole 200-sweep step: 256 rows (32 strips,
+// 1184 tiles) 10.05-10.17 ms, 249 rows (33 strips) 9.87, 241 rows 9.87,
+// 228 rows 10.12, 272 rows 10.36.
 inline int single_grid_rows(int n, int L, int elem_bytes, int wave_slots) {
     const double busy = 0.8 * (wave_slots > 0 ? wave_slots : 1024);
     const int cap = elem_bytes == 8 ? 512 : 256;
@@ -88,6 +94,12 @@ inline int single_grid_rows(int n, int L, int elem_bytes, int wave_slots) {
             best_score = score;
             best = rows;
         }
+    }
+    if (elem_bytes == 8) {
+        const Geometry g = geometry(n, elem_bytes, L / 2, best);
+        const int more = (n + g.strips) / (g.strips + 1);  // ceil(n / (strips + 1))
+        if (g.ntiles < 1.2 * (wave_slots > 0 ? wave_slots : 1024) && more >= L && more >= kMinRows)
+            best = more;
     }
     return best;
 }
