@@ -370,8 +370,11 @@ __device__ __forceinline__ bf16x8 load8(const bf16* p) {
     return bf16x8{*reinterpret_cast<const uint4*>(p)};
 }
 
+// F (the coarsening factor, 2 or 4) is a template parameter so that the
+// window loops unroll and their loads are in flight together.
+template <int F>
 __global__ __launch_bounds__(256) void k_restrict(const bf16* in, int64_t is, bf16* out, int64_t os,
-                                                  int batch, int nc, int c, int F, float scale,
+                                                  int batch, int nc, int c, float scale,
                                                   int accumulate) {
     const int c8 = c / 8;
     const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
@@ -388,12 +391,14 @@ __global__ __launch_bounds__(256) void k_restrict(const bf16* in, int64_t is, bf
     float s[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) s[k] = 0.f;
+#pragma unroll
     for (int di = 1 - F; di < F; ++di) {
         const float wi = float(F - (di < 0 ? -di : di));
         const bf16* row = in + ((int64_t(b) * nf + ci + di) * nf + cj) * is + ch;
         float t[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) t[k] = 0.f;
+#pragma unroll
         for (int dj = 1 - F; dj < F; ++dj) {
             const float wj = float(F - (dj < 0 ? -dj : dj));
             const bf16x8 x = load8(row + dj * is);
@@ -415,8 +420,9 @@ __global__ __launch_bounds__(256) void k_restrict(const bf16* in, int64_t is, bf
     *reinterpret_cast<uint4*>(o) = res.v;
 }
 
+template <int F>
 __global__ __launch_bounds__(256) void k_prolong(const bf16* in, int64_t is, bf16* out, int64_t os,
-                                                 int batch, int nc, int c, int F, float scale,
+                                                 int batch, int nc, int c, float scale,
                                                  int accumulate) {
     const int nf = F * nc + F - 1;
     const int c8 = c / 8;
@@ -435,10 +441,12 @@ __global__ __launch_bounds__(256) void k_prolong(const bf16* in, int64_t is, bf1
     float s[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) s[k] = 0.f;
+#pragma unroll
     for (int I = (i + 1) / F - 1; I <= (i + 1) / F; ++I) {
         const int di = i - (F * I + F - 1);
         if (I < 0 || I >= nc || di <= -F || di >= F) continue;
         const float wi = float(F - (di < 0 ? -di : di)) * invF;
+#pragma unroll
         for (int J = (j + 1) / F - 1; J <= (j + 1) / F; ++J) {
             const int dj = j - (F * J + F - 1);
             if (J < 0 || J >= nc || dj <= -F || dj >= F) continue;
@@ -929,8 +937,15 @@ hipError_t restrict_op(const Net& net, const bf16* in, int64_t is, bf16* out, in
                        int nc, int c, float scale, int acc, hipStream_t s) {
     if (!transfer_ok(in, is, out, os, c) || int64_t(batch) * nc * nc * (c / 8) > (int64_t(1) << 32) - 256)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_restrict, dim3(blocks_for(int64_t(batch) * nc * nc * (c / 8))), dim3(256), 0, s,
-                       in, is, out, os, batch, nc, c, net.factor, scale, acc);
+    const dim3 grid(blocks_for(int64_t(batch) * nc * nc * (c / 8)));
+    if (net.factor == 2)
+        hipLaunchKernelGGL(k_restrict<2>, grid, dim3(256), 0, s, in, is, out, os, batch, nc, c,
+                           scale, acc);
+    else if (net.factor == 4)
+        hipLaunchKernelGGL(k_restrict<4>, grid, dim3(256), 0, s, in, is, out, os, batch, nc, c,
+                           scale, acc);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -939,8 +954,15 @@ hipError_t prolong_op(const Net& net, const bf16* in, int64_t is, bf16* out, int
     const int nf = net.factor * nc + net.factor - 1;
     if (!transfer_ok(in, is, out, os, c) || int64_t(batch) * nf * nf * (c / 8) > (int64_t(1) << 32) - 256)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_prolong, dim3(blocks_for(int64_t(batch) * nf * nf * (c / 8))), dim3(256), 0, s,
-                       in, is, out, os, batch, nc, c, net.factor, scale, acc);
+    const dim3 grid(blocks_for(int64_t(batch) * nf * nf * (c / 8)));
+    if (net.factor == 2)
+        hipLaunchKernelGGL(k_prolong<2>, grid, dim3(256), 0, s, in, is, out, os, batch, nc, c, scale,
+                           acc);
+    else if (net.factor == 4)
+        hipLaunchKernelGGL(k_prolong<4>, grid, dim3(256), 0, s, in, is, out, os, batch, nc, c, scale,
+                           acc);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
