@@ -370,6 +370,45 @@ __device__ __forceinline__ bf16x8 load8(const bf16* p) {
     return bf16x8{*reinterpret_cast<const uint4*>(p)};
 }
 
+// k_bias_grad with 16-byte loads (c a multiple of 8, 16-byte aligned rows):
+// thread t takes channels 8 (t % c8) .. 8 (t % c8) + 7 of pixels t / c8,
+// t / c8 + g, ... (c8 = c / 8, g = 256 / c8), then a fixed tree over the g
+// pixel groups; one partial per (row, channel) as there.
+__global__ __launch_bounds__(256) void k_bias_grad8(const bf16* dy, int64_t dys, const bf16* y,
+                                                    int64_t ys, float* part, int wd, int c) {
+    const int64_t row = blockIdx.x;
+    const int t = threadIdx.x;
+    const int c8 = c / 8;
+    const int g = 256 / c8;
+    const int grp = t / c8, ch = (t % c8) * 8;
+    float s[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] = 0.f;
+    for (int x = grp; x < wd; x += g) {
+        const int64_t p = row * wd + x;
+        const bf16x8 yv = load8(y + p * ys + ch);
+        const bf16x8 dv = load8(dy + p * dys + ch);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (yv.get(k) > 0.f) s[k] += dv.get(k);
+    }
+    __shared__ float sh[8][256];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[k][t] = s[k];
+    __syncthreads();
+    for (int st = g / 2; st > 0; st >>= 1) {
+        if (grp < st) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sh[k][t] += sh[k][t + st * c8];
+        }
+        __syncthreads();
+    }
+    if (grp == 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) part[row * c + ch + k] = sh[k][t];
+    }
+}
+
 // F (the coarsening factor, 2 or 4) is a template parameter so that the
 // window loops unroll and their loads are in flight together.
 template <int F>
@@ -907,8 +946,14 @@ hipError_t wgrad(const Net& net, const Layer& L, const bf16* x, int64_t xs, cons
     if ((e = reduce_slots(net, int64_t(batch) * rb, wcount, net.grad + L.w_off, s)) != hipSuccess)
         return e;
     if (L.cout > 256 || (256 % L.cout) != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_bias_grad, dim3(unsigned(int64_t(batch) * a.h)), dim3(256), 0, s, dy, dys,
-                       y, ys, net.parts, a.wd, L.cout);
+    const bool wide = L.cout % 8 == 0 && dys % 8 == 0 && ys % 8 == 0 &&
+                      (reinterpret_cast<uintptr_t>(dy) | reinterpret_cast<uintptr_t>(y)) % 16 == 0;
+    if (wide)
+        hipLaunchKernelGGL(k_bias_grad8, dim3(unsigned(int64_t(batch) * a.h)), dim3(256), 0, s, dy,
+                           dys, y, ys, net.parts, a.wd, L.cout);
+    else
+        hipLaunchKernelGGL(k_bias_grad, dim3(unsigned(int64_t(batch) * a.h)), dim3(256), 0, s, dy,
+                           dys, y, ys, net.parts, a.wd, L.cout);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return reduce_slots(net, int64_t(batch) * a.h, int64_t(L.cout), net.grad + L.b_off, s);
 }
