@@ -24,9 +24,9 @@
 // then the error word, which makes every workgroup leave).
 //
 // Within a block lane l takes column J0 + l % qw of rows I0 + l / qw,
-// I0 + l / qw + 64 / qw, ...; each point is updated with the plain
-// quarter-sweep's operations in its order (so the result is bitwise the
-// same):
+// I0 + l / qw + 64 / qw, ..., kChunk rows at a time; each point is updated
+// with the plain quarter-sweep's operations in its order (so the result is
+// bitwise the same):
 //   e = ((u[i+1][j] + u[i-1][j]) + u[i][j+1]) + u[i][j-1]
 //   c = ((u[i+1][j+1] + u[i+1][j-1]) + u[i-1][j+1]) + u[i-1][j-1]
 //   u[i][j] = ((4 e + c) - c6 f[i][j]) / 20,   c6 = 6 (h h).
@@ -42,6 +42,7 @@ namespace mc9f {
 
 constexpr int kLanes = 64;
 constexpr int kErrTimeout = 1;
+constexpr int kChunk = 4;  // rows of a lane whose loads are in flight together
 
 struct Args {
     double* u[4];       // colour arrays of u
@@ -131,7 +132,9 @@ __device__ __forceinline__ bool wait_neighbours(const Args& a, int b, int level)
     return true;
 }
 
-// Quarter-sweep of colour `colour` over block b.
+// Quarter-sweep of colour `colour` over block b.  A lane's rows go kChunk
+// at a time: the chunk's loads are issued before any of its stores (the
+// stores go to the colour being updated, which none of the loads read).
 __device__ __forceinline__ void sweep_block(const Args& a, int b, int colour) {
     const int pi = colour & 1, pj = colour >> 1;
     double* __restrict__ self = a.u[colour];
@@ -148,20 +151,43 @@ __device__ __forceinline__ void sweep_block(const Args& a, int b, int colour) {
     const int64_t Jw = J - 1 + pj, Je = J + pj;  // columns of j - 1 and j + 1
     const int64_t I0 = int64_t(bi) * a.ri;
     const int64_t I1 = I0 + a.ri - 1 < a.rows - 1 ? I0 + a.ri - 1 : a.rows - 1;
-    for (int64_t I = I0 + lane / a.qw; I <= I1; I += kLanes / a.qw) {
-        const int64_t i = 2 * I + pi;
-        if (i < 1 || i > a.n) continue;
-        const int64_t Iu = I - 1 + pi, Id = I + pi;  // rows of i - 1 and i + 1
-        double e = ns[Id * P + J] + ns[Iu * P + J];
-        e = e + ew[I * P + Je];
-        e = e + ew[I * P + Jw];
-        double c = cc[Id * P + Je] + cc[Id * P + Jw];
-        c = c + cc[Iu * P + Je];
-        c = c + cc[Iu * P + Jw];
-        double s = 4.0 * e + c;
-        const double t = a.c6 * f[I * P + J];
-        s = s - t;
-        self[I * P + J] = s / 20.0;
+    const int64_t step = kLanes / a.qw;
+    for (int64_t Ic = I0 + lane / a.qw; Ic <= I1; Ic += kChunk * step) {
+        double nd[kChunk], nu[kChunk], we[kChunk], ww[kChunk];
+        double cde[kChunk], cdw[kChunk], cue[kChunk], cuw[kChunk], fv[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            const int64_t I = Ic + k * step;
+            const int64_t i = 2 * I + pi;
+            nd[k] = nu[k] = we[k] = ww[k] = cde[k] = cdw[k] = cue[k] = cuw[k] = fv[k] = 0.0;
+            if (I > I1 || i < 1 || i > a.n) continue;
+            const int64_t Iu = I - 1 + pi, Id = I + pi;  // rows of i - 1 and i + 1
+            nd[k] = ns[Id * P + J];
+            nu[k] = ns[Iu * P + J];
+            we[k] = ew[I * P + Je];
+            ww[k] = ew[I * P + Jw];
+            cde[k] = cc[Id * P + Je];
+            cdw[k] = cc[Id * P + Jw];
+            cue[k] = cc[Iu * P + Je];
+            cuw[k] = cc[Iu * P + Jw];
+            fv[k] = f[I * P + J];
+        }
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            const int64_t I = Ic + k * step;
+            const int64_t i = 2 * I + pi;
+            if (I > I1 || i < 1 || i > a.n) continue;
+            double e = nd[k] + nu[k];
+            e = e + we[k];
+            e = e + ww[k];
+            double c = cde[k] + cdw[k];
+            c = c + cue[k];
+            c = c + cuw[k];
+            double s = 4.0 * e + c;
+            const double t = a.c6 * fv[k];
+            s = s - t;
+            self[I * P + J] = s / 20.0;
+        }
     }
 }
 
