@@ -874,7 +874,7 @@ int rb3_flags_error(const Rb3Workspace& w, hipStream_t s) {
 
 int rb3_flags_setup(const rbgs_grid* g, const rbgs_rb3_opts* o, const Rb3Workspace& w,
                     hipStream_t s, int* capacity) {
-    *capacity = rb3_flags_capacity();
+    *capacity = rb3_flags_capacity(g->n);
     if (*capacity < 64) return fail(RBGS_EHIP, "occupancy query for the 3D flag-driven kernel");
     if (o->debug_stall_block > rb3_flags_blocks(g->n, *capacity))
         return fail(RBGS_EINVAL, "debug_stall_block beyond the block count");

@@ -27,10 +27,13 @@
 //
 // Within a block a lane takes the q-column q0 + lane % qw of rows j0 +
 // lane / qw, j0 + lane / qw + 64 / qw, ..., marching each row's column down
-// the block's planes kChunk planes at a time: the loads of a chunk are
-// issued before any of its stores, then the points are updated with the
-// same operations in the same order as the plain half-sweep (so the result
-// is bitwise the same).
+// the block's planes C planes at a time: the loads of a chunk are issued
+// before any of its stores, then the points are updated with the same
+// operations in the same order as the plain half-sweep (so the result is
+// bitwise the same).  Two chunk sizes are built: kDeepChunk keeps more
+// loads of one wave in flight (one wave per SIMD), kLeanChunk needs fewer
+// registers, so four waves fit on a SIMD and the largest grids get more
+// and smaller blocks in flight; the launch picks one by grid size.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,7 +46,8 @@ namespace rb3f {
 
 constexpr int kLanes = 64;
 constexpr int kErrTimeout = 1;
-constexpr int kChunk = 8;  // planes whose loads are in flight together
+constexpr int kDeepChunk = 8;  // planes whose loads are in flight together: 1 wave per SIMD
+constexpr int kLeanChunk = 2;  // 4 waves per SIMD
 
 struct Args {
     double* red;
@@ -146,7 +150,8 @@ __device__ __forceinline__ bool wait_neighbours(const Args& a, int b, int level)
     return true;
 }
 
-// Half-sweep of colour `colour` over block b.
+// Half-sweep of colour `colour` over block b, C planes at a time.
+template <int C>
 __device__ __forceinline__ void sweep_block(const Args& a, int b, int colour) {
     double* __restrict__ self = colour ? a.black : a.red;
     const double* __restrict__ other = colour ? a.red : a.black;
@@ -167,10 +172,10 @@ __device__ __forceinline__ void sweep_block(const Args& a, int b, int colour) {
         // current one
         double o_dn = other[((i0 - 1) * np2 + j) * P + q];
         double o_c = other[(i0 * np2 + j) * P + q];
-        for (int64_t ic = i0; ic <= i1; ic += kChunk) {
-            double up[kChunk], jp[kChunk], jm[kChunk], kx[kChunk], fv[kChunk];
+        for (int64_t ic = i0; ic <= i1; ic += C) {
+            double up[C], jp[C], jm[C], kx[C], fv[C];
 #pragma unroll
-            for (int c = 0; c < kChunk; ++c) {
+            for (int c = 0; c < C; ++c) {
                 const int64_t i = ic + c;
                 up[c] = jp[c] = jm[c] = kx[c] = fv[c] = 0.0;
                 if (i > i1) continue;
@@ -186,7 +191,7 @@ __device__ __forceinline__ void sweep_block(const Args& a, int b, int colour) {
                 }
             }
 #pragma unroll
-            for (int c = 0; c < kChunk; ++c) {
+            for (int c = 0; c < C; ++c) {
                 const int64_t i = ic + c;
                 if (i > i1) break;
                 const int64_t p = (i + j + colour) & 1;
@@ -211,6 +216,7 @@ __device__ __forceinline__ void sweep_block(const Args& a, int b, int colour) {
 }
 
 // The persistent kernel's body, run by every workgroup of the launch.
+template <int C>
 __device__ __forceinline__ void run(const Args& a) {
     if (a.stop && *a.stop) return;
     const int total = a.levels * a.nblocks;
@@ -228,7 +234,7 @@ __device__ __forceinline__ void run(const Args& a) {
                 stall_hash(uint32_t(level) * 0x9e3779b9u + uint32_t(b)) % uint32_t(a.delay + 1);
             for (uint32_t w = 0; w < loops; ++w) __builtin_amdgcn_s_sleep(127);
         }
-        sweep_block(a, b, level & 1);
+        sweep_block<C>(a, b, level & 1);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (threadIdx.x == 0 && b + 1 != a.stall_block)
             __hip_atomic_store(a.progress + b, level + 1, __ATOMIC_RELAXED,

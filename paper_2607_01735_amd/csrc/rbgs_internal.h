@@ -212,12 +212,12 @@ hipError_t launch_rb3_half(double* self, const double* other, const double* f, i
                            int64_t pitch, double h2, int colour, const int* stop, hipStream_t s);
 // The flag-driven 3D form: `levels` half-sweeps (red first) of the split
 // iterate in one launch (levels x rb3_flags_blocks(n, capacity) < 2^31).
-// capacity: resident one-wave workgroups (rb3_flags_capacity()); ticket
+// capacity: resident one-wave workgroups (rb3_flags_capacity(n)); ticket
 // and progress: a zeroed counter and rb3_flags_blocks(n, capacity) zeroed
 // block counters; error: a zeroed word, raised when a bounded wait
 // (spin_limit polls) expires.
 constexpr int kRb3MaxBlocks = 65536;
-int rb3_flags_capacity();
+int rb3_flags_capacity(int n);
 int rb3_flags_blocks(int n, int capacity);
 hipError_t launch_rb3_flags(double* red, double* black, const double* f_red,
                             const double* f_black, int n, int64_t pitch, double h2, int levels,

@@ -297,16 +297,19 @@ __global__ __launch_bounds__(kThreads) void k_rb3_reduce(const double* __restric
 }
 
 // The flag-driven form (rb3_flags.h): one launch for every half-sweep.
-__global__ __launch_bounds__(rb3f::kLanes) void k_rb3_flags(rb3f::Args a) { rb3f::run(a); }
+template <int C>
+__global__ __launch_bounds__(rb3f::kLanes) void k_rb3_flags(rb3f::Args a) { rb3f::run<C>(a); }
 
-}  // namespace
-
-int rb3_flags_capacity() {
+// Resident one-wave workgroups of the kernel with chunk C (0 if the query
+// fails).
+template <int C>
+int capacity_of() {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(&k_rb3_flags), rb3f::kLanes, 0) != hipSuccess) {
+            &per_cu, reinterpret_cast<const void*>(&k_rb3_flags<C>), rb3f::kLanes, 0) !=
+            hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
@@ -314,13 +317,29 @@ int rb3_flags_capacity() {
     return int(c < kRb3MaxBlocks ? c : kRb3MaxBlocks);
 }
 
+double wanted_items(int n) { return std::sqrt(double(n) * double(n) * double(n) / 10.0); }
+
+// The lean chunk from this size up.  Per sweep, flag-driven, FP64, deep
+// (one wave per SIMD) against lean (four): 127^3 0.053 / 0.068 ms, 255^3
+// 0.192 / 0.222, 383^3 0.564 / 0.618, 511^3 1.107 / 1.217, 767^3 3.933 /
+// 3.396; the deep kernel then holds 1024 waves for 864 blocks of 64 x 64 x
+// 64, the lean one 3456 blocks of 64 x 32 x 32.
+constexpr int kRb3LeanMinN = 640;
+
+bool use_deep_chunk(int n) { return n < kRb3LeanMinN; }
+
+}  // namespace
+
+int rb3_flags_capacity(int n) {
+    return use_deep_chunk(n) ? capacity_of<rb3f::kDeepChunk>() : capacity_of<rb3f::kLeanChunk>();
+}
+
 // Bound on the blocks per half-sweep.  Every item costs one ticket, and
 // tickets of the whole device go through one counter (about 40 ns each on
 // MI355X), while an item's time grows with its size; the two balance near
 // sqrt(n^3 / 10) items per half-sweep, capped at the waves the chip holds.
 int rb3_flags_target(int n, int capacity) {
-    const double items = std::sqrt(double(n) * double(n) * double(n) / 10.0);
-    return int(std::max(64.0, std::min(double(capacity), items)));
+    return int(std::max(64.0, std::min(double(capacity), wanted_items(n))));
 }
 
 int rb3_flags_blocks(int n, int capacity) {
@@ -364,7 +383,12 @@ hipError_t launch_rb3_flags(double* red, double* black, const double* f_red,
     int64_t waves = std::min<int64_t>(capacity, geo.nblocks);
     if (waves > items) waves = items;
     if (waves < 1) waves = 1;
-    hipLaunchKernelGGL(k_rb3_flags, dim3(unsigned(waves)), dim3(rb3f::kLanes), 0, s, a);
+    if (use_deep_chunk(n))
+        hipLaunchKernelGGL(k_rb3_flags<rb3f::kDeepChunk>, dim3(unsigned(waves)),
+                           dim3(rb3f::kLanes), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_rb3_flags<rb3f::kLeanChunk>, dim3(unsigned(waves)),
+                           dim3(rb3f::kLanes), 0, s, a);
     return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 //
 // Build: g++ -std=c++17 -I tests/emu -I paper_2607_01735_amd/csrc ...
 // Run:   emu n sweeps h in.bin out.bin max_blocks workgroups [delay [stall_block]]
+//        (EMU_CHUNK=lean in the environment: the lean plane chunk, else the deep one)
 //   in.bin  = u then f, natural (n+2)^3 arrays of doubles, index (i, j, k)
 //   out.bin = u after the sweeps, same layout
 // Exit status 4 when the kernel raised its error word (a wait expired).
@@ -45,6 +46,7 @@ thread_local void* host_fiber;
 static thread_local ucontext_t g_host_ctx, g_start_ctx[emu::kMaxThreads];
 static thread_local jmp_buf g_host_jmp;
 static rbgs::rb3f::Args g_args;
+static bool g_lean = false;  // the kernel with the lean plane chunk (EMU_CHUNK=lean)
 
 static void to_host() {
 #ifdef EMU_TSAN
@@ -60,7 +62,10 @@ static void lane_start(int lane) {
 #endif
         swapcontext(&g_start_ctx[lane], &g_host_ctx);
     }
-    rbgs::rb3f::run(g_args);
+    if (g_lean)
+        rbgs::rb3f::run<rbgs::rb3f::kLeanChunk>(g_args);
+    else
+        rbgs::rb3f::run<rbgs::rb3f::kDeepChunk>(g_args);
     emu::lane_done[lane] = true;
     for (int k = 1; k < emu::nthreads; ++k) {
         const int nx = (lane + k) % emu::nthreads;
@@ -107,6 +112,8 @@ int main(int argc, char** argv) {
     const int n = atoi(argv[1]), sweeps = atoi(argv[2]);
     const double h = atof(argv[3]);
     const int max_blocks = atoi(argv[6]), workgroups = atoi(argv[7]);
+    const char* chunk = getenv("EMU_CHUNK");
+    g_lean = chunk && chunk[0] == 'l';
     const rbgs::rb3f::Geometry geo = rbgs::rb3f::geometry(n, max_blocks);
     const size_t W = size_t(n) + 2;
     const size_t cells_nat = W * W * W;
@@ -169,9 +176,9 @@ int main(int argc, char** argv) {
         for (int w = 0; w < workgroups; ++w) threads.emplace_back(run_workgroup, w);
         for (auto& t : threads) t.join();
     }
-    printf("n=%d sweeps=%d qw=%d rj=%d rz=%d blocks=%d (%d x %d x %d) workgroups=%d\n", n,
+    printf("n=%d sweeps=%d qw=%d rj=%d rz=%d blocks=%d (%d x %d x %d) workgroups=%d chunk=%s\n", n,
            sweeps, geo.qw, geo.rj, geo.rz, geo.nblocks, geo.qblocks, geo.jblocks, geo.zblocks,
-           workgroups);
+           workgroups, g_lean ? "lean" : "deep");
     if (*a.error != 0) {
         fprintf(stderr, "the kernel raised its error word (%d)\n", *a.error);
         return 4;

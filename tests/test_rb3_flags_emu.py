@@ -2,8 +2,9 @@
 
 The kernel's device code (`csrc/rb3_flags.h`: the block geometry, the
 level-by-level walk of each wave's blocks, the seven-counter dependency wait,
-the plane-marching half-sweep of a block) is compiled unchanged for the host
-against the stand-in for HIP's device features in `tests/emu/hip`.  Any
+the plane-marching half-sweep of a block, with either plane chunk) is
+compiled unchanged for the host against the stand-in for HIP's device
+features in `tests/emu/hip`.  Any
 schedule that honours the block dependencies computes the sequential
 red-black sweep, so the result must equal the oracle's 3D sweeps bit for bit.
 
@@ -34,18 +35,22 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "tests", "emu", "rb3_flags_emu.cpp")
 INCLUDES = [os.path.join(ROOT, "tests", "emu"), os.path.join(ROOT, "paper_2607_01735_amd", "csrc")]
 
-# n, sweeps, max_blocks, workgroups, sanitizer, delay
+# n, sweeps, max_blocks, workgroups, sanitizer, delay, plane chunk
 CASES = [
-    (1, 3, 64, 1, "address", 0),      # one block, 8-lane rows, a single point
-    (7, 4, 64, 1, "address", 0),      # 8 q-columns of 8 rows per step
-    (20, 3, 64, 1, "address", 0),     # 16-lane rows, grown blocks
-    (37, 2, 64, 1, "address", 0),     # 32-lane rows
-    (70, 2, 64, 1, "address", 0),     # two 64-lane q-blocks
-    (9, 5, 64, 4, "thread", 0),       # 4 workgroups, more blocks than workgroups
-    (21, 3, 64, 5, "thread", 0),      # several tickets per workgroup
-    (40, 3, 200, 8, "thread", 0),     # 32-lane rows, 8 waves
-    (66, 2, 64, 6, "thread", 0),      # 64-lane rows, two q-blocks
-    (21, 3, 64, 4, "thread", 3),      # schedule stress: random stalls per block
+    (1, 3, 64, 1, "address", 0, "deep"),      # one block, 8-lane rows, a single point
+    (7, 4, 64, 1, "address", 0, "deep"),      # 8 q-columns of 8 rows per step
+    (20, 3, 64, 1, "address", 0, "deep"),     # 16-lane rows, grown blocks
+    (37, 2, 64, 1, "address", 0, "deep"),     # 32-lane rows
+    (70, 2, 64, 1, "address", 0, "deep"),     # two 64-lane q-blocks
+    (9, 5, 64, 4, "thread", 0, "deep"),       # 4 workgroups, more blocks than workgroups
+    (21, 3, 64, 5, "thread", 0, "deep"),      # several tickets per workgroup
+    (40, 3, 200, 8, "thread", 0, "deep"),     # 32-lane rows, 8 waves
+    (66, 2, 64, 6, "thread", 0, "deep"),      # 64-lane rows, two q-blocks
+    (21, 3, 64, 4, "thread", 3, "deep"),      # schedule stress: random stalls per block
+    (20, 3, 64, 1, "address", 0, "lean"),     # the lean plane chunk
+    (37, 2, 64, 1, "address", 0, "lean"),     # 16 + 16 + 5 planes: a chunk cut short
+    (40, 3, 200, 8, "thread", 0, "lean"),
+    (21, 3, 64, 4, "thread", 3, "lean"),
 ]
 
 pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
@@ -86,9 +91,9 @@ def _inputs(n):
     return u, f
 
 
-def _run(exe, out, n, sweeps, max_blocks, wgs, delay=0, stall=0):
+def _run(exe, out, n, sweeps, max_blocks, wgs, delay=0, stall=0, chunk="deep"):
     u, f = _inputs(n)
-    tag = f"{n}_{sweeps}_{max_blocks}_{wgs}_{delay}_{stall}_{exe.name}"
+    tag = f"{n}_{sweeps}_{max_blocks}_{wgs}_{delay}_{stall}_{chunk}_{exe.name}"
     fin, fout = out / f"in_{tag}.bin", out / f"out_{tag}.bin"
     with open(fin, "wb") as fh:
         fh.write(u.tobytes())
@@ -97,18 +102,21 @@ def _run(exe, out, n, sweeps, max_blocks, wgs, delay=0, stall=0):
     args = [str(exe), str(n), str(sweeps), repr(h), str(fin), str(fout), str(max_blocks), str(wgs)]
     if delay or stall:
         args += [str(delay), str(stall)]
-    res = subprocess.run(args, capture_output=True, text=True, env=_env(), timeout=600)
+    res = subprocess.run(args, capture_output=True, text=True, env=dict(_env(), EMU_CHUNK=chunk),
+                         timeout=600)
     got = np.fromfile(fout, dtype=np.float64).reshape(u.shape) if res.returncode == 0 else None
     return res, u, f, h, got
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"n{c[0]}-s{c[1]}-b{c[2]}-wg{c[3]}-{c[4]}-d{c[5]}")
+@pytest.mark.parametrize("case", CASES,
+                         ids=lambda c: f"n{c[0]}-s{c[1]}-b{c[2]}-wg{c[3]}-{c[4]}-d{c[5]}-{c[6]}")
 def test_rb3_flags_matches_oracle(oracle, emulators, case):
-    n, sweeps, max_blocks, wgs, san, delay = case
+    n, sweeps, max_blocks, wgs, san, delay, chunk = case
     out, exes = emulators
-    res, u, f, h, got = _run(exes[san], out, n, sweeps, max_blocks, wgs, delay)
+    res, u, f, h, got = _run(exes[san], out, n, sweeps, max_blocks, wgs, delay, chunk=chunk)
     assert res.returncode == 0, res.stdout + res.stderr[-4000:]
+    assert f"chunk={chunk}" in res.stdout
     # the block shape the kernel used covers the interior exactly, its lanes
     # split rows evenly, and the block count fits the bound
     import re
