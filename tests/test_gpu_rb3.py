@@ -101,8 +101,9 @@ def test_large_grid_sweeps_bitwise(oracle):
     assert np.array_equal(got, oracle.rb3_sweep(np.zeros_like(f), f, h, 2))
 
 
-# The flag-driven form (kernel "resident": one cooperative launch, a counter
-# per block, each block's half-sweep waiting only on its six face neighbours)
+# The flag-driven form (kernel "resident": one launch, (half-sweep, block)
+# items from a ticket queue, a counter per block, each block's half-sweep
+# waiting only on its six face neighbours)
 
 @pytest.mark.parametrize("n,sweeps", [(1, 3), (2, 4), (7, 5), (20, 3), (33, 4), (64, 3), (127, 5),
                                       (200, 2)])
@@ -175,11 +176,12 @@ def test_flags_blocked_kernel_rejected():
     assert e.value.status == rb.rbgs.EUNSUPPORTED
 
 
-def test_flags_large_grid_bitwise(oracle):
+@pytest.mark.parametrize("n", [639, 640, 767])
+def test_flags_large_grid_bitwise(oracle, n):
     """767^3, the size the benchmark times (3.6 GB per FP64 array), in the
-    launch configuration it times: two flag-driven sweeps equal the
-    oracle's on every point."""
-    n = 767
+    launch configuration it times, and the two sides of the switch from the
+    deep to the lean plane chunk (639^3, 640^3): two flag-driven sweeps
+    equal the oracle's on every point."""
     say(f"rb3 flag-driven large n={n}")
     h = 1.0 / (n + 1)
     rng = np.random.default_rng(0)
