@@ -71,7 +71,10 @@ __global__ __launch_bounds__(kThreads) void k_rb3_unpack(double* __restrict__ na
 // contiguous range of workgroups (rows next to each other share that XCD's
 // L2).  A thread loads the other colour and f as 16-byte pairs (q, q + 1):
 // twice the bytes in flight per load of a one-column thread; the one k
-// neighbour outside the pair (q + 2 or q - 1) is a separate 8-byte load.
+// neighbour outside the pair (q + 2 or q - 1) is the neighbouring lane's
+// value, passed by a cross-lane shuffle (a wave is 64 consecutive pairs of
+// one row), and loaded only at the wave's ends or next to a lane without
+// points.
 constexpr int kQ = 64, kJ = 8;
 // Grid size from which each thread takes two q-columns: measured on MI355X,
 // 767^3 runs 2.22 ms per sweep with two against 2.33 with one, while 63^3
@@ -164,20 +167,30 @@ __global__ __launch_bounds__(kQ * kJ) void k_rb3_half(double* __restrict__ self,
     const int nb = int(gridDim.x);
     const int b = xcd_logical_block(int(blockIdx.x), nb);
     const int bq = b % qblocks, bj = (b / qblocks) % jblocks, bz = b / (qblocks * jblocks);
-    const int64_t q = 2 * (int64_t(bq) * kQ + (threadIdx.x % kQ));  // pair (q, q + 1)
+    const int lane = int(threadIdx.x % kQ);
+    const int64_t q = 2 * (int64_t(bq) * kQ + lane);  // pair (q, q + 1)
     const int64_t j = int64_t(bj) * kJ + (threadIdx.x / kQ) + 1;
     const int64_t i0 = int64_t(bz) * kPlanes + 1;
-    if (j > n || q >= pitch || 2 * q > n) return;  // no interior point of either parity beyond
+    // no interior point of either parity beyond; such lanes stay for the
+    // shuffles but load and store nothing
+    const bool act = j <= n && q < pitch && 2 * q <= n;
+    // the lane to the right holds the pair (q + 2, q + 3) when it is active
+    const bool right_act = lane + 1 < kQ && j <= n && q + 2 < pitch && 2 * (q + 2) <= n;
     const int64_t i1 = i0 + kPlanes - 1 < n ? i0 + kPlanes - 1 : n;
     const int64_t np2 = int64_t(n) + 2;
     auto row = [&](int64_t i, int64_t jj) { return (i * np2 + jj) * pitch; };
-    D2 o_dn = load2(other + row(i0 - 1, j) + q);
-    D2 o_c = load2(other + row(i0, j) + q);
+    const D2 zero{0.0, 0.0};
+    D2 o_dn = act ? load2(other + row(i0 - 1, j) + q) : zero;
+    D2 o_c = act ? load2(other + row(i0, j) + q) : zero;
     for (int64_t i = i0; i <= i1; ++i) {
-        const D2 o_up = load2(other + row(i + 1, j) + q);
+        const D2 o_up = act ? load2(other + row(i + 1, j) + q) : zero;
+        // the k neighbours just outside the pair, other[q + 2] and
+        // other[q - 1], from the lanes next to this one
+        const double from_right = __shfl_down(o_c.x, 1, kQ);
+        const double from_left = __shfl_up(o_c.y, 1, kQ);
         const int64_t p = (i + j + colour) & 1;
         const int64_t k0 = 2 * q + p, k1 = k0 + 2;  // the points of q and q + 1
-        const bool v0 = k0 >= 1 && k0 <= n, v1 = k1 <= n;
+        const bool v0 = act && k0 >= 1 && k0 <= n, v1 = act && k1 <= n;
         if (v0 || v1) {
             const int64_t r = row(i, j);
             const D2 jp = load2(other + r + pitch + q);  // row j + 1 of plane i
@@ -185,7 +198,12 @@ __global__ __launch_bounds__(kQ * kJ) void k_rb3_half(double* __restrict__ self,
             // p = 1: q's k neighbours are o_c.y (k + 1) and o_c.x (k - 1), and
             // q + 1's are other[q + 2] and o_c.y; p = 0: q's are o_c.x and
             // other[q - 1], q + 1's are o_c.y and o_c.x
-            const double outer = p ? (v1 ? other[r + q + 2] : 0.0) : (v0 ? other[r + q - 1] : 0.0);
+            double outer = 0.0;
+            if (p) {
+                if (v1) outer = right_act ? from_right : other[r + q + 2];
+            } else {
+                if (v0) outer = lane > 0 ? from_left : other[r + q - 1];
+            }
             // f is read once per sweep and the new values are not read again
             // before the other colour's half-sweep has streamed the whole
             // grid: both go through the caches as streaming (non-temporal)

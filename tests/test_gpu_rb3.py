@@ -38,7 +38,8 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 7, 33, 64, 127])
+# 384 and up: the two-column kernel (odd and even n, padded rows)
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 33, 64, 127, 384, 385, 386])
 def test_sweeps_bitwise(oracle, n):
     say(f"rb3 sweeps n={n}")
     h = 1.0 / (n + 1)
